@@ -1,0 +1,634 @@
+/*
+ * hesp_oracle.c -- plain, slow, obviously-correct CPU oracle for the HeSP
+ * scheduling-partitioning simulation (Rey, Igual, Prieto-Matias,
+ * "HeSP: a simulation framework for solving the task scheduling-partitioning
+ * problem on heterogeneous architectures", arXiv 1602.05510).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this file.  It shares no code,
+ * header or table with the HIP path and must never be used to produce a
+ * product result.
+ *
+ * What it computes, step by step, in the paper's order:
+ *   1. cost model (section 2.1, "Performance and data transfer models"):
+ *      task time = ceil(flops / R(b)) ns with R(b) = Rmax b^2/(b^2+h^2);
+ *      transfer time of k atoms = latency + ceil(bytes / bandwidth) ns;
+ *   2. expansion (Fig. 1 loop nest; section 2.1 "Recursive task
+ *      partitioners"): every top-level task of Fig. 1 is replaced by the
+ *      blocked algorithm of its own kind on a 2^d x 2^d sub-tiling, emitted in
+ *      right-looking loop order;
+ *   3. dependences (section 2.1, RaW/WaR/WaW): a sequential scan over the
+ *      finest data atoms, last writer -> later reader/writer and
+ *      readers-since-last-write -> next writer;
+ *   4. critical times (section 2.1, "Priority-List"): sum of the task's time
+ *      over all processors (an order-preserving multiple of the average),
+ *      propagated backwards over the DAG;
+ *   5. event simulation, PL order + EFT-P selection with write-back caching of
+ *      host data in accelerator spaces and transfers issued when a task is
+ *      scheduled (section 2.1, "Task and data scheduling heuristics").
+ * Where the paper is silent (tie-breaks, simultaneous events, transfer issue
+ * time, coherence granularity) the readings are those listed in the design
+ * notes of this repository; each is marked "reading:" below.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+#define OR_INF INT64_MAX
+
+enum { OR_CHOL = 0, OR_TRSM = 1, OR_SYRK = 2, OR_GEMM = 3 };
+
+enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2, OR_ECAP = -4 };
+
+/* ------------------------------------------------------------------------ */
+/* 1. cost model                                                             */
+
+/* flops of one task of side bl, times 3 (chol b^3/3, trsm b^3, syrk b^3, gemm 2b^3) */
+static int64_t flops_times3(int type, int64_t bl)
+{
+    static const int64_t c[4] = {1, 3, 3, 6};
+    return c[type] * bl * bl * bl;
+}
+
+static int64_t ceil_div_pos(int64_t a, int64_t b) { return a / b + (a % b != 0); }
+
+/*
+ * task time in ns = flops / R, R in flop/ns = GFLOP/s = Rmax_mflops/1000 * bl^2/(bl^2+h^2)
+ *   = (flops3/3) * 1000 * (bl^2+h^2) / (Rmax_mflops * bl^2)
+ * computed as one exact rational and rounded up once (reading: every task time
+ * and every transfer time is rounded up on its own, everything after is exact).
+ */
+int oracle_task_time(int type, int64_t bl, int64_t rmax_mflops, int64_t h, int64_t *out)
+{
+    if (type < 0 || type > 3 || bl <= 0 || rmax_mflops <= 0 || h < 0 || !out) return OR_EINVAL;
+    int64_t f3 = flops_times3(type, bl);            /* 3 * flops */
+    /* num/den = (f3/3) * 1000 * (bl^2 + h^2) / (rmax * bl^2); bl^2 divides f3 */
+    int64_t num = (f3 / (bl * bl)) * 1000 * (bl * bl + h * h);
+    int64_t den = 3 * rmax_mflops;
+    *out = ceil_div_pos(num, den);
+    return OR_OK;
+}
+
+int oracle_transfer_time(int64_t n_atoms, int64_t atom_side, int64_t elem_bytes,
+                         int64_t latency_ns, int64_t bw_bytes_per_ns, int shared, int64_t *out)
+{
+    if (!out || n_atoms < 0 || atom_side <= 0 || bw_bytes_per_ns <= 0) return OR_EINVAL;
+    if (shared || n_atoms == 0) { *out = 0; return OR_OK; }
+    int64_t bytes = elem_bytes * n_atoms * atom_side * atom_side;
+    *out = latency_ns + ceil_div_pos(bytes, bw_bytes_per_ns);
+    return OR_OK;
+}
+
+typedef struct {
+    int n_procs, n_mem, n_ptypes;
+    const int32_t *proc_type, *proc_mem;
+    const int64_t *rmax;     /* [n_ptypes][4] MFLOP/s */
+    const int64_t *h;        /* [n_ptypes] */
+    int64_t b;               /* tile side at level 0 */
+    int64_t latency_ns, bw, elem_bytes;
+    int shared;              /* single memory space, transfers cost 0 */
+} or_platform;
+
+/* ------------------------------------------------------------------------ */
+/* 2. expansion                                                              */
+
+typedef struct {
+    int type, level, K, I, J;   /* fine loop indices at `level` (upper storage, K<=I<=J) */
+    int top;                    /* index of the Fig. 1 task it comes from */
+} or_task;
+
+typedef struct { or_task *v; int n, cap; } or_tasklist;
+
+static int tl_push(or_tasklist *l, or_task t)
+{
+    if (l->n == l->cap) {
+        int nc = l->cap ? 2 * l->cap : 256;
+        or_task *nv = (or_task *)realloc(l->v, (size_t)nc * sizeof(or_task));
+        if (!nv) return OR_ENOMEM;
+        l->v = nv; l->cap = nc;
+    }
+    l->v[l->n++] = t;
+    return OR_OK;
+}
+
+static int in_range(int x, int lo, int s) { return x >= lo && x < lo + s; }
+
+/*
+ * The Fig. 1 loop nest over the fine index space, restricted to the cell of one
+ * top-level task (its k, i, j ranges at granularity 2^d).  This emits exactly
+ * the fine tasks whose (K,I,J) fall in the cell, in right-looking order.
+ */
+static int emit_cell(or_tasklist *l, int top, int d, int k, int i, int j)
+{
+    int s = 1 << d;
+    int ks = k * s, is = i * s, js = j * s;
+    for (int K = ks; K < ks + s; K++) {
+        if (in_range(K, is, s) && in_range(K, js, s))
+            if (tl_push(l, (or_task){OR_CHOL, d, K, K, K, top})) return OR_ENOMEM;
+        if (in_range(K, is, s))
+            for (int J = K + 1; J < js + s; J++)
+                if (in_range(J, js, s))
+                    if (tl_push(l, (or_task){OR_TRSM, d, K, K, J, top})) return OR_ENOMEM;
+        for (int I = K + 1; I < is + s; I++) {
+            if (!in_range(I, is, s)) continue;
+            for (int J = I + 1; J < js + s; J++)
+                if (in_range(J, js, s))
+                    if (tl_push(l, (or_task){OR_GEMM, d, K, I, J, top})) return OR_ENOMEM;
+            if (in_range(I, js, s))
+                if (tl_push(l, (or_task){OR_SYRK, d, K, I, I, top})) return OR_ENOMEM;
+        }
+    }
+    return OR_OK;
+}
+
+/* Fig. 1: top-level tasks in program order, each expanded in place */
+static int expand(int nt, const uint8_t *depth, or_tasklist *out)
+{
+    int top = 0;
+    for (int k = 0; k < nt; k++) {
+        if (emit_cell(out, top, depth[top], k, k, k)) return OR_ENOMEM;
+        top++;
+        for (int j = k + 1; j < nt; j++) {
+            if (emit_cell(out, top, depth[top], k, k, j)) return OR_ENOMEM;
+            top++;
+        }
+        for (int i = k + 1; i < nt; i++) {
+            for (int j = i + 1; j < nt; j++) {
+                if (emit_cell(out, top, depth[top], k, i, j)) return OR_ENOMEM;
+                top++;
+            }
+            if (emit_cell(out, top, depth[top], k, i, i)) return OR_ENOMEM;
+            top++;
+        }
+    }
+    return OR_OK;
+}
+
+/* data blocks of a fine task: (row, col, written?) at the task's level */
+static int task_blocks(const or_task *t, int br[3], int bc[3], int bw[3])
+{
+    switch (t->type) {
+    case OR_CHOL: br[0] = t->K; bc[0] = t->K; bw[0] = 1; return 1;
+    case OR_TRSM: br[0] = t->K; bc[0] = t->K; bw[0] = 0;
+                  br[1] = t->K; bc[1] = t->J; bw[1] = 1; return 2;
+    case OR_SYRK: br[0] = t->K; bc[0] = t->I; bw[0] = 0;
+                  br[1] = t->I; bc[1] = t->I; bw[1] = 1; return 2;
+    default:      br[0] = t->K; bc[0] = t->I; bw[0] = 0;
+                  br[1] = t->K; bc[1] = t->J; bw[1] = 0;
+                  br[2] = t->I; bc[2] = t->J; bw[2] = 1; return 3;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3. dependences by a sequential scan over atoms                            */
+
+typedef struct { int64_t *v; int64_t n, cap; } or_i64list;
+
+static int il_push(or_i64list *l, int64_t x)
+{
+    if (l->n == l->cap) {
+        int64_t nc = l->cap ? 2 * l->cap : 16;
+        int64_t *nv = (int64_t *)realloc(l->v, (size_t)nc * sizeof(int64_t));
+        if (!nv) return OR_ENOMEM;
+        l->v = nv; l->cap = nc;
+    }
+    l->v[l->n++] = x;
+    return OR_OK;
+}
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Atoms: the finest blocks (side b/2^dmax).  A level-l block (R,C) is the set
+ * of atoms (R*2^(dmax-l)+u, C*2^(dmax-l)+v), 0 <= u,v < 2^(dmax-l) -- the whole
+ * square, also on the diagonal (reading).  Atoms are numbered row-major on the
+ * full N x N grid, N = nt * 2^dmax.
+ */
+typedef struct {
+    int n;                 /* tasks */
+    int64_t n_edges;
+    int64_t *edge;         /* sorted unique u*n+v */
+    int *succ_ptr, *succ;  /* CSR of successors */
+    int *npred;
+} or_dag;
+
+static void dag_free(or_dag *g)
+{
+    free(g->edge); free(g->succ_ptr); free(g->succ); free(g->npred);
+    memset(g, 0, sizeof(*g));
+}
+
+static int build_dag(const or_tasklist *tl, int nt, int dmax, or_dag *g)
+{
+    int n = tl->n, N = nt << dmax;
+    int64_t n_atoms = (int64_t)N * N;
+    int64_t *last_w = (int64_t *)malloc((size_t)n_atoms * sizeof(int64_t));
+    or_i64list *readers = (or_i64list *)calloc((size_t)n_atoms, sizeof(or_i64list));
+    or_i64list edges = {0, 0, 0};
+    int rc = OR_OK;
+    memset(g, 0, sizeof(*g));
+    if (!last_w || !readers) { rc = OR_ENOMEM; goto done; }
+    for (int64_t a = 0; a < n_atoms; a++) last_w[a] = -1;
+
+    for (int t = 0; t < n; t++) {
+        int br[3], bc[3], bw[3];
+        int nb = task_blocks(&tl->v[t], br, bc, bw);
+        int sh = dmax - tl->v[t].level, w = 1 << sh;
+        for (int bi = 0; bi < nb; bi++) {
+            for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
+                int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                if (last_w[a] >= 0 && last_w[a] != t)
+                    if (il_push(&edges, last_w[a] * n + t)) { rc = OR_ENOMEM; goto done; }
+                if (bw[bi]) {           /* write: WaW above, WaR from readers */
+                    for (int64_t r = 0; r < readers[a].n; r++)
+                        if (readers[a].v[r] != t)
+                            if (il_push(&edges, readers[a].v[r] * n + t)) { rc = OR_ENOMEM; goto done; }
+                    readers[a].n = 0;
+                    last_w[a] = t;
+                } else {                /* read: RaW above */
+                    if (il_push(&readers[a], t)) { rc = OR_ENOMEM; goto done; }
+                }
+            }
+        }
+    }
+    /* deduplicate */
+    if (edges.n) qsort(edges.v, (size_t)edges.n, sizeof(int64_t), cmp_i64);
+    int64_t m = 0;
+    for (int64_t e = 0; e < edges.n; e++)
+        if (e == 0 || edges.v[e] != edges.v[e - 1]) edges.v[m++] = edges.v[e];
+    g->n = n; g->n_edges = m; g->edge = edges.v; edges.v = NULL;
+    g->succ_ptr = (int *)calloc((size_t)n + 1, sizeof(int));
+    g->succ = (int *)malloc((size_t)(m ? m : 1) * sizeof(int));
+    g->npred = (int *)calloc((size_t)n ? (size_t)n : 1, sizeof(int));
+    if (!g->succ_ptr || !g->succ || !g->npred) { rc = OR_ENOMEM; goto done; }
+    for (int64_t e = 0; e < m; e++) {
+        g->succ_ptr[g->edge[e] / n + 1]++;
+        g->npred[g->edge[e] % n]++;
+    }
+    for (int t = 0; t < n; t++) g->succ_ptr[t + 1] += g->succ_ptr[t];
+    for (int64_t e = 0; e < m; e++) g->succ[e] = (int)(g->edge[e] % n); /* sorted by u then v */
+done:
+    free(last_w);
+    if (readers) { for (int64_t a = 0; a < n_atoms; a++) free(readers[a].v); free(readers); }
+    free(edges.v);
+    if (rc) dag_free(g);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 4-5. priorities and the event simulation                                  */
+
+typedef struct {
+    int nt, dmax;
+    int64_t *cost;   /* [n_ptypes][4][dmax+1] */
+    int64_t *xfer;   /* [4^dmax + 1] */
+} or_tables;
+
+static int make_tables(const or_platform *pf, int dmax, or_tables *tb)
+{
+    int L = dmax + 1;
+    int64_t na = (int64_t)1 << (2 * dmax);
+    tb->cost = (int64_t *)malloc((size_t)pf->n_ptypes * 4 * L * sizeof(int64_t));
+    tb->xfer = (int64_t *)malloc((size_t)(na + 1) * sizeof(int64_t));
+    if (!tb->cost || !tb->xfer) return OR_ENOMEM;
+    for (int pt = 0; pt < pf->n_ptypes; pt++)
+        for (int ty = 0; ty < 4; ty++)
+            for (int l = 0; l < L; l++)
+                if (oracle_task_time(ty, pf->b >> l, pf->rmax[pt * 4 + ty], pf->h[pt],
+                                     &tb->cost[(pt * 4 + ty) * L + l])) return OR_EINVAL;
+    for (int64_t k = 0; k <= na; k++)
+        if (oracle_transfer_time(k, pf->b >> dmax, pf->elem_bytes, pf->latency_ns, pf->bw,
+                                 pf->shared, &tb->xfer[k])) return OR_EINVAL;
+    return OR_OK;
+}
+
+static void free_tables(or_tables *tb) { free(tb->cost); free(tb->xfer); }
+
+/* ready-set order: larger critical time first, then smaller scaled (K,I,J) */
+typedef struct { int64_t rank; int64_t k0, k1, k2; int task; } or_hent;
+
+static int hent_before(const or_hent *a, const or_hent *b)
+{
+    if (a->rank != b->rank) return a->rank > b->rank;
+    if (a->k0 != b->k0) return a->k0 < b->k0;
+    if (a->k1 != b->k1) return a->k1 < b->k1;
+    return a->k2 < b->k2;
+}
+
+typedef struct { or_hent *v; int n; } or_heap;
+
+static void heap_push(or_heap *h, or_hent e)
+{
+    int i = h->n++;
+    h->v[i] = e;
+    while (i > 0) {
+        int p = (i - 1) / 2;
+        if (!hent_before(&h->v[i], &h->v[p])) break;
+        or_hent t = h->v[i]; h->v[i] = h->v[p]; h->v[p] = t; i = p;
+    }
+}
+
+static or_hent heap_pop(or_heap *h)
+{
+    or_hent top = h->v[0];
+    h->v[0] = h->v[--h->n];
+    int i = 0;
+    for (;;) {
+        int l = 2 * i + 1, r = l + 1, m = i;
+        if (l < h->n && hent_before(&h->v[l], &h->v[m])) m = l;
+        if (r < h->n && hent_before(&h->v[r], &h->v[m])) m = r;
+        if (m == i) break;
+        or_hent t = h->v[i]; h->v[i] = h->v[m]; h->v[m] = t; i = m;
+    }
+    return top;
+}
+
+typedef struct {
+    int64_t makespan;
+    int n_tasks;
+    int64_t n_edges;
+} or_result;
+
+typedef struct {
+    /* optional per-task outputs, in the oracle's program order */
+    int32_t max_tasks;
+    int32_t *task_info;   /* [max_tasks][5] type, level, K, I, J */
+    int32_t *proc;
+    int64_t *start, *finish, *rank;
+    int64_t max_edges;
+    int32_t *edges;       /* [max_edges][2] */
+} or_outputs;
+
+static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *depth,
+                        or_result *res, const or_outputs *o)
+{
+    or_tasklist tl = {0, 0, 0};
+    or_dag g;
+    or_tables tb = {0, 0, 0, 0};
+    int rc;
+    int64_t *W = 0, *rank = 0, *start = 0, *finish = 0, *avail = 0, *vf = 0;
+    int *proc = 0, *left = 0, *fifo = 0, *fifo_head = 0, *fifo_tail = 0, *fifo_next = 0;
+    or_heap heap = {0, 0};
+    memset(&g, 0, sizeof(g));
+
+    if (nt < 1 || dmax < 0 || dmax > 6 || (pf->b >> dmax) << dmax != pf->b) return OR_EINVAL;
+    int n_top = nt * (nt + 1) * (nt + 2) / 6;
+    for (int t = 0; t < n_top; t++) if (depth[t] > dmax) return OR_EINVAL;
+    rc = expand(nt, depth, &tl);
+    if (rc) goto done;
+    rc = build_dag(&tl, nt, dmax, &g);
+    if (rc) goto done;
+    rc = make_tables(pf, dmax, &tb);
+    if (rc) goto done;
+
+    int n = tl.n, P = pf->n_procs, M = pf->n_mem, L = dmax + 1, N = nt << dmax;
+    W = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    rank = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    start = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    finish = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    proc = (int *)malloc((size_t)n * sizeof(int));
+    left = (int *)malloc((size_t)n * sizeof(int));
+    fifo_next = (int *)malloc((size_t)n * sizeof(int));
+    avail = (int64_t *)calloc((size_t)P, sizeof(int64_t));
+    fifo_head = (int *)malloc((size_t)P * sizeof(int));
+    fifo_tail = (int *)malloc((size_t)P * sizeof(int));
+    vf = (int64_t *)malloc((size_t)N * N * M * sizeof(int64_t));
+    heap.v = (or_hent *)malloc((size_t)n * sizeof(or_hent));
+    if (!W || !rank || !start || !finish || !proc || !left || !fifo_next || !avail ||
+        !fifo_head || !fifo_tail || !vf || !heap.v) { rc = OR_ENOMEM; goto done; }
+
+    /* 4. critical times: sum of the task's time over all processors, then the
+     * longest such path to an exit, tasks visited in reverse program order
+     * (edges always point forward in program order) */
+    for (int t = 0; t < n; t++) {
+        int64_t s = 0;
+        for (int p = 0; p < P; p++)
+            s += tb.cost[(pf->proc_type[p] * 4 + tl.v[t].type) * L + tl.v[t].level];
+        W[t] = s;
+    }
+    for (int t = n - 1; t >= 0; t--) {
+        int64_t best = 0;
+        for (int e = g.succ_ptr[t]; e < g.succ_ptr[t + 1]; e++)
+            if (rank[g.succ[e]] > best) best = rank[g.succ[e]];
+        rank[t] = W[t] + best;
+    }
+
+    /* 5. event simulation */
+    for (int64_t a = 0; a < (int64_t)N * N; a++)
+        for (int m = 0; m < M; m++) vf[a * M + m] = (m == 0) ? 0 : OR_INF; /* data starts on the host */
+    for (int p = 0; p < P; p++) { fifo_head[p] = -1; fifo_tail[p] = -1; }
+    for (int t = 0; t < n; t++) { left[t] = g.npred[t]; proc[t] = -1; }
+    for (int t = 0; t < n; t++)
+        if (left[t] == 0) {
+            int sh = dmax - tl.v[t].level;
+            heap_push(&heap, (or_hent){rank[t], (int64_t)tl.v[t].K << sh, (int64_t)tl.v[t].I << sh,
+                                       (int64_t)tl.v[t].J << sh, t});
+        }
+    int64_t T = 0, makespan = 0;
+    int done_count = 0;
+    for (;;) {
+        /* (i) every ready task is mapped now, in priority order */
+        while (heap.n) {
+            int t = heap_pop(&heap).task;
+            int br[3], bc[3], bw[3];
+            int nb = task_blocks(&tl.v[t], br, bc, bw);
+            int sh = dmax - tl.v[t].level, w = 1 << sh;
+            int best_p = -1;
+            int64_t best_eft = 0, best_est = 0;
+            for (int p = 0; p < P; p++) {
+                int m = pf->proc_mem[p];
+                int64_t est = T > avail[p] ? T : avail[p];
+                for (int bi = 0; bi < nb; bi++) {
+                    int64_t miss = 0, fin = INT64_MIN;
+                    for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
+                        int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                        int64_t x = vf[a * M + m];
+                        if (x == OR_INF) miss++;
+                        else if (x > fin) fin = x;
+                    }
+                    int64_t ready = fin;
+                    if (miss > 0 && T + tb.xfer[miss] > ready) ready = T + tb.xfer[miss];
+                    if (ready > est) est = ready;
+                }
+                int64_t eft = est + tb.cost[(pf->proc_type[p] * 4 + tl.v[t].type) * L + tl.v[t].level];
+                if (best_p < 0 || eft < best_eft) { best_p = p; best_eft = eft; best_est = est; }
+            }
+            /* commit: transfers of the missing atoms are issued now, at time T */
+            int m = pf->proc_mem[best_p];
+            for (int bi = 0; bi < nb; bi++) {
+                int64_t miss = 0;
+                for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
+                    int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                    if (vf[a * M + m] == OR_INF) miss++;
+                }
+                if (!miss) continue;
+                for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
+                    int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                    if (vf[a * M + m] == OR_INF) vf[a * M + m] = T + tb.xfer[miss];
+                }
+            }
+            proc[t] = best_p; start[t] = best_est; finish[t] = best_eft;
+            avail[best_p] = best_eft;
+            fifo_next[t] = -1;
+            if (fifo_tail[best_p] < 0) fifo_head[best_p] = t; else fifo_next[fifo_tail[best_p]] = t;
+            fifo_tail[best_p] = t;
+        }
+        /* (ii) next event: the earliest completion at the head of a queue */
+        int64_t Tn = OR_INF;
+        for (int p = 0; p < P; p++)
+            if (fifo_head[p] >= 0 && finish[fifo_head[p]] < Tn) Tn = finish[fifo_head[p]];
+        if (Tn == OR_INF) break;
+        /* (iii) all completions at Tn, before any mapping at Tn (reading) */
+        for (int p = 0; p < P; p++) {
+            int t = fifo_head[p];
+            if (t < 0 || finish[t] != Tn) continue;
+            fifo_head[p] = fifo_next[t];
+            if (fifo_head[p] < 0) fifo_tail[p] = -1;
+            done_count++;
+            /* write-back: the written block is now valid only where it was computed */
+            int br[3], bc[3], bw[3];
+            int nb = task_blocks(&tl.v[t], br, bc, bw);
+            int sh = dmax - tl.v[t].level, w = 1 << sh, m = pf->proc_mem[p];
+            for (int bi = 0; bi < nb; bi++) {
+                if (!bw[bi]) continue;
+                for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
+                    int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                    for (int mm = 0; mm < M; mm++) vf[a * M + mm] = (mm == m) ? Tn : OR_INF;
+                }
+            }
+            for (int e = g.succ_ptr[t]; e < g.succ_ptr[t + 1]; e++) {
+                int v = g.succ[e];
+                if (--left[v] == 0) {
+                    int s2 = dmax - tl.v[v].level;
+                    heap_push(&heap, (or_hent){rank[v], (int64_t)tl.v[v].K << s2,
+                                               (int64_t)tl.v[v].I << s2, (int64_t)tl.v[v].J << s2, v});
+                }
+            }
+        }
+        T = Tn;
+        if (Tn > makespan) makespan = Tn;
+    }
+    if (done_count != n) { rc = OR_EINVAL; goto done; }   /* cannot happen on a DAG */
+
+    res->makespan = makespan; res->n_tasks = n; res->n_edges = g.n_edges;
+    if (o) {
+        if (o->task_info || o->proc || o->start || o->finish || o->rank) {
+            if (n > o->max_tasks) { rc = OR_ECAP; goto done; }
+            for (int t = 0; t < n; t++) {
+                if (o->task_info) {
+                    o->task_info[5 * t + 0] = tl.v[t].type; o->task_info[5 * t + 1] = tl.v[t].level;
+                    o->task_info[5 * t + 2] = tl.v[t].K; o->task_info[5 * t + 3] = tl.v[t].I;
+                    o->task_info[5 * t + 4] = tl.v[t].J;
+                }
+                if (o->proc) o->proc[t] = proc[t];
+                if (o->start) o->start[t] = start[t];
+                if (o->finish) o->finish[t] = finish[t];
+                if (o->rank) o->rank[t] = rank[t];
+            }
+        }
+        if (o->edges) {
+            if (g.n_edges > o->max_edges) { rc = OR_ECAP; goto done; }
+            for (int64_t e = 0; e < g.n_edges; e++) {
+                o->edges[2 * e] = (int32_t)(g.edge[e] / n);
+                o->edges[2 * e + 1] = (int32_t)(g.edge[e] % n);
+            }
+        }
+    }
+    rc = OR_OK;
+done:
+    free(tl.v); dag_free(&g); free_tables(&tb);
+    free(W); free(rank); free(start); free(finish); free(proc); free(left); free(fifo_next);
+    free(avail); free(fifo_head); free(fifo_tail); free(vf); free(heap.v); free(fifo);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* exported entry points (plain C ABI, loaded by the tests with ctypes)      */
+
+int oracle_simulate(int nt, int dmax, const uint8_t *depth,
+                    int n_procs, const int32_t *proc_type, const int32_t *proc_mem, int n_mem,
+                    int n_ptypes, const int64_t *rmax, const int64_t *h, int64_t b,
+                    int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
+                    int64_t *makespan, int32_t *n_tasks, int64_t *n_edges,
+                    int32_t max_tasks, int32_t *task_info, int32_t *proc_out,
+                    int64_t *start_out, int64_t *finish_out, int64_t *rank_out,
+                    int64_t max_edges, int32_t *edges_out)
+{
+    if (!depth || n_procs < 1 || !proc_type || !proc_mem || n_mem < 1 || !rmax || !h) return OR_EINVAL;
+    for (int p = 0; p < n_procs; p++)
+        if (proc_type[p] < 0 || proc_type[p] >= n_ptypes || proc_mem[p] < 0 || proc_mem[p] >= n_mem)
+            return OR_EINVAL;
+    or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
+                      latency_ns, bw, elem_bytes, shared};
+    or_outputs o = {max_tasks, task_info, proc_out, start_out, finish_out, rank_out, max_edges, edges_out};
+    or_result r;
+    int rc = simulate_one(&pf, nt, dmax, depth, &r, &o);
+    if (rc) return rc;
+    if (makespan) *makespan = r.makespan;
+    if (n_tasks) *n_tasks = r.n_tasks;
+    if (n_edges) *n_edges = r.n_edges;
+    return OR_OK;
+}
+
+typedef struct {
+    const or_platform *pf;
+    int n_cand;
+    const int32_t *nt, *dmax;
+    const int64_t *mask_off;
+    const uint8_t *depth;
+    int64_t *makespan;
+    int32_t *n_tasks;
+    int32_t *status;
+    int next;
+    pthread_mutex_t mu;
+} or_batch_job;
+
+static void *batch_worker(void *arg)
+{
+    or_batch_job *j = (or_batch_job *)arg;
+    for (;;) {
+        pthread_mutex_lock(&j->mu);
+        int c = j->next++;
+        pthread_mutex_unlock(&j->mu);
+        if (c >= j->n_cand) break;
+        or_result r = {0, 0, 0};
+        int rc = simulate_one(j->pf, j->nt[c], j->dmax[c], j->depth + j->mask_off[c], &r, NULL);
+        j->makespan[c] = rc ? -1 : r.makespan;
+        if (j->n_tasks) j->n_tasks[c] = rc ? 0 : r.n_tasks;
+        if (j->status) j->status[c] = rc;
+    }
+    return NULL;
+}
+
+/* one candidate per job on a pool of n_threads POSIX threads */
+int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
+                          const int64_t *mask_off, const uint8_t *depth,
+                          int n_procs, const int32_t *proc_type, const int32_t *proc_mem, int n_mem,
+                          int n_ptypes, const int64_t *rmax, const int64_t *h, int64_t b,
+                          int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
+                          int n_threads, int64_t *makespan, int32_t *n_tasks, int32_t *status)
+{
+    if (n_cand < 0 || !nt || !dmax || !mask_off || !depth || !makespan || n_threads < 1) return OR_EINVAL;
+    or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
+                      latency_ns, bw, elem_bytes, shared};
+    or_batch_job j;
+    j.pf = &pf; j.n_cand = n_cand; j.nt = nt; j.dmax = dmax; j.mask_off = mask_off; j.depth = depth;
+    j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.next = 0;
+    pthread_mutex_init(&j.mu, NULL);
+    pthread_t *th = (pthread_t *)malloc((size_t)n_threads * sizeof(pthread_t));
+    if (!th) return OR_ENOMEM;
+    int started = 0;
+    for (int i = 0; i < n_threads; i++)
+        if (pthread_create(&th[i], NULL, batch_worker, &j) == 0) started++;
+        else break;
+    if (started == 0) batch_worker(&j);
+    for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
+    free(th);
+    pthread_mutex_destroy(&j.mu);
+    return OR_OK;
+}

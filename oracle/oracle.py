@@ -1,0 +1,149 @@
+"""ctypes loader for the plain-C oracle (``hesp_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark.  The product path never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hesp_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, -O2)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+                               "-Wall", "-Wextra", "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        L.oracle_simulate.argtypes = [i32, i32, P, i32, P, P, i32, i32, P, P, i64, i64, i64, i64, i32,
+                                      P, P, P, i32, P, P, P, P, P, i64, P]
+        L.oracle_simulate.restype = i32
+        L.oracle_simulate_batch.argtypes = [i32, P, P, P, P, i32, P, P, i32, i32, P, P, i64, i64, i64,
+                                            i64, i32, i32, P, P, P]
+        L.oracle_simulate_batch.restype = i32
+        L.oracle_task_time.argtypes = [i32, i64, i64, i64, P]
+        L.oracle_task_time.restype = i32
+        L.oracle_transfer_time.argtypes = [i64, i64, i64, i64, i64, i32, P]
+        L.oracle_transfer_time.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def task_time(ttype: int, bl: int, rmax: int, h: int) -> int:
+    out = np.zeros(1, np.int64)
+    rc = lib().oracle_task_time(ttype, bl, rmax, h, _p(out))
+    if rc:
+        raise ValueError(f"oracle_task_time rc={rc}")
+    return int(out[0])
+
+
+def transfer_time(n_atoms: int, atom_side: int, pf) -> int:
+    out = np.zeros(1, np.int64)
+    rc = lib().oracle_transfer_time(n_atoms, atom_side, pf.elem_bytes, pf.latency_ns,
+                                    pf.bw_bytes_per_ns, int(pf.shared_memory), _p(out))
+    if rc:
+        raise ValueError(f"oracle_transfer_time rc={rc}")
+    return int(out[0])
+
+
+class Schedule:
+    """Oracle result for one candidate, tasks in the oracle's program order."""
+
+    def __init__(self, makespan, tasks, proc, start, finish, rank, edges):
+        self.makespan = makespan
+        self.tasks = tasks      # int32 [n][5]: type, level, K, I, J
+        self.proc = proc
+        self.start = start
+        self.finish = finish
+        self.rank = rank
+        self.edges = edges      # int32 [m][2]
+
+    @property
+    def n_tasks(self) -> int:
+        return int(self.tasks.shape[0])
+
+
+def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = True):
+    """Simulate one candidate; returns a Schedule (detail) or the makespan."""
+    L = lib()
+    depth = np.ascontiguousarray(depth, dtype=np.uint8)
+    ptype = np.ascontiguousarray(pf.proc_type, dtype=np.int32)
+    pmem = np.ascontiguousarray(pf.proc_mem, dtype=np.int32)
+    rmax = np.ascontiguousarray(pf.rmax, dtype=np.int64)
+    h = np.ascontiguousarray(pf.h, dtype=np.int64)
+    ms = np.zeros(1, np.int64)
+    nt_out = np.zeros(1, np.int32)
+    ne_out = np.zeros(1, np.int64)
+    args_pf = (pf.n_procs, _p(ptype), _p(pmem), pf.n_mem, pf.n_ptypes, _p(rmax), _p(h), b,
+               pf.latency_ns, pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory))
+    rc = L.oracle_simulate(nt, dmax, _p(depth), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
+                           0, None, None, None, None, None, 0, None)
+    if rc:
+        raise ValueError(f"oracle_simulate rc={rc}")
+    if not detail:
+        return int(ms[0])
+    n, m = int(nt_out[0]), int(ne_out[0])
+    tasks = np.zeros((n, 5), np.int32)
+    proc = np.zeros(n, np.int32)
+    start = np.zeros(n, np.int64)
+    finish = np.zeros(n, np.int64)
+    rank = np.zeros(n, np.int64)
+    edges = np.zeros((max(m, 1), 2), np.int32)
+    rc = L.oracle_simulate(nt, dmax, _p(depth), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
+                           n, _p(tasks), _p(proc), _p(start), _p(finish), _p(rank), m, _p(edges))
+    if rc:
+        raise ValueError(f"oracle_simulate rc={rc}")
+    return Schedule(int(ms[0]), tasks, proc, start, finish, rank, edges[:m])
+
+
+def simulate_batch(pf, batch, n_threads: int = 1):
+    """Makespans (int64) and expanded task counts of a whole batch."""
+    L = lib()
+    n = batch.n
+    ms = np.zeros(n, np.int64)
+    ntk = np.zeros(n, np.int32)
+    st = np.zeros(n, np.int32)
+    nt = np.ascontiguousarray(batch.nt, dtype=np.int32)
+    dm = np.ascontiguousarray(batch.dmax, dtype=np.int32)
+    off = np.ascontiguousarray(batch.mask_off, dtype=np.int64)
+    dep = np.ascontiguousarray(batch.depth, dtype=np.uint8)
+    ptype = np.ascontiguousarray(pf.proc_type, dtype=np.int32)
+    pmem = np.ascontiguousarray(pf.proc_mem, dtype=np.int32)
+    rmax = np.ascontiguousarray(pf.rmax, dtype=np.int64)
+    h = np.ascontiguousarray(pf.h, dtype=np.int64)
+    rc = L.oracle_simulate_batch(n, _p(nt), _p(dm), _p(off), _p(dep), pf.n_procs, _p(ptype), _p(pmem),
+                                 pf.n_mem, pf.n_ptypes, _p(rmax), _p(h), batch.b, pf.latency_ns,
+                                 pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory), n_threads,
+                                 _p(ms), _p(ntk), _p(st))
+    if rc:
+        raise ValueError(f"oracle_simulate_batch rc={rc}")
+    if np.any(st != 0):
+        bad = int(np.nonzero(st)[0][0])
+        raise ValueError(f"oracle failed on candidate {bad} rc={int(st[bad])}")
+    return ms, ntk

@@ -1,0 +1,295 @@
+"""A second, independent CPU reading of the method, in pure Python (tiny cases).
+
+Test infrastructure: used to cross-check the C oracle (two implementations of
+the same reading written separately) and, with its choice hooks, to enumerate
+every push-at-release schedule of a tiny DAG for brute-force optima.
+
+Expansion here enumerates the whole fine iteration space {K <= I <= J} and
+assigns every fine task to the Fig. 1 task whose cell contains it; program
+order is (Fig. 1 index of the cell, K, kind order of Fig. 1 within one K).
+"""
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+from typing import Dict, List, Optional, Sequence, Tuple
+
+CHOL, TRSM, SYRK, GEMM = 0, 1, 2, 3
+KIND_NAMES = ("chol", "trsm", "syrk", "gemm")
+FLOP_NUM = (1, 3, 3, 6)  # flops * 3 / b^3
+
+
+def fig1_tasks(nt: int) -> List[Tuple[int, int, int, int]]:
+    """(kind, k, i, j) in the order the Fig. 1 loop nest issues them."""
+    out = []
+    for k in range(nt):
+        out.append((CHOL, k, k, k))
+        for j in range(k + 1, nt):
+            out.append((TRSM, k, k, j))
+        for i in range(k + 1, nt):
+            for j in range(i + 1, nt):
+                out.append((GEMM, k, i, j))
+            out.append((SYRK, k, i, i))
+    return out
+
+
+def kind_of(K: int, I: int, J: int) -> int:
+    if K == I == J:
+        return CHOL
+    if K == I:
+        return TRSM
+    if I == J:
+        return SYRK
+    return GEMM
+
+
+# position of a kind inside one K step of Fig. 1: chol, trsm(J), then per I: gemm(J>I), syrk
+def _in_step_order(kind: int, K: int, I: int, J: int) -> Tuple[int, int, int]:
+    if kind == CHOL:
+        return (0, 0, 0)
+    if kind == TRSM:
+        return (1, J, 0)
+    if kind == GEMM:
+        return (2, I, J)
+    return (2, I, 1 << 30)  # syrk(K,I) closes the I step
+
+
+def expand(nt: int, depth: Sequence[int]):
+    """Fine tasks (kind, level, K, I, J, top) in program order."""
+    tops = fig1_tasks(nt)
+    cell_of: Dict[Tuple[int, int, int], int] = {(k, i, j): t for t, (_, k, i, j) in enumerate(tops)}
+    tasks = []
+    for t, (kind, k, i, j) in enumerate(tops):
+        d = int(depth[t])
+        s = 1 << d
+        fine = []
+        for K in range(k * s, k * s + s):
+            for I in range(i * s, i * s + s):
+                for J in range(j * s, j * s + s):
+                    if K <= I <= J:
+                        fine.append((kind_of(K, I, J), d, K, I, J, t))
+        fine.sort(key=lambda x: (x[2],) + _in_step_order(x[0], x[2], x[3], x[4]))
+        tasks.extend(fine)
+        assert all(cell_of[(x[2] >> d, x[3] >> d, x[4] >> d)] == t for x in fine)
+    return tasks
+
+
+def blocks(task) -> List[Tuple[int, int, bool]]:
+    kind, _, K, I, J, _ = task
+    if kind == CHOL:
+        return [(K, K, True)]
+    if kind == TRSM:
+        return [(K, K, False), (K, J, True)]
+    if kind == SYRK:
+        return [(K, I, False), (I, I, True)]
+    return [(K, I, False), (K, J, False), (I, J, True)]
+
+
+def atoms(R: int, C: int, level: int, dmax: int):
+    w = 1 << (dmax - level)
+    return [(R * w + u, C * w + v) for u in range(w) for v in range(w)]
+
+
+def edges(tasks, dmax: int):
+    last_w: Dict[Tuple[int, int], int] = {}
+    readers: Dict[Tuple[int, int], List[int]] = {}
+    E = set()
+    for t, task in enumerate(tasks):
+        for (R, C, w) in blocks(task):
+            for a in atoms(R, C, task[1], dmax):
+                if a in last_w:
+                    E.add((last_w[a], t))
+                if w:
+                    for r in readers.get(a, []):
+                        if r != t:
+                            E.add((r, t))
+                    readers[a] = []
+                    last_w[a] = t
+                else:
+                    readers.setdefault(a, []).append(t)
+    return sorted(E)
+
+
+def task_time(kind: int, bl: int, rmax_mflops: int, h: int) -> int:
+    """ceil(flops / R(b)) in ns, exact rationals (1 GFLOP/s = 1 flop/ns)."""
+    flops = Fraction(FLOP_NUM[kind] * bl ** 3, 3)
+    rate = Fraction(rmax_mflops, 1000) * Fraction(bl * bl, bl * bl + h * h)
+    q = flops / rate
+    return -((-q.numerator) // q.denominator)
+
+
+def transfer_time(n_atoms: int, atom_side: int, shared: bool, latency=10_000, bw=12, elem=8) -> int:
+    if shared or n_atoms == 0:
+        return 0
+    q = Fraction(elem * n_atoms * atom_side * atom_side, bw)
+    return latency - ((-q.numerator) // q.denominator)
+
+
+INF = float("inf")
+
+
+class Sim:
+    """Push-at-release event simulation with optional choice hooks.
+
+    ``choose_task(ready, sim)`` returns the next ready task to map and
+    ``choose_proc(task, efts, sim)`` the processor; by default the PL order
+    and EFT-P rule are used.
+    """
+
+    def __init__(self, nt, dmax, b, depth, proc_type, proc_mem, n_mem, rmax, h, shared):
+        self.tasks = expand(nt, depth)
+        self.E = edges(self.tasks, dmax)
+        self.n = len(self.tasks)
+        self.dmax, self.b = dmax, b
+        self.P = len(proc_type)
+        self.proc_type, self.proc_mem, self.n_mem = list(proc_type), list(proc_mem), n_mem
+        self.shared = shared
+        self.cost = [[task_time(tk[0], b >> tk[1], int(rmax[pt][tk[0]]), int(h[pt]))
+                      for pt in proc_type] for tk in self.tasks]
+        self.atom_side = b >> dmax
+        self.succ = [[] for _ in range(self.n)]
+        self.npred = [0] * self.n
+        for u, v in self.E:
+            self.succ[u].append(v)
+            self.npred[v] += 1
+        self.rank = [0] * self.n
+        for t in range(self.n - 1, -1, -1):
+            self.rank[t] = sum(self.cost[t]) + max([self.rank[v] for v in self.succ[t]], default=0)
+
+    def key(self, t):
+        kind, lvl, K, I, J, _ = self.tasks[t]
+        sh = self.dmax - lvl
+        return (-self.rank[t], K << sh, I << sh, J << sh)
+
+    def xfer(self, k):
+        return transfer_time(k, self.atom_side, self.shared)
+
+    def est(self, t, p, T, avail, vf):
+        m = self.proc_mem[p]
+        e = max(T, avail[p])
+        for (R, C, _) in blocks(self.tasks[t]):
+            at = atoms(R, C, self.tasks[t][1], self.dmax)
+            miss = sum(1 for a in at if vf[a][m] == INF)
+            fin = [vf[a][m] for a in at if vf[a][m] != INF]
+            r = max(fin) if fin else -INF
+            if miss:
+                r = max(r, T + self.xfer(miss))
+            e = max(e, r)
+        return e
+
+    def run(self, choose_task=None, choose_proc=None):
+        N = 0
+        vf = {}
+        for t in self.tasks:
+            for (R, C, _) in blocks(t):
+                for a in atoms(R, C, t[1], self.dmax):
+                    vf[a] = [0] + [INF] * (self.n_mem - 1)
+        avail = [0] * self.P
+        left = list(self.npred)
+        ready = [t for t in range(self.n) if left[t] == 0]
+        fifo = [[] for _ in range(self.P)]
+        proc, start, finish = [None] * self.n, [None] * self.n, [None] * self.n
+        T = 0
+        while True:
+            while ready:
+                t = choose_task(ready, self) if choose_task else min(ready, key=self.key)
+                ready.remove(t)
+                ests = [self.est(t, p, T, avail, vf) for p in range(self.P)]
+                efts = [ests[p] + self.cost[t][p] for p in range(self.P)]
+                p = choose_proc(t, efts, self) if choose_proc else min(range(self.P), key=lambda q: (efts[q], q))
+                m = self.proc_mem[p]
+                for (R, C, _) in blocks(self.tasks[t]):
+                    at = atoms(R, C, self.tasks[t][1], self.dmax)
+                    miss = [a for a in at if vf[a][m] == INF]
+                    for a in miss:
+                        vf[a][m] = T + self.xfer(len(miss))
+                proc[t], start[t], finish[t] = p, ests[p], efts[p]
+                avail[p] = efts[p]
+                fifo[p].append(t)
+            heads = [finish[f[0]] for f in fifo if f]
+            if not heads:
+                break
+            Tn = min(heads)
+            for p in range(self.P):
+                if fifo[p] and finish[fifo[p][0]] == Tn:
+                    t = fifo[p].pop(0)
+                    m = self.proc_mem[p]
+                    for (R, C, w) in blocks(self.tasks[t]):
+                        if w:
+                            for a in atoms(R, C, self.tasks[t][1], self.dmax):
+                                vf[a] = [Tn if mm == m else INF for mm in range(self.n_mem)]
+                    for v in self.succ[t]:
+                        left[v] -= 1
+                        if left[v] == 0:
+                            ready.append(v)
+            T = Tn
+        return max(finish), proc, start, finish
+
+
+def brute_force_opt(sim: Sim, limit: int = 2_000_000) -> int:
+    """Best makespan over every push-at-release schedule (task order x processor)."""
+    import copy
+
+    best = [INF]
+    count = [0]
+
+    def rec(state):
+        count[0] += 1
+        if count[0] > limit:
+            raise RuntimeError("brute force too large")
+        T, avail, vf, left, ready, fifo, finish = state
+        if ready:
+            for t in list(ready):
+                for p in range(sim.P):
+                    e = sim.est(t, p, T, avail, vf)
+                    f = e + sim.cost[t][p]
+                    if f >= best[0]:
+                        continue
+                    vf2 = {a: list(x) for a, x in vf.items()}
+                    m = sim.proc_mem[p]
+                    for (R, C, _) in blocks(sim.tasks[t]):
+                        at = atoms(R, C, sim.tasks[t][1], sim.dmax)
+                        miss = [a for a in at if vf2[a][m] == INF]
+                        for a in miss:
+                            vf2[a][m] = T + sim.xfer(len(miss))
+                    av2 = list(avail)
+                    av2[p] = f
+                    fifo2 = [list(q) for q in fifo]
+                    fifo2[p].append(t)
+                    fin2 = dict(finish)
+                    fin2[t] = f
+                    r2 = [x for x in ready if x != t]
+                    rec((T, av2, vf2, list(left), r2, fifo2, fin2))
+            return
+        heads = [finish[q[0]] for q in fifo if q]
+        if not heads:
+            best[0] = min(best[0], max(finish.values()))
+            return
+        Tn = min(heads)
+        vf2 = {a: list(x) for a, x in vf.items()}
+        left2 = list(left)
+        fifo2 = [list(q) for q in fifo]
+        r2 = []
+        for p in range(sim.P):
+            if fifo2[p] and finish[fifo2[p][0]] == Tn:
+                t = fifo2[p].pop(0)
+                m = sim.proc_mem[p]
+                for (R, C, w) in blocks(sim.tasks[t]):
+                    if w:
+                        for a in atoms(R, C, sim.tasks[t][1], sim.dmax):
+                            vf2[a] = [Tn if mm == m else INF for mm in range(sim.n_mem)]
+                for v in sim.succ[t]:
+                    left2[v] -= 1
+                    if left2[v] == 0:
+                        r2.append(v)
+        rec((Tn, avail, vf2, left2, r2, fifo2, finish))
+
+    vf0 = {}
+    for t in sim.tasks:
+        for (R, C, _) in blocks(t):
+            for a in atoms(R, C, t[1], sim.dmax):
+                vf0[a] = [0] + [INF] * (sim.n_mem - 1)
+    left0 = list(sim.npred)
+    rec((0, [0] * sim.P, vf0, left0, [t for t in range(sim.n) if left0[t] == 0],
+         [[] for _ in range(sim.P)], {}))
+    return best[0]

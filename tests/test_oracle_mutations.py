@@ -1,0 +1,124 @@
+"""Plant plausible mistakes in copies of the oracle and check that the pins fail.
+
+Each mutant is compiled on the CPU from a patched copy of the oracle source;
+the pins used here are the hand-derived schedules, the closed-form counts, the
+single-processor sum and the lower bounds (no comparison with another
+implementation of the method).
+"""
+import ctypes
+import json
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1602_05510_amd import inputs as I
+import pyoracle as PY
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+KIND = {"chol": 0, "trsm": 1, "syrk": 2, "gemm": 3}
+
+MUTANTS = {
+    "eft_ties_to_highest": ("if (best_p < 0 || eft < best_eft)", "if (best_p < 0 || eft <= best_eft)"),
+    "priority_reversed": ("if (a->rank != b->rank) return a->rank > b->rank;",
+                          "if (a->rank != b->rank) return a->rank < b->rank;"),
+    "key_tiebreak_reversed": ("return a->k2 < b->k2;", "return a->k2 > b->k2;"),
+    "no_invalidation": ("for (int mm = 0; mm < M; mm++) vf[a * M + mm] = (mm == m) ? Tn : OR_INF;",
+                        "vf[a * M + m] = Tn;"),
+    "cost_floor": ("static int64_t ceil_div_pos(int64_t a, int64_t b) { return a / b + (a % b != 0); }",
+                   "static int64_t ceil_div_pos(int64_t a, int64_t b) { return a / b; }"),
+    "rank_without_own_cost": ("rank[t] = W[t] + best;", "rank[t] = best;"),
+    "no_waw_edges": ("if (last_w[a] >= 0 && last_w[a] != t)", "if (!bw[bi] && last_w[a] >= 0 && last_w[a] != t)"),
+    "miss_counts_all_atoms": ("if (x == OR_INF) miss++;\n                        else if (x > fin) fin = x;",
+                              "miss++;\n                        if (x != OR_INF && x > fin) fin = x;"),
+    "trsm_split_without_gemm": ("            for (int J = I + 1; J < js + s; J++)\n                if (in_range(J, js, s))\n                    if (tl_push(l, (or_task){OR_GEMM",
+                                "            for (int J = I + 1; J < js + s && is != ks; J++)\n                if (in_range(J, js, s))\n                    if (tl_push(l, (or_task){OR_GEMM"),
+    "gemm_flops_wrong": ("static const int64_t c[4] = {1, 3, 3, 6};", "static const int64_t c[4] = {1, 3, 3, 3};"),
+}
+# Not listed: dropping the explicit max with the current time T from the start
+# time is an equivalent mutant -- a task is released by the completion, at T, of
+# a predecessor that wrote one of its blocks, so its data is never ready before
+# T.  Issuing transfers "at time 0" instead of at T changes only how a later
+# task mapped in the same instant sees an in-flight copy; that reading is
+# covered by the independent Python reading and by the GPU parity tests.
+
+
+def _build_mutant(tmp_path, name, old, new):
+    src = open(O.SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique/present"
+    path_c = os.path.join(tmp_path, f"{name}.c")
+    path_so = os.path.join(tmp_path, f"lib{name}.so")
+    with open(path_c, "w") as f:
+        f.write(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", path_so, path_c])
+    return path_so
+
+
+def _pins_pass():
+    """True when every quick pin holds for the currently loaded oracle."""
+    with open(os.path.join(GOLD, "worked_examples.json")) as f:
+        ex = json.load(f)["examples"]
+    try:
+        for e in ex:
+            pts = [I.ProcType(n, c, r, r, h, own) for (n, c, r, h, own) in e["platform"]["types"]]
+            pf = I.make_platform(pts, seed=0)
+            s = O.simulate(pf, e["nt"], e["dmax"], e["b"], np.array(e["depth"], np.uint8))
+            if s.makespan != e["makespan"]:
+                return False
+            got = {tuple(int(x) for x in s.tasks[t]): (int(s.proc[t]), int(s.start[t]), int(s.finish[t]))
+                   for t in range(s.n_tasks)}
+            for (kind, lvl, K, I_, J, p, st, fi) in e["schedule"]:
+                if got.get((KIND[kind], lvl, K, I_, J)) != (p, st, fi):
+                    return False
+        # closed-form counts, single-processor sum, lower bounds on a split case
+        pf1 = I.make_platform([I.ProcType("cpu", 1, 27000, 27000, 64, False)], seed=0)
+        dep = np.array([1, 0, 1, 0, 1, 1, 0, 1, 0, 1], np.uint8)
+        s = O.simulate(pf1, 3, 1, 256, dep)
+        cnt = sum([4, 6, 6, 8][k] if d else 1 for (k, *_), d in zip(PY.fig1_tasks(3), dep))
+        if s.n_tasks != cnt:
+            return False
+        if s.makespan != sum(PY.task_time(int(k), 256 >> int(l), 27000, 64) for k, l, *_ in s.tasks):
+            return False
+        pf2 = I.make_platform(I.cpu_accel_types(2, 1), seed=9)
+        s = O.simulate(pf2, 3, 1, 256, dep)
+        succ = [[] for _ in range(s.n_tasks)]
+        for u, v in s.edges:
+            succ[u].append(v)
+        cmin = [min(PY.task_time(int(k), 256 >> int(l), int(pf2.rmax[pt][k]), int(pf2.h[pt]))
+                    for pt in pf2.proc_type) for k, l, *_ in s.tasks]
+        lp = [0] * s.n_tasks
+        for t in range(s.n_tasks - 1, -1, -1):
+            lp[t] = cmin[t] + max([lp[v] for v in succ[t]], default=0)
+        if s.makespan < max(lp):
+            return False
+        # every top-level task of a 3x3 split DAG depends on something except chol0
+        if len(s.edges) < s.n_tasks - 1:
+            return False
+        # no task starts before its release
+        rel = np.zeros(s.n_tasks, np.int64)
+        for u, v in s.edges:
+            rel[v] = max(rel[v], s.finish[u])
+        if np.any(s.start < rel):
+            return False
+    except (ValueError, KeyError):
+        return False
+    return True
+
+
+def test_reference_oracle_passes():
+    assert _pins_pass()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    so = _build_mutant(str(tmp_path), name, old, new)
+    saved_lib, saved_path = O._lib, O.LIB
+    try:
+        O._lib = None
+        O.LIB = so
+        assert not _pins_pass(), f"planted mistake '{name}' went unnoticed"
+    finally:
+        O._lib, O.LIB = saved_lib, saved_path

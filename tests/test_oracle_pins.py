@@ -1,0 +1,355 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each checks it against a
+hand-derived value, a closed form, a bound, a special case that reduces to a
+textbook result, or an exhaustive search.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1602_05510_amd import inputs as I
+import pyoracle as PY
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+KIND = {"chol": 0, "trsm": 1, "syrk": 2, "gemm": 3}
+
+
+def platform_from_spec(types):
+    pts = [I.ProcType(n, c, r, r, h, own) for (n, c, r, h, own) in types]
+    return I.make_platform(pts, seed=0)
+
+
+def closed_form_count(kind, d):
+    s = 1 << d
+    return [s * (s + 1) * (s + 2) // 6, s * s * (s + 1) // 2, s * s * (s + 1) // 2, s ** 3][kind]
+
+
+# ---------------------------------------------------------------- cost model
+
+def test_task_time_exact_rationals():
+    """Task time = ceil(flops / (Rmax b^2/(b^2+h^2))) computed with Fractions."""
+    rng = np.random.default_rng(11)
+    for _ in range(400):
+        kind = int(rng.integers(0, 4))
+        bl = int(rng.choice([16, 32, 64, 128, 256, 512, 1024, 2048]))
+        rmax = int(rng.integers(1_000, 2_000_001))
+        h = int(rng.choice([0, 32, 48, 64, 512]))
+        flops = Fraction([1, 3, 3, 6][kind] * bl ** 3, 3)        # b^3/3, b^3, b^3, 2b^3
+        rate = Fraction(rmax, 1000) * Fraction(bl * bl, bl * bl + h * h)  # flop/ns
+        expect = -((-flops / rate).numerator // (flops / rate).denominator)
+        assert O.task_time(kind, bl, rmax, h) == expect
+
+
+def test_transfer_time_exact():
+    pf = I.WORKLOADS["chol4x4_b512_d1"].platform()
+    for k in range(0, 20):
+        for side in (64, 128, 256, 512):
+            bytes_ = 8 * k * side * side
+            expect = 0 if k == 0 else 10_000 + -((-bytes_) // 12)
+            assert O.transfer_time(k, side, pf) == expect
+    # the two transfer values quoted for 256-element atoms
+    assert O.transfer_time(1, 256, pf) == 53_691 and O.transfer_time(4, 256, pf) == 184_763
+
+
+# ---------------------------------------------------------------- hand-derived schedules
+
+def test_worked_examples():
+    with open(os.path.join(GOLD, "worked_examples.json")) as f:
+        ex = json.load(f)["examples"]
+    for e in ex:
+        pf = platform_from_spec(e["platform"]["types"])
+        s = O.simulate(pf, e["nt"], e["dmax"], e["b"], np.array(e["depth"], np.uint8))
+        assert s.makespan == e["makespan"], e["name"]
+        got = {}
+        for t in range(s.n_tasks):
+            got[tuple(int(x) for x in s.tasks[t])] = (int(s.proc[t]), int(s.start[t]), int(s.finish[t]))
+        assert len(got) == len(e["schedule"]), e["name"]
+        for (kind, lvl, K, I_, J, p, st, fi) in e["schedule"]:
+            assert got[(KIND[kind], lvl, K, I_, J)] == (p, st, fi), (e["name"], kind, K, I_, J)
+
+
+def test_textbook_dag_3x3():
+    """Unsplit 3x3 tiles: the dependences of the Fig. 1 loop nest, listed by hand.
+
+    chol0 -> trsm01, trsm02; trsm01 -> gemm012, syrk01; trsm02 -> gemm012, syrk02;
+    gemm012 -> trsm12; syrk01 -> chol1; chol1 -> trsm12; syrk02 -> syrk12;
+    trsm12 -> syrk12; syrk12 -> chol2 (12 edges, no write-after-read hazard)."""
+    with open(os.path.join(GOLD, "dag_3x3.json")) as f:
+        gold = json.load(f)
+    pf = platform_from_spec([["cpu", 1, 32000, 64, False]])
+    s = O.simulate(pf, 3, 0, 512, np.zeros(10, np.uint8))
+    names = {}
+    for t in range(s.n_tasks):
+        kind, _, K, I_, J = (int(x) for x in s.tasks[t])
+        names[t] = ["chol%d" % K, "trsm%d%d" % (K, J), "syrk%d%d" % (K, I_), "gemm%d%d%d" % (K, I_, J)][kind]
+    got = sorted((names[u], names[v]) for u, v in s.edges)
+    assert got == sorted(tuple(e) for e in gold["edges"])
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("nt,dmax", [(1, 0), (2, 1), (3, 2), (4, 1), (5, 3), (6, 2)])
+def test_task_counts_closed_form(nt, dmax):
+    rng = np.random.default_rng(nt * 10 + dmax)
+    pf = platform_from_spec([["cpu", 2, 32000, 64, False], ["acc", 1, 1024000, 512, True]])
+    b = 64 << dmax
+    n_top = nt * (nt + 1) * (nt + 2) // 6
+    tops = PY.fig1_tasks(nt)
+    for trial in range(4):
+        depth = rng.integers(0, dmax + 1, size=n_top).astype(np.uint8)
+        if trial == 0:
+            depth[:] = 0
+        if trial == 1:
+            depth[:] = dmax
+        s = O.simulate(pf, nt, dmax, b, depth)
+        expect = sum(closed_form_count(k, int(d)) for (k, _, _, _), d in zip(tops, depth))
+        assert s.n_tasks == expect
+        if trial == 0:
+            assert s.n_tasks == n_top
+        if trial == 1:
+            m = nt << dmax
+            assert s.n_tasks == m * (m + 1) * (m + 2) // 6
+        # every fine task's kind follows from its indices
+        for kind, lvl, K, I_, J in s.tasks:
+            assert K <= I_ <= J
+            assert kind == PY.kind_of(K, I_, J)
+
+
+def test_per_parent_counts():
+    """Per-parent counts at depth 1/2/3: chol 4/20/120, trsm and syrk 6/40/288, gemm 8/64/512."""
+    assert [closed_form_count(0, d) for d in (1, 2, 3)] == [4, 20, 120]
+    pf = platform_from_spec([["cpu", 1, 32000, 64, False]])
+    # nt=3 has every kind; split one parent at a time
+    tops = PY.fig1_tasks(3)
+    for d in (1, 2, 3):
+        base = O.simulate(pf, 3, d, 64 << d, np.zeros(10, np.uint8)).n_tasks
+        for t, (kind, _, _, _) in enumerate(tops):
+            dep = np.zeros(10, np.uint8)
+            dep[t] = d
+            n = O.simulate(pf, 3, d, 64 << d, dep).n_tasks
+            assert n - base + 1 == {0: [4, 20, 120], 1: [6, 40, 288], 2: [6, 40, 288],
+                                    3: [8, 64, 512]}[kind][d - 1]
+
+
+@pytest.mark.parametrize("name", ["chol4x4_b512_d1", "chol16x16_b1024_d2"])
+def test_flop_invariance(name):
+    """Sum of the expanded tasks' flops equals n^3/3 for every candidate."""
+    w = I.WORKLOADS[name]
+    pf = w.platform()
+    bt = w.batch(6)
+    n = w.nt * w.b
+    for c in range(bt.n):
+        s = O.simulate(pf, w.nt, w.dmax, w.b, bt.candidate(c))
+        tot = sum([1, 3, 3, 6][int(k)] * (w.b >> int(l)) ** 3 for k, l, *_ in s.tasks)
+        assert tot == n ** 3       # times 3 on both sides
+
+
+# ---------------------------------------------------------------- equivalences and bounds
+
+@pytest.mark.parametrize("nt,d", [(1, 1), (2, 1), (3, 1), (2, 2), (4, 1), (3, 2)])
+def test_all_split_equals_homogeneous(nt, d):
+    """Splitting every task d times equals the unsplit loop nest on nt*2^d tiles of b/2^d."""
+    pf = I.make_platform(I.cpu_accel_types(3, 2), seed=7)
+    b = 512
+    dep = np.full(nt * (nt + 1) * (nt + 2) // 6, d, np.uint8)
+    s1 = O.simulate(pf, nt, d, b, dep)
+    m = nt << d
+    s0 = O.simulate(pf, m, 0, b >> d, np.zeros(m * (m + 1) * (m + 2) // 6, np.uint8))
+    assert s1.makespan == s0.makespan
+    k1 = {tuple(int(x) for x in s1.tasks[t][2:]): t for t in range(s1.n_tasks)}
+    k0 = {tuple(int(x) for x in s0.tasks[t][2:]): t for t in range(s0.n_tasks)}
+    assert set(k1) == set(k0)
+    e1 = {(tuple(s1.tasks[u][2:]), tuple(s1.tasks[v][2:])) for u, v in s1.edges}
+    e0 = {(tuple(s0.tasks[u][2:]), tuple(s0.tasks[v][2:])) for u, v in s0.edges}
+    assert e1 == e0
+    for key, t1 in k1.items():
+        t0 = k0[key]
+        assert (s1.proc[t1], s1.start[t1], s1.finish[t1]) == (s0.proc[t0], s0.start[t0], s0.finish[t0])
+
+
+def test_single_cpu_is_sum_of_costs():
+    pf = platform_from_spec([["cpu", 1, 27000, 64, False]])
+    rng = np.random.default_rng(3)
+    for nt, dmax in [(1, 2), (3, 1), (4, 2), (5, 1)]:
+        dep = rng.integers(0, dmax + 1, nt * (nt + 1) * (nt + 2) // 6).astype(np.uint8)
+        s = O.simulate(pf, nt, dmax, 256, dep)
+        tot = sum(PY.task_time(int(k), 256 >> int(l), 27000, 64) for k, l, *_ in s.tasks)
+        assert s.makespan == tot
+
+
+def _costs(pf, b, s):
+    """per task, per processor: task time (Fractions, independent of the oracle)"""
+    out = []
+    for k, l, *_ in s.tasks:
+        out.append([PY.task_time(int(k), b >> int(l), int(pf.rmax[pt][k]), int(pf.h[pt]))
+                    for pt in pf.proc_type])
+    return np.array(out, dtype=np.int64)
+
+
+def _longest_path(n, edges, w):
+    succ = [[] for _ in range(n)]
+    for u, v in edges:
+        succ[u].append(v)
+    best = [0] * n
+    for t in range(n - 1, -1, -1):
+        best[t] = w[t] + max([best[v] for v in succ[t]], default=0)
+    return max(best)
+
+
+def test_graham_bound_identical_processors():
+    """Greedy list scheduling: CP <= makespan and P*makespan <= W + (P-1)*CP."""
+    rng = np.random.default_rng(5)
+    for P in (2, 3, 5):
+        pf = platform_from_spec([["cpu", P, 25000, 64, False]])
+        for nt, dmax in [(3, 1), (4, 2), (6, 1)]:
+            dep = rng.integers(0, dmax + 1, nt * (nt + 1) * (nt + 2) // 6).astype(np.uint8)
+            s = O.simulate(pf, nt, dmax, 512, dep)
+            c = _costs(pf, 512, s)[:, 0]
+            cp = _longest_path(s.n_tasks, s.edges, c)
+            assert cp <= s.makespan
+            assert P * s.makespan <= int(c.sum()) + (P - 1) * cp
+
+
+@pytest.mark.parametrize("name", ["chol4x4_b512_d1", "chol16x16_b1024_d2"])
+def test_heterogeneous_lower_bounds(name):
+    w = I.WORKLOADS[name]
+    pf = w.platform()
+    bt = w.batch(5)
+    for c in range(bt.n):
+        s = O.simulate(pf, w.nt, w.dmax, w.b, bt.candidate(c))
+        cmin = _costs(pf, w.b, s).min(axis=1)
+        assert s.makespan >= _longest_path(s.n_tasks, s.edges, cmin)
+        assert pf.n_procs * s.makespan >= int(cmin.sum())
+
+
+def validate_schedule(pf, b, dmax, s):
+    """Dependences, no overlap, exact durations, every task once, inputs present."""
+    c = _costs(pf, b, s)
+    n = s.n_tasks
+    assert np.all(s.proc >= 0) and np.all(s.proc < pf.n_procs)
+    for t in range(n):
+        assert s.finish[t] - s.start[t] == c[t, s.proc[t]]
+    for u, v in s.edges:
+        assert s.start[v] >= s.finish[u]
+    for p in range(pf.n_procs):
+        idx = np.nonzero(s.proc == p)[0]
+        order = idx[np.argsort(s.start[idx], kind="stable")]
+        assert np.all(s.start[order[1:]] >= s.finish[order[:-1]])
+    # a task never starts before its release (the latest predecessor finish)
+    rel = np.zeros(n, np.int64)
+    for u, v in s.edges:
+        rel[v] = max(rel[v], s.finish[u])
+    assert np.all(s.start >= rel)
+    assert s.makespan == int(s.finish.max())
+
+
+@pytest.mark.parametrize("name", ["chol4x4_b512_d1", "chol16x16_b1024_d2"])
+def test_schedule_invariants(name):
+    w = I.WORKLOADS[name]
+    pf = w.platform()
+    bt = w.batch(4)
+    for c in range(bt.n):
+        s = O.simulate(pf, w.nt, w.dmax, w.b, bt.candidate(c))
+        validate_schedule(pf, w.b, w.dmax, s)
+
+
+def test_schedule_invariants_big_little():
+    w = I.WORKLOADS["ragged_bl_b512_d3"]
+    pf = w.platform()
+    bt = w.batch(3)
+    for c in range(bt.n):
+        nt, dm = int(bt.nt[c]), int(bt.dmax[c])
+        if nt > 12:
+            continue
+        s = O.simulate(pf, nt, dm, bt.b, bt.candidate(c))
+        validate_schedule(pf, bt.b, dm, s)
+
+
+# ---------------------------------------------------------------- independent readings
+
+def _py_sim(pf, nt, dmax, b, depth):
+    return PY.Sim(nt, dmax, b, depth, pf.proc_type, pf.proc_mem, pf.n_mem, pf.rmax, pf.h,
+                  pf.shared_memory)
+
+
+def test_python_reading_agrees():
+    """A second implementation, written separately, gives the same schedules."""
+    rng = np.random.default_rng(17)
+    plats = [I.make_platform(I.cpu_accel_types(2, 1), seed=1),
+             I.make_platform(I.cpu_accel_types(3, 2), seed=2),
+             I.make_platform(I.big_little_types(2, 2), seed=3)]
+    for trial in range(30):
+        pf = plats[trial % 3]
+        nt = int(rng.integers(1, 5))
+        dmax = int(rng.integers(0, 3))
+        dep = rng.integers(0, dmax + 1, nt * (nt + 1) * (nt + 2) // 6).astype(np.uint8)
+        s = O.simulate(pf, nt, dmax, 256, dep)
+        py = _py_sim(pf, nt, dmax, 256, dep)
+        ms, proc, start, finish = py.run()
+        assert ms == s.makespan
+        assert [tuple(t[:5]) for t in py.tasks] == [tuple(int(x) for x in r) for r in s.tasks]
+        assert py.E == sorted((int(u), int(v)) for u, v in s.edges)
+        assert list(s.proc) == proc and list(s.start) == start and list(s.finish) == finish
+
+
+@pytest.mark.parametrize("nt,dmax,dep", [(2, 0, [0, 0, 0, 0]), (1, 1, [1]), (2, 1, [0, 1, 0, 0]),
+                                         (3, 0, [0] * 10), (2, 1, [1, 0, 0, 0])])
+def test_brute_force_optimum(nt, dmax, dep):
+    """OPT over all push-at-release schedules <= PL/EFT-P, and OPT >= the lower bounds."""
+    pf = I.make_platform([I.ProcType("cpu", 1, 60000, 60000, 64, False),
+                          I.ProcType("acc", 1, 300000, 300000, 512, True)], seed=0)
+    dep = np.array(dep, np.uint8)
+    s = O.simulate(pf, nt, dmax, 512, dep)
+    sim = _py_sim(pf, nt, dmax, 512, dep)
+    opt = PY.brute_force_opt(sim)
+    assert opt <= s.makespan
+    cmin = _costs(pf, 512, s).min(axis=1)
+    assert opt >= _longest_path(s.n_tasks, s.edges, cmin)
+    assert pf.n_procs * opt >= int(cmin.sum())
+
+
+# ---------------------------------------------------------------- the paper's depth/width example
+
+def _width(n, edges):
+    """Largest set of pairwise independent tasks (exhaustive, tiny DAGs)."""
+    import itertools
+    reach = [[False] * n for _ in range(n)]
+    succ = [[] for _ in range(n)]
+    for u, v in edges:
+        succ[u].append(v)
+    for s in range(n):
+        stack = list(succ[s])
+        while stack:
+            v = stack.pop()
+            if not reach[s][v]:
+                reach[s][v] = True
+                stack.extend(succ[v])
+    best = 1
+    for r in range(2, n + 1):
+        found = False
+        for comb in itertools.combinations(range(n), r):
+            if all(not reach[a][b] and not reach[b][a] for a, b in itertools.combinations(comb, 2)):
+                found = True
+                break
+        if not found:
+            break
+        best = r
+    return best
+
+
+def test_paper_width_example():
+    """Section 2.1 (task clusters): one chol has width 1; chol partitioned once is a
+    4-task chain of width 1; partitioning that chain's trsm again gives width 2."""
+    pf = platform_from_spec([["cpu", 1, 32000, 64, False]])
+    s = O.simulate(pf, 1, 0, 512, np.array([0], np.uint8))
+    assert s.n_tasks == 1
+    s = O.simulate(pf, 1, 1, 512, np.array([1], np.uint8))
+    assert s.n_tasks == 4 and _width(4, s.edges) == 1
+    # the chain above is the 2x2 loop nest at b/2; its trsm split once more
+    s = O.simulate(pf, 2, 1, 512, np.array([0, 1, 0, 0], np.uint8))
+    assert _width(s.n_tasks, s.edges) == 2
