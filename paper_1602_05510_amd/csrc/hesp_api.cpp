@@ -1,0 +1,379 @@
+// hesp_api.cpp -- implementation of the C ABI declared in include/hesp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hesp.h"
+#include "hesp_core.h"
+#include "hesp_internal.h"
+
+using namespace hesp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() { return HESP_OK; }
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(HESP_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t pow4(int x) { return (int64_t)1 << (2 * x); }
+
+void hfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+// exact ceil(a / b) for a >= 0, b > 0 with a 128-bit numerator
+int64_t ceil_div128(__int128 a, __int128 b) { return (int64_t)((a + b - 1) / b); }
+
+}  // namespace
+
+struct hesp_plan {
+  hesp_plan_opts opts{};
+  int32_t slots = 0;
+  char* ws = nullptr;
+  int64_t ws_bytes = 0;
+  uint32_t* counter = nullptr;
+  int32_t* cnt_tasks = nullptr;   // auto sizing buffers
+  int64_t* cnt_edges = nullptr;
+  int64_t* max2 = nullptr;
+  int32_t cnt_cap = 0;
+};
+
+extern "C" {
+
+const char* hesp_last_error(void) { return g_err.c_str(); }
+const char* hesp_version(void) { return "hesp-mi355x 0.1 (gfx950)"; }
+
+int hesp_cost_tables(const hesp_cost_model* cm, int64_t* cost_ns, int64_t* xfer_ns) {
+  if (!cm || !cost_ns || !xfer_ns) return fail(HESP_EINVAL, "hesp_cost_tables: null argument");
+  if (cm->n_ptypes < 1 || cm->n_ptypes > HESP_MAX_PTYPES || !cm->rmax_mflops || !cm->h)
+    return fail(HESP_EINVAL, "hesp_cost_tables: bad processor types");
+  if (cm->max_level < 0 || cm->max_level > HESP_MAX_LEVEL) return fail(HESP_EINVAL, "hesp_cost_tables: max_level");
+  if (cm->b <= 0 || ((cm->b >> cm->max_level) << cm->max_level) != cm->b)
+    return fail(HESP_EINVAL, "hesp_cost_tables: b must be a positive multiple of 2^max_level");
+  if (cm->bw_bytes_per_ns <= 0 || cm->latency_ns < 0 || cm->elem_bytes <= 0)
+    return fail(HESP_EINVAL, "hesp_cost_tables: transfer model");
+  static const int64_t c3[4] = {1, 3, 3, 6};  // flops * 3 / bl^3
+  const int L = cm->max_level + 1;
+  for (int pt = 0; pt < cm->n_ptypes; pt++) {
+    const int64_t h = cm->h[pt];
+    if (h < 0) return fail(HESP_EINVAL, "hesp_cost_tables: h < 0");
+    for (int k = 0; k < 4; k++) {
+      const int64_t r = cm->rmax_mflops[pt * 4 + k];
+      if (r <= 0) return fail(HESP_EINVAL, "hesp_cost_tables: rmax <= 0");
+      for (int l = 0; l < L; l++) {
+        const int64_t bl = cm->b >> l;
+        // time = (c3 bl^3 / 3) / (r/1000 * bl^2/(bl^2+h^2)) = 1000 c3 bl (bl^2+h^2) / (3 r)
+        const __int128 num = (__int128)1000 * c3[k] * bl * ((__int128)bl * bl + (__int128)h * h);
+        cost_ns[(pt * 4 + k) * L + l] = ceil_div128(num, (__int128)3 * r);
+      }
+    }
+  }
+  const int64_t a = cm->b >> cm->max_level;
+  for (int64_t k = 0; k <= pow4(cm->max_level); k++) {
+    if (k == 0 || cm->shared_memory) xfer_ns[k] = 0;
+    else xfer_ns[k] = cm->latency_ns + ceil_div128((__int128)cm->elem_bytes * k * a * a, cm->bw_bytes_per_ns);
+  }
+  return ok();
+}
+
+int hesp_expand(int32_t nt, int32_t dmax, const uint8_t* depth, int32_t* n_tasks, int64_t* n_edges,
+                hesp_task* tasks, int64_t* succ_ptr, int32_t* succ_idx) {
+  if (nt < 1 || dmax < 0 || dmax > HESP_MAX_LEVEL || (nt << dmax) > HESP_MAX_FINE)
+    return fail(HESP_EINVAL, "hesp_expand: nt=%d dmax=%d outside 1 <= nt, 0 <= dmax <= %d, nt*2^dmax <= %d", nt,
+                dmax, HESP_MAX_LEVEL, HESP_MAX_FINE);
+  if (!depth || !n_tasks || !n_edges) return fail(HESP_EINVAL, "hesp_expand: null argument");
+  const int64_t n_top = tet3(nt);
+  for (int64_t t = 0; t < n_top; t++)
+    if (depth[t] > dmax) return fail(HESP_EINVAL, "hesp_expand: depth[%lld]=%d > dmax", (long long)t, depth[t]);
+  std::vector<int64_t> first(n_top + 1);
+  std::vector<uint32_t> cells(n_top);
+  first[0] = 0;
+  for (int64_t t = 0; t < n_top; t++) {
+    cells[t] = top_cell(nt, t);
+    first[t + 1] = first[t] + fine_count(kind_of(cell_k(cells[t]), cell_i(cells[t]), cell_j(cells[t])), depth[t]);
+  }
+  const int64_t n = first[n_top];
+  auto depth_of = [&](int64_t t) { return (int)depth[t]; };
+  auto first_of = [&](int64_t t) { return first[t]; };
+  // enumerate (task number, top, cell, d, K, I, J)
+  auto each_task = [&](auto&& fn) {
+    for (int64_t t = 0; t < n_top; t++) {
+      const uint32_t cell = cells[t];
+      const int d = depth[t], s = 1 << d;
+      const int kind = kind_of(cell_k(cell), cell_i(cell), cell_j(cell));
+      for (int64_t x = 0; x < first[t + 1] - first[t]; x++) {
+        int q, r, c;
+        local_coords(kind, s, (int)x, q, r, c);
+        fn(first[t] + x, t, cell, d, cell_k(cell) * s + q, cell_i(cell) * s + r, cell_j(cell) * s + c);
+      }
+    }
+  };
+  std::vector<int64_t> cnt(n + 1, 0);
+  int64_t m = 0;
+  each_task([&](int64_t f, int64_t t, uint32_t cell, int d, int K, int I, int J) {
+    (void)f;
+    m += for_each_pred(nt, depth_of, first_of, t, cell, d, K, I, J, [&](int64_t p) { cnt[p + 1]++; });
+  });
+  if (n > INT32_MAX) return fail(HESP_EUNSUPPORTED, "hesp_expand: too many tasks");
+  *n_tasks = (int32_t)n;
+  *n_edges = m;
+  if (!tasks && !succ_ptr && !succ_idx) return ok();
+  if (!tasks || !succ_ptr || !succ_idx) return fail(HESP_EINVAL, "hesp_expand: give all or none of the arrays");
+  for (int64_t f = 0; f < n; f++) cnt[f + 1] += cnt[f];
+  for (int64_t f = 0; f <= n; f++) succ_ptr[f] = cnt[f];
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  each_task([&](int64_t f, int64_t t, uint32_t cell, int d, int K, int I, int J) {
+    tasks[f] = hesp_task{kind_of(K, I, J), d, K, I, J};
+    for_each_pred(nt, depth_of, first_of, t, cell, d, K, I, J,
+                  [&](int64_t p) { succ_idx[pos[p]++] = (int32_t)f; });
+  });
+  return ok();
+}
+
+// ---- generation -------------------------------------------------------------
+
+static int check_thr(uint32_t thr) {
+  return thr <= (1u << 21) ? HESP_OK : fail(HESP_EINVAL, "split_thr must be <= 2^21");
+}
+
+int hesp_generate_uniform(uint64_t seed, int64_t first, int32_t n_cand, int32_t nt, int32_t dmax,
+                          uint32_t split_thr, uint8_t* d_depth, void* stream) {
+  if (n_cand < 0 || nt < 1 || dmax < 0 || dmax > HESP_MAX_LEVEL || first < 0 || (!d_depth && n_cand > 0))
+    return fail(HESP_EINVAL, "hesp_generate_uniform: bad argument");
+  if (check_thr(split_thr)) return HESP_EINVAL;
+  HIP_TRY(launch_gen_uniform(seed, first, n_cand, nt, dmax, split_thr, d_depth, (hipStream_t)stream));
+  return ok();
+}
+
+int hesp_generate_ragged_shape(uint64_t seed, int64_t first, int32_t n_cand, int32_t nt_lo, int32_t nt_hi,
+                               int32_t dmax_hi, int32_t* d_nt, int32_t* d_dmax, int64_t* d_mask_off,
+                               void* stream) {
+  if (n_cand < 0 || nt_lo < 1 || nt_hi < nt_lo || dmax_hi < 0 || dmax_hi > HESP_MAX_LEVEL || first < 0 ||
+      !d_mask_off || (n_cand > 0 && (!d_nt || !d_dmax)))
+    return fail(HESP_EINVAL, "hesp_generate_ragged_shape: bad argument");
+  HIP_TRY(launch_gen_shape(seed, first, n_cand, nt_lo, nt_hi, dmax_hi, d_nt, d_dmax, d_mask_off,
+                           (hipStream_t)stream));
+  return ok();
+}
+
+static int batch_view(const hesp_batch* b, BatchView& v, const char* who) {
+  if (!b) return fail(HESP_EINVAL, "%s: null batch", who);
+  if (b->n_cand < 0 || (b->n_cand > 0 && !b->d_depth)) return fail(HESP_EINVAL, "%s: bad batch", who);
+  if ((b->d_nt == nullptr) != (b->d_dmax == nullptr))
+    return fail(HESP_EINVAL, "%s: give both or neither of d_nt and d_dmax", who);
+  if (b->d_nt && !b->d_mask_off) return fail(HESP_EINVAL, "%s: a ragged batch needs d_mask_off", who);
+  if (b->nt < 1 || b->dmax < 0 || b->dmax > HESP_MAX_LEVEL || (b->nt << b->dmax) > HESP_MAX_FINE)
+    return fail(HESP_EINVAL, "%s: nt=%d dmax=%d outside the supported range", who, b->nt, b->dmax);
+  v.n_cand = b->n_cand;
+  v.nt = b->nt;
+  v.dmax = b->dmax;
+  v.nt_arr = b->d_nt;
+  v.dmax_arr = b->d_dmax;
+  v.off = b->d_mask_off;
+  v.depth = b->d_depth;
+  return HESP_OK;
+}
+
+int hesp_generate_ragged_depth(uint64_t seed, int64_t first, const hesp_batch* batch, uint32_t split_thr,
+                               uint8_t* d_depth, void* stream) {
+  BatchView v;
+  hesp_batch b2 = batch ? *batch : hesp_batch{};
+  b2.d_depth = d_depth;
+  if (int r = batch_view(&b2, v, "hesp_generate_ragged_depth")) return r;
+  if (!v.nt_arr) return fail(HESP_EINVAL, "hesp_generate_ragged_depth: needs d_nt, d_dmax, d_mask_off");
+  if (check_thr(split_thr)) return HESP_EINVAL;
+  HIP_TRY(launch_gen_ragged_depth(seed, first, v, split_thr, d_depth, (hipStream_t)stream));
+  return ok();
+}
+
+int hesp_count_batch(const hesp_batch* batch, int32_t* d_n_tasks, int64_t* d_n_edges, void* stream) {
+  BatchView v;
+  if (int r = batch_view(batch, v, "hesp_count_batch")) return r;
+  HIP_TRY(launch_count(v, d_n_tasks, d_n_edges, (hipStream_t)stream));
+  return ok();
+}
+
+// ---- plans -------------------------------------------------------------------
+
+int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
+  if (!plan) return fail(HESP_EINVAL, "hesp_plan_create: null plan");
+  hesp_plan* p = new (std::nothrow) hesp_plan();
+  if (!p) return fail(HESP_ENOMEM, "hesp_plan_create: out of host memory");
+  if (opts) p->opts = *opts;
+  if (p->opts.slots < 0 || p->opts.max_tasks < 0 || p->opts.max_edges < 0 || p->opts.max_nt < 0) {
+    delete p;
+    return fail(HESP_EINVAL, "hesp_plan_create: negative option");
+  }
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(HESP_EHIP, "hesp_plan_create: %s", hipGetErrorString(e));
+  }
+  p->slots = p->opts.slots ? p->opts.slots : 8 * cus;
+  e = hipMalloc(&p->counter, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&p->max2, 2 * sizeof(int64_t));
+  if (e != hipSuccess) {
+    hfree(p->counter);
+    delete p;
+    return fail(HESP_ENOMEM, "hesp_plan_create: %s", hipGetErrorString(e));
+  }
+  *plan = p;
+  return ok();
+}
+
+int hesp_plan_destroy(hesp_plan* p) {
+  if (!p) return ok();
+  hfree(p->ws);
+  hfree(p->counter);
+  hfree(p->max2);
+  hfree(p->cnt_tasks);
+  hfree(p->cnt_edges);
+  delete p;
+  return ok();
+}
+
+int hesp_plan_bytes(const hesp_plan* p, int64_t* bytes) {
+  if (!p || !bytes) return fail(HESP_EINVAL, "hesp_plan_bytes: null argument");
+  *bytes = p->ws_bytes;
+  return ok();
+}
+
+static int build_tables(const hesp_platform* pf, SimTables& t) {
+  if (!pf) return fail(HESP_EINVAL, "hesp_simulate_batch: null platform");
+  if (pf->n_procs < 1 || pf->n_procs > HESP_MAX_PROCS || pf->n_ptypes < 1 || pf->n_ptypes > HESP_MAX_PTYPES ||
+      pf->n_mem < 1 || pf->n_mem > HESP_MAX_MEM || pf->max_level < 0 || pf->max_level > HESP_MAX_LEVEL ||
+      !pf->proc_type || !pf->proc_mem || !pf->cost_ns || !pf->xfer_ns)
+    return fail(HESP_EINVAL, "hesp_simulate_batch: bad platform description");
+  memset(&t, 0, sizeof t);
+  t.n_procs = pf->n_procs;
+  t.n_ptypes = pf->n_ptypes;
+  t.n_mem = pf->n_mem;
+  t.max_level = pf->max_level;
+  const int L = pf->max_level + 1;
+  for (int p = 0; p < pf->n_procs; p++) {
+    if (pf->proc_type[p] < 0 || pf->proc_type[p] >= pf->n_ptypes || pf->proc_mem[p] < 0 ||
+        pf->proc_mem[p] >= pf->n_mem)
+      return fail(HESP_EINVAL, "hesp_simulate_batch: processor %d has a bad type or memory space", p);
+    t.proc_type[p] = (int8_t)pf->proc_type[p];
+    t.proc_mem[p] = (int8_t)pf->proc_mem[p];
+  }
+  for (int pt = 0; pt < pf->n_ptypes; pt++)
+    for (int k = 0; k < 4; k++)
+      for (int l = 0; l < L; l++) {
+        const int64_t c = pf->cost_ns[(pt * 4 + k) * L + l];
+        if (c < 1 || c > ((int64_t)1 << 40)) return fail(HESP_EINVAL, "hesp_simulate_batch: task time out of range");
+        t.cost[pt][k][l] = c;
+      }
+  for (int p = 0; p < pf->n_procs; p++)
+    for (int k = 0; k < 4; k++)
+      for (int l = 0; l < L; l++) t.W[k][l] += t.cost[t.proc_type[p]][k][l];
+  const int64_t nx = pow4(pf->max_level) + 1;
+  if (pf->xfer_ns[0] != 0) return fail(HESP_EINVAL, "hesp_simulate_batch: xfer_ns[0] must be 0");
+  for (int64_t k = 0; k < nx; k++) {
+    if (pf->xfer_ns[k] < 0 || pf->xfer_ns[k] > ((int64_t)1 << 40) || (k > 0 && pf->xfer_ns[k] < pf->xfer_ns[k - 1]))
+      return fail(HESP_EINVAL, "hesp_simulate_batch: xfer_ns must be non-decreasing and in range");
+    t.xfer[k] = pf->xfer_ns[k];
+  }
+  return HESP_OK;
+}
+
+int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,
+                        const hesp_outputs* out, void* stream) {
+  if (!plan) return fail(HESP_EINVAL, "hesp_simulate_batch: null plan");
+  if (policy.order != HESP_ORDER_PL || policy.select != HESP_SELECT_EFT || policy.cache != HESP_CACHE_WB)
+    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: only PL order, EFT-P selection and WB caching");
+  SimTables tb;
+  if (int r = build_tables(pf, tb)) return r;
+  BatchView bv;
+  if (int r = batch_view(batch, bv, "hesp_simulate_batch")) return r;
+  if (bv.dmax > pf->max_level) return fail(HESP_EINVAL, "hesp_simulate_batch: dmax above the platform's max_level");
+  if (!out || !out->d_makespan || !out->d_status) return fail(HESP_EINVAL, "hesp_simulate_batch: null outputs");
+  if (out->d_sched_off && (!out->d_proc || !out->d_start || !out->d_finish))
+    return fail(HESP_EINVAL, "hesp_simulate_batch: schedule outputs need proc, start and finish");
+  if (bv.n_cand == 0) return ok();
+  hipStream_t s = (hipStream_t)stream;
+
+  // capacities
+  int64_t cap_tasks = plan->opts.max_tasks, cap_edges = plan->opts.max_edges;
+  const int max_nt = plan->opts.max_nt ? std::max(plan->opts.max_nt, bv.nt) : std::max(64, bv.nt);
+  if (cap_tasks == 0 || cap_edges == 0) {
+    if (plan->cnt_cap < bv.n_cand) {
+      hfree(plan->cnt_tasks);
+      hfree(plan->cnt_edges);
+      plan->cnt_tasks = nullptr;
+      plan->cnt_edges = nullptr;
+      plan->cnt_cap = 0;
+      HIP_TRY(hipMalloc(&plan->cnt_tasks, sizeof(int32_t) * bv.n_cand));
+      HIP_TRY(hipMalloc(&plan->cnt_edges, sizeof(int64_t) * bv.n_cand));
+      plan->cnt_cap = bv.n_cand;
+    }
+    HIP_TRY(launch_count(bv, plan->cnt_tasks, plan->cnt_edges, s));
+    HIP_TRY(launch_max_i32_i64(plan->cnt_tasks, plan->cnt_edges, bv.n_cand, plan->max2, s));
+    int64_t mx[2];
+    HIP_TRY(hipMemcpyAsync(mx, plan->max2, sizeof mx, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (cap_tasks == 0) cap_tasks = std::max<int64_t>(mx[0], 1);
+    if (cap_edges == 0) cap_edges = std::max<int64_t>(mx[1], 1);
+  }
+  const int64_t cap_tops = tet3(bv.nt_arr ? max_nt : bv.nt) + 1;
+  const int64_t cap_vf = ((int64_t)tri2(bv.nt_arr ? max_nt : bv.nt) << (2 * bv.dmax)) * pf->n_mem;
+  Workspace ws = make_workspace_layout(cap_tasks, cap_edges, cap_tops, cap_vf);
+  int32_t slots = std::min(plan->slots, bv.n_cand);
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  const int64_t need = ws.stride * (int64_t)slots;
+  if (need > plan->ws_bytes) {
+    const int64_t budget = (int64_t)(free_b + (size_t)plan->ws_bytes) / 2;   // leave room for the caller
+    if (need > budget) {
+      slots = (int32_t)std::max<int64_t>(1, budget / ws.stride);
+      if (slots < 1 || ws.stride > budget)
+        return fail(HESP_ENOMEM, "hesp_simulate_batch: one slot needs %lld bytes", (long long)ws.stride);
+    }
+    const int64_t need2 = ws.stride * (int64_t)slots;
+    if (need2 > plan->ws_bytes) {
+      hfree(plan->ws);
+      plan->ws = nullptr;
+      plan->ws_bytes = 0;
+      hipError_t e = hipMalloc(&plan->ws, need2);
+      if (e != hipSuccess) return fail(HESP_ENOMEM, "hesp_simulate_batch: workspace of %lld bytes: %s",
+                                       (long long)need2, hipGetErrorString(e));
+      plan->ws_bytes = need2;
+    }
+  }
+  ws.base = plan->ws;
+  OutView ov{out->d_makespan, out->d_status, out->d_sched_off, out->d_proc, out->d_start, out->d_finish};
+  HIP_TRY(launch_simulate(tb, bv, ws, ov, slots, plan->counter, s));
+  return ok();
+}
+
+int hesp_argmin(const int64_t* d_makespan, int32_t n, int64_t* d_best, void* stream) {
+  if (n < 0 || !d_best || (n > 0 && !d_makespan)) return fail(HESP_EINVAL, "hesp_argmin: bad argument");
+  HIP_TRY(launch_argmin(d_makespan, n, d_best, (hipStream_t)stream));
+  return ok();
+}
+
+}  // extern "C"

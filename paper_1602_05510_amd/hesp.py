@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libhesp.so (include/hesp.h), argument marshalling only.
+
+Every step of the simulation runs in the library's HIP kernels; PyTorch is used
+for device memory and streams.  Importing this module fails loudly when the
+compiled library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhesp.so")
+
+HESP_OK, HESP_EINVAL, HESP_ENOMEM, HESP_EHIP, HESP_ECAPACITY, HESP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+MAX_PROCS, MAX_PTYPES, MAX_MEM, MAX_LEVEL, MAX_FINE = 64, 8, 16, 3, 512
+
+P = ctypes.c_void_p
+i32, i64, u32, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+
+
+class CostModel(ctypes.Structure):
+    _fields_ = [("n_ptypes", i32), ("rmax_mflops", P), ("h", P), ("b", i64), ("max_level", i32),
+                ("latency_ns", i64), ("bw_bytes_per_ns", i64), ("elem_bytes", i64), ("shared_memory", i32)]
+
+
+class PlatformC(ctypes.Structure):
+    _fields_ = [("n_procs", i32), ("n_ptypes", i32), ("n_mem", i32), ("max_level", i32),
+                ("proc_type", P), ("proc_mem", P), ("cost_ns", P), ("xfer_ns", P)]
+
+
+class Policy(ctypes.Structure):
+    _fields_ = [("order", i32), ("select", i32), ("cache", i32)]
+
+
+class Task(ctypes.Structure):
+    _fields_ = [("kind", i32), ("level", i32), ("K", i32), ("I", i32), ("J", i32)]
+
+
+class BatchC(ctypes.Structure):
+    _fields_ = [("n_cand", i32), ("nt", i32), ("dmax", i32), ("d_nt", P), ("d_dmax", P), ("d_mask_off", P),
+                ("d_depth", P)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("slots", i32), ("max_tasks", i64), ("max_edges", i64), ("max_nt", i32)]
+
+
+class OutputsC(ctypes.Structure):
+    _fields_ = [("d_makespan", P), ("d_status", P), ("d_sched_off", P), ("d_proc", P), ("d_start", P),
+                ("d_finish", P)]
+
+
+class HespError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python -m paper_1602_05510_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        L.hesp_last_error.restype = ctypes.c_char_p
+        L.hesp_version.restype = ctypes.c_char_p
+        sig = {
+            "hesp_cost_tables": [ctypes.POINTER(CostModel), P, P],
+            "hesp_expand": [i32, i32, P, P, P, P, P, P],
+            "hesp_generate_uniform": [u64, i64, i32, i32, i32, u32, P, P],
+            "hesp_generate_ragged_shape": [u64, i64, i32, i32, i32, i32, P, P, P, P],
+            "hesp_generate_ragged_depth": [u64, i64, ctypes.POINTER(BatchC), u32, P, P],
+            "hesp_count_batch": [ctypes.POINTER(BatchC), P, P, P],
+            "hesp_plan_create": [ctypes.POINTER(P), ctypes.POINTER(PlanOpts)],
+            "hesp_plan_destroy": [P],
+            "hesp_plan_bytes": [P, ctypes.POINTER(i64)],
+            "hesp_simulate_batch": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(BatchC),
+                                    ctypes.POINTER(OutputsC), P],
+            "hesp_argmin": [P, i32, P, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, rc: int):
+    if rc != HESP_OK:
+        raise HespError(fn, rc, lib().hesp_last_error().decode())
+
+
+def _np(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(P)
+
+
+def _dev(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def version() -> str:
+    return lib().hesp_version().decode()
+
+
+# ----------------------------------------------------------------- cost model
+
+def cost_tables(rmax_mflops: np.ndarray, h: np.ndarray, b: int, max_level: int, latency_ns: int = 10_000,
+                bw_bytes_per_ns: int = 12, elem_bytes: int = 8, shared_memory: bool = False):
+    """int64 cost_ns[n_ptypes][4][max_level+1] and xfer_ns[4^max_level + 1]."""
+    rmax = np.ascontiguousarray(rmax_mflops, dtype=np.int64).reshape(-1, 4)
+    hh = np.ascontiguousarray(h, dtype=np.int64).reshape(-1)
+    n_pt = rmax.shape[0]
+    cost = np.zeros((n_pt, 4, max_level + 1), np.int64)
+    xfer = np.zeros(4 ** max_level + 1, np.int64)
+    cm = CostModel(n_pt, _np(rmax), _np(hh), b, max_level, latency_ns, bw_bytes_per_ns, elem_bytes,
+                   int(bool(shared_memory)))
+    _check("hesp_cost_tables", lib().hesp_cost_tables(ctypes.byref(cm), _np(cost), _np(xfer)))
+    return cost, xfer
+
+
+class Platform:
+    """A platform with its cost tables (host arrays kept alive for the C structs)."""
+
+    def __init__(self, proc_type, proc_mem, n_mem: int, cost: np.ndarray, xfer: np.ndarray):
+        self.proc_type = np.ascontiguousarray(proc_type, dtype=np.int32)
+        self.proc_mem = np.ascontiguousarray(proc_mem, dtype=np.int32)
+        self.n_mem = int(n_mem)
+        self.cost = np.ascontiguousarray(cost, dtype=np.int64)
+        self.xfer = np.ascontiguousarray(xfer, dtype=np.int64)
+        self.max_level = self.cost.shape[2] - 1
+        self.c = PlatformC(len(self.proc_type), self.cost.shape[0], self.n_mem, self.max_level,
+                           _np(self.proc_type), _np(self.proc_mem), _np(self.cost), _np(self.xfer))
+
+    @classmethod
+    def from_inputs(cls, pf, b: int, max_level: int) -> "Platform":
+        """From a drawn platform of ``inputs.make_platform``."""
+        cost, xfer = cost_tables(pf.rmax, pf.h, b, max_level, pf.latency_ns, pf.bw_bytes_per_ns,
+                                 pf.elem_bytes, pf.shared_memory)
+        return cls(pf.proc_type, pf.proc_mem, pf.n_mem, cost, xfer)
+
+
+# ----------------------------------------------------------------- expansion
+
+def expand(nt: int, dmax: int, depth: np.ndarray):
+    """Fine tasks (int32 [n][5]: kind, level, K, I, J) and successor CSR of one candidate."""
+    dep = np.ascontiguousarray(depth, dtype=np.uint8)
+    n_tasks = np.zeros(1, np.int32)
+    n_edges = np.zeros(1, np.int64)
+    L = lib()
+    _check("hesp_expand", L.hesp_expand(nt, dmax, _np(dep), _np(n_tasks), _np(n_edges), None, None, None))
+    n, m = int(n_tasks[0]), int(n_edges[0])
+    tasks = np.zeros((n, 5), np.int32)
+    ptr = np.zeros(n + 1, np.int64)
+    idx = np.zeros(max(m, 1), np.int32)
+    _check("hesp_expand", L.hesp_expand(nt, dmax, _np(dep), _np(n_tasks), _np(n_edges), _np(tasks), _np(ptr),
+                                        _np(idx)))
+    return tasks, ptr, idx[:m]
+
+
+# ----------------------------------------------------------------- device batches
+
+class DeviceBatch:
+    """A batch of candidates in device memory (torch tensors) and its C view."""
+
+    def __init__(self, n_cand: int, nt: int, dmax: int, depth, nt_arr=None, dmax_arr=None, mask_off=None):
+        self.n_cand, self.nt, self.dmax = int(n_cand), int(nt), int(dmax)
+        self.depth, self.nt_arr, self.dmax_arr, self.mask_off = depth, nt_arr, dmax_arr, mask_off
+        self.c = BatchC(self.n_cand, self.nt, self.dmax, _dev(nt_arr), _dev(dmax_arr), _dev(mask_off),
+                        _dev(depth))
+
+    @classmethod
+    def from_host(cls, batch, device="cuda") -> "DeviceBatch":
+        import torch
+        dep = torch.from_numpy(np.ascontiguousarray(batch.depth)).to(device)
+        if batch.uniform:
+            return cls(batch.n, int(batch.nt[0]), int(batch.dmax[0]), dep)
+        return cls(batch.n, int(batch.nt.max()), int(batch.dmax.max()), dep,
+                   torch.from_numpy(batch.nt.astype(np.int32)).to(device),
+                   torch.from_numpy(batch.dmax.astype(np.int32)).to(device),
+                   torch.from_numpy(batch.mask_off.astype(np.int64)).to(device))
+
+
+def generate_uniform(seed: int, first: int, n_cand: int, nt: int, dmax: int, split_thr: int, stream=None,
+                     device="cuda") -> DeviceBatch:
+    import torch
+    n_top = nt * (nt + 1) * (nt + 2) // 6
+    dep = torch.empty(n_cand * n_top, dtype=torch.uint8, device=device)
+    _check("hesp_generate_uniform", lib().hesp_generate_uniform(seed, first, n_cand, nt, dmax, split_thr,
+                                                                _dev(dep), _stream(stream)))
+    return DeviceBatch(n_cand, nt, dmax, dep)
+
+
+def generate_ragged(seed: int, first: int, n_cand: int, nt_lo: int, nt_hi: int, dmax_hi: int, split_thr: int,
+                    stream=None, device="cuda") -> DeviceBatch:
+    """Ragged batch: shapes, then depths, both drawn on the GPU (one device-to-host read of the size)."""
+    import torch
+    nt = torch.empty(n_cand, dtype=torch.int32, device=device)
+    dm = torch.empty(n_cand, dtype=torch.int32, device=device)
+    off = torch.empty(n_cand + 1, dtype=torch.int64, device=device)
+    st = _stream(stream)
+    _check("hesp_generate_ragged_shape", lib().hesp_generate_ragged_shape(seed, first, n_cand, nt_lo, nt_hi,
+                                                                          dmax_hi, _dev(nt), _dev(dm), _dev(off),
+                                                                          st))
+    total = int(off[-1].item())
+    dep = torch.empty(max(total, 1), dtype=torch.uint8, device=device)
+    b = DeviceBatch(n_cand, nt_hi, dmax_hi, dep, nt, dm, off)
+    _check("hesp_generate_ragged_depth", lib().hesp_generate_ragged_depth(seed, first, ctypes.byref(b.c),
+                                                                          split_thr, _dev(dep), st))
+    return b
+
+
+def count_batch(batch: DeviceBatch, stream=None):
+    import torch
+    nt = torch.empty(batch.n_cand, dtype=torch.int32, device=batch.depth.device)
+    ne = torch.empty(batch.n_cand, dtype=torch.int64, device=batch.depth.device)
+    _check("hesp_count_batch", lib().hesp_count_batch(ctypes.byref(batch.c), _dev(nt), _dev(ne), _stream(stream)))
+    return nt, ne
+
+
+class Plan:
+    def __init__(self, slots: int = 0, max_tasks: int = 0, max_edges: int = 0, max_nt: int = 0):
+        self.h = P()
+        self.opts = PlanOpts(slots, max_tasks, max_edges, max_nt)
+        _check("hesp_plan_create", lib().hesp_plan_create(ctypes.byref(self.h), ctypes.byref(self.opts)))
+
+    def bytes(self) -> int:
+        v = i64(0)
+        _check("hesp_plan_bytes", lib().hesp_plan_bytes(self.h, ctypes.byref(v)))
+        return int(v.value)
+
+    def close(self):
+        if self.h:
+            lib().hesp_plan_destroy(self.h)
+            self.h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def simulate_batch(plan: Plan, pf: Platform, batch: DeviceBatch, makespan, status, sched_off=None, proc=None,
+                   start=None, finish=None, stream=None, policy=(0, 0, 0)):
+    out = OutputsC(_dev(makespan), _dev(status), _dev(sched_off), _dev(proc), _dev(start), _dev(finish))
+    _check("hesp_simulate_batch", lib().hesp_simulate_batch(plan.h, ctypes.byref(pf.c), Policy(*policy),
+                                                            ctypes.byref(batch.c), ctypes.byref(out),
+                                                            _stream(stream)))
+
+
+def argmin(makespan, best, stream=None):
+    _check("hesp_argmin", lib().hesp_argmin(_dev(makespan), int(makespan.numel()), _dev(best), _stream(stream)))
