@@ -155,7 +155,7 @@ int hesp_count_batch(const hesp_batch *batch, int32_t *d_n_tasks, int64_t *d_n_e
 /* ---- plans: workspace, launch shape, capacities ------------------------------- */
 typedef struct hesp_plan hesp_plan;
 typedef struct {
-  int32_t slots;               /* persistent single-wave workgroups; 0 = 8 per compute unit */
+  int32_t slots;               /* persistent single-wave workgroups; 0 = 32 per compute unit */
   int64_t max_tasks;           /* per-candidate expanded-task capacity; 0 = sized per batch */
   int64_t max_edges;           /* per-candidate edge capacity; 0 = sized per batch */
   int32_t max_nt;              /* largest nt a fixed-capacity plan must accept (0 = 64) */
@@ -181,6 +181,7 @@ int hesp_plan_bytes(const hesp_plan *plan, int64_t *bytes);
 typedef struct {
   int64_t *d_makespan;         /* [n_cand] */
   int32_t *d_status;           /* [n_cand] */
+  int32_t *d_n_tasks;          /* [n_cand] expanded tasks per candidate, or NULL */
   const int64_t *d_sched_off;  /* [n_cand + 1] or NULL */
   int32_t *d_proc;             /* [d_sched_off[n_cand]] or NULL */
   int64_t *d_start;

@@ -233,7 +233,7 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
     delete p;
     return fail(HESP_EHIP, "hesp_plan_create: %s", hipGetErrorString(e));
   }
-  p->slots = p->opts.slots ? p->opts.slots : 8 * cus;
+  p->slots = p->opts.slots ? p->opts.slots : 32 * cus;
   e = hipMalloc(&p->counter, sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&p->max2, 2 * sizeof(int64_t));
   if (e != hipSuccess) {
@@ -365,7 +365,8 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
     }
   }
   ws.base = plan->ws;
-  OutView ov{out->d_makespan, out->d_status, out->d_sched_off, out->d_proc, out->d_start, out->d_finish};
+  OutView ov{out->d_makespan, out->d_status, out->d_n_tasks, out->d_sched_off, out->d_proc, out->d_start,
+             out->d_finish};
   HIP_TRY(launch_simulate(tb, bv, ws, ov, slots, plan->counter, s));
   return ok();
 }

@@ -43,6 +43,7 @@ struct Workspace {
 struct OutView {
   int64_t* makespan;
   int32_t* status;
+  int32_t* n_tasks;
   const int64_t* sched_off;
   int32_t* proc;
   int64_t* start;

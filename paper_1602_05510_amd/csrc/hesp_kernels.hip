@@ -41,8 +41,18 @@ template <class T>
 __device__ __forceinline__ T vld(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+// Arrays updated by atomic read-modify-writes (performed in L2, past the L1)
+// are read at device scope so that no stale L1 line can be returned.
+template <class T>
+__device__ __forceinline__ T vld_l2(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-__device__ __forceinline__ void wg_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+// Every workgroup is a single wavefront, and the lanes of one wavefront share
+// the compute unit's vector L1: global-memory accesses of the wavefront are
+// coherent between its lanes without waiting on the memory counters.  Only the
+// compiler must not move memory accesses across these points.
+__device__ __forceinline__ void wave_order() { asm volatile("" ::: "memory"); }
 
 __device__ __forceinline__ int64_t rdl64(int64_t v, int l) {
   uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
@@ -286,6 +296,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
       else if (carry > ws.cap_tasks) status = kECAP;
     }
     const int64_t n_fine = carry;
+    if (l == 0 && out.n_tasks) out.n_tasks[c] = status == kOK ? (int32_t)n_fine : 0;
     if (status != kOK) {
       if (l == 0) {
         out.makespan[c] = -1;
@@ -294,7 +305,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
       continue;
     }
     for (int64_t f = l; f < n_fine; f += kWave) sp.cur[f] = 0u;
-    wg_fence();
+    wave_order();
 
     auto depth_of = [&](int64_t t) { return (int)cd.depth[t]; };
     auto first_of = [&](int64_t t) { return (int64_t)vld(&sp.top_first[t]); };
@@ -307,13 +318,13 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
                                    [&](int64_t p) { atomicAdd(&sp.cur[p], 1u); });
       sp.indeg[f] = (uint32_t)np;
     });
-    wg_fence();
+    wave_order();
 
     // pass C: exclusive scan of successor counts (cur[f] = first edge of f)
     int64_t ecarry = 0;
     for (int64_t f0 = 0; f0 < n_fine; f0 += kWave) {
       const int64_t f = f0 + l;
-      const int v = f < n_fine ? (int)vld(&sp.cur[f]) : 0;
+      const int v = f < n_fine ? (int)vld_l2(&sp.cur[f]) : 0;
       const int incl = wave_incl_scan(v);
       if (f < n_fine) sp.cur[f] = (uint32_t)(ecarry + incl - v);
       ecarry += rdl32(incl, kWave - 1);
@@ -326,7 +337,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
       }
       continue;
     }
-    wg_fence();
+    wave_order();
 
     // pass D: fill successor lists; afterwards cur[f] = one past the last edge of f
     for_each_fine(cd, [&](bool valid, int64_t f, int64_t top, uint32_t cell, int d, int K, int I, int J) {
@@ -336,7 +347,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
         sp.succ[pos] = (uint32_t)f;
       });
     });
-    wg_fence();
+    wave_order();
 
     // ---------------- R: critical times, last chunk first ---------------------
     const int64_t n_chunks = (n_fine + kWave - 1) / kWave;
@@ -348,12 +359,12 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
       if (vf_) {
         const uint32_t dsc = vld(&sp.desc[f]);
         w = s_W[desc_kind(dsc)][desc_level(dsc)];
-        e0 = f == 0 ? 0u : vld(&sp.cur[f - 1]);
-        e1 = vld(&sp.cur[f]);
+        e0 = f == 0 ? 0u : vld_l2(&sp.cur[f - 1]);
+        e1 = vld_l2(&sp.cur[f]);
         myr = w;
         sp.rank[f] = w;
       }
-      wg_fence();
+      wave_order();
       // successors inside the chunk form chains of at most 64 tasks, so the
       // fixed point is reached within 65 sweeps; the cap only guards the loop
       for (int sweep = 0; sweep < 2 * kWave + 2; sweep++) {
@@ -371,7 +382,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
             changed = true;
           }
         }
-        wg_fence();
+        wave_order();
         if (!__ballot(changed)) break;
       }
     }
@@ -393,12 +404,12 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
     int64_t n_ready = 0;
     for (int64_t f0 = 0; f0 < n_fine; f0 += kWave) {
       const int64_t f = f0 + l;
-      const bool src = f < n_fine && vld(&sp.indeg[f]) == 0u;
+      const bool src = f < n_fine && vld_l2(&sp.indeg[f]) == 0u;
       const uint64_t m = __ballot(src);
       if (src) sp.ready[n_ready + __popcll(m & lanes_below())] = (uint32_t)f;
       n_ready += __popcll(m);
     }
-    wg_fence();
+    wave_order();
 
     int64_t T = 0;
     for (;;) {
@@ -433,7 +444,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
               sp.sortbuf[2 * x + 1] = INT64_MAX;
             }
           }
-          wg_fence();
+          wave_order();
           for (int64_t k2 = 2; k2 <= n2; k2 <<= 1) {
             for (int64_t j2 = k2 >> 1; j2 > 0; j2 >>= 1) {
               for (int64_t x = l; x < n2; x += kWave) {
@@ -450,7 +461,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
                   }
                 }
               }
-              wg_fence();
+              wave_order();
             }
           }
         }
@@ -529,7 +540,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
             out.start[sbase + t] = est_star;
             out.finish[sbase + t] = eft_star;
           }
-          wg_fence();
+          wave_order();
         }
         n_ready = 0;
         __syncthreads();
@@ -564,8 +575,8 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
           }
         }
         // release successors
-        const uint32_t e0 = t == 0 ? 0u : vld(&sp.cur[t - 1]);
-        const uint32_t e1 = vld(&sp.cur[t]);
+        const uint32_t e0 = t == 0 ? 0u : vld_l2(&sp.cur[t - 1]);
+        const uint32_t e1 = vld_l2(&sp.cur[t]);
         for (uint32_t e = e0; e < e1; e += kWave) {
           const uint32_t ee = e + l;
           bool rel = false;
@@ -590,7 +601,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
           st.headfin = vld(&sp.fifo_fin[old]);
         }
       }
-      wg_fence();
+      wave_order();
       T = Tn;
     }
     if (l == 0) {

@@ -50,8 +50,8 @@ class PlanOpts(ctypes.Structure):
 
 
 class OutputsC(ctypes.Structure):
-    _fields_ = [("d_makespan", P), ("d_status", P), ("d_sched_off", P), ("d_proc", P), ("d_start", P),
-                ("d_finish", P)]
+    _fields_ = [("d_makespan", P), ("d_status", P), ("d_n_tasks", P), ("d_sched_off", P), ("d_proc", P),
+                ("d_start", P), ("d_finish", P)]
 
 
 class HespError(RuntimeError):
@@ -257,8 +257,9 @@ class Plan:
 
 
 def simulate_batch(plan: Plan, pf: Platform, batch: DeviceBatch, makespan, status, sched_off=None, proc=None,
-                   start=None, finish=None, stream=None, policy=(0, 0, 0)):
-    out = OutputsC(_dev(makespan), _dev(status), _dev(sched_off), _dev(proc), _dev(start), _dev(finish))
+                   start=None, finish=None, stream=None, policy=(0, 0, 0), n_tasks=None):
+    out = OutputsC(_dev(makespan), _dev(status), _dev(n_tasks), _dev(sched_off), _dev(proc), _dev(start),
+                   _dev(finish))
     _check("hesp_simulate_batch", lib().hesp_simulate_batch(plan.h, ctypes.byref(pf.c), Policy(*policy),
                                                             ctypes.byref(batch.c), ctypes.byref(out),
                                                             _stream(stream)))
