@@ -61,19 +61,47 @@ __device__ __forceinline__ int64_t rdl64(int64_t v, int l) {
 }
 __device__ __forceinline__ int rdl32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// DPP lane moves of a 64-bit value (lanes left out by the row mask keep v)
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ int64_t dpp64(int64_t v) {
+  const int lo = (int)(uint32_t)(uint64_t)v, hi = (int)(uint32_t)((uint64_t)v >> 32);
+  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+  return (int64_t)(((uint64_t)(uint32_t)rhi << 32) | (uint32_t)rlo);
+}
+constexpr int kQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+__device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return b < a ? b : a; }
+__device__ __forceinline__ int64_t max64(int64_t a, int64_t b) { return b > a ? b : a; }
+
+// minimum over the 64 lanes, returned to every lane
 __device__ __forceinline__ int64_t wave_min64(int64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    int64_t y = __shfl_xor(v, o, kWave);
-    v = y < v ? y : v;
-  }
-  return v;
+  v = min64(v, dpp64<kQuadSwap1>(v));
+  v = min64(v, dpp64<kQuadSwap2>(v));
+  v = min64(v, dpp64<kRowRor4>(v));
+  v = min64(v, dpp64<kRowRor8>(v));
+  v = min64(v, dpp64<kRowBcast15, 0xA>(v));
+  v = min64(v, dpp64<kRowBcast31, 0xC>(v));
+  return rdl64(v, kWave - 1);
 }
 
-__device__ __forceinline__ int64_t seg_max64(int64_t v, int seg) {
-  for (int o = seg >> 1; o > 0; o >>= 1) {
-    int64_t y = __shfl_xor(v, o, kWave);
-    v = y > v ? y : v;
+// maximum over aligned segments of 4^k lanes (k = lg/2, lg even, 0..6); the
+// last lane of every segment holds its segment's maximum
+__device__ __forceinline__ int64_t seg_max64(int64_t v, int lg) {
+  if (lg >= 2) {
+    v = max64(v, dpp64<kQuadSwap1>(v));
+    v = max64(v, dpp64<kQuadSwap2>(v));
+  }
+  if (lg >= 4) {
+    v = max64(v, dpp64<kRowRor4>(v));
+    v = max64(v, dpp64<kRowRor8>(v));
+  }
+  if (lg >= 6) {
+    v = max64(v, dpp64<kRowBcast15, 0xA>(v));
+    v = max64(v, dpp64<kRowBcast31, 0xC>(v));
   }
   return v;
 }
@@ -89,6 +117,12 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 }
 
 __device__ __forceinline__ uint64_t lanes_below() { return (1ull << lane()) - 1ull; }
+
+// the ready list: first 64 entries in LDS, the rest in the slot's buffer
+__device__ __forceinline__ void push_ready(uint32_t* s_ready, uint32_t* g_ready, int64_t pos, uint32_t v) {
+  if (pos < kWave) s_ready[pos] = v;
+  else g_ready[pos] = v;
+}
 
 // ---------------------------------------------------------------- candidates
 
@@ -249,6 +283,10 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
   __shared__ int64_t s_xfer[kXferLen];
   __shared__ int64_t s_W[4][kLevels];
   __shared__ uint32_t s_order[kWave];
+  __shared__ int64_t s_rdy[4][kMaxMem];   // readiness of block b in space m (current task)
+  __shared__ int32_t s_miss[4][kMaxMem];  // its finest blocks missing in space m
+  __shared__ int64_t s_rk[kWave];          // critical times of one chunk
+  __shared__ uint32_t s_ready[kWave];      // first 64 entries of the ready list
 
   const int l = lane();
   for (int x = l; x < kMaxPtypes * 4 * kLevels; x += kWave) (&s_cost[0][0][0])[x] = (&tb.cost[0][0][0])[x];
@@ -350,45 +388,67 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
     wave_order();
 
     // ---------------- R: critical times, last chunk first ---------------------
+    // Successors always have larger numbers: those beyond the chunk are final
+    // and read once; those inside it are resolved by iterating the chunk's 64
+    // values in LDS to their fixed point (monotone from below).
     const int64_t n_chunks = (n_fine + kWave - 1) / kWave;
     for (int64_t ch = n_chunks - 1; ch >= 0; ch--) {
-      const int64_t f = ch * kWave + l;
-      const bool vf_ = f < n_fine;
-      int64_t w = 0, myr = 0;
+      const int64_t base = ch * kWave, lim = base + kWave;
+      const int64_t f = base + l;
+      const bool valid = f < n_fine;
+      int64_t w = 0, ext = 0;
+      uint64_t inl = 0;                       // up to 8 successor lanes inside the chunk
+      int nin = 0;
+      bool ovf = false;
       uint32_t e0 = 0, e1 = 0;
-      if (vf_) {
+      if (valid) {
         const uint32_t dsc = vld(&sp.desc[f]);
         w = s_W[desc_kind(dsc)][desc_level(dsc)];
         e0 = f == 0 ? 0u : vld_l2(&sp.cur[f - 1]);
         e1 = vld_l2(&sp.cur[f]);
-        myr = w;
-        sp.rank[f] = w;
-      }
-      wave_order();
-      // successors inside the chunk form chains of at most 64 tasks, so the
-      // fixed point is reached within 65 sweeps; the cap only guards the loop
-      for (int sweep = 0; sweep < 2 * kWave + 2; sweep++) {
-        bool changed = false;
-        if (vf_) {
-          int64_t best = 0;
-          for (uint32_t e = e0; e < e1; e++) {
-            const int64_t r = vld(&sp.rank[vld(&sp.succ[e])]);
-            best = r > best ? r : best;
-          }
-          const int64_t nr = w + best;
-          if (nr != myr) {
-            myr = nr;
-            sp.rank[f] = nr;
-            changed = true;
+        for (uint32_t e = e0; e < e1; e++) {
+          const uint32_t v = vld(&sp.succ[e]);
+          if (v >= lim) {
+            ext = max64(ext, vld(&sp.rank[v]));
+          } else if (nin < 8) {
+            inl |= (uint64_t)(v - base) << (6 * nin);
+            nin++;
+          } else {
+            ovf = true;
           }
         }
-        wave_order();
+      }
+      int64_t r = w + ext;
+      for (int sweep = 0; sweep < kWave + 2; sweep++) {
+        s_rk[l] = r;
+        __syncthreads();
+        int64_t mx = ext;
+        for (int j = 0; j < nin; j++) mx = max64(mx, s_rk[(inl >> (6 * j)) & 63]);
+        if (ovf)
+          for (uint32_t e = e0; e < e1; e++) {
+            const uint32_t v = vld(&sp.succ[e]);
+            if (v < lim) mx = max64(mx, s_rk[v - base]);
+          }
+        const int64_t nr = w + mx;
+        const bool changed = valid && nr != r;
+        r = nr;
+        __syncthreads();
         if (!__ballot(changed)) break;
       }
+      if (valid) sp.rank[f] = r;
     }
 
     // ---------------- S: event simulation -------------------------------------
-    for (int64_t a = l; a < n_atoms * M; a += kWave) sp.vf[a] = (a % M == 0) ? 0 : kInf;
+    {
+      // data starts valid on the host (space 0) only
+      const int step = kWave % M;
+      int m = l % M;
+      for (int64_t e = l; e < n_atoms * M; e += kWave) {
+        sp.vf[e] = m == 0 ? 0 : kInf;
+        m += step;
+        m = m >= M ? m - M : m;
+      }
+    }
     SimState st;
     st.avail = 0;
     st.headfin = kInf;
@@ -406,7 +466,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
       const int64_t f = f0 + l;
       const bool src = f < n_fine && vld_l2(&sp.indeg[f]) == 0u;
       const uint64_t m = __ballot(src);
-      if (src) sp.ready[n_ready + __popcll(m & lanes_below())] = (uint32_t)f;
+      if (src) push_ready(s_ready, sp.ready, n_ready + __popcll(m & lanes_below()), (uint32_t)f);
       n_ready += __popcll(m);
     }
     wave_order();
@@ -417,9 +477,12 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
       if (n_ready > 0) {
         // order the ready tasks: decreasing critical time, then increasing key
         const bool small = n_ready <= kWave;
-        if (small) {
+        if (n_ready == 1) {
+          s_order[0] = s_ready[0];
+          __syncthreads();
+        } else if (small) {
           const bool v = l < n_ready;
-          const uint32_t id = v ? vld(&sp.ready[l]) : 0u;
+          const uint32_t id = v ? s_ready[l] : 0u;
           const int64_t rk = v ? vld(&sp.rank[id]) : -1;
           const uint32_t ky = v ? task_key(vld(&sp.desc[id]), dmax) : 0u;
           int pos = 0;
@@ -436,7 +499,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
           while (n2 < n_ready) n2 <<= 1;
           for (int64_t x = l; x < n2; x += kWave) {
             if (x < n_ready) {
-              const uint32_t id = vld(&sp.ready[x]);
+              const uint32_t id = x < kWave ? s_ready[x] : vld(&sp.ready[x]);
               sp.sortbuf[2 * x] = vld(&sp.rank[id]);
               sp.sortbuf[2 * x + 1] = ((int64_t)task_key(vld(&sp.desc[id]), dmax) << 32) | id;
             } else {
@@ -472,38 +535,49 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
           t = (uint32_t)rdl32((int)t, 0);
           const uint32_t dsc = vld(&sp.desc[t]);
           const int kind = desc_kind(dsc), lvl = desc_level(dsc);
-          const int w = 1 << (dmax - lvl), ww = w * w;
+          const int sh = dmax - lvl;                 // a block is 2^sh x 2^sh finest blocks
+          const int lg = 2 * sh;
+          const int wmask = (1 << sh) - 1;
           int br[3], bc[3];
           const int nb = desc_blocks(dsc, br, bc);
-          int64_t est = T > st.avail ? T : st.avail;
-          // readiness of every block in every memory space
-          for (int bi = 0; bi < nb; bi++) {
-            const int64_t abase = atom_base(nt, dmax, lvl, br[bi], bc[bi]);
-            const int items = M * ww;
-            for (int i0 = 0; i0 < items; i0 += kWave) {
-              const int it = i0 + l;
-              const bool act = it < items;
-              const int m = it / ww, a = it % ww;
-              const int64_t atom = abase + ((int64_t)(a / w) << dmax) + (a % w);
-              const int64_t x = act ? vld(&sp.vf[atom * M + m]) : kInf;
-              const uint64_t infm = __ballot(act && x == kInf);
-              const int64_t fin = seg_max64((act && x != kInf) ? x : INT64_MIN, ww);
-              // lane p takes the segment of its own memory space, if it is in this pass
-              const int m0 = i0 / ww, m1 = m0 + kWave / ww;
-              const int src = (st.pmem - m0) * ww;
-              const int64_t fin_p = __shfl(fin, src < 0 ? 0 : (src > kWave - 1 ? kWave - 1 : src), kWave);
-              if (l < P && st.pmem >= m0 && st.pmem < m1) {
-                const uint64_t segm = (ww == 64 ? ~0ull : ((1ull << ww) - 1ull)) << (src);
-                const int miss = __popcll(infm & segm);
-                int64_t rdy = fin_p;
-                if (miss > 0) {
-                  const int64_t tx = T + s_xfer[miss * xs];
-                  rdy = tx > rdy ? tx : rdy;
-                }
-                est = rdy > est ? rdy : est;
-              }
+          const int64_t ab0 = atom_base(nt, dmax, lvl, br[0], bc[0]);
+          const int64_t ab1 = nb > 1 ? atom_base(nt, dmax, lvl, br[1], bc[1]) : 0;
+          const int64_t ab2 = nb > 2 ? atom_base(nt, dmax, lvl, br[2], bc[2]) : 0;
+          // one lane per (space m, block b, finest block a): it = ((m*4 + b) << lg) | a
+          const int items = (M << 2) << lg;
+          const bool one_pass = items <= kWave;
+          int64_t my_x = 0, my_addr = -1;
+          int my_m = 0, my_b = 0;
+          for (int i0 = 0; i0 < items; i0 += kWave) {
+            const int it = i0 + l;
+            const int a = it & ((1 << lg) - 1);
+            const int b = (it >> lg) & 3;
+            const int m = it >> (lg + 2);
+            const bool act = it < items && b < nb;
+            const int64_t abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
+            const int64_t addr = (abase + ((int64_t)(a >> sh) << dmax) + (a & wmask)) * M + m;
+            const int64_t x = act ? vld(&sp.vf[addr]) : kInf;
+            const uint64_t infm = __ballot(act && x == kInf);
+            const int64_t fin = seg_max64((act && x != kInf) ? x : INT64_MIN, lg);
+            if (act && a == (1 << lg) - 1) {         // last lane of the (m, b) segment
+              const uint64_t segm = lg == 6 ? ~0ull : (((1ull << (1 << lg)) - 1ull) << (l + 1 - (1 << lg)));
+              const int miss = __popcll(infm & segm);
+              int64_t rdy = fin;
+              if (miss > 0) rdy = max64(rdy, T + s_xfer[miss * xs]);
+              s_rdy[b][m] = rdy;
+              s_miss[b][m] = miss;
+            }
+            if (one_pass) {
+              my_x = x;
+              my_addr = act ? addr : -1;
+              my_m = m;
+              my_b = b;
             }
           }
+          __syncthreads();
+          int64_t est = T > st.avail ? T : st.avail;
+          if (l < P)
+            for (int b = 0; b < nb; b++) est = max64(est, s_rdy[b][st.pmem]);
           const int64_t eft = est + s_cost[st.ptype][kind][lvl];
           const int64_t key = l < P ? ((eft << 6) | l) : kInf;
           const int64_t best = wave_min64(key);
@@ -511,16 +585,23 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
           const int64_t eft_star = best >> 6;
           const int64_t est_star = rdl64(est, pstar);
           const int mstar = rdl32(st.pmem, pstar);
-          // transfers of the missing blocks start now
-          for (int bi = 0; bi < nb; bi++) {
-            const int64_t abase = atom_base(nt, dmax, lvl, br[bi], bc[bi]);
-            const bool act = l < ww;
-            const int64_t atom = abase + ((int64_t)(l / w) << dmax) + (l % w);
-            const int64_t x = act ? vld(&sp.vf[atom * M + mstar]) : 0;
-            const uint64_t infm = __ballot(act && x == kInf);
-            if (infm) {
-              const int64_t arrive = T + s_xfer[__popcll(infm) * xs];
-              if (act && x == kInf) sp.vf[atom * M + mstar] = arrive;
+          // transfers of the missing finest blocks start now
+          if (one_pass) {
+            if (my_addr >= 0 && my_m == mstar && my_x == kInf)
+              sp.vf[my_addr] = T + s_xfer[s_miss[my_b][mstar] * xs];
+          } else {
+            for (int b = 0; b < nb; b++) {
+              const int miss = s_miss[b][mstar];
+              if (miss == 0) continue;
+              const int64_t arrive = T + s_xfer[miss * xs];
+              const int64_t abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
+              for (int a0 = 0; a0 < (1 << lg); a0 += kWave) {
+                const int a = a0 + l;
+                if (a < (1 << lg)) {
+                  const int64_t addr = (abase + ((int64_t)(a >> sh) << dmax) + (a & wmask)) * M + mstar;
+                  if (vld(&sp.vf[addr]) == kInf) sp.vf[addr] = arrive;
+                }
+              }
             }
           }
           if (l == pstar) {
@@ -560,17 +641,17 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
         const int ms = rdl32(st.pmem, p);
         const uint32_t dsc = vld(&sp.desc[t]);
         const int lvl = desc_level(dsc);
-        const int w = 1 << (dmax - lvl), ww = w * w;
+        const int sh = dmax - lvl, lg = 2 * sh, wmask = (1 << sh) - 1;
         int br[3], bc[3];
         const int nb = desc_blocks(dsc, br, bc);
         // write-back: the written block is valid only where it was computed
         const int64_t abase = atom_base(nt, dmax, lvl, br[nb - 1], bc[nb - 1]);
-        const int items = M * ww;
+        const int items = M << lg;
         for (int i0 = 0; i0 < items; i0 += kWave) {
           const int it = i0 + l;
           if (it < items) {
-            const int m = it / ww, a = it % ww;
-            const int64_t atom = abase + ((int64_t)(a / w) << dmax) + (a % w);
+            const int m = it >> lg, a = it & ((1 << lg) - 1);
+            const int64_t atom = abase + ((int64_t)(a >> sh) << dmax) + (a & wmask);
             sp.vf[atom * M + m] = (m == ms) ? Tn : kInf;
           }
         }
@@ -586,7 +667,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
             rel = atomicSub(&sp.indeg[v], 1u) == 1u;
           }
           const uint64_t rm = __ballot(rel);
-          if (rel) sp.ready[n_ready + __popcll(rm & lanes_below())] = v;
+          if (rel) push_ready(s_ready, sp.ready, n_ready + __popcll(rm & lanes_below()), v);
           n_ready += __popcll(rm);
         }
       }
