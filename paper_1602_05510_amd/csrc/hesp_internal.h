@@ -36,8 +36,7 @@ struct Workspace {
   char* base;
   int64_t stride;
   int64_t cap_tasks, cap_edges, cap_tops, cap_vf;  // cap_vf = atoms * memory spaces
-  int64_t o_top_first, o_desc, o_rank, o_indeg, o_cur, o_succ, o_fifo_fin, o_fifo_next, o_ready,
-      o_sort, o_vf;
+  int64_t o_top_first, o_desc, o_rec, o_indeg, o_cur, o_succ, o_fifo, o_ready, o_sort, o_vf;
 };
 
 struct OutView {

@@ -118,11 +118,16 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 
 __device__ __forceinline__ uint64_t lanes_below() { return (1ull << lane()) - 1ull; }
 
-// the ready list: first 64 entries in LDS, the rest in the slot's buffer
-__device__ __forceinline__ void push_ready(uint32_t* s_ready, uint32_t* g_ready, int64_t pos, uint32_t v) {
-  if (pos < kWave) s_ready[pos] = v;
-  else g_ready[pos] = v;
-}
+// The ready list: the first 64 entries live in LDS with the task's record
+// (critical time, descriptor, successor range); the rest in the slot's buffer
+// as bare task numbers.
+struct Ready {
+  uint32_t id[kWave];
+  int64_t rank[kWave];
+  uint32_t desc[kWave];
+  uint32_t e0[kWave];
+  uint32_t e1[kWave];
+};
 
 // ---------------------------------------------------------------- candidates
 
@@ -226,12 +231,11 @@ __global__ void __launch_bounds__(kWave) k_count(BatchView b, int32_t* n_tasks, 
 struct SlotPtrs {
   uint32_t* top_first;
   uint32_t* desc;
-  int64_t* rank;
+  int64_t* rec;        // per task: [critical time, descriptor | first successor edge << 32]
   uint32_t* indeg;
   uint32_t* cur;
   uint32_t* succ;
-  int64_t* fifo_fin;
-  uint32_t* fifo_next;
+  int64_t* fifo;       // per queued task: [finish, id | desc << 32, e0 | e1 << 32] of the task behind it
   uint32_t* ready;
   int64_t* sortbuf;
   int64_t* vf;
@@ -242,12 +246,11 @@ __device__ __forceinline__ SlotPtrs slot_ptrs(const Workspace& w, int slot) {
   SlotPtrs s;
   s.top_first = (uint32_t*)(p + w.o_top_first);
   s.desc = (uint32_t*)(p + w.o_desc);
-  s.rank = (int64_t*)(p + w.o_rank);
+  s.rec = (int64_t*)(p + w.o_rec);
   s.indeg = (uint32_t*)(p + w.o_indeg);
   s.cur = (uint32_t*)(p + w.o_cur);
   s.succ = (uint32_t*)(p + w.o_succ);
-  s.fifo_fin = (int64_t*)(p + w.o_fifo_fin);
-  s.fifo_next = (uint32_t*)(p + w.o_fifo_next);
+  s.fifo = (int64_t*)(p + w.o_fifo);
   s.ready = (uint32_t*)(p + w.o_ready);
   s.sortbuf = (int64_t*)(p + w.o_sort);
   s.vf = (int64_t*)(p + w.o_vf);
@@ -270,13 +273,6 @@ __device__ __forceinline__ uint32_t task_key(uint32_t dsc, int dmax) {
          (uint32_t)(desc_J(dsc) << sh);
 }
 
-struct SimState {
-  // per-lane processor state (lane p < P)
-  int64_t avail, headfin;
-  uint32_t head, tail;
-  int pmem, ptype;
-};
-
 __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, Workspace ws, OutView out,
                                                     uint32_t* counter) {
   __shared__ int64_t s_cost[kMaxPtypes][4][kLevels];
@@ -286,7 +282,7 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
   __shared__ int64_t s_rdy[4][kMaxMem];   // readiness of block b in space m (current task)
   __shared__ int32_t s_miss[4][kMaxMem];  // its finest blocks missing in space m
   __shared__ int64_t s_rk[kWave];          // critical times of one chunk
-  __shared__ uint32_t s_ready[kWave];      // first 64 entries of the ready list
+  __shared__ Ready s_ready;                // first 64 entries of the ready list
 
   const int l = lane();
   for (int x = l; x < kMaxPtypes * 4 * kLevels; x += kWave) (&s_cost[0][0][0])[x] = (&tb.cost[0][0][0])[x];
@@ -400,16 +396,17 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
       uint64_t inl = 0;                       // up to 8 successor lanes inside the chunk
       int nin = 0;
       bool ovf = false;
-      uint32_t e0 = 0, e1 = 0;
+      uint32_t e0 = 0, e1 = 0, dsc_f = 0;
       if (valid) {
         const uint32_t dsc = vld(&sp.desc[f]);
+        dsc_f = dsc;
         w = s_W[desc_kind(dsc)][desc_level(dsc)];
         e0 = f == 0 ? 0u : vld_l2(&sp.cur[f - 1]);
         e1 = vld_l2(&sp.cur[f]);
         for (uint32_t e = e0; e < e1; e++) {
           const uint32_t v = vld(&sp.succ[e]);
           if (v >= lim) {
-            ext = max64(ext, vld(&sp.rank[v]));
+            ext = max64(ext, vld(&sp.rec[2 * v]));
           } else if (nin < 8) {
             inl |= (uint64_t)(v - base) << (6 * nin);
             nin++;
@@ -435,8 +432,12 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
         __syncthreads();
         if (!__ballot(changed)) break;
       }
-      if (valid) sp.rank[f] = r;
+      if (valid) {
+        sp.rec[2 * f] = r;
+        sp.rec[2 * f + 1] = (int64_t)(dsc_f | ((uint64_t)e0 << 32));
+      }
     }
+    if (l == 0) sp.rec[2 * n_fine + 1] = (int64_t)((uint64_t)n_edges << 32);   // end of the last range
 
     // ---------------- S: event simulation -------------------------------------
     {
@@ -449,59 +450,83 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
         m = m >= M ? m - M : m;
       }
     }
-    SimState st;
-    st.avail = 0;
-    st.headfin = kInf;
-    st.head = kNil;
-    st.tail = kNil;
-    st.pmem = my_mem;
-    st.ptype = my_ptype;
+    // processor p lives in lane p: availability, its FIFO queue's head (with
+    // the head's record) and tail
+    int64_t avail = 0, hfin = kInf;
+    uint32_t hid = kNil, hdesc = 0, he0 = 0, he1 = 0, tail = kNil;
+    const int pmem = my_mem, ptype = my_ptype;
 
     const int64_t xs = (int64_t)1 << (2 * (tb.max_level - dmax));   // transfer index scale
     const bool want_sched = out.sched_off != nullptr;
     const int64_t sbase = want_sched ? out.sched_off[c] : 0;
 
+    // release of task v at ready position pos; r0/r1/r3 are its record words
+    auto push = [&](int64_t pos, uint32_t v, int64_t r0, int64_t r1, int64_t r3) {
+      if (pos < kWave) {
+        s_ready.id[pos] = v;
+        s_ready.rank[pos] = r0;
+        s_ready.desc[pos] = (uint32_t)r1;
+        s_ready.e0[pos] = (uint32_t)((uint64_t)r1 >> 32);
+        s_ready.e1[pos] = (uint32_t)((uint64_t)r3 >> 32);
+      } else {
+        sp.ready[pos] = v;
+      }
+    };
+
     int64_t n_ready = 0;
     for (int64_t f0 = 0; f0 < n_fine; f0 += kWave) {
       const int64_t f = f0 + l;
       const bool src = f < n_fine && vld_l2(&sp.indeg[f]) == 0u;
+      int64_t r0 = 0, r1 = 0, r3 = 0;
+      if (src) {
+        r0 = vld(&sp.rec[2 * f]);
+        r1 = vld(&sp.rec[2 * f + 1]);
+        r3 = vld(&sp.rec[2 * f + 3]);
+      }
       const uint64_t m = __ballot(src);
-      if (src) push_ready(s_ready, sp.ready, n_ready + __popcll(m & lanes_below()), (uint32_t)f);
+      if (src) push(n_ready + __popcll(m & lanes_below()), (uint32_t)f, r0, r1, r3);
       n_ready += __popcll(m);
     }
-    wave_order();
+    __syncthreads();
 
     int64_t T = 0;
     for (;;) {
       // (i) map every released task, in priority order
       if (n_ready > 0) {
-        // order the ready tasks: decreasing critical time, then increasing key
         const bool small = n_ready <= kWave;
         if (n_ready == 1) {
-          s_order[0] = s_ready[0];
-          __syncthreads();
+          s_order[0] = 0;
         } else if (small) {
+          // position of each entry: decreasing critical time, then increasing key
           const bool v = l < n_ready;
-          const uint32_t id = v ? s_ready[l] : 0u;
-          const int64_t rk = v ? vld(&sp.rank[id]) : -1;
-          const uint32_t ky = v ? task_key(vld(&sp.desc[id]), dmax) : 0u;
+          const int64_t rk = v ? s_ready.rank[l] : -1;
+          const uint32_t ky = v ? task_key(s_ready.desc[l], dmax) : 0u;
           int pos = 0;
           for (int j = 0; j < (int)n_ready; j++) {
             const int64_t rj = rdl64(rk, j);
             const uint32_t kj = (uint32_t)rdl32((int)ky, j);
             pos += (rj > rk || (rj == rk && kj < ky)) ? 1 : 0;
           }
-          if (v) s_order[pos] = id;
-          __syncthreads();
+          if (v) s_order[pos] = (uint32_t)l;
         } else {
           // bitonic sort of (critical time, key|id) pairs in the slot's buffer
           int64_t n2 = 1;
           while (n2 < n_ready) n2 <<= 1;
           for (int64_t x = l; x < n2; x += kWave) {
             if (x < n_ready) {
-              const uint32_t id = x < kWave ? s_ready[x] : vld(&sp.ready[x]);
-              sp.sortbuf[2 * x] = vld(&sp.rank[id]);
-              sp.sortbuf[2 * x + 1] = ((int64_t)task_key(vld(&sp.desc[id]), dmax) << 32) | id;
+              uint32_t id, dsc;
+              int64_t rk;
+              if (x < kWave) {
+                id = s_ready.id[x];
+                rk = s_ready.rank[x];
+                dsc = s_ready.desc[x];
+              } else {
+                id = vld(&sp.ready[x]);
+                rk = vld(&sp.rec[2 * id]);
+                dsc = (uint32_t)vld(&sp.rec[2 * id + 1]);
+              }
+              sp.sortbuf[2 * x] = rk;
+              sp.sortbuf[2 * x + 1] = ((int64_t)task_key(dsc, dmax) << 32) | id;
             } else {
               sp.sortbuf[2 * x] = -1;
               sp.sortbuf[2 * x + 1] = INT64_MAX;
@@ -528,12 +553,27 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
             }
           }
         }
+        __syncthreads();
         for (int64_t r = 0; r < n_ready; r++) {
-          uint32_t t;
-          if (small) t = s_order[r];
-          else t = (uint32_t)(vld(&sp.sortbuf[2 * r + 1]) & 0xFFFFFFFFll);
+          uint32_t t, dsc, e0, e1;
+          if (small) {
+            const int q = (int)s_order[r];
+            t = s_ready.id[q];
+            dsc = s_ready.desc[q];
+            e0 = s_ready.e0[q];
+            e1 = s_ready.e1[q];
+          } else {
+            t = (uint32_t)(vld(&sp.sortbuf[2 * r + 1]) & 0xFFFFFFFFll);
+            t = (uint32_t)rdl32((int)t, 0);
+            const int64_t r1 = vld(&sp.rec[2 * t + 1]);
+            dsc = (uint32_t)r1;
+            e0 = (uint32_t)((uint64_t)r1 >> 32);
+            e1 = (uint32_t)((uint64_t)vld(&sp.rec[2 * t + 3]) >> 32);
+          }
           t = (uint32_t)rdl32((int)t, 0);
-          const uint32_t dsc = vld(&sp.desc[t]);
+          dsc = (uint32_t)rdl32((int)dsc, 0);
+          e0 = (uint32_t)rdl32((int)e0, 0);
+          e1 = (uint32_t)rdl32((int)e1, 0);
           const int kind = desc_kind(dsc), lvl = desc_level(dsc);
           const int sh = dmax - lvl;                 // a block is 2^sh x 2^sh finest blocks
           const int lg = 2 * sh;
@@ -575,16 +615,16 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
             }
           }
           __syncthreads();
-          int64_t est = T > st.avail ? T : st.avail;
+          int64_t est = T > avail ? T : avail;
           if (l < P)
-            for (int b = 0; b < nb; b++) est = max64(est, s_rdy[b][st.pmem]);
-          const int64_t eft = est + s_cost[st.ptype][kind][lvl];
+            for (int b = 0; b < nb; b++) est = max64(est, s_rdy[b][pmem]);
+          const int64_t eft = est + s_cost[ptype][kind][lvl];
           const int64_t key = l < P ? ((eft << 6) | l) : kInf;
           const int64_t best = wave_min64(key);
           const int pstar = (int)(best & 63);
           const int64_t eft_star = best >> 6;
           const int64_t est_star = rdl64(est, pstar);
-          const int mstar = rdl32(st.pmem, pstar);
+          const int mstar = rdl32(pmem, pstar);
           // transfers of the missing finest blocks start now
           if (one_pass) {
             if (my_addr >= 0 && my_m == mstar && my_x == kInf)
@@ -604,42 +644,54 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
               }
             }
           }
+          // append to the chosen processor's queue
           if (l == pstar) {
-            st.avail = eft_star;
-            sp.fifo_next[t] = kNil;
-            if (st.tail == kNil) {
-              st.head = t;
-              st.headfin = eft_star;
+            avail = eft_star;
+            if (hid == kNil) {
+              hid = t;
+              hfin = eft_star;
+              hdesc = dsc;
+              he0 = e0;
+              he1 = e1;
             } else {
-              sp.fifo_next[st.tail] = t;
-              sp.fifo_fin[st.tail] = eft_star;
+              sp.fifo[3 * tail] = eft_star;
+              sp.fifo[3 * tail + 1] = (int64_t)(t | ((uint64_t)dsc << 32));
+              sp.fifo[3 * tail + 2] = (int64_t)(e0 | ((uint64_t)e1 << 32));
             }
-            st.tail = t;
+            tail = t;
           }
           if (want_sched && l == 0) {
             out.proc[sbase + t] = pstar;
             out.start[sbase + t] = est_star;
             out.finish[sbase + t] = eft_star;
           }
-          wave_order();
+          __syncthreads();
         }
         n_ready = 0;
-        __syncthreads();
       }
 
-      // (ii) next event
-      const int64_t Tn = wave_min64(l < P ? st.headfin : kInf);
+      // (ii) next event: the earliest queue head
+      const int64_t Tn = wave_min64(l < P ? hfin : kInf);
       if (Tn == kInf) break;
 
-      // (iii) completions at Tn
-      const uint64_t cm = __ballot(l < P && st.headfin == Tn);
+      // (iii) completions at Tn; the next queue entries are fetched first
+      const uint64_t cm = __ballot(l < P && hfin == Tn);
+      const bool adv = (cm >> l) & 1ull;
+      const bool has_next = adv && hid != tail;
+      int64_t nf = kInf, nid = 0, ne = 0;
+      if (has_next) {
+        nf = vld(&sp.fifo[3 * hid]);
+        nid = vld(&sp.fifo[3 * hid + 1]);
+        ne = vld(&sp.fifo[3 * hid + 2]);
+      }
       uint64_t rem = cm;
       while (rem) {
         const int p = __ffsll((unsigned long long)rem) - 1;
         rem &= rem - 1;
-        const uint32_t t = (uint32_t)rdl32((int)st.head, p);
-        const int ms = rdl32(st.pmem, p);
-        const uint32_t dsc = vld(&sp.desc[t]);
+        const int ms = rdl32(pmem, p);
+        const uint32_t dsc = (uint32_t)rdl32((int)hdesc, p);
+        const uint32_t e0 = (uint32_t)rdl32((int)he0, p);
+        const uint32_t e1 = (uint32_t)rdl32((int)he1, p);
         const int lvl = desc_level(dsc);
         const int sh = dmax - lvl, lg = 2 * sh, wmask = (1 << sh) - 1;
         int br[3], bc[3];
@@ -655,34 +707,38 @@ __global__ void __launch_bounds__(kWave) k_simulate(SimTables tb, BatchView bv, 
             sp.vf[atom * M + m] = (m == ms) ? Tn : kInf;
           }
         }
-        // release successors
-        const uint32_t e0 = t == 0 ? 0u : vld_l2(&sp.cur[t - 1]);
-        const uint32_t e1 = vld_l2(&sp.cur[t]);
+        // release successors (their records are fetched alongside the decrement)
         for (uint32_t e = e0; e < e1; e += kWave) {
           const uint32_t ee = e + l;
           bool rel = false;
           uint32_t v = 0;
+          int64_t r0 = 0, r1 = 0, r3 = 0;
           if (ee < e1) {
             v = vld(&sp.succ[ee]);
+            r0 = vld(&sp.rec[2 * v]);
+            r1 = vld(&sp.rec[2 * v + 1]);
+            r3 = vld(&sp.rec[2 * v + 3]);
             rel = atomicSub(&sp.indeg[v], 1u) == 1u;
           }
           const uint64_t rm = __ballot(rel);
-          if (rel) push_ready(s_ready, sp.ready, n_ready + __popcll(rm & lanes_below()), v);
+          if (rel) push(n_ready + __popcll(rm & lanes_below()), v, r0, r1, r3);
           n_ready += __popcll(rm);
         }
       }
-      if ((cm >> l) & 1ull) {
-        const uint32_t old = st.head;
-        const uint32_t nx = vld(&sp.fifo_next[old]);
-        st.head = nx;
-        if (nx == kNil) {
-          st.tail = kNil;
-          st.headfin = kInf;
+      if (adv) {
+        if (has_next) {
+          hid = (uint32_t)nid;
+          hdesc = (uint32_t)((uint64_t)nid >> 32);
+          hfin = nf;
+          he0 = (uint32_t)ne;
+          he1 = (uint32_t)((uint64_t)ne >> 32);
         } else {
-          st.headfin = vld(&sp.fifo_fin[old]);
+          hid = kNil;
+          hfin = kInf;
+          tail = kNil;
         }
       }
-      wave_order();
+      __syncthreads();
       T = Tn;
     }
     if (l == 0) {
@@ -844,12 +900,11 @@ Workspace make_workspace_layout(int64_t cap_tasks, int64_t cap_edges, int64_t ca
   int64_t o = 0;
   w.o_top_first = o; o = al(o + 4 * (cap_tops + 1));
   w.o_desc = o;      o = al(o + 4 * cap_tasks);
-  w.o_rank = o;      o = al(o + 8 * cap_tasks);
+  w.o_rec = o;       o = al(o + 16 * (cap_tasks + 1));
   w.o_indeg = o;     o = al(o + 4 * cap_tasks);
   w.o_cur = o;       o = al(o + 4 * cap_tasks);
   w.o_succ = o;      o = al(o + 4 * (cap_edges > 0 ? cap_edges : 1));
-  w.o_fifo_fin = o;  o = al(o + 8 * cap_tasks);
-  w.o_fifo_next = o; o = al(o + 4 * cap_tasks);
+  w.o_fifo = o;      o = al(o + 24 * cap_tasks);
   w.o_ready = o;     o = al(o + 4 * cap_tasks);
   int64_t n2 = 1;
   while (n2 < cap_tasks) n2 <<= 1;
