@@ -155,15 +155,24 @@ int hesp_count_batch(const hesp_batch *batch, int32_t *d_n_tasks, int64_t *d_n_e
 /* ---- plans: workspace, launch shape, capacities ------------------------------- */
 typedef struct hesp_plan hesp_plan;
 typedef struct {
-  int32_t slots;               /* persistent single-wave workgroups; 0 = 32 per compute unit */
-  int64_t max_tasks;           /* per-candidate expanded-task capacity; 0 = sized per batch */
-  int64_t max_edges;           /* per-candidate edge capacity; 0 = sized per batch */
-  int32_t max_nt;              /* largest nt a fixed-capacity plan must accept (0 = 64) */
+  int32_t slots;               /* persistent single-wave workgroups of the simulation; 0 = 32 per compute unit */
+  int64_t max_tasks;           /* optional per-candidate task limit (larger: HESP_ECAPACITY); 0 = none */
+  int64_t max_edges;           /* optional per-candidate edge limit; 0 = none */
+  int32_t max_nt;              /* reserved, 0 */
+  int32_t group;               /* lanes per candidate in the event simulation: 16, 32 or 64 (>= processors);
+                                  0 = chosen per batch shape by timing each size once (autotuning) */
 } hesp_plan_opts;
 int hesp_plan_create(hesp_plan **plan, const hesp_plan_opts *opts);
 int hesp_plan_destroy(hesp_plan *plan);
 /* device bytes currently held by the plan */
 int hesp_plan_bytes(const hesp_plan *plan, int64_t *bytes);
+/* Kernel timing: with `enable` set, the next hesp_simulate_batch calls record HIP
+ * events around every preparation and simulation launch on their stream;
+ * hesp_plan_last_ms waits for those events and returns, for the last call, the
+ * summed milliseconds of the preparation launches, of the simulation launches,
+ * and the number of simulation launches (ms[0], ms[1], ms[2]). */
+int hesp_plan_timing(hesp_plan *plan, int32_t enable);
+int hesp_plan_last_ms(hesp_plan *plan, double *ms);
 
 /* ---- batched simulation ------------------------------------------------------
  * For every candidate: expansion, critical times, and the event simulation of
@@ -196,6 +205,120 @@ int hesp_simulate_batch(hesp_plan *plan, const hesp_platform *pf, hesp_policy po
  * Negative makespans (failed candidates) are ignored.  d_best gets
  * {makespan, index}, or {-1, -1} when no candidate succeeded. */
 int hesp_argmin(const int64_t *d_makespan, int32_t n, int64_t *d_best, void *stream);
+
+/* ---- learned surrogate ----------------------------------------------------
+ * Not part of the paper's method: a small network that predicts a candidate's
+ * normalised log-makespan from its split depths and the platform's rates, so
+ * that only the best-scored proposals are simulated exactly (the exact
+ * simulation above stays the judge).  Network: 32 inputs -> 256 -> 256 -> 256
+ * -> 1, ReLU; weights and activations bf16 (round to nearest even) wherever they
+ * enter a product, fp32 accumulation on the MFMA units, fp32 biases, fp32
+ * master weights updated by Adam (Kingma and Ba 2015; beta1 0.9, beta2 0.999,
+ * eps 1e-8); loss = mean squared error.  Flat parameter layout (floats):
+ * W1 [32][256], b1 [256], W2 [256][256], b2, W3 [256][256], b3, w4 [256], b4 [1]. */
+typedef struct hesp_mlp hesp_mlp;
+int64_t hesp_mlp_param_count(void);
+/* He-uniform weights from SplitMix64 draws of `seed`, zero biases */
+int hesp_mlp_create(hesp_mlp **mlp, uint64_t seed);
+int hesp_mlp_destroy(hesp_mlp *mlp);
+/* host float arrays of hesp_mlp_param_count() entries; set resets Adam */
+int hesp_mlp_set_params(hesp_mlp *mlp, const float *params, int64_t n);
+int hesp_mlp_get_params(hesp_mlp *mlp, float *params, int64_t n);
+int hesp_mlp_get_grads(hesp_mlp *mlp, float *grads, int64_t n);
+/* d_x [n][32] bf16 bit patterns: split depths of the n_top top-level tasks,
+ * then the n_rate values of d_rate, then zeros (n_top + n_rate <= 32) */
+int hesp_mlp_features(const uint8_t *d_depth, int64_t n, int32_t n_top, const float *d_rate, int32_t n_rate,
+                      uint16_t *d_x, void *stream);
+/* d_t[i] = (ln(d_makespan[i]) - mu) / sigma */
+int hesp_mlp_targets(const int64_t *d_makespan, int64_t n, float mu, float sigma, float *d_t, void *stream);
+/* d_y[i] = network output for row i of d_x (any n) */
+int hesp_mlp_forward(hesp_mlp *mlp, const uint16_t *d_x, int64_t n, float *d_y, void *stream);
+/* gradients of the mean squared error over `batch` rows (a multiple of 512) into
+ * the network's gradient buffer; d_loss (device float, nullable) gets the loss */
+int hesp_mlp_grad(hesp_mlp *mlp, const uint16_t *d_x, const float *d_t, int32_t batch, float *d_loss, void *stream);
+/* one Adam step with the current gradients */
+int hesp_mlp_adam(hesp_mlp *mlp, float lr, void *stream);
+/* `steps` (gradient, Adam) steps over consecutive batches of d_x/d_t (wrapping
+ * after the last full batch); d_loss [steps] (nullable) gets each loss */
+int hesp_mlp_train(hesp_mlp *mlp, const uint16_t *d_x, const float *d_t, int64_t n, int32_t batch, int32_t steps,
+                   float lr, float *d_loss, void *stream);
+/* Rate features of a platform (host): out[4*p + kind] = log2(rmax_mflops / 131072) / 4
+ * for processor type p and task kind (chol, trsm, syrk, gemm); n_out >= 4 * n_ptypes. */
+int hesp_mlp_rate_features(const hesp_cost_model *cm, float *out, int32_t n_out);
+/* Features of candidates with more top-level tasks than inputs: for each kind the
+ * fraction of its top-level tasks at each depth 0..3 (16 values, kind-major), for
+ * each kind and each half of the k range (k < nt/2, k >= nt/2) the mean depth (8
+ * values), then the n_rate (<= 8) values of d_rate.  d_depth [n][tet(nt)].
+ * Synchronises `stream` (a small table of the top-level tasks is uploaded). */
+int hesp_mlp_features_agg(const uint8_t *d_depth, int64_t n, int32_t nt, const float *d_rate, int32_t n_rate,
+                          uint16_t *d_x, void *stream);
+
+/* ---- candidate enumeration and top-k ----------------------------------------
+ * Enumeration: the depth of top-level task t of candidate c is digit t (least
+ * significant first) of first + c in base dmax + 1, so the candidates
+ * 0 .. (dmax+1)^tet(nt) - 1 are every partition of the instance once. */
+int hesp_generate_enumerate(int64_t first, int32_t n_cand, int32_t nt, int32_t dmax, uint8_t *d_depth, void *stream);
+/* Top-k: d_idx[0..k) gets the indices of the k smallest values in increasing
+ * order, ties to the lower index (bitonic sort of (value, index) keys on the
+ * GPU).  Makespans: negative values (failed candidates) and values >= 2^40 rank
+ * last; scores: NaN ranks last.  n <= 2^24.  d_ws: caller-owned device
+ * workspace of hesp_topk_workspace_bytes(n) bytes. */
+int64_t hesp_topk_workspace_bytes(int64_t n);
+int hesp_topk_makespan(const int64_t *d_makespan, int32_t n, int32_t k, int32_t *d_idx, void *d_ws, int64_t ws_bytes,
+                       void *stream);
+int hesp_topk_score(const float *d_score, int32_t n, int32_t k, int32_t *d_idx, void *d_ws, int64_t ws_bytes,
+                    void *stream);
+
+/* ---- partition search --------------------------------------------------------
+ * Rounds of proposals judged by the exact batched simulation (the iterative
+ * solver of section 2.1 keeps the partition with the best simulated makespan).
+ *   RANDOM:    every round draws `batch` fresh candidates (hesp_generate_uniform).
+ *   GREEDY:    after `warm_rounds` random rounds of `warm_batch` candidates, each
+ *              round mutates incumbents: proposal c copies incumbent
+ *              parent(c) = draw(seed, 5, round << 32 | c) mod pool_size and redraws
+ *              the depth of each top-level task with probability mutate_thr / 2^21
+ *              (SplitMix64 stream of draw(seed, 6, round << 32 | c)).
+ *   SURROGATE: as GREEDY, but `proposals` mutations per round are scored by the
+ *              network and only the `batch` best-scored are simulated; the network
+ *              is trained online (train_steps Adam steps of train_batch rows per
+ *              round) on every exact result kept in a ring of `replay` rows, with
+ *              targets normalised by the warm-up rounds' log-makespans.  Features:
+ *              raw depths when tet(nt) + n_rate <= 32, else the aggregate features
+ *              of hesp_mlp_features_agg.
+ * The incumbents are the `pool` best distinct-index results so far.  best_depth
+ * (host, tet(nt) bytes) and best_makespan (host) get the best partition;
+ * trace[rounds] (host, nullable) gets, after each round, the wall time since the
+ * start, the best makespan, and the simulated and proposed candidate counts
+ * (each round synchronises `stream`).  Device workspace is allocated per call. */
+enum { HESP_SEARCH_RANDOM = 0, HESP_SEARCH_GREEDY = 1, HESP_SEARCH_SURROGATE = 2 };
+typedef struct {
+  int32_t mode;
+  int32_t nt, dmax;            /* instance: nt x nt tiles, split depths 0..dmax */
+  int32_t rounds;
+  int32_t batch;               /* exact simulations per round after the warm-up */
+  int32_t warm_rounds;         /* >= 1 rounds of random candidates */
+  int32_t warm_batch;
+  int32_t proposals;           /* SURROGATE: proposals scored per round (>= batch) */
+  int32_t pool;                /* incumbents kept */
+  uint32_t split_thr;          /* random candidates, as in hesp_generate_uniform */
+  uint32_t mutate_thr;         /* per-task redraw probability * 2^21 */
+  uint64_t seed;
+  hesp_mlp *mlp;               /* SURROGATE: the network, trained in place */
+  const float *d_rate;         /* SURROGATE: platform rate features (device) */
+  int32_t n_rate;
+  int32_t train_steps;
+  int32_t train_batch;         /* multiple of 512 */
+  float lr;
+  int64_t replay;              /* rows of training data kept (>= train_batch) */
+} hesp_search_params;
+typedef struct {
+  double wall_ms;
+  int64_t best_makespan;
+  int64_t simulated;
+  int64_t proposed;
+} hesp_trace_point;
+int hesp_search(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy, const hesp_search_params *params,
+                uint8_t *best_depth, int64_t *best_makespan, hesp_trace_point *trace, void *stream);
 
 #ifdef __cplusplus
 }

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <map>
+#include <tuple>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -48,19 +50,62 @@ int64_t ceil_div128(__int128 a, __int128 b) { return (int64_t)((a + b - 1) / b);
 
 }  // namespace
 
+// A device buffer that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  int64_t bytes = 0;
+  hipError_t ensure(int64_t need) {
+    if (need <= bytes) return hipSuccess;
+    hfree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&p, (size_t)(need > 0 ? need : 1));
+    if (e == hipSuccess) bytes = need;
+    return e;
+  }
+  void release() {
+    hfree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return (T*)p; }
+};
+
 struct hesp_plan {
   hesp_plan_opts opts{};
-  int32_t slots = 0;
-  char* ws = nullptr;
-  int64_t ws_bytes = 0;
+  int32_t slots = 0;          // waves of the persistent simulation kernel
+  int32_t chunk = 0;          // candidates per chunk
   uint32_t* counter = nullptr;
-  int32_t* cnt_tasks = nullptr;   // auto sizing buffers
-  int64_t* cnt_edges = nullptr;
-  int64_t* max2 = nullptr;
-  int32_t cnt_cap = 0;
+  // per batch
+  DevBuf cnt_tasks, cnt_edges, off_t, off_e, off_v, off_top, bounds;
+  // per chunk
+  DevBuf top_first, desc, indeg, cur, succ, rec, fifo, ready, sortbuf, vf, nsrc;
+  std::vector<int64_t> h_bounds;
+  // autotuned lanes per candidate, by (processors, memory spaces, nt, dmax, ragged)
+  std::map<std::tuple<int, int, int, int, int>, int> tuned;
+  // optional kernel timing of the last call: events around each launch
+  bool timing = false;
+  std::vector<hipEvent_t> ev;   // per chunk: prepare start, prepare end = sim start, sim end
+  size_t ev_used = 0;
+  int64_t held() const {
+    return cnt_tasks.bytes + cnt_edges.bytes + off_t.bytes + off_e.bytes + off_v.bytes + off_top.bytes +
+           bounds.bytes + top_first.bytes + desc.bytes + indeg.bytes + cur.bytes + succ.bytes + rec.bytes +
+           fifo.bytes + ready.bytes + sortbuf.bytes + vf.bytes + nsrc.bytes;
+  }
+  void release() {
+    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds, &top_first, &desc, &indeg,
+                      &cur, &succ, &rec, &fifo, &ready, &sortbuf, &vf, &nsrc})
+      b->release();
+  }
 };
 
 extern "C" {
+
+int hesp_internal_fail(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
 
 const char* hesp_last_error(void) { return g_err.c_str(); }
 const char* hesp_version(void) { return "hesp-mi355x 0.1 (gfx950)"; }
@@ -222,7 +267,8 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
   hesp_plan* p = new (std::nothrow) hesp_plan();
   if (!p) return fail(HESP_ENOMEM, "hesp_plan_create: out of host memory");
   if (opts) p->opts = *opts;
-  if (p->opts.slots < 0 || p->opts.max_tasks < 0 || p->opts.max_edges < 0 || p->opts.max_nt < 0) {
+  if (p->opts.slots < 0 || p->opts.max_tasks < 0 || p->opts.max_edges < 0 || p->opts.max_nt < 0 ||
+      (p->opts.group != 0 && p->opts.group != 16 && p->opts.group != 32 && p->opts.group != 64)) {
     delete p;
     return fail(HESP_EINVAL, "hesp_plan_create: negative option");
   }
@@ -234,10 +280,9 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
     return fail(HESP_EHIP, "hesp_plan_create: %s", hipGetErrorString(e));
   }
   p->slots = p->opts.slots ? p->opts.slots : 32 * cus;
+  p->chunk = 32768;
   e = hipMalloc(&p->counter, sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc(&p->max2, 2 * sizeof(int64_t));
   if (e != hipSuccess) {
-    hfree(p->counter);
     delete p;
     return fail(HESP_ENOMEM, "hesp_plan_create: %s", hipGetErrorString(e));
   }
@@ -247,18 +292,38 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
 
 int hesp_plan_destroy(hesp_plan* p) {
   if (!p) return ok();
-  hfree(p->ws);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  p->release();
   hfree(p->counter);
-  hfree(p->max2);
-  hfree(p->cnt_tasks);
-  hfree(p->cnt_edges);
   delete p;
   return ok();
 }
 
 int hesp_plan_bytes(const hesp_plan* p, int64_t* bytes) {
   if (!p || !bytes) return fail(HESP_EINVAL, "hesp_plan_bytes: null argument");
-  *bytes = p->ws_bytes;
+  *bytes = p->held();
+  return ok();
+}
+
+int hesp_plan_timing(hesp_plan* p, int32_t enable) {
+  if (!p) return fail(HESP_EINVAL, "hesp_plan_timing: null plan");
+  p->timing = enable != 0;
+  p->ev_used = 0;
+  return ok();
+}
+
+int hesp_plan_last_ms(hesp_plan* p, double* ms) {
+  if (!p || !ms) return fail(HESP_EINVAL, "hesp_plan_last_ms: null argument");
+  ms[0] = ms[1] = ms[2] = 0.0;
+  for (size_t i = 0; i + 3 <= p->ev_used; i += 3) {
+    HIP_TRY(hipEventSynchronize(p->ev[i + 2]));
+    float a = 0.f, b = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, p->ev[i], p->ev[i + 1]));
+    HIP_TRY(hipEventElapsedTime(&b, p->ev[i + 1], p->ev[i + 2]));
+    ms[0] += a;
+    ms[1] += b;
+    ms[2] += 1.0;
+  }
   return ok();
 }
 
@@ -314,60 +379,142 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   if (!out || !out->d_makespan || !out->d_status) return fail(HESP_EINVAL, "hesp_simulate_batch: null outputs");
   if (out->d_sched_off && (!out->d_proc || !out->d_start || !out->d_finish))
     return fail(HESP_EINVAL, "hesp_simulate_batch: schedule outputs need proc, start and finish");
-  if (bv.n_cand == 0) return ok();
+  const int n = bv.n_cand;
+  if (n == 0) return ok();
   hipStream_t s = (hipStream_t)stream;
 
-  // capacities
-  int64_t cap_tasks = plan->opts.max_tasks, cap_edges = plan->opts.max_edges;
-  const int max_nt = plan->opts.max_nt ? std::max(plan->opts.max_nt, bv.nt) : std::max(64, bv.nt);
-  if (cap_tasks == 0 || cap_edges == 0) {
-    if (plan->cnt_cap < bv.n_cand) {
-      hfree(plan->cnt_tasks);
-      hfree(plan->cnt_edges);
-      plan->cnt_tasks = nullptr;
-      plan->cnt_edges = nullptr;
-      plan->cnt_cap = 0;
-      HIP_TRY(hipMalloc(&plan->cnt_tasks, sizeof(int32_t) * bv.n_cand));
-      HIP_TRY(hipMalloc(&plan->cnt_edges, sizeof(int64_t) * bv.n_cand));
-      plan->cnt_cap = bv.n_cand;
-    }
-    HIP_TRY(launch_count(bv, plan->cnt_tasks, plan->cnt_edges, s));
-    HIP_TRY(launch_max_i32_i64(plan->cnt_tasks, plan->cnt_edges, bv.n_cand, plan->max2, s));
-    int64_t mx[2];
-    HIP_TRY(hipMemcpyAsync(mx, plan->max2, sizeof mx, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (cap_tasks == 0) cap_tasks = std::max<int64_t>(mx[0], 1);
-    if (cap_edges == 0) cap_edges = std::max<int64_t>(mx[1], 1);
-  }
-  const int64_t cap_tops = tet3(bv.nt_arr ? max_nt : bv.nt) + 1;
-  const int64_t cap_vf = ((int64_t)tri2(bv.nt_arr ? max_nt : bv.nt) << (2 * bv.dmax)) * pf->n_mem;
-  Workspace ws = make_workspace_layout(cap_tasks, cap_edges, cap_tops, cap_vf);
-  int32_t slots = std::min(plan->slots, bv.n_cand);
+  // exact sizes of every candidate and their prefix sums
+  HIP_TRY(plan->cnt_tasks.ensure(4 * (int64_t)n));
+  HIP_TRY(plan->cnt_edges.ensure(8 * (int64_t)n));
+  for (DevBuf* b : {&plan->off_t, &plan->off_e, &plan->off_v, &plan->off_top}) HIP_TRY(b->ensure(8 * ((int64_t)n + 1)));
+  HIP_TRY(launch_count(bv, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(), s));
+  HIP_TRY(launch_layout(bv, pf->n_mem, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(),
+                        plan->off_t.as<int64_t>(), plan->off_e.as<int64_t>(), plan->off_v.as<int64_t>(),
+                        plan->off_top.as<int64_t>(), s));
+
+  // chunk boundaries: the largest chunk must fit the memory budget
   size_t free_b = 0, total_b = 0;
   HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-  const int64_t need = ws.stride * (int64_t)slots;
-  if (need > plan->ws_bytes) {
-    const int64_t budget = (int64_t)(free_b + (size_t)plan->ws_bytes) / 2;   // leave room for the caller
-    if (need > budget) {
-      slots = (int32_t)std::max<int64_t>(1, budget / ws.stride);
-      if (slots < 1 || ws.stride > budget)
-        return fail(HESP_ENOMEM, "hesp_simulate_batch: one slot needs %lld bytes", (long long)ws.stride);
+  const int64_t budget = (int64_t)(free_b + (size_t)plan->held()) / 2;
+  int32_t chunk = std::min<int32_t>(plan->chunk, n);
+  int32_t n_chunks = 0;
+  int64_t mT = 0, mE = 0, mV = 0, mP = 0;
+  for (;;) {
+    n_chunks = (n + chunk - 1) / chunk;
+    HIP_TRY(plan->bounds.ensure(4 * 8 * ((int64_t)n_chunks + 1)));
+    HIP_TRY(launch_bounds(plan->off_t.as<int64_t>(), plan->off_e.as<int64_t>(), plan->off_v.as<int64_t>(),
+                          plan->off_top.as<int64_t>(), n, chunk, n_chunks, plan->bounds.as<int64_t>(), s));
+    plan->h_bounds.resize(4 * ((size_t)n_chunks + 1));
+    HIP_TRY(hipMemcpyAsync(plan->h_bounds.data(), plan->bounds.p, 8 * plan->h_bounds.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int64_t* hb = plan->h_bounds.data();
+    mT = mE = mV = mP = 0;
+    for (int i = 0; i < n_chunks; i++) {
+      mT = std::max(mT, hb[0 * (n_chunks + 1) + i + 1] - hb[0 * (n_chunks + 1) + i]);
+      mE = std::max(mE, hb[1 * (n_chunks + 1) + i + 1] - hb[1 * (n_chunks + 1) + i]);
+      mV = std::max(mV, hb[2 * (n_chunks + 1) + i + 1] - hb[2 * (n_chunks + 1) + i]);
+      mP = std::max(mP, hb[3 * (n_chunks + 1) + i + 1] - hb[3 * (n_chunks + 1) + i]);
     }
-    const int64_t need2 = ws.stride * (int64_t)slots;
-    if (need2 > plan->ws_bytes) {
-      hfree(plan->ws);
-      plan->ws = nullptr;
-      plan->ws_bytes = 0;
-      hipError_t e = hipMalloc(&plan->ws, need2);
-      if (e != hipSuccess) return fail(HESP_ENOMEM, "hesp_simulate_batch: workspace of %lld bytes: %s",
-                                       (long long)need2, hipGetErrorString(e));
-      plan->ws_bytes = need2;
+    const int64_t bytes = 88 * mT + 4 * mE + 8 * mV + 4 * mP + 24 * (int64_t)chunk;
+    if (bytes <= budget || chunk == 1) {
+      if (bytes > budget) return fail(HESP_ENOMEM, "hesp_simulate_batch: one candidate needs %lld bytes", (long long)bytes);
+      break;
     }
+    chunk = (chunk + 1) / 2;
   }
-  ws.base = plan->ws;
+  HIP_TRY(plan->top_first.ensure(4 * mP));
+  HIP_TRY(plan->desc.ensure(4 * mT));
+  HIP_TRY(plan->indeg.ensure(4 * mT));
+  HIP_TRY(plan->cur.ensure(4 * mT));
+  HIP_TRY(plan->succ.ensure(4 * mE));
+  HIP_TRY(plan->rec.ensure(16 * (mT + chunk)));
+  HIP_TRY(plan->fifo.ensure(24 * mT));
+  HIP_TRY(plan->ready.ensure(4 * mT));
+  HIP_TRY(plan->sortbuf.ensure(32 * mT));
+  HIP_TRY(plan->vf.ensure(8 * mV));
+  HIP_TRY(plan->nsrc.ensure(4 * (int64_t)chunk));
+
   OutView ov{out->d_makespan, out->d_status, out->d_n_tasks, out->d_sched_off, out->d_proc, out->d_start,
              out->d_finish};
-  HIP_TRY(launch_simulate(tb, bv, ws, ov, slots, plan->counter, s));
+  auto chunk_view = [&](int32_t c0, int32_t nc) {
+    ChunkView cv{};
+    cv.task_off = plan->off_t.as<int64_t>();
+    cv.edge_off = plan->off_e.as<int64_t>();
+    cv.vf_off = plan->off_v.as<int64_t>();
+    cv.top_off = plan->off_top.as<int64_t>();
+    cv.c0 = c0;
+    cv.nc = nc;
+    cv.cap_tasks = plan->opts.max_tasks;
+    cv.cap_edges = plan->opts.max_edges;
+    cv.top_first = plan->top_first.as<uint32_t>();
+    cv.desc = plan->desc.as<uint32_t>();
+    cv.indeg = plan->indeg.as<uint32_t>();
+    cv.cur = plan->cur.as<uint32_t>();
+    cv.succ = plan->succ.as<uint32_t>();
+    cv.rec = plan->rec.as<int64_t>();
+    cv.fifo = plan->fifo.as<int64_t>();
+    cv.ready = plan->ready.as<uint32_t>();
+    cv.sortbuf = plan->sortbuf.as<int64_t>();
+    cv.vf = plan->vf.as<int64_t>();
+    cv.nsrc = plan->nsrc.as<int32_t>();
+    return cv;
+  };
+
+  // lanes per candidate: forced by the plan, or timed once per batch shape on a
+  // sub-batch of the first chunk (outputs of that sub-batch are rewritten below)
+  int group = plan->opts.group;
+  if (group == 0) {
+    const auto key = std::make_tuple(pf->n_procs, pf->n_mem, bv.nt, bv.dmax, bv.nt_arr ? 1 : 0);
+    auto it = plan->tuned.find(key);
+    if (it != plan->tuned.end()) {
+      group = it->second;
+    } else {
+      const int32_t sub = std::min<int32_t>(std::min(chunk, n), 8192);
+      float best_ms = 0.f;
+      hipEvent_t e0, e1;
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      for (int G : {16, 32, 64}) {
+        if (G < pf->n_procs) continue;
+        ChunkView cv = chunk_view(0, sub);
+        HIP_TRY(launch_prepare(tb, bv, cv, ov, s));
+        HIP_TRY(hipEventRecord(e0, s));
+        HIP_TRY(launch_sim(tb, bv, cv, ov, plan->slots, G, plan->counter, s));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (group == 0 || ms < best_ms) {
+          best_ms = ms;
+          group = G;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      plan->tuned[key] = group;
+    }
+  } else if (group < pf->n_procs) {
+    return fail(HESP_EINVAL, "hesp_simulate_batch: %d lanes per candidate < %d processors", group, pf->n_procs);
+  }
+
+  plan->ev_used = 0;
+  if (plan->timing)
+    while (plan->ev.size() < 3 * (size_t)n_chunks) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      plan->ev.push_back(e);
+    }
+  for (int i = 0; i < n_chunks; i++) {
+    const ChunkView cv = chunk_view(i * chunk, std::min(chunk, n - i * chunk));
+    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[3 * i], s));
+    HIP_TRY(launch_prepare(tb, bv, cv, ov, s));
+    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[3 * i + 1], s));
+    HIP_TRY(launch_sim(tb, bv, cv, ov, plan->slots, group, plan->counter, s));
+    if (plan->timing) {
+      HIP_TRY(hipEventRecord(plan->ev[3 * i + 2], s));
+      plan->ev_used = 3 * (size_t)(i + 1);
+    }
+  }
   return ok();
 }
 

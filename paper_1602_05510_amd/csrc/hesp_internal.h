@@ -31,12 +31,27 @@ struct BatchView {
   const uint8_t* depth;
 };
 
-// Per-slot workspace: one slot per persistent workgroup, `stride` bytes apart.
-struct Workspace {
-  char* base;
-  int64_t stride;
-  int64_t cap_tasks, cap_edges, cap_tops, cap_vf;  // cap_vf = atoms * memory spaces
-  int64_t o_top_first, o_desc, o_rec, o_indeg, o_cur, o_succ, o_fifo, o_ready, o_sort, o_vf;
+// A chunk of consecutive candidates [c0, c0 + nc) and its buffers.  The
+// *_off arrays are exclusive prefix sums over the whole batch of the exact
+// per-candidate sizes; a candidate's arrays start at (off[c] - off[c0]).
+struct ChunkView {
+  const int64_t* task_off;
+  const int64_t* edge_off;
+  const int64_t* vf_off;
+  const int64_t* top_off;
+  int32_t c0, nc;
+  int64_t cap_tasks, cap_edges;            // 0 = unlimited; larger candidates get HESP_ECAPACITY
+  uint32_t* top_first;                      // tet(nt)+1 per candidate
+  uint32_t* desc;                           // per task
+  uint32_t* indeg;                          // per task
+  uint32_t* cur;                            // per task
+  uint32_t* succ;                           // per edge
+  int64_t* rec;                             // 2 per task + 2 per candidate
+  int64_t* fifo;                            // 3 per task
+  uint32_t* ready;                          // per task
+  int64_t* sortbuf;                         // 4 per task
+  int64_t* vf;                              // finest blocks x memory spaces
+  int32_t* nsrc;                            // per candidate of the chunk
 };
 
 struct OutView {
@@ -49,11 +64,16 @@ struct OutView {
   int64_t* finish;
 };
 
-Workspace make_workspace_layout(int64_t cap_tasks, int64_t cap_edges, int64_t cap_tops, int64_t cap_vf);
-
 hipError_t launch_count(const BatchView& b, int32_t* n_tasks, int64_t* n_edges, hipStream_t s);
-hipError_t launch_simulate(const SimTables& t, const BatchView& b, const Workspace& w, const OutView& o,
-                           int32_t slots, uint32_t* counter, hipStream_t s);
+hipError_t launch_layout(const BatchView& b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
+                         int64_t* off_t, int64_t* off_e, int64_t* off_v, int64_t* off_top, hipStream_t s);
+hipError_t launch_bounds(const int64_t* off_t, const int64_t* off_e, const int64_t* off_v, const int64_t* off_top,
+                         int32_t n, int32_t chunk, int32_t n_chunks, int64_t* out, hipStream_t s);
+hipError_t launch_prepare(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o,
+                          hipStream_t s);
+hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o, int32_t slots,
+                      int32_t group, uint32_t* counter, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t* p, hipStream_t s);
 hipError_t launch_gen_uniform(uint64_t seed, int64_t first, int32_t n_cand, int32_t nt, int32_t dmax,
                               uint32_t thr, uint8_t* depth, hipStream_t s);
 hipError_t launch_gen_shape(uint64_t seed, int64_t first, int32_t n_cand, int32_t nt_lo, int32_t nt_hi,
@@ -61,6 +81,5 @@ hipError_t launch_gen_shape(uint64_t seed, int64_t first, int32_t n_cand, int32_
 hipError_t launch_gen_ragged_depth(uint64_t seed, int64_t first, const BatchView& b, uint32_t thr,
                                    uint8_t* depth, hipStream_t s);
 hipError_t launch_argmin(const int64_t* v, int32_t n, int64_t* best, hipStream_t s);
-hipError_t launch_max_i32_i64(const int32_t* a, const int64_t* b, int32_t n, int64_t* out2, hipStream_t s);
 
 }  // namespace hesp

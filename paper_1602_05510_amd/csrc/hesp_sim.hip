@@ -1,0 +1,694 @@
+// hesp_sim.hip -- the batched simulation on gfx950: layout, preparation and
+// the lane-group event loop.
+//
+// For a chunk of candidates:
+//   k_layout   prefix sums of the exact per-candidate sizes (tasks, edges,
+//              finest-block validity words, top-level tasks) over the batch;
+//   k_prepare  one wavefront per candidate: expansion of the Fig. 1 loop nest
+//              by the candidate's split depths into fine tasks and a successor
+//              CSR (section 2.1, "Recursive task partitioners"; RaW/WaW
+//              dependences by data block), then critical times (sum of the task
+//              time over all processors plus the largest critical time of a
+//              successor; "Priority-List", section 2.1);
+//   k_sim<G>   persistent: lane groups of G lanes, each running the event
+//              simulation of its own candidate -- every task released at the
+//              current time is mapped at once, in decreasing critical time (ties:
+//              smaller fine indices), to the processor with the earliest finish
+//              time counting the transfers it needs (EFT-P, ties: lowest
+//              processor index); transfers start at mapping time; on completion
+//              the written block becomes valid only in the executing processor's
+//              memory space (write-back).  Completions at one instant are all
+//              applied before any mapping at that instant.
+// Inside a group, lane p < P is processor p; the readiness of a task's blocks
+// is read with one lane per (memory space, block, finest block); successors are
+// released one per lane.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hesp_core.h"
+#include "hesp_device.h"
+#include "hesp_internal.h"
+
+namespace hesp {
+
+namespace {
+
+using namespace dev;
+
+// ---------------------------------------------------------------- layout
+
+// off_X[c] = sum over candidates before c; four columns at once (one workgroup)
+__global__ void __launch_bounds__(1024) k_layout(BatchView b, int32_t n_mem, const int32_t* n_tasks,
+                                                 const int64_t* n_edges, int64_t* off_t, int64_t* off_e,
+                                                 int64_t* off_v, int64_t* off_top) {
+  __shared__ int64_t s_part[4][16];
+  __shared__ int64_t s_carry[4];
+  const int l = lane(), wv = threadIdx.x / kWave;
+  if (threadIdx.x < 4) s_carry[threadIdx.x] = 0;
+  __syncthreads();
+  for (int base = 0; base < b.n_cand; base += 1024) {
+    const int c = base + (int)threadIdx.x;
+    int64_t x[4] = {0, 0, 0, 0};
+    if (c < b.n_cand) {
+      const int nt = b.nt_arr ? b.nt_arr[c] : b.nt;
+      const int dmax = b.dmax_arr ? b.dmax_arr[c] : b.dmax;
+      const bool ok = nt >= 1 && dmax >= 0 && dmax <= kMaxLevel && (nt << dmax) <= kMaxFine;
+      x[0] = n_tasks[c];
+      x[1] = n_edges[c];
+      x[2] = ok ? ((int64_t)tri2(nt) << (2 * dmax)) * n_mem : 0;
+      x[3] = ok ? tet3(nt) + 1 : 0;
+    }
+    int64_t incl[4];
+    for (int q = 0; q < 4; q++) {
+      int64_t v = x[q];
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t y = __shfl_up(v, o, kWave);
+        if (l >= o) v += y;
+      }
+      incl[q] = v;
+      if (l == kWave - 1) s_part[q][wv] = v;
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; q++) {
+      int64_t pre = s_carry[q];
+      for (int w = 0; w < wv; w++) pre += s_part[q][w];
+      int64_t* off = q == 0 ? off_t : (q == 1 ? off_e : (q == 2 ? off_v : off_top));
+      if (c < b.n_cand) off[c + 1] = pre + incl[q];
+      if (c == 0) off[0] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      int64_t s = 0;
+      for (int w = 0; w < 16; w++) s += s_part[threadIdx.x][w];
+      s_carry[threadIdx.x] += s;
+    }
+    __syncthreads();
+  }
+  if (b.n_cand == 0 && threadIdx.x == 0) { off_t[0] = 0; off_e[0] = 0; off_v[0] = 0; off_top[0] = 0; }
+}
+
+// off_X at the chunk boundaries min(i * chunk, n): out[q * (n_chunks + 1) + i]
+__global__ void k_bounds(const int64_t* off_t, const int64_t* off_e, const int64_t* off_v, const int64_t* off_top,
+                         int32_t n, int32_t chunk, int32_t n_chunks, int64_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n_chunks) return;
+  const int64_t c = (int64_t)i * chunk < n ? (int64_t)i * chunk : n;
+  out[0 * (n_chunks + 1) + i] = off_t[c];
+  out[1 * (n_chunks + 1) + i] = off_e[c];
+  out[2 * (n_chunks + 1) + i] = off_v[c];
+  out[3 * (n_chunks + 1) + i] = off_top[c];
+}
+
+// ---------------------------------------------------------------- candidate views
+
+struct CandPtrs {
+  int64_t toff;        // first task of the candidate in the chunk's task arrays
+  uint32_t* top_first;
+  uint32_t* desc;
+  uint32_t* indeg;
+  uint32_t* cur;
+  uint32_t* succ;
+  int64_t* rec;        // per task: [critical time, descriptor | first edge << 32], plus one closing entry
+  int64_t* fifo;       // per queued task: [finish, id | desc << 32, e0 | e1 << 32] of the task behind it
+  uint32_t* ready;
+  int64_t* sortbuf;
+  int64_t* vf;         // [finest block][memory space] valid-from times
+};
+
+__device__ __forceinline__ CandPtrs cand_ptrs(const ChunkView& v, int c) {
+  CandPtrs p;
+  const int64_t t = v.task_off[c] - v.task_off[v.c0];
+  const int64_t e = v.edge_off[c] - v.edge_off[v.c0];
+  const int64_t f = v.vf_off[c] - v.vf_off[v.c0];
+  const int64_t tp = v.top_off[c] - v.top_off[v.c0];
+  p.toff = t;
+  p.top_first = v.top_first + tp;
+  p.desc = v.desc + t;
+  p.indeg = v.indeg + t;
+  p.cur = v.cur + t;
+  p.succ = v.succ + e;
+  p.rec = v.rec + 2 * (t + (c - v.c0));
+  p.fifo = v.fifo + 3 * t;
+  p.ready = v.ready + t;
+  p.sortbuf = v.sortbuf + 4 * t;
+  p.vf = v.vf + f;
+  return p;
+}
+
+// ---------------------------------------------------------------- preparation
+
+__global__ void __launch_bounds__(kWave) k_prepare(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
+  __shared__ int64_t s_W[4][kLevels];
+  __shared__ int64_t s_rk[kWave];
+  const int l = lane();
+  for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
+  __syncthreads();
+
+  const int c = cv.c0 + (int)blockIdx.x;
+  if (c >= bv.n_cand) return;
+  const Cand cd = load_cand(bv, c);
+  const int nt = cd.nt, dmax = cd.dmax, M = tb.n_mem;
+  int status = kOK;
+  if (nt < 1 || dmax < 0 || dmax > kMaxLevel || dmax > tb.max_level || (nt << dmax) > kMaxFine) status = kEINVAL;
+  const int64_t n_tasks = cv.task_off[c + 1] - cv.task_off[c];
+  const int64_t n_edges = cv.edge_off[c + 1] - cv.edge_off[c];
+  if (status == kOK && ((cv.cap_tasks > 0 && n_tasks > cv.cap_tasks) || (cv.cap_edges > 0 && n_edges > cv.cap_edges)))
+    status = kECAP;
+  const CandPtrs sp = cand_ptrs(cv, c);
+
+  // pass A: first fine task of every top-level task; depths above dmax
+  int64_t carry = 0;
+  if (status == kOK) {
+    bool bad = false;
+    for (int t0 = 0; t0 < cd.n_top; t0 += kWave) {
+      const int t = t0 + l;
+      const bool vt = t < cd.n_top;
+      const uint32_t cell = vt ? top_cell(nt, t) : 0u;
+      const int d = vt ? (int)cd.depth[t] : 0;
+      bad |= vt && d > dmax;
+      const int cnt = vt ? fine_count(kind_of(cell_k(cell), cell_i(cell), cell_j(cell)), d > dmax ? dmax : d) : 0;
+      const int incl = wave_incl_scan(cnt);
+      if (vt) sp.top_first[t] = (uint32_t)(carry + incl - cnt);
+      carry += rdl32(incl, kWave - 1);
+    }
+    if (l == 0) sp.top_first[cd.n_top] = (uint32_t)carry;
+    if (__ballot(bad) || carry != n_tasks) status = kEINVAL;
+  }
+  if (status != kOK) {
+    if (l == 0) {
+      out.makespan[c] = -1;
+      out.status[c] = status;
+      if (out.n_tasks) out.n_tasks[c] = 0;
+    }
+    return;
+  }
+  const int64_t n_fine = n_tasks;
+  for (int64_t f = l; f < n_fine; f += kWave) sp.cur[f] = 0u;
+  wave_order();
+
+  auto depth_of = [&](int64_t t) { return (int)cd.depth[t]; };
+  auto first_of = [&](int64_t t) { return (int64_t)vld(&sp.top_first[t]); };
+
+  // pass B: descriptors, predecessor counts, successor counts
+  for_each_fine(cd, [&](bool valid, int64_t f, int64_t top, uint32_t cell, int d, int K, int I, int J) {
+    if (!valid) return;
+    sp.desc[f] = pack_desc(kind_of(K, I, J), d, K, I, J);
+    const int np = for_each_pred(nt, depth_of, first_of, top, cell, d, K, I, J,
+                                 [&](int64_t p) { atomicAdd(&sp.cur[p], 1u); });
+    sp.indeg[f] = (uint32_t)np;
+  });
+  wave_order();
+
+  // pass C: exclusive scan of successor counts (cur[f] = first edge of f)
+  int64_t ecarry = 0;
+  for (int64_t f0 = 0; f0 < n_fine; f0 += kWave) {
+    const int64_t f = f0 + l;
+    const int v = f < n_fine ? (int)vld_l2(&sp.cur[f]) : 0;
+    const int incl = wave_incl_scan(v);
+    if (f < n_fine) sp.cur[f] = (uint32_t)(ecarry + incl - v);
+    ecarry += rdl32(incl, kWave - 1);
+  }
+  wave_order();
+
+  // pass D: fill successor lists; afterwards cur[f] = one past the last edge of f
+  for_each_fine(cd, [&](bool valid, int64_t f, int64_t top, uint32_t cell, int d, int K, int I, int J) {
+    if (!valid) return;
+    for_each_pred(nt, depth_of, first_of, top, cell, d, K, I, J, [&](int64_t p) {
+      const uint32_t pos = atomicAdd(&sp.cur[p], 1u);
+      sp.succ[pos] = (uint32_t)f;
+    });
+  });
+  wave_order();
+
+  // R: critical times, last chunk of 64 tasks first.  Successors beyond the
+  // chunk are final and read once; those inside it are resolved by iterating
+  // the chunk's values in LDS to their fixed point (monotone from below).
+  const int64_t n_chunks = (n_fine + kWave - 1) / kWave;
+  for (int64_t ch = n_chunks - 1; ch >= 0; ch--) {
+    const int64_t base = ch * kWave, lim = base + kWave;
+    const int64_t f = base + l;
+    const bool valid = f < n_fine;
+    int64_t w = 0, ext = 0;
+    uint64_t inl = 0;                       // up to 8 successor lanes inside the chunk
+    int nin = 0;
+    bool ovf = false;
+    uint32_t e0 = 0, e1 = 0, dsc = 0;
+    if (valid) {
+      dsc = vld(&sp.desc[f]);
+      w = s_W[desc_kind(dsc)][desc_level(dsc)];
+      e0 = f == 0 ? 0u : vld_l2(&sp.cur[f - 1]);
+      e1 = vld_l2(&sp.cur[f]);
+      for (uint32_t e = e0; e < e1; e++) {
+        const uint32_t v = vld(&sp.succ[e]);
+        if (v >= lim) {
+          ext = max64(ext, vld(&sp.rec[2 * v]));
+        } else if (nin < 8) {
+          inl |= (uint64_t)(v - base) << (6 * nin);
+          nin++;
+        } else {
+          ovf = true;
+        }
+      }
+    }
+    int64_t r = w + ext;
+    for (int sweep = 0; sweep < kWave + 2; sweep++) {
+      s_rk[l] = r;
+      __syncthreads();
+      int64_t mx = ext;
+      for (int j = 0; j < nin; j++) mx = max64(mx, s_rk[(inl >> (6 * j)) & 63]);
+      if (ovf)
+        for (uint32_t e = e0; e < e1; e++) {
+          const uint32_t v = vld(&sp.succ[e]);
+          if (v < lim) mx = max64(mx, s_rk[v - base]);
+        }
+      const int64_t nr = w + mx;
+      const bool changed = valid && nr != r;
+      r = nr;
+      __syncthreads();
+      if (!__ballot(changed)) break;
+    }
+    if (valid) {
+      sp.rec[2 * f] = r;
+      sp.rec[2 * f + 1] = (int64_t)(dsc | ((uint64_t)e0 << 32));
+    }
+  }
+  if (l == 0) {
+    sp.rec[2 * n_fine] = 0;
+    sp.rec[2 * n_fine + 1] = (int64_t)((uint64_t)n_edges << 32);   // end of the last range
+  }
+
+  // initial validity: data valid on the host (space 0) only
+  {
+    const int64_t n_vf = ((int64_t)tri2(nt) << (2 * dmax)) * M;
+    const int step = kWave % M;
+    int m = l % M;
+    for (int64_t e = l; e < n_vf; e += kWave) {
+      sp.vf[e] = m == 0 ? 0 : kInf;
+      m += step;
+      m = m >= M ? m - M : m;
+    }
+  }
+  // tasks without predecessors start the ready list
+  int64_t n_src = 0;
+  for (int64_t f0 = 0; f0 < n_fine; f0 += kWave) {
+    const int64_t f = f0 + l;
+    const bool src = f < n_fine && vld(&sp.indeg[f]) == 0u;
+    const uint64_t m = __ballot(src);
+    if (src) sp.ready[n_src + __popcll(m & lanes_below())] = (uint32_t)f;
+    n_src += __popcll(m);
+  }
+  if (l == 0) {
+    cv.nsrc[c - cv.c0] = (int32_t)n_src;
+    out.status[c] = kOK;
+    if (out.n_tasks) out.n_tasks[c] = (int32_t)n_fine;
+  }
+}
+
+// ---------------------------------------------------------------- event simulation
+
+template <int G>
+__global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
+                                               uint32_t* counter) {
+  constexpr int NG = kWave / G;
+  constexpr int LGG = G == 16 ? 4 : (G == 32 ? 5 : 6);
+  __shared__ int64_t s_cost[kMaxPtypes][4][kLevels];
+  __shared__ int64_t s_xfer[kXferLen];
+  __shared__ int64_t s_fin[NG][4][kMaxMem];    // per (block, space): latest finite valid-from
+  __shared__ int32_t s_miss[NG][4][kMaxMem];   // per (block, space): finest blocks missing
+  __shared__ uint32_t s_rid[NG][G];            // ready list, first G entries, with records
+  __shared__ int64_t s_rrank[NG][G];
+  __shared__ uint32_t s_rdesc[NG][G];
+  __shared__ uint32_t s_re0[NG][G];
+  __shared__ uint32_t s_re1[NG][G];
+  __shared__ uint8_t s_order[NG][G];
+
+  const Grp<G> gp;
+  const int l = gp.l, g = gp.g, gl = gp.gl;
+  for (int x = l; x < kMaxPtypes * 4 * kLevels; x += kWave) (&s_cost[0][0][0])[x] = (&tb.cost[0][0][0])[x];
+  for (int x = l; x < kXferLen; x += kWave) s_xfer[x] = tb.xfer[x];
+  __syncthreads();
+
+  const int P = tb.n_procs, M = tb.n_mem;
+  const int pmem = gl < P ? tb.proc_mem[gl] : 0;
+  const int ptype = gl < P ? tb.proc_type[gl] : 0;
+  const bool want_sched = out.sched_off != nullptr;
+
+  bool active = false, exhausted = false;
+  int c = 0, nt = 0, dmax = 0;
+  int64_t xs = 0, T = 0, n_ready = 0, sbase = 0;
+  CandPtrs sp{};
+  int64_t avail = 0, hfin = kInf;
+  uint32_t hid = kNil, hdesc = 0, he0 = 0, he1 = 0, tail = kNil;
+
+  auto push = [&](int64_t pos, uint32_t v, int64_t r0, int64_t r1, int64_t r3) {
+    if (pos < G) {
+      s_rid[g][pos] = v;
+      s_rrank[g][pos] = r0;
+      s_rdesc[g][pos] = (uint32_t)r1;
+      s_re0[g][pos] = (uint32_t)((uint64_t)r1 >> 32);
+      s_re1[g][pos] = (uint32_t)((uint64_t)r3 >> 32);
+    } else {
+      sp.ready[pos] = v;
+    }
+  };
+
+  for (;;) {
+    // groups without a candidate take the next one
+    if (!active && !exhausted) {
+      int cc = 0;
+      if (gl == 0) cc = (int)atomicAdd(counter, 1u);
+      cc = gp.bcast(cc, 0);
+      if (cc >= cv.nc) {
+        exhausted = true;
+      } else {
+        c = cv.c0 + cc;
+        if (out.status[c] == kOK) {
+          const Cand cd = load_cand(bv, c);
+          nt = cd.nt;
+          dmax = cd.dmax;
+          xs = (int64_t)1 << (2 * (tb.max_level - dmax));
+          sp = cand_ptrs(cv, c);
+          sbase = want_sched ? out.sched_off[c] : 0;
+          T = 0;
+          avail = 0;
+          hfin = kInf;
+          hid = kNil;
+          tail = kNil;
+          n_ready = cv.nsrc[c - cv.c0];
+          for (int64_t x = gl; x < n_ready && x < G; x += G) {
+            const uint32_t v = vld(&sp.ready[x]);
+            push(x, v, vld(&sp.rec[2 * v]), vld(&sp.rec[2 * v + 1]), vld(&sp.rec[2 * v + 3]));
+          }
+          active = true;
+        }
+      }
+    }
+    if (__ballot(!exhausted) == 0) break;
+    if (!active) continue;
+    wave_order();
+
+    // (i) map every released task, in priority order
+    if (n_ready > 0) {
+      const bool small = n_ready <= G;
+      if (n_ready == 1) {
+        if (gl == 0) s_order[g][0] = 0;
+      } else if (small) {
+        // position of each entry: decreasing critical time, then increasing key
+        const bool v = gl < n_ready;
+        const int64_t rk = v ? s_rrank[g][gl] : -1;
+        const uint32_t ky = v ? task_key(s_rdesc[g][gl], dmax) : 0u;
+        int pos = 0;
+        for (int j = 0; j < (int)n_ready; j++) {
+          const int64_t rj = gp.bcast64(rk, j);
+          const uint32_t kj = (uint32_t)gp.bcast((int)ky, j);
+          pos += (rj > rk || (rj == rk && kj < ky)) ? 1 : 0;
+        }
+        if (v) s_order[g][pos] = (uint8_t)gl;
+      } else {
+        // bitonic sort of (critical time, key|id) pairs in the candidate's buffer
+        int64_t n2 = 1;
+        while (n2 < n_ready) n2 <<= 1;
+        for (int64_t x = gl; x < n2; x += G) {
+          if (x < n_ready) {
+            uint32_t id, dsc;
+            int64_t rk;
+            if (x < G) {
+              id = s_rid[g][x];
+              rk = s_rrank[g][x];
+              dsc = s_rdesc[g][x];
+            } else {
+              id = vld(&sp.ready[x]);
+              rk = vld(&sp.rec[2 * id]);
+              dsc = (uint32_t)vld(&sp.rec[2 * id + 1]);
+            }
+            sp.sortbuf[2 * x] = rk;
+            sp.sortbuf[2 * x + 1] = ((int64_t)task_key(dsc, dmax) << 32) | id;
+          } else {
+            sp.sortbuf[2 * x] = -1;
+            sp.sortbuf[2 * x + 1] = INT64_MAX;
+          }
+        }
+        wave_order();
+        for (int64_t k2 = 2; k2 <= n2; k2 <<= 1) {
+          for (int64_t j2 = k2 >> 1; j2 > 0; j2 >>= 1) {
+            for (int64_t x = gl; x < n2; x += G) {
+              const int64_t y = x ^ j2;
+              if (y > x) {
+                const int64_t ra = vld(&sp.sortbuf[2 * x]), ka = vld(&sp.sortbuf[2 * x + 1]);
+                const int64_t rb = vld(&sp.sortbuf[2 * y]), kb = vld(&sp.sortbuf[2 * y + 1]);
+                // "a before b": larger rank, then smaller key
+                const bool a_first = ra > rb || (ra == rb && ka < kb);
+                const bool up = (x & k2) == 0;
+                if (up != a_first) {
+                  sp.sortbuf[2 * x] = rb;
+                  sp.sortbuf[2 * x + 1] = kb;
+                  sp.sortbuf[2 * y] = ra;
+                  sp.sortbuf[2 * y + 1] = ka;
+                }
+              }
+            }
+            wave_order();
+          }
+        }
+      }
+      wave_order();
+      for (int64_t r = 0; r < n_ready; r++) {
+        uint32_t t, dsc, e0, e1;
+        if (small) {
+          const int q = gp.uni(s_order[g][r]);
+          t = s_rid[g][q];
+          dsc = s_rdesc[g][q];
+          e0 = s_re0[g][q];
+          e1 = s_re1[g][q];
+        } else {
+          t = (uint32_t)(vld(&sp.sortbuf[2 * r + 1]) & 0xFFFFFFFFll);
+          const int64_t r1 = vld(&sp.rec[2 * t + 1]);
+          dsc = (uint32_t)r1;
+          e0 = (uint32_t)((uint64_t)r1 >> 32);
+          e1 = (uint32_t)((uint64_t)vld(&sp.rec[2 * t + 3]) >> 32);
+        }
+        t = (uint32_t)gp.uni((int)t);
+        dsc = (uint32_t)gp.uni((int)dsc);
+        e0 = (uint32_t)gp.uni((int)e0);
+        e1 = (uint32_t)gp.uni((int)e1);
+        const int kind = desc_kind(dsc), lvl = desc_level(dsc);
+        const int sh = dmax - lvl;                 // a block is 2^sh x 2^sh finest blocks
+        const int lg = 2 * sh;
+        const int lgs = lg < LGG ? lg : LGG;      // lanes per segment chunk: 2^lgs
+        const int wmask = (1 << sh) - 1;
+        int br[3], bc[3];
+        const int nb = desc_blocks(dsc, br, bc);
+        const int64_t ab0 = atom_base(nt, dmax, lvl, br[0], bc[0]);
+        const int64_t ab1 = nb > 1 ? atom_base(nt, dmax, lvl, br[1], bc[1]) : 0;
+        const int64_t ab2 = nb > 2 ? atom_base(nt, dmax, lvl, br[2], bc[2]) : 0;
+        for (int x = gl; x < 4 * M; x += G) {
+          (&s_fin[g][0][0])[(x >> 2) + (x & 3) * kMaxMem] = INT64_MIN;
+          (&s_miss[g][0][0])[(x >> 2) + (x & 3) * kMaxMem] = 0;
+        }
+        wave_order();
+        // one lane per (space m, block b, finest block a): it = ((m*4 + b) << lg) | a
+        const int items = (M << 2) << lg;
+        const bool one_pass = items <= G;
+        int64_t my_x = 0, my_addr = -1;
+        int my_m = 0, my_b = 0;
+        for (int i0 = 0; i0 < items; i0 += G) {
+          const int it = i0 + gl;
+          const int a = it & ((1 << lg) - 1);
+          const int b = (it >> lg) & 3;
+          const int m = it >> (lg + 2);
+          const bool act = it < items && b < nb;
+          const int64_t abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
+          const int64_t addr = (abase + ((int64_t)(a >> sh) << dmax) + (a & wmask)) * M + m;
+          const int64_t x = act ? vld(&sp.vf[addr]) : kInf;
+          const uint64_t infm = gp.ballot(act && x == kInf);
+          const int64_t fin = seg_max64((act && x != kInf) ? x : INT64_MIN, lgs);
+          if (act && (a & ((1 << lgs) - 1)) == (1 << lgs) - 1) {   // last lane of its segment chunk
+            const uint64_t segm = lgs == 6 ? ~0ull : (((1ull << (1 << lgs)) - 1ull) << (gl + 1 - (1 << lgs)));
+            s_fin[g][b][m] = max64(s_fin[g][b][m], fin);
+            s_miss[g][b][m] += __popcll(infm & segm);
+          }
+          if (one_pass) {
+            my_x = x;
+            my_addr = act ? addr : -1;
+            my_m = m;
+            my_b = b;
+          }
+        }
+        wave_order();
+        int64_t est = T > avail ? T : avail;
+        if (gl < P)
+          for (int b = 0; b < nb; b++) {
+            const int ms = s_miss[g][b][pmem];
+            int64_t rdy = s_fin[g][b][pmem];
+            if (ms > 0) rdy = max64(rdy, T + s_xfer[ms * xs]);
+            est = max64(est, rdy);
+          }
+        const int64_t eft = est + s_cost[ptype][kind][lvl];
+        const int64_t key = gl < P ? ((eft << 6) | gl) : kInf;
+        const int64_t best = gp.min64all(key);
+        const int pstar = (int)(best & 63);
+        const int64_t eft_star = best >> 6;
+        const int64_t est_star = gp.bcast64(est, pstar);
+        const int mstar = gp.bcast(pmem, pstar);
+        // transfers of the missing finest blocks start now
+        if (one_pass) {
+          if (my_addr >= 0 && my_m == mstar && my_x == kInf) sp.vf[my_addr] = T + s_xfer[s_miss[g][my_b][mstar] * xs];
+        } else {
+          for (int b = 0; b < nb; b++) {
+            const int miss = s_miss[g][b][mstar];
+            if (miss == 0) continue;
+            const int64_t arrive = T + s_xfer[miss * xs];
+            const int64_t abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
+            for (int a0 = 0; a0 < (1 << lg); a0 += G) {
+              const int a = a0 + gl;
+              if (a < (1 << lg)) {
+                const int64_t addr = (abase + ((int64_t)(a >> sh) << dmax) + (a & wmask)) * M + mstar;
+                if (vld(&sp.vf[addr]) == kInf) sp.vf[addr] = arrive;
+              }
+            }
+          }
+        }
+        // append to the chosen processor's queue
+        if (gl == pstar) {
+          avail = eft_star;
+          if (hid == kNil) {
+            hid = t;
+            hfin = eft_star;
+            hdesc = dsc;
+            he0 = e0;
+            he1 = e1;
+          } else {
+            sp.fifo[3 * tail] = eft_star;
+            sp.fifo[3 * tail + 1] = (int64_t)(t | ((uint64_t)dsc << 32));
+            sp.fifo[3 * tail + 2] = (int64_t)(e0 | ((uint64_t)e1 << 32));
+          }
+          tail = t;
+        }
+        if (want_sched && gl == 0) {
+          out.proc[sbase + t] = pstar;
+          out.start[sbase + t] = est_star;
+          out.finish[sbase + t] = eft_star;
+        }
+        wave_order();
+      }
+      n_ready = 0;
+    }
+
+    // (ii) next event: the earliest queue head
+    const int64_t Tn = gp.min64all(gl < P ? hfin : kInf);
+    if (Tn == kInf) {
+      if (gl == 0) out.makespan[c] = T;
+      active = false;
+      continue;
+    }
+
+    // (iii) completions at Tn; the next queue entries are fetched first
+    const uint64_t cm = gp.ballot(gl < P && hfin == Tn);
+    const bool adv = (cm >> gl) & 1ull;
+    const bool has_next = adv && hid != tail;
+    int64_t nf = kInf, nid = 0, ne = 0;
+    if (has_next) {
+      nf = vld(&sp.fifo[3 * hid]);
+      nid = vld(&sp.fifo[3 * hid + 1]);
+      ne = vld(&sp.fifo[3 * hid + 2]);
+    }
+    uint64_t rem = cm;
+    while (rem) {
+      const int p = __ffsll((unsigned long long)rem) - 1;
+      rem &= rem - 1;
+      const int ms = gp.bcast(pmem, p);
+      const uint32_t dsc = (uint32_t)gp.bcast((int)hdesc, p);
+      const uint32_t e0 = (uint32_t)gp.bcast((int)he0, p);
+      const uint32_t e1 = (uint32_t)gp.bcast((int)he1, p);
+      const int lvl = desc_level(dsc);
+      const int sh = dmax - lvl, lg = 2 * sh, wmask = (1 << sh) - 1;
+      int br[3], bc[3];
+      const int nb = desc_blocks(dsc, br, bc);
+      // write-back: the written block is valid only where it was computed
+      const int64_t abase = atom_base(nt, dmax, lvl, br[nb - 1], bc[nb - 1]);
+      const int items = M << lg;
+      for (int i0 = 0; i0 < items; i0 += G) {
+        const int it = i0 + gl;
+        if (it < items) {
+          const int m = it >> lg, a = it & ((1 << lg) - 1);
+          const int64_t atom = abase + ((int64_t)(a >> sh) << dmax) + (a & wmask);
+          sp.vf[atom * M + m] = (m == ms) ? Tn : kInf;
+        }
+      }
+      // release successors (their records are fetched alongside the decrement)
+      for (uint32_t e = e0; e < e1; e += G) {
+        const uint32_t ee = e + gl;
+        bool rel = false;
+        uint32_t v = 0;
+        int64_t r0 = 0, r1 = 0, r3 = 0;
+        if (ee < e1) {
+          v = vld(&sp.succ[ee]);
+          r0 = vld(&sp.rec[2 * v]);
+          r1 = vld(&sp.rec[2 * v + 1]);
+          r3 = vld(&sp.rec[2 * v + 3]);
+          rel = atomicSub(&sp.indeg[v], 1u) == 1u;
+        }
+        const uint64_t rm = gp.ballot(rel);
+        if (rel) push(n_ready + __popcll(rm & gp.below()), v, r0, r1, r3);
+        n_ready += __popcll(rm);
+      }
+    }
+    if (adv) {
+      if (has_next) {
+        hid = (uint32_t)nid;
+        hdesc = (uint32_t)((uint64_t)nid >> 32);
+        hfin = nf;
+        he0 = (uint32_t)ne;
+        he1 = (uint32_t)((uint64_t)ne >> 32);
+      } else {
+        hid = kNil;
+        hfin = kInf;
+        tail = kNil;
+      }
+    }
+    wave_order();
+    T = Tn;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_layout(const BatchView& b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
+                         int64_t* off_t, int64_t* off_e, int64_t* off_v, int64_t* off_top, hipStream_t s) {
+  hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, b, n_mem, n_tasks, n_edges, off_t, off_e, off_v, off_top);
+  return hipGetLastError();
+}
+
+hipError_t launch_bounds(const int64_t* off_t, const int64_t* off_e, const int64_t* off_v, const int64_t* off_top,
+                         int32_t n, int32_t chunk, int32_t n_chunks, int64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_bounds, dim3((n_chunks + 1 + 255) / 256), dim3(256), 0, s, off_t, off_e, off_v, off_top, n,
+                     chunk, n_chunks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o,
+                          hipStream_t s) {
+  if (v.nc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prepare, dim3(v.nc), dim3(kWave), 0, s, t, b, v, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o, int32_t slots,
+                      int32_t group, uint32_t* counter, hipStream_t s) {
+  if (v.nc <= 0) return hipSuccess;
+  if ((group != 16 && group != 32 && group != 64) || group < t.n_procs) return hipErrorInvalidValue;
+  hipError_t e = launch_zero_u32(counter, s);
+  if (e != hipSuccess) return e;
+  const int G = group;
+  const int per_wave = kWave / G;
+  int waves = (v.nc + per_wave - 1) / per_wave;
+  if (waves > slots) waves = slots;
+  if (G == 16) hipLaunchKernelGGL(k_sim<16>, dim3(waves), dim3(kWave), 0, s, t, b, v, o, counter);
+  else if (G == 32) hipLaunchKernelGGL(k_sim<32>, dim3(waves), dim3(kWave), 0, s, t, b, v, o, counter);
+  else hipLaunchKernelGGL(k_sim<64>, dim3(waves), dim3(kWave), 0, s, t, b, v, o, counter);
+  return hipGetLastError();
+}
+
+}  // namespace hesp

@@ -46,12 +46,26 @@ class BatchC(ctypes.Structure):
 
 
 class PlanOpts(ctypes.Structure):
-    _fields_ = [("slots", i32), ("max_tasks", i64), ("max_edges", i64), ("max_nt", i32)]
+    _fields_ = [("slots", i32), ("max_tasks", i64), ("max_edges", i64), ("max_nt", i32), ("group", i32)]
 
 
 class OutputsC(ctypes.Structure):
     _fields_ = [("d_makespan", P), ("d_status", P), ("d_n_tasks", P), ("d_sched_off", P), ("d_proc", P),
                 ("d_start", P), ("d_finish", P)]
+
+
+SEARCH_RANDOM, SEARCH_GREEDY, SEARCH_SURROGATE = 0, 1, 2
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("mode", i32), ("nt", i32), ("dmax", i32), ("rounds", i32), ("batch", i32), ("warm_rounds", i32),
+                ("warm_batch", i32), ("proposals", i32), ("pool", i32), ("split_thr", u32), ("mutate_thr", u32),
+                ("seed", u64), ("mlp", P), ("d_rate", P), ("n_rate", i32), ("train_steps", i32),
+                ("train_batch", i32), ("lr", ctypes.c_float), ("replay", i64)]
+
+
+class TracePoint(ctypes.Structure):
+    _fields_ = [("wall_ms", ctypes.c_double), ("best_makespan", i64), ("simulated", i64), ("proposed", i64)]
 
 
 class HespError(RuntimeError):
@@ -82,14 +96,38 @@ def lib():
             "hesp_plan_create": [ctypes.POINTER(P), ctypes.POINTER(PlanOpts)],
             "hesp_plan_destroy": [P],
             "hesp_plan_bytes": [P, ctypes.POINTER(i64)],
+            "hesp_plan_timing": [P, i32],
+            "hesp_plan_last_ms": [P, P],
             "hesp_simulate_batch": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(BatchC),
                                     ctypes.POINTER(OutputsC), P],
             "hesp_argmin": [P, i32, P, P],
+            "hesp_mlp_create": [ctypes.POINTER(P), u64],
+            "hesp_mlp_destroy": [P],
+            "hesp_mlp_set_params": [P, P, i64],
+            "hesp_mlp_get_params": [P, P, i64],
+            "hesp_mlp_get_grads": [P, P, i64],
+            "hesp_mlp_features": [P, i64, i32, P, i32, P, P],
+            "hesp_mlp_targets": [P, i64, ctypes.c_float, ctypes.c_float, P, P],
+            "hesp_mlp_forward": [P, P, i64, P, P],
+            "hesp_mlp_grad": [P, P, P, i32, P, P],
+            "hesp_mlp_adam": [P, ctypes.c_float, P],
+            "hesp_mlp_train": [P, P, P, i64, i32, i32, ctypes.c_float, P, P],
+            "hesp_mlp_rate_features": [ctypes.POINTER(CostModel), P, i32],
+            "hesp_mlp_features_agg": [P, i64, i32, P, i32, P, P],
+            "hesp_generate_enumerate": [i64, i32, i32, i32, P, P],
+            "hesp_topk_makespan": [P, i32, i32, P, P, i64, P],
+            "hesp_topk_score": [P, i32, i32, P, P, i64, P],
+            "hesp_search": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(SearchParams), P,
+                            ctypes.POINTER(i64), P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = i32
+        L.hesp_mlp_param_count.argtypes = []
+        L.hesp_mlp_param_count.restype = i64
+        L.hesp_topk_workspace_bytes.argtypes = [i64]
+        L.hesp_topk_workspace_bytes.restype = i64
         _lib = L
     return _lib
 
@@ -234,15 +272,24 @@ def count_batch(batch: DeviceBatch, stream=None):
 
 
 class Plan:
-    def __init__(self, slots: int = 0, max_tasks: int = 0, max_edges: int = 0, max_nt: int = 0):
+    def __init__(self, slots: int = 0, max_tasks: int = 0, max_edges: int = 0, max_nt: int = 0, group: int = 0):
         self.h = P()
-        self.opts = PlanOpts(slots, max_tasks, max_edges, max_nt)
+        self.opts = PlanOpts(slots, max_tasks, max_edges, max_nt, group)
         _check("hesp_plan_create", lib().hesp_plan_create(ctypes.byref(self.h), ctypes.byref(self.opts)))
 
     def bytes(self) -> int:
         v = i64(0)
         _check("hesp_plan_bytes", lib().hesp_plan_bytes(self.h, ctypes.byref(v)))
         return int(v.value)
+
+    def timing(self, enable: bool = True):
+        _check("hesp_plan_timing", lib().hesp_plan_timing(self.h, int(enable)))
+
+    def last_ms(self):
+        """(prepare ms, simulate ms, simulate launches) of the last simulate_batch call."""
+        out = np.zeros(3, np.float64)
+        _check("hesp_plan_last_ms", lib().hesp_plan_last_ms(self.h, _np(out)))
+        return float(out[0]), float(out[1]), int(out[2])
 
     def close(self):
         if self.h:
@@ -267,3 +314,137 @@ def simulate_batch(plan: Plan, pf: Platform, batch: DeviceBatch, makespan, statu
 
 def argmin(makespan, best, stream=None):
     _check("hesp_argmin", lib().hesp_argmin(_dev(makespan), int(makespan.numel()), _dev(best), _stream(stream)))
+
+
+# ----------------------------------------------------------------- learned surrogate
+
+MLP_IN, MLP_HIDDEN = 32, 256
+
+
+class MLP:
+    """The surrogate network (device parameters, gradients and Adam state)."""
+
+    def __init__(self, seed: int = 0):
+        self.h = P()
+        _check("hesp_mlp_create", lib().hesp_mlp_create(ctypes.byref(self.h), seed))
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib().hesp_mlp_param_count())
+
+    def set_params(self, flat: np.ndarray):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check("hesp_mlp_set_params", lib().hesp_mlp_set_params(self.h, _np(a), a.size))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.param_count(), np.float32)
+        _check("hesp_mlp_get_params", lib().hesp_mlp_get_params(self.h, _np(a), a.size))
+        return a
+
+    def get_grads(self) -> np.ndarray:
+        a = np.zeros(self.param_count(), np.float32)
+        _check("hesp_mlp_get_grads", lib().hesp_mlp_get_grads(self.h, _np(a), a.size))
+        return a
+
+    def forward(self, x, y, stream=None):
+        """x: uint16/int16 [n][32] bf16 bit patterns (device); y: float32 [n] (device)."""
+        _check("hesp_mlp_forward", lib().hesp_mlp_forward(self.h, _dev(x), int(y.numel()), _dev(y),
+                                                          _stream(stream)))
+
+    def grad(self, x, t, batch: int, loss=None, stream=None):
+        _check("hesp_mlp_grad", lib().hesp_mlp_grad(self.h, _dev(x), _dev(t), batch, _dev(loss), _stream(stream)))
+
+    def adam(self, lr: float, stream=None):
+        _check("hesp_mlp_adam", lib().hesp_mlp_adam(self.h, lr, _stream(stream)))
+
+    def train(self, x, t, batch: int, steps: int, lr: float, loss=None, stream=None):
+        _check("hesp_mlp_train", lib().hesp_mlp_train(self.h, _dev(x), _dev(t), int(t.numel()), batch, steps, lr,
+                                                      _dev(loss), _stream(stream)))
+
+    def close(self):
+        if self.h:
+            lib().hesp_mlp_destroy(self.h)
+            self.h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlp_features(depth, n: int, n_top: int, rate, x, stream=None):
+    """x[n][32] (bf16 bits) from depth (uint8 [n][n_top]) and rate (float32 [n_rate]), device tensors."""
+    n_rate = 0 if rate is None else int(rate.numel())
+    _check("hesp_mlp_features", lib().hesp_mlp_features(_dev(depth), n, n_top, _dev(rate), n_rate, _dev(x),
+                                                        _stream(stream)))
+
+
+def mlp_targets(makespan, mu: float, sigma: float, t, stream=None):
+    _check("hesp_mlp_targets", lib().hesp_mlp_targets(_dev(makespan), int(makespan.numel()), mu, sigma, _dev(t),
+                                                      _stream(stream)))
+
+
+def mlp_rate_features(rmax_mflops: np.ndarray) -> np.ndarray:
+    """float32 [n_ptypes * 4] rate features of a platform's R_max table (host)."""
+    rmax = np.ascontiguousarray(rmax_mflops, dtype=np.int64).reshape(-1, 4)
+    h = np.zeros(rmax.shape[0], np.int64)
+    cm = CostModel(rmax.shape[0], _np(rmax), _np(h), 0, 0, 0, 0, 0, 0)
+    out = np.zeros(rmax.size, np.float32)
+    _check("hesp_mlp_rate_features", lib().hesp_mlp_rate_features(ctypes.byref(cm), _np(out), out.size))
+    return out
+
+
+def mlp_features_agg(depth, n: int, nt: int, rate, x, stream=None):
+    n_rate = 0 if rate is None else int(rate.numel())
+    _check("hesp_mlp_features_agg", lib().hesp_mlp_features_agg(_dev(depth), n, nt, _dev(rate), n_rate, _dev(x),
+                                                                _stream(stream)))
+
+
+# ----------------------------------------------------------------- enumeration, top-k, search
+
+def generate_enumerate(first: int, n_cand: int, nt: int, dmax: int, stream=None, device="cuda") -> DeviceBatch:
+    import torch
+    n_top = nt * (nt + 1) * (nt + 2) // 6
+    dep = torch.empty(max(n_cand * n_top, 1), dtype=torch.uint8, device=device)
+    _check("hesp_generate_enumerate", lib().hesp_generate_enumerate(first, n_cand, nt, dmax, _dev(dep),
+                                                                    _stream(stream)))
+    return DeviceBatch(n_cand, nt, dmax, dep)
+
+
+def topk_workspace(n: int, device="cuda"):
+    import torch
+    return torch.empty(int(lib().hesp_topk_workspace_bytes(n)), dtype=torch.uint8, device=device)
+
+
+def topk(values, k: int, ws=None, stream=None):
+    """Indices (int32 device tensor) of the k smallest values (int64 makespans or float32 scores)."""
+    import torch
+    n = int(values.numel())
+    if ws is None:
+        ws = topk_workspace(n, values.device)
+    idx = torch.empty(max(k, 1), dtype=torch.int32, device=values.device)
+    fn = "hesp_topk_makespan" if values.dtype == torch.int64 else "hesp_topk_score"
+    if values.dtype not in (torch.int64, torch.float32):
+        raise TypeError("topk takes int64 makespans or float32 scores")
+    _check(fn, getattr(lib(), fn)(_dev(values), n, k, _dev(idx), _dev(ws), int(ws.numel()), _stream(stream)))
+    return idx[:k]
+
+
+def search(plan: Plan, pf: Platform, nt: int, dmax: int, mode: int, rounds: int, batch: int, seed: int,
+           warm_rounds: int = 1, warm_batch: int = 0, proposals: int = 0, pool: int = 64, split_thr: int = 0,
+           mutate_thr: int = 0, mlp: "MLP" = None, rate=None, train_steps: int = 0, train_batch: int = 512,
+           lr: float = 1e-3, replay: int = 0, stream=None, policy=(0, 0, 0)):
+    """Runs hesp_search; returns (best depth (uint8 numpy), best makespan, trace as a list of dicts)."""
+    sp = SearchParams(mode, nt, dmax, rounds, batch, warm_rounds, warm_batch or batch, proposals or batch, pool,
+                      split_thr, mutate_thr, seed, mlp.h if mlp is not None else None, _dev(rate),
+                      0 if rate is None else int(rate.numel()), train_steps, train_batch, lr, replay)
+    n_top = nt * (nt + 1) * (nt + 2) // 6
+    best = np.zeros(n_top, np.uint8)
+    best_ms = i64(0)
+    trace = (TracePoint * rounds)()
+    _check("hesp_search", lib().hesp_search(plan.h, ctypes.byref(pf.c), Policy(*policy), ctypes.byref(sp), _np(best),
+                                            ctypes.byref(best_ms), trace, _stream(stream)))
+    tr = [{"wall_ms": t.wall_ms, "best_makespan": t.best_makespan, "simulated": t.simulated,
+           "proposed": t.proposed} for t in trace]
+    return best, int(best_ms.value), tr

@@ -127,9 +127,11 @@ def test_parity_chol4x4_all_candidates(H, torch_cuda):
     w = I.WORKLOADS["chol4x4_b512_d1"]
     pf = w.platform()
     bt = w.batch()
-    ms, st = gpu_run(H, torch_cuda, pf, bt, w.dmax)
-    assert np.all(st == 0)
-    assert np.array_equal(ms, oracle_batch(pf, bt))
+    ref = oracle_batch(pf, bt)
+    for group in (0, 16, 64):
+        ms, st = gpu_run(H, torch_cuda, pf, bt, w.dmax, plan=H.Plan(group=group))
+        assert np.all(st == 0)
+        assert np.array_equal(ms, ref), group
 
 
 def test_parity_chol16x16_subset(H, torch_cuda):
@@ -231,6 +233,12 @@ def test_invariance_to_order_and_slots(H, torch_cuda):
     for slots in (1, 7, 1000):
         ms_s, _ = gpu_run(H, torch_cuda, pf, bt, w.dmax, plan=H.Plan(slots=slots))
         assert np.array_equal(ms_s, ref)
+    # every lane-group size of the simulation kernel gives the same makespans
+    for group in (16, 32, 64):
+        ms_g, st_g = gpu_run(H, torch_cuda, pf, bt, w.dmax, plan=H.Plan(group=group))
+        assert np.all(st_g == 0) and np.array_equal(ms_g, ref), group
+    with pytest.raises(H.HespError):
+        H.Plan(group=8)
 
 
 def test_argmin(H, torch_cuda):
