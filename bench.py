@@ -114,6 +114,178 @@ def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float):
             "candidates_per_s": n / dt, "seconds": dt, "bit_exact_vs_gpu": exact}
 
 
+# ----------------------------------------------------------------------- surrogate
+
+MLP_FLOPS_PER_ROW = 2 * (32 * 256 + 2 * 256 * 256 + 256)     # multiply-adds of one forward row, x2
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_surrogate(args, torch, H):
+    """Train the network on exact simulations of many platforms, then score every
+    partition of held-out platforms and re-simulate the best-scored 1%."""
+    w = I.WORKLOADS["surrogate_chol4x4"]
+    n_pf, per, n_held = args.train_platforms, w.n_cand, 4
+    n_all = 1 << I.tet(w.nt)                       # 2^20 partitions of the 4x4 instance
+    thr = I.split_threshold(w.p_num, w.p_den)
+    dev = torch.device("cuda")
+    plan = H.Plan()
+    N = n_pf * per
+    X = torch.empty((N, 32), dtype=torch.int16, device=dev)
+    MS = torch.empty(N, dtype=torch.int64, device=dev)
+    st = torch.empty(max(per, n_all), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in range(n_pf):
+        pf_in = w.platform(p)
+        pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
+        db = H.generate_uniform(w.seed, p * per, per, w.nt, w.dmax, thr)
+        H.simulate_batch(plan, pf, db, MS[p * per:(p + 1) * per], st[:per])
+        if not bool((st[:per] == 0).all().item()):
+            raise SystemExit("training simulation reported a non-OK status")
+        rate = torch.from_numpy(H.mlp_rate_features(pf_in.rmax)).to(dev)
+        H.mlp_features(db.depth, per, I.tet(w.nt), rate, X[p * per:(p + 1) * per])
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    lms = torch.log(MS.double())
+    mu, sigma = float(lms.mean()), float(lms.std())
+    T = torch.empty(N, dtype=torch.float32, device=dev)
+    H.mlp_targets(MS, mu, sigma, T)
+    m = H.MLP(args.mlp_seed)
+    loss = torch.zeros(args.train_steps, dtype=torch.float32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    m.train(X, T, args.train_batch, args.train_steps, args.lr, seed=args.mlp_seed, loss=loss)
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    lh = loss.cpu().numpy()
+    del X, MS, T
+
+    # held-out platforms: every partition simulated (the judge) and scored
+    k_top = (n_all + 99) // 100
+    Xh = torch.empty((n_all, 32), dtype=torch.int16, device=dev)
+    y = torch.empty(n_all, dtype=torch.float32, device=dev)
+    ms = torch.empty(n_all, dtype=torch.int64, device=dev)
+    ws = H.topk_workspace(n_all)
+    per_pf, fwd_ms = [], []
+    for q in range(n_held):
+        pf_in = w.platform(n_pf + q)
+        pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
+        db = H.generate_enumerate(0, n_all, w.nt, w.dmax)
+        H.simulate_batch(plan, pf, db, ms, st[:n_all])
+        rate = torch.from_numpy(H.mlp_rate_features(pf_in.rmax)).to(dev)
+        H.mlp_features(db.depth, n_all, I.tet(w.nt), rate, Xh)
+        for rep in range(3):                      # first launch warms up
+            e0.record()
+            m.forward(Xh, y)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep:
+                fwd_ms.append(e0.elapsed_time(e1))
+        idx = H.topk(y, k_top, ws).long()
+        # re-simulate the best-scored 1% exactly
+        sub = H.DeviceBatch(k_top, w.nt, w.dmax, db.depth.view(n_all, -1)[idx].contiguous().view(-1))
+        ms_top = torch.empty(k_top, dtype=torch.int64, device=dev)
+        H.simulate_batch(plan, pf, sub, ms_top, st[:k_top])
+        exact = ms.double()
+        pred = torch.exp(y.double() * sigma + mu)
+        err = (pred - exact).abs()
+        best = int(ms.min())
+        best_idx = int(torch.argmin(ms))
+        pos = (idx == best_idx).nonzero()
+        order = torch.argsort(ms)
+        rnd = torch.randperm(n_all, generator=torch.Generator().manual_seed(q))[:k_top].to(dev)
+        per_pf.append({
+            "platform": n_pf + q,
+            "mae_ns": float(err.mean()), "mae_rel": float((err / exact).mean()),
+            "exhaustive_best": best,
+            "top1pct_best": int(ms_top.min()),
+            "top1pct_best_over_exhaustive": int(ms_top.min()) / best,
+            "top1pct_resim_matches_sweep": bool(torch.equal(ms_top, ms[idx])),
+            "exhaustive_best_rank_in_top1pct": int(pos[0, 0]) if pos.numel() else None,
+            "top1_scored_exact_rank": int((order == int(idx[0])).nonzero()[0, 0]),
+            "random1pct_best_over_exhaustive": int(ms[rnd].min()) / best,
+            "top1pct_mean_over_random1pct_mean": float(ms_top.double().mean() / ms[rnd].double().mean()),
+        })
+    fwd = float(np.median(fwd_ms))
+    tflops = MLP_FLOPS_PER_ROW * n_all / (fwd * 1e-3) / 1e12
+    train_tflops = 3 * MLP_FLOPS_PER_ROW * args.train_batch * args.train_steps / (train_ms * 1e-3) / 1e12
+    rec = {
+        "metric": "surrogate-scored partitions/sec (bf16 MFMA forward)",
+        "value": n_all / (fwd * 1e-3), "unit": "candidates/s", "n_gpus": 1, "steps": len(fwd_ms),
+        "warmup": n_held, "ms_per_step": fwd, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": w.name, "train_platforms": n_pf, "pairs": N, "held_out_platforms": n_held,
+                   "proposals": n_all * n_held, "top_fraction": "1%", "network": "32-256-256-256-1 ReLU",
+                   "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "mfma", "kernel": "forward pass (3 bf16 GEMMs + output dot)", "achieved": tflops,
+                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / MFMA_BF16_PEAK_TFLOPS,
+                     "traffic": None, "flops_per_row": MLP_FLOPS_PER_ROW, "rows_per_launch": n_all},
+        "training": {"steps": args.train_steps, "batch": args.train_batch, "lr": args.lr, "ms": train_ms,
+                     "tflops": train_tflops, "loss_first": float(lh[:10].mean()), "loss_last": float(lh[-50:].mean()),
+                     "data_generation_s": data_s, "target_mu": mu, "target_sigma": sigma},
+        "held_out": per_pf,
+        "mae_rel_mean": float(np.mean([r["mae_rel"] for r in per_pf])),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import mlp_ref as R
+        p = R.unflatten(m.get_params())
+        xs = Xh[:args.cpu_rows].cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+        xs = xs.view(np.float32)
+        t0 = time.perf_counter()
+        yr, _ = R.forward(p, xs, bf16=True)
+        dt = time.perf_counter() - t0
+        yg = y[:args.cpu_rows].cpu().numpy()
+        rec["cpu_baseline"] = {"value": args.cpu_rows / dt, "unit": "candidates/s", "cores": torch.get_num_threads(),
+                               "kind": "oracle", "sample": f"first {args.cpu_rows} rows of the last held-out platform",
+                               "max_abs_diff_vs_gpu": float(np.abs(yr - yg).max())}
+    print(json.dumps(rec), flush=True)
+
+
+# ----------------------------------------------------------------------- search
+
+def run_search(args, torch, H):
+    """Plain (random warm-up + greedy mutation) search against surrogate-guided
+    search on the 64x64 instance; best makespan against wall time."""
+    w = I.WORKLOADS["chol64x64_b1024_d3"]
+    nt = args.search_nt or w.nt
+    dev = torch.device("cuda")
+    pf_in = w.platform()
+    pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
+    thr = I.split_threshold(w.p_num, w.p_den)
+    mut = int(round(args.mutate * (1 << 21)))
+    plan = H.Plan()
+    common = dict(rounds=args.rounds, seed=w.seed, warm_rounds=1, pool=args.pool, split_thr=thr, mutate_thr=mut)
+    _, plain_best, plain_tr = H.search(plan, pf, nt, w.dmax, H.SEARCH_GREEDY, batch=args.batch,
+                                       warm_batch=args.batch, **common)
+    m = H.MLP(args.mlp_seed)
+    rate = torch.from_numpy(H.mlp_rate_features(pf_in.rmax)).to(dev)
+    sbatch = max(1, args.batch // args.sur_ratio)
+    best_d, sur_best, sur_tr = H.search(plan, pf, nt, w.dmax, H.SEARCH_SURROGATE, batch=sbatch,
+                                        warm_batch=args.sur_warm or args.batch,
+                                        proposals=sbatch * args.sur_proposals, mlp=m, rate=rate,
+                                        train_steps=args.sur_train_steps, train_batch=512, lr=1e-3,
+                                        replay=1 << 16, **common)
+    target = plain_best * 1.01
+    reach = next((t["wall_ms"] for t in sur_tr if t["best_makespan"] <= target), None)
+    plain_ms = plain_tr[-1]["wall_ms"]
+    rec = {
+        "metric": "time-to-best-makespan: surrogate-guided vs plain search",
+        "value": (reach / plain_ms) if reach is not None else None, "unit": "fraction of plain search wall time",
+        "n_gpus": 1, "steps": args.rounds, "warmup": 0, "ms_per_step": plain_ms / args.rounds,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": w.name if nt == w.nt else f"{w.name} platform and depth, nt={nt}",
+                   "nt": nt, "b": w.b, "dmax": w.dmax, "rounds": args.rounds,
+                   "plain_batch": args.batch, "surrogate_batch": sbatch,
+                   "surrogate_proposals": sbatch * args.sur_proposals, "pool": args.pool,
+                   "mutate_prob": args.mutate, "parallelism": "none (1 GPU)"},
+        "plain": {"best_makespan": plain_best, "wall_ms": plain_ms, "trace": plain_tr},
+        "surrogate": {"best_makespan": sur_best, "wall_ms": sur_tr[-1]["wall_ms"], "trace": sur_tr,
+                      "reached_1pct_of_plain_at_ms": reach},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 # ----------------------------------------------------------------------- main
 
 def main():
@@ -125,6 +297,22 @@ def main():
     ap.add_argument("--n-cand", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--train-platforms", type=int, default=64)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--mlp-seed", type=int, default=1)
+    ap.add_argument("--cpu-rows", type=int, default=65536)
+    ap.add_argument("--search-nt", type=int, default=16,
+                    help="tiles per dimension of the searched instance (the 64x64 one: 64)")
+    ap.add_argument("--rounds", type=int, default=64)
+    ap.add_argument("--batch", type=int, default=16384)
+    ap.add_argument("--pool", type=int, default=64)
+    ap.add_argument("--mutate", type=float, default=0.004)
+    ap.add_argument("--sur-ratio", type=int, default=16)
+    ap.add_argument("--sur-proposals", type=int, default=16)
+    ap.add_argument("--sur-warm", type=int, default=4096)
+    ap.add_argument("--sur-train-steps", type=int, default=20)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -139,6 +327,10 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
 
+    if args.workload == "surrogate_chol4x4":
+        return run_surrogate(args, torch, H)
+    if args.workload == "chol64x64_b1024_d3":
+        return run_search(args, torch, H)
     w = I.WORKLOADS[args.workload]
     if w.ragged:
         raise SystemExit("bench.py times uniform workloads; the ragged one is a parity case")

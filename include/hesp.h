@@ -238,10 +238,12 @@ int hesp_mlp_forward(hesp_mlp *mlp, const uint16_t *d_x, int64_t n, float *d_y, 
 int hesp_mlp_grad(hesp_mlp *mlp, const uint16_t *d_x, const float *d_t, int32_t batch, float *d_loss, void *stream);
 /* one Adam step with the current gradients */
 int hesp_mlp_adam(hesp_mlp *mlp, float lr, void *stream);
-/* `steps` (gradient, Adam) steps over consecutive batches of d_x/d_t (wrapping
- * after the last full batch); d_loss [steps] (nullable) gets each loss */
+/* `steps` (gradient, Adam) steps, each on `batch` rows (a multiple of 512) of the
+ * n rows of d_x/d_t drawn with replacement: row r of step s is row
+ * draw(seed, 7, s << 32 | r) mod n, s counting the network's Adam steps so far.
+ * d_loss [steps] (nullable) gets each step's loss. */
 int hesp_mlp_train(hesp_mlp *mlp, const uint16_t *d_x, const float *d_t, int64_t n, int32_t batch, int32_t steps,
-                   float lr, float *d_loss, void *stream);
+                   float lr, uint64_t seed, float *d_loss, void *stream);
 /* Rate features of a platform (host): out[4*p + kind] = log2(rmax_mflops / 131072) / 4
  * for processor type p and task kind (chol, trsm, syrk, gemm); n_out >= 4 * n_ptypes. */
 int hesp_mlp_rate_features(const hesp_cost_model *cm, float *out, int32_t n_out);
@@ -280,9 +282,9 @@ int hesp_topk_score(const float *d_score, int32_t n, int32_t k, int32_t *d_idx, 
  *              (SplitMix64 stream of draw(seed, 6, round << 32 | c)).
  *   SURROGATE: as GREEDY, but `proposals` mutations per round are scored by the
  *              network and only the `batch` best-scored are simulated; the network
- *              is trained online (train_steps Adam steps of train_batch rows per
- *              round) on every exact result kept in a ring of `replay` rows, with
- *              targets normalised by the warm-up rounds' log-makespans.  Features:
+ *              is trained online, each round by hesp_mlp_train (train_steps steps
+ *              of train_batch rows drawn from every exact result kept in a ring of
+ *              `replay` rows), with targets normalised by the warm-up rounds' log-makespans.  Features:
  *              raw depths when tet(nt) + n_rate <= 32, else the aggregate features
  *              of hesp_mlp_features_agg.
  * The incumbents are the `pool` best distinct-index results so far.  best_depth

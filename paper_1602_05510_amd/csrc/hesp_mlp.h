@@ -19,6 +19,16 @@ constexpr int64_t kOffB3 = kOffW3 + (int64_t)kHidden * kHidden;
 constexpr int64_t kOffW4 = kOffB3 + kHidden;
 constexpr int64_t kOffB4 = kOffW4 + kHidden;
 constexpr int64_t kParams = kOffB4 + 1;
+// transposed bf16 copies of the weight matrices used by the fused forward pass
+constexpr int64_t kOffT1 = 0;                                   // [hidden][in]
+constexpr int64_t kOffT2 = kOffT1 + (int64_t)kInDim * kHidden;  // [hidden][hidden]
+constexpr int64_t kOffT3 = kOffT2 + (int64_t)kHidden * kHidden;
+constexpr int64_t kTParams = kOffT3 + (int64_t)kHidden * kHidden;
+
+// whole network, any n: y[n] (fp32) from x[n][in] (bf16)
+hipError_t mlp_forward(const uint16_t* x, int64_t n, const uint16_t* wt, const float* p, const uint16_t* w4, float* y,
+                       hipStream_t s);
+hipError_t transpose_w(const float* p, uint16_t* wt, hipStream_t s);
 
 hipError_t gemm(bool ta, bool tb, int M, int N, int K, int splits, const uint16_t* A, int lda, const uint16_t* B,
                 int ldb, const float* bias, bool relu, const uint16_t* mask, int ldm, float* out_f32,
@@ -39,6 +49,8 @@ hipError_t adam(float* w, const float* g, float* m1, float* m2, int64_t n, float
                 int step, uint16_t* wbf, hipStream_t s);
 hipError_t to_bf16(const float* w, int64_t n, uint16_t* out, hipStream_t s);
 hipError_t zero_f32(float* p, int64_t n, hipStream_t s);
+hipError_t sample_rows(const uint16_t* x, const float* t, int64_t n, uint64_t seed, uint64_t step, int batch,
+                       uint16_t* xb, float* tb, hipStream_t s);
 
 }  // namespace mlp
 }  // namespace hesp

@@ -109,6 +109,118 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int kc, const uint16
       }
 }
 
+// ---------------------------------------------------------------- fused forward
+// The whole network for 128 rows per 256-thread workgroup.  Activations stay in
+// LDS (128 x 256 bf16); weights come from L2 in a transposed bf16 copy
+// (wt[n][k], k contiguous) so that each lane's MFMA B operand is one 16-byte
+// load.  Wave w owns output columns [64w, 64w + 64) of every layer: 8 row
+// blocks x 4 column blocks of 16x16 accumulators.  The last layer's dot with w4
+// is reduced across lanes and waves through LDS.
+constexpr int FM = 128, FLD = kHidden + 8;
+
+__device__ __forceinline__ void fwd_epilogue(const f32x4 (&acc)[8][4], const float* __restrict__ bias, int w, int l,
+                                             uint16_t (*sH)[FLD]) {
+  for (int cb = 0; cb < 4; cb++) {
+    const int col = w * 64 + cb * 16 + (l & 15);
+    const float bv = bias[col];
+    for (int rb = 0; rb < 8; rb++)
+      for (int i = 0; i < 4; i++) {
+        const float v = acc[rb][cb][i] + bv;
+        sH[rb * 16 + (l >> 4) * 4 + i][col] = f2bf(v > 0.f ? v : 0.f);
+      }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mlp_fwd(const uint16_t* __restrict__ x, int64_t n,
+                                                 const uint16_t* __restrict__ wt, const float* __restrict__ p,
+                                                 const uint16_t* __restrict__ w4, float* __restrict__ y) {
+  __shared__ __attribute__((aligned(16))) uint16_t sH[FM][FLD];
+  __shared__ float sY[4][FM];
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * FM;
+  f32x4 acc[8][4];
+  // layer 1 (K = 32): A straight from the input rows
+  for (int rb = 0; rb < 8; rb++)
+    for (int cb = 0; cb < 4; cb++) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  {
+    bf16x8 b[4];
+    for (int cb = 0; cb < 4; cb++)
+      b[cb] = *(const bf16x8*)(wt + kOffT1 + (int64_t)(w * 64 + cb * 16 + (l & 15)) * kInDim + (l >> 4) * 8);
+    for (int rb = 0; rb < 8; rb++) {
+      const int64_t row = r0 + rb * 16 + (l & 15);
+      u32x4 av = {0u, 0u, 0u, 0u};
+      if (row < n) av = *(const u32x4*)(x + row * kInDim + (l >> 4) * 8);
+      const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+      for (int cb = 0; cb < 4; cb++) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[cb], acc[rb][cb], 0, 0, 0);
+    }
+  }
+  fwd_epilogue(acc, p + kOffB1, w, l, sH);
+  __syncthreads();
+  // layers 2 and 3 (K = 256): A from LDS
+  for (int layer = 0; layer < 2; layer++) {
+    const uint16_t* wl = wt + (layer == 0 ? kOffT2 : kOffT3);
+    for (int rb = 0; rb < 8; rb++)
+      for (int cb = 0; cb < 4; cb++) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < kHidden; k0 += 32) {
+      bf16x8 b[4];
+      for (int cb = 0; cb < 4; cb++)
+        b[cb] = *(const bf16x8*)(wl + (int64_t)(w * 64 + cb * 16 + (l & 15)) * kHidden + k0 + (l >> 4) * 8);
+      for (int rb = 0; rb < 8; rb++) {
+        const bf16x8 a = *(const bf16x8*)&sH[rb * 16 + (l & 15)][k0 + (l >> 4) * 8];
+        for (int cb = 0; cb < 4; cb++)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[cb], acc[rb][cb], 0, 0, 0);
+      }
+    }
+    __syncthreads();   // every wave has read this layer's input
+    if (layer == 0) {
+      fwd_epilogue(acc, p + kOffB2, w, l, sH);
+      __syncthreads();
+    }
+  }
+  // output: y = bf16(relu(z3 + b3)) . w4 + b4
+  float part[8][4];
+  for (int rb = 0; rb < 8; rb++)
+    for (int i = 0; i < 4; i++) part[rb][i] = 0.f;
+  for (int cb = 0; cb < 4; cb++) {
+    const int col = w * 64 + cb * 16 + (l & 15);
+    const float bv = p[kOffB3 + col];
+    const float wv = bf2f(w4[col]);
+    for (int rb = 0; rb < 8; rb++)
+      for (int i = 0; i < 4; i++) {
+        const float v = acc[rb][cb][i] + bv;
+        part[rb][i] += bf2f(f2bf(v > 0.f ? v : 0.f)) * wv;
+      }
+  }
+  for (int rb = 0; rb < 8; rb++)
+    for (int i = 0; i < 4; i++) {
+      float v = part[rb][i];
+      for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+      if ((l & 15) == 0) sY[w][rb * 16 + (l >> 4) * 4 + i] = v;
+    }
+  __syncthreads();
+  if (t < FM) {
+    const int64_t row = r0 + t;
+    if (row < n) y[row] = ((sY[0][t] + sY[1][t]) + (sY[2][t] + sY[3][t])) + p[kOffB4];
+  }
+}
+
+// transposed bf16 copies of W1, W2, W3 (wt[n][k] = W[k][n])
+__global__ void k_transpose_w(const float* __restrict__ p, uint16_t* __restrict__ wt) {
+  const int64_t total = kTParams;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t src;
+    if (e < kOffT2) {
+      const int64_t nn = e / kInDim, kk = e % kInDim;
+      src = kOffW1 + kk * kHidden + nn;
+    } else {
+      const int64_t f = e < kOffT3 ? e - kOffT2 : e - kOffT3;
+      const int64_t nn = f / kHidden, kk = f % kHidden;
+      src = (e < kOffT3 ? kOffW2 : kOffW3) + kk * kHidden + nn;
+    }
+    wt[e] = f2bf(p[src]);
+  }
+}
+
 // sum of `splits` fp32 slices of size count -> out (fp32)
 __global__ void k_sum_splits(const float* __restrict__ parts, int splits, int64_t count, float* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
@@ -277,6 +389,25 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
   }
 }
 
+// training batch: row r is row draw(seed, 7, step << 32 | r) mod n of (x, t)
+__global__ void k_sample_rows(const uint16_t* __restrict__ x, const float* __restrict__ t, int64_t n, uint64_t seed,
+                              uint64_t step, int batch, uint16_t* __restrict__ xb, float* __restrict__ tb) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= batch) return;
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * 8ull;   // purpose 7
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = (z ^ (z >> 31)) + 0x9E3779B97F4A7C15ull * (((step << 32) | (uint64_t)r) + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  const int64_t row = (int64_t)(z % (uint64_t)n);
+  const u32x4* src = (const u32x4*)(x + row * kInDim);
+  u32x4* dst = (u32x4*)(xb + (int64_t)r * kInDim);
+  for (int q = 0; q < kInDim / 8; q++) dst[q] = src[q];
+  tb[r] = t[row];
+}
+
 __global__ void k_zero_f32(float* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.f;
 }
@@ -312,6 +443,18 @@ hipError_t gemm(bool ta, bool tb, int M, int N, int K, int splits, const uint16_
   else
     hipLaunchKernelGGL((k_gemm<true, true>), grid, block, 0, s, M, N, kc, A, lda, B, ldb, bias, relu ? 1 : 0, mask, ldm,
                        out_f32, out_bf16, ldc);
+  return hipGetLastError();
+}
+
+hipError_t mlp_forward(const uint16_t* x, int64_t n, const uint16_t* wt, const float* p, const uint16_t* w4, float* y,
+                       hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((n + FM - 1) / FM)), dim3(256), 0, s, x, n, wt, p, w4, y);
+  return hipGetLastError();
+}
+
+hipError_t transpose_w(const float* p, uint16_t* wt, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose_w, dim3(grid1(kTParams)), dim3(256), 0, s, p, wt);
   return hipGetLastError();
 }
 
@@ -363,6 +506,12 @@ hipError_t adam(float* w, const float* g, float* m1, float* m2, int64_t n, float
                 int step, uint16_t* wbf, hipStream_t s) {
   const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
   hipLaunchKernelGGL(k_adam, dim3(grid1(n)), dim3(256), 0, s, w, g, m1, m2, n, lr, b1, b2, eps, c1, c2, wbf);
+  return hipGetLastError();
+}
+
+hipError_t sample_rows(const uint16_t* x, const float* t, int64_t n, uint64_t seed, uint64_t step, int batch,
+                       uint16_t* xb, float* tb, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_rows, dim3((batch + 255) / 256), dim3(256), 0, s, x, t, n, seed, step, batch, xb, tb);
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // hesp_mlp_api.cpp -- C ABI of the learned surrogate (declared in include/hesp.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -52,13 +53,17 @@ struct hesp_mlp {
   float* m1 = nullptr;      // Adam first moment
   float* m2 = nullptr;      // Adam second moment
   uint16_t* wbf = nullptr;  // bf16 copy of the parameters
+  uint16_t* wbt = nullptr;  // transposed bf16 copies of W1, W2, W3 (fused forward)
   int step = 0;
   int64_t rows = 0;         // activation capacity
   uint16_t *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *dza = nullptr, *dzb = nullptr;
   float *y = nullptr, *dy = nullptr, *parts = nullptr, *loss = nullptr;
   int64_t parts_cap = 0;
+  uint16_t* xb = nullptr;   // sampled training batch
+  float* tb = nullptr;
+  int64_t sample_rows = 0;
   void release() {
-    for (void* q : {(void*)p, (void*)g, (void*)m1, (void*)m2, (void*)wbf}) hfree(q);
+    for (void* q : {(void*)p, (void*)g, (void*)m1, (void*)m2, (void*)wbf, (void*)wbt, (void*)xb, (void*)tb}) hfree(q);
     release_ws();
   }
   void release_ws() {
@@ -144,7 +149,8 @@ int hesp_mlp_create(hesp_mlp** out, uint64_t seed) {
   const size_t pb = kParams * sizeof(float);
   hipError_t e;
   if ((e = hipMalloc(&m->p, pb)) || (e = hipMalloc(&m->g, pb)) || (e = hipMalloc(&m->m1, pb)) ||
-      (e = hipMalloc(&m->m2, pb)) || (e = hipMalloc(&m->wbf, kParams * sizeof(uint16_t)))) {
+      (e = hipMalloc(&m->m2, pb)) || (e = hipMalloc(&m->wbf, kParams * sizeof(uint16_t))) ||
+      (e = hipMalloc(&m->wbt, kTParams * sizeof(uint16_t)))) {
     m->release();
     delete m;
     return fail(HESP_ENOMEM, "hesp_mlp_create: %s", hipGetErrorString(e));
@@ -190,6 +196,7 @@ int hesp_mlp_set_params(hesp_mlp* m, const float* host, int64_t n) {
   HIP_TRY(hipMemset(m->m2, 0, kParams * sizeof(float)));
   HIP_TRY(hipMemset(m->g, 0, kParams * sizeof(float)));
   HIP_TRY(to_bf16(m->p, kParams, m->wbf, nullptr));
+  HIP_TRY(transpose_w(m->p, m->wbt, nullptr));
   HIP_TRY(hipDeviceSynchronize());
   m->step = 0;
   return HESP_OK;
@@ -228,14 +235,12 @@ int hesp_mlp_targets(const int64_t* d_makespan, int64_t n, float mu, float sigma
 
 int hesp_mlp_forward(hesp_mlp* m, const uint16_t* d_x, int64_t n, float* d_y, void* stream) {
   if (!m || n < 0 || (n > 0 && (!d_x || !d_y))) return fail(HESP_EINVAL, "hesp_mlp_forward: bad argument");
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t chunk = n < 262144 ? n : 262144;
   if (n == 0) return HESP_OK;
-  HIP_TRY(m->ensure(chunk, 0));
-  for (int64_t r = 0; r < n; r += chunk) {
-    const int64_t k = n - r < chunk ? n - r : chunk;
-    HIP_TRY(forward_rows(m, d_x + r * kInDim, k, d_y + r, s));
-  }
+  // one fused launch (activations never leave LDS); at most 2^31 rows per launch
+  const int64_t chunk = (int64_t)1 << 31;
+  for (int64_t r = 0; r < n; r += chunk)
+    HIP_TRY(mlp_forward(d_x + r * kInDim, std::min(chunk, n - r), m->wbt, m->p, m->wbf + kOffW4, d_y + r,
+                        (hipStream_t)stream));
   return HESP_OK;
 }
 
@@ -276,16 +281,29 @@ int hesp_mlp_adam(hesp_mlp* m, float lr, void* stream) {
   if (!m || !(lr > 0.f)) return fail(HESP_EINVAL, "hesp_mlp_adam: bad argument");
   m->step++;
   HIP_TRY(adam(m->p, m->g, m->m1, m->m2, kParams, lr, 0.9f, 0.999f, 1e-8f, m->step, m->wbf, (hipStream_t)stream));
+  HIP_TRY(transpose_w(m->p, m->wbt, (hipStream_t)stream));
   return HESP_OK;
 }
 
 int hesp_mlp_train(hesp_mlp* m, const uint16_t* d_x, const float* d_t, int64_t n, int32_t batch, int32_t steps,
-                   float lr, float* d_loss, void* stream) {
-  if (!m || batch <= 0 || n < batch || steps < 0) return fail(HESP_EINVAL, "hesp_mlp_train: bad argument");
-  const int64_t nb = n / batch;
+                   float lr, uint64_t seed, float* d_loss, void* stream) {
+  if (!m || !d_x || !d_t || batch <= 0 || batch % 512 || n < 1 || steps < 0 || !(lr > 0.f))
+    return fail(HESP_EINVAL, "hesp_mlp_train: bad argument (batch a positive multiple of 512, n >= 1)");
+  hipStream_t s = (hipStream_t)stream;
+  if (m->sample_rows < batch) {
+    hfree(m->xb);
+    hfree(m->tb);
+    m->xb = nullptr;
+    m->tb = nullptr;
+    m->sample_rows = 0;
+    HIP_TRY(hipMalloc(&m->xb, (size_t)batch * kInDim * sizeof(uint16_t)));
+    HIP_TRY(hipMalloc(&m->tb, (size_t)batch * sizeof(float)));
+    m->sample_rows = batch;
+  }
   for (int32_t i = 0; i < steps; i++) {
-    const int64_t r = (i % nb) * (int64_t)batch;
-    int rc = hesp_mlp_grad(m, d_x + r * kInDim, d_t + r, batch, d_loss ? d_loss + i : nullptr, stream);
+    // rows drawn with replacement; the counter is the network's Adam step number
+    HIP_TRY(sample_rows(d_x, d_t, n, seed, (uint64_t)m->step, batch, m->xb, m->tb, s));
+    int rc = hesp_mlp_grad(m, m->xb, m->tb, batch, d_loss ? d_loss + i : nullptr, stream);
     if (rc) return rc;
     rc = hesp_mlp_adam(m, lr, stream);
     if (rc) return rc;

@@ -224,7 +224,7 @@ int hesp_search(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, co
   };
 
   int cur = 0, pool_n = 0;
-  int64_t first = 0, simulated = 0, proposed = 0, filled = 0, rep_pos = 0, train_off = 0;
+  int64_t first = 0, simulated = 0, proposed = 0, filled = 0, rep_pos = 0;
   float mu = 0.f, sigma = 1.f;
   HIP_TRY(hipStreamSynchronize(s));
   const double t0 = now_ms();
@@ -301,12 +301,8 @@ int hesp_search(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, co
       }
       if (r >= sp->warm_rounds - 1 && filled >= sp->train_batch) {
         RC_TRY(hesp_mlp_targets(rep_ms, filled, mu, sigma, rep_t, s));
-        for (int q = 0; q < sp->train_steps; q++) {
-          if (train_off + sp->train_batch > filled) train_off = 0;
-          RC_TRY(hesp_mlp_grad(sp->mlp, rep_x + train_off * mlp::kInDim, rep_t + train_off, sp->train_batch, nullptr, s));
-          RC_TRY(hesp_mlp_adam(sp->mlp, sp->lr, s));
-          train_off += sp->train_batch;
-        }
+        RC_TRY(hesp_mlp_train(sp->mlp, rep_x, rep_t, filled, sp->train_batch, sp->train_steps, sp->lr, sp->seed,
+                              nullptr, s));
       }
     }
     if (trace) {

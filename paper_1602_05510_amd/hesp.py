@@ -111,7 +111,7 @@ def lib():
             "hesp_mlp_forward": [P, P, i64, P, P],
             "hesp_mlp_grad": [P, P, P, i32, P, P],
             "hesp_mlp_adam": [P, ctypes.c_float, P],
-            "hesp_mlp_train": [P, P, P, i64, i32, i32, ctypes.c_float, P, P],
+            "hesp_mlp_train": [P, P, P, i64, i32, i32, ctypes.c_float, u64, P, P],
             "hesp_mlp_rate_features": [ctypes.POINTER(CostModel), P, i32],
             "hesp_mlp_features_agg": [P, i64, i32, P, i32, P, P],
             "hesp_generate_enumerate": [i64, i32, i32, i32, P, P],
@@ -357,9 +357,10 @@ class MLP:
     def adam(self, lr: float, stream=None):
         _check("hesp_mlp_adam", lib().hesp_mlp_adam(self.h, lr, _stream(stream)))
 
-    def train(self, x, t, batch: int, steps: int, lr: float, loss=None, stream=None):
+    def train(self, x, t, batch: int, steps: int, lr: float, seed: int = 0, loss=None, stream=None):
+        """steps Adam steps on batches drawn with replacement from the rows of (x, t)."""
         _check("hesp_mlp_train", lib().hesp_mlp_train(self.h, _dev(x), _dev(t), int(t.numel()), batch, steps, lr,
-                                                      _dev(loss), _stream(stream)))
+                                                      seed, _dev(loss), _stream(stream)))
 
     def close(self):
         if self.h:

@@ -198,7 +198,7 @@ def test_train_reduces_loss(H):
     xd, td = _x_bits(X), torch.from_numpy(t).cuda()
     steps = 400
     loss = torch.zeros(steps, dtype=torch.float32, device="cuda")
-    m.train(xd, td, 1024, steps, 1e-3, loss)
+    m.train(xd, td, 1024, steps, 1e-3, seed=7, loss=loss)
     l = loss.cpu().numpy()
     assert np.isfinite(l).all()
     assert l[-20:].mean() < 0.1 * l[:5].mean(), (l[:5], l[-20:])

@@ -215,3 +215,49 @@ def test_exhaustive_sweep_4x4(H, torch):
     idx = rng.choice(n, 256, replace=False)
     want, _ = O.simulate_batch(pf_in, _host_batch(dep[idx], 4, 1, w.b), NTHREADS)
     assert np.array_equal(msh[idx], want)
+
+
+def test_surrogate_gain_over_random_selection(H, torch):
+    """What the trained network gains: on a platform it never saw, the 1% of all
+    2^20 partitions it ranks best are far better than a random 1%, and contain a
+    partition close to the exhaustive optimum."""
+    w = I.WORKLOADS["surrogate_chol4x4"]
+    thr = I.split_threshold(1, 2)
+    n_pf, per = 16, 8192
+    X = torch.empty((n_pf * per, 32), dtype=torch.int16, device="cuda")
+    MS = torch.empty(n_pf * per, dtype=torch.int64, device="cuda")
+    st = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
+    plan = H.Plan()
+    for p in range(n_pf):
+        pf_in = w.platform(p)
+        pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
+        db = H.generate_uniform(w.seed, p * per, per, 4, 1, thr)
+        H.simulate_batch(plan, pf, db, MS[p * per:(p + 1) * per], st[:per])
+        rate = torch.from_numpy(H.mlp_rate_features(pf_in.rmax)).cuda()
+        H.mlp_features(db.depth, per, 20, rate, X[p * per:(p + 1) * per])
+    lms = torch.log(MS.double())
+    mu, sigma = float(lms.mean()), float(lms.std())
+    T = torch.empty(n_pf * per, dtype=torch.float32, device="cuda")
+    H.mlp_targets(MS, mu, sigma, T)
+    m = H.MLP(2)
+    m.train(X, T, 2048, 1500, 1e-3, seed=3)
+    n = 1 << 20
+    pf_in = w.platform(1000)
+    pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
+    db = H.generate_enumerate(0, n, 4, 1)
+    ms = torch.empty(n, dtype=torch.int64, device="cuda")
+    H.simulate_batch(plan, pf, db, ms, st)
+    rate = torch.from_numpy(H.mlp_rate_features(pf_in.rmax)).cuda()
+    Xh = torch.empty((n, 32), dtype=torch.int16, device="cuda")
+    H.mlp_features(db.depth, n, 20, rate, Xh)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    m.forward(Xh, y)
+    k = n // 100
+    top = ms[H.topk(y, k).long()].cpu().numpy()
+    msh = ms.cpu().numpy()
+    rnd = msh[np.random.default_rng(0).choice(n, k, replace=False)]
+    best = msh.min()
+    print("top1% best/opt", top.min() / best, "random1% best/opt", rnd.min() / best,
+          "mean ratio", top.mean() / rnd.mean())
+    assert top.mean() < 0.95 * rnd.mean()
+    assert top.min() <= 1.02 * best

@@ -153,3 +153,26 @@ def test_expand_counts_two_call():
         tasks, ptr, idx = H.expand(w.nt, w.dmax, bt.candidate(c))
         s = O.simulate(w.platform(), w.nt, w.dmax, w.b, bt.candidate(c), detail=False)
         assert len(tasks) > 0 and ptr[-1] == len(idx)
+
+
+def test_rate_features():
+    # log2(R / 2^17) / 4: R = 2^17 gives 0, R = 2^21 gives 1, R = 2^13 gives -1
+    r = np.array([[1 << 17, 1 << 21, 1 << 13, 3 << 17]], np.int64)
+    f = H.mlp_rate_features(r)
+    assert f.dtype == np.float32 and f.shape == (4,)
+    assert f[0] == 0.0 and f[1] == 1.0 and f[2] == -1.0
+    assert abs(f[3] - np.log2(3) / 4) < 1e-7
+    with pytest.raises(H.HespError):
+        H.mlp_rate_features(np.array([[1, 2, 0, 4]], np.int64))
+
+
+def test_search_argument_errors_need_no_gpu():
+    # argument checks run before any device work
+    w = I.WORKLOADS["chol4x4_b512_d1"]
+    pf = H.Platform.from_inputs(w.platform(), w.b, w.dmax)
+    sp = H.SearchParams(H.SEARCH_GREEDY, 4, 1, 0, 16, 1, 16, 16, 4, 0, 0, 1, None, None, 0, 0, 512, 1e-3, 0)
+    best = np.zeros(20, np.uint8)
+    ms = H.i64(0)
+    rc = H.lib().hesp_search(ctypes.c_void_p(1), ctypes.byref(pf.c), H.Policy(0, 0, 0), ctypes.byref(sp),
+                             best.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ms), None, None)
+    assert rc == H.HESP_EINVAL          # rounds = 0
