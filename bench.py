@@ -332,8 +332,6 @@ def main():
     if args.workload == "chol64x64_b1024_d3":
         return run_search(args, torch, H)
     w = I.WORKLOADS[args.workload]
-    if w.ragged:
-        raise SystemExit("bench.py times uniform workloads; the ragged one is a parity case")
     n = args.n_cand or w.n_cand
     pf_in = w.platform()
     pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
@@ -350,8 +348,14 @@ def main():
     plan.timing(True)
     sim_ms = []
 
+    def gen(i: int):
+        if w.ragged:
+            r = w.ragged
+            return H.generate_ragged(w.seed, i * n, n, r["nt_lo"], r["nt_hi"], r["dmax_hi"], thr)
+        return H.generate_uniform(w.seed, i * n, n, w.nt, w.dmax, thr)
+
     def step(i: int, timed: bool):
-        db = H.generate_uniform(w.seed, i * n, n, w.nt, w.dmax, thr)
+        db = gen(i)
         H.simulate_batch(plan, pf, db, ms, st, n_tasks=ntk)
         H.argmin(ms, best)
         if timed:
@@ -384,20 +388,22 @@ def main():
     launches_per_step = sim_launches / len(sim_ms)
 
     # roofline accounting for the simulation kernel (steps are statistically alike;
-    # the accounting uses the batch of the last step)
-    host_last = w.batch(n, first=(args.steps - 1) * n)
-    db_last = H.DeviceBatch.from_host(host_last)
-    _, e_last = H.count_batch(db_last)
-    alg_bytes, alg_tasks = algorithmic_bytes(host_last, pf_in.n_mem, int(e_last.sum().item()))
-    achieved = alg_bytes / (sim_avg_ms * launches_per_step * 1e-3) / 1e9
-    traffic = None
-    pmc_path = os.path.join(PROFILES, f"k_sim_{w.name}_pmc.json")
-    if os.path.exists(pmc_path):
-        with open(pmc_path) as f:
-            pmc = json.load(f)
-        if pmc.get("kernel_sha") == kernel_hash() and pmc.get("n_cand") == n:
-            traffic = pmc.get("hbm_bytes_per_launch")
-    traffic_note = None if traffic is not None else "no counter run on this kernel source"
+    # the accounting uses the batch of the last step); uniform batches only
+    achieved = traffic = alg_bytes = None
+    traffic_note = "ragged batch: no algorithmic byte count"
+    if not w.ragged:
+        host_last = w.batch(n, first=(args.steps - 1) * n)
+        db_last = H.DeviceBatch.from_host(host_last)
+        _, e_last = H.count_batch(db_last)
+        alg_bytes, alg_tasks = algorithmic_bytes(host_last, pf_in.n_mem, int(e_last.sum().item()))
+        achieved = alg_bytes / (sim_avg_ms * launches_per_step * 1e-3) / 1e9
+        pmc_path = os.path.join(PROFILES, f"k_sim_{w.name}_pmc.json")
+        if os.path.exists(pmc_path):
+            with open(pmc_path) as f:
+                pmc = json.load(f)
+            if pmc.get("kernel_sha") == kernel_hash() and pmc.get("n_cand") == n:
+                traffic = pmc.get("hbm_bytes_per_launch")
+        traffic_note = None if traffic is not None else "no counter run on this kernel source"
 
     value = tasks_total / elapsed
     rec = {
@@ -413,22 +419,26 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_cand": n, "nt": w.nt, "b": w.b, "dmax": w.dmax,
+        "config": {"workload": w.name, "n_cand": n,
+                   "nt": f"{w.ragged['nt_lo']}..{w.ragged['nt_hi']}" if w.ragged else w.nt, "b": w.b,
+                   "dmax": f"0..{w.ragged['dmax_hi']}" if w.ragged else w.dmax,
                    "split_prob": f"{w.p_num}/{w.p_den}",
                    "platform": " + ".join(f"{t.count} {t.name}" for t in w.ptypes),
                    "parallelism": "none (1 GPU)"},
         "candidates_per_s": n * args.steps / elapsed,
         "tasks_per_step": tasks_total / args.steps,
         "roofline": {"bound": "hbm", "kernel": "k_sim", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": alg_bytes / launches_per_step, "launch_ms": sim_avg_ms,
+                     "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "traffic_note": traffic_note,
+                     "algorithmic_bytes_per_launch": None if alg_bytes is None else alg_bytes / launches_per_step,
+                     "launch_ms": sim_avg_ms,
                      "launches_per_step": launches_per_step, "prepare_launch_ms": prep_avg_ms,
                      "kernel_sha": kernel_hash()},
     }
     if not args.no_cpu_baseline:
         host0 = w.batch(n, first=0)
         # recompute step 0's makespans for the sample comparison
-        db = H.generate_uniform(w.seed, 0, n, w.nt, w.dmax, thr)
+        db = gen(0)
         H.simulate_batch(plan, pf, db, ms, st, n_tasks=ntk)
         torch.cuda.synchronize()
         rec["cpu_baseline"] = cpu_baseline(w, pf_in, host0, ms.cpu().numpy(), args.cpu_budget)

@@ -14,6 +14,7 @@
 #include "hesp.h"
 #include "hesp_core.h"
 #include "hesp_internal.h"
+#include "hesp_search.h"
 
 using namespace hesp;
 
@@ -80,7 +81,7 @@ struct hesp_plan {
   // per batch
   DevBuf cnt_tasks, cnt_edges, off_t, off_e, off_v, off_top, bounds;
   // per chunk
-  DevBuf top_first, desc, indeg, cur, succ, rec, fifo, ready, sortbuf, vf, nsrc;
+  DevBuf top_first, desc, indeg, cur, succ, rec, fifo, ready, sortbuf, vf, nsrc, order_keys, order;
   std::vector<int64_t> h_bounds;
   // autotuned lanes per candidate, by (processors, memory spaces, nt, dmax, ragged)
   std::map<std::tuple<int, int, int, int, int>, int> tuned;
@@ -91,11 +92,11 @@ struct hesp_plan {
   int64_t held() const {
     return cnt_tasks.bytes + cnt_edges.bytes + off_t.bytes + off_e.bytes + off_v.bytes + off_top.bytes +
            bounds.bytes + top_first.bytes + desc.bytes + indeg.bytes + cur.bytes + succ.bytes + rec.bytes +
-           fifo.bytes + ready.bytes + sortbuf.bytes + vf.bytes + nsrc.bytes;
+           fifo.bytes + ready.bytes + sortbuf.bytes + vf.bytes + nsrc.bytes + order_keys.bytes + order.bytes;
   }
   void release() {
     for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds, &top_first, &desc, &indeg,
-                      &cur, &succ, &rec, &fifo, &ready, &sortbuf, &vf, &nsrc})
+                      &cur, &succ, &rec, &fifo, &ready, &sortbuf, &vf, &nsrc, &order_keys, &order})
       b->release();
   }
 };
@@ -280,7 +281,7 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
     return fail(HESP_EHIP, "hesp_plan_create: %s", hipGetErrorString(e));
   }
   p->slots = p->opts.slots ? p->opts.slots : 32 * cus;
-  p->chunk = 32768;
+  p->chunk = 1 << 22;   // bounded by device memory below
   e = hipMalloc(&p->counter, sizeof(uint32_t));
   if (e != hipSuccess) {
     delete p;
@@ -433,6 +434,8 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   HIP_TRY(plan->sortbuf.ensure(32 * mT));
   HIP_TRY(plan->vf.ensure(8 * mV));
   HIP_TRY(plan->nsrc.ensure(4 * (int64_t)chunk));
+  HIP_TRY(plan->order_keys.ensure(8 * srch::sort_len(chunk)));
+  HIP_TRY(plan->order.ensure(4 * (int64_t)chunk));
 
   OutView ov{out->d_makespan, out->d_status, out->d_n_tasks, out->d_sched_off, out->d_proc, out->d_start,
              out->d_finish};
@@ -505,8 +508,12 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
       plan->ev.push_back(e);
     }
   for (int i = 0; i < n_chunks; i++) {
-    const ChunkView cv = chunk_view(i * chunk, std::min(chunk, n - i * chunk));
+    ChunkView cv = chunk_view(i * chunk, std::min(chunk, n - i * chunk));
     if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[3 * i], s));
+    // largest candidates first, so that the persistent launch does not end on a long one
+    HIP_TRY(srch::size_order(plan->cnt_tasks.as<int32_t>(), cv.c0, cv.nc, plan->order_keys.as<uint64_t>(),
+                             plan->order.as<uint32_t>(), s));
+    cv.order = plan->order.as<uint32_t>();
     HIP_TRY(launch_prepare(tb, bv, cv, ov, s));
     if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[3 * i + 1], s));
     HIP_TRY(launch_sim(tb, bv, cv, ov, plan->slots, group, plan->counter, s));

@@ -52,6 +52,7 @@ struct ChunkView {
   int64_t* sortbuf;                         // 4 per task
   int64_t* vf;                              // finest blocks x memory spaces
   int32_t* nsrc;                            // per candidate of the chunk
+  const uint32_t* order;                    // nullable: simulation order of the chunk's candidates
 };
 
 struct OutView {

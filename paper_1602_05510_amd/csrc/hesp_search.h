@@ -18,6 +18,9 @@ hipError_t keys_ms(const int64_t* a, int32_t na, const int64_t* b, int32_t nb, i
 // key = order-preserving bits of the score << 32 | position
 hipError_t keys_f32(const float* v, int64_t n, int64_t n2, uint64_t* keys, hipStream_t s);
 hipError_t sort(uint64_t* keys, int64_t n2, hipStream_t s);
+// order[0..nc) = local indices of candidates c0 .. c0+nc-1, largest task count
+// first (ties to the lower index); keys: sort_len(nc) entries of workspace
+hipError_t size_order(const int32_t* n_tasks, int32_t c0, int32_t nc, uint64_t* keys, uint32_t* order, hipStream_t s);
 hipError_t key_index(const uint64_t* keys, int32_t k, uint64_t mask, int32_t* idx, hipStream_t s);
 hipError_t gather_rows(const int32_t* idx, int32_t k, const uint8_t* src, int32_t n_top, uint8_t* out, hipStream_t s);
 hipError_t gather_pool(const uint64_t* keys, int32_t k, const uint8_t* pool_d, const int64_t* pool_ms, int32_t pool_n,

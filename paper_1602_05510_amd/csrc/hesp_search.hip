@@ -76,6 +76,16 @@ __global__ void k_keys_ms(const int64_t* __restrict__ a, int32_t na, const int64
   }
 }
 
+// keys of the candidates [c0, c0 + nc) by decreasing size: (2^32-1 - tasks) << 32 | local index
+__global__ void k_keys_size(const int32_t* __restrict__ n_tasks, int32_t c0, int32_t nc, int64_t n2,
+                            uint64_t* __restrict__ keys) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t k = ~0ull;
+    if (i < nc) k = ((uint64_t)(0xFFFFFFFFu - (uint32_t)n_tasks[c0 + i]) << 32) | (uint64_t)i;
+    keys[i] = k;
+  }
+}
+
 // keys of float scores: order-preserving bits (NaN last) above the index
 __global__ void k_keys_f32(const float* __restrict__ s, int64_t n, int64_t n2, uint64_t* __restrict__ keys) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
@@ -207,6 +217,14 @@ hipError_t keys_ms(const int64_t* a, int32_t na, const int64_t* b, int32_t nb, i
                    hipStream_t s) {
   hipLaunchKernelGGL(k_keys_ms, dim3(grid_for(n2)), dim3(256), 0, s, a, na, b, nb, n2, keys);
   return hipGetLastError();
+}
+
+hipError_t size_order(const int32_t* n_tasks, int32_t c0, int32_t nc, uint64_t* keys, uint32_t* order, hipStream_t s) {
+  const int64_t n2 = sort_len(nc);
+  hipLaunchKernelGGL(k_keys_size, dim3(grid_for(n2)), dim3(256), 0, s, n_tasks, c0, nc, n2, keys);
+  hipError_t e = sort(keys, n2, s);
+  if (e != hipSuccess) return e;
+  return key_index(keys, nc, 0xFFFFFFFFull, (int32_t*)order, s);
 }
 
 hipError_t keys_f32(const float* v, int64_t n, int64_t n2, uint64_t* keys, hipStream_t s) {

@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
       if (cc >= cv.nc) {
         exhausted = true;
       } else {
-        c = cv.c0 + cc;
+        c = cv.c0 + (cv.order ? (int)cv.order[cc] : cc);
         if (out.status[c] == kOK) {
           const Cand cd = load_cand(bv, c);
           nt = cd.nt;
