@@ -162,6 +162,13 @@ typedef struct {
   int32_t group;               /* lanes per candidate in the event simulation: 16, 32 or 64 (>= processors);
                                   0 = chosen per batch shape by timing each size once (autotuning) */
 } hesp_plan_opts;
+/* A plan with max_tasks, max_edges and group all set is a fixed-capacity plan:
+ * its workspace follows from the capacities and the batch shape, so after one
+ * call with a batch of a given (n_cand, nt, dmax) further calls of that shape do
+ * no host synchronisation, no allocation and no autotuning -- only kernel
+ * launches on `stream`, which can be captured in a HIP graph and replayed (the
+ * graph keeps the batch and output pointers of the captured call).  Candidates
+ * above the capacities get HESP_ECAPACITY. */
 int hesp_plan_create(hesp_plan **plan, const hesp_plan_opts *opts);
 int hesp_plan_destroy(hesp_plan *plan);
 /* device bytes currently held by the plan */

@@ -85,6 +85,9 @@ struct hesp_plan {
   std::vector<int64_t> h_bounds;
   // autotuned lanes per candidate, by (processors, memory spaces, nt, dmax, ragged)
   std::map<std::tuple<int, int, int, int, int>, int> tuned;
+  // fixed-capacity plans: chunk size chosen for (candidates, validity words, top-level tasks)
+  std::tuple<int64_t, int64_t, int64_t> fixed_key{-1, -1, -1};
+  int32_t fixed_chunk = 0;
   // optional kernel timing of the last call: events around each launch
   bool timing = false;
   std::vector<hipEvent_t> ev;   // per chunk: prepare start, prepare end = sim start, sim end
@@ -390,17 +393,40 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   for (DevBuf* b : {&plan->off_t, &plan->off_e, &plan->off_v, &plan->off_top}) HIP_TRY(b->ensure(8 * ((int64_t)n + 1)));
   HIP_TRY(launch_count(bv, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(), s));
   HIP_TRY(launch_layout(bv, pf->n_mem, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(),
-                        plan->off_t.as<int64_t>(), plan->off_e.as<int64_t>(), plan->off_v.as<int64_t>(),
-                        plan->off_top.as<int64_t>(), s));
+                        plan->opts.max_tasks, plan->opts.max_edges, plan->off_t.as<int64_t>(),
+                        plan->off_e.as<int64_t>(), plan->off_v.as<int64_t>(), plan->off_top.as<int64_t>(), s));
 
   // chunk boundaries: the largest chunk must fit the memory budget
-  size_t free_b = 0, total_b = 0;
-  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-  const int64_t budget = (int64_t)(free_b + (size_t)plan->held()) / 2;
+  const bool fixed = plan->opts.max_tasks > 0 && plan->opts.max_edges > 0 && plan->opts.group > 0;
   int32_t chunk = std::min<int32_t>(plan->chunk, n);
   int32_t n_chunks = 0;
   int64_t mT = 0, mE = 0, mV = 0, mP = 0;
-  for (;;) {
+  if (fixed) {
+    // fixed capacities: sizes follow from the plan and the batch shape alone, so
+    // nothing is read back and nothing is allocated once the plan has seen a
+    // batch of this shape and size (the call can be captured in a HIP graph)
+    const int64_t cT = plan->opts.max_tasks, cE = plan->opts.max_edges;
+    const int64_t cV = ((int64_t)tri2(bv.nt) << (2 * bv.dmax)) * pf->n_mem, cP = tet3(bv.nt) + 1;
+    const int64_t per = 88 * cT + 4 * cE + 8 * cV + 4 * cP + 24 + 4 + 16;
+    const auto key = std::make_tuple(n, cV, cP);
+    if (plan->fixed_key != key) {
+      size_t free_b = 0, total_b = 0;
+      HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+      const int64_t budget = (int64_t)(free_b + (size_t)plan->held()) / 2;
+      plan->fixed_chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n, budget / per));
+      plan->fixed_key = key;
+    }
+    chunk = plan->fixed_chunk;
+    n_chunks = (n + chunk - 1) / chunk;
+    mT = cT * chunk;
+    mE = cE * chunk;
+    mV = cV * chunk;
+    mP = cP * chunk;
+  }
+  size_t free_b = 0, total_b = 0;
+  if (!fixed) HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  const int64_t budget = (int64_t)(free_b + (size_t)plan->held()) / 2;
+  for (; !fixed;) {
     n_chunks = (n + chunk - 1) / chunk;
     HIP_TRY(plan->bounds.ensure(4 * 8 * ((int64_t)n_chunks + 1)));
     HIP_TRY(launch_bounds(plan->off_t.as<int64_t>(), plan->off_e.as<int64_t>(), plan->off_v.as<int64_t>(),
@@ -460,6 +486,8 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
     cv.sortbuf = plan->sortbuf.as<int64_t>();
     cv.vf = plan->vf.as<int64_t>();
     cv.nsrc = plan->nsrc.as<int32_t>();
+    cv.cnt_tasks = plan->cnt_tasks.as<int32_t>();
+    cv.cnt_edges = plan->cnt_edges.as<int64_t>();
     return cv;
   };
 

@@ -53,6 +53,8 @@ struct ChunkView {
   int64_t* vf;                              // finest blocks x memory spaces
   int32_t* nsrc;                            // per candidate of the chunk
   const uint32_t* order;                    // nullable: simulation order of the chunk's candidates
+  const int32_t* cnt_tasks;                 // per candidate of the batch: expanded tasks
+  const int64_t* cnt_edges;                 // per candidate of the batch: edges
 };
 
 struct OutView {
@@ -67,7 +69,8 @@ struct OutView {
 
 hipError_t launch_count(const BatchView& b, int32_t* n_tasks, int64_t* n_edges, hipStream_t s);
 hipError_t launch_layout(const BatchView& b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
-                         int64_t* off_t, int64_t* off_e, int64_t* off_v, int64_t* off_top, hipStream_t s);
+                         int64_t cap_t, int64_t cap_e, int64_t* off_t, int64_t* off_e, int64_t* off_v,
+                         int64_t* off_top, hipStream_t s);
 hipError_t launch_bounds(const int64_t* off_t, const int64_t* off_e, const int64_t* off_v, const int64_t* off_top,
                          int32_t n, int32_t chunk, int32_t n_chunks, int64_t* out, hipStream_t s);
 hipError_t launch_prepare(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o,

@@ -38,9 +38,12 @@ using namespace dev;
 // ---------------------------------------------------------------- layout
 
 // off_X[c] = sum over candidates before c; four columns at once (one workgroup)
+// Candidates above a plan's task or edge capacity get no task or edge storage
+// (k_prepare marks them HESP_ECAPACITY), so a chunk never needs more than
+// (candidates x capacity).
 __global__ void __launch_bounds__(1024) k_layout(BatchView b, int32_t n_mem, const int32_t* n_tasks,
-                                                 const int64_t* n_edges, int64_t* off_t, int64_t* off_e,
-                                                 int64_t* off_v, int64_t* off_top) {
+                                                 const int64_t* n_edges, int64_t cap_t, int64_t cap_e,
+                                                 int64_t* off_t, int64_t* off_e, int64_t* off_v, int64_t* off_top) {
   __shared__ int64_t s_part[4][16];
   __shared__ int64_t s_carry[4];
   const int l = lane(), wv = threadIdx.x / kWave;
@@ -53,8 +56,9 @@ __global__ void __launch_bounds__(1024) k_layout(BatchView b, int32_t n_mem, con
       const int nt = b.nt_arr ? b.nt_arr[c] : b.nt;
       const int dmax = b.dmax_arr ? b.dmax_arr[c] : b.dmax;
       const bool ok = nt >= 1 && dmax >= 0 && dmax <= kMaxLevel && (nt << dmax) <= kMaxFine;
-      x[0] = n_tasks[c];
-      x[1] = n_edges[c];
+      const bool fits = (cap_t <= 0 || n_tasks[c] <= cap_t) && (cap_e <= 0 || n_edges[c] <= cap_e);
+      x[0] = fits ? n_tasks[c] : 0;
+      x[1] = fits ? n_edges[c] : 0;
       x[2] = ok ? ((int64_t)tri2(nt) << (2 * dmax)) * n_mem : 0;
       x[3] = ok ? tet3(nt) + 1 : 0;
     }
@@ -150,10 +154,11 @@ __global__ void __launch_bounds__(kWave) k_prepare(SimTables tb, BatchView bv, C
   const int nt = cd.nt, dmax = cd.dmax, M = tb.n_mem;
   int status = kOK;
   if (nt < 1 || dmax < 0 || dmax > kMaxLevel || dmax > tb.max_level || (nt << dmax) > kMaxFine) status = kEINVAL;
+  if (status == kOK && ((cv.cap_tasks > 0 && cv.cnt_tasks[c] > cv.cap_tasks) ||
+                        (cv.cap_edges > 0 && cv.cnt_edges[c] > cv.cap_edges)))
+    status = kECAP;
   const int64_t n_tasks = cv.task_off[c + 1] - cv.task_off[c];
   const int64_t n_edges = cv.edge_off[c + 1] - cv.edge_off[c];
-  if (status == kOK && ((cv.cap_tasks > 0 && n_tasks > cv.cap_tasks) || (cv.cap_edges > 0 && n_edges > cv.cap_edges)))
-    status = kECAP;
   const CandPtrs sp = cand_ptrs(cv, c);
 
   // pass A: first fine task of every top-level task; depths above dmax
@@ -656,8 +661,10 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_layout(const BatchView& b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
-                         int64_t* off_t, int64_t* off_e, int64_t* off_v, int64_t* off_top, hipStream_t s) {
-  hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, b, n_mem, n_tasks, n_edges, off_t, off_e, off_v, off_top);
+                         int64_t cap_t, int64_t cap_e, int64_t* off_t, int64_t* off_e, int64_t* off_v,
+                         int64_t* off_top, hipStream_t s) {
+  hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, b, n_mem, n_tasks, n_edges, cap_t, cap_e, off_t, off_e,
+                     off_v, off_top);
   return hipGetLastError();
 }
 
