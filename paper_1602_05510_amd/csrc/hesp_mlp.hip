@@ -110,65 +110,73 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int kc, const uint16
 }
 
 // ---------------------------------------------------------------- fused forward
-// The whole network for 128 rows per 256-thread workgroup.  Activations stay in
+// The whole network for 128 rows per 512-thread workgroup.  Activations stay in
 // LDS (128 x 256 bf16); weights come from L2 in a transposed bf16 copy
-// (wt[n][k], k contiguous) so that each lane's MFMA B operand is one 16-byte
-// load.  Wave w owns output columns [64w, 64w + 64) of every layer: 8 row
-// blocks x 4 column blocks of 16x16 accumulators.  The last layer's dot with w4
-// is reduced across lanes and waves through LDS.
-constexpr int FM = 128, FLD = kHidden + 8;
+// (wt[n][k], k contiguous) so that each lane's weight operand is one 16-byte
+// load.  Eight 16x16 blocks x two column blocks of accumulators per wave (64
+// registers), so four waves fit on each SIMD; two workgroups share a CU's LDS.
+// The last layer's dot with w4 is reduced across lanes and waves through LDS.
+constexpr int FM = 128, FLD = kHidden + 8, FWAVES = 8;
 
-__device__ __forceinline__ void fwd_epilogue(const f32x4 (&acc)[8][4], const float* __restrict__ bias, int w, int l,
+// Products are formed transposed (A operand = weight rows, B operand =
+// activation rows), so lane l of a 16x16 block holds output row (l % 16) and four
+// consecutive output columns 4 (l / 16) .. + 3: one 8-byte LDS store each.
+// Wave w owns all 128 rows and columns [32 w, 32 w + 32): each weight fragment
+// read from L2 feeds 8 products, each activation fragment read from LDS feeds 2.
+__device__ __forceinline__ void fwd_epilogue(const f32x4 (&acc)[8][2], const float* __restrict__ bias, int w, int l,
                                              uint16_t (*sH)[FLD]) {
-  for (int cb = 0; cb < 4; cb++) {
-    const int col = w * 64 + cb * 16 + (l & 15);
-    const float bv = bias[col];
-    for (int rb = 0; rb < 8; rb++)
-      for (int i = 0; i < 4; i++) {
-        const float v = acc[rb][cb][i] + bv;
-        sH[rb * 16 + (l >> 4) * 4 + i][col] = f2bf(v > 0.f ? v : 0.f);
+  for (int cb = 0; cb < 2; cb++) {
+    const int col = w * 32 + cb * 16 + (l >> 4) * 4;
+    const f32x4 bv = *(const f32x4*)(bias + col);
+    for (int rb = 0; rb < 8; rb++) {
+      uint32_t q[2];
+      for (int h = 0; h < 2; h++) {
+        const float v0 = acc[rb][cb][2 * h] + bv[2 * h], v1 = acc[rb][cb][2 * h + 1] + bv[2 * h + 1];
+        q[h] = (uint32_t)f2bf(v0 > 0.f ? v0 : 0.f) | ((uint32_t)f2bf(v1 > 0.f ? v1 : 0.f) << 16);
       }
+      *(uint2*)&sH[rb * 16 + (l & 15)][col] = make_uint2(q[0], q[1]);
+    }
   }
 }
 
-__global__ void __launch_bounds__(256) k_mlp_fwd(const uint16_t* __restrict__ x, int64_t n,
-                                                 const uint16_t* __restrict__ wt, const float* __restrict__ p,
-                                                 const uint16_t* __restrict__ w4, float* __restrict__ y) {
+__global__ void __launch_bounds__(FWAVES * 64, 4) k_mlp_fwd(const uint16_t* __restrict__ x, int64_t n,
+                                                            const uint16_t* __restrict__ wt,
+                                                            const float* __restrict__ p,
+                                                            const uint16_t* __restrict__ w4, float* __restrict__ y) {
   __shared__ __attribute__((aligned(16))) uint16_t sH[FM][FLD];
-  __shared__ float sY[4][FM];
+  __shared__ float sY[FWAVES][FM];
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * FM;
-  f32x4 acc[8][4];
-  // layer 1 (K = 32): A straight from the input rows
+  f32x4 acc[8][2];
+  // layer 1 (K = 32): activation operand straight from the input rows
   for (int rb = 0; rb < 8; rb++)
-    for (int cb = 0; cb < 4; cb++) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int cb = 0; cb < 2; cb++) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
   {
-    bf16x8 b[4];
-    for (int cb = 0; cb < 4; cb++)
-      b[cb] = *(const bf16x8*)(wt + kOffT1 + (int64_t)(w * 64 + cb * 16 + (l & 15)) * kInDim + (l >> 4) * 8);
+    bf16x8 wf[2];
+    for (int cb = 0; cb < 2; cb++)
+      wf[cb] = *(const bf16x8*)(wt + kOffT1 + (int64_t)(w * 32 + cb * 16 + (l & 15)) * kInDim + (l >> 4) * 8);
     for (int rb = 0; rb < 8; rb++) {
       const int64_t row = r0 + rb * 16 + (l & 15);
       u32x4 av = {0u, 0u, 0u, 0u};
       if (row < n) av = *(const u32x4*)(x + row * kInDim + (l >> 4) * 8);
       const bf16x8 a = __builtin_bit_cast(bf16x8, av);
-      for (int cb = 0; cb < 4; cb++) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[cb], acc[rb][cb], 0, 0, 0);
+      for (int cb = 0; cb < 2; cb++) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[cb], a, acc[rb][cb], 0, 0, 0);
     }
   }
   fwd_epilogue(acc, p + kOffB1, w, l, sH);
   __syncthreads();
-  // layers 2 and 3 (K = 256): A from LDS
+  // layers 2 and 3 (K = 256): activations from LDS, weights from L2
   for (int layer = 0; layer < 2; layer++) {
-    const uint16_t* wl = wt + (layer == 0 ? kOffT2 : kOffT3);
+    const uint16_t* wl = wt + (layer == 0 ? kOffT2 : kOffT3) + (int64_t)(w * 32 + (l & 15)) * kHidden + (l >> 4) * 8;
     for (int rb = 0; rb < 8; rb++)
-      for (int cb = 0; cb < 4; cb++) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int cb = 0; cb < 2; cb++) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < kHidden; k0 += 32) {
-      bf16x8 b[4];
-      for (int cb = 0; cb < 4; cb++)
-        b[cb] = *(const bf16x8*)(wl + (int64_t)(w * 64 + cb * 16 + (l & 15)) * kHidden + k0 + (l >> 4) * 8);
+      bf16x8 wf[2];
+      for (int cb = 0; cb < 2; cb++) wf[cb] = *(const bf16x8*)(wl + (int64_t)cb * 16 * kHidden + k0);
       for (int rb = 0; rb < 8; rb++) {
         const bf16x8 a = *(const bf16x8*)&sH[rb * 16 + (l & 15)][k0 + (l >> 4) * 8];
-        for (int cb = 0; cb < 4; cb++)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[cb], acc[rb][cb], 0, 0, 0);
+        for (int cb = 0; cb < 2; cb++)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[cb], a, acc[rb][cb], 0, 0, 0);
       }
     }
     __syncthreads();   // every wave has read this layer's input
@@ -178,29 +186,30 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const uint16_t* __restrict__ x,
     }
   }
   // output: y = bf16(relu(z3 + b3)) . w4 + b4
-  float part[8][4];
-  for (int rb = 0; rb < 8; rb++)
-    for (int i = 0; i < 4; i++) part[rb][i] = 0.f;
-  for (int cb = 0; cb < 4; cb++) {
-    const int col = w * 64 + cb * 16 + (l & 15);
-    const float bv = p[kOffB3 + col];
-    const float wv = bf2f(w4[col]);
+  float part[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int cb = 0; cb < 2; cb++) {
+    const int col = w * 32 + cb * 16 + (l >> 4) * 4;
+    const f32x4 bv = *(const f32x4*)(p + kOffB3 + col);
+    float wv[4];
+    for (int i = 0; i < 4; i++) wv[i] = bf2f(w4[col + i]);
     for (int rb = 0; rb < 8; rb++)
       for (int i = 0; i < 4; i++) {
-        const float v = acc[rb][cb][i] + bv;
-        part[rb][i] += bf2f(f2bf(v > 0.f ? v : 0.f)) * wv;
+        const float v = acc[rb][cb][i] + bv[i];
+        part[rb] += bf2f(f2bf(v > 0.f ? v : 0.f)) * wv[i];
       }
   }
-  for (int rb = 0; rb < 8; rb++)
-    for (int i = 0; i < 4; i++) {
-      float v = part[rb][i];
-      for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
-      if ((l & 15) == 0) sY[w][rb * 16 + (l >> 4) * 4 + i] = v;
-    }
+  for (int rb = 0; rb < 8; rb++) {
+    float v = part[rb];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (l < 16) sY[w][rb * 16 + l] = v;
+  }
   __syncthreads();
   if (t < FM) {
     const int64_t row = r0 + t;
-    if (row < n) y[row] = ((sY[0][t] + sY[1][t]) + (sY[2][t] + sY[3][t])) + p[kOffB4];
+    float s = 0.f;
+    for (int q = 0; q < FWAVES; q++) s += sY[q][t];
+    if (row < n) y[row] = s + p[kOffB4];
   }
 }
 
@@ -449,7 +458,7 @@ hipError_t gemm(bool ta, bool tb, int M, int N, int K, int splits, const uint16_
 hipError_t mlp_forward(const uint16_t* x, int64_t n, const uint16_t* wt, const float* p, const uint16_t* w4, float* y,
                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((n + FM - 1) / FM)), dim3(256), 0, s, x, n, wt, p, w4, y);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((n + FM - 1) / FM)), dim3(FWAVES * 64), 0, s, x, n, wt, p, w4, y);
   return hipGetLastError();
 }
 
