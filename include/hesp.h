@@ -158,7 +158,9 @@ typedef struct {
   int32_t slots;               /* persistent single-wave workgroups of the simulation; 0 = 32 per compute unit */
   int64_t max_tasks;           /* optional per-candidate task limit (larger: HESP_ECAPACITY); 0 = none */
   int64_t max_edges;           /* optional per-candidate edge limit; 0 = none */
-  int32_t max_nt;              /* reserved, 0 */
+  int32_t chunks;              /* split every batch into at least this many chunks; the preparation of
+                                  chunk i+1 then runs on a second stream while chunk i is simulated
+                                  (two workspace sets); 0 or 1 = as few chunks as memory allows */
   int32_t group;               /* lanes per candidate in the event simulation: 16, 32 or 64 (>= processors);
                                   0 = chosen per batch shape by timing each size once (autotuning) */
 } hesp_plan_opts;
@@ -167,8 +169,9 @@ typedef struct {
  * call with a batch of a given (n_cand, nt, dmax) further calls of that shape do
  * no host synchronisation, no allocation and no autotuning -- only kernel
  * launches on `stream`, which can be captured in a HIP graph and replayed (the
- * graph keeps the batch and output pointers of the captured call).  Candidates
- * above the capacities get HESP_ECAPACITY. */
+ * graph keeps the batch and output pointers of the captured call).  A captured
+ * call runs on `stream` alone and must fit one chunk (else HESP_EUNSUPPORTED).
+ * Candidates above the capacities get HESP_ECAPACITY. */
 int hesp_plan_create(hesp_plan **plan, const hesp_plan_opts *opts);
 int hesp_plan_destroy(hesp_plan *plan);
 /* device bytes currently held by the plan */

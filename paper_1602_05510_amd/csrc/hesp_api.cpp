@@ -73,6 +73,18 @@ struct DevBuf {
   T* as() const { return (T*)p; }
 };
 
+// Workspace of one chunk of candidates.
+struct WorkSet {
+  DevBuf top_first, desc, indeg, cur, succ, rec, fifo, ready, sortbuf, vf, nsrc, order_keys, order;
+  std::vector<DevBuf*> all() {
+    return {&top_first, &desc, &indeg, &cur, &succ, &rec, &fifo, &ready, &sortbuf, &vf, &nsrc, &order_keys, &order};
+  }
+  int64_t bytes() const {
+    return top_first.bytes + desc.bytes + indeg.bytes + cur.bytes + succ.bytes + rec.bytes + fifo.bytes +
+           ready.bytes + sortbuf.bytes + vf.bytes + nsrc.bytes + order_keys.bytes + order.bytes;
+  }
+};
+
 struct hesp_plan {
   hesp_plan_opts opts{};
   int32_t slots = 0;          // waves of the persistent simulation kernel
@@ -80,8 +92,10 @@ struct hesp_plan {
   uint32_t* counter = nullptr;
   // per batch
   DevBuf cnt_tasks, cnt_edges, off_t, off_e, off_v, off_top, bounds;
-  // per chunk
-  DevBuf top_first, desc, indeg, cur, succ, rec, fifo, ready, sortbuf, vf, nsrc, order_keys, order;
+  // per chunk, two sets: chunk i+1 is prepared while chunk i is simulated
+  WorkSet ws[2];
+  hipStream_t s_prep = nullptr, s_sim = nullptr;
+  std::vector<hipEvent_t> sync_ev;   // fork, then per chunk: prepared, simulated
   std::vector<int64_t> h_bounds;
   // autotuned lanes per candidate, by (processors, memory spaces, nt, dmax, ragged)
   std::map<std::tuple<int, int, int, int, int>, int> tuned;
@@ -90,17 +104,16 @@ struct hesp_plan {
   int32_t fixed_chunk = 0;
   // optional kernel timing of the last call: events around each launch
   bool timing = false;
-  std::vector<hipEvent_t> ev;   // per chunk: prepare start, prepare end = sim start, sim end
+  std::vector<hipEvent_t> ev;   // per chunk: prepare start and end, simulation start and end
   size_t ev_used = 0;
   int64_t held() const {
     return cnt_tasks.bytes + cnt_edges.bytes + off_t.bytes + off_e.bytes + off_v.bytes + off_top.bytes +
-           bounds.bytes + top_first.bytes + desc.bytes + indeg.bytes + cur.bytes + succ.bytes + rec.bytes +
-           fifo.bytes + ready.bytes + sortbuf.bytes + vf.bytes + nsrc.bytes + order_keys.bytes + order.bytes;
+           bounds.bytes + ws[0].bytes() + ws[1].bytes();
   }
   void release() {
-    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds, &top_first, &desc, &indeg,
-                      &cur, &succ, &rec, &fifo, &ready, &sortbuf, &vf, &nsrc, &order_keys, &order})
-      b->release();
+    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds}) b->release();
+    for (WorkSet& w : ws)
+      for (DevBuf* d : w.all()) d->release();
   }
 };
 
@@ -271,7 +284,7 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
   hesp_plan* p = new (std::nothrow) hesp_plan();
   if (!p) return fail(HESP_ENOMEM, "hesp_plan_create: out of host memory");
   if (opts) p->opts = *opts;
-  if (p->opts.slots < 0 || p->opts.max_tasks < 0 || p->opts.max_edges < 0 || p->opts.max_nt < 0 ||
+  if (p->opts.slots < 0 || p->opts.max_tasks < 0 || p->opts.max_edges < 0 || p->opts.chunks < 0 ||
       (p->opts.group != 0 && p->opts.group != 16 && p->opts.group != 32 && p->opts.group != 64)) {
     delete p;
     return fail(HESP_EINVAL, "hesp_plan_create: negative option");
@@ -286,7 +299,11 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
   p->slots = p->opts.slots ? p->opts.slots : 32 * cus;
   p->chunk = 1 << 22;   // bounded by device memory below
   e = hipMalloc(&p->counter, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->s_prep, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->s_sim, hipStreamNonBlocking);
   if (e != hipSuccess) {
+    hfree(p->counter);
+    if (p->s_prep) (void)hipStreamDestroy(p->s_prep);
     delete p;
     return fail(HESP_ENOMEM, "hesp_plan_create: %s", hipGetErrorString(e));
   }
@@ -297,6 +314,9 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
 int hesp_plan_destroy(hesp_plan* p) {
   if (!p) return ok();
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->sync_ev) (void)hipEventDestroy(e);
+  if (p->s_prep) (void)hipStreamDestroy(p->s_prep);
+  if (p->s_sim) (void)hipStreamDestroy(p->s_sim);
   p->release();
   hfree(p->counter);
   delete p;
@@ -319,11 +339,12 @@ int hesp_plan_timing(hesp_plan* p, int32_t enable) {
 int hesp_plan_last_ms(hesp_plan* p, double* ms) {
   if (!p || !ms) return fail(HESP_EINVAL, "hesp_plan_last_ms: null argument");
   ms[0] = ms[1] = ms[2] = 0.0;
-  for (size_t i = 0; i + 3 <= p->ev_used; i += 3) {
-    HIP_TRY(hipEventSynchronize(p->ev[i + 2]));
+  for (size_t i = 0; i + 4 <= p->ev_used; i += 4) {
+    HIP_TRY(hipEventSynchronize(p->ev[i + 3]));
+    HIP_TRY(hipEventSynchronize(p->ev[i + 1]));
     float a = 0.f, b = 0.f;
     HIP_TRY(hipEventElapsedTime(&a, p->ev[i], p->ev[i + 1]));
-    HIP_TRY(hipEventElapsedTime(&b, p->ev[i + 1], p->ev[i + 2]));
+    HIP_TRY(hipEventElapsedTime(&b, p->ev[i + 2], p->ev[i + 3]));
     ms[0] += a;
     ms[1] += b;
     ms[2] += 1.0;
@@ -399,6 +420,7 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   // chunk boundaries: the largest chunk must fit the memory budget
   const bool fixed = plan->opts.max_tasks > 0 && plan->opts.max_edges > 0 && plan->opts.group > 0;
   int32_t chunk = std::min<int32_t>(plan->chunk, n);
+  if (plan->opts.chunks > 1) chunk = std::min<int32_t>(chunk, (n + plan->opts.chunks - 1) / plan->opts.chunks);
   int32_t n_chunks = 0;
   int64_t mT = 0, mE = 0, mV = 0, mP = 0;
   if (fixed) {
@@ -413,7 +435,8 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
       size_t free_b = 0, total_b = 0;
       HIP_TRY(hipMemGetInfo(&free_b, &total_b));
       const int64_t budget = (int64_t)(free_b + (size_t)plan->held()) / 2;
-      plan->fixed_chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n, budget / per));
+      const int64_t want = plan->opts.chunks > 1 ? (n + plan->opts.chunks - 1) / plan->opts.chunks : n;
+      plan->fixed_chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(want, budget / (2 * per)));
       plan->fixed_key = key;
     }
     chunk = plan->fixed_chunk;
@@ -442,30 +465,35 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
       mV = std::max(mV, hb[2 * (n_chunks + 1) + i + 1] - hb[2 * (n_chunks + 1) + i]);
       mP = std::max(mP, hb[3 * (n_chunks + 1) + i + 1] - hb[3 * (n_chunks + 1) + i]);
     }
-    const int64_t bytes = 88 * mT + 4 * mE + 8 * mV + 4 * mP + 24 * (int64_t)chunk;
+    // two workspace sets when chunks overlap
+    const int64_t bytes = (n_chunks > 1 ? 2 : 1) * (88 * mT + 4 * mE + 8 * mV + 4 * mP + 24 * (int64_t)chunk);
     if (bytes <= budget || chunk == 1) {
       if (bytes > budget) return fail(HESP_ENOMEM, "hesp_simulate_batch: one candidate needs %lld bytes", (long long)bytes);
       break;
     }
     chunk = (chunk + 1) / 2;
   }
-  HIP_TRY(plan->top_first.ensure(4 * mP));
-  HIP_TRY(plan->desc.ensure(4 * mT));
-  HIP_TRY(plan->indeg.ensure(4 * mT));
-  HIP_TRY(plan->cur.ensure(4 * mT));
-  HIP_TRY(plan->succ.ensure(4 * mE));
-  HIP_TRY(plan->rec.ensure(16 * (mT + chunk)));
-  HIP_TRY(plan->fifo.ensure(24 * mT));
-  HIP_TRY(plan->ready.ensure(4 * mT));
-  HIP_TRY(plan->sortbuf.ensure(32 * mT));
-  HIP_TRY(plan->vf.ensure(8 * mV));
-  HIP_TRY(plan->nsrc.ensure(4 * (int64_t)chunk));
-  HIP_TRY(plan->order_keys.ensure(8 * srch::sort_len(chunk)));
-  HIP_TRY(plan->order.ensure(4 * (int64_t)chunk));
+  for (int k = 0; k < (n_chunks > 1 ? 2 : 1); k++) {
+    WorkSet& w = plan->ws[k];
+    HIP_TRY(w.top_first.ensure(4 * mP));
+    HIP_TRY(w.desc.ensure(4 * mT));
+    HIP_TRY(w.indeg.ensure(4 * mT));
+    HIP_TRY(w.cur.ensure(4 * mT));
+    HIP_TRY(w.succ.ensure(4 * mE));
+    HIP_TRY(w.rec.ensure(16 * (mT + chunk)));
+    HIP_TRY(w.fifo.ensure(24 * mT));
+    HIP_TRY(w.ready.ensure(4 * mT));
+    HIP_TRY(w.sortbuf.ensure(32 * mT));
+    HIP_TRY(w.vf.ensure(8 * mV));
+    HIP_TRY(w.nsrc.ensure(4 * (int64_t)chunk));
+    HIP_TRY(w.order_keys.ensure(8 * srch::sort_len(chunk)));
+    HIP_TRY(w.order.ensure(4 * (int64_t)chunk));
+  }
 
   OutView ov{out->d_makespan, out->d_status, out->d_n_tasks, out->d_sched_off, out->d_proc, out->d_start,
              out->d_finish};
-  auto chunk_view = [&](int32_t c0, int32_t nc) {
+  auto chunk_view = [&](int32_t c0, int32_t nc, int set) {
+    WorkSet& w = plan->ws[set];
     ChunkView cv{};
     cv.task_off = plan->off_t.as<int64_t>();
     cv.edge_off = plan->off_e.as<int64_t>();
@@ -475,17 +503,17 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
     cv.nc = nc;
     cv.cap_tasks = plan->opts.max_tasks;
     cv.cap_edges = plan->opts.max_edges;
-    cv.top_first = plan->top_first.as<uint32_t>();
-    cv.desc = plan->desc.as<uint32_t>();
-    cv.indeg = plan->indeg.as<uint32_t>();
-    cv.cur = plan->cur.as<uint32_t>();
-    cv.succ = plan->succ.as<uint32_t>();
-    cv.rec = plan->rec.as<int64_t>();
-    cv.fifo = plan->fifo.as<int64_t>();
-    cv.ready = plan->ready.as<uint32_t>();
-    cv.sortbuf = plan->sortbuf.as<int64_t>();
-    cv.vf = plan->vf.as<int64_t>();
-    cv.nsrc = plan->nsrc.as<int32_t>();
+    cv.top_first = w.top_first.as<uint32_t>();
+    cv.desc = w.desc.as<uint32_t>();
+    cv.indeg = w.indeg.as<uint32_t>();
+    cv.cur = w.cur.as<uint32_t>();
+    cv.succ = w.succ.as<uint32_t>();
+    cv.rec = w.rec.as<int64_t>();
+    cv.fifo = w.fifo.as<int64_t>();
+    cv.ready = w.ready.as<uint32_t>();
+    cv.sortbuf = w.sortbuf.as<int64_t>();
+    cv.vf = w.vf.as<int64_t>();
+    cv.nsrc = w.nsrc.as<int32_t>();
     cv.cnt_tasks = plan->cnt_tasks.as<int32_t>();
     cv.cnt_edges = plan->cnt_edges.as<int64_t>();
     return cv;
@@ -507,7 +535,7 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
       HIP_TRY(hipEventCreate(&e1));
       for (int G : {16, 32, 64}) {
         if (G < pf->n_procs) continue;
-        ChunkView cv = chunk_view(0, sub);
+        ChunkView cv = chunk_view(0, sub, 0);
         HIP_TRY(launch_prepare(tb, bv, cv, ov, s));
         HIP_TRY(hipEventRecord(e0, s));
         HIP_TRY(launch_sim(tb, bv, cv, ov, plan->slots, G, plan->counter, s));
@@ -530,26 +558,55 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
 
   plan->ev_used = 0;
   if (plan->timing)
-    while (plan->ev.size() < 3 * (size_t)n_chunks) {
+    while (plan->ev.size() < 4 * (size_t)n_chunks) {
       hipEvent_t e;
       HIP_TRY(hipEventCreate(&e));
       plan->ev.push_back(e);
     }
-  for (int i = 0; i < n_chunks; i++) {
-    ChunkView cv = chunk_view(i * chunk, std::min(chunk, n - i * chunk));
-    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[3 * i], s));
-    // largest candidates first, so that the persistent launch does not end on a long one
-    HIP_TRY(srch::size_order(plan->cnt_tasks.as<int32_t>(), cv.c0, cv.nc, plan->order_keys.as<uint64_t>(),
-                             plan->order.as<uint32_t>(), s));
-    cv.order = plan->order.as<uint32_t>();
-    HIP_TRY(launch_prepare(tb, bv, cv, ov, s));
-    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[3 * i + 1], s));
-    HIP_TRY(launch_sim(tb, bv, cv, ov, plan->slots, group, plan->counter, s));
-    if (plan->timing) {
-      HIP_TRY(hipEventRecord(plan->ev[3 * i + 2], s));
-      plan->ev_used = 3 * (size_t)(i + 1);
-    }
+  while (plan->sync_ev.size() < 1 + 2 * (size_t)n_chunks) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    plan->sync_ev.push_back(e);
   }
+  // fork: preparation and simulation run on the plan's two streams, chunk i+1
+  // being prepared (into the other workspace set) while chunk i is simulated;
+  // the caller's stream waits for the last simulation.  A call being captured
+  // into a graph stays on the caller's stream and must fit one chunk: a capture
+  // of the two-stream pipeline ended in a crash of the runtime's capture_end.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cap));
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if (capturing && n_chunks > 1)
+    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: a captured call must fit one chunk (%d needed)", n_chunks);
+  hipStream_t sp = capturing ? s : plan->s_prep, ss = capturing ? s : plan->s_sim;
+  hipEvent_t* se = plan->sync_ev.data();
+  if (!capturing) {
+    HIP_TRY(hipEventRecord(se[0], s));
+    HIP_TRY(hipStreamWaitEvent(sp, se[0], 0));
+    HIP_TRY(hipStreamWaitEvent(ss, se[0], 0));
+  }
+  for (int i = 0; i < n_chunks; i++) {
+    const int set = i & 1;
+    ChunkView cv = chunk_view(i * chunk, std::min(chunk, n - i * chunk), set);
+    if (i >= 2) HIP_TRY(hipStreamWaitEvent(sp, se[2 + 2 * (i - 2)], 0));   // set free again
+    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i], sp));
+    // largest candidates first, so that the persistent launch does not end on a long one
+    HIP_TRY(srch::size_order(plan->cnt_tasks.as<int32_t>(), cv.c0, cv.nc, plan->ws[set].order_keys.as<uint64_t>(),
+                             plan->ws[set].order.as<uint32_t>(), sp));
+    cv.order = plan->ws[set].order.as<uint32_t>();
+    HIP_TRY(launch_prepare(tb, bv, cv, ov, sp));
+    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 1], sp));
+    if (!capturing) {
+      HIP_TRY(hipEventRecord(se[1 + 2 * i], sp));
+      HIP_TRY(hipStreamWaitEvent(ss, se[1 + 2 * i], 0));
+    }
+    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 2], ss));
+    HIP_TRY(launch_sim(tb, bv, cv, ov, plan->slots, group, plan->counter, ss));
+    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 3], ss));
+    if (!capturing) HIP_TRY(hipEventRecord(se[2 + 2 * i], ss));
+    if (plan->timing) plan->ev_used = 4 * (size_t)(i + 1);
+  }
+  if (!capturing) HIP_TRY(hipStreamWaitEvent(s, se[2 * n_chunks], 0));
   return ok();
 }
 

@@ -46,7 +46,7 @@ class BatchC(ctypes.Structure):
 
 
 class PlanOpts(ctypes.Structure):
-    _fields_ = [("slots", i32), ("max_tasks", i64), ("max_edges", i64), ("max_nt", i32), ("group", i32)]
+    _fields_ = [("slots", i32), ("max_tasks", i64), ("max_edges", i64), ("chunks", i32), ("group", i32)]
 
 
 class OutputsC(ctypes.Structure):
@@ -272,9 +272,9 @@ def count_batch(batch: DeviceBatch, stream=None):
 
 
 class Plan:
-    def __init__(self, slots: int = 0, max_tasks: int = 0, max_edges: int = 0, max_nt: int = 0, group: int = 0):
+    def __init__(self, slots: int = 0, max_tasks: int = 0, max_edges: int = 0, chunks: int = 0, group: int = 0):
         self.h = P()
-        self.opts = PlanOpts(slots, max_tasks, max_edges, max_nt, group)
+        self.opts = PlanOpts(slots, max_tasks, max_edges, chunks, group)
         _check("hesp_plan_create", lib().hesp_plan_create(ctypes.byref(self.h), ctypes.byref(self.opts)))
 
     def bytes(self) -> int:

@@ -23,7 +23,13 @@ def H(torch):
     return hesp
 
 
-def test_graph_replay_matches_eager(H, torch):
+@pytest.mark.parametrize("chunks", [
+    1,
+    pytest.param(3, marks=pytest.mark.skip(
+        reason="the capture of a three-chunk call (then forked over two streams) crashed in the runtime's "
+               "capture_end; captured calls are now refused unless they fit one chunk")),
+])
+def test_graph_replay_matches_eager(H, torch, chunks):
     w = I.WORKLOADS["chol16x16_b1024_d2"]
     pf_in = w.platform()
     pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
@@ -39,7 +45,7 @@ def test_graph_replay_matches_eager(H, torch):
     db = H.DeviceBatch(n, w.nt, w.dmax, dep)
     ms = torch.empty(n, dtype=torch.int64, device="cuda")
     st = torch.empty(n, dtype=torch.int32, device="cuda")
-    plan = H.Plan(max_tasks=cap_t, max_edges=cap_e, group=16)
+    plan = H.Plan(max_tasks=cap_t, max_edges=cap_e, group=16, chunks=chunks)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -81,3 +87,21 @@ def test_fixed_plan_capacity_status(H, torch):
     over = nt_ > cap
     assert bool((st[over] == H.HESP_ECAPACITY).all().item()) and bool((ms[over] == -1).all().item())
     assert bool((st[~over] == 0).all().item()) and torch.equal(ms[~over], ref[~over])
+
+
+def test_chunk_pipeline_matches_single_chunk(H, torch):
+    """Chunks prepared on one stream while the previous chunk is simulated on
+    another (two workspace sets) give the results of a single chunk."""
+    w = I.WORKLOADS["ragged_bl_b512_d3"]
+    pf = H.Platform.from_inputs(w.platform(), w.b, w.dmax)
+    r = w.ragged
+    db = H.generate_ragged(w.seed, 0, 3000, r["nt_lo"], r["nt_hi"], r["dmax_hi"], I.split_threshold(3, 10))
+    out = []
+    for chunks in (1, 2, 5):
+        ms = torch.empty(3000, dtype=torch.int64, device="cuda")
+        st = torch.empty(3000, dtype=torch.int32, device="cuda")
+        H.simulate_batch(H.Plan(chunks=chunks), pf, db, ms, st)
+        torch.cuda.synchronize()
+        assert bool((st == 0).all().item())
+        out.append(ms)
+    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
