@@ -23,9 +23,12 @@
  *   4. critical times (section 2.1, "Priority-List"): sum of the task's time
  *      over all processors (an order-preserving multiple of the average),
  *      propagated backwards over the DAG;
- *   5. event simulation, PL order + EFT-P selection with write-back caching of
- *      host data in accelerator spaces and transfers issued when a task is
- *      scheduled (section 2.1, "Task and data scheduling heuristics").
+ *   5. event simulation with write-back caching of host data in accelerator
+ *      spaces and transfers issued when a task is scheduled (section 2.1,
+ *      "Task and data scheduling heuristics"); task order Priority-List
+ *      (decreasing critical time) or FCFS (order of release), processor
+ *      selection EFT-P (earliest finish counting transfers) or EIT-P (the
+ *      processor that becomes idle first).
  * Where the paper is silent (tie-breaks, simultaneous events, transfer issue
  * time, coherence granularity) the readings are those listed in the design
  * notes of this repository; each is marked "reading:" below.
@@ -88,6 +91,8 @@ typedef struct {
     int64_t b;               /* tile side at level 0 */
     int64_t latency_ns, bw, elem_bytes;
     int shared;              /* single memory space, transfers cost 0 */
+    int order;               /* policy: 0 = Priority-List, 1 = FCFS */
+    int select;              /* policy: 0 = EFT-P, 1 = EIT-P */
 } or_platform;
 
 /* ------------------------------------------------------------------------ */
@@ -309,7 +314,9 @@ static int make_tables(const or_platform *pf, int dmax, or_tables *tb)
 
 static void free_tables(or_tables *tb) { free(tb->cost); free(tb->xfer); }
 
-/* ready-set order: larger critical time first, then smaller scaled (K,I,J) */
+/* ready-set order: larger `rank` first, then smaller scaled (K,I,J).  For the
+ * Priority-List order `rank` is the critical time; for FCFS it is minus the
+ * release time (earlier releases first). */
 typedef struct { int64_t rank; int64_t k0, k1, k2; int task; } or_hent;
 
 static int hent_before(const or_hent *a, const or_hent *b)
@@ -426,8 +433,8 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
     for (int t = 0; t < n; t++)
         if (left[t] == 0) {
             int sh = dmax - tl.v[t].level;
-            heap_push(&heap, (or_hent){rank[t], (int64_t)tl.v[t].K << sh, (int64_t)tl.v[t].I << sh,
-                                       (int64_t)tl.v[t].J << sh, t});
+            heap_push(&heap, (or_hent){pf->order ? 0 : rank[t], (int64_t)tl.v[t].K << sh,
+                                       (int64_t)tl.v[t].I << sh, (int64_t)tl.v[t].J << sh, t});
         }
     int64_t T = 0, makespan = 0;
     int done_count = 0;
@@ -439,7 +446,7 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             int nb = task_blocks(&tl.v[t], br, bc, bw);
             int sh = dmax - tl.v[t].level, w = 1 << sh;
             int best_p = -1;
-            int64_t best_eft = 0, best_est = 0;
+            int64_t best_eft = 0, best_est = 0, best_sel = 0;
             for (int p = 0; p < P; p++) {
                 int m = pf->proc_mem[p];
                 int64_t est = T > avail[p] ? T : avail[p];
@@ -456,7 +463,11 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                     if (ready > est) est = ready;
                 }
                 int64_t eft = est + tb.cost[(pf->proc_type[p] * 4 + tl.v[t].type) * L + tl.v[t].level];
-                if (best_p < 0 || eft < best_eft) { best_p = p; best_eft = eft; best_est = est; }
+                /* EFT-P: earliest finish; EIT-P: earliest time the processor is idle
+                 * (reading: an idle processor counts as idle from now, so idle
+                 * processors tie); ties to the lowest index */
+                int64_t sel = pf->select ? (T > avail[p] ? T : avail[p]) : eft;
+                if (best_p < 0 || sel < best_sel) { best_p = p; best_sel = sel; best_eft = eft; best_est = est; }
             }
             /* commit: transfers of the missing atoms are issued now, at time T */
             int m = pf->proc_mem[best_p];
@@ -505,7 +516,7 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                 int v = g.succ[e];
                 if (--left[v] == 0) {
                     int s2 = dmax - tl.v[v].level;
-                    heap_push(&heap, (or_hent){rank[v], (int64_t)tl.v[v].K << s2,
+                    heap_push(&heap, (or_hent){pf->order ? -Tn : rank[v], (int64_t)tl.v[v].K << s2,
                                                (int64_t)tl.v[v].I << s2, (int64_t)tl.v[v].J << s2, v});
                 }
             }
@@ -557,14 +568,15 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
                     int64_t *makespan, int32_t *n_tasks, int64_t *n_edges,
                     int32_t max_tasks, int32_t *task_info, int32_t *proc_out,
                     int64_t *start_out, int64_t *finish_out, int64_t *rank_out,
-                    int64_t max_edges, int32_t *edges_out)
+                    int64_t max_edges, int32_t *edges_out, int order, int select)
 {
     if (!depth || n_procs < 1 || !proc_type || !proc_mem || n_mem < 1 || !rmax || !h) return OR_EINVAL;
+    if (order < 0 || order > 1 || select < 0 || select > 1) return OR_EINVAL;
     for (int p = 0; p < n_procs; p++)
         if (proc_type[p] < 0 || proc_type[p] >= n_ptypes || proc_mem[p] < 0 || proc_mem[p] >= n_mem)
             return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared};
+                      latency_ns, bw, elem_bytes, shared, order, select};
     or_outputs o = {max_tasks, task_info, proc_out, start_out, finish_out, rank_out, max_edges, edges_out};
     or_result r;
     int rc = simulate_one(&pf, nt, dmax, depth, &r, &o);
@@ -611,11 +623,13 @@ int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
                           int n_procs, const int32_t *proc_type, const int32_t *proc_mem, int n_mem,
                           int n_ptypes, const int64_t *rmax, const int64_t *h, int64_t b,
                           int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
-                          int n_threads, int64_t *makespan, int32_t *n_tasks, int32_t *status)
+                          int n_threads, int64_t *makespan, int32_t *n_tasks, int32_t *status,
+                          int order, int select)
 {
     if (n_cand < 0 || !nt || !dmax || !mask_off || !depth || !makespan || n_threads < 1) return OR_EINVAL;
+    if (order < 0 || order > 1 || select < 0 || select > 1) return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared};
+                      latency_ns, bw, elem_bytes, shared, order, select};
     or_batch_job j;
     j.pf = &pf; j.n_cand = n_cand; j.nt = nt; j.dmax = dmax; j.mask_off = mask_off; j.depth = depth;
     j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.next = 0;

@@ -177,7 +177,10 @@ class Sim:
             e = max(e, r)
         return e
 
-    def run(self, choose_task=None, choose_proc=None):
+    def run(self, choose_task=None, choose_proc=None, order="PL", select="EFT"):
+        """order: "PL" (decreasing critical time) or "FCFS" (first released first);
+        select: "EFT" (earliest finish) or "EIT" (processor idle first).  Ties:
+        smaller scaled (K, I, J), then lower processor index."""
         N = 0
         vf = {}
         for t in self.tasks:
@@ -187,16 +190,27 @@ class Sim:
         avail = [0] * self.P
         left = list(self.npred)
         ready = [t for t in range(self.n) if left[t] == 0]
+        released = {t: 0 for t in ready}
         fifo = [[] for _ in range(self.P)]
         proc, start, finish = [None] * self.n, [None] * self.n, [None] * self.n
         T = 0
         while True:
             while ready:
-                t = choose_task(ready, self) if choose_task else min(ready, key=self.key)
+                if choose_task:
+                    t = choose_task(ready, self)
+                elif order == "FCFS":
+                    t = min(ready, key=lambda u: (released[u],) + self.key(u)[1:])
+                else:
+                    t = min(ready, key=self.key)
                 ready.remove(t)
                 ests = [self.est(t, p, T, avail, vf) for p in range(self.P)]
                 efts = [ests[p] + self.cost[t][p] for p in range(self.P)]
-                p = choose_proc(t, efts, self) if choose_proc else min(range(self.P), key=lambda q: (efts[q], q))
+                if choose_proc:
+                    p = choose_proc(t, efts, self)
+                elif select == "EIT":
+                    p = min(range(self.P), key=lambda q: (max(T, avail[q]), q))
+                else:
+                    p = min(range(self.P), key=lambda q: (efts[q], q))
                 m = self.proc_mem[p]
                 for (R, C, _) in blocks(self.tasks[t]):
                     at = atoms(R, C, self.tasks[t][1], self.dmax)
@@ -222,6 +236,7 @@ class Sim:
                         left[v] -= 1
                         if left[v] == 0:
                             ready.append(v)
+                            released[v] = Tn
             T = Tn
         return max(finish), proc, start, finish
 

@@ -21,7 +21,13 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden")
 KIND = {"chol": 0, "trsm": 1, "syrk": 2, "gemm": 3}
 
 MUTANTS = {
-    "eft_ties_to_highest": ("if (best_p < 0 || eft < best_eft)", "if (best_p < 0 || eft <= best_eft)"),
+    "eft_ties_to_highest": ("if (best_p < 0 || sel < best_sel)", "if (best_p < 0 || sel <= best_sel)"),
+    "eit_ignores_now": ("int64_t sel = pf->select ? (T > avail[p] ? T : avail[p]) : eft;",
+                        "int64_t sel = pf->select ? avail[p] : eft;"),
+    "eit_uses_finish": ("int64_t sel = pf->select ? (T > avail[p] ? T : avail[p]) : eft;",
+                        "int64_t sel = eft;"),
+    "fcfs_keeps_priority": ("heap_push(&heap, (or_hent){pf->order ? -Tn : rank[v],",
+                            "heap_push(&heap, (or_hent){rank[v],"),
     "priority_reversed": ("if (a->rank != b->rank) return a->rank > b->rank;",
                           "if (a->rank != b->rank) return a->rank < b->rank;"),
     "key_tiebreak_reversed": ("return a->k2 < b->k2;", "return a->k2 > b->k2;"),
@@ -37,6 +43,8 @@ MUTANTS = {
                                 "            for (int J = I + 1; J < js + s && is != ks; J++)\n                if (in_range(J, js, s))\n                    if (tl_push(l, (or_task){OR_GEMM"),
     "gemm_flops_wrong": ("static const int64_t c[4] = {1, 3, 3, 6};", "static const int64_t c[4] = {1, 3, 3, 3};"),
 }
+# Not listed: ordering FCFS releases latest first is an equivalent mutant -- the
+# ready set is emptied at every instant, so it never holds two release times.
 # Not listed: dropping the explicit max with the current time T from the start
 # time is an equivalent mutant -- a task is released by the completion, at T, of
 # a predecessor that wrote one of its blocks, so its data is never ready before
@@ -60,11 +68,14 @@ def _pins_pass():
     """True when every quick pin holds for the currently loaded oracle."""
     with open(os.path.join(GOLD, "worked_examples.json")) as f:
         ex = json.load(f)["examples"]
+    with open(os.path.join(GOLD, "policy_examples.json")) as f:
+        ex = ex + json.load(f)["examples"]
     try:
         for e in ex:
             pts = [I.ProcType(n, c, r, r, h, own) for (n, c, r, h, own) in e["platform"]["types"]]
             pf = I.make_platform(pts, seed=0)
-            s = O.simulate(pf, e["nt"], e["dmax"], e["b"], np.array(e["depth"], np.uint8))
+            s = O.simulate(pf, e["nt"], e["dmax"], e["b"], np.array(e["depth"], np.uint8),
+                           policy=tuple(e.get("policy", (0, 0))))
             if s.makespan != e["makespan"]:
                 return False
             got = {tuple(int(x) for x in s.tasks[t]): (int(s.proc[t]), int(s.start[t]), int(s.finish[t]))

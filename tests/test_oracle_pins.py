@@ -353,3 +353,94 @@ def test_paper_width_example():
     # the chain above is the 2x2 loop nest at b/2; its trsm split once more
     s = O.simulate(pf, 2, 1, 512, np.array([0, 1, 0, 0], np.uint8))
     assert _width(s.n_tasks, s.edges) == 2
+
+
+# ---------------------------------------------------------------- other heuristics of section 2.1
+# policy = (order, select): order 0 Priority-List, 1 FCFS; select 0 EFT-P, 1 EIT-P
+POLICIES = [(0, 0), (1, 0), (0, 1), (1, 1)]
+
+
+def test_policy_worked_examples():
+    """Hand-derived FCFS and EIT-P schedules (tests/golden/policy_examples.json)."""
+    with open(os.path.join(GOLD, "policy_examples.json")) as f:
+        ex = json.load(f)["examples"]
+    for e in ex:
+        pf = platform_from_spec(e["platform"]["types"])
+        s = O.simulate(pf, e["nt"], e["dmax"], e["b"], np.array(e["depth"], np.uint8), policy=tuple(e["policy"]))
+        assert s.makespan == e["makespan"], e["name"]
+        got = {tuple(int(x) for x in s.tasks[t]): (int(s.proc[t]), int(s.start[t]), int(s.finish[t]))
+               for t in range(s.n_tasks)}
+        assert len(got) == len(e["schedule"])
+        for (kind, lvl, K, I_, J, p, st, fi) in e["schedule"]:
+            assert got[(KIND[kind], lvl, K, I_, J)] == (p, st, fi), (e["name"], kind, K, I_, J)
+
+
+@pytest.mark.parametrize("policy", POLICIES)
+def test_python_reading_agrees_on_policies(policy):
+    """The independent Python reading of FCFS / EIT-P gives the same schedules."""
+    rng = np.random.default_rng(100 + 2 * policy[0] + policy[1])
+    plats = [I.make_platform(I.cpu_accel_types(2, 1), seed=4),
+             I.make_platform(I.cpu_accel_types(3, 2), seed=5),
+             I.make_platform(I.big_little_types(2, 2), seed=6)]
+    for trial in range(24):
+        pf = plats[trial % 3]
+        nt = int(rng.integers(1, 5))
+        dmax = int(rng.integers(0, 3))
+        dep = rng.integers(0, dmax + 1, nt * (nt + 1) * (nt + 2) // 6).astype(np.uint8)
+        s = O.simulate(pf, nt, dmax, 256, dep, policy=policy)
+        ms, proc, start, finish = _py_sim(pf, nt, dmax, 256, dep).run(order=["PL", "FCFS"][policy[0]],
+                                                                      select=["EFT", "EIT"][policy[1]])
+        assert ms == s.makespan
+        assert list(s.proc) == proc and list(s.start) == start and list(s.finish) == finish
+
+
+def test_eit_equals_eft_on_identical_processors_without_transfers():
+    """With identical processors in one memory space every finish time is the
+    idle time plus the same cost, so EIT-P and EFT-P choose alike."""
+    rng = np.random.default_rng(8)
+    for P in (2, 3, 4):
+        pf = platform_from_spec([["cpu", P, 23000, 64, False]])
+        for nt, dmax in [(3, 1), (4, 2), (5, 1)]:
+            dep = rng.integers(0, dmax + 1, nt * (nt + 1) * (nt + 2) // 6).astype(np.uint8)
+            for order in (0, 1):
+                a = O.simulate(pf, nt, dmax, 512, dep, policy=(order, 0))
+                b = O.simulate(pf, nt, dmax, 512, dep, policy=(order, 1))
+                assert a.makespan == b.makespan
+                assert np.array_equal(a.proc, b.proc) and np.array_equal(a.start, b.start)
+
+
+def test_fcfs_equals_pl_when_releases_are_single():
+    """The 2x2 unsplit DAG is a chain: one task is released at a time, so the
+    task order cannot matter."""
+    pf = I.make_platform(I.cpu_accel_types(2, 1), seed=11)
+    for sel in (0, 1):
+        a = O.simulate(pf, 2, 0, 512, np.zeros(4, np.uint8), policy=(0, sel))
+        b = O.simulate(pf, 2, 0, 512, np.zeros(4, np.uint8), policy=(1, sel))
+        assert a.makespan == b.makespan and np.array_equal(a.proc, b.proc)
+
+
+@pytest.mark.parametrize("policy", POLICIES)
+def test_policy_invariants(policy):
+    """Every policy: a single processor gives the sum of the costs; schedules are
+    valid; the heterogeneous lower bounds hold; identical processors obey
+    Graham's bound."""
+    rng = np.random.default_rng(20 + 2 * policy[0] + policy[1])
+    pf1 = platform_from_spec([["cpu", 1, 27000, 64, False]])
+    dep = rng.integers(0, 2, 20).astype(np.uint8)
+    s = O.simulate(pf1, 4, 1, 256, dep, policy=policy)
+    assert s.makespan == sum(PY.task_time(int(k), 256 >> int(l), 27000, 64) for k, l, *_ in s.tasks)
+    w = I.WORKLOADS["chol4x4_b512_d1"]
+    pf = w.platform()
+    bt = w.batch(4)
+    for c in range(bt.n):
+        s = O.simulate(pf, w.nt, w.dmax, w.b, bt.candidate(c), policy=policy)
+        validate_schedule(pf, w.b, w.dmax, s)
+        cmin = _costs(pf, w.b, s).min(axis=1)
+        assert s.makespan >= _longest_path(s.n_tasks, s.edges, cmin)
+        assert pf.n_procs * s.makespan >= int(cmin.sum())
+    pf3 = platform_from_spec([["cpu", 3, 25000, 64, False]])
+    dep = rng.integers(0, 3, 20).astype(np.uint8)
+    s = O.simulate(pf3, 4, 2, 512, dep, policy=policy)
+    c = _costs(pf3, 512, s)[:, 0]
+    cp = _longest_path(s.n_tasks, s.edges, c)
+    assert cp <= s.makespan and 3 * s.makespan <= int(c.sum()) + 2 * cp
