@@ -98,10 +98,18 @@ typedef struct {
   const int64_t *xfer_ns;      /* [4^max_level + 1], xfer_ns[0] = 0, non-decreasing */
 } hesp_platform;
 
-/* Heuristics of section 2.1.  Only Priority-List order, EFT-P selection and
- * write-back caching are implemented; any other value gives HESP_EUNSUPPORTED. */
+/* Heuristics of section 2.1 ("Task and data scheduling heuristics").  Tasks are
+ * mapped when released (push at release).  Order of the tasks released at one
+ * instant: Priority-List (decreasing critical time) or FCFS (release order; all
+ * of them share the instant, so ties by scaled (K,I,J) decide); both break ties
+ * by scaled (K,I,J).  Processor: EFT-P (earliest finish counting the transfers
+ * the task needs) or EIT-P (earliest idle time, an idle processor counting from
+ * now); ties to the lowest index.  Caching: write-back.  Other values (R-P,
+ * F-P, write-through, write-around) give HESP_EUNSUPPORTED. */
 #define HESP_ORDER_PL 0
+#define HESP_ORDER_FCFS 1
 #define HESP_SELECT_EFT 0
+#define HESP_SELECT_EIT 1
 #define HESP_CACHE_WB 0
 typedef struct { int32_t order, select, cache; } hesp_policy;
 

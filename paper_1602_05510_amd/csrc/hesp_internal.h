@@ -21,6 +21,8 @@ struct SimTables {
   int64_t cost[kMaxPtypes][4][kLevels];   // task time, ns
   int64_t W[4][kLevels];                  // sum of the task time over all processors
   int64_t xfer[kXferLen];                 // transfer time by number of finest blocks
+  int32_t fcfs;                           // task order: 0 Priority-List, 1 first released first
+  int32_t eit;                            // processor selection: 0 earliest finish, 1 earliest idle
 };
 
 struct BatchView {

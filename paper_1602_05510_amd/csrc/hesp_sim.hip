@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
       } else if (small) {
         // position of each entry: decreasing critical time, then increasing key
         const bool v = gl < n_ready;
-        const int64_t rk = v ? s_rrank[g][gl] : -1;
+        const int64_t rk = v ? (tb.fcfs ? 0 : s_rrank[g][gl]) : -1;   // FCFS: same instant, keys decide
         const uint32_t ky = v ? task_key(s_rdesc[g][gl], dmax) : 0u;
         int pos = 0;
         for (int j = 0; j < (int)n_ready; j++) {
@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
               rk = vld(&sp.rec[2 * id]);
               dsc = (uint32_t)vld(&sp.rec[2 * id + 1]);
             }
-            sp.sortbuf[2 * x] = rk;
+            sp.sortbuf[2 * x] = tb.fcfs ? 0 : rk;
             sp.sortbuf[2 * x + 1] = ((int64_t)task_key(dsc, dmax) << 32) | id;
           } else {
             sp.sortbuf[2 * x] = -1;
@@ -529,10 +529,12 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
             est = max64(est, rdy);
           }
         const int64_t eft = est + s_cost[ptype][kind][lvl];
-        const int64_t key = gl < P ? ((eft << 6) | gl) : kInf;
+        // EFT-P: earliest finish; EIT-P: earliest idle time (an idle processor from now)
+        const int64_t sel = tb.eit ? (T > avail ? T : avail) : eft;
+        const int64_t key = gl < P ? ((sel << 6) | gl) : kInf;
         const int64_t best = gp.min64all(key);
         const int pstar = (int)(best & 63);
-        const int64_t eft_star = best >> 6;
+        const int64_t eft_star = tb.eit ? gp.bcast64(eft, pstar) : best >> 6;
         const int64_t est_star = gp.bcast64(est, pstar);
         const int mstar = gp.bcast(pmem, pstar);
         // transfers of the missing finest blocks start now

@@ -55,6 +55,10 @@ class OutputsC(ctypes.Structure):
 
 
 SEARCH_RANDOM, SEARCH_GREEDY, SEARCH_SURROGATE = 0, 1, 2
+# heuristics of section 2.1: policy = (order, select, cache)
+ORDER_PL, ORDER_FCFS = 0, 1
+SELECT_EFT, SELECT_EIT = 0, 1
+CACHE_WB = 0
 
 
 class SearchParams(ctypes.Structure):

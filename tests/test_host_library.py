@@ -176,3 +176,14 @@ def test_search_argument_errors_need_no_gpu():
     rc = H.lib().hesp_search(ctypes.c_void_p(1), ctypes.byref(pf.c), H.Policy(0, 0, 0), ctypes.byref(sp),
                              best.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ms), None, None)
     assert rc == H.HESP_EINVAL          # rounds = 0
+
+
+def test_unsupported_policies_rejected_before_device_work():
+    w = I.WORKLOADS["chol4x4_b512_d1"]
+    pf = H.Platform.from_inputs(w.platform(), w.b, w.dmax)
+    b = H.BatchC(1, 4, 1, None, None, None, None)
+    out = H.OutputsC(None, None, None, None, None, None, None)
+    for pol in [(2, 0, 0), (0, 2, 0), (0, 0, 1), (0, 3, 0)]:       # R-P / F-P / write-through are not built
+        rc = H.lib().hesp_simulate_batch(ctypes.c_void_p(1), ctypes.byref(pf.c), H.Policy(*pol), ctypes.byref(b),
+                                         ctypes.byref(out), None)
+        assert rc == H.HESP_EUNSUPPORTED, pol
