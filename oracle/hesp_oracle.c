@@ -27,8 +27,10 @@
  *      spaces and transfers issued when a task is scheduled (section 2.1,
  *      "Task and data scheduling heuristics"); task order Priority-List
  *      (decreasing critical time) or FCFS (order of release), processor
- *      selection EFT-P (earliest finish counting transfers) or EIT-P (the
- *      processor that becomes idle first).
+ *      selection EFT-P (earliest finish counting transfers), EIT-P (the
+ *      processor that becomes idle first), R-P (random) or F-P (fastest) --
+ *      the last two among the processors idle at that time; a task finding no
+ *      idle processor waits for the next completion.
  * Where the paper is silent (tie-breaks, simultaneous events, transfer issue
  * time, coherence granularity) the readings are those listed in the design
  * notes of this repository; each is marked "reading:" below.
@@ -92,8 +94,23 @@ typedef struct {
     int64_t latency_ns, bw, elem_bytes;
     int shared;              /* single memory space, transfers cost 0 */
     int order;               /* policy: 0 = Priority-List, 1 = FCFS */
-    int select;              /* policy: 0 = EFT-P, 1 = EIT-P */
+    int select;              /* policy: 0 = EFT-P, 1 = EIT-P, 2 = R-P, 3 = F-P */
+    uint64_t seed;           /* R-P draws */
 } or_platform;
+
+/* SplitMix64 (Steele, Lea, Flood 2014): value number idx+1 of the sequence
+ * that starts at mix(seed + gamma (purpose+1)); used for the R-P choice. */
+static uint64_t sm_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+static uint64_t sm_draw(uint64_t seed, uint64_t purpose, uint64_t idx)
+{
+    const uint64_t g = 0x9E3779B97F4A7C15ull;
+    return sm_mix(sm_mix(seed + g * (purpose + 1)) + g * (idx + 1));
+}
 
 /* ------------------------------------------------------------------------ */
 /* 2. expansion                                                              */
@@ -439,15 +456,39 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
     int64_t T = 0, makespan = 0;
     int done_count = 0;
     for (;;) {
-        /* (i) every ready task is mapped now, in priority order */
+        /* (i) ready tasks are mapped now, in order; with R-P / F-P only onto
+         * processors idle now (nothing queued), the others wait */
         while (heap.n) {
+            int n_idle = 0, pick = -1;
+            if (pf->select >= 2) {
+                for (int p = 0; p < P; p++) n_idle += avail[p] <= T;
+                if (n_idle == 0) break;          /* every processor busy: wait */
+            }
             int t = heap_pop(&heap).task;
             int br[3], bc[3], bw[3];
             int nb = task_blocks(&tl.v[t], br, bc, bw);
             int sh = dmax - tl.v[t].level, w = 1 << sh;
+            if (pf->select == 2) {
+                /* R-P: the u-th idle processor (index order), u drawn for the
+                 * task's finest-grid corner (K, I, J) */
+                uint64_t key = ((uint64_t)tl.v[t].K << sh << 18) | ((uint64_t)tl.v[t].I << sh << 9) |
+                               ((uint64_t)tl.v[t].J << sh);
+                int u = (int)(sm_draw(pf->seed, 8, key) % (uint64_t)n_idle);
+                for (int p = 0; p < P; p++)
+                    if (avail[p] <= T && u-- == 0) { pick = p; break; }
+            } else if (pf->select == 3) {
+                /* F-P: the idle processor with the smallest task time, ties lowest */
+                int64_t best_c = 0;
+                for (int p = 0; p < P; p++) {
+                    if (avail[p] > T) continue;
+                    int64_t c = tb.cost[(pf->proc_type[p] * 4 + tl.v[t].type) * L + tl.v[t].level];
+                    if (pick < 0 || c < best_c) { pick = p; best_c = c; }
+                }
+            }
             int best_p = -1;
             int64_t best_eft = 0, best_est = 0, best_sel = 0;
             for (int p = 0; p < P; p++) {
+                if (pick >= 0 && p != pick) continue;
                 int m = pf->proc_mem[p];
                 int64_t est = T > avail[p] ? T : avail[p];
                 for (int bi = 0; bi < nb; bi++) {
@@ -568,15 +609,15 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
                     int64_t *makespan, int32_t *n_tasks, int64_t *n_edges,
                     int32_t max_tasks, int32_t *task_info, int32_t *proc_out,
                     int64_t *start_out, int64_t *finish_out, int64_t *rank_out,
-                    int64_t max_edges, int32_t *edges_out, int order, int select)
+                    int64_t max_edges, int32_t *edges_out, int order, int select, uint64_t seed)
 {
     if (!depth || n_procs < 1 || !proc_type || !proc_mem || n_mem < 1 || !rmax || !h) return OR_EINVAL;
-    if (order < 0 || order > 1 || select < 0 || select > 1) return OR_EINVAL;
+    if (order < 0 || order > 1 || select < 0 || select > 3) return OR_EINVAL;
     for (int p = 0; p < n_procs; p++)
         if (proc_type[p] < 0 || proc_type[p] >= n_ptypes || proc_mem[p] < 0 || proc_mem[p] >= n_mem)
             return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared, order, select};
+                      latency_ns, bw, elem_bytes, shared, order, select, seed};
     or_outputs o = {max_tasks, task_info, proc_out, start_out, finish_out, rank_out, max_edges, edges_out};
     or_result r;
     int rc = simulate_one(&pf, nt, dmax, depth, &r, &o);
@@ -624,12 +665,12 @@ int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
                           int n_ptypes, const int64_t *rmax, const int64_t *h, int64_t b,
                           int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
                           int n_threads, int64_t *makespan, int32_t *n_tasks, int32_t *status,
-                          int order, int select)
+                          int order, int select, uint64_t seed)
 {
     if (n_cand < 0 || !nt || !dmax || !mask_off || !depth || !makespan || n_threads < 1) return OR_EINVAL;
-    if (order < 0 || order > 1 || select < 0 || select > 1) return OR_EINVAL;
+    if (order < 0 || order > 1 || select < 0 || select > 3) return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared, order, select};
+                      latency_ns, bw, elem_bytes, shared, order, select, seed};
     or_batch_job j;
     j.pf = &pf; j.n_cand = n_cand; j.nt = nt; j.dmax = dmax; j.mask_off = mask_off; j.depth = depth;
     j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.next = 0;

@@ -177,10 +177,13 @@ class Sim:
             e = max(e, r)
         return e
 
-    def run(self, choose_task=None, choose_proc=None, order="PL", select="EFT"):
+    def run(self, choose_task=None, choose_proc=None, order="PL", select="EFT", seed=0):
         """order: "PL" (decreasing critical time) or "FCFS" (first released first);
-        select: "EFT" (earliest finish) or "EIT" (processor idle first).  Ties:
-        smaller scaled (K, I, J), then lower processor index."""
+        select: "EFT" (earliest finish), "EIT" (processor idle first), "RP"
+        (random idle processor) or "FP" (fastest idle processor); with RP / FP a
+        task that finds no idle processor waits for a completion.  Ties: smaller
+        scaled (K, I, J), then lower processor index."""
+        from paper_1602_05510_amd.inputs import draw
         N = 0
         vf = {}
         for t in self.tasks:
@@ -196,6 +199,9 @@ class Sim:
         T = 0
         while True:
             while ready:
+                idle = [q for q in range(self.P) if avail[q] <= T]
+                if select in ("RP", "FP") and not idle:
+                    break
                 if choose_task:
                     t = choose_task(ready, self)
                 elif order == "FCFS":
@@ -209,6 +215,13 @@ class Sim:
                     p = choose_proc(t, efts, self)
                 elif select == "EIT":
                     p = min(range(self.P), key=lambda q: (max(T, avail[q]), q))
+                elif select == "RP":
+                    kind, lvl, K, I, J, _ = self.tasks[t]
+                    sh = self.dmax - lvl
+                    corner = ((K << sh) << 18) | ((I << sh) << 9) | (J << sh)
+                    p = idle[draw(seed, 8, corner) % len(idle)]
+                elif select == "FP":
+                    p = min(idle, key=lambda q: (self.cost[t][q], q))
                 else:
                     p = min(range(self.P), key=lambda q: (efts[q], q))
                 m = self.proc_mem[p]

@@ -28,6 +28,14 @@ MUTANTS = {
                         "int64_t sel = eft;"),
     "fcfs_keeps_priority": ("heap_push(&heap, (or_hent){pf->order ? -Tn : rank[v],",
                             "heap_push(&heap, (or_hent){rank[v],"),
+    "pull_never_waits": ("if (n_idle == 0) break;          /* every processor busy: wait */",
+                         "if (n_idle < 0) break;"),
+    "fp_slowest": ("if (pick < 0 || c < best_c) { pick = p; best_c = c; }",
+                   "if (pick < 0 || c > best_c) { pick = p; best_c = c; }"),
+    "rp_other_stream": ("int u = (int)(sm_draw(pf->seed, 8, key) % (uint64_t)n_idle);",
+                        "int u = (int)(sm_draw(pf->seed, 9, key) % (uint64_t)n_idle);"),
+    "rp_any_processor": ("if (avail[p] <= T && u-- == 0) { pick = p; break; }",
+                         "if (u-- == 0) { pick = p; break; }"),
     "priority_reversed": ("if (a->rank != b->rank) return a->rank > b->rank;",
                           "if (a->rank != b->rank) return a->rank < b->rank;"),
     "key_tiebreak_reversed": ("return a->k2 < b->k2;", "return a->k2 > b->k2;"),
@@ -104,6 +112,13 @@ def _pins_pass():
             lp[t] = cmin[t] + max([lp[v] for v in succ[t]], default=0)
         if s.makespan < max(lp):
             return False
+        # R-P against the independent Python reading
+        pf3 = I.make_platform(I.big_little_types(2, 2), seed=6)
+        for seed, dep3 in ((7, np.array([1, 0, 1, 0, 1, 1, 0, 1, 0, 1], np.uint8)), (3, np.zeros(10, np.uint8))):
+            r = O.simulate(pf3, 3, 1, 256, dep3, policy=(0, 2, seed))
+            py = PY.Sim(3, 1, 256, dep3, pf3.proc_type, pf3.proc_mem, pf3.n_mem, pf3.rmax, pf3.h, pf3.shared_memory)
+            if py.run(select="RP", seed=seed)[1] != list(r.proc):
+                return False
         # every top-level task of a 3x3 split DAG depends on something except chol0
         if len(s.edges) < s.n_tasks - 1:
             return False

@@ -356,8 +356,10 @@ def test_paper_width_example():
 
 
 # ---------------------------------------------------------------- other heuristics of section 2.1
-# policy = (order, select): order 0 Priority-List, 1 FCFS; select 0 EFT-P, 1 EIT-P
-POLICIES = [(0, 0), (1, 0), (0, 1), (1, 1)]
+# policy = (order, select[, seed]): order 0 Priority-List, 1 FCFS; select 0 EFT-P,
+# 1 EIT-P, 2 R-P, 3 F-P (the last two choose among idle processors; tasks wait)
+POLICIES = [(0, 0), (1, 0), (0, 1), (1, 1), (0, 2, 7), (1, 2, 7), (0, 3), (1, 3)]
+SELECT_NAMES = ["EFT", "EIT", "RP", "FP"]
 
 
 def test_policy_worked_examples():
@@ -377,8 +379,8 @@ def test_policy_worked_examples():
 
 @pytest.mark.parametrize("policy", POLICIES)
 def test_python_reading_agrees_on_policies(policy):
-    """The independent Python reading of FCFS / EIT-P gives the same schedules."""
-    rng = np.random.default_rng(100 + 2 * policy[0] + policy[1])
+    """The independent Python reading of FCFS / EIT-P / R-P / F-P gives the same schedules."""
+    rng = np.random.default_rng(100 + 4 * policy[0] + policy[1])
     plats = [I.make_platform(I.cpu_accel_types(2, 1), seed=4),
              I.make_platform(I.cpu_accel_types(3, 2), seed=5),
              I.make_platform(I.big_little_types(2, 2), seed=6)]
@@ -388,8 +390,8 @@ def test_python_reading_agrees_on_policies(policy):
         dmax = int(rng.integers(0, 3))
         dep = rng.integers(0, dmax + 1, nt * (nt + 1) * (nt + 2) // 6).astype(np.uint8)
         s = O.simulate(pf, nt, dmax, 256, dep, policy=policy)
-        ms, proc, start, finish = _py_sim(pf, nt, dmax, 256, dep).run(order=["PL", "FCFS"][policy[0]],
-                                                                      select=["EFT", "EIT"][policy[1]])
+        ms, proc, start, finish = _py_sim(pf, nt, dmax, 256, dep).run(
+            order=["PL", "FCFS"][policy[0]], select=SELECT_NAMES[policy[1]], seed=(tuple(policy) + (0,))[2])
         assert ms == s.makespan
         assert list(s.proc) == proc and list(s.start) == start and list(s.finish) == finish
 
@@ -424,7 +426,7 @@ def test_policy_invariants(policy):
     """Every policy: a single processor gives the sum of the costs; schedules are
     valid; the heterogeneous lower bounds hold; identical processors obey
     Graham's bound."""
-    rng = np.random.default_rng(20 + 2 * policy[0] + policy[1])
+    rng = np.random.default_rng(20 + 4 * policy[0] + policy[1])
     pf1 = platform_from_spec([["cpu", 1, 27000, 64, False]])
     dep = rng.integers(0, 2, 20).astype(np.uint8)
     s = O.simulate(pf1, 4, 1, 256, dep, policy=policy)
@@ -444,3 +446,23 @@ def test_policy_invariants(policy):
     c = _costs(pf3, 512, s)[:, 0]
     cp = _longest_path(s.n_tasks, s.edges, c)
     assert cp <= s.makespan and 3 * s.makespan <= int(c.sum()) + 2 * cp
+
+
+def test_random_choice_on_one_processor_is_the_fastest_choice():
+    """With one processor there is one idle choice: R-P and F-P coincide, for any seed."""
+    pf = platform_from_spec([["cpu", 1, 30000, 64, False]])
+    dep = np.array([1, 0, 1, 0, 1, 1, 0, 1, 0, 1], np.uint8)
+    for order in (0, 1):
+        a = O.simulate(pf, 3, 1, 512, dep, policy=(order, 3))
+        for seed in (0, 1, 99):
+            b = O.simulate(pf, 3, 1, 512, dep, policy=(order, 2, seed))
+            assert np.array_equal(a.start, b.start)
+
+
+def test_random_choice_depends_on_the_seed_and_spreads():
+    """R-P draws differ between seeds and reach every processor."""
+    pf = platform_from_spec([["cpu", 4, 30000, 64, False]])
+    dep = np.zeros(I.tet(6), np.uint8)
+    runs = [O.simulate(pf, 6, 0, 512, dep, policy=(0, 2, seed)) for seed in range(4)]
+    assert len({tuple(r.proc) for r in runs}) > 1
+    assert set(np.concatenate([r.proc for r in runs]).tolist()) == {0, 1, 2, 3}
