@@ -104,14 +104,25 @@ typedef struct {
  * of them share the instant, so ties by scaled (K,I,J) decide); both break ties
  * by scaled (K,I,J).  Processor: EFT-P (earliest finish counting the transfers
  * the task needs) or EIT-P (earliest idle time, an idle processor counting from
- * now); ties to the lowest index.  Caching: write-back.  Other values (R-P,
- * F-P, write-through, write-around) give HESP_EUNSUPPORTED. */
+ * now); ties to the lowest index.  R-P (random) and F-P (fastest: smallest task
+ * time, ties to the lowest index) choose among the processors idle now (nothing
+ * queued); while none is idle the remaining released tasks wait and are mapped,
+ * in order, at later completions (FCFS then means earliest release first).  R-P
+ * takes the u-th idle processor in index order, u = SplitMix64 value
+ * draw(seed, 8, corner) mod (idle count), corner = K' << 18 | I' << 9 | J' with
+ * (K', I', J') the task's first cell on the finest grid.  Caching: write-back;
+ * other values (write-through, write-around) give HESP_EUNSUPPORTED. */
 #define HESP_ORDER_PL 0
 #define HESP_ORDER_FCFS 1
 #define HESP_SELECT_EFT 0
 #define HESP_SELECT_EIT 1
+#define HESP_SELECT_RP 2
+#define HESP_SELECT_FP 3
 #define HESP_CACHE_WB 0
-typedef struct { int32_t order, select, cache; } hesp_policy;
+typedef struct {
+  int32_t order, select, cache;
+  uint64_t seed;               /* R-P draws */
+} hesp_policy;
 
 /* ---- expansion of one candidate (host) ----------------------------------------
  * Section 2.1, "Recursive task partitioners", applied to the Fig. 1 loop nest:

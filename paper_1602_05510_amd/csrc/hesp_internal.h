@@ -22,7 +22,9 @@ struct SimTables {
   int64_t W[4][kLevels];                  // sum of the task time over all processors
   int64_t xfer[kXferLen];                 // transfer time by number of finest blocks
   int32_t fcfs;                           // task order: 0 Priority-List, 1 first released first
-  int32_t eit;                            // processor selection: 0 earliest finish, 1 earliest idle
+  int32_t sel;                            // processor: 0 earliest finish, 1 earliest idle, 2 random idle,
+                                          // 3 fastest idle (2, 3: tasks wait while no processor is idle)
+  uint64_t seed;                          // random choices (SplitMix64)
 };
 
 struct BatchView {

@@ -311,6 +311,18 @@ __global__ void __launch_bounds__(kWave) k_prepare(SimTables tb, BatchView bv, C
 
 // ---------------------------------------------------------------- event simulation
 
+// SplitMix64 (Steele, Lea, Flood 2014): value idx+1 of the stream of purpose 8
+// (random processor choices) of `seed`
+__device__ __forceinline__ uint64_t choice_draw(uint64_t seed, uint64_t idx) {
+  auto mix = [](uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  const uint64_t g = 0x9E3779B97F4A7C15ull;
+  return mix(mix(seed + g * 9ull) + g * (idx + 1));
+}
+
 template <int G>
 __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
                                                uint32_t* counter) {
@@ -380,9 +392,11 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
           hid = kNil;
           tail = kNil;
           n_ready = cv.nsrc[c - cv.c0];
-          for (int64_t x = gl; x < n_ready && x < G; x += G) {
+          // FCFS keeps minus the release time in the rank slot (sources: 0)
+          for (int64_t x = gl; x < n_ready; x += G) {
             const uint32_t v = vld(&sp.ready[x]);
-            push(x, v, vld(&sp.rec[2 * v]), vld(&sp.rec[2 * v + 1]), vld(&sp.rec[2 * v + 3]));
+            if (tb.fcfs) sp.rec[2 * v] = 0;
+            if (x < G) push(x, v, tb.fcfs ? 0 : vld(&sp.rec[2 * v]), vld(&sp.rec[2 * v + 1]), vld(&sp.rec[2 * v + 3]));
           }
           active = true;
         }
@@ -400,7 +414,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
       } else if (small) {
         // position of each entry: decreasing critical time, then increasing key
         const bool v = gl < n_ready;
-        const int64_t rk = v ? (tb.fcfs ? 0 : s_rrank[g][gl]) : -1;   // FCFS: same instant, keys decide
+        const int64_t rk = v ? s_rrank[g][gl] : INT64_MIN;
         const uint32_t ky = v ? task_key(s_rdesc[g][gl], dmax) : 0u;
         int pos = 0;
         for (int j = 0; j < (int)n_ready; j++) {
@@ -426,10 +440,10 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
               rk = vld(&sp.rec[2 * id]);
               dsc = (uint32_t)vld(&sp.rec[2 * id + 1]);
             }
-            sp.sortbuf[2 * x] = tb.fcfs ? 0 : rk;
+            sp.sortbuf[2 * x] = rk;
             sp.sortbuf[2 * x + 1] = ((int64_t)task_key(dsc, dmax) << 32) | id;
           } else {
-            sp.sortbuf[2 * x] = -1;
+            sp.sortbuf[2 * x] = INT64_MIN;
             sp.sortbuf[2 * x + 1] = INT64_MAX;
           }
         }
@@ -457,7 +471,17 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
         }
       }
       wave_order();
+      int64_t r_stop = n_ready;
       for (int64_t r = 0; r < n_ready; r++) {
+        // R-P / F-P map onto processors idle now; without one the rest wait
+        uint64_t idle = 0;
+        if (tb.sel >= 2) {
+          idle = gp.ballot(gl < P && avail <= T);
+          if (idle == 0) {
+            r_stop = r;
+            break;
+          }
+        }
         uint32_t t, dsc, e0, e1;
         if (small) {
           const int q = gp.uni(s_order[g][r]);
@@ -529,12 +553,25 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
             est = max64(est, rdy);
           }
         const int64_t eft = est + s_cost[ptype][kind][lvl];
-        // EFT-P: earliest finish; EIT-P: earliest idle time (an idle processor from now)
-        const int64_t sel = tb.eit ? (T > avail ? T : avail) : eft;
-        const int64_t key = gl < P ? ((sel << 6) | gl) : kInf;
-        const int64_t best = gp.min64all(key);
-        const int pstar = (int)(best & 63);
-        const int64_t eft_star = tb.eit ? gp.bcast64(eft, pstar) : best >> 6;
+        int pstar;
+        int64_t eft_star;
+        if (tb.sel == 2) {
+          // R-P: the u-th idle processor in index order
+          const int u = (int)(choice_draw(tb.seed, task_key(dsc, dmax)) % (uint64_t)__popcll(idle));
+          const bool mine = ((idle >> gl) & 1ull) && __popcll(idle & gp.below()) == u;
+          pstar = __ffsll((unsigned long long)gp.ballot(mine)) - 1;
+          eft_star = gp.bcast64(eft, pstar);
+        } else {
+          // EFT-P: earliest finish; EIT-P: earliest idle time (an idle processor
+          // from now); F-P: smallest task time among the idle processors
+          int64_t sel = eft;
+          if (tb.sel == 1) sel = T > avail ? T : avail;
+          if (tb.sel == 3) sel = ((idle >> gl) & 1ull) ? s_cost[ptype][kind][lvl] : (kInf >> 6);
+          const int64_t key = gl < P ? ((sel << 6) | gl) : kInf;
+          const int64_t best = gp.min64all(key);
+          pstar = (int)(best & 63);
+          eft_star = tb.sel == 0 ? best >> 6 : gp.bcast64(eft, pstar);
+        }
         const int64_t est_star = gp.bcast64(est, pstar);
         const int mstar = gp.bcast(pmem, pstar);
         // transfers of the missing finest blocks start now
@@ -578,7 +615,40 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
         }
         wave_order();
       }
-      n_ready = 0;
+      if (r_stop < n_ready) {
+        // the tasks that found no idle processor stay released, in front
+        const int rem = (int)(n_ready - r_stop);
+        if (small) {
+          uint32_t id = 0, d1 = 0, a0 = 0, a1 = 0;
+          int64_t rk = 0;
+          if (gl < rem) {
+            const int q = s_order[g][r_stop + gl];
+            id = s_rid[g][q];
+            rk = s_rrank[g][q];
+            d1 = s_rdesc[g][q];
+            a0 = s_re0[g][q];
+            a1 = s_re1[g][q];
+          }
+          wave_order();
+          if (gl < rem) {
+            s_rid[g][gl] = id;
+            s_rrank[g][gl] = rk;
+            s_rdesc[g][gl] = d1;
+            s_re0[g][gl] = a0;
+            s_re1[g][gl] = a1;
+          }
+        } else {
+          for (int x = gl; x < rem; x += G) {
+            const uint32_t id = (uint32_t)(vld(&sp.sortbuf[2 * (r_stop + x) + 1]) & 0xFFFFFFFFll);
+            if (x < G) push(x, id, vld(&sp.rec[2 * id]), vld(&sp.rec[2 * id + 1]), vld(&sp.rec[2 * id + 3]));
+            else sp.ready[x] = id;
+          }
+        }
+        n_ready = rem;
+      } else {
+        n_ready = 0;
+      }
+      wave_order();
     }
 
     // (ii) next event: the earliest queue head
@@ -634,6 +704,10 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
           r1 = vld(&sp.rec[2 * v + 1]);
           r3 = vld(&sp.rec[2 * v + 3]);
           rel = atomicSub(&sp.indeg[v], 1u) == 1u;
+          if (tb.fcfs) {
+            r0 = -Tn;
+            if (rel) sp.rec[2 * v] = -Tn;
+          }
         }
         const uint64_t rm = gp.ballot(rel);
         if (rel) push(n_ready + __popcll(rm & gp.below()), v, r0, r1, r3);

@@ -33,7 +33,7 @@ class PlatformC(ctypes.Structure):
 
 
 class Policy(ctypes.Structure):
-    _fields_ = [("order", i32), ("select", i32), ("cache", i32)]
+    _fields_ = [("order", i32), ("select", i32), ("cache", i32), ("seed", u64)]
 
 
 class Task(ctypes.Structure):
@@ -57,7 +57,7 @@ class OutputsC(ctypes.Structure):
 SEARCH_RANDOM, SEARCH_GREEDY, SEARCH_SURROGATE = 0, 1, 2
 # heuristics of section 2.1: policy = (order, select, cache)
 ORDER_PL, ORDER_FCFS = 0, 1
-SELECT_EFT, SELECT_EIT = 0, 1
+SELECT_EFT, SELECT_EIT, SELECT_RP, SELECT_FP = 0, 1, 2, 3
 CACHE_WB = 0
 
 

@@ -1,5 +1,6 @@
-"""GPU parity of the FCFS task order and EIT-P processor selection (section 2.1)
-against the CPU oracle: makespans and per-task schedules bit-exact."""
+"""GPU parity of the task orders (Priority-List, FCFS) and processor selections
+(EFT-P, EIT-P, R-P, F-P) of section 2.1 against the CPU oracle: makespans and
+per-task schedules bit-exact."""
 import json
 import os
 
@@ -12,7 +13,7 @@ from paper_1602_05510_amd import inputs as I
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 KIND = {"chol": 0, "trsm": 1, "syrk": 2, "gemm": 3}
-POLICIES = [(0, 0), (1, 0), (0, 1), (1, 1)]
+POLICIES = [(0, 0), (1, 0), (0, 1), (1, 1), (0, 2, 7), (1, 2, 7), (0, 3), (1, 3)]
 NTHREADS = min(16, os.cpu_count() or 1)
 
 
@@ -45,7 +46,8 @@ def _run(H, torch, pf_in, batch, max_level, policy, sched=False, group=0):
         kw = dict(sched_off=off, proc=torch.empty(tot, dtype=torch.int32, device="cuda"),
                   start=torch.empty(tot, dtype=torch.int64, device="cuda"),
                   finish=torch.empty(tot, dtype=torch.int64, device="cuda"))
-    H.simulate_batch(H.Plan(group=group), pf, db, ms, st, policy=tuple(policy) + (0,), **kw)
+    pol = (policy[0], policy[1], 0, policy[2] if len(policy) > 2 else 0)
+    H.simulate_batch(H.Plan(group=group), pf, db, ms, st, policy=pol, **kw)
     torch.cuda.synchronize()
     assert bool((st == 0).all().item())
     return ms.cpu().numpy(), kw
@@ -109,3 +111,26 @@ def test_policy_worked_examples_on_gpu(H, torch):
                      np.array([0, n_top], np.int64), np.array(e["depth"], np.uint8))
         got, _ = _run(H, torch, pf, bt, e["dmax"], e["policy"])
         assert int(got[0]) == e["makespan"], e["name"]
+
+
+def test_random_choice_seed_changes_schedules(H, torch):
+    w = I.WORKLOADS["chol4x4_b512_d1"]
+    pf = w.platform()
+    bt = w.batch(256)
+    a, _ = _run(H, torch, pf, bt, w.dmax, (0, 2, 1))
+    b, _ = _run(H, torch, pf, bt, w.dmax, (0, 2, 2))
+    assert not np.array_equal(a, b)
+    want, _ = O.simulate_batch(pf, bt, NTHREADS, policy=(0, 2, 2))
+    assert np.array_equal(b, want)
+
+
+def test_waiting_on_one_processor(H, torch):
+    """One CPU: with R-P / F-P every release waits for the CPU; the makespan is the
+    sum of the task times and the schedule matches the oracle task by task."""
+    pf = I.make_platform([I.ProcType("cpu", 1, 30000, 30000, 64, False)], seed=0)
+    bt = I.WORKLOADS["chol4x4_b512_d1"].batch(64)
+    for pol in ((0, 3), (1, 3), (0, 2, 5)):
+        want, _ = O.simulate_batch(pf, bt, NTHREADS, policy=pol)
+        for group in (16, 64):
+            got, _ = _run(H, torch, pf, bt, 1, pol, group=group)
+            assert np.array_equal(got, want), (pol, group)
