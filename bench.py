@@ -286,6 +286,59 @@ def run_search(args, torch, H):
     print(json.dumps(rec), flush=True)
 
 
+# ----------------------------------------------------------------------- policy sweep
+
+POLICY_NAMES = {(0, 0): "PL/EFT-P", (1, 0): "FCFS/EFT-P", (0, 1): "PL/EIT-P", (1, 1): "FCFS/EIT-P",
+                (0, 2): "PL/R-P", (1, 2): "FCFS/R-P", (0, 3): "PL/F-P", (1, 3): "FCFS/F-P"}
+
+
+def run_policy_sweep(args, torch, H):
+    """Homogeneous tilings of one matrix (every task unsplit) under every task
+    order x processor selection pair: GFLOPS = (n^3 / 3) / makespan against the
+    tile count, each point checked against the oracle."""
+    from oracle import oracle as O
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf_in = w.platform()
+    n = args.sweep_n
+    dev = torch.device("cuda")
+    rows, exact = [], True
+    plan = H.Plan()
+    t_gpu = 0.0
+    for nt in args.sweep_nt:
+        b = n // nt
+        pf = H.Platform.from_inputs(pf_in, b, 0)
+        db = H.DeviceBatch(1, nt, 0, torch.zeros(I.tet(nt), dtype=torch.uint8, device=dev))
+        ms = torch.empty(1, dtype=torch.int64, device=dev)
+        st = torch.empty(1, dtype=torch.int32, device=dev)
+        host = I.Batch(b, np.array([nt], np.int32), np.array([0], np.int32), np.array([0, I.tet(nt)], np.int64),
+                       np.zeros(I.tet(nt), np.uint8))
+        for (order, sel), name in POLICY_NAMES.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H.simulate_batch(plan, pf, db, ms, st, policy=(order, sel, 0, args.sweep_seed))
+            torch.cuda.synchronize()
+            t_gpu += time.perf_counter() - t0
+            got = int(ms.item())
+            want, _ = O.simulate_batch(pf_in, host, 1, policy=(order, sel, args.sweep_seed))
+            exact &= got == int(want[0]) and int(st.item()) == 0
+            rows.append({"nt": nt, "b": b, "policy": name, "makespan_ns": got,
+                         "gflops": (n ** 3 / 3) / got})
+            print(f"sweep nt={nt} {name}: {got} ns, oracle {int(want[0])}, {time.perf_counter() - t0:.2f} s",
+                  file=sys.stderr, flush=True)
+    best = {}
+    for r in rows:
+        if r["policy"] not in best or r["gflops"] > best[r["policy"]]["gflops"]:
+            best[r["policy"]] = r
+    rec = {"metric": "policy x tile-count sweep (homogeneous partitions)", "value": None, "unit": "GFLOPS",
+           "n_gpus": 1, "steps": len(rows), "warmup": 0, "ms_per_step": 1e3 * t_gpu / len(rows),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"{w.name} platform, n={n}, unsplit tiles", "tile_counts": args.sweep_nt,
+                      "seed": args.sweep_seed, "parallelism": "none (1 GPU)"},
+           "bit_exact_vs_oracle": exact, "points": rows,
+           "best_tile_count": {k: {"nt": v["nt"], "gflops": v["gflops"]} for k, v in best.items()}}
+    print(json.dumps(rec), flush=True)
+
+
 # ----------------------------------------------------------------------- main
 
 def main():
@@ -313,6 +366,9 @@ def main():
     ap.add_argument("--sur-proposals", type=int, default=16)
     ap.add_argument("--sur-warm", type=int, default=4096)
     ap.add_argument("--sur-train-steps", type=int, default=20)
+    ap.add_argument("--sweep-n", type=int, default=16384)
+    ap.add_argument("--sweep-nt", type=int, nargs="+", default=[2, 4, 8, 16, 32, 64])
+    ap.add_argument("--sweep-seed", type=int, default=1)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -331,6 +387,8 @@ def main():
         return run_surrogate(args, torch, H)
     if args.workload == "chol64x64_b1024_d3":
         return run_search(args, torch, H)
+    if args.workload == "policy_sweep":
+        return run_policy_sweep(args, torch, H)
     w = I.WORKLOADS[args.workload]
     n = args.n_cand or w.n_cand
     pf_in = w.platform()

@@ -448,7 +448,9 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
           }
         }
         wave_order();
-        for (int64_t k2 = 2; k2 <= n2; k2 <<= 1) {
+        // R-P / F-P map at most one task per idle processor now: the entries are
+        // selected one at a time below instead of sorted
+        for (int64_t k2 = 2; k2 <= (tb.sel >= 2 ? 1 : n2); k2 <<= 1) {
           for (int64_t j2 = k2 >> 1; j2 > 0; j2 >>= 1) {
             for (int64_t x = gl; x < n2; x += G) {
               const int64_t y = x ^ j2;
@@ -490,7 +492,28 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
           e0 = s_re0[g][q];
           e1 = s_re1[g][q];
         } else {
-          t = (uint32_t)(vld(&sp.sortbuf[2 * r + 1]) & 0xFFFFFFFFll);
+          if (tb.sel >= 2) {
+            // best remaining entry: largest rank, then smallest key; taken entries
+            // have their key set to INT64_MAX
+            int64_t br = INT64_MIN, bk = INT64_MAX;
+            int bp = -1;
+            for (int x = gl; x < n_ready; x += G) {
+              const int64_t ra = vld(&sp.sortbuf[2 * x]), ka = vld(&sp.sortbuf[2 * x + 1]);
+              if (ka != INT64_MAX && (bp < 0 || ra > br || (ra == br && ka < bk))) {
+                br = ra;
+                bk = ka;
+                bp = x;
+              }
+            }
+            const int64_t rbest = ~gp.min64all(bp >= 0 ? ~br : kInf);   // ~ reverses the order exactly
+            const int64_t kbest = gp.min64all(bp >= 0 && br == rbest ? bk : kInf);
+            const int owner = __ffsll((unsigned long long)gp.ballot(bp >= 0 && br == rbest && bk == kbest)) - 1;
+            const int pos = gp.bcast(bp, owner);
+            if (gl == owner) sp.sortbuf[2 * pos + 1] = INT64_MAX;
+            t = (uint32_t)(kbest & 0xFFFFFFFFll);
+          } else {
+            t = (uint32_t)(vld(&sp.sortbuf[2 * r + 1]) & 0xFFFFFFFFll);
+          }
           const int64_t r1 = vld(&sp.rec[2 * t + 1]);
           dsc = (uint32_t)r1;
           e0 = (uint32_t)((uint64_t)r1 >> 32);
@@ -638,10 +661,22 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
             s_re1[g][gl] = a1;
           }
         } else {
-          for (int x = gl; x < rem; x += G) {
-            const uint32_t id = (uint32_t)(vld(&sp.sortbuf[2 * (r_stop + x) + 1]) & 0xFFFFFFFFll);
-            if (x < G) push(x, id, vld(&sp.rec[2 * id]), vld(&sp.rec[2 * id + 1]), vld(&sp.rec[2 * id + 3]));
-            else sp.ready[x] = id;
+          // entries not taken by the selection, in buffer order (the next round
+          // orders them again)
+          int kept = 0;
+          for (int x0 = 0; x0 < n_ready; x0 += G) {
+            const int x = x0 + gl;
+            int64_t ka = INT64_MAX;
+            if (x < n_ready) ka = vld(&sp.sortbuf[2 * x + 1]);
+            const bool keep = ka != INT64_MAX;
+            const uint64_t km = gp.ballot(keep);
+            const int at = kept + __popcll(km & gp.below());
+            if (keep) {
+              const uint32_t id = (uint32_t)(ka & 0xFFFFFFFFll);
+              if (at < G) push(at, id, vld(&sp.rec[2 * id]), vld(&sp.rec[2 * id + 1]), vld(&sp.rec[2 * id + 3]));
+              else sp.ready[at] = id;
+            }
+            kept += __popcll(km);
           }
         }
         n_ready = rem;
