@@ -582,9 +582,11 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   const bool capturing = cap != hipStreamCaptureStatusNone;
   if (capturing && n_chunks > 1)
     return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: a captured call must fit one chunk (%d needed)", n_chunks);
-  hipStream_t sp = capturing ? s : plan->s_prep, ss = capturing ? s : plan->s_sim;
+  // a single chunk has nothing to overlap: it stays on the caller's stream
+  const bool fork = !capturing && n_chunks > 1;
+  hipStream_t sp = fork ? plan->s_prep : s, ss = fork ? plan->s_sim : s;
   hipEvent_t* se = plan->sync_ev.data();
-  if (!capturing) {
+  if (fork) {
     HIP_TRY(hipEventRecord(se[0], s));
     HIP_TRY(hipStreamWaitEvent(sp, se[0], 0));
     HIP_TRY(hipStreamWaitEvent(ss, se[0], 0));
@@ -600,17 +602,17 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
     cv.order = plan->ws[set].order.as<uint32_t>();
     HIP_TRY(launch_prepare(tb, bv, cv, ov, sp));
     if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 1], sp));
-    if (!capturing) {
+    if (fork) {
       HIP_TRY(hipEventRecord(se[1 + 2 * i], sp));
       HIP_TRY(hipStreamWaitEvent(ss, se[1 + 2 * i], 0));
     }
     if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 2], ss));
     HIP_TRY(launch_sim(tb, bv, cv, ov, plan->slots, group, plan->counter, ss));
     if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 3], ss));
-    if (!capturing) HIP_TRY(hipEventRecord(se[2 + 2 * i], ss));
+    if (fork) HIP_TRY(hipEventRecord(se[2 + 2 * i], ss));
     if (plan->timing) plan->ev_used = 4 * (size_t)(i + 1);
   }
-  if (!capturing) HIP_TRY(hipStreamWaitEvent(s, se[2 * n_chunks], 0));
+  if (fork) HIP_TRY(hipStreamWaitEvent(s, se[2 * n_chunks], 0));
   return ok();
 }
 

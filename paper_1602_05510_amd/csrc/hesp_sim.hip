@@ -323,9 +323,16 @@ __device__ __forceinline__ uint64_t choice_draw(uint64_t seed, uint64_t idx) {
   return mix(mix(seed + g * 9ull) + g * (idx + 1));
 }
 
-template <int G>
+// Instantiated per policy class so that the default policy carries no policy
+// code: R-P / F-P map tasks only onto idle processors and may make them wait.
+template <int G, int POL>
 __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
                                                uint32_t* counter) {
+  // POL 0: Priority-List + EFT-P (no policy flags read); 1: the other push
+  // policies (FCFS, EIT-P); 2: R-P / F-P
+  constexpr bool PULL = POL == 2;
+  const bool fcfs = POL != 0 && tb.fcfs;
+  const int sel = POL == 0 ? 0 : tb.sel;
   constexpr int NG = kWave / G;
   constexpr int LGG = G == 16 ? 4 : (G == 32 ? 5 : 6);
   __shared__ int64_t s_cost[kMaxPtypes][4][kLevels];
@@ -393,10 +400,10 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
           tail = kNil;
           n_ready = cv.nsrc[c - cv.c0];
           // FCFS keeps minus the release time in the rank slot (sources: 0)
-          for (int64_t x = gl; x < n_ready; x += G) {
+          for (int64_t x = gl; x < (fcfs || n_ready < G ? n_ready : G); x += G) {
             const uint32_t v = vld(&sp.ready[x]);
-            if (tb.fcfs) sp.rec[2 * v] = 0;
-            if (x < G) push(x, v, tb.fcfs ? 0 : vld(&sp.rec[2 * v]), vld(&sp.rec[2 * v + 1]), vld(&sp.rec[2 * v + 3]));
+            if (fcfs) sp.rec[2 * v] = 0;
+            if (x < G) push(x, v, fcfs ? 0 : vld(&sp.rec[2 * v]), vld(&sp.rec[2 * v + 1]), vld(&sp.rec[2 * v + 3]));
           }
           active = true;
         }
@@ -450,7 +457,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
         wave_order();
         // R-P / F-P map at most one task per idle processor now: the entries are
         // selected one at a time below instead of sorted
-        for (int64_t k2 = 2; k2 <= (tb.sel >= 2 ? 1 : n2); k2 <<= 1) {
+        for (int64_t k2 = 2; k2 <= (PULL ? 1 : n2); k2 <<= 1) {
           for (int64_t j2 = k2 >> 1; j2 > 0; j2 >>= 1) {
             for (int64_t x = gl; x < n2; x += G) {
               const int64_t y = x ^ j2;
@@ -477,7 +484,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
       for (int64_t r = 0; r < n_ready; r++) {
         // R-P / F-P map onto processors idle now; without one the rest wait
         uint64_t idle = 0;
-        if (tb.sel >= 2) {
+        if (PULL) {
           idle = gp.ballot(gl < P && avail <= T);
           if (idle == 0) {
             r_stop = r;
@@ -492,7 +499,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
           e0 = s_re0[g][q];
           e1 = s_re1[g][q];
         } else {
-          if (tb.sel >= 2) {
+          if (PULL) {
             // best remaining entry: largest rank, then smallest key; taken entries
             // have their key set to INT64_MAX
             int64_t br = INT64_MIN, bk = INT64_MAX;
@@ -578,7 +585,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
         const int64_t eft = est + s_cost[ptype][kind][lvl];
         int pstar;
         int64_t eft_star;
-        if (tb.sel == 2) {
+        if (PULL && sel == 2) {
           // R-P: the u-th idle processor in index order
           const int u = (int)(choice_draw(tb.seed, task_key(dsc, dmax)) % (uint64_t)__popcll(idle));
           const bool mine = ((idle >> gl) & 1ull) && __popcll(idle & gp.below()) == u;
@@ -587,13 +594,13 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
         } else {
           // EFT-P: earliest finish; EIT-P: earliest idle time (an idle processor
           // from now); F-P: smallest task time among the idle processors
-          int64_t sel = eft;
-          if (tb.sel == 1) sel = T > avail ? T : avail;
-          if (tb.sel == 3) sel = ((idle >> gl) & 1ull) ? s_cost[ptype][kind][lvl] : (kInf >> 6);
-          const int64_t key = gl < P ? ((sel << 6) | gl) : kInf;
+          int64_t score = eft;
+          if (sel == 1) score = T > avail ? T : avail;
+          if (PULL && sel == 3) score = ((idle >> gl) & 1ull) ? s_cost[ptype][kind][lvl] : (kInf >> 6);
+          const int64_t key = gl < P ? ((score << 6) | gl) : kInf;
           const int64_t best = gp.min64all(key);
           pstar = (int)(best & 63);
-          eft_star = tb.sel == 0 ? best >> 6 : gp.bcast64(eft, pstar);
+          eft_star = sel == 0 ? best >> 6 : gp.bcast64(eft, pstar);
         }
         const int64_t est_star = gp.bcast64(est, pstar);
         const int mstar = gp.bcast(pmem, pstar);
@@ -638,7 +645,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
         }
         wave_order();
       }
-      if (r_stop < n_ready) {
+      if (PULL && r_stop < n_ready) {
         // the tasks that found no idle processor stay released, in front
         const int rem = (int)(n_ready - r_stop);
         if (small) {
@@ -739,7 +746,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
           r1 = vld(&sp.rec[2 * v + 1]);
           r3 = vld(&sp.rec[2 * v + 3]);
           rel = atomicSub(&sp.indeg[v], 1u) == 1u;
-          if (tb.fcfs) {
+          if (fcfs) {
             r0 = -Tn;
             if (rel) sp.rec[2 * v] = -Tn;
           }
@@ -803,9 +810,23 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
   const int per_wave = kWave / G;
   int waves = (v.nc + per_wave - 1) / per_wave;
   if (waves > slots) waves = slots;
-  if (G == 16) hipLaunchKernelGGL(k_sim<16>, dim3(waves), dim3(kWave), 0, s, t, b, v, o, counter);
-  else if (G == 32) hipLaunchKernelGGL(k_sim<32>, dim3(waves), dim3(kWave), 0, s, t, b, v, o, counter);
-  else hipLaunchKernelGGL(k_sim<64>, dim3(waves), dim3(kWave), 0, s, t, b, v, o, counter);
+  const int pol = t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs ? 1 : 0);
+  const dim3 grid(waves), block(kWave);
+#define HESP_SIM_LAUNCH(GG, PP) hipLaunchKernelGGL((k_sim<GG, PP>), grid, block, 0, s, t, b, v, o, counter)
+  if (G == 16) {
+    if (pol == 0) HESP_SIM_LAUNCH(16, 0);
+    else if (pol == 1) HESP_SIM_LAUNCH(16, 1);
+    else HESP_SIM_LAUNCH(16, 2);
+  } else if (G == 32) {
+    if (pol == 0) HESP_SIM_LAUNCH(32, 0);
+    else if (pol == 1) HESP_SIM_LAUNCH(32, 1);
+    else HESP_SIM_LAUNCH(32, 2);
+  } else {
+    if (pol == 0) HESP_SIM_LAUNCH(64, 0);
+    else if (pol == 1) HESP_SIM_LAUNCH(64, 1);
+    else HESP_SIM_LAUNCH(64, 2);
+  }
+#undef HESP_SIM_LAUNCH
   return hipGetLastError();
 }
 
