@@ -218,10 +218,23 @@ __global__ void __launch_bounds__(kWave) k_prepare(SimTables tb, BatchView bv, C
   // pass D: fill successor lists; afterwards cur[f] = one past the last edge of f
   for_each_fine(cd, [&](bool valid, int64_t f, int64_t top, uint32_t cell, int d, int K, int I, int J) {
     if (!valid) return;
+    // the first eight predecessors are collected (predicated register writes),
+    // then their slots are claimed together and written together
+    uint32_t pl[8];
+    int np = 0;
     for_each_pred(nt, depth_of, first_of, top, cell, d, K, I, J, [&](int64_t p) {
-      const uint32_t pos = atomicAdd(&sp.cur[p], 1u);
-      sp.succ[pos] = (uint32_t)f;
+      if (np < 8) {
+        for (int q = 0; q < 8; q++) pl[q] = q == np ? (uint32_t)p : pl[q];
+        np++;
+      } else {
+        const uint32_t pos = atomicAdd(&sp.cur[p], 1u);
+        sp.succ[pos] = (uint32_t)f;
+      }
     });
+    uint32_t pos[8];
+    for (int q = 0; q < 8; q++) pos[q] = q < np ? atomicAdd(&sp.cur[pl[q]], 1u) : 0u;
+    for (int q = 0; q < 8; q++)
+      if (q < np) sp.succ[pos[q]] = (uint32_t)f;
   });
   wave_order();
 
@@ -243,15 +256,23 @@ __global__ void __launch_bounds__(kWave) k_prepare(SimTables tb, BatchView bv, C
       w = s_W[desc_kind(dsc)][desc_level(dsc)];
       e0 = f == 0 ? 0u : vld_l2(&sp.cur[f - 1]);
       e1 = vld_l2(&sp.cur[f]);
-      for (uint32_t e = e0; e < e1; e++) {
-        const uint32_t v = vld(&sp.succ[e]);
-        if (v >= lim) {
-          ext = max64(ext, vld(&sp.rec[2 * v]));
-        } else if (nin < 8) {
-          inl |= (uint64_t)(v - base) << (6 * nin);
-          nin++;
-        } else {
-          ovf = true;
+      // four successors at a time: their ids, then the critical times of those
+      // outside the chunk, are loaded together (two dependent round trips per four)
+      for (uint32_t e = e0; e < e1; e += 4) {
+        uint32_t v[4];
+        int64_t rv[4];
+        for (int q = 0; q < 4; q++) v[q] = e + q < e1 ? vld(&sp.succ[e + q]) : kNil;
+        for (int q = 0; q < 4; q++) rv[q] = (v[q] != kNil && v[q] >= lim) ? vld(&sp.rec[2 * v[q]]) : INT64_MIN;
+        for (int q = 0; q < 4; q++) {
+          if (v[q] == kNil) continue;
+          if (v[q] >= lim) {
+            ext = max64(ext, rv[q]);
+          } else if (nin < 8) {
+            inl |= (uint64_t)(v[q] - base) << (6 * nin);
+            nin++;
+          } else {
+            ovf = true;
+          }
         }
       }
     }
