@@ -466,3 +466,22 @@ def test_random_choice_depends_on_the_seed_and_spreads():
     runs = [O.simulate(pf, 6, 0, 512, dep, policy=(0, 2, seed)) for seed in range(4)]
     assert len({tuple(r.proc) for r in runs}) > 1
     assert set(np.concatenate([r.proc for r in runs]).tolist()) == {0, 1, 2, 3}
+
+
+def test_python_reading_agrees_on_ten_thousand_candidates():
+    """The two independent readings agree on 10^4 small random candidates (all
+    eight order x selection pairs, three platform shapes)."""
+    rng = np.random.default_rng(2024)
+    plats = [I.make_platform(I.cpu_accel_types(2, 1), seed=s) for s in range(4)] + \
+            [I.make_platform(I.big_little_types(2, 2), seed=s) for s in range(4)] + \
+            [I.make_platform(I.cpu_accel_types(1, 2), seed=s) for s in range(4)]
+    for trial in range(10_000):
+        pf = plats[trial % len(plats)]
+        policy = POLICIES[trial % len(POLICIES)]
+        nt = int(rng.integers(1, 4))
+        dmax = int(rng.integers(0, 2))
+        dep = rng.integers(0, dmax + 1, nt * (nt + 1) * (nt + 2) // 6).astype(np.uint8)
+        s = O.simulate(pf, nt, dmax, 256, dep, policy=policy)
+        ms, proc, start, finish = _py_sim(pf, nt, dmax, 256, dep).run(
+            order=["PL", "FCFS"][policy[0]], select=SELECT_NAMES[policy[1]], seed=(tuple(policy) + (0,))[2])
+        assert ms == s.makespan and list(s.proc) == proc and list(s.start) == start, (trial, nt, dmax, policy)
