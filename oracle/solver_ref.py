@@ -1,0 +1,192 @@
+"""CPU reference of HeSP's iterative scheduler-partitioner (section 2.1,
+"Iterative solver"), written from the paper's description.
+
+TEST INFRASTRUCTURE ONLY: used by the test-suite to check the library's solver;
+the product path never imports it.
+
+Every iteration is a schedule stage (an exact simulation of the current
+partition, by the C oracle) followed by a partition stage that changes the
+split depth of one task cluster (a top-level task of Fig. 1 and the fine tasks
+it was split into).  The paper leaves the score and the partition parameter
+open; the reading used here (all integer arithmetic, so that results are exact):
+
+* span(c)   = latest finish - earliest start over the cluster's tasks;
+  t0(c) the earliest start; ptype(c) the processor type that ran the task
+  starting at t0 (smallest scaled key on ties).
+* avail(c)  = P - (number of tasks running at t0) + 1: the processors idle when
+  the cluster started, plus the one it started on ("available parallelism at its
+  scheduling time").
+* For every other depth d' in 0..dmax:
+    work(c,d') = sum over the cluster's tasks at depth d' of their time on ptype(c);
+    par(d')    = max(1, floor(tasks at depth d' / 2^d')), the tasks per step of
+                 the blocked algorithm's outer loop;
+    est(c,d')  = ceil(work / min(avail(c), par(d')));
+    score      = span(c) - est(c,d').
+  The cluster's proposal is the depth with the largest score (smallest depth on
+  ties); it is a candidate when that score is positive.  A smaller depth merges
+  the cluster back (p = 1 relative to the old split), a larger one splits it
+  further (p < 1).
+* Candidate lists: All (every cluster), CP (clusters with a task on the
+  critical path: from the last-finishing task, repeatedly the predecessor -- a
+  DAG predecessor or the previous task on the same processor -- with the latest
+  finish, smallest scaled key on ties), Shallow (clusters whose depth is the
+  smallest present).
+* Selection: Hard, the largest score (smallest cluster index on ties); Soft,
+  u = SplitMix64 draw(seed, 10, iteration) mod (sum of scores), the first
+  candidate in cluster order whose running score sum exceeds u.
+* No candidate: the partition is kept (a fixed point) for the remaining
+  iterations.  The solver returns the best simulated partition (earliest on
+  ties) and the makespan of every iteration.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_1602_05510_amd.inputs import tet
+
+LISTS = {"all": 0, "cp": 1, "shallow": 2}
+_M64 = (1 << 64) - 1
+_GAMMA = 0x9E3779B97F4A7C15
+
+
+def _mix(z: int) -> int:
+    """SplitMix64 finaliser (Steele, Lea and Flood, 2014)."""
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def _draw(seed: int, purpose: int, index: int) -> int:
+    """Value number index+1 of the SplitMix64 sequence started at mix(seed + gamma (purpose+1))."""
+    state = _mix((seed + _GAMMA * (purpose + 1)) & _M64)
+    return _mix((state + _GAMMA * (index + 1)) & _M64)
+SAMPLING = {"hard": 0, "soft": 1}
+
+
+def _fine_counts(kind: int, d: int):
+    """Fine tasks of each kind (chol, trsm, syrk, gemm) in a cluster of `kind` split d times."""
+    s = 1 << d
+    if kind == 3:
+        return [0, 0, 0, s ** 3]
+    if kind == 2:
+        return [0, 0, s * s, s * s * (s - 1) // 2]
+    if kind == 1:
+        return [0, s * s, 0, s * s * (s - 1) // 2]
+    return [s, s * (s - 1) // 2, s * (s - 1) // 2, s * (s - 1) * (s - 2) // 6]
+
+
+def _kind_of_top(nt: int):
+    kinds, cells = [], []
+    for k in range(nt):
+        kinds.append(0); cells.append((k, k, k))
+        for j in range(k + 1, nt):
+            kinds.append(1); cells.append((k, k, j))
+        for i in range(k + 1, nt):
+            for j in range(i + 1, nt):
+                kinds.append(3); cells.append((k, i, j))
+            kinds.append(2); cells.append((k, i, i))
+    return kinds, {c: t for t, c in enumerate(cells)}
+
+
+def partition_step(pf, nt, dmax, b, depth, sched, cost, it, lst, sampling, seed):
+    """One partition stage: returns (cluster, new depth, score) or None."""
+    kinds, index = _kind_of_top(nt)
+    n_top = len(kinds)
+    tasks = np.asarray(sched.tasks)
+    n = len(tasks)
+    level = tasks[:, 1]
+    key = [((int(K) << (dmax - int(l))), (int(I) << (dmax - int(l))), (int(J) << (dmax - int(l))))
+           for (_, l, K, I, J) in tasks]
+    cl = np.array([index[(int(K) >> int(l), int(I) >> int(l), int(J) >> int(l))] for (_, l, K, I, J) in tasks])
+    start, finish, proc = sched.start.astype(np.int64), sched.finish.astype(np.int64), sched.proc
+    P = pf.n_procs
+    span, t0, pt = {}, {}, {}
+    for c in range(n_top):
+        idx = np.nonzero(cl == c)[0]
+        first = min(idx, key=lambda t: (int(start[t]), key[t]))
+        t0[c] = int(start[first])
+        span[c] = int(finish[idx].max()) - t0[c]
+        pt[c] = int(pf.proc_type[proc[first]])
+    # candidate list
+    if lst == 0:
+        cand = list(range(n_top))
+    elif lst == 2:
+        dm = int(min(depth))
+        cand = [c for c in range(n_top) if int(depth[c]) == dm]
+    else:
+        preds = [[] for _ in range(n)]
+        for u, v in sched.edges:
+            preds[int(v)].append(int(u))
+        t = max(range(n), key=lambda x: (int(finish[x]), tuple(-k for k in key[x])))
+        on = set()
+        while True:
+            on.add(int(cl[t]))
+            options = list(preds[t])
+            same = [x for x in range(n) if proc[x] == proc[t] and finish[x] <= start[t] and x != t]
+            if same:
+                options.append(max(same, key=lambda x: (int(finish[x]), tuple(-k for k in key[x]))))
+            if not options:
+                break
+            t = max(options, key=lambda x: (int(finish[x]), tuple(-k for k in key[x])))
+        cand = sorted(on)
+    # proposals
+    best = []
+    for c in cand:
+        running = int(np.sum((start <= t0[c]) & (t0[c] < finish)))
+        avail = P - running + 1
+        top = None
+        for dn in range(dmax + 1):
+            if dn == int(depth[c]):
+                continue
+            cnt = _fine_counts(kinds[c], dn)
+            work = sum(cnt[k] * int(cost[pt[c], k, dn]) for k in range(4))
+            par = max(1, sum(cnt) >> dn)
+            lanes = min(avail, par)
+            est = -(-work // lanes)
+            score = span[c] - est
+            if top is None or score > top[1]:
+                top = (dn, score)
+        if top is not None and top[1] > 0:
+            best.append((c, top[0], top[1]))
+    if not best:
+        return None
+    if sampling == 0:
+        return max(best, key=lambda x: (x[2], -x[0]))
+    total = sum(x[2] for x in best)
+    u = _draw(seed, 10, it) % total
+    acc = 0
+    for x in best:
+        acc += x[2]
+        if acc > u:
+            return x
+    return best[-1]
+
+
+def solve(pf, nt, dmax, b, iters, lst=0, sampling=0, seed=0, policy=(0, 0), depth0=None, cost=None):
+    """Runs the iterative solver; returns (best depth, best makespan, makespans per iteration, steps)."""
+    n_top = tet(nt)
+    depth = np.zeros(n_top, np.uint8) if depth0 is None else np.array(depth0, np.uint8)
+    if cost is None:
+        cost = np.zeros((pf.n_ptypes, 4, dmax + 1), np.int64)
+        for p in range(pf.n_ptypes):
+            for k in range(4):
+                for lv in range(dmax + 1):
+                    cost[p, k, lv] = O.task_time(k, b >> lv, int(pf.rmax[p][k]), int(pf.h[p]))
+    best_d, best_ms, trace, steps = depth.copy(), None, [], []
+    fixed = False
+    for it in range(iters):
+        s = O.simulate(pf, nt, dmax, b, depth, detail=True, policy=policy)
+        trace.append(s.makespan)
+        if best_ms is None or s.makespan < best_ms:
+            best_ms, best_d = s.makespan, depth.copy()
+        if fixed:
+            steps.append(None)
+            continue
+        st = partition_step(pf, nt, dmax, b, depth, s, cost, it, lst, sampling, seed)
+        steps.append(st)
+        if st is None:
+            fixed = True
+        else:
+            depth[st[0]] = st[1]
+    return best_d, best_ms, trace, steps

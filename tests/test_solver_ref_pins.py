@@ -1,0 +1,83 @@
+"""Pins of the CPU reference of the iterative scheduler-partitioner
+(oracle/solver_ref.py; section 2.1, "Iterative solver", with the readings
+stated in that module)."""
+import numpy as np
+
+from oracle import oracle as O
+from oracle import solver_ref as S
+from paper_1602_05510_amd import inputs as I
+
+
+def test_hand_derived_split_and_merge():
+    """Two identical CPUs, one 512 tile, depths 0..1.
+    Depth 0: one chol, 0..1,419,947; span 1,419,947; one processor busy at its
+    start, so 2 - 1 + 1 = 2 available.  Depth 1: 2 chol (185,686) + trsm +
+    syrk (557,056 each) = 1,485,484 of work over min(2, 4 >> 1 = 2) lanes ->
+    742,742; score 1,419,947 - 742,742 = 677,205 > 0: split.  The split cluster
+    is a 4-task chain, 1,485,484 long; merging back estimates 1,419,947 over
+    min(2, 1) lane, score 65,537: merge.  The solver oscillates and keeps the
+    unsplit partition."""
+    pf = I.make_platform([I.ProcType("cpu", 2, 32000, 32000, 64, False)], seed=0)
+    bd, bm, tr, steps = S.solve(pf, 1, 1, 512, 5, 0, 0)
+    assert tr == [1419947, 1485484, 1419947, 1485484, 1419947]
+    assert steps == [(0, 1, 677205), (0, 0, 65537), (0, 1, 677205), (0, 0, 65537), (0, 1, 677205)]
+    assert list(bd) == [0] and bm == 1419947
+
+
+def test_fixed_point_when_no_positive_score():
+    """A CPU and an accelerator, one 512 tile: the chol runs on the accelerator
+    (87,382 after a 184,763 transfer, span 87,382); split, 2 x 27,307 + 2 x
+    81,920 = 218,454 over 2 lanes = 109,227 > 87,382: no candidate."""
+    pf = I.make_platform([I.ProcType("cpu", 1, 32000, 32000, 64, False),
+                          I.ProcType("acc", 1, 1024000, 1024000, 512, True)], seed=0)
+    bd, bm, tr, steps = S.solve(pf, 1, 1, 512, 4, 0, 0)
+    assert tr == [272145] * 4 and steps == [None] * 4 and bm == 272145
+
+
+def test_trace_is_the_simulation_of_each_partition():
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf = w.platform()
+    for lst in (0, 1, 2):
+        bd, bm, tr, steps = S.solve(pf, 6, 2, 1024, 8, lst, 0)
+        dep = np.zeros(I.tet(6), np.uint8)
+        for it in range(8):
+            assert tr[it] == O.simulate(pf, 6, 2, 1024, dep, detail=False)
+            if steps[it] is not None:
+                c, dn, score = steps[it]
+                assert score > 0 and dep[c] != dn and 0 <= dn <= 2
+                if lst == 2:
+                    assert dep[c] == dep.min()          # Shallow: only the shallowest clusters
+                dep[c] = dn
+        assert bm == min(tr)
+        assert O.simulate(pf, 6, 2, 1024, bd, detail=False) == bm
+
+
+def test_soft_sampling_depends_on_the_seed_only():
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf = w.platform()
+    a = S.solve(pf, 6, 2, 1024, 10, 0, 1, seed=5)
+    b = S.solve(pf, 6, 2, 1024, 10, 0, 1, seed=5)
+    c = S.solve(pf, 6, 2, 1024, 10, 0, 1, seed=6)
+    assert a[2] == b[2] and a[3] == b[3]
+    assert a[3] != c[3]
+
+
+def test_splitmix64_published_sequence():
+    """SplitMix64 from state 0 (gamma increments, then the finaliser) gives
+    0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F: the values of
+    the published generator for seed 0."""
+    st = 0
+    out = []
+    for _ in range(3):
+        st = (st + S._GAMMA) & S._M64
+        out.append(S._mix(st))
+    assert out == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_lanes_are_bounded_by_the_outer_loop_width():
+    """Four identical CPUs: all four are available, but the split chol runs at
+    most 4 tasks >> 1 = 2 per outer step, so the estimate stays 742,742 and the
+    score 677,205 (four lanes would give 1,048,576)."""
+    pf = I.make_platform([I.ProcType("cpu", 4, 32000, 32000, 64, False)], seed=0)
+    bd, bm, tr, steps = S.solve(pf, 1, 1, 512, 2, 0, 0)
+    assert steps == [(0, 1, 677205), (0, 0, 65537)]
