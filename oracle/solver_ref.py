@@ -11,8 +11,9 @@ it was split into).  The paper leaves the score and the partition parameter
 open; the reading used here (all integer arithmetic, so that results are exact):
 
 * span(c)   = latest finish - earliest start over the cluster's tasks;
-  t0(c) the earliest start; ptype(c) the processor type that ran the task
-  starting at t0 (smallest scaled key on ties).
+  t0(c) the earliest start; ptype(c) the type of the processor that ran the
+  task starting at t0 (lowest processor index on ties: a processor runs one
+  task at a time, so the pair (start, processor) names one task).
 * avail(c)  = P - (number of tasks running at t0) + 1: the processors idle when
   the cluster started, plus the one it started on ("available parallelism at its
   scheduling time").
@@ -27,9 +28,10 @@ open; the reading used here (all integer arithmetic, so that results are exact):
   the cluster back (p = 1 relative to the old split), a larger one splits it
   further (p < 1).
 * Candidate lists: All (every cluster), CP (clusters with a task on the
-  critical path: from the last-finishing task, repeatedly the predecessor -- a
-  DAG predecessor or the previous task on the same processor -- with the latest
-  finish, smallest scaled key on ties), Shallow (clusters whose depth is the
+  critical path, read on the task DAG with the previous step's times: from the
+  last-finishing task, repeatedly the DAG predecessor that finished last, until
+  a task without predecessors; ties to the lowest processor index, which is
+  unique among tasks finishing together), Shallow (clusters whose depth is the
   smallest present).
 * Selection: Hard, the largest score (smallest cluster index on ties); Soft,
   u = SplitMix64 draw(seed, 10, iteration) mod (sum of scores), the first
@@ -89,28 +91,13 @@ def _kind_of_top(nt: int):
     return kinds, {c: t for t, c in enumerate(cells)}
 
 
-def partition_step(pf, nt, dmax, b, depth, sched, cost, it, lst, sampling, seed):
-    """One partition stage: returns (cluster, new depth, score) or None."""
-    kinds, index = _kind_of_top(nt)
-    n_top = len(kinds)
-    tasks = np.asarray(sched.tasks)
-    n = len(tasks)
-    level = tasks[:, 1]
-    key = [((int(K) << (dmax - int(l))), (int(I) << (dmax - int(l))), (int(J) << (dmax - int(l))))
-           for (_, l, K, I, J) in tasks]
-    cl = np.array([index[(int(K) >> int(l), int(I) >> int(l), int(J) >> int(l))] for (_, l, K, I, J) in tasks])
+def candidates(n_top, depth, sched, cl, lst):
+    """Clusters proposed for a change: All, CP or Shallow (see the module header);
+    cl[t] is the cluster of task t."""
     start, finish, proc = sched.start.astype(np.int64), sched.finish.astype(np.int64), sched.proc
-    P = pf.n_procs
-    span, t0, pt = {}, {}, {}
-    for c in range(n_top):
-        idx = np.nonzero(cl == c)[0]
-        first = min(idx, key=lambda t: (int(start[t]), key[t]))
-        t0[c] = int(start[first])
-        span[c] = int(finish[idx].max()) - t0[c]
-        pt[c] = int(pf.proc_type[proc[first]])
-    # candidate list
+    n = len(start)
     if lst == 0:
-        cand = list(range(n_top))
+        return list(range(n_top))
     elif lst == 2:
         dm = int(min(depth))
         cand = [c for c in range(n_top) if int(depth[c]) == dm]
@@ -118,18 +105,34 @@ def partition_step(pf, nt, dmax, b, depth, sched, cost, it, lst, sampling, seed)
         preds = [[] for _ in range(n)]
         for u, v in sched.edges:
             preds[int(v)].append(int(u))
-        t = max(range(n), key=lambda x: (int(finish[x]), tuple(-k for k in key[x])))
+        last = lambda xs: max(xs, key=lambda x: (int(finish[x]), -int(proc[x])))
+        t = last(range(n))
         on = set()
         while True:
             on.add(int(cl[t]))
-            options = list(preds[t])
-            same = [x for x in range(n) if proc[x] == proc[t] and finish[x] <= start[t] and x != t]
-            if same:
-                options.append(max(same, key=lambda x: (int(finish[x]), tuple(-k for k in key[x]))))
-            if not options:
+            if not preds[t]:
                 break
-            t = max(options, key=lambda x: (int(finish[x]), tuple(-k for k in key[x])))
+            t = last(preds[t])
         cand = sorted(on)
+    return cand
+
+
+def partition_step(pf, nt, dmax, b, depth, sched, cost, it, lst, sampling, seed):
+    """One partition stage: returns (cluster, new depth, score) or None."""
+    kinds, index = _kind_of_top(nt)
+    n_top = len(kinds)
+    tasks = np.asarray(sched.tasks)
+    cl = np.array([index[(int(K) >> int(l), int(I) >> int(l), int(J) >> int(l))] for (_, l, K, I, J) in tasks])
+    start, finish, proc = sched.start.astype(np.int64), sched.finish.astype(np.int64), sched.proc
+    P = pf.n_procs
+    span, t0, pt = {}, {}, {}
+    for c in range(n_top):
+        idx = np.nonzero(cl == c)[0]
+        first = min(idx, key=lambda t: (int(start[t]), int(proc[t])))
+        t0[c] = int(start[first])
+        span[c] = int(finish[idx].max()) - t0[c]
+        pt[c] = int(pf.proc_type[proc[first]])
+    cand = candidates(n_top, depth, sched, cl, lst)
     # proposals
     best = []
     for c in cand:

@@ -81,3 +81,22 @@ def test_lanes_are_bounded_by_the_outer_loop_width():
     pf = I.make_platform([I.ProcType("cpu", 4, 32000, 32000, 64, False)], seed=0)
     bd, bm, tr, steps = S.solve(pf, 1, 1, 512, 2, 0, 0)
     assert steps == [(0, 1, 677205), (0, 0, 65537)]
+
+
+def test_critical_path_follows_the_last_arriving_dependence():
+    """nt = 3 on eight identical CPUs, nothing split.  With chol < trsm = syrk
+    and gemm = 2 syrk, the (1,2) update gemm(0,1,2) (start after both trsm,
+    length 2 t) outlasts chol(1) (after trsm and syrk: c + t + s + c), so the
+    path from chol(2) runs syrk(1,2,2) <- trsm(1,1,2) <- gemm(0,1,2) <- trsm(0,0,1)
+    (both trsm finish together; trsm(0,0,1) was mapped first, to processor 0)
+    <- chol(0): Fig. 1 clusters 9, 8, 7, 3, 1, 0.  Following the earliest
+    predecessor instead would pass through chol(1) (cluster 6)."""
+    pf = I.make_platform([I.ProcType("cpu", 8, 32000, 32000, 64, False)], seed=0)
+    dep = np.zeros(10, np.uint8)
+    s = O.simulate(pf, 3, 0, 512, dep, detail=True)
+    kinds, index = S._kind_of_top(3)
+    cl = [index[(int(K) >> int(l), int(i) >> int(l), int(j) >> int(l))] for (_, l, K, i, j) in s.tasks]
+    assert S.candidates(10, dep, s, cl, 1) == [0, 1, 3, 7, 8, 9]
+    assert S.candidates(10, dep, s, cl, 0) == list(range(10))
+    dep2 = dep.copy(); dep2[[0, 4]] = 1
+    assert S.candidates(10, dep2, s, cl, 2) == [1, 2, 3, 5, 6, 7, 8, 9]
