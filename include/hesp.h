@@ -351,6 +351,54 @@ typedef struct {
 int hesp_search(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy, const hesp_search_params *params,
                 uint8_t *best_depth, int64_t *best_makespan, hesp_trace_point *trace, void *stream);
 
+/* ---- iterative scheduler-partitioner (section 2.1, "Iterative solver") -------
+ * n_chains independent runs, each alternating a schedule stage (the exact
+ * simulation of its current partition, as hesp_simulate_batch) and a partition
+ * stage that changes the split depth of one cluster (top-level task t and the
+ * fine tasks it was split into).  The paper leaves the score open; this reading
+ * is exact integer arithmetic on the stage's schedule:
+ *   span(t) = latest finish - earliest start t0 over the cluster's tasks;
+ *   ptype   = type of the processor of the cluster's earliest task (lowest
+ *             processor index on ties);
+ *   avail   = n_procs - (tasks with start <= t0 < finish) + 1;
+ *   for every other depth d' in 0..dmax: work = sum of the task times on ptype of
+ *   the cluster's tasks at depth d', width = max(1, their count >> d'),
+ *   estimate = ceil(work / min(avail, width)), score = span - estimate.
+ * A cluster proposes its best-scoring other depth (the smallest on ties) when
+ * that score is positive (a smaller depth merges it back, a larger one splits
+ * it).  Candidate clusters: ALL; CP, those with a task on the critical path (from
+ * the last-finishing task, repeatedly the DAG predecessor that finished last;
+ * ties to the lowest processor index); SHALLOW, those of the smallest depth
+ * present.  HARD takes the largest score (smallest cluster index on ties); SOFT
+ * draws u = SplitMix64 draw(seed + r, 10, iteration) mod (sum of scores) for
+ * chain r and takes the first candidate, in cluster order, whose running score
+ * sum exceeds u.  Without a candidate the partition stays (a fixed point).
+ * d_depth [n_chains][tet(nt)] (device) holds the initial partitions and gets the
+ * last ones; d_best_depth / d_best_makespan get each chain's best simulated
+ * partition (earliest on ties); d_trace [n_chains][iters] (nullable) every
+ * iteration's makespan; d_steps [n_chains][iters][3] (nullable) the change made
+ * (cluster, new depth, score; cluster -1 when none).  A chain whose simulation
+ * fails (a depth above dmax, or above a fixed-capacity plan) gets -1 in its
+ * trace and keeps makespan -1 if it never succeeded.  Limits: tet(nt) <= 4096,
+ * n_procs <= 64.  Device workspace is allocated per call (n_chains x
+ * tet(nt 2^dmax) tasks); the call synchronises `stream` before it returns. */
+#define HESP_LIST_ALL 0
+#define HESP_LIST_CP 1
+#define HESP_LIST_SHALLOW 2
+#define HESP_SAMPLE_HARD 0
+#define HESP_SAMPLE_SOFT 1
+typedef struct {
+  int32_t n_chains;
+  int32_t nt, dmax;
+  int32_t iters;
+  int32_t list;                /* HESP_LIST_* */
+  int32_t sampling;            /* HESP_SAMPLE_* */
+  uint64_t seed;
+} hesp_solve_params;
+int hesp_solve(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy, const hesp_solve_params *params,
+               uint8_t *d_depth, uint8_t *d_best_depth, int64_t *d_best_makespan, int64_t *d_trace,
+               int64_t *d_steps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,426 @@
+// hesp_solve.hip -- the partition stage of the iterative scheduler-partitioner
+// (section 2.1, "Iterative solver") on gfx950, for many independent chains.
+//
+// One iteration of every chain: the batched simulation (hesp_simulate_batch)
+// gives the schedule of the chain's current partition; then
+//   k_sv_first   one workgroup per chain: first fine task of every top-level
+//                task (a "cluster": the task of Fig. 1 and the fine tasks it was
+//                split into), cluster bounds reset;
+//   k_sv_tasks   one lane per fine task: cluster start/finish bounds (atomics),
+//                the DAG predecessor that finished last, the chain's last task;
+//   k_sv_part    one workgroup per chain: tasks running at every cluster's
+//                start, the proposal of every candidate cluster (the other depth
+//                with the largest score span - estimated time), the candidate
+//                list (All / CP / Shallow), the Hard or Soft choice, the update.
+// Scores and estimates are integers (nanoseconds), so every chain follows the
+// same trajectory as an exact sequential implementation.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hesp_core.h"
+#include "hesp_solve.h"
+
+namespace hesp {
+namespace solve {
+
+namespace {
+
+constexpr int kPartThreads = 1024;
+constexpr int kPerThread = kMaxTop / kPartThreads;   // clusters owned by one thread
+constexpr int kTile = 1024;                          // tasks staged in LDS at a time
+
+__device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// SplitMix64 (Steele, Lea, Flood 2014): value idx+1 of the sequence that starts
+// at mix(seed + gamma (purpose + 1))
+__device__ __forceinline__ uint64_t sm_draw(uint64_t seed, uint64_t purpose, uint64_t idx) {
+  const uint64_t g = 0x9E3779B97F4A7C15ull;
+  return sm_mix(sm_mix(seed + g * (purpose + 1)) + g * (idx + 1));
+}
+
+// fine tasks of each kind (chol, trsm, syrk, gemm) in a cluster of `kind` split d times
+__device__ __forceinline__ void kind_counts(int kind, int d, int64_t* n) {
+  const int64_t s = 1 << d;
+  n[0] = n[1] = n[2] = n[3] = 0;
+  if (kind == CHOL) {
+    n[0] = s; n[1] = s * (s - 1) / 2; n[2] = s * (s - 1) / 2; n[3] = s * (s - 1) * (s - 2) / 6;
+  } else if (kind == TRSM) {
+    n[1] = s * s; n[3] = s * s * (s - 1) / 2;
+  } else if (kind == SYRK) {
+    n[2] = s * s; n[3] = s * s * (s - 1) / 2;
+  } else {
+    n[3] = s * s * s;
+  }
+}
+
+// packed (time, processor) keys: a processor runs one task at a time, so the
+// pair names one task.  Start keys order by start, then lower processor; finish
+// keys order by finish, then lower processor (the larger key wins).
+__device__ __forceinline__ uint64_t start_key(int64_t t, int p) { return ((uint64_t)t << 6) | (uint64_t)p; }
+__device__ __forceinline__ uint64_t finish_key(int64_t t, int p) {
+  return ((uint64_t)t << 6) | (uint64_t)(kMaxP - 1 - p);
+}
+
+// ---------------------------------------------------------------- per chain: first tasks
+
+__global__ void __launch_bounds__(256) k_sv_first(SolveView v) {
+  __shared__ int s_part[256 / 64];
+  __shared__ int s_carry;
+  const int r = blockIdx.x;
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const uint8_t* depth = v.depth + (int64_t)r * v.n_top;
+  uint32_t* first = v.first + (int64_t)r * (v.n_top + 1);
+  uint64_t* t0key = v.t0key + (int64_t)r * v.n_top;
+  uint64_t* fin = v.fin + (int64_t)r * v.n_top;
+  if (tid == 0) {
+    s_carry = 0;
+    v.lastkey[r] = 0;
+  }
+  __syncthreads();
+  for (int base = 0; base < v.n_top; base += 256) {
+    const int t = base + tid;
+    int cnt = 0;
+    if (t < v.n_top) {
+      const uint32_t c = top_cell(v.nt, t);
+      int d = depth[t];
+      d = d > v.dmax ? v.dmax : d;
+      cnt = fine_count(kind_of(cell_k(c), cell_i(c), cell_j(c)), d);
+      t0key[t] = ~0ull;
+      fin[t] = 0;
+    }
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (l >= o) incl += y;
+    }
+    if (l == 63) s_part[w] = incl;
+    __syncthreads();
+    int pre = s_carry;
+    for (int q = 0; q < w; q++) pre += s_part[q];
+    if (t < v.n_top) first[t] = (uint32_t)(pre + incl - cnt);
+    __syncthreads();
+    if (tid == 0) {
+      int s = 0;
+      for (int q = 0; q < 256 / 64; q++) s += s_part[q];
+      s_carry += s;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) first[v.n_top] = (uint32_t)s_carry;
+}
+
+// ---------------------------------------------------------------- per task
+
+__global__ void __launch_bounds__(256) k_sv_tasks(SolveView v) {
+  const int r = blockIdx.y;
+  if (v.status[r] != 0) return;
+  const int64_t o = v.sched_off[r];
+  const int64_t n = v.sched_off[r + 1] - o;
+  const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (f >= n) return;
+  const uint8_t* depth = v.depth + (int64_t)r * v.n_top;
+  const uint32_t* first = v.first + (int64_t)r * (v.n_top + 1);
+  // cluster of f: the last top-level task whose first fine task is <= f
+  int lo = 0, hi = v.n_top - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)first[mid] <= f) lo = mid; else hi = mid - 1;
+  }
+  const int t = lo;
+  const uint32_t cell = top_cell(v.nt, t);
+  const int d = depth[t];
+  const int s = 1 << d;
+  const int kind = kind_of(cell_k(cell), cell_i(cell), cell_j(cell));
+  int q, rr, cc;
+  local_coords(kind, s, (int)(f - first[t]), q, rr, cc);
+  const int K = cell_k(cell) * s + q, I = cell_i(cell) * s + rr, J = cell_j(cell) * s + cc;
+
+  const int p = v.proc[o + f];
+  const int64_t st = v.start[o + f], fi = v.finish[o + f];
+  atomicMin((unsigned long long*)&v.t0key[(int64_t)r * v.n_top + t], (unsigned long long)start_key(st, p));
+  atomicMax((unsigned long long*)&v.fin[(int64_t)r * v.n_top + t], (unsigned long long)fi);
+  atomicMax((unsigned long long*)&v.lastkey[r], (unsigned long long)finish_key(fi, p));
+
+  uint64_t best = 0;
+  int32_t bid = -1;
+  auto depth_of = [&](int64_t x) { return (int)depth[x]; };
+  auto first_of = [&](int64_t x) { return (int64_t)first[x]; };
+  for_each_pred(v.nt, depth_of, first_of, (int64_t)t, cell, d, K, I, J, [&](int64_t u) {
+    const uint64_t k = finish_key(v.finish[o + u], v.proc[o + u]);
+    if (bid < 0 || k > best) {
+      best = k;
+      bid = (int32_t)u;
+    }
+  });
+  v.par[o + f] = bid;
+  v.cl[o + f] = t;
+}
+
+// ---------------------------------------------------------------- per chain: partition stage
+
+__device__ __forceinline__ uint64_t block_max_u64(uint64_t x, uint64_t* s_red) {
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint64_t y = __shfl_xor(x, o, 64);
+    x = y > x ? y : x;
+  }
+  __syncthreads();
+  if (l == 0) s_red[w] = x;
+  __syncthreads();
+  uint64_t m = 0;
+  for (int q = 0; q < kPartThreads / 64; q++) m = s_red[q] > m ? s_red[q] : m;
+  return m;
+}
+
+__global__ void __launch_bounds__(kPartThreads) k_sv_part(SolveView v, SolveTables tb) {
+  __shared__ int64_t s_st[kTile];
+  __shared__ int64_t s_fi[kTile];
+  __shared__ int64_t s_red[kPartThreads / 64];
+  __shared__ uint32_t s_cp[kMaxTop / 32];
+  __shared__ int32_t s_last;
+  __shared__ int64_t s_pick[3];
+
+  const int r = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int it = v.iter;
+  const int n_top = v.n_top;
+  uint8_t* depth = v.depth + (int64_t)r * n_top;
+  int64_t* trace = v.trace ? v.trace + (int64_t)r * v.iters : nullptr;
+  int64_t* steps = v.steps ? v.steps + ((int64_t)r * v.iters + it) * 3 : nullptr;
+  if (v.status[r] != 0) {
+    if (tid == 0) {
+      if (trace) trace[it] = -1;
+      if (steps) { steps[0] = -1; steps[1] = -1; steps[2] = 0; }
+    }
+    return;
+  }
+  const int64_t ms = v.makespan[r];
+  // best partition so far (the earliest on ties): taken before the update
+  const bool better = it == 0 || ms < v.best_ms[r];
+  __syncthreads();
+  if (better) {
+    uint8_t* bd = v.best_depth + (int64_t)r * n_top;
+    for (int t = tid; t < n_top; t += kPartThreads) bd[t] = depth[t];
+  }
+  if (tid == 0) {
+    if (trace) trace[it] = ms;
+    if (better) v.best_ms[r] = ms;
+  }
+
+  // clusters tid * kPerThread + j, in Fig. 1 order along the threads
+  int64_t t0[kPerThread], span[kPerThread];
+  int run[kPerThread], pt[kPerThread];
+  const int c0 = tid * kPerThread;
+  for (int j = 0; j < kPerThread; j++) {
+    const int c = c0 + j;
+    t0[j] = INT64_MAX;
+    span[j] = 0;
+    run[j] = 0;
+    pt[j] = 0;
+    if (c < n_top) {
+      const uint64_t k = v.t0key[(int64_t)r * n_top + c];
+      t0[j] = (int64_t)(k >> 6);
+      span[j] = (int64_t)v.fin[(int64_t)r * n_top + c] - t0[j];
+      pt[j] = tb.proc_type[(int)(k & 63)];
+    }
+  }
+  for (int q = tid; q < kMaxTop / 32; q += kPartThreads) s_cp[q] = 0;
+  if (tid == 0) s_last = -1;
+  const uint64_t lastkey = v.lastkey[r];
+
+  // tasks running at every cluster's start: start <= t0 < finish
+  const int64_t o = v.sched_off[r];
+  const int64_t n = v.sched_off[r + 1] - o;
+  for (int64_t base = 0; base < n; base += kTile) {
+    __syncthreads();
+    const int64_t f = base + tid;
+    if (f < n) {
+      const int64_t st = v.start[o + f], fi = v.finish[o + f];
+      s_st[tid] = st;
+      s_fi[tid] = fi;
+      if (finish_key(fi, v.proc[o + f]) == lastkey) s_last = (int32_t)f;
+    }
+    __syncthreads();
+    const int m = (int)(n - base < kTile ? n - base : kTile);
+    for (int x = 0; x < m; x++) {
+      const int64_t st = s_st[x], fi = s_fi[x];
+      for (int j = 0; j < kPerThread; j++) run[j] += (st <= t0[j]) & (t0[j] < fi);
+    }
+  }
+  __syncthreads();
+
+  // candidate list
+  int dmin = 255;
+  for (int j = 0; j < kPerThread; j++)
+    if (c0 + j < n_top) dmin = min(dmin, (int)depth[c0 + j]);
+  const int64_t shallow = -block_max_u64((uint64_t)(255 - dmin), (uint64_t*)s_red) + 255;
+  if (v.list == 1 && tid == 0) {
+    // critical path: from the last-finishing task along the latest-finishing
+    // DAG predecessors (at most n steps)
+    int32_t x = s_last;
+    for (int64_t guard = 0; x >= 0 && guard < n; guard++) {
+      const int c = v.cl[o + x];
+      s_cp[c >> 5] |= 1u << (c & 31);
+      x = v.par[o + x];
+    }
+  }
+  __syncthreads();
+
+  // proposals: the other depth with the largest score (the smallest on ties)
+  int64_t score[kPerThread];
+  int dnew[kPerThread];
+  for (int j = 0; j < kPerThread; j++) {
+    const int c = c0 + j;
+    score[j] = 0;
+    dnew[j] = -1;
+    if (c >= n_top) continue;
+    const int dc = depth[c];
+    bool in = true;
+    if (v.list == 1) in = (s_cp[c >> 5] >> (c & 31)) & 1u;
+    if (v.list == 2) in = dc == (int)shallow;
+    if (!in) continue;
+    const uint32_t cell = top_cell(v.nt, c);
+    const int kind = kind_of(cell_k(cell), cell_i(cell), cell_j(cell));
+    const int64_t avail = (int64_t)tb.n_procs - run[j] + 1;
+    bool have = false;
+    int64_t top = 0;
+    int td = -1;
+    for (int dn = 0; dn <= v.dmax; dn++) {
+      if (dn == dc) continue;
+      int64_t cnt[4];
+      kind_counts(kind, dn, cnt);
+      int64_t work = 0;
+      for (int k = 0; k < 4; k++) work += cnt[k] * tb.cost[pt[j]][k][dn];
+      int64_t par = (cnt[0] + cnt[1] + cnt[2] + cnt[3]) >> dn;
+      par = par < 1 ? 1 : par;
+      const int64_t lanes = avail < par ? avail : par;
+      const int64_t est = (work + lanes - 1) / lanes;
+      const int64_t sc = span[j] - est;
+      if (!have || sc > top) {
+        have = true;
+        top = sc;
+        td = dn;
+      }
+    }
+    if (have && top > 0) {
+      score[j] = top;
+      dnew[j] = td;
+    }
+  }
+
+  // selection
+  if (tid == 0) { s_pick[0] = -1; s_pick[1] = -1; s_pick[2] = 0; }
+  if (v.sampling == 0) {
+    uint64_t key = 0;   // score << 12 | (kMaxTop - 1 - cluster): largest score, then smallest cluster
+    for (int j = 0; j < kPerThread; j++)
+      if (dnew[j] >= 0) {
+        const uint64_t k = ((uint64_t)score[j] << 12) | (uint64_t)(kMaxTop - 1 - (c0 + j));
+        key = k > key ? k : key;
+      }
+    const uint64_t bestk = block_max_u64(key, (uint64_t*)s_red);
+    if (bestk != 0) {
+      const int c = kMaxTop - 1 - (int)(bestk & (kMaxTop - 1));
+      if (c >= c0 && c < c0 + kPerThread) {
+        s_pick[0] = c;
+        s_pick[1] = dnew[c - c0];
+        s_pick[2] = score[c - c0];
+      }
+    }
+  } else {
+    int64_t mine = 0;
+    for (int j = 0; j < kPerThread; j++) mine += score[j];
+    // exclusive prefix of the score sums in cluster order
+    const int l = tid & 63, w = tid >> 6;
+    int64_t incl = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(incl, off, 64);
+      if (l >= off) incl += y;
+    }
+    __syncthreads();
+    if (l == 63) s_red[w] = incl;
+    __syncthreads();
+    int64_t pre = 0, total = 0;
+    for (int q = 0; q < kPartThreads / 64; q++) {
+      if (q < w) pre += s_red[q];
+      total += s_red[q];
+    }
+    pre += incl - mine;
+    if (total > 0) {
+      const int64_t u = (int64_t)(sm_draw(v.seed + (uint64_t)r, 10, (uint64_t)it) % (uint64_t)total);
+      int64_t acc = pre;
+      for (int j = 0; j < kPerThread; j++) {
+        if (dnew[j] < 0) continue;
+        if (acc <= u && u < acc + score[j]) {
+          s_pick[0] = c0 + j;
+          s_pick[1] = dnew[j];
+          s_pick[2] = score[j];
+        }
+        acc += score[j];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (steps) { steps[0] = s_pick[0]; steps[1] = s_pick[1]; steps[2] = s_pick[2]; }
+    if (s_pick[0] >= 0) depth[s_pick[0]] = (uint8_t)s_pick[1];
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_sv_offsets(const int32_t* n, int32_t count, int64_t* off) {
+  __shared__ int64_t s_part[16];
+  __shared__ int64_t s_carry;
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  if (tid == 0) { s_carry = 0; off[0] = 0; }
+  __syncthreads();
+  for (int base = 0; base < count; base += 1024) {
+    const int c = base + tid;
+    const int64_t x = c < count ? n[c] : 0;
+    int64_t incl = x;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t y = __shfl_up(incl, o, 64);
+      if (l >= o) incl += y;
+    }
+    if (l == 63) s_part[w] = incl;
+    __syncthreads();
+    int64_t pre = s_carry;
+    for (int q = 0; q < w; q++) pre += s_part[q];
+    if (c < count) off[c + 1] = pre + incl;
+    __syncthreads();
+    if (tid == 0) {
+      int64_t s = 0;
+      for (int q = 0; q < 16; q++) s += s_part[q];
+      s_carry += s;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_offsets(const int32_t* n, int32_t count, int64_t* off, hipStream_t s) {
+  hipLaunchKernelGGL(k_sv_offsets, dim3(1), dim3(1024), 0, s, n, count, off);
+  return hipGetLastError();
+}
+
+hipError_t launch_first(const SolveView& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_sv_first, dim3(v.n_chains), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_tasks(const SolveView& v, int64_t max_tasks, hipStream_t s) {
+  const int64_t nb = (max_tasks + 255) / 256;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sv_tasks, dim3((unsigned)nb, v.n_chains), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_part(const SolveView& v, const SolveTables& t, hipStream_t s) {
+  hipLaunchKernelGGL(k_sv_part, dim3(v.n_chains), dim3(kPartThreads), 0, s, v, t);
+  return hipGetLastError();
+}
+
+}  // namespace solve
+}  // namespace hesp

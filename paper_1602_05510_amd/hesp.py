@@ -68,6 +68,16 @@ class SearchParams(ctypes.Structure):
                 ("train_batch", i32), ("lr", ctypes.c_float), ("replay", i64)]
 
 
+# iterative solver (section 2.1): candidate lists and final selection
+LIST_ALL, LIST_CP, LIST_SHALLOW = 0, 1, 2
+SAMPLE_HARD, SAMPLE_SOFT = 0, 1
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("n_chains", i32), ("nt", i32), ("dmax", i32), ("iters", i32), ("list", i32), ("sampling", i32),
+                ("seed", u64)]
+
+
 class TracePoint(ctypes.Structure):
     _fields_ = [("wall_ms", ctypes.c_double), ("best_makespan", i64), ("simulated", i64), ("proposed", i64)]
 
@@ -123,6 +133,7 @@ def lib():
             "hesp_topk_score": [P, i32, i32, P, P, i64, P],
             "hesp_search": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(SearchParams), P,
                             ctypes.POINTER(i64), P, P],
+            "hesp_solve": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(SolveParams), P, P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -453,3 +464,24 @@ def search(plan: Plan, pf: Platform, nt: int, dmax: int, mode: int, rounds: int,
     tr = [{"wall_ms": t.wall_ms, "best_makespan": t.best_makespan, "simulated": t.simulated,
            "proposed": t.proposed} for t in trace]
     return best, int(best_ms.value), tr
+
+
+def solve(plan: Plan, pf: Platform, nt: int, dmax: int, depth, iters: int, lst: int = LIST_ALL,
+          sampling: int = SAMPLE_HARD, seed: int = 0, policy=(0, 0, 0), stream=None):
+    """Runs hesp_solve on the chains whose initial partitions are the rows of
+    `depth` (uint8 device tensor [n_chains, tet(nt)], updated in place to the last
+    partitions); returns (best depths, best makespans, makespan per iteration,
+    steps [n_chains, iters, 3] = (cluster, new depth, score))."""
+    import torch
+    n_top = nt * (nt + 1) * (nt + 2) // 6
+    if depth.dtype != torch.uint8 or depth.dim() != 2 or depth.shape[1] != n_top or not depth.is_contiguous():
+        raise ValueError("depth must be a contiguous uint8 tensor [n_chains, tet(nt)]")
+    B = int(depth.shape[0])
+    best = torch.empty_like(depth)
+    best_ms = torch.empty(B, dtype=torch.int64, device=depth.device)
+    trace = torch.empty((B, iters), dtype=torch.int64, device=depth.device)
+    steps = torch.empty((B, iters, 3), dtype=torch.int64, device=depth.device)
+    sp = SolveParams(B, nt, dmax, iters, lst, sampling, seed)
+    _check("hesp_solve", lib().hesp_solve(plan.h, ctypes.byref(pf.c), Policy(*policy), ctypes.byref(sp), _dev(depth),
+                                          _dev(best), _dev(best_ms), _dev(trace), _dev(steps), _stream(stream)))
+    return best, best_ms, trace, steps

@@ -187,3 +187,20 @@ def test_unsupported_policies_rejected_before_device_work():
         rc = H.lib().hesp_simulate_batch(ctypes.c_void_p(1), ctypes.byref(pf.c), H.Policy(*pol), ctypes.byref(b),
                                          ctypes.byref(out), None)
         assert rc == H.HESP_EUNSUPPORTED, pol
+
+
+def test_solve_argument_errors_need_no_gpu():
+    w = I.WORKLOADS["chol4x4_b512_d1"]
+    pf = H.Platform.from_inputs(w.platform(), w.b, w.dmax)
+    fake = ctypes.c_void_p(1)          # never dereferenced: every check runs first
+    def call(sp, plan=fake):
+        return H.lib().hesp_solve(plan, ctypes.byref(pf.c), H.Policy(0, 0, 0), ctypes.byref(sp), fake, fake, fake,
+                                  None, None, None)
+    assert call(H.SolveParams(1, 4, 1, 4, 0, 0, 0), plan=None) == H.HESP_EINVAL
+    assert call(H.SolveParams(0, 4, 1, 4, 0, 0, 0)) == H.HESP_EINVAL            # no chains
+    assert call(H.SolveParams(1, 4, 1, 0, 0, 0, 0)) == H.HESP_EINVAL            # no iterations
+    assert call(H.SolveParams(1, 4, 1, 4, 3, 0, 0)) == H.HESP_EINVAL            # no such list
+    assert call(H.SolveParams(1, 4, 1, 4, 0, 2, 0)) == H.HESP_EINVAL            # no such sampling
+    assert call(H.SolveParams(1, 4, 2, 4, 0, 0, 0)) == H.HESP_EINVAL            # dmax above the tables
+    assert call(H.SolveParams(1, 29, 0, 4, 0, 0, 0)) == H.HESP_EUNSUPPORTED     # tet(29) > 4096 clusters
+    assert "hesp_solve" in H.lib().hesp_last_error().decode()
