@@ -339,6 +339,94 @@ def run_policy_sweep(args, torch, H):
     print(json.dumps(rec), flush=True)
 
 
+# ----------------------------------------------------------------------- iterative solver
+
+LIST_NAMES = {0: "All", 1: "CP", 2: "Shallow"}
+SAMPLING_NAMES = {0: "Hard", 1: "Soft"}
+
+
+def run_solver(args, torch, H):
+    """The iterative scheduler-partitioner (section 2.1) on the 16x16 instance:
+    many independent chains (one unsplit, the others from random initial
+    partitions), each iteration an exact simulation of every
+    chain plus one partition change.  value = chain-iterations per second of the
+    All/Soft configuration; the other list x sampling pairs are reported for
+    quality; the CPU reference is timed on one chain and its trajectory compared."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    nt, dmax, b = w.nt, w.dmax, w.b
+    B, iters, seed = args.solve_chains, args.solve_iters, args.solve_seed
+    n_top = I.tet(nt)
+    pf_in = w.platform()
+    pf = H.Platform.from_inputs(pf_in, b, dmax)
+    init = I.uniform_batch(seed, B, nt, b, dmax, 1, 4).depth.reshape(B, n_top).copy()
+    init[0] = 0                     # chain 0 starts unsplit, the others from random partitions
+    d0 = torch.from_numpy(init).cuda()
+    plan = H.Plan()
+    # uniform partitions for reference (not chains: a chain split everywhere would
+    # hold every iteration back by its length)
+    homog = {}
+    for d in range(dmax + 1):
+        ms1 = torch.empty(1, dtype=torch.int64, device="cuda")
+        st1 = torch.empty(1, dtype=torch.int32, device="cuda")
+        db = H.DeviceBatch(1, nt, dmax, torch.full((n_top,), d, dtype=torch.uint8, device="cuda"))
+        H.simulate_batch(plan, pf, db, ms1, st1)
+        homog[f"depth{d}"] = int(ms1.item())
+
+    def once(lst, samp):
+        d = d0.clone()
+        out = H.solve(plan, pf, nt, dmax, d, iters, lst, samp, seed)
+        torch.cuda.synchronize()
+        return out
+
+    for _ in range(args.warmup):
+        once(0, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        best, best_ms, trace, steps = once(0, 1)
+    dt = time.perf_counter() - t0
+    value = B * iters * args.steps / dt
+    print(f"solver All/Soft: {B} chains x {iters} iterations, {1e3 * dt / args.steps:.1f} ms per call",
+          file=sys.stderr, flush=True)
+
+    quality = []
+    for lst in (0, 1, 2):
+        for samp in (0, 1):
+            bd, bm, tr, st = (x.cpu().numpy() for x in once(lst, samp))
+            moved = (st[:, :, 0] >= 0).sum(axis=1)
+            quality.append({"list": LIST_NAMES[lst], "sampling": SAMPLING_NAMES[samp],
+                            "best_makespan": int(bm.min()), "best_chain": int(bm.argmin()),
+                            "mean_best_over_initial": float(np.mean(bm / tr[:, 0])),
+                            "chains_improved": int((bm < tr[:, 0]).sum()),
+                            "mean_changes": float(moved.mean())})
+    tr0 = trace.cpu().numpy()
+
+    cpu = None
+    exact = None
+    if not args.no_cpu_baseline:
+        from oracle import solver_ref as S
+        r = min(B - 1, 3)
+        t1 = time.perf_counter()
+        S.solve(pf_in, nt, dmax, b, 1, 0, 1, seed + r, depth0=init[r])
+        one = time.perf_counter() - t1
+        k = int(max(1, min(iters, args.cpu_budget / max(one, 1e-6))))
+        t1 = time.perf_counter()
+        _, _, want, _ = S.solve(pf_in, nt, dmax, b, k, 0, 1, seed + r, depth0=init[r])
+        t_cpu = time.perf_counter() - t1
+        exact = list(tr0[r, :k]) == want
+        cpu = {"value": k / t_cpu, "unit": "chain-iterations/s", "cores": 1, "kind": "oracle",
+               "sample": f"chain {r}, {k} iterations of All/Soft (one exact simulation + partition stage each)"}
+
+    rec = {"metric": "iterative solver throughput (All/Soft)", "value": value, "unit": "chain-iterations/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"{w.name} iterative solver", "nt": nt, "b": b, "dmax": dmax, "chains": B,
+                      "iterations": iters, "seed": seed, "parallelism": "none (1 GPU)"},
+           "cpu_baseline": cpu, "bit_exact_vs_oracle": exact,
+           "homogeneous_makespans": homog, "quality": quality}
+    print(json.dumps(rec), flush=True)
+
+
 # ----------------------------------------------------------------------- main
 
 def main():
@@ -369,6 +457,9 @@ def main():
     ap.add_argument("--sweep-n", type=int, default=16384)
     ap.add_argument("--sweep-nt", type=int, nargs="+", default=[2, 4, 8, 16, 32, 64])
     ap.add_argument("--sweep-seed", type=int, default=1)
+    ap.add_argument("--solve-chains", type=int, default=16384)
+    ap.add_argument("--solve-iters", type=int, default=16)
+    ap.add_argument("--solve-seed", type=int, default=7)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -389,6 +480,8 @@ def main():
         return run_search(args, torch, H)
     if args.workload == "policy_sweep":
         return run_policy_sweep(args, torch, H)
+    if args.workload == "iterative_solver":
+        return run_solver(args, torch, H)
     w = I.WORKLOADS[args.workload]
     n = args.n_cand or w.n_cand
     pf_in = w.platform()

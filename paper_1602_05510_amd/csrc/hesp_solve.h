@@ -27,8 +27,9 @@ struct SolveView {
   int64_t* best_ms;              // [n_chains]
   int64_t* trace;                // [n_chains][iters] or null
   int64_t* steps;                // [n_chains][iters][3] or null
-  // schedule of the current partitions
-  const int64_t* sched_off;      // [n_chains + 1]
+  // schedule of the current partitions: chain r's tasks at r * stride
+  int64_t stride;
+  const int32_t* n_tasks;        // [n_chains]
   const int32_t* proc;
   const int64_t* start;
   const int64_t* finish;
@@ -43,8 +44,8 @@ struct SolveView {
   uint64_t* lastkey;             // [n_chains]: latest (finish, lowest processor)
 };
 
-// off[0] = 0, off[c + 1] = off[c] + n[c]
-hipError_t launch_offsets(const int32_t* n, int32_t count, int64_t* off, hipStream_t s);
+// off[c] = c * stride for c = 0..count
+hipError_t launch_strided(int64_t stride, int32_t count, int64_t* off, hipStream_t s);
 hipError_t launch_first(const SolveView& v, hipStream_t s);
 hipError_t launch_tasks(const SolveView& v, int64_t max_tasks, hipStream_t s);
 hipError_t launch_part(const SolveView& v, const SolveTables& t, hipStream_t s);

@@ -27,7 +27,6 @@ namespace {
 
 constexpr int kPartThreads = 1024;
 constexpr int kPerThread = kMaxTop / kPartThreads;   // clusters owned by one thread
-constexpr int kTile = 1024;                          // tasks staged in LDS at a time
 
 __device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -117,8 +116,8 @@ __global__ void __launch_bounds__(256) k_sv_first(SolveView v) {
 __global__ void __launch_bounds__(256) k_sv_tasks(SolveView v) {
   const int r = blockIdx.y;
   if (v.status[r] != 0) return;
-  const int64_t o = v.sched_off[r];
-  const int64_t n = v.sched_off[r + 1] - o;
+  const int64_t o = (int64_t)r * v.stride;
+  const int64_t n = v.n_tasks[r];
   const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (f >= n) return;
   const uint8_t* depth = v.depth + (int64_t)r * v.n_top;
@@ -176,8 +175,9 @@ __device__ __forceinline__ uint64_t block_max_u64(uint64_t x, uint64_t* s_red) {
 }
 
 __global__ void __launch_bounds__(kPartThreads) k_sv_part(SolveView v, SolveTables tb) {
-  __shared__ int64_t s_st[kTile];
-  __shared__ int64_t s_fi[kTile];
+  __shared__ int64_t s_q[kMaxTop];        // cluster start times, sorted
+  __shared__ int16_t s_qc[kMaxTop];       // their clusters
+  __shared__ int32_t s_diff[kMaxTop + 1]; // running-count differences over the sorted starts
   __shared__ int64_t s_red[kPartThreads / 64];
   __shared__ uint32_t s_cp[kMaxTop / 32];
   __shared__ int32_t s_last;
@@ -231,24 +231,89 @@ __global__ void __launch_bounds__(kPartThreads) k_sv_part(SolveView v, SolveTabl
   if (tid == 0) s_last = -1;
   const uint64_t lastkey = v.lastkey[r];
 
-  // tasks running at every cluster's start: start <= t0 < finish
-  const int64_t o = v.sched_off[r];
-  const int64_t n = v.sched_off[r + 1] - o;
-  for (int64_t base = 0; base < n; base += kTile) {
-    __syncthreads();
-    const int64_t f = base + tid;
-    if (f < n) {
-      const int64_t st = v.start[o + f], fi = v.finish[o + f];
-      s_st[tid] = st;
-      s_fi[tid] = fi;
-      if (finish_key(fi, v.proc[o + f]) == lastkey) s_last = (int32_t)f;
+  // tasks running at every cluster's start (start <= t0 < finish): the starts
+  // are sorted; a task adds one over the sorted range [first t0 >= its start,
+  // first t0 >= its finish), recorded as two differences
+  int q2 = 1;
+  while (q2 < n_top) q2 <<= 1;
+  for (int j = 0; j < kPerThread; j++) {
+    const int c = c0 + j;
+    if (c < q2) {
+      s_q[c] = t0[j];
+      s_qc[c] = (int16_t)c;
+    }
+  }
+  for (int i = tid; i <= q2; i += kPartThreads) s_diff[i] = 0;
+  __syncthreads();
+  for (int k = 2; k <= q2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < q2; i += kPartThreads) {
+        const int x = i ^ j;
+        if (x > i) {
+          const int64_t a = s_q[i], b = s_q[x];
+          const int ca = s_qc[i], cb = s_qc[x];
+          const bool gt = a > b || (a == b && ca > cb);
+          if (((i & k) == 0) == gt) {
+            s_q[i] = b; s_q[x] = a;
+            s_qc[i] = (int16_t)cb; s_qc[x] = (int16_t)ca;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  const int64_t o = (int64_t)r * v.stride;
+  const int64_t n = v.n_tasks[r];
+  auto lower = [&](int64_t t) {          // first sorted position with s_q >= t
+    int lo = 0, hi = q2;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_q[mid] < t) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  for (int64_t f = tid; f < n; f += kPartThreads) {
+    const int64_t st = v.start[o + f], fi = v.finish[o + f];
+    if (finish_key(fi, v.proc[o + f]) == lastkey) s_last = (int32_t)f;
+    const int a = lower(st), b = lower(fi);
+    if (a < b) {
+      atomicAdd(&s_diff[a], 1);
+      atomicAdd(&s_diff[b], -1);
+    }
+  }
+  __syncthreads();
+  {
+    // inclusive scan of the differences: thread tid owns sorted positions tid*4 .. tid*4+3
+    int loc[kPerThread], sum = 0;
+    for (int j = 0; j < kPerThread; j++) {
+      const int i = tid * kPerThread + j;
+      sum += i < q2 ? s_diff[i] : 0;
+      loc[j] = sum;
+    }
+    const int l = tid & 63, w = tid >> 6;
+    int incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off, 64);
+      if (l >= off) incl += y;
     }
     __syncthreads();
-    const int m = (int)(n - base < kTile ? n - base : kTile);
-    for (int x = 0; x < m; x++) {
-      const int64_t st = s_st[x], fi = s_fi[x];
-      for (int j = 0; j < kPerThread; j++) run[j] += (st <= t0[j]) & (t0[j] < fi);
+    if (l == 63) ((int*)s_red)[w] = incl;
+    __syncthreads();
+    int pre = incl - sum;
+    for (int q = 0; q < w; q++) pre += ((int*)s_red)[q];
+    __syncthreads();
+    // counts back to the clusters (s_diff is reused: count of cluster c at c)
+    for (int j = 0; j < kPerThread; j++) {
+      const int i = tid * kPerThread + j;
+      if (i < q2) loc[j] += pre;
     }
+    __syncthreads();
+    for (int j = 0; j < kPerThread; j++) {
+      const int i = tid * kPerThread + j;
+      if (i < q2) s_diff[s_qc[i]] = loc[j];
+    }
+    __syncthreads();
+    for (int j = 0; j < kPerThread; j++)
+      if (c0 + j < n_top) run[j] = s_diff[c0 + j];
   }
   __syncthreads();
 
@@ -369,39 +434,15 @@ __global__ void __launch_bounds__(kPartThreads) k_sv_part(SolveView v, SolveTabl
   }
 }
 
-__global__ void __launch_bounds__(1024) k_sv_offsets(const int32_t* n, int32_t count, int64_t* off) {
-  __shared__ int64_t s_part[16];
-  __shared__ int64_t s_carry;
-  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
-  if (tid == 0) { s_carry = 0; off[0] = 0; }
-  __syncthreads();
-  for (int base = 0; base < count; base += 1024) {
-    const int c = base + tid;
-    const int64_t x = c < count ? n[c] : 0;
-    int64_t incl = x;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int64_t y = __shfl_up(incl, o, 64);
-      if (l >= o) incl += y;
-    }
-    if (l == 63) s_part[w] = incl;
-    __syncthreads();
-    int64_t pre = s_carry;
-    for (int q = 0; q < w; q++) pre += s_part[q];
-    if (c < count) off[c + 1] = pre + incl;
-    __syncthreads();
-    if (tid == 0) {
-      int64_t s = 0;
-      for (int q = 0; q < 16; q++) s += s_part[q];
-      s_carry += s;
-    }
-    __syncthreads();
-  }
+__global__ void k_sv_strided(int64_t stride, int32_t count, int64_t* off) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c <= count) off[c] = (int64_t)c * stride;
 }
 
 }  // namespace
 
-hipError_t launch_offsets(const int32_t* n, int32_t count, int64_t* off, hipStream_t s) {
-  hipLaunchKernelGGL(k_sv_offsets, dim3(1), dim3(1024), 0, s, n, count, off);
+hipError_t launch_strided(int64_t stride, int32_t count, int64_t* off, hipStream_t s) {
+  hipLaunchKernelGGL(k_sv_strided, dim3((count + 256) / 256), dim3(256), 0, s, stride, count, off);
   return hipGetLastError();
 }
 

@@ -101,12 +101,11 @@ int hesp_solve(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, con
   Scratch sc;
   sc.s = s;
   int32_t *cnt, *status, *proc, *par, *cl;
-  int64_t *ecnt, *off, *ms, *start, *finish;
+  int64_t *off, *ms, *start, *finish;
   uint32_t* first;
   uint64_t *t0key, *fin, *lastkey;
   HIP_TRY(sc.get(&cnt, B));
   HIP_TRY(sc.get(&status, B));
-  HIP_TRY(sc.get(&ecnt, B));
   HIP_TRY(sc.get(&off, (int64_t)B + 1));
   HIP_TRY(sc.get(&ms, B));
   HIP_TRY(sc.get(&proc, tasks));
@@ -137,7 +136,8 @@ int hesp_solve(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, con
   v.best_ms = d_best_makespan;
   v.trace = d_trace;
   v.steps = d_steps;
-  v.sched_off = off;
+  v.stride = max_tasks;
+  v.n_tasks = cnt;
   v.proc = proc;
   v.start = start;
   v.finish = finish;
@@ -151,12 +151,12 @@ int hesp_solve(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, con
   v.lastkey = lastkey;
 
   hesp_batch hb{B, nt, dmax, nullptr, nullptr, nullptr, d_depth};
-  hesp_outputs out{ms, status, nullptr, off, proc, start, finish};
+  // chain r's schedule at r * max_tasks: no per-iteration offsets needed
+  HIP_TRY(solve::launch_strided(max_tasks, B, off, s));
+  hesp_outputs out{ms, status, cnt, off, proc, start, finish};
   for (int it = 0; it < sp->iters; it++) {
     // schedule stage: exact simulation of every chain's partition, with the
     // processor, start and finish of every task
-    RC_TRY(hesp_count_batch(&hb, cnt, ecnt, s));
-    HIP_TRY(solve::launch_offsets(cnt, B, off, s));
     RC_TRY(hesp_simulate_batch(plan, pf, policy, &hb, &out, s));
     // partition stage
     v.iter = it;
