@@ -5,9 +5,10 @@
 // gives the schedule of the chain's current partition; then
 //   k_sv_first   one workgroup per chain: first fine task of every top-level
 //                task (a "cluster": the task of Fig. 1 and the fine tasks it was
-//                split into), cluster bounds reset;
-//   k_sv_tasks   one lane per fine task: cluster start/finish bounds (atomics),
-//                the DAG predecessor that finished last, the chain's last task;
+//                split into);
+//   k_sv_tasks   one lane per fine task: its cluster, the DAG predecessor that
+//                finished last; cluster start/finish bounds and the chain's last
+//                task (reduced in the wavefront, then atomics);
 //   k_sv_part    one workgroup per chain: tasks running at every cluster's
 //                start, the proposal of every candidate cluster (the other depth
 //                with the largest score span - estimated time), the candidate
@@ -72,8 +73,6 @@ __global__ void __launch_bounds__(256) k_sv_first(SolveView v) {
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const uint8_t* depth = v.depth + (int64_t)r * v.n_top;
   uint32_t* first = v.first + (int64_t)r * (v.n_top + 1);
-  uint64_t* t0key = v.t0key + (int64_t)r * v.n_top;
-  uint64_t* fin = v.fin + (int64_t)r * v.n_top;
   if (tid == 0) {
     s_carry = 0;
     v.lastkey[r] = 0;
@@ -87,8 +86,8 @@ __global__ void __launch_bounds__(256) k_sv_first(SolveView v) {
       int d = depth[t];
       d = d > v.dmax ? v.dmax : d;
       cnt = fine_count(kind_of(cell_k(c), cell_i(c), cell_j(c)), d);
-      t0key[t] = ~0ull;
-      fin[t] = 0;
+      v.t0key[(int64_t)r * v.n_top + t] = ~0ull;
+      v.fin[(int64_t)r * v.n_top + t] = 0;
     }
     int incl = cnt;
     for (int o = 1; o < 64; o <<= 1) {
@@ -113,13 +112,10 @@ __global__ void __launch_bounds__(256) k_sv_first(SolveView v) {
 
 // ---------------------------------------------------------------- per task
 
-__global__ void __launch_bounds__(256) k_sv_tasks(SolveView v) {
-  const int r = blockIdx.y;
-  if (v.status[r] != 0) return;
-  const int64_t o = (int64_t)r * v.stride;
-  const int64_t n = v.n_tasks[r];
-  const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (f >= n) return;
+// one fine task: its cluster and latest-finishing DAG predecessor; returns its
+// finish key, its cluster and its start key
+__device__ __forceinline__ uint64_t sv_task(const SolveView& v, int r, int64_t o, int64_t f, int& cl_out,
+                                            uint64_t& sk_out, int64_t& fi_out) {
   const uint8_t* depth = v.depth + (int64_t)r * v.n_top;
   const uint32_t* first = v.first + (int64_t)r * (v.n_top + 1);
   // cluster of f: the last top-level task whose first fine task is <= f
@@ -138,10 +134,10 @@ __global__ void __launch_bounds__(256) k_sv_tasks(SolveView v) {
   const int K = cell_k(cell) * s + q, I = cell_i(cell) * s + rr, J = cell_j(cell) * s + cc;
 
   const int p = v.proc[o + f];
-  const int64_t st = v.start[o + f], fi = v.finish[o + f];
-  atomicMin((unsigned long long*)&v.t0key[(int64_t)r * v.n_top + t], (unsigned long long)start_key(st, p));
-  atomicMax((unsigned long long*)&v.fin[(int64_t)r * v.n_top + t], (unsigned long long)fi);
-  atomicMax((unsigned long long*)&v.lastkey[r], (unsigned long long)finish_key(fi, p));
+  const int64_t fi = v.finish[o + f];
+  cl_out = t;
+  sk_out = start_key(v.start[o + f], p);
+  fi_out = fi;
 
   uint64_t best = 0;
   int32_t bid = -1;
@@ -156,6 +152,44 @@ __global__ void __launch_bounds__(256) k_sv_tasks(SolveView v) {
   });
   v.par[o + f] = bid;
   v.cl[o + f] = t;
+  return finish_key(fi, p);
+}
+
+__global__ void __launch_bounds__(256) k_sv_tasks(SolveView v) {
+  const int r = blockIdx.y;
+  if (v.status[r] != 0) return;
+  const int64_t o = (int64_t)r * v.stride;
+  const int64_t n = v.n_tasks[r];
+  // the same trip count on every lane (n is uniform): the last-task key is
+  // reduced over the wavefront, and the cluster bounds over each run of lanes
+  // holding one cluster (a cluster's tasks are consecutive), before the atomics
+  const int l = threadIdx.x & 63;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+    const int64_t f = base + threadIdx.x;
+    int c = -1;
+    uint64_t sk = ~0ull;
+    int64_t fi = 0;
+    uint64_t key = f < n ? sv_task(v, r, o, f, c, sk, fi) : 0;
+    for (int off = 32; off >= 1; off >>= 1) {
+      const uint64_t y = __shfl_xor(key, off, 64);
+      key = y > key ? y : key;
+    }
+    if (l == 0 && key != 0) atomicMax((unsigned long long*)&v.lastkey[r], (unsigned long long)key);
+    for (int off = 1; off < 64; off <<= 1) {
+      const int c2 = __shfl_down(c, off, 64);
+      const uint64_t sk2 = __shfl_down(sk, off, 64);
+      const int64_t fi2 = __shfl_down(fi, off, 64);
+      if (l + off < 64 && c2 == c) {
+        sk = sk2 < sk ? sk2 : sk;
+        fi = fi2 > fi ? fi2 : fi;
+      }
+    }
+    const int cprev = __shfl_up(c, 1, 64);
+    if (c >= 0 && (l == 0 || cprev != c)) {
+      atomicMin((unsigned long long*)&v.t0key[(int64_t)r * v.n_top + c], (unsigned long long)sk);
+      atomicMax((unsigned long long*)&v.fin[(int64_t)r * v.n_top + c], (unsigned long long)fi);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- per chain: partition stage
@@ -214,6 +248,8 @@ __global__ void __launch_bounds__(kPartThreads) k_sv_part(SolveView v, SolveTabl
   int64_t t0[kPerThread], span[kPerThread];
   int run[kPerThread], pt[kPerThread];
   const int c0 = tid * kPerThread;
+  const int64_t o = (int64_t)r * v.stride;
+  const int64_t n = v.n_tasks[r];
   for (int j = 0; j < kPerThread; j++) {
     const int c = c0 + j;
     t0[j] = INT64_MAX;
@@ -261,8 +297,6 @@ __global__ void __launch_bounds__(kPartThreads) k_sv_part(SolveView v, SolveTabl
       }
       __syncthreads();
     }
-  const int64_t o = (int64_t)r * v.stride;
-  const int64_t n = v.n_tasks[r];
   auto lower = [&](int64_t t) {          // first sorted position with s_q >= t
     int lo = 0, hi = q2;
     while (lo < hi) {
@@ -452,7 +486,9 @@ hipError_t launch_first(const SolveView& v, hipStream_t s) {
 }
 
 hipError_t launch_tasks(const SolveView& v, int64_t max_tasks, hipStream_t s) {
-  const int64_t nb = (max_tasks + 255) / 256;
+  // a few workgroups per chain, each striding over the chain's tasks
+  int64_t nb = (max_tasks + 255) / 256;
+  nb = nb < 8 ? nb : 8;
   if (nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_sv_tasks, dim3((unsigned)nb, v.n_chains), dim3(256), 0, s, v);
   return hipGetLastError();
