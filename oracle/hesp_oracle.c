@@ -23,8 +23,9 @@
  *   4. critical times (section 2.1, "Priority-List"): sum of the task's time
  *      over all processors (an order-preserving multiple of the average),
  *      propagated backwards over the DAG;
- *   5. event simulation with write-back caching of host data in accelerator
- *      spaces and transfers issued when a task is scheduled (section 2.1,
+ *   5. event simulation with write-back, write-through or write-around
+ *      caching of host data in accelerator spaces and transfers issued when a
+ *      task is scheduled (section 2.1,
  *      "Task and data scheduling heuristics"); task order Priority-List
  *      (decreasing critical time) or FCFS (order of release), processor
  *      selection EFT-P (earliest finish counting transfers), EIT-P (the
@@ -96,6 +97,7 @@ typedef struct {
     int order;               /* policy: 0 = Priority-List, 1 = FCFS */
     int select;              /* policy: 0 = EFT-P, 1 = EIT-P, 2 = R-P, 3 = F-P */
     uint64_t seed;           /* R-P draws */
+    int cache;               /* policy: 0 = write-back, 1 = write-through, 2 = write-around */
 } or_platform;
 
 /* SplitMix64 (Steele, Lea, Flood 2014): value number idx+1 of the sequence
@@ -305,6 +307,24 @@ done:
 /* ------------------------------------------------------------------------ */
 /* 4-5. priorities and the event simulation                                  */
 
+/* When the transfer of a block's missing atoms into space m can start: at the
+ * mapping time T, or later if some missing atom has no copy valid yet (its
+ * earliest valid-from over all spaces is still ahead, as for a host copy still
+ * in flight after a write-around). */
+static int64_t xfer_start(const int64_t *vf, int M, int64_t N, int R, int C, int sh, int m, int64_t T)
+{
+    int64_t go = T;
+    int w = 1 << sh;
+    for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
+        int64_t a = (int64_t)((R << sh) + u) * N + ((C << sh) + v);
+        if (vf[a * M + m] != OR_INF) continue;
+        int64_t src = OR_INF;
+        for (int mm = 0; mm < M; mm++) if (vf[a * M + mm] < src) src = vf[a * M + mm];
+        if (src != OR_INF && src > go) go = src;
+    }
+    return go;
+}
+
 typedef struct {
     int nt, dmax;
     int64_t *cost;   /* [n_ptypes][4][dmax+1] */
@@ -500,7 +520,10 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                         else if (x > fin) fin = x;
                     }
                     int64_t ready = fin;
-                    if (miss > 0 && T + tb.xfer[miss] > ready) ready = T + tb.xfer[miss];
+                    if (miss > 0) {
+                        int64_t go = xfer_start(vf, M, N, br[bi], bc[bi], sh, m, T);
+                        if (go + tb.xfer[miss] > ready) ready = go + tb.xfer[miss];
+                    }
                     if (ready > est) est = ready;
                 }
                 int64_t eft = est + tb.cost[(pf->proc_type[p] * 4 + tl.v[t].type) * L + tl.v[t].level];
@@ -519,9 +542,10 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                     if (vf[a * M + m] == OR_INF) miss++;
                 }
                 if (!miss) continue;
+                int64_t go = xfer_start(vf, M, N, br[bi], bc[bi], sh, m, T);
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
                     int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
-                    if (vf[a * M + m] == OR_INF) vf[a * M + m] = T + tb.xfer[miss];
+                    if (vf[a * M + m] == OR_INF) vf[a * M + m] = go + tb.xfer[miss];
                 }
             }
             proc[t] = best_p; start[t] = best_est; finish[t] = best_eft;
@@ -542,15 +566,29 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             fifo_head[p] = fifo_next[t];
             if (fifo_head[p] < 0) fifo_tail[p] = -1;
             done_count++;
-            /* write-back: the written block is now valid only where it was computed */
+            /* coherence of the written block (memory spaces as software caches of
+             * the host, space 0):
+             *   write-back: valid only where it was computed;
+             *   write-through: valid there, and on the host once a copy issued now
+             *     has arrived; nowhere else;
+             *   write-around: not kept in an accelerator's space: valid on the host
+             *     only, once the copy issued now has arrived.
+             * reading: the copy to the host costs the transfer of the whole block */
             int br[3], bc[3], bw[3];
             int nb = task_blocks(&tl.v[t], br, bc, bw);
             int sh = dmax - tl.v[t].level, w = 1 << sh, m = pf->proc_mem[p];
+            int64_t host_at = (m == 0) ? Tn : Tn + tb.xfer[(int64_t)w * w];
             for (int bi = 0; bi < nb; bi++) {
                 if (!bw[bi]) continue;
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
                     int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
-                    for (int mm = 0; mm < M; mm++) vf[a * M + mm] = (mm == m) ? Tn : OR_INF;
+                    for (int mm = 0; mm < M; mm++) {
+                        int64_t x = OR_INF;
+                        if (pf->cache == 0) x = (mm == m) ? Tn : OR_INF;
+                        else if (pf->cache == 1) x = (mm == m) ? Tn : (mm == 0 ? host_at : OR_INF);
+                        else x = (mm == 0) ? host_at : OR_INF;
+                        vf[a * M + mm] = x;
+                    }
                 }
             }
             for (int e = g.succ_ptr[t]; e < g.succ_ptr[t + 1]; e++) {
@@ -609,15 +647,16 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
                     int64_t *makespan, int32_t *n_tasks, int64_t *n_edges,
                     int32_t max_tasks, int32_t *task_info, int32_t *proc_out,
                     int64_t *start_out, int64_t *finish_out, int64_t *rank_out,
-                    int64_t max_edges, int32_t *edges_out, int order, int select, uint64_t seed)
+                    int64_t max_edges, int32_t *edges_out, int order, int select, uint64_t seed,
+                    int cache)
 {
     if (!depth || n_procs < 1 || !proc_type || !proc_mem || n_mem < 1 || !rmax || !h) return OR_EINVAL;
-    if (order < 0 || order > 1 || select < 0 || select > 3) return OR_EINVAL;
+    if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2) return OR_EINVAL;
     for (int p = 0; p < n_procs; p++)
         if (proc_type[p] < 0 || proc_type[p] >= n_ptypes || proc_mem[p] < 0 || proc_mem[p] >= n_mem)
             return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared, order, select, seed};
+                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache};
     or_outputs o = {max_tasks, task_info, proc_out, start_out, finish_out, rank_out, max_edges, edges_out};
     or_result r;
     int rc = simulate_one(&pf, nt, dmax, depth, &r, &o);
@@ -665,12 +704,12 @@ int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
                           int n_ptypes, const int64_t *rmax, const int64_t *h, int64_t b,
                           int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
                           int n_threads, int64_t *makespan, int32_t *n_tasks, int32_t *status,
-                          int order, int select, uint64_t seed)
+                          int order, int select, uint64_t seed, int cache)
 {
     if (n_cand < 0 || !nt || !dmax || !mask_off || !depth || !makespan || n_threads < 1) return OR_EINVAL;
-    if (order < 0 || order > 1 || select < 0 || select > 3) return OR_EINVAL;
+    if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2) return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared, order, select, seed};
+                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache};
     or_batch_job j;
     j.pf = &pf; j.n_cand = n_cand; j.nt = nt; j.dmax = dmax; j.mask_off = mask_off; j.depth = depth;
     j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.next = 0;

@@ -164,25 +164,34 @@ class Sim:
     def xfer(self, k):
         return transfer_time(k, self.atom_side, self.shared)
 
+    @staticmethod
+    def go_time(miss, T, vf):
+        """Transfers of the missing atoms leave once every one of them has a valid
+        copy somewhere (a host copy may still be in flight)."""
+        src = [min(v for v in vf[a] if v != INF) for a in miss if any(v != INF for v in vf[a])]
+        return max([T] + src)
+
     def est(self, t, p, T, avail, vf):
         m = self.proc_mem[p]
         e = max(T, avail[p])
         for (R, C, _) in blocks(self.tasks[t]):
             at = atoms(R, C, self.tasks[t][1], self.dmax)
-            miss = sum(1 for a in at if vf[a][m] == INF)
+            miss = [a for a in at if vf[a][m] == INF]
             fin = [vf[a][m] for a in at if vf[a][m] != INF]
             r = max(fin) if fin else -INF
             if miss:
-                r = max(r, T + self.xfer(miss))
+                r = max(r, self.go_time(miss, T, vf) + self.xfer(len(miss)))
             e = max(e, r)
         return e
 
-    def run(self, choose_task=None, choose_proc=None, order="PL", select="EFT", seed=0):
+    def run(self, choose_task=None, choose_proc=None, order="PL", select="EFT", seed=0, cache="WB"):
         """order: "PL" (decreasing critical time) or "FCFS" (first released first);
         select: "EFT" (earliest finish), "EIT" (processor idle first), "RP"
         (random idle processor) or "FP" (fastest idle processor); with RP / FP a
         task that finds no idle processor waits for a completion.  Ties: smaller
-        scaled (K, I, J), then lower processor index."""
+        scaled (K, I, J), then lower processor index.  cache: "WB" (the written
+        block stays only where it was computed), "WT" (also sent to the host at
+        completion) or "WA" (sent to the host, not kept by an accelerator)."""
         from paper_1602_05510_amd.inputs import draw
         N = 0
         vf = {}
@@ -228,8 +237,9 @@ class Sim:
                 for (R, C, _) in blocks(self.tasks[t]):
                     at = atoms(R, C, self.tasks[t][1], self.dmax)
                     miss = [a for a in at if vf[a][m] == INF]
+                    go = self.go_time(miss, T, vf) if miss else T
                     for a in miss:
-                        vf[a][m] = T + self.xfer(len(miss))
+                        vf[a][m] = go + self.xfer(len(miss))
                 proc[t], start[t], finish[t] = p, ests[p], efts[p]
                 avail[p] = efts[p]
                 fifo[p].append(t)
@@ -243,8 +253,15 @@ class Sim:
                     m = self.proc_mem[p]
                     for (R, C, w) in blocks(self.tasks[t]):
                         if w:
-                            for a in atoms(R, C, self.tasks[t][1], self.dmax):
-                                vf[a] = [Tn if mm == m else INF for mm in range(self.n_mem)]
+                            at = atoms(R, C, self.tasks[t][1], self.dmax)
+                            home = Tn if m == 0 else Tn + self.xfer(len(at))
+                            for a in at:
+                                copies = [INF] * self.n_mem
+                                if cache == "WB" or (cache == "WT" and m != 0):
+                                    copies[m] = Tn
+                                if cache in ("WT", "WA"):
+                                    copies[0] = home
+                                vf[a] = copies
                     for v in self.succ[t]:
                         left[v] -= 1
                         if left[v] == 0:

@@ -39,8 +39,13 @@ MUTANTS = {
     "priority_reversed": ("if (a->rank != b->rank) return a->rank > b->rank;",
                           "if (a->rank != b->rank) return a->rank < b->rank;"),
     "key_tiebreak_reversed": ("return a->k2 < b->k2;", "return a->k2 > b->k2;"),
-    "no_invalidation": ("for (int mm = 0; mm < M; mm++) vf[a * M + mm] = (mm == m) ? Tn : OR_INF;",
-                        "vf[a * M + m] = Tn;"),
+    "no_invalidation": ("if (pf->cache == 0) x = (mm == m) ? Tn : OR_INF;",
+                        "if (pf->cache == 0) x = (mm == m) ? Tn : vf[a * M + mm];"),
+    "wt_host_copy_instant": ("int64_t host_at = (m == 0) ? Tn : Tn + tb.xfer[(int64_t)w * w];",
+                             "int64_t host_at = (m == 0) ? Tn : Tn + (pf->cache == 2 ? tb.xfer[(int64_t)w * w] : 0);"),
+    "wa_keeps_local_copy": ("else x = (mm == 0) ? host_at : OR_INF;",
+                            "else x = (mm == 0) ? host_at : (mm == m ? Tn : OR_INF);"),
+    "transfer_ignores_source": ("if (src != OR_INF && src > go) go = src;", "if (src != OR_INF && src > go) go = T;"),
     "cost_floor": ("static int64_t ceil_div_pos(int64_t a, int64_t b) { return a / b + (a % b != 0); }",
                    "static int64_t ceil_div_pos(int64_t a, int64_t b) { return a / b; }"),
     "rank_without_own_cost": ("rank[t] = W[t] + best;", "rank[t] = best;"),
@@ -77,6 +82,8 @@ def _pins_pass():
     with open(os.path.join(GOLD, "worked_examples.json")) as f:
         ex = json.load(f)["examples"]
     with open(os.path.join(GOLD, "policy_examples.json")) as f:
+        ex = ex + json.load(f)["examples"]
+    with open(os.path.join(GOLD, "cache_examples.json")) as f:
         ex = ex + json.load(f)["examples"]
     try:
         for e in ex:

@@ -377,6 +377,56 @@ def test_policy_worked_examples():
             assert got[(KIND[kind], lvl, K, I_, J)] == (p, st, fi), (e["name"], kind, K, I_, J)
 
 
+def test_cache_worked_examples():
+    """Hand-derived write-through and write-around schedules
+    (tests/golden/cache_examples.json)."""
+    with open(os.path.join(GOLD, "cache_examples.json")) as f:
+        ex = json.load(f)["examples"]
+    for e in ex:
+        pf = platform_from_spec(e["platform"]["types"])
+        s = O.simulate(pf, e["nt"], e["dmax"], e["b"], np.array(e["depth"], np.uint8), policy=tuple(e["policy"]))
+        assert s.makespan == e["makespan"], e["name"]
+        got = {tuple(int(x) for x in s.tasks[t]): (int(s.proc[t]), int(s.start[t]), int(s.finish[t]))
+               for t in range(s.n_tasks)}
+        assert len(got) == len(e["schedule"])
+        for (kind, lvl, K, I_, J, p, st, fi) in e["schedule"]:
+            assert got[(KIND[kind], lvl, K, I_, J)] == (p, st, fi), (e["name"], kind, K, I_, J)
+
+
+CACHE_NAMES = ["WB", "WT", "WA"]
+
+
+@pytest.mark.parametrize("cache", [1, 2])
+@pytest.mark.parametrize("policy", [(0, 0), (1, 1), (0, 3)])
+def test_python_reading_agrees_on_caching(policy, cache):
+    """The independent Python reading of write-through / write-around gives the
+    same schedules, split partitions included."""
+    rng = np.random.default_rng(300 + 10 * cache + 4 * policy[0] + policy[1])
+    plats = [I.make_platform(I.cpu_accel_types(2, 1), seed=7),
+             I.make_platform(I.cpu_accel_types(3, 2), seed=8),
+             I.make_platform(I.cpu_accel_types(1, 2), seed=9)]
+    for trial in range(24):
+        pf = plats[trial % 3]
+        nt = int(rng.integers(1, 5))
+        dmax = int(rng.integers(0, 3))
+        dep = rng.integers(0, dmax + 1, nt * (nt + 1) * (nt + 2) // 6).astype(np.uint8)
+        s = O.simulate(pf, nt, dmax, 256, dep, policy=policy + (0, cache))
+        ms, proc, start, finish = _py_sim(pf, nt, dmax, 256, dep).run(
+            order=["PL", "FCFS"][policy[0]], select=SELECT_NAMES[policy[1]], cache=CACHE_NAMES[cache])
+        assert ms == s.makespan
+        assert list(s.proc) == proc and list(s.start) == start and list(s.finish) == finish
+
+
+def test_caching_policies_coincide_without_accelerator_spaces():
+    """With every processor in the host space there is nothing to cache: the
+    three policies give the same schedule."""
+    pf = I.make_platform([I.ProcType("cpu", 3, 27000, 27000, 64, False)], seed=0)
+    dep = np.array([1, 0, 1, 0, 1, 1, 0, 1, 0, 1], np.uint8)
+    runs = [O.simulate(pf, 3, 1, 256, dep, policy=(0, 0, 0, c)) for c in range(3)]
+    for r in runs[1:]:
+        assert r.makespan == runs[0].makespan and list(r.start) == list(runs[0].start)
+
+
 @pytest.mark.parametrize("policy", POLICIES)
 def test_python_reading_agrees_on_policies(policy):
     """The independent Python reading of FCFS / EIT-P / R-P / F-P gives the same schedules."""
