@@ -110,8 +110,14 @@ typedef struct {
  * in order, at later completions (FCFS then means earliest release first).  R-P
  * takes the u-th idle processor in index order, u = SplitMix64 value
  * draw(seed, 8, corner) mod (idle count), corner = K' << 18 | I' << 9 | J' with
- * (K', I', J') the task's first cell on the finest grid.  Caching: write-back;
- * other values (write-through, write-around) give HESP_EUNSUPPORTED. */
+ * (K', I', J') the task's first cell on the finest grid.
+ * Caching (section 2: accelerator spaces as software caches of the host, space
+ * 0): write-back keeps a written block only in the executing space;
+ * write-through keeps it there and sends a copy to the host at the completion,
+ * valid there one block transfer later; write-around keeps no accelerator copy,
+ * only that host copy.  A missing block's transfer starts at the mapping time,
+ * or once every missing finest block has a valid copy somewhere (write-around:
+ * its host copy may still be in flight).  Other values give HESP_EUNSUPPORTED. */
 #define HESP_ORDER_PL 0
 #define HESP_ORDER_FCFS 1
 #define HESP_SELECT_EFT 0
@@ -119,6 +125,8 @@ typedef struct {
 #define HESP_SELECT_RP 2
 #define HESP_SELECT_FP 3
 #define HESP_CACHE_WB 0
+#define HESP_CACHE_WT 1
+#define HESP_CACHE_WA 2
 typedef struct {
   int32_t order, select, cache;
   uint64_t seed;               /* R-P draws */

@@ -25,6 +25,7 @@ struct SimTables {
   int32_t sel;                            // processor: 0 earliest finish, 1 earliest idle, 2 random idle,
                                           // 3 fastest idle (2, 3: tasks wait while no processor is idle)
   uint64_t seed;                          // random choices (SplitMix64)
+  int32_t cache;                          // written blocks: 0 write-back, 1 write-through, 2 write-around
 };
 
 struct BatchView {

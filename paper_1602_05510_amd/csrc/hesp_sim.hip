@@ -349,17 +349,21 @@ __device__ __forceinline__ uint64_t choice_draw(uint64_t seed, uint64_t idx) {
 template <int G, int POL>
 __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
                                                uint32_t* counter) {
-  // POL 0: Priority-List + EFT-P (no policy flags read); 1: the other push
-  // policies (FCFS, EIT-P); 2: R-P / F-P
+  // POL 0: Priority-List + EFT-P + write-back (no policy flags read); 1: the
+  // other push policies (FCFS, EIT-P) and caching policies; 2: R-P / F-P
   constexpr bool PULL = POL == 2;
   const bool fcfs = POL != 0 && tb.fcfs;
   const int sel = POL == 0 ? 0 : tb.sel;
+  const int cache = POL == 0 ? 0 : tb.cache;
   constexpr int NG = kWave / G;
   constexpr int LGG = G == 16 ? 4 : (G == 32 ? 5 : 6);
   __shared__ int64_t s_cost[kMaxPtypes][4][kLevels];
   __shared__ int64_t s_xfer[kXferLen];
   __shared__ int64_t s_fin[NG][4][kMaxMem];    // per (block, space): latest finite valid-from
   __shared__ int32_t s_miss[NG][4][kMaxMem];   // per (block, space): finest blocks missing
+  // write-around: per (block, space), the latest host valid-from of the missing
+  // finest blocks (their transfer cannot leave before)
+  __shared__ int64_t s_src[POL == 0 ? 1 : NG][4][kMaxMem];
   __shared__ uint32_t s_rid[NG][G];            // ready list, first G entries, with records
   __shared__ int64_t s_rrank[NG][G];
   __shared__ uint32_t s_rdesc[NG][G];
@@ -564,6 +568,7 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
         for (int x = gl; x < 4 * M; x += G) {
           (&s_fin[g][0][0])[(x >> 2) + (x & 3) * kMaxMem] = INT64_MIN;
           (&s_miss[g][0][0])[(x >> 2) + (x & 3) * kMaxMem] = 0;
+          if (POL != 0) (&s_src[POL == 0 ? 0 : g][0][0])[(x >> 2) + (x & 3) * kMaxMem] = INT64_MIN;
         }
         wave_order();
         // one lane per (space m, block b, finest block a): it = ((m*4 + b) << lg) | a
@@ -582,10 +587,18 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
           const int64_t x = act ? vld(&sp.vf[addr]) : kInf;
           const uint64_t infm = gp.ballot(act && x == kInf);
           const int64_t fin = seg_max64((act && x != kInf) ? x : INT64_MIN, lgs);
+          int64_t src = INT64_MIN;
+          if (POL != 0 && cache == 2) {
+            // write-around keeps a valid (possibly future) copy of every block on
+            // the host, and no other copy is valid earlier
+            const int64_t h = (act && x == kInf) ? vld(&sp.vf[addr - m]) : INT64_MIN;
+            src = seg_max64(h, lgs);
+          }
           if (act && (a & ((1 << lgs) - 1)) == (1 << lgs) - 1) {   // last lane of its segment chunk
             const uint64_t segm = lgs == 6 ? ~0ull : (((1ull << (1 << lgs)) - 1ull) << (gl + 1 - (1 << lgs)));
             s_fin[g][b][m] = max64(s_fin[g][b][m], fin);
             s_miss[g][b][m] += __popcll(infm & segm);
+            if (POL != 0 && cache == 2) s_src[POL == 0 ? 0 : g][b][m] = max64(s_src[POL == 0 ? 0 : g][b][m], src);
           }
           if (one_pass) {
             my_x = x;
@@ -600,7 +613,9 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
           for (int b = 0; b < nb; b++) {
             const int ms = s_miss[g][b][pmem];
             int64_t rdy = s_fin[g][b][pmem];
-            if (ms > 0) rdy = max64(rdy, T + s_xfer[ms * xs]);
+            int64_t go = T;
+            if (POL != 0 && cache == 2) go = max64(T, s_src[POL == 0 ? 0 : g][b][pmem]);
+            if (ms > 0) rdy = max64(rdy, go + s_xfer[ms * xs]);
             est = max64(est, rdy);
           }
         const int64_t eft = est + s_cost[ptype][kind][lvl];
@@ -626,13 +641,17 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
         const int64_t est_star = gp.bcast64(est, pstar);
         const int mstar = gp.bcast(pmem, pstar);
         // transfers of the missing finest blocks start now
+        auto leave = [&](int b) {   // when the transfer of block b's missing finest blocks starts
+          return (POL != 0 && cache == 2) ? max64(T, s_src[POL == 0 ? 0 : g][b][mstar]) : T;
+        };
         if (one_pass) {
-          if (my_addr >= 0 && my_m == mstar && my_x == kInf) sp.vf[my_addr] = T + s_xfer[s_miss[g][my_b][mstar] * xs];
+          if (my_addr >= 0 && my_m == mstar && my_x == kInf)
+            sp.vf[my_addr] = leave(my_b) + s_xfer[s_miss[g][my_b][mstar] * xs];
         } else {
           for (int b = 0; b < nb; b++) {
             const int miss = s_miss[g][b][mstar];
             if (miss == 0) continue;
-            const int64_t arrive = T + s_xfer[miss * xs];
+            const int64_t arrive = leave(b) + s_xfer[miss * xs];
             const int64_t abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
             for (int a0 = 0; a0 < (1 << lg); a0 += G) {
               const int a = a0 + gl;
@@ -744,15 +763,21 @@ __global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, Chunk
       const int sh = dmax - lvl, lg = 2 * sh, wmask = (1 << sh) - 1;
       int br[3], bc[3];
       const int nb = desc_blocks(dsc, br, bc);
-      // write-back: the written block is valid only where it was computed
+      // write-back: the written block is valid only where it was computed;
+      // write-through: also on the host, once the copy sent now has arrived;
+      // write-around: on the host only, once that copy has arrived
       const int64_t abase = atom_base(nt, dmax, lvl, br[nb - 1], bc[nb - 1]);
       const int items = M << lg;
+      const int64_t host_at = (POL != 0 && cache != 0 && ms != 0) ? Tn + s_xfer[(1 << lg) * xs] : Tn;
       for (int i0 = 0; i0 < items; i0 += G) {
         const int it = i0 + gl;
         if (it < items) {
           const int m = it >> lg, a = it & ((1 << lg) - 1);
           const int64_t atom = abase + ((int64_t)(a >> sh) << dmax) + (a & wmask);
-          sp.vf[atom * M + m] = (m == ms) ? Tn : kInf;
+          int64_t x = (m == ms) ? Tn : kInf;
+          if (POL != 0 && cache == 1) x = (m == ms) ? Tn : (m == 0 ? host_at : kInf);
+          if (POL != 0 && cache == 2) x = (m == 0) ? host_at : kInf;
+          sp.vf[atom * M + m] = x;
         }
       }
       // release successors (their records are fetched alongside the decrement)
@@ -831,7 +856,7 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
   const int per_wave = kWave / G;
   int waves = (v.nc + per_wave - 1) / per_wave;
   if (waves > slots) waves = slots;
-  const int pol = t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs ? 1 : 0);
+  const int pol = t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs || t.cache != 0 ? 1 : 0);
   const dim3 grid(waves), block(kWave);
 #define HESP_SIM_LAUNCH(GG, PP) hipLaunchKernelGGL((k_sim<GG, PP>), grid, block, 0, s, t, b, v, o, counter)
   if (G == 16) {

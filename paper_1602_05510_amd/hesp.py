@@ -58,7 +58,7 @@ SEARCH_RANDOM, SEARCH_GREEDY, SEARCH_SURROGATE = 0, 1, 2
 # heuristics of section 2.1: policy = (order, select, cache)
 ORDER_PL, ORDER_FCFS = 0, 1
 SELECT_EFT, SELECT_EIT, SELECT_RP, SELECT_FP = 0, 1, 2, 3
-CACHE_WB = 0
+CACHE_WB, CACHE_WT, CACHE_WA = 0, 1, 2
 
 
 class SearchParams(ctypes.Structure):
