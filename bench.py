@@ -91,7 +91,7 @@ def algorithmic_bytes(batch, n_mem: int, n_edges_total: int) -> tuple:
 
 # ----------------------------------------------------------------------- CPU baseline
 
-def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float):
+def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float, policy=(0, 0, 0, 0)):
     """The oracle, as it stands, on the host cores, over a bounded sample of the batch."""
     sys.path.insert(0, ROOT)
     from oracle import oracle as O
@@ -100,13 +100,13 @@ def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float):
     # calibrate the sample size with a small probe
     probe = batch_host.subset(range(min(64, batch_host.n)))
     t0 = time.perf_counter()
-    ms, ntk = O.simulate_batch(pf, probe, cores)
+    ms, ntk = O.simulate_batch(pf, probe, cores, policy=policy)
     dt = max(time.perf_counter() - t0, 1e-3)
     per_cand = dt / probe.n
     n = int(min(batch_host.n, max(probe.n, budget_s / per_cand)))
     sample = batch_host.subset(range(n))
     t0 = time.perf_counter()
-    ms, ntk = O.simulate_batch(pf, sample, cores)
+    ms, ntk = O.simulate_batch(pf, sample, cores, policy=policy)
     dt = time.perf_counter() - t0
     exact = bool(np.array_equal(ms, gpu_makespan[:n]))
     return {"value": float(ntk.sum()) / dt, "unit": "tasks/s", "cores": cores, "kind": "oracle",
@@ -457,6 +457,9 @@ def main():
     ap.add_argument("--sweep-n", type=int, default=16384)
     ap.add_argument("--sweep-nt", type=int, nargs="+", default=[2, 4, 8, 16, 32, 64])
     ap.add_argument("--sweep-seed", type=int, default=1)
+    ap.add_argument("--policy", type=int, nargs=3, default=[0, 0, 0], metavar=("ORDER", "SELECT", "CACHE"),
+                    help="order 0 PL / 1 FCFS, select 0 EFT-P / 1 EIT-P / 2 R-P / 3 F-P, cache 0 WB / 1 WT / 2 WA")
+    ap.add_argument("--policy-seed", type=int, default=0)
     ap.add_argument("--solve-chains", type=int, default=16384)
     ap.add_argument("--solve-iters", type=int, default=16)
     ap.add_argument("--solve-seed", type=int, default=7)
@@ -505,9 +508,12 @@ def main():
             return H.generate_ragged(w.seed, i * n, n, r["nt_lo"], r["nt_hi"], r["dmax_hi"], thr)
         return H.generate_uniform(w.seed, i * n, n, w.nt, w.dmax, thr)
 
+    order, select, cache = args.policy
+    gpol = (order, select, cache, args.policy_seed)
+
     def step(i: int, timed: bool):
         db = gen(i)
-        H.simulate_batch(plan, pf, db, ms, st, n_tasks=ntk)
+        H.simulate_batch(plan, pf, db, ms, st, n_tasks=ntk, policy=gpol)
         H.argmin(ms, best)
         if timed:
             # waits for this step's kernel events; the next step is queued after
@@ -553,13 +559,16 @@ def main():
         if os.path.exists(pmc_path):
             with open(pmc_path) as f:
                 pmc = json.load(f)
-            if pmc.get("kernel_sha") == kernel_hash() and pmc.get("n_cand") == n:
+            if pmc.get("kernel_sha") == kernel_hash() and pmc.get("n_cand") == n and tuple(args.policy) == (0, 0, 0):
                 traffic = pmc.get("hbm_bytes_per_launch")
         traffic_note = None if traffic is not None else "no counter run on this kernel source"
 
     value = tasks_total / elapsed
+    pname = (["PL", "FCFS"][order] + "/" + ["EFT-P", "EIT-P", "R-P", "F-P"][select] + "/" +
+             ["WB", "WT", "WA"][cache])
     rec = {
-        "metric": "simulated tasks/sec (bit-exact PL/EFT-P makespans)",
+        "metric": "simulated tasks/sec (bit-exact PL/EFT-P makespans)" if pname == "PL/EFT-P/WB" else
+                  f"simulated tasks/sec (bit-exact {pname} makespans)",
         "value": value,
         "unit": "tasks/s",
         "n_gpus": 1,
@@ -576,7 +585,7 @@ def main():
                    "dmax": f"0..{w.ragged['dmax_hi']}" if w.ragged else w.dmax,
                    "split_prob": f"{w.p_num}/{w.p_den}",
                    "platform": " + ".join(f"{t.count} {t.name}" for t in w.ptypes),
-                   "parallelism": "none (1 GPU)"},
+                   "policy": pname, "parallelism": "none (1 GPU)"},
         "candidates_per_s": n * args.steps / elapsed,
         "tasks_per_step": tasks_total / args.steps,
         "roofline": {"bound": "hbm", "kernel": "k_sim", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -591,9 +600,10 @@ def main():
         host0 = w.batch(n, first=0)
         # recompute step 0's makespans for the sample comparison
         db = gen(0)
-        H.simulate_batch(plan, pf, db, ms, st, n_tasks=ntk)
+        H.simulate_batch(plan, pf, db, ms, st, n_tasks=ntk, policy=gpol)
         torch.cuda.synchronize()
-        rec["cpu_baseline"] = cpu_baseline(w, pf_in, host0, ms.cpu().numpy(), args.cpu_budget)
+        rec["cpu_baseline"] = cpu_baseline(w, pf_in, host0, ms.cpu().numpy(), args.cpu_budget,
+                                           policy=(order, select, args.policy_seed, cache))
         rec["gpu_vs_cpu"] = value / rec["cpu_baseline"]["value"]
     if args.copy_calib:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
