@@ -189,6 +189,84 @@ static int expand(int nt, const uint8_t *depth, or_tasklist *out)
     return OR_OK;
 }
 
+/*
+ * Recursive per-task splitting (section 2.1, "Recursive task partitioners": any
+ * task, fine tasks included, may be partitioned again).  split[l] holds one flag
+ * per task of the uniform level-l expansion (nt * 2^l tiles, Fig. 1 order); a
+ * level-l task exists when all its ancestors were split, and it is split itself
+ * when its flag is set and l < dmax.  A split task is replaced, in place, by the
+ * blocked algorithm of its kind on the 2 x 2 sub-tiling of its cell.
+ */
+typedef struct {
+    int nt, dmax;
+    const uint8_t *flags;     /* concatenated levels 0 .. dmax-1 */
+    int64_t off[8];           /* start of level l in flags */
+    int *index[8];            /* Fig. 1 position of cell (K, I, J) at level l, N_l^3 entries */
+} or_tree;
+
+static int tree_init(or_tree *t, int nt, int dmax, const uint8_t *flags)
+{
+    memset(t, 0, sizeof(*t));
+    t->nt = nt; t->dmax = dmax; t->flags = flags;
+    int64_t off = 0;
+    for (int l = 0; l < dmax; l++) {
+        int N = nt << l;
+        t->off[l] = off;
+        t->index[l] = (int *)malloc((size_t)N * N * N * sizeof(int));
+        if (!t->index[l]) return OR_ENOMEM;
+        int pos = 0;                       /* Fig. 1 order on N tiles */
+        for (int k = 0; k < N; k++) {
+            t->index[l][((size_t)k * N + k) * N + k] = pos++;
+            for (int j = k + 1; j < N; j++) t->index[l][((size_t)k * N + k) * N + j] = pos++;
+            for (int i = k + 1; i < N; i++) {
+                for (int j = i + 1; j < N; j++) t->index[l][((size_t)k * N + i) * N + j] = pos++;
+                t->index[l][((size_t)k * N + i) * N + i] = pos++;
+            }
+        }
+        off += pos;
+    }
+    return OR_OK;
+}
+
+static void tree_free(or_tree *t)
+{
+    for (int l = 0; l < 8; l++) free(t->index[l]);
+}
+
+static int emit_tree(or_tasklist *out, const or_tree *tr, int top, int type, int l, int K, int I, int J)
+{
+    int N = tr->nt << l;
+    if (l < tr->dmax && tr->flags[tr->off[l] + tr->index[l][((size_t)K * N + I) * N + J]]) {
+        or_tasklist kids = {0, 0, 0};
+        if (emit_cell(&kids, top, 1, K, I, J)) { free(kids.v); return OR_ENOMEM; }
+        for (int c = 0; c < kids.n; c++)
+            if (emit_tree(out, tr, top, kids.v[c].type, l + 1, kids.v[c].K, kids.v[c].I, kids.v[c].J)) {
+                free(kids.v);
+                return OR_ENOMEM;
+            }
+        free(kids.v);
+        return OR_OK;
+    }
+    return tl_push(out, (or_task){type, l, K, I, J, top});
+}
+
+static int expand_tree(int nt, int dmax, const uint8_t *flags, or_tasklist *out)
+{
+    or_tree tr;
+    int rc = tree_init(&tr, nt, dmax, flags);
+    int top = 0;
+    for (int k = 0; k < nt && !rc; k++) {
+        rc = emit_tree(out, &tr, top++, OR_CHOL, 0, k, k, k);
+        for (int j = k + 1; j < nt && !rc; j++) rc = emit_tree(out, &tr, top++, OR_TRSM, 0, k, k, j);
+        for (int i = k + 1; i < nt && !rc; i++) {
+            for (int j = i + 1; j < nt && !rc; j++) rc = emit_tree(out, &tr, top++, OR_GEMM, 0, k, i, j);
+            if (!rc) rc = emit_tree(out, &tr, top++, OR_SYRK, 0, k, i, i);
+        }
+    }
+    tree_free(&tr);
+    return rc;
+}
+
 /* data blocks of a fine task: (row, col, written?) at the task's level */
 static int task_blocks(const or_task *t, int br[3], int bc[3], int bw[3])
 {
@@ -408,7 +486,19 @@ typedef struct {
     int32_t *edges;       /* [max_edges][2] */
 } or_outputs;
 
-static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *depth,
+/* flags of the split trees: sum over l < dmax of tet(nt 2^l) */
+static int64_t tree_flag_count(int nt, int dmax)
+{
+    int64_t n = 0;
+    for (int l = 0; l < dmax; l++) {
+        int64_t N = (int64_t)nt << l;
+        n += N * (N + 1) * (N + 2) / 6;
+    }
+    return n;
+}
+
+/* depth: split depth per top-level task, or (tree != 0) the split flags above */
+static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *depth, int tree,
                         or_result *res, const or_outputs *o)
 {
     or_tasklist tl = {0, 0, 0};
@@ -421,9 +511,15 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
     memset(&g, 0, sizeof(g));
 
     if (nt < 1 || dmax < 0 || dmax > 6 || (pf->b >> dmax) << dmax != pf->b) return OR_EINVAL;
-    int n_top = nt * (nt + 1) * (nt + 2) / 6;
-    for (int t = 0; t < n_top; t++) if (depth[t] > dmax) return OR_EINVAL;
-    rc = expand(nt, depth, &tl);
+    if (tree) {
+        int64_t nf = tree_flag_count(nt, dmax);
+        for (int64_t x = 0; x < nf; x++) if (depth[x] > 1) return OR_EINVAL;
+        rc = expand_tree(nt, dmax, depth, &tl);
+    } else {
+        int n_top = nt * (nt + 1) * (nt + 2) / 6;
+        for (int t = 0; t < n_top; t++) if (depth[t] > dmax) return OR_EINVAL;
+        rc = expand(nt, depth, &tl);
+    }
     if (rc) goto done;
     rc = build_dag(&tl, nt, dmax, &g);
     if (rc) goto done;
@@ -648,7 +744,7 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
                     int32_t max_tasks, int32_t *task_info, int32_t *proc_out,
                     int64_t *start_out, int64_t *finish_out, int64_t *rank_out,
                     int64_t max_edges, int32_t *edges_out, int order, int select, uint64_t seed,
-                    int cache)
+                    int cache, int tree)
 {
     if (!depth || n_procs < 1 || !proc_type || !proc_mem || n_mem < 1 || !rmax || !h) return OR_EINVAL;
     if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2) return OR_EINVAL;
@@ -659,7 +755,7 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
                       latency_ns, bw, elem_bytes, shared, order, select, seed, cache};
     or_outputs o = {max_tasks, task_info, proc_out, start_out, finish_out, rank_out, max_edges, edges_out};
     or_result r;
-    int rc = simulate_one(&pf, nt, dmax, depth, &r, &o);
+    int rc = simulate_one(&pf, nt, dmax, depth, tree, &r, &o);
     if (rc) return rc;
     if (makespan) *makespan = r.makespan;
     if (n_tasks) *n_tasks = r.n_tasks;
@@ -676,6 +772,7 @@ typedef struct {
     int64_t *makespan;
     int32_t *n_tasks;
     int32_t *status;
+    int tree;
     int next;
     pthread_mutex_t mu;
 } or_batch_job;
@@ -689,7 +786,7 @@ static void *batch_worker(void *arg)
         pthread_mutex_unlock(&j->mu);
         if (c >= j->n_cand) break;
         or_result r = {0, 0, 0};
-        int rc = simulate_one(j->pf, j->nt[c], j->dmax[c], j->depth + j->mask_off[c], &r, NULL);
+        int rc = simulate_one(j->pf, j->nt[c], j->dmax[c], j->depth + j->mask_off[c], j->tree, &r, NULL);
         j->makespan[c] = rc ? -1 : r.makespan;
         if (j->n_tasks) j->n_tasks[c] = rc ? 0 : r.n_tasks;
         if (j->status) j->status[c] = rc;
@@ -704,7 +801,7 @@ int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
                           int n_ptypes, const int64_t *rmax, const int64_t *h, int64_t b,
                           int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
                           int n_threads, int64_t *makespan, int32_t *n_tasks, int32_t *status,
-                          int order, int select, uint64_t seed, int cache)
+                          int order, int select, uint64_t seed, int cache, int tree)
 {
     if (n_cand < 0 || !nt || !dmax || !mask_off || !depth || !makespan || n_threads < 1) return OR_EINVAL;
     if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2) return OR_EINVAL;
@@ -712,7 +809,7 @@ int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
                       latency_ns, bw, elem_bytes, shared, order, select, seed, cache};
     or_batch_job j;
     j.pf = &pf; j.n_cand = n_cand; j.nt = nt; j.dmax = dmax; j.mask_off = mask_off; j.depth = depth;
-    j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.next = 0;
+    j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.tree = tree; j.next = 0;
     pthread_mutex_init(&j.mu, NULL);
     pthread_t *th = (pthread_t *)malloc((size_t)n_threads * sizeof(pthread_t));
     if (!th) return OR_ENOMEM;

@@ -38,10 +38,10 @@ def lib():
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         L.oracle_simulate.argtypes = [i32, i32, P, i32, P, P, i32, i32, P, P, i64, i64, i64, i64, i32,
-                                      P, P, P, i32, P, P, P, P, P, i64, P, i32, i32, ctypes.c_uint64, i32]
+                                      P, P, P, i32, P, P, P, P, P, i64, P, i32, i32, ctypes.c_uint64, i32, i32]
         L.oracle_simulate.restype = i32
         L.oracle_simulate_batch.argtypes = [i32, P, P, P, P, i32, P, P, i32, i32, P, P, i64, i64, i64,
-                                            i64, i32, i32, P, P, P, i32, i32, ctypes.c_uint64, i32]
+                                            i64, i32, i32, P, P, P, i32, i32, ctypes.c_uint64, i32, i32]
         L.oracle_simulate_batch.restype = i32
         L.oracle_task_time.argtypes = [i32, i64, i64, i64, P]
         L.oracle_task_time.restype = i32
@@ -89,8 +89,13 @@ class Schedule:
         return int(self.tasks.shape[0])
 
 
-def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = True, policy=(0, 0)):
+def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = True, policy=(0, 0),
+             tree: bool = False):
     """Simulate one candidate; returns a Schedule (detail) or the makespan.
+
+    depth: split depth per top-level task, or with tree=True the split flags of
+    every level l < dmax (one per task of the uniform level-l expansion, Fig. 1
+    order, levels concatenated).
 
     policy = (order, select[, seed[, cache]]): order 0 = Priority-List, 1 = FCFS;
     select 0 = EFT-P, 1 = EIT-P, 2 = R-P, 3 = F-P (section 2.1, "Task and data
@@ -109,7 +114,7 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     args_pf = (pf.n_procs, _p(ptype), _p(pmem), pf.n_mem, pf.n_ptypes, _p(rmax), _p(h), b,
                pf.latency_ns, pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory))
     rc = L.oracle_simulate(nt, dmax, _p(depth), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
-                           0, None, None, None, None, None, 0, None, order, select, seed, cache)
+                           0, None, None, None, None, None, 0, None, order, select, seed, cache, int(tree))
     if rc:
         raise ValueError(f"oracle_simulate rc={rc}")
     if not detail:
@@ -123,14 +128,16 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     edges = np.zeros((max(m, 1), 2), np.int32)
     rc = L.oracle_simulate(nt, dmax, _p(depth), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
                            n, _p(tasks), _p(proc), _p(start), _p(finish), _p(rank), m, _p(edges), order, select,
-                           seed, cache)
+                           seed, cache, int(tree))
     if rc:
         raise ValueError(f"oracle_simulate rc={rc}")
     return Schedule(int(ms[0]), tasks, proc, start, finish, rank, edges[:m])
 
 
-def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0)):
-    """Makespans (int64) and expanded task counts of a whole batch (policy as in simulate)."""
+def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = False):
+    """Makespans (int64) and expanded task counts of a whole batch (policy and
+    tree as in simulate; with tree=True batch.depth holds split flags and
+    batch.mask_off their offsets)."""
     order, select, seed, cache = (tuple(policy) + (0, 0))[:4]
     L = lib()
     n = batch.n
@@ -148,7 +155,7 @@ def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0)):
     rc = L.oracle_simulate_batch(n, _p(nt), _p(dm), _p(off), _p(dep), pf.n_procs, _p(ptype), _p(pmem),
                                  pf.n_mem, pf.n_ptypes, _p(rmax), _p(h), batch.b, pf.latency_ns,
                                  pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory), n_threads,
-                                 _p(ms), _p(ntk), _p(st), order, select, seed, cache)
+                                 _p(ms), _p(ntk), _p(st), order, select, seed, cache, int(tree))
     if rc:
         raise ValueError(f"oracle_simulate_batch rc={rc}")
     if np.any(st != 0):

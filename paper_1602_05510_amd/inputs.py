@@ -22,7 +22,11 @@ paper's problem statement, section 2, with synthetic rate models):
   (chol, trsm, syrk, gemm);
 * a candidate partitioning is one split depth per top-level task of the tiled
   Cholesky loop nest (Fig. 1 order); the depth is the number of consecutive
-  successes of a Bernoulli(p) split draw, capped at the candidate's maximum.
+  successes of a Bernoulli(p) split draw, capped at the candidate's maximum;
+* a split-tree candidate holds one split flag per task of every uniform level-l
+  tiling (nt * 2^l tiles per dimension, Fig. 1 order, levels 0 .. dmax-1
+  concatenated); flag x of candidate c is set when the leading 21 bits of the
+  draw for index (c << 32 | x) fall below the split threshold.
 """
 from __future__ import annotations
 
@@ -41,6 +45,7 @@ P_RMAX = 1
 P_DEPTH = 2
 P_SHAPE = 3
 P_PLATFORM = 4
+P_TREE = 5
 
 CHUNK_BITS = 21  # one split draw uses 21 random bits; depth <= 3 uses 63 bits
 
@@ -236,6 +241,48 @@ def uniform_batch(seed: int, n_cand: int, nt: int, b: int, dmax: int, p_num: int
     depth = depth_from_draw(u, thr, dmax).reshape(-1)
     off = np.arange(n_cand + 1, dtype=np.int64) * n_top
     return Batch(b, np.full(n_cand, nt, np.int32), np.full(n_cand, dmax, np.int32), off, depth)
+
+
+def tree_flag_count(nt: int, dmax: int) -> int:
+    """Split flags of one split-tree candidate: one per task of each uniform
+    level-l tiling, l < dmax."""
+    return sum(tet(nt << l) for l in range(dmax))
+
+
+def fig1_cells(n: int):
+    """Cells (k, i, j) of the tasks of the loop nest of Fig. 1 on n tiles, in its order."""
+    out = []
+    for k in range(n):
+        out.append((k, k, k))
+        out += [(k, k, j) for j in range(k + 1, n)]
+        for i in range(k + 1, n):
+            out += [(k, i, j) for j in range(i + 1, n)]
+            out.append((k, i, i))
+    return out
+
+
+def tree_flags_from_depth(nt: int, dmax: int, depth: np.ndarray) -> np.ndarray:
+    """The split-tree encoding of a depth-per-top-level-task candidate: a level-l
+    cell is flagged when its top-level task's depth exceeds l."""
+    top = {c: int(d) for c, d in zip(fig1_cells(nt), depth)}
+    flags = []
+    for l in range(dmax):
+        flags += [1 if top[(k >> l, i >> l, j >> l)] > l else 0 for (k, i, j) in fig1_cells(nt << l)]
+    return np.array(flags, np.uint8)
+
+
+def tree_batch(seed: int, n_cand: int, nt: int, b: int, dmax: int, p_num: int, p_den: int,
+               first: int = 0) -> Batch:
+    """n_cand split-tree candidates: independent Bernoulli(p) flags drawn with
+    counters (candidate, flag); depth holds the flags, mask_off their offsets."""
+    nf = tree_flag_count(nt, dmax)
+    thr = split_threshold(p_num, p_den)
+    c = np.arange(first, first + n_cand, dtype=np.uint64)[:, None]
+    x = np.arange(nf, dtype=np.uint64)[None, :]
+    u = draw_np(seed, P_TREE, (c << np.uint64(32)) | x)
+    flags = ((u >> np.uint64(64 - CHUNK_BITS)) < np.uint64(thr)).astype(np.uint8).reshape(-1)
+    off = np.arange(n_cand + 1, dtype=np.int64) * nf
+    return Batch(b, np.full(n_cand, nt, np.int32), np.full(n_cand, dmax, np.int32), off, flags)
 
 
 def ragged_batch(seed: int, n_cand: int, nt_lo: int, nt_hi: int, dmax_hi: int, b: int,

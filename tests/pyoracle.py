@@ -74,6 +74,36 @@ def expand(nt: int, depth: Sequence[int]):
     return tasks
 
 
+def expand_tree(nt: int, dmax: int, flags: Sequence[int]):
+    """Fine tasks (kind, level, K, I, J, top) in program order for split-tree
+    flags (one per task of each uniform level-l tiling, Fig. 1 order, levels
+    concatenated): a flagged task is replaced in place by the tasks of its cell
+    on the 2x2 sub-tiling, in the same K-step order, each expanded again."""
+    pos = []
+    base = 0
+    for l in range(dmax):
+        tops = fig1_tasks(nt << l)
+        pos.append({(k, i, j): base + x for x, (_, k, i, j) in enumerate(tops)})
+        base += len(tops)
+
+    def rec(kind, l, K, I, J, top):
+        if l < dmax and flags[pos[l][(K, I, J)]]:
+            kids = [(kind_of(a, b_, c), a, b_, c)
+                    for a in (2 * K, 2 * K + 1) for b_ in (2 * I, 2 * I + 1) for c in (2 * J, 2 * J + 1)
+                    if a <= b_ <= c]
+            kids.sort(key=lambda x: (x[1],) + _in_step_order(x[0], x[1], x[2], x[3]))
+            out = []
+            for (kk, a, b_, c) in kids:
+                out += rec(kk, l + 1, a, b_, c, top)
+            return out
+        return [(kind, l, K, I, J, top)]
+
+    tasks = []
+    for t, (kind, k, i, j) in enumerate(fig1_tasks(nt)):
+        tasks += rec(kind, 0, k, i, j, t)
+    return tasks
+
+
 def blocks(task) -> List[Tuple[int, int, bool]]:
     kind, _, K, I, J, _ = task
     if kind == CHOL:
@@ -136,8 +166,8 @@ class Sim:
     and EFT-P rule are used.
     """
 
-    def __init__(self, nt, dmax, b, depth, proc_type, proc_mem, n_mem, rmax, h, shared):
-        self.tasks = expand(nt, depth)
+    def __init__(self, nt, dmax, b, depth, proc_type, proc_mem, n_mem, rmax, h, shared, tree=False):
+        self.tasks = expand_tree(nt, dmax, depth) if tree else expand(nt, depth)
         self.E = edges(self.tasks, dmax)
         self.n = len(self.tasks)
         self.dmax, self.b = dmax, b
