@@ -236,6 +236,41 @@ typedef struct {
 int hesp_simulate_batch(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy,
                         const hesp_batch *batch, const hesp_outputs *out, void *stream);
 
+/* ---- split-tree candidates ---------------------------------------------------
+ * Section 2.1 ("Recursive task partitioners") applies a partition to any task,
+ * so sub-tasks of one top-level task may end at different depths.  A split-tree
+ * candidate holds one flag (0 or 1) per task of each uniform level-l tiling
+ * (nt 2^l tiles per dimension, Fig. 1 order), levels 0 .. dmax-1 concatenated:
+ * hesp_tree_flag_count(nt, dmax) = sum over l < dmax of tet(nt 2^l) bytes.  A
+ * level-l task exists when all its ancestors are split; it is split itself when
+ * its flag is 1 (flags of tasks that do not exist are ignored): it is replaced,
+ * in place, by the blocked algorithm of its kind on the 2 x 2 sub-tiling of its
+ * cell.  Flags that split every task under a top-level task to depth d give the
+ * depth-d candidate of hesp_simulate_batch (same tasks, same schedule).  The
+ * batch has one shape: d_flags (device) holds n_cand x flag_count bytes.
+ * Schedule outputs number the tasks in program order: top-level tasks in Fig. 1
+ * order, each split task replaced in place by its children in the order of the
+ * Fig. 1 loop nest restricted to its 2 x 2 sub-tiling, recursively.
+ * hesp_simulate_tree_batch behaves as hesp_simulate_batch (outputs, statuses,
+ * fixed-capacity plans; HESP_EINVAL for a flag above 1); it also keeps a
+ * last-writer table of 4 bytes per finest block and candidate in the plan.
+ * hesp_count_tree_batch gives the exact task and edge counts (it allocates and
+ * frees device workspace and synchronises `stream`).
+ * hesp_generate_tree_uniform: flag x of candidate first + c is 1 when the
+ * leading 21 bits of the SplitMix64 value draw(seed, 5, (first + c) << 32 | x)
+ * fall below split_thr. */
+typedef struct {
+  int32_t n_cand;
+  int32_t nt, dmax;
+  const uint8_t *d_flags;
+} hesp_tree_batch;
+int64_t hesp_tree_flag_count(int32_t nt, int32_t dmax);   /* -1 for a bad shape */
+int hesp_generate_tree_uniform(uint64_t seed, int64_t first, int32_t n_cand, int32_t nt, int32_t dmax,
+                               uint32_t split_thr, uint8_t *d_flags, void *stream);
+int hesp_count_tree_batch(const hesp_tree_batch *batch, int32_t *d_n_tasks, int64_t *d_n_edges, void *stream);
+int hesp_simulate_tree_batch(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy,
+                             const hesp_tree_batch *batch, const hesp_outputs *out, void *stream);
+
 /* ---- batch reduction -------------------------------------------------------
  * Best candidate of a batch: the smallest makespan, ties to the lowest index
  * (section 2.1, "Iterative solver": the partition that best fits the platform).

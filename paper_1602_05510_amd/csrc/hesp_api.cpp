@@ -92,6 +92,7 @@ struct hesp_plan {
   uint32_t* counter = nullptr;
   // per batch
   DevBuf cnt_tasks, cnt_edges, off_t, off_e, off_v, off_top, bounds;
+  DevBuf tree_lw;             // split-tree counts: last writer per finest block and candidate
   // per chunk, two sets: chunk i+1 is prepared while chunk i is simulated
   WorkSet ws[2];
   hipStream_t s_prep = nullptr, s_sim = nullptr;
@@ -108,10 +109,10 @@ struct hesp_plan {
   size_t ev_used = 0;
   int64_t held() const {
     return cnt_tasks.bytes + cnt_edges.bytes + off_t.bytes + off_e.bytes + off_v.bytes + off_top.bytes +
-           bounds.bytes + ws[0].bytes() + ws[1].bytes();
+           bounds.bytes + tree_lw.bytes + ws[0].bytes() + ws[1].bytes();
   }
   void release() {
-    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds}) b->release();
+    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds, &tree_lw}) b->release();
     for (WorkSet& w : ws)
       for (DevBuf* d : w.all()) d->release();
   }
@@ -255,6 +256,25 @@ static int batch_view(const hesp_batch* b, BatchView& v, const char* who) {
   v.dmax_arr = b->d_dmax;
   v.off = b->d_mask_off;
   v.depth = b->d_depth;
+  v.tree_stride = 0;
+  return HESP_OK;
+}
+
+static int tree_view(const hesp_tree_batch* b, BatchView& v, const char* who) {
+  if (!b) return fail(HESP_EINVAL, "%s: null batch", who);
+  if (b->n_cand < 0 || b->nt < 1 || b->dmax < 0 || b->dmax > HESP_MAX_LEVEL || (b->nt << b->dmax) > HESP_MAX_FINE)
+    return fail(HESP_EINVAL, "%s: n_cand=%d nt=%d dmax=%d outside the supported range", who, b->n_cand, b->nt,
+                b->dmax);
+  const int64_t nf = hesp_tree_flag_count(b->nt, b->dmax);
+  if (b->n_cand > 0 && nf > 0 && !b->d_flags) return fail(HESP_EINVAL, "%s: null flags", who);
+  v.n_cand = b->n_cand;
+  v.nt = b->nt;
+  v.dmax = b->dmax;
+  v.nt_arr = nullptr;
+  v.dmax_arr = nullptr;
+  v.off = nullptr;
+  v.depth = b->d_flags;
+  v.tree_stride = nf > 0 ? nf : 1;     // dmax = 0: no flags, the unsplit problem
   return HESP_OK;
 }
 
@@ -391,8 +411,13 @@ static int build_tables(const hesp_platform* pf, SimTables& t) {
   return HESP_OK;
 }
 
-int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,
-                        const hesp_outputs* out, void* stream) {
+static OutView ov_of(const hesp_outputs* o) {
+  return OutView{o->d_makespan, o->d_status, o->d_n_tasks, o->d_sched_off, o->d_proc, o->d_start, o->d_finish};
+}
+
+// depth batches (batch) or split-tree batches (tree)
+static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,
+                        const hesp_tree_batch* tree, const hesp_outputs* out, void* stream) {
   if (!plan) return fail(HESP_EINVAL, "hesp_simulate_batch: null plan");
   if ((policy.order != HESP_ORDER_PL && policy.order != HESP_ORDER_FCFS) || policy.select < HESP_SELECT_EFT ||
       policy.select > HESP_SELECT_FP || policy.cache < HESP_CACHE_WB || policy.cache > HESP_CACHE_WA)
@@ -405,7 +430,9 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   tb.seed = policy.seed;
   tb.cache = policy.cache;
   BatchView bv;
-  if (int r = batch_view(batch, bv, "hesp_simulate_batch")) return r;
+  if (int r = tree ? tree_view(tree, bv, "hesp_simulate_tree_batch") : batch_view(batch, bv, "hesp_simulate_batch"))
+    return r;
+  const bool is_tree = tree != nullptr;
   if (bv.dmax > pf->max_level) return fail(HESP_EINVAL, "hesp_simulate_batch: dmax above the platform's max_level");
   if (!out || !out->d_makespan || !out->d_status) return fail(HESP_EINVAL, "hesp_simulate_batch: null outputs");
   if (out->d_sched_off && (!out->d_proc || !out->d_start || !out->d_finish))
@@ -418,7 +445,16 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   HIP_TRY(plan->cnt_tasks.ensure(4 * (int64_t)n));
   HIP_TRY(plan->cnt_edges.ensure(8 * (int64_t)n));
   for (DevBuf* b : {&plan->off_t, &plan->off_e, &plan->off_v, &plan->off_top}) HIP_TRY(b->ensure(8 * ((int64_t)n + 1)));
-  HIP_TRY(launch_count(bv, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(), s));
+  if (is_tree) {
+    HIP_TRY(plan->tree_lw.ensure(4 * (int64_t)n * ((int64_t)tri2(bv.nt) << (2 * bv.dmax))));
+    HIP_TRY(launch_count_tree(bv, plan->tree_lw.as<uint32_t>(), plan->cnt_tasks.as<int32_t>(),
+                              plan->cnt_edges.as<int64_t>(), s));
+  } else {
+    HIP_TRY(launch_count(bv, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(), s));
+  }
+  auto prepare = [&](const ChunkView& cv, hipStream_t st) {
+    return is_tree ? launch_prepare_tree(tb, bv, cv, ov_of(out), st) : launch_prepare(tb, bv, cv, ov_of(out), st);
+  };
   HIP_TRY(launch_layout(bv, pf->n_mem, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(),
                         plan->opts.max_tasks, plan->opts.max_edges, plan->off_t.as<int64_t>(),
                         plan->off_e.as<int64_t>(), plan->off_v.as<int64_t>(), plan->off_top.as<int64_t>(), s));
@@ -529,7 +565,7 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   // sub-batch of the first chunk (outputs of that sub-batch are rewritten below)
   int group = plan->opts.group;
   if (group == 0) {
-    const auto key = std::make_tuple(pf->n_procs, pf->n_mem, bv.nt, bv.dmax, bv.nt_arr ? 1 : 0);
+    const auto key = std::make_tuple(pf->n_procs, pf->n_mem, bv.nt, bv.dmax, (bv.nt_arr ? 1 : 0) | (is_tree ? 2 : 0));
     auto it = plan->tuned.find(key);
     if (it != plan->tuned.end()) {
       group = it->second;
@@ -542,7 +578,7 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
       for (int G : {16, 32, 64}) {
         if (G < pf->n_procs) continue;
         ChunkView cv = chunk_view(0, sub, 0);
-        HIP_TRY(launch_prepare(tb, bv, cv, ov, s));
+        HIP_TRY(prepare(cv, s));
         HIP_TRY(hipEventRecord(e0, s));
         HIP_TRY(launch_sim(tb, bv, cv, ov, plan->slots, G, plan->counter, s));
         HIP_TRY(hipEventRecord(e1, s));
@@ -602,7 +638,7 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
     HIP_TRY(srch::size_order(plan->cnt_tasks.as<int32_t>(), cv.c0, cv.nc, plan->ws[set].order_keys.as<uint64_t>(),
                              plan->ws[set].order.as<uint32_t>(), sp));
     cv.order = plan->ws[set].order.as<uint32_t>();
-    HIP_TRY(launch_prepare(tb, bv, cv, ov, sp));
+    HIP_TRY(prepare(cv, sp));
     if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 1], sp));
     if (fork) {
       HIP_TRY(hipEventRecord(se[1 + 2 * i], sp));
@@ -615,6 +651,50 @@ int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
     if (plan->timing) plan->ev_used = 4 * (size_t)(i + 1);
   }
   if (fork) HIP_TRY(hipStreamWaitEvent(s, se[2 * n_chunks], 0));
+  return ok();
+}
+
+int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,
+                        const hesp_outputs* out, void* stream) {
+  if (!batch) return fail(HESP_EINVAL, "hesp_simulate_batch: null batch");
+  return simulate_any(plan, pf, policy, batch, nullptr, out, stream);
+}
+
+int hesp_simulate_tree_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy,
+                             const hesp_tree_batch* batch, const hesp_outputs* out, void* stream) {
+  if (!batch) return fail(HESP_EINVAL, "hesp_simulate_tree_batch: null batch");
+  return simulate_any(plan, pf, policy, nullptr, batch, out, stream);
+}
+
+int64_t hesp_tree_flag_count(int32_t nt, int32_t dmax) {
+  if (nt < 1 || dmax < 0 || dmax > HESP_MAX_LEVEL) return -1;
+  int64_t n = 0;
+  for (int l = 0; l < dmax; l++) n += tet3((int64_t)nt << l);
+  return n;
+}
+
+int hesp_generate_tree_uniform(uint64_t seed, int64_t first, int32_t n_cand, int32_t nt, int32_t dmax,
+                               uint32_t split_thr, uint8_t* d_flags, void* stream) {
+  const int64_t nf = hesp_tree_flag_count(nt, dmax);
+  if (n_cand < 0 || nf < 0 || first < 0 || (nt << dmax) > HESP_MAX_FINE || (!d_flags && n_cand > 0 && nf > 0))
+    return fail(HESP_EINVAL, "hesp_generate_tree_uniform: bad argument");
+  if (check_thr(split_thr)) return HESP_EINVAL;
+  HIP_TRY(launch_gen_tree(seed, first, n_cand, nf, split_thr, d_flags, (hipStream_t)stream));
+  return ok();
+}
+
+int hesp_count_tree_batch(const hesp_tree_batch* batch, int32_t* d_n_tasks, int64_t* d_n_edges, void* stream) {
+  BatchView bv;
+  if (int r = tree_view(batch, bv, "hesp_count_tree_batch")) return r;
+  if (bv.n_cand == 0) return ok();
+  if (!d_n_tasks || !d_n_edges) return fail(HESP_EINVAL, "hesp_count_tree_batch: null outputs");
+  hipStream_t s = (hipStream_t)stream;
+  void* lw = nullptr;
+  HIP_TRY(hipMalloc(&lw, 4 * (size_t)bv.n_cand * ((size_t)tri2(bv.nt) << (2 * bv.dmax))));
+  hipError_t e = launch_count_tree(bv, (uint32_t*)lw, d_n_tasks, d_n_edges, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(lw);
+  if (e != hipSuccess) return fail(HESP_EHIP, "hesp_count_tree_batch: %s", hipGetErrorString(e));
   return ok();
 }
 

@@ -33,7 +33,8 @@ struct BatchView {
   const int32_t* nt_arr;                   // nullable
   const int32_t* dmax_arr;                 // nullable
   const int64_t* off;                      // nullable: c * tet(nt)
-  const uint8_t* depth;
+  const uint8_t* depth;                    // split depth per top-level task, or split-tree flags
+  int64_t tree_stride;                     // 0: depths; > 0: split-tree flags, this many per candidate
 };
 
 // A chunk of consecutive candidates [c0, c0 + nc) and its buffers.  The
@@ -80,11 +81,20 @@ hipError_t launch_bounds(const int64_t* off_t, const int64_t* off_e, const int64
                          int32_t n, int32_t chunk, int32_t n_chunks, int64_t* out, hipStream_t s);
 hipError_t launch_prepare(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o,
                           hipStream_t s);
+// split-tree batches (b.tree_stride > 0, uniform shape): exact task and edge
+// counts (scratch: one last-writer word per finest block and candidate), and
+// the preparation of a chunk
+hipError_t launch_count_tree(const BatchView& b, uint32_t* scratch, int32_t* n_tasks, int64_t* n_edges,
+                             hipStream_t s);
+hipError_t launch_prepare_tree(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o,
+                               hipStream_t s);
 hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o, int32_t slots,
                       int32_t group, uint32_t* counter, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, hipStream_t s);
 hipError_t launch_gen_uniform(uint64_t seed, int64_t first, int32_t n_cand, int32_t nt, int32_t dmax,
                               uint32_t thr, uint8_t* depth, hipStream_t s);
+hipError_t launch_gen_tree(uint64_t seed, int64_t first, int32_t n_cand, int64_t n_flags, uint32_t thr,
+                           uint8_t* flags, hipStream_t s);
 hipError_t launch_gen_shape(uint64_t seed, int64_t first, int32_t n_cand, int32_t nt_lo, int32_t nt_hi,
                             int32_t dmax_hi, int32_t* nt, int32_t* dmax, int64_t* off, hipStream_t s);
 hipError_t launch_gen_ragged_depth(uint64_t seed, int64_t first, const BatchView& b, uint32_t thr,

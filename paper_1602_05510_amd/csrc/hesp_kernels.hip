@@ -54,7 +54,7 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
-constexpr int kPurposeDepth = 2, kPurposeShape = 3;
+constexpr int kPurposeDepth = 2, kPurposeShape = 3, kPurposeTree = 5;
 
 __device__ __forceinline__ uint64_t draw(uint64_t seed, int purpose, uint64_t idx) {
   const uint64_t s = mix64(seed + kGamma * (uint64_t)(purpose + 1));
@@ -79,6 +79,19 @@ __global__ void k_gen_uniform(uint64_t seed, int64_t first, int32_t n_cand, int3
     const int64_t c = x / n_top, t = x % n_top;
     const uint64_t u = draw(seed, kPurposeDepth, ((uint64_t)(first + c) << 24) | (uint64_t)t);
     depth[x] = depth_of_draw(u, thr, dmax);
+  }
+}
+
+// split-tree flags: flag x of candidate c is set when the leading 21 bits of the
+// draw for (c << 32 | x) fall below thr
+__global__ void k_gen_tree(uint64_t seed, int64_t first, int32_t n_cand, int64_t n_flags, uint32_t thr,
+                           uint8_t* flags) {
+  const int64_t total = (int64_t)n_cand * n_flags;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = x / n_flags, i = x % n_flags;
+    const uint64_t u = draw(seed, kPurposeTree, ((uint64_t)(first + c) << 32) | (uint64_t)i);
+    flags[x] = (uint32_t)(u >> 43) < thr ? 1 : 0;
   }
 }
 
@@ -180,6 +193,16 @@ hipError_t launch_gen_uniform(uint64_t seed, int64_t first, int32_t n_cand, int3
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_gen_uniform, dim3((unsigned)blocks), dim3(256), 0, s, seed, first, n_cand,
                      (int32_t)tet3(nt), dmax, thr, depth);
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_tree(uint64_t seed, int64_t first, int32_t n_cand, int64_t n_flags, uint32_t thr,
+                           uint8_t* flags, hipStream_t s) {
+  if (n_cand <= 0 || n_flags <= 0) return hipSuccess;
+  const int64_t total = (int64_t)n_cand * n_flags;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_gen_tree, dim3((unsigned)blocks), dim3(256), 0, s, seed, first, n_cand, n_flags, thr, flags);
   return hipGetLastError();
 }
 

@@ -139,72 +139,12 @@ __device__ __forceinline__ CandPtrs cand_ptrs(const ChunkView& v, int c) {
   return p;
 }
 
-// ---------------------------------------------------------------- preparation
+// ---------------------------------------------------------------- preparation, shared steps
 
-__global__ void __launch_bounds__(kWave) k_prepare(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
-  __shared__ int64_t s_W[4][kLevels];
-  __shared__ int64_t s_rk[kWave];
+// exclusive scan of the successor counts: afterwards cur[f] = first edge of f;
+// returns the number of edges
+__device__ __forceinline__ int64_t prep_scan_succ(const CandPtrs& sp, int64_t n_fine) {
   const int l = lane();
-  for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
-  __syncthreads();
-
-  const int c = cv.c0 + (int)blockIdx.x;
-  if (c >= bv.n_cand) return;
-  const Cand cd = load_cand(bv, c);
-  const int nt = cd.nt, dmax = cd.dmax, M = tb.n_mem;
-  int status = kOK;
-  if (nt < 1 || dmax < 0 || dmax > kMaxLevel || dmax > tb.max_level || (nt << dmax) > kMaxFine) status = kEINVAL;
-  if (status == kOK && ((cv.cap_tasks > 0 && cv.cnt_tasks[c] > cv.cap_tasks) ||
-                        (cv.cap_edges > 0 && cv.cnt_edges[c] > cv.cap_edges)))
-    status = kECAP;
-  const int64_t n_tasks = cv.task_off[c + 1] - cv.task_off[c];
-  const int64_t n_edges = cv.edge_off[c + 1] - cv.edge_off[c];
-  const CandPtrs sp = cand_ptrs(cv, c);
-
-  // pass A: first fine task of every top-level task; depths above dmax
-  int64_t carry = 0;
-  if (status == kOK) {
-    bool bad = false;
-    for (int t0 = 0; t0 < cd.n_top; t0 += kWave) {
-      const int t = t0 + l;
-      const bool vt = t < cd.n_top;
-      const uint32_t cell = vt ? top_cell(nt, t) : 0u;
-      const int d = vt ? (int)cd.depth[t] : 0;
-      bad |= vt && d > dmax;
-      const int cnt = vt ? fine_count(kind_of(cell_k(cell), cell_i(cell), cell_j(cell)), d > dmax ? dmax : d) : 0;
-      const int incl = wave_incl_scan(cnt);
-      if (vt) sp.top_first[t] = (uint32_t)(carry + incl - cnt);
-      carry += rdl32(incl, kWave - 1);
-    }
-    if (l == 0) sp.top_first[cd.n_top] = (uint32_t)carry;
-    if (__ballot(bad) || carry != n_tasks) status = kEINVAL;
-  }
-  if (status != kOK) {
-    if (l == 0) {
-      out.makespan[c] = -1;
-      out.status[c] = status;
-      if (out.n_tasks) out.n_tasks[c] = 0;
-    }
-    return;
-  }
-  const int64_t n_fine = n_tasks;
-  for (int64_t f = l; f < n_fine; f += kWave) sp.cur[f] = 0u;
-  wave_order();
-
-  auto depth_of = [&](int64_t t) { return (int)cd.depth[t]; };
-  auto first_of = [&](int64_t t) { return (int64_t)vld(&sp.top_first[t]); };
-
-  // pass B: descriptors, predecessor counts, successor counts
-  for_each_fine(cd, [&](bool valid, int64_t f, int64_t top, uint32_t cell, int d, int K, int I, int J) {
-    if (!valid) return;
-    sp.desc[f] = pack_desc(kind_of(K, I, J), d, K, I, J);
-    const int np = for_each_pred(nt, depth_of, first_of, top, cell, d, K, I, J,
-                                 [&](int64_t p) { atomicAdd(&sp.cur[p], 1u); });
-    sp.indeg[f] = (uint32_t)np;
-  });
-  wave_order();
-
-  // pass C: exclusive scan of successor counts (cur[f] = first edge of f)
   int64_t ecarry = 0;
   for (int64_t f0 = 0; f0 < n_fine; f0 += kWave) {
     const int64_t f = f0 + l;
@@ -215,29 +155,15 @@ __global__ void __launch_bounds__(kWave) k_prepare(SimTables tb, BatchView bv, C
   }
   wave_order();
 
-  // pass D: fill successor lists; afterwards cur[f] = one past the last edge of f
-  for_each_fine(cd, [&](bool valid, int64_t f, int64_t top, uint32_t cell, int d, int K, int I, int J) {
-    if (!valid) return;
-    // the first eight predecessors are collected (predicated register writes),
-    // then their slots are claimed together and written together
-    uint32_t pl[8];
-    int np = 0;
-    for_each_pred(nt, depth_of, first_of, top, cell, d, K, I, J, [&](int64_t p) {
-      if (np < 8) {
-        for (int q = 0; q < 8; q++) pl[q] = q == np ? (uint32_t)p : pl[q];
-        np++;
-      } else {
-        const uint32_t pos = atomicAdd(&sp.cur[p], 1u);
-        sp.succ[pos] = (uint32_t)f;
-      }
-    });
-    uint32_t pos[8];
-    for (int q = 0; q < 8; q++) pos[q] = q < np ? atomicAdd(&sp.cur[pl[q]], 1u) : 0u;
-    for (int q = 0; q < 8; q++)
-      if (q < np) sp.succ[pos[q]] = (uint32_t)f;
-  });
-  wave_order();
+  return ecarry;
+}
 
+// critical times, the closing record, initial validity and the first ready
+// list; cur[f] = one past the last edge of f, successor lists filled
+__device__ __forceinline__ void prep_finish(const ChunkView& cv, const OutView& out, int c, int nt, int dmax, int M,
+                                            const CandPtrs& sp, int64_t n_fine, int64_t n_edges,
+                                            const int64_t (*s_W)[kLevels], int64_t* s_rk) {
+  const int l = lane();
   // R: critical times, last chunk of 64 tasks first.  Successors beyond the
   // chunk are final and read once; those inside it are resolved by iterating
   // the chunk's values in LDS to their fixed point (monotone from below).
@@ -328,6 +254,311 @@ __global__ void __launch_bounds__(kWave) k_prepare(SimTables tb, BatchView bv, C
     out.status[c] = kOK;
     if (out.n_tasks) out.n_tasks[c] = (int32_t)n_fine;
   }
+}
+
+// ---------------------------------------------------------------- preparation
+
+__global__ void __launch_bounds__(kWave) k_prepare(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
+  __shared__ int64_t s_W[4][kLevels];
+  __shared__ int64_t s_rk[kWave];
+  const int l = lane();
+  for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
+  __syncthreads();
+
+  const int c = cv.c0 + (int)blockIdx.x;
+  if (c >= bv.n_cand) return;
+  const Cand cd = load_cand(bv, c);
+  const int nt = cd.nt, dmax = cd.dmax, M = tb.n_mem;
+  int status = kOK;
+  if (nt < 1 || dmax < 0 || dmax > kMaxLevel || dmax > tb.max_level || (nt << dmax) > kMaxFine) status = kEINVAL;
+  if (status == kOK && ((cv.cap_tasks > 0 && cv.cnt_tasks[c] > cv.cap_tasks) ||
+                        (cv.cap_edges > 0 && cv.cnt_edges[c] > cv.cap_edges)))
+    status = kECAP;
+  const int64_t n_tasks = cv.task_off[c + 1] - cv.task_off[c];
+  const int64_t n_edges = cv.edge_off[c + 1] - cv.edge_off[c];
+  const CandPtrs sp = cand_ptrs(cv, c);
+
+  // pass A: first fine task of every top-level task; depths above dmax
+  int64_t carry = 0;
+  if (status == kOK) {
+    bool bad = false;
+    for (int t0 = 0; t0 < cd.n_top; t0 += kWave) {
+      const int t = t0 + l;
+      const bool vt = t < cd.n_top;
+      const uint32_t cell = vt ? top_cell(nt, t) : 0u;
+      const int d = vt ? (int)cd.depth[t] : 0;
+      bad |= vt && d > dmax;
+      const int cnt = vt ? fine_count(kind_of(cell_k(cell), cell_i(cell), cell_j(cell)), d > dmax ? dmax : d) : 0;
+      const int incl = wave_incl_scan(cnt);
+      if (vt) sp.top_first[t] = (uint32_t)(carry + incl - cnt);
+      carry += rdl32(incl, kWave - 1);
+    }
+    if (l == 0) sp.top_first[cd.n_top] = (uint32_t)carry;
+    if (__ballot(bad) || carry != n_tasks) status = kEINVAL;
+  }
+  if (status != kOK) {
+    if (l == 0) {
+      out.makespan[c] = -1;
+      out.status[c] = status;
+      if (out.n_tasks) out.n_tasks[c] = 0;
+    }
+    return;
+  }
+  const int64_t n_fine = n_tasks;
+  for (int64_t f = l; f < n_fine; f += kWave) sp.cur[f] = 0u;
+  wave_order();
+
+  auto depth_of = [&](int64_t t) { return (int)cd.depth[t]; };
+  auto first_of = [&](int64_t t) { return (int64_t)vld(&sp.top_first[t]); };
+
+  // pass B: descriptors, predecessor counts, successor counts
+  for_each_fine(cd, [&](bool valid, int64_t f, int64_t top, uint32_t cell, int d, int K, int I, int J) {
+    if (!valid) return;
+    sp.desc[f] = pack_desc(kind_of(K, I, J), d, K, I, J);
+    const int np = for_each_pred(nt, depth_of, first_of, top, cell, d, K, I, J,
+                                 [&](int64_t p) { atomicAdd(&sp.cur[p], 1u); });
+    sp.indeg[f] = (uint32_t)np;
+  });
+  wave_order();
+
+  prep_scan_succ(sp, n_fine);
+
+  // pass D: fill successor lists; afterwards cur[f] = one past the last edge of f
+  for_each_fine(cd, [&](bool valid, int64_t f, int64_t top, uint32_t cell, int d, int K, int I, int J) {
+    if (!valid) return;
+    // the first eight predecessors are collected (predicated register writes),
+    // then their slots are claimed together and written together
+    uint32_t pl[8];
+    int np = 0;
+    for_each_pred(nt, depth_of, first_of, top, cell, d, K, I, J, [&](int64_t p) {
+      if (np < 8) {
+        for (int q = 0; q < 8; q++) pl[q] = q == np ? (uint32_t)p : pl[q];
+        np++;
+      } else {
+        const uint32_t pos = atomicAdd(&sp.cur[p], 1u);
+        sp.succ[pos] = (uint32_t)f;
+      }
+    });
+    uint32_t pos[8];
+    for (int q = 0; q < 8; q++) pos[q] = q < np ? atomicAdd(&sp.cur[pl[q]], 1u) : 0u;
+    for (int q = 0; q < 8; q++)
+      if (q < np) sp.succ[pos[q]] = (uint32_t)f;
+  });
+  wave_order();
+
+  prep_finish(cv, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_rk);
+}
+
+// ---------------------------------------------------------------- split trees
+// A split-tree candidate holds one flag per task of each uniform level-l tiling
+// (nt 2^l tiles, Fig. 1 order, levels 0 .. dmax-1 concatenated).  A level-l
+// task exists when its ancestors are split; a flagged one is replaced in place
+// by the blocked algorithm of its kind on the 2 x 2 sub-tiling of its cell
+// (section 2.1, "Recursive task partitioners", applied to any task).
+
+__device__ __forceinline__ int64_t tree_level_off(int nt, int l) {
+  int64_t o = 0;
+  for (int x = 0; x < l; x++) o += tet3((int64_t)nt << x);
+  return o;
+}
+
+// Child x of a split task in the order of the Fig. 1 loop nest restricted to its
+// 2 x 2 sub-tiling, as a local index: the same order except in a syrk cell,
+// where each row step issues its gemm before its syrk.
+__device__ __forceinline__ int fig1_child(int kind, int x) {
+  if (kind != SYRK) return x;
+  const int r = x % 3;
+  return x - r + (r == 0 ? 1 : (r == 1 ? 0 : 2));
+}
+
+// The tasks (leaves) of a candidate in program order: fn(kind, level, K, I, J)
+// with wave-uniform arguments.  Depth is at most 3, so level-3 tasks are leaves.
+template <class Fn>
+__device__ void walk_tree(int nt, int dmax, const uint8_t* flags, Fn&& fn) {
+  const int64_t n_top = tet3(nt);
+  const int64_t off1 = tree_level_off(nt, 1), off2 = tree_level_off(nt, 2);
+  auto split = [&](int lv, int64_t off, int K, int I, int J) {
+    return lv < dmax && flags[off + top_index(nt << lv, K, I, J)] != 0;
+  };
+  for (int64_t t = 0; t < n_top; t++) {
+    const uint32_t cell = top_cell(nt, t);
+    const int k0 = cell_k(cell), i0 = cell_i(cell), j0 = cell_j(cell), kd0 = kind_of(k0, i0, j0);
+    if (!split(0, 0, k0, i0, j0)) {
+      fn(kd0, 0, k0, i0, j0);
+      continue;
+    }
+    for (int x1 = 0; x1 < fine_count(kd0, 1); x1++) {
+      int q, r, w;
+      local_coords(kd0, 2, fig1_child(kd0, x1), q, r, w);
+      const int k1 = 2 * k0 + q, i1 = 2 * i0 + r, j1 = 2 * j0 + w, kd1 = kind_of(k1, i1, j1);
+      if (!split(1, off1, k1, i1, j1)) {
+        fn(kd1, 1, k1, i1, j1);
+        continue;
+      }
+      for (int x2 = 0; x2 < fine_count(kd1, 1); x2++) {
+        local_coords(kd1, 2, fig1_child(kd1, x2), q, r, w);
+        const int k2 = 2 * k1 + q, i2 = 2 * i1 + r, j2 = 2 * j1 + w, kd2 = kind_of(k2, i2, j2);
+        if (!split(2, off2, k2, i2, j2)) {
+          fn(kd2, 2, k2, i2, j2);
+          continue;
+        }
+        for (int x3 = 0; x3 < fine_count(kd2, 1); x3++) {
+          local_coords(kd2, 2, fig1_child(kd2, x3), q, r, w);
+          const int k3 = 2 * k2 + q, i3 = 2 * i2 + r, j3 = 2 * j2 + w;
+          fn(kind_of(k3, i3, j3), 3, k3, i3, j3);
+        }
+      }
+    }
+  }
+}
+
+// Dependences of task f from the last writer of every finest block it reads or
+// writes (read-after-write and write-after-write; in this factorization a task
+// reads only finalized blocks and its own output block, so write-after-read
+// edges are implied by these): emit(p) once per distinct writer, smallest
+// first, wave-uniform; then the blocks f writes record it.  Returns the count.
+template <class EmitF>
+__device__ __forceinline__ int scan_task(uint32_t* lw, int nt, int dmax, int kind, int lvl, int K, int I, int J,
+                                         uint32_t f, EmitF&& emit) {
+  const int l = lane();
+  int br[3], bc[3];
+  const int nb = desc_blocks(pack_desc(kind, lvl, K, I, J), br, bc);
+  const int sh = dmax - lvl, lg = 2 * sh, wmask = (1 << sh) - 1;
+  const int items = nb << lg;                       // at most 3 x 64 finest blocks
+  auto atom_of = [&](int it) {
+    const int b = it >> lg, a = it & ((1 << lg) - 1);
+    const int R = b == 0 ? br[0] : (b == 1 ? br[1] : br[2]);
+    const int C = b == 0 ? bc[0] : (b == 1 ? bc[1] : bc[2]);
+    return atom_base(nt, dmax, lvl, R, C) + ((int64_t)(a >> sh) << dmax) + (a & wmask);
+  };
+  uint32_t v0 = kNil, v1 = kNil, v2 = kNil;
+  if (l < items) v0 = vld(&lw[atom_of(l)]);
+  if (l + kWave < items) v1 = vld(&lw[atom_of(l + kWave)]);
+  if (l + 2 * kWave < items) v2 = vld(&lw[atom_of(l + 2 * kWave)]);
+  int n = 0;
+  for (;;) {
+    const uint32_t mine = v0 < v1 ? (v0 < v2 ? v0 : v2) : (v1 < v2 ? v1 : v2);
+    const uint32_t m = (uint32_t)wave_min64((int64_t)mine);
+    if (m == kNil) break;
+    emit(m);
+    n++;
+    v0 = v0 == m ? kNil : v0;
+    v1 = v1 == m ? kNil : v1;
+    v2 = v2 == m ? kNil : v2;
+  }
+  wave_order();
+  const int na = 1 << lg, bw = nb - 1;
+  const int64_t wbase = atom_base(nt, dmax, lvl, br[bw], bc[bw]);
+  for (int a0 = 0; a0 < na; a0 += kWave) {
+    const int a = a0 + l;
+    if (a < na) lw[wbase + ((int64_t)(a >> sh) << dmax) + (a & wmask)] = f;
+  }
+  wave_order();
+  return n;
+}
+
+__device__ __forceinline__ bool tree_shape_ok(int nt, int dmax) {
+  return nt >= 1 && dmax >= 0 && dmax <= kMaxLevel && (nt << dmax) <= kMaxFine;
+}
+
+// exact task and edge counts of every split-tree candidate
+__global__ void __launch_bounds__(kWave) k_count_tree(BatchView bv, uint32_t* scratch, int32_t* n_tasks,
+                                                      int64_t* n_edges) {
+  const int c = blockIdx.x;
+  if (c >= bv.n_cand) return;
+  const int nt = bv.nt, dmax = bv.dmax, l = lane();
+  if (!tree_shape_ok(nt, dmax)) {
+    if (l == 0) { n_tasks[c] = 0; n_edges[c] = 0; }
+    return;
+  }
+  const int64_t n_atoms = (int64_t)tri2(nt) << (2 * dmax);
+  uint32_t* lw = scratch + (int64_t)c * n_atoms;
+  for (int64_t a = l; a < n_atoms; a += kWave) lw[a] = kNil;
+  wave_order();
+  int64_t tasks = 0, edges = 0;
+  walk_tree(nt, dmax, bv.depth + (int64_t)c * bv.tree_stride, [&](int kind, int lv, int K, int I, int J) {
+    edges += scan_task(lw, nt, dmax, kind, lv, K, I, J, (uint32_t)tasks, [](uint32_t) {});
+    tasks++;
+  });
+  if (l == 0) {
+    n_tasks[c] = (int32_t)tasks;
+    n_edges[c] = edges;
+  }
+}
+
+// preparation of a split-tree candidate: descriptors and predecessor counts from
+// the scan, successor offsets, a second scan filling the successor lists, then
+// the steps shared with depth candidates (the last-writer table lives in the
+// candidate's validity words until they are initialized)
+__global__ void __launch_bounds__(kWave) k_prepare_tree(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
+  __shared__ int64_t s_W[4][kLevels];
+  __shared__ int64_t s_rk[kWave];
+  const int l = lane();
+  for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
+  __syncthreads();
+
+  const int c = cv.c0 + (int)blockIdx.x;
+  if (c >= bv.n_cand) return;
+  const int nt = bv.nt, dmax = bv.dmax, M = tb.n_mem;
+  int status = kOK;
+  if (!tree_shape_ok(nt, dmax) || dmax > tb.max_level) status = kEINVAL;
+  if (status == kOK && ((cv.cap_tasks > 0 && cv.cnt_tasks[c] > cv.cap_tasks) ||
+                        (cv.cap_edges > 0 && cv.cnt_edges[c] > cv.cap_edges)))
+    status = kECAP;
+  const uint8_t* flags = bv.depth + (int64_t)c * bv.tree_stride;
+  if (status == kOK) {
+    bool bad = false;
+    const int64_t nf = tree_level_off(nt, dmax);
+    for (int64_t x = l; x < nf; x += kWave) bad |= flags[x] > 1;
+    if (__ballot(bad)) status = kEINVAL;
+  }
+  const int64_t n_fine = cv.task_off[c + 1] - cv.task_off[c];
+  const int64_t n_edges = cv.edge_off[c + 1] - cv.edge_off[c];
+  if (status != kOK) {
+    if (l == 0) {
+      out.makespan[c] = -1;
+      out.status[c] = status;
+      if (out.n_tasks) out.n_tasks[c] = 0;
+    }
+    return;
+  }
+  const CandPtrs sp = cand_ptrs(cv, c);
+  const int64_t n_atoms = (int64_t)tri2(nt) << (2 * dmax);
+  uint32_t* lw = reinterpret_cast<uint32_t*>(sp.vf);
+  for (int64_t a = l; a < n_atoms; a += kWave) lw[a] = kNil;
+  for (int64_t f = l; f < n_fine; f += kWave) sp.cur[f] = 0u;
+  wave_order();
+
+  // descriptors, predecessor counts, successor counts
+  uint32_t nf_seen = 0;
+  walk_tree(nt, dmax, flags, [&](int kind, int lv, int K, int I, int J) {
+    const uint32_t f = nf_seen++;
+    const int np = scan_task(lw, nt, dmax, kind, lv, K, I, J, f, [&](uint32_t p) {
+      if (l == 0) atomicAdd(&sp.cur[p], 1u);
+    });
+    if (l == 0 && f < n_fine) {            // the counts came from the same walk: always true
+      sp.desc[f] = pack_desc(kind, lv, K, I, J);
+      sp.indeg[f] = (uint32_t)np;
+    }
+  });
+  wave_order();
+  prep_scan_succ(sp, n_fine);
+
+  // successor lists; afterwards cur[f] = one past the last edge of f
+  for (int64_t a = l; a < n_atoms; a += kWave) lw[a] = kNil;
+  wave_order();
+  nf_seen = 0;
+  walk_tree(nt, dmax, flags, [&](int kind, int lv, int K, int I, int J) {
+    const uint32_t f = nf_seen++;
+    scan_task(lw, nt, dmax, kind, lv, K, I, J, f, [&](uint32_t p) {
+      if (l == 0) {
+        const uint32_t pos = atomicAdd(&sp.cur[p], 1u);
+        if (pos < n_edges) sp.succ[pos] = f;
+      }
+    });
+  });
+  wave_order();
+  prep_finish(cv, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_rk);
 }
 
 // ---------------------------------------------------------------- event simulation
@@ -843,6 +1074,20 @@ hipError_t launch_prepare(const SimTables& t, const BatchView& b, const ChunkVie
                           hipStream_t s) {
   if (v.nc <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_prepare, dim3(v.nc), dim3(kWave), 0, s, t, b, v, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_tree(const BatchView& b, uint32_t* scratch, int32_t* n_tasks, int64_t* n_edges,
+                             hipStream_t s) {
+  if (b.n_cand <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_tree, dim3(b.n_cand), dim3(kWave), 0, s, b, scratch, n_tasks, n_edges);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_tree(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o,
+                               hipStream_t s) {
+  if (v.nc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prepare_tree, dim3(v.nc), dim3(kWave), 0, s, t, b, v, o);
   return hipGetLastError();
 }
 

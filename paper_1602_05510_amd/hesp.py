@@ -45,6 +45,10 @@ class BatchC(ctypes.Structure):
                 ("d_depth", P)]
 
 
+class TreeBatchC(ctypes.Structure):
+    _fields_ = [("n_cand", i32), ("nt", i32), ("dmax", i32), ("d_flags", P)]
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("slots", i32), ("max_tasks", i64), ("max_edges", i64), ("chunks", i32), ("group", i32)]
 
@@ -133,6 +137,10 @@ def lib():
             "hesp_topk_score": [P, i32, i32, P, P, i64, P],
             "hesp_search": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(SearchParams), P,
                             ctypes.POINTER(i64), P, P],
+            "hesp_generate_tree_uniform": [u64, i64, i32, i32, i32, u32, P, P],
+            "hesp_count_tree_batch": [ctypes.POINTER(TreeBatchC), P, P, P],
+            "hesp_simulate_tree_batch": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(TreeBatchC),
+                                         ctypes.POINTER(OutputsC), P],
             "hesp_solve": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(SolveParams), P, P, P, P, P, P],
         }
         for name, args in sig.items():
@@ -141,6 +149,8 @@ def lib():
             fn.restype = i32
         L.hesp_mlp_param_count.argtypes = []
         L.hesp_mlp_param_count.restype = i64
+        L.hesp_tree_flag_count.argtypes = [i32, i32]
+        L.hesp_tree_flag_count.restype = i64
         L.hesp_topk_workspace_bytes.argtypes = [i64]
         L.hesp_topk_workspace_bytes.restype = i64
         _lib = L
@@ -325,6 +335,51 @@ def simulate_batch(plan: Plan, pf: Platform, batch: DeviceBatch, makespan, statu
     _check("hesp_simulate_batch", lib().hesp_simulate_batch(plan.h, ctypes.byref(pf.c), Policy(*policy),
                                                             ctypes.byref(batch.c), ctypes.byref(out),
                                                             _stream(stream)))
+
+
+class TreeBatch:
+    """Split-tree candidates of one shape in device memory: flags [n_cand, flag_count]."""
+
+    def __init__(self, n_cand: int, nt: int, dmax: int, flags):
+        self.n_cand, self.nt, self.dmax, self.flags = int(n_cand), int(nt), int(dmax), flags
+        self.c = TreeBatchC(self.n_cand, self.nt, self.dmax, _dev(flags))
+
+    @classmethod
+    def from_host(cls, batch, device="cuda") -> "TreeBatch":
+        import torch
+        fl = torch.from_numpy(np.ascontiguousarray(batch.depth)).to(device)
+        return cls(batch.n, int(batch.nt[0]), int(batch.dmax[0]), fl)
+
+
+def tree_flag_count(nt: int, dmax: int) -> int:
+    return int(lib().hesp_tree_flag_count(nt, dmax))
+
+
+def generate_tree_uniform(seed: int, first: int, n_cand: int, nt: int, dmax: int, split_thr: int, stream=None,
+                          device="cuda") -> TreeBatch:
+    import torch
+    fl = torch.empty(max(1, n_cand * tree_flag_count(nt, dmax)), dtype=torch.uint8, device=device)
+    _check("hesp_generate_tree_uniform", lib().hesp_generate_tree_uniform(seed, first, n_cand, nt, dmax, split_thr,
+                                                                          _dev(fl), _stream(stream)))
+    return TreeBatch(n_cand, nt, dmax, fl)
+
+
+def count_tree_batch(batch: TreeBatch, stream=None):
+    import torch
+    nt = torch.empty(max(1, batch.n_cand), dtype=torch.int32, device="cuda")
+    ne = torch.empty(max(1, batch.n_cand), dtype=torch.int64, device="cuda")
+    _check("hesp_count_tree_batch", lib().hesp_count_tree_batch(ctypes.byref(batch.c), _dev(nt), _dev(ne),
+                                                                _stream(stream)))
+    return nt[:batch.n_cand], ne[:batch.n_cand]
+
+
+def simulate_tree_batch(plan: Plan, pf: Platform, batch: TreeBatch, makespan, status, sched_off=None, proc=None,
+                        start=None, finish=None, stream=None, policy=(0, 0, 0), n_tasks=None):
+    out = OutputsC(_dev(makespan), _dev(status), _dev(n_tasks), _dev(sched_off), _dev(proc), _dev(start),
+                   _dev(finish))
+    _check("hesp_simulate_tree_batch", lib().hesp_simulate_tree_batch(plan.h, ctypes.byref(pf.c), Policy(*policy),
+                                                                      ctypes.byref(batch.c), ctypes.byref(out),
+                                                                      _stream(stream)))
 
 
 def argmin(makespan, best, stream=None):
