@@ -91,7 +91,7 @@ def algorithmic_bytes(batch, n_mem: int, n_edges_total: int) -> tuple:
 
 # ----------------------------------------------------------------------- CPU baseline
 
-def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float, policy=(0, 0, 0, 0)):
+def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float, policy=(0, 0, 0, 0), tree: bool = False):
     """The oracle, as it stands, on the host cores, over a bounded sample of the batch."""
     sys.path.insert(0, ROOT)
     from oracle import oracle as O
@@ -100,13 +100,13 @@ def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float, policy=(0, 0,
     # calibrate the sample size with a small probe
     probe = batch_host.subset(range(min(64, batch_host.n)))
     t0 = time.perf_counter()
-    ms, ntk = O.simulate_batch(pf, probe, cores, policy=policy)
+    ms, ntk = O.simulate_batch(pf, probe, cores, policy=policy, tree=tree)
     dt = max(time.perf_counter() - t0, 1e-3)
     per_cand = dt / probe.n
     n = int(min(batch_host.n, max(probe.n, budget_s / per_cand)))
     sample = batch_host.subset(range(n))
     t0 = time.perf_counter()
-    ms, ntk = O.simulate_batch(pf, sample, cores, policy=policy)
+    ms, ntk = O.simulate_batch(pf, sample, cores, policy=policy, tree=tree)
     dt = time.perf_counter() - t0
     exact = bool(np.array_equal(ms, gpu_makespan[:n]))
     return {"value": float(ntk.sum()) / dt, "unit": "tasks/s", "cores": cores, "kind": "oracle",
@@ -460,6 +460,8 @@ def main():
     ap.add_argument("--policy", type=int, nargs=3, default=[0, 0, 0], metavar=("ORDER", "SELECT", "CACHE"),
                     help="order 0 PL / 1 FCFS, select 0 EFT-P / 1 EIT-P / 2 R-P / 3 F-P, cache 0 WB / 1 WT / 2 WA")
     ap.add_argument("--policy-seed", type=int, default=0)
+    ap.add_argument("--tree", action="store_true",
+                    help="split-tree candidates (every task split on its own) of the same shape")
     ap.add_argument("--solve-chains", type=int, default=16384)
     ap.add_argument("--solve-iters", type=int, default=16)
     ap.add_argument("--solve-seed", type=int, default=7)
@@ -503,6 +505,8 @@ def main():
     sim_ms = []
 
     def gen(i: int):
+        if args.tree:
+            return H.generate_tree_uniform(w.seed, i * n, n, w.nt, w.dmax, thr)
         if w.ragged:
             r = w.ragged
             return H.generate_ragged(w.seed, i * n, n, r["nt_lo"], r["nt_hi"], r["dmax_hi"], thr)
@@ -511,9 +515,15 @@ def main():
     order, select, cache = args.policy
     gpol = (order, select, cache, args.policy_seed)
 
+    def sim(db):
+        if args.tree:
+            H.simulate_tree_batch(plan, pf, db, ms, st, n_tasks=ntk, policy=gpol)
+        else:
+            H.simulate_batch(plan, pf, db, ms, st, n_tasks=ntk, policy=gpol)
+
     def step(i: int, timed: bool):
         db = gen(i)
-        H.simulate_batch(plan, pf, db, ms, st, n_tasks=ntk, policy=gpol)
+        sim(db)
         H.argmin(ms, best)
         if timed:
             # waits for this step's kernel events; the next step is queued after
@@ -548,8 +558,8 @@ def main():
     # roofline accounting for the simulation kernel (steps are statistically alike;
     # the accounting uses the batch of the last step); uniform batches only
     achieved = traffic = alg_bytes = None
-    traffic_note = "ragged batch: no algorithmic byte count"
-    if not w.ragged:
+    traffic_note = "split-tree batch: no algorithmic byte count" if args.tree else "ragged batch: no algorithmic byte count"
+    if not w.ragged and not args.tree:
         host_last = w.batch(n, first=(args.steps - 1) * n)
         db_last = H.DeviceBatch.from_host(host_last)
         _, e_last = H.count_batch(db_last)
@@ -567,8 +577,8 @@ def main():
     pname = (["PL", "FCFS"][order] + "/" + ["EFT-P", "EIT-P", "R-P", "F-P"][select] + "/" +
              ["WB", "WT", "WA"][cache])
     rec = {
-        "metric": "simulated tasks/sec (bit-exact PL/EFT-P makespans)" if pname == "PL/EFT-P/WB" else
-                  f"simulated tasks/sec (bit-exact {pname} makespans)",
+        "metric": ("simulated tasks/sec (bit-exact PL/EFT-P makespans)" if pname == "PL/EFT-P/WB" else
+                   f"simulated tasks/sec (bit-exact {pname} makespans)") + (", split-tree candidates" if args.tree else ""),
         "value": value,
         "unit": "tasks/s",
         "n_gpus": 1,
@@ -580,7 +590,8 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_cand": n,
+        "config": {"workload": w.name + (" split trees (one Bernoulli flag per task and level)" if args.tree else ""),
+                   "n_cand": n,
                    "nt": f"{w.ragged['nt_lo']}..{w.ragged['nt_hi']}" if w.ragged else w.nt, "b": w.b,
                    "dmax": f"0..{w.ragged['dmax_hi']}" if w.ragged else w.dmax,
                    "split_prob": f"{w.p_num}/{w.p_den}",
@@ -597,13 +608,16 @@ def main():
                      "kernel_sha": kernel_hash()},
     }
     if not args.no_cpu_baseline:
-        host0 = w.batch(n, first=0)
+        if args.tree:
+            host0 = I.tree_batch(w.seed, min(n, 16384), w.nt, w.b, w.dmax, w.p_num, w.p_den)
+        else:
+            host0 = w.batch(n, first=0)
         # recompute step 0's makespans for the sample comparison
         db = gen(0)
-        H.simulate_batch(plan, pf, db, ms, st, n_tasks=ntk, policy=gpol)
+        sim(db)
         torch.cuda.synchronize()
         rec["cpu_baseline"] = cpu_baseline(w, pf_in, host0, ms.cpu().numpy(), args.cpu_budget,
-                                           policy=(order, select, args.policy_seed, cache))
+                                           policy=(order, select, args.policy_seed, cache), tree=args.tree)
         rec["gpu_vs_cpu"] = value / rec["cpu_baseline"]["value"]
     if args.copy_calib:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
