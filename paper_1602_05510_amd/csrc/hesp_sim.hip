@@ -577,8 +577,12 @@ __device__ __forceinline__ uint64_t choice_draw(uint64_t seed, uint64_t idx) {
 
 // Instantiated per policy class so that the default policy carries no policy
 // code: R-P / F-P map tasks only onto idle processors and may make them wait.
+// The whole-wave variant is limited to 72 VGPRs, seven waves per SIMD: the event
+// loop waits on memory between short bursts of issue, and a seventh wave hides
+// more of it than the few spilled registers cost (-15% per launch measured); the
+// 16- and 32-lane variants lose when squeezed and keep their registers.
 template <int G, int POL>
-__global__ void __launch_bounds__(kWave) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
+__global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
                                                uint32_t* counter) {
   // POL 0: Priority-List + EFT-P + write-back (no policy flags read); 1: the
   // other push policies (FCFS, EIT-P) and caching policies; 2: R-P / F-P
