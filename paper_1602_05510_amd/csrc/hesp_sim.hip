@@ -258,7 +258,8 @@ __device__ __forceinline__ void prep_finish(const ChunkView& cv, const OutView& 
 
 // ---------------------------------------------------------------- preparation
 
-__global__ void __launch_bounds__(kWave) k_prepare(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
+// eight waves per SIMD (64 VGPRs): the passes wait on memory most of the time
+__global__ void __launch_bounds__(kWave, 8) k_prepare(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
   __shared__ int64_t s_W[4][kLevels];
   __shared__ int64_t s_rk[kWave];
   const int l = lane();
@@ -462,7 +463,9 @@ __device__ __forceinline__ bool tree_shape_ok(int nt, int dmax) {
 }
 
 // exact task and edge counts of every split-tree candidate
-__global__ void __launch_bounds__(kWave) k_count_tree(BatchView bv, uint32_t* scratch, int32_t* n_tasks,
+// both split-tree kernels run at eight waves per SIMD: their walks wait on memory
+// per task, and the extra waves hide more than the spilled registers cost
+__global__ void __launch_bounds__(kWave, 8) k_count_tree(BatchView bv, uint32_t* scratch, int32_t* n_tasks,
                                                       int64_t* n_edges) {
   const int c = blockIdx.x;
   if (c >= bv.n_cand) return;
@@ -490,7 +493,7 @@ __global__ void __launch_bounds__(kWave) k_count_tree(BatchView bv, uint32_t* sc
 // the scan, successor offsets, a second scan filling the successor lists, then
 // the steps shared with depth candidates (the last-writer table lives in the
 // candidate's validity words until they are initialized)
-__global__ void __launch_bounds__(kWave) k_prepare_tree(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
+__global__ void __launch_bounds__(kWave, 8) k_prepare_tree(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
   __shared__ int64_t s_W[4][kLevels];
   __shared__ int64_t s_rk[kWave];
   const int l = lane();
