@@ -31,7 +31,8 @@
  *      selection EFT-P (earliest finish counting transfers), EIT-P (the
  *      processor that becomes idle first), R-P (random) or F-P (fastest) --
  *      the last two among the processors idle at that time; a task finding no
- *      idle processor waits for the next completion.
+ *      idle processor waits for the next completion; optionally every transfer
+ *      shares one interconnect (one at a time, in issue order).
  * Where the paper is silent (tie-breaks, simultaneous events, transfer issue
  * time, coherence granularity) the readings are those listed in the design
  * notes of this repository; each is marked "reading:" below.
@@ -98,6 +99,7 @@ typedef struct {
     int select;              /* policy: 0 = EFT-P, 1 = EIT-P, 2 = R-P, 3 = F-P */
     uint64_t seed;           /* R-P draws */
     int cache;               /* policy: 0 = write-back, 1 = write-through, 2 = write-around */
+    int bus;                 /* 1: transfers share one interconnect, one at a time */
 } or_platform;
 
 /* SplitMix64 (Steele, Lea, Flood 2014): value number idx+1 of the sequence
@@ -569,7 +571,7 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             heap_push(&heap, (or_hent){pf->order ? 0 : rank[t], (int64_t)tl.v[t].K << sh,
                                        (int64_t)tl.v[t].I << sh, (int64_t)tl.v[t].J << sh, t});
         }
-    int64_t T = 0, makespan = 0;
+    int64_t T = 0, makespan = 0, bus_free = 0;
     int done_count = 0;
     for (;;) {
         /* (i) ready tasks are mapped now, in order; with R-P / F-P only onto
@@ -607,6 +609,7 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                 if (pick >= 0 && p != pick) continue;
                 int m = pf->proc_mem[p];
                 int64_t est = T > avail[p] ? T : avail[p];
+                int64_t bus_at = bus_free;       /* where this mapping's transfers would queue */
                 for (int bi = 0; bi < nb; bi++) {
                     int64_t miss = 0, fin = INT64_MIN;
                     for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
@@ -618,6 +621,8 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                     int64_t ready = fin;
                     if (miss > 0) {
                         int64_t go = xfer_start(vf, M, N, br[bi], bc[bi], sh, m, T);
+                        if (pf->bus && bus_at > go) go = bus_at;
+                        if (pf->bus) bus_at = go + tb.xfer[miss];
                         if (go + tb.xfer[miss] > ready) ready = go + tb.xfer[miss];
                     }
                     if (ready > est) est = ready;
@@ -639,6 +644,10 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                 }
                 if (!miss) continue;
                 int64_t go = xfer_start(vf, M, N, br[bi], bc[bi], sh, m, T);
+                /* shared interconnect: one transfer at a time, in issue order (the
+                 * blocks of one task in their order) */
+                if (pf->bus && bus_free > go) go = bus_free;
+                if (pf->bus) bus_free = go + tb.xfer[miss];
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
                     int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
                     if (vf[a * M + m] == OR_INF) vf[a * M + m] = go + tb.xfer[miss];
@@ -674,6 +683,11 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             int nb = task_blocks(&tl.v[t], br, bc, bw);
             int sh = dmax - tl.v[t].level, w = 1 << sh, m = pf->proc_mem[p];
             int64_t host_at = (m == 0) ? Tn : Tn + tb.xfer[(int64_t)w * w];
+            if (pf->bus && pf->cache != 0 && m != 0) {     /* the host copy queues on the interconnect */
+                int64_t go = Tn > bus_free ? Tn : bus_free;
+                host_at = go + tb.xfer[(int64_t)w * w];
+                bus_free = host_at;
+            }
             for (int bi = 0; bi < nb; bi++) {
                 if (!bw[bi]) continue;
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
@@ -744,15 +758,16 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
                     int32_t max_tasks, int32_t *task_info, int32_t *proc_out,
                     int64_t *start_out, int64_t *finish_out, int64_t *rank_out,
                     int64_t max_edges, int32_t *edges_out, int order, int select, uint64_t seed,
-                    int cache, int tree)
+                    int cache, int tree, int bus)
 {
     if (!depth || n_procs < 1 || !proc_type || !proc_mem || n_mem < 1 || !rmax || !h) return OR_EINVAL;
-    if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2) return OR_EINVAL;
+    if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2 || bus < 0 || bus > 1)
+        return OR_EINVAL;
     for (int p = 0; p < n_procs; p++)
         if (proc_type[p] < 0 || proc_type[p] >= n_ptypes || proc_mem[p] < 0 || proc_mem[p] >= n_mem)
             return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache};
+                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus};
     or_outputs o = {max_tasks, task_info, proc_out, start_out, finish_out, rank_out, max_edges, edges_out};
     or_result r;
     int rc = simulate_one(&pf, nt, dmax, depth, tree, &r, &o);
@@ -801,12 +816,13 @@ int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
                           int n_ptypes, const int64_t *rmax, const int64_t *h, int64_t b,
                           int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
                           int n_threads, int64_t *makespan, int32_t *n_tasks, int32_t *status,
-                          int order, int select, uint64_t seed, int cache, int tree)
+                          int order, int select, uint64_t seed, int cache, int tree, int bus)
 {
     if (n_cand < 0 || !nt || !dmax || !mask_off || !depth || !makespan || n_threads < 1) return OR_EINVAL;
-    if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2) return OR_EINVAL;
+    if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2 || bus < 0 || bus > 1)
+        return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache};
+                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus};
     or_batch_job j;
     j.pf = &pf; j.n_cand = n_cand; j.nt = nt; j.dmax = dmax; j.mask_off = mask_off; j.depth = depth;
     j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.tree = tree; j.next = 0;

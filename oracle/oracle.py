@@ -38,10 +38,10 @@ def lib():
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         L.oracle_simulate.argtypes = [i32, i32, P, i32, P, P, i32, i32, P, P, i64, i64, i64, i64, i32,
-                                      P, P, P, i32, P, P, P, P, P, i64, P, i32, i32, ctypes.c_uint64, i32, i32]
+                                      P, P, P, i32, P, P, P, P, P, i64, P, i32, i32, ctypes.c_uint64, i32, i32, i32]
         L.oracle_simulate.restype = i32
         L.oracle_simulate_batch.argtypes = [i32, P, P, P, P, i32, P, P, i32, i32, P, P, i64, i64, i64,
-                                            i64, i32, i32, P, P, P, i32, i32, ctypes.c_uint64, i32, i32]
+                                            i64, i32, i32, P, P, P, i32, i32, ctypes.c_uint64, i32, i32, i32]
         L.oracle_simulate_batch.restype = i32
         L.oracle_task_time.argtypes = [i32, i64, i64, i64, P]
         L.oracle_task_time.restype = i32
@@ -97,11 +97,12 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     every level l < dmax (one per task of the uniform level-l expansion, Fig. 1
     order, levels concatenated).
 
-    policy = (order, select[, seed[, cache]]): order 0 = Priority-List, 1 = FCFS;
-    select 0 = EFT-P, 1 = EIT-P, 2 = R-P, 3 = F-P (section 2.1, "Task and data
-    scheduling heuristics"); seed feeds the R-P draws; cache 0 = write-back,
-    1 = write-through, 2 = write-around."""
-    order, select, seed, cache = (tuple(policy) + (0, 0))[:4]
+    policy = (order, select[, seed[, cache[, bus]]]): order 0 = Priority-List,
+    1 = FCFS; select 0 = EFT-P, 1 = EIT-P, 2 = R-P, 3 = F-P (section 2.1, "Task
+    and data scheduling heuristics"); seed feeds the R-P draws; cache 0 =
+    write-back, 1 = write-through, 2 = write-around; bus 1 = every transfer
+    shares one interconnect."""
+    order, select, seed, cache, bus = (tuple(policy) + (0, 0, 0))[:5]
     L = lib()
     depth = np.ascontiguousarray(depth, dtype=np.uint8)
     ptype = np.ascontiguousarray(pf.proc_type, dtype=np.int32)
@@ -114,7 +115,7 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     args_pf = (pf.n_procs, _p(ptype), _p(pmem), pf.n_mem, pf.n_ptypes, _p(rmax), _p(h), b,
                pf.latency_ns, pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory))
     rc = L.oracle_simulate(nt, dmax, _p(depth), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
-                           0, None, None, None, None, None, 0, None, order, select, seed, cache, int(tree))
+                           0, None, None, None, None, None, 0, None, order, select, seed, cache, int(tree), bus)
     if rc:
         raise ValueError(f"oracle_simulate rc={rc}")
     if not detail:
@@ -128,7 +129,7 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     edges = np.zeros((max(m, 1), 2), np.int32)
     rc = L.oracle_simulate(nt, dmax, _p(depth), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
                            n, _p(tasks), _p(proc), _p(start), _p(finish), _p(rank), m, _p(edges), order, select,
-                           seed, cache, int(tree))
+                           seed, cache, int(tree), bus)
     if rc:
         raise ValueError(f"oracle_simulate rc={rc}")
     return Schedule(int(ms[0]), tasks, proc, start, finish, rank, edges[:m])
@@ -138,7 +139,7 @@ def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = Fa
     """Makespans (int64) and expanded task counts of a whole batch (policy and
     tree as in simulate; with tree=True batch.depth holds split flags and
     batch.mask_off their offsets)."""
-    order, select, seed, cache = (tuple(policy) + (0, 0))[:4]
+    order, select, seed, cache, bus = (tuple(policy) + (0, 0, 0))[:5]
     L = lib()
     n = batch.n
     ms = np.zeros(n, np.int64)
@@ -155,7 +156,7 @@ def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = Fa
     rc = L.oracle_simulate_batch(n, _p(nt), _p(dm), _p(off), _p(dep), pf.n_procs, _p(ptype), _p(pmem),
                                  pf.n_mem, pf.n_ptypes, _p(rmax), _p(h), batch.b, pf.latency_ns,
                                  pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory), n_threads,
-                                 _p(ms), _p(ntk), _p(st), order, select, seed, cache, int(tree))
+                                 _p(ms), _p(ntk), _p(st), order, select, seed, cache, int(tree), bus)
     if rc:
         raise ValueError(f"oracle_simulate_batch rc={rc}")
     if np.any(st != 0):

@@ -201,20 +201,38 @@ class Sim:
         src = [min(v for v in vf[a] if v != INF) for a in miss if any(v != INF for v in vf[a])]
         return max([T] + src)
 
-    def est(self, t, p, T, avail, vf):
-        m = self.proc_mem[p]
-        e = max(T, avail[p])
+    def transfers(self, t, m, T, vf, bus):
+        """Arrival time of each block of task t that space m misses (None when
+        it misses nothing); bus = time the shared interconnect frees up, or None
+        when transfers do not contend.  Returns (arrivals, bus after them)."""
+        out = []
         for (R, C, _) in blocks(self.tasks[t]):
             at = atoms(R, C, self.tasks[t][1], self.dmax)
             miss = [a for a in at if vf[a][m] == INF]
+            if not miss:
+                out.append(None)
+                continue
+            go = self.go_time(miss, T, vf)
+            if bus is not None:
+                go = max(go, bus)
+                bus = go + self.xfer(len(miss))
+            out.append(go + self.xfer(len(miss)))
+        return out, bus
+
+    def est(self, t, p, T, avail, vf, bus=None):
+        m = self.proc_mem[p]
+        e = max(T, avail[p])
+        arr, _ = self.transfers(t, m, T, vf, bus)
+        for (R, C, _), x in zip(blocks(self.tasks[t]), arr):
+            at = atoms(R, C, self.tasks[t][1], self.dmax)
             fin = [vf[a][m] for a in at if vf[a][m] != INF]
             r = max(fin) if fin else -INF
-            if miss:
-                r = max(r, self.go_time(miss, T, vf) + self.xfer(len(miss)))
+            if x is not None:
+                r = max(r, x)
             e = max(e, r)
         return e
 
-    def run(self, choose_task=None, choose_proc=None, order="PL", select="EFT", seed=0, cache="WB"):
+    def run(self, choose_task=None, choose_proc=None, order="PL", select="EFT", seed=0, cache="WB", bus=False):
         """order: "PL" (decreasing critical time) or "FCFS" (first released first);
         select: "EFT" (earliest finish), "EIT" (processor idle first), "RP"
         (random idle processor) or "FP" (fastest idle processor); with RP / FP a
@@ -236,6 +254,7 @@ class Sim:
         fifo = [[] for _ in range(self.P)]
         proc, start, finish = [None] * self.n, [None] * self.n, [None] * self.n
         T = 0
+        bus_free = 0
         while True:
             while ready:
                 idle = [q for q in range(self.P) if avail[q] <= T]
@@ -248,7 +267,7 @@ class Sim:
                 else:
                     t = min(ready, key=self.key)
                 ready.remove(t)
-                ests = [self.est(t, p, T, avail, vf) for p in range(self.P)]
+                ests = [self.est(t, p, T, avail, vf, bus_free if bus else None) for p in range(self.P)]
                 efts = [ests[p] + self.cost[t][p] for p in range(self.P)]
                 if choose_proc:
                     p = choose_proc(t, efts, self)
@@ -264,12 +283,13 @@ class Sim:
                 else:
                     p = min(range(self.P), key=lambda q: (efts[q], q))
                 m = self.proc_mem[p]
-                for (R, C, _) in blocks(self.tasks[t]):
-                    at = atoms(R, C, self.tasks[t][1], self.dmax)
-                    miss = [a for a in at if vf[a][m] == INF]
-                    go = self.go_time(miss, T, vf) if miss else T
-                    for a in miss:
-                        vf[a][m] = go + self.xfer(len(miss))
+                arr, after = self.transfers(t, m, T, vf, bus_free if bus else None)
+                if bus:
+                    bus_free = after
+                for (R, C, _), x in zip(blocks(self.tasks[t]), arr):
+                    for a in atoms(R, C, self.tasks[t][1], self.dmax):
+                        if vf[a][m] == INF:
+                            vf[a][m] = x
                 proc[t], start[t], finish[t] = p, ests[p], efts[p]
                 avail[p] = efts[p]
                 fifo[p].append(t)
@@ -285,6 +305,9 @@ class Sim:
                         if w:
                             at = atoms(R, C, self.tasks[t][1], self.dmax)
                             home = Tn if m == 0 else Tn + self.xfer(len(at))
+                            if bus and cache != "WB" and m != 0:
+                                home = max(Tn, bus_free) + self.xfer(len(at))
+                                bus_free = home
                             for a in at:
                                 copies = [INF] * self.n_mem
                                 if cache == "WB" or (cache == "WT" and m != 0):

@@ -46,6 +46,14 @@ MUTANTS = {
     "wa_keeps_local_copy": ("else x = (mm == 0) ? host_at : OR_INF;",
                             "else x = (mm == 0) ? host_at : (mm == m ? Tn : OR_INF);"),
     "transfer_ignores_source": ("if (src != OR_INF && src > go) go = src;", "if (src != OR_INF && src > go) go = T;"),
+    "bus_estimate_blocks_in_parallel": ("                        if (pf->bus) bus_at = go + tb.xfer[miss];",
+                                        "                        if (0) bus_at = go + tb.xfer[miss];"),
+    "bus_frees_at_transfer_start": ("                if (pf->bus) bus_free = go + tb.xfer[miss];",
+                                    "                if (pf->bus) bus_free = go;"),
+    "bus_estimate_ignores_queue": ("                        if (pf->bus && bus_at > go) go = bus_at;",
+                                   "                        if (0) go = bus_at;"),
+    "bus_host_copy_free": ("                int64_t go = Tn > bus_free ? Tn : bus_free;",
+                           "                int64_t go = Tn;"),
     "cost_floor": ("static int64_t ceil_div_pos(int64_t a, int64_t b) { return a / b + (a % b != 0); }",
                    "static int64_t ceil_div_pos(int64_t a, int64_t b) { return a / b; }"),
     "rank_without_own_cost": ("rank[t] = W[t] + best;", "rank[t] = best;"),
@@ -84,6 +92,8 @@ def _pins_pass():
     with open(os.path.join(GOLD, "policy_examples.json")) as f:
         ex = ex + json.load(f)["examples"]
     with open(os.path.join(GOLD, "cache_examples.json")) as f:
+        ex = ex + json.load(f)["examples"]
+    with open(os.path.join(GOLD, "bus_examples.json")) as f:
         ex = ex + json.load(f)["examples"]
     try:
         for e in ex:
@@ -125,6 +135,15 @@ def _pins_pass():
             r = O.simulate(pf3, 3, 1, 256, dep3, policy=(0, 2, seed))
             py = PY.Sim(3, 1, 256, dep3, pf3.proc_type, pf3.proc_mem, pf3.n_mem, pf3.rmax, pf3.h, pf3.shared_memory)
             if py.run(select="RP", seed=seed)[1] != list(r.proc):
+                return False
+        # shared interconnect, write-around, against the independent Python reading
+        rng = np.random.default_rng(77)
+        pf4 = I.make_platform(I.cpu_accel_types(1, 2), seed=9)
+        for _ in range(6):
+            dep4 = rng.integers(0, 2, 10).astype(np.uint8)
+            r = O.simulate(pf4, 3, 1, 256, dep4, policy=(0, 0, 0, 2, 1))
+            py = PY.Sim(3, 1, 256, dep4, pf4.proc_type, pf4.proc_mem, pf4.n_mem, pf4.rmax, pf4.h, pf4.shared_memory)
+            if py.run(cache="WA", bus=True)[2] != list(r.start):
                 return False
         # every top-level task of a 3x3 split DAG depends on something except chol0
         if len(s.edges) < s.n_tasks - 1:

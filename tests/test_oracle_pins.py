@@ -396,6 +396,48 @@ def test_cache_worked_examples():
 CACHE_NAMES = ["WB", "WT", "WA"]
 
 
+def test_bus_worked_examples():
+    """Hand-derived schedules with one shared interconnect
+    (tests/golden/bus_examples.json)."""
+    with open(os.path.join(GOLD, "bus_examples.json")) as f:
+        ex = json.load(f)["examples"]
+    for e in ex:
+        pf = platform_from_spec(e["platform"]["types"])
+        s = O.simulate(pf, e["nt"], e["dmax"], e["b"], np.array(e["depth"], np.uint8), policy=tuple(e["policy"]))
+        assert s.makespan == e["makespan"], e["name"]
+        got = {tuple(int(x) for x in s.tasks[t]): (int(s.proc[t]), int(s.start[t]), int(s.finish[t]))
+               for t in range(s.n_tasks)}
+        for (kind, lvl, K, I_, J, p, st, fi) in e["schedule"]:
+            assert got[(KIND[kind], lvl, K, I_, J)] == (p, st, fi), (e["name"], kind, K, I_, J)
+
+
+@pytest.mark.parametrize("cache", [0, 1, 2])
+@pytest.mark.parametrize("policy", [(0, 0), (1, 1), (0, 3)])
+def test_python_reading_agrees_on_the_shared_interconnect(policy, cache):
+    rng = np.random.default_rng(500 + 10 * cache + 4 * policy[0] + policy[1])
+    plats = [I.make_platform(I.cpu_accel_types(2, 1), seed=7),
+             I.make_platform(I.cpu_accel_types(3, 2), seed=8),
+             I.make_platform(I.cpu_accel_types(1, 2), seed=9)]
+    for trial in range(16):
+        pf = plats[trial % 3]
+        nt = int(rng.integers(1, 5))
+        dmax = int(rng.integers(0, 3))
+        dep = rng.integers(0, dmax + 1, nt * (nt + 1) * (nt + 2) // 6).astype(np.uint8)
+        s = O.simulate(pf, nt, dmax, 256, dep, policy=policy + (0, cache, 1))
+        ms, proc, start, finish = _py_sim(pf, nt, dmax, 256, dep).run(
+            order=["PL", "FCFS"][policy[0]], select=SELECT_NAMES[policy[1]], cache=CACHE_NAMES[cache], bus=True)
+        assert ms == s.makespan
+        assert list(s.proc) == proc and list(s.start) == start and list(s.finish) == finish
+
+
+def test_shared_interconnect_changes_nothing_without_transfers():
+    pf = I.make_platform([I.ProcType("cpu", 3, 27000, 27000, 64, False)], seed=0)
+    dep = np.array([1, 0, 1, 0, 1, 1, 0, 1, 0, 1], np.uint8)
+    a = O.simulate(pf, 3, 1, 256, dep)
+    b = O.simulate(pf, 3, 1, 256, dep, policy=(0, 0, 0, 0, 1))
+    assert a.makespan == b.makespan and list(a.start) == list(b.start)
+
+
 @pytest.mark.parametrize("cache", [1, 2])
 @pytest.mark.parametrize("policy", [(0, 0), (1, 1), (0, 3)])
 def test_python_reading_agrees_on_caching(policy, cache):
