@@ -460,6 +460,7 @@ def main():
     ap.add_argument("--policy", type=int, nargs=3, default=[0, 0, 0], metavar=("ORDER", "SELECT", "CACHE"),
                     help="order 0 PL / 1 FCFS, select 0 EFT-P / 1 EIT-P / 2 R-P / 3 F-P, cache 0 WB / 1 WT / 2 WA")
     ap.add_argument("--policy-seed", type=int, default=0)
+    ap.add_argument("--bus", action="store_true", help="every transfer shares one interconnect")
     ap.add_argument("--tree", action="store_true",
                     help="split-tree candidates (every task split on its own) of the same shape")
     ap.add_argument("--solve-chains", type=int, default=16384)
@@ -513,7 +514,8 @@ def main():
         return H.generate_uniform(w.seed, i * n, n, w.nt, w.dmax, thr)
 
     order, select, cache = args.policy
-    gpol = (order, select, cache, args.policy_seed)
+    bus = int(args.bus)
+    gpol = (order, select, cache, args.policy_seed, bus)
 
     def sim(db):
         if args.tree:
@@ -569,13 +571,14 @@ def main():
         if os.path.exists(pmc_path):
             with open(pmc_path) as f:
                 pmc = json.load(f)
-            if pmc.get("kernel_sha") == kernel_hash() and pmc.get("n_cand") == n and tuple(args.policy) == (0, 0, 0):
+            if (pmc.get("kernel_sha") == kernel_hash() and pmc.get("n_cand") == n and tuple(args.policy) == (0, 0, 0)
+                    and not bus):
                 traffic = pmc.get("hbm_bytes_per_launch")
         traffic_note = None if traffic is not None else "no counter run on this kernel source"
 
     value = tasks_total / elapsed
     pname = (["PL", "FCFS"][order] + "/" + ["EFT-P", "EIT-P", "R-P", "F-P"][select] + "/" +
-             ["WB", "WT", "WA"][cache])
+             ["WB", "WT", "WA"][cache] + ("/shared interconnect" if bus else ""))
     rec = {
         "metric": ("simulated tasks/sec (bit-exact PL/EFT-P makespans)" if pname == "PL/EFT-P/WB" else
                    f"simulated tasks/sec (bit-exact {pname} makespans)") + (", split-tree candidates" if args.tree else ""),
@@ -617,7 +620,7 @@ def main():
         sim(db)
         torch.cuda.synchronize()
         rec["cpu_baseline"] = cpu_baseline(w, pf_in, host0, ms.cpu().numpy(), args.cpu_budget,
-                                           policy=(order, select, args.policy_seed, cache), tree=args.tree)
+                                           policy=(order, select, args.policy_seed, cache, bus), tree=args.tree)
         rec["gpu_vs_cpu"] = value / rec["cpu_baseline"]["value"]
     if args.copy_calib:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)

@@ -117,7 +117,11 @@ typedef struct {
  * valid there one block transfer later; write-around keeps no accelerator copy,
  * only that host copy.  A missing block's transfer starts at the mapping time,
  * or once every missing finest block has a valid copy somewhere (write-around:
- * its host copy may still be in flight).  Other values give HESP_EUNSUPPORTED. */
+ * its host copy may still be in flight).  Other values give HESP_EUNSUPPORTED.
+ * bus = 1: every transfer uses one shared interconnect, one at a time in issue
+ * order (the missing blocks of a task in their order; write-through and
+ * write-around host copies queue at the completion); the EFT-P estimate sees the
+ * queue.  bus = 0: transfers do not contend. */
 #define HESP_ORDER_PL 0
 #define HESP_ORDER_FCFS 1
 #define HESP_SELECT_EFT 0
@@ -130,6 +134,7 @@ typedef struct {
 typedef struct {
   int32_t order, select, cache;
   uint64_t seed;               /* R-P draws */
+  int32_t bus;                 /* 0 or 1: one shared interconnect */
 } hesp_policy;
 
 /* ---- expansion of one candidate (host) ----------------------------------------

@@ -420,15 +420,17 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
                         const hesp_tree_batch* tree, const hesp_outputs* out, void* stream) {
   if (!plan) return fail(HESP_EINVAL, "hesp_simulate_batch: null plan");
   if ((policy.order != HESP_ORDER_PL && policy.order != HESP_ORDER_FCFS) || policy.select < HESP_SELECT_EFT ||
-      policy.select > HESP_SELECT_FP || policy.cache < HESP_CACHE_WB || policy.cache > HESP_CACHE_WA)
-    return fail(HESP_EUNSUPPORTED,
-                "hesp_simulate_batch: PL or FCFS order, EFT-P, EIT-P, R-P or F-P selection, WB, WT or WA caching");
+      policy.select > HESP_SELECT_FP || policy.cache < HESP_CACHE_WB || policy.cache > HESP_CACHE_WA ||
+      policy.bus < 0 || policy.bus > 1)
+    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: PL or FCFS order, EFT-P, EIT-P, R-P or F-P selection, "
+                                   "WB, WT or WA caching, bus 0 or 1");
   SimTables tb;
   if (int r = build_tables(pf, tb)) return r;
   tb.fcfs = policy.order == HESP_ORDER_FCFS;
   tb.sel = policy.select;
   tb.seed = policy.seed;
   tb.cache = policy.cache;
+  tb.bus = policy.bus;
   BatchView bv;
   if (int r = tree ? tree_view(tree, bv, "hesp_simulate_tree_batch") : batch_view(batch, bv, "hesp_simulate_batch"))
     return r;

@@ -26,6 +26,7 @@ struct SimTables {
                                           // 3 fastest idle (2, 3: tasks wait while no processor is idle)
   uint64_t seed;                          // random choices (SplitMix64)
   int32_t cache;                          // written blocks: 0 write-back, 1 write-through, 2 write-around
+  int32_t bus;                            // 1: transfers share one interconnect, one at a time
 };
 
 struct BatchView {

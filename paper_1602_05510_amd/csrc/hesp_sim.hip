@@ -593,6 +593,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
   const bool fcfs = POL != 0 && tb.fcfs;
   const int sel = POL == 0 ? 0 : tb.sel;
   const int cache = POL == 0 ? 0 : tb.cache;
+  const bool bus = POL != 0 && tb.bus != 0;
   constexpr int NG = kWave / G;
   constexpr int LGG = G == 16 ? 4 : (G == 32 ? 5 : 6);
   __shared__ int64_t s_cost[kMaxPtypes][4][kLevels];
@@ -625,6 +626,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
   int64_t xs = 0, T = 0, n_ready = 0, sbase = 0;
   CandPtrs sp{};
   int64_t avail = 0, hfin = kInf;
+  int64_t bus_free = 0;                       // shared interconnect: free from this time
   uint32_t hid = kNil, hdesc = 0, he0 = 0, he1 = 0, tail = kNil;
 
   auto push = [&](int64_t pos, uint32_t v, int64_t r0, int64_t r1, int64_t r3) {
@@ -658,6 +660,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
           sbase = want_sched ? out.sched_off[c] : 0;
           T = 0;
           avail = 0;
+          bus_free = 0;
           hfin = kInf;
           hid = kNil;
           tail = kNil;
@@ -847,15 +850,22 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
         }
         wave_order();
         int64_t est = T > avail ? T : avail;
-        if (gl < P)
+        if (gl < P) {
+          int64_t lb = bus_free;                    // with a shared interconnect: the blocks in order
           for (int b = 0; b < nb; b++) {
             const int ms = s_miss[g][b][pmem];
             int64_t rdy = s_fin[g][b][pmem];
             int64_t go = T;
             if (POL != 0 && cache == 2) go = max64(T, s_src[POL == 0 ? 0 : g][b][pmem]);
-            if (ms > 0) rdy = max64(rdy, go + s_xfer[ms * xs]);
+            if (ms > 0) {
+              if (bus) go = max64(go, lb);
+              const int64_t arr = go + s_xfer[ms * xs];
+              if (bus) lb = arr;
+              rdy = max64(rdy, arr);
+            }
             est = max64(est, rdy);
           }
+        }
         const int64_t eft = est + s_cost[ptype][kind][lvl];
         int pstar;
         int64_t eft_star;
@@ -879,17 +889,37 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
         const int64_t est_star = gp.bcast64(est, pstar);
         const int mstar = gp.bcast(pmem, pstar);
         // transfers of the missing finest blocks start now
-        auto leave = [&](int b) {   // when the transfer of block b's missing finest blocks starts
+        auto leave = [&](int b) {   // when the transfer of block b's missing finest blocks can start
           return (POL != 0 && cache == 2) ? max64(T, s_src[POL == 0 ? 0 : g][b][mstar]) : T;
         };
+        // arrival of each block's transfer (in block order on a shared interconnect)
+        int64_t arr0 = 0, arr1 = 0, arr2 = 0;
+        if constexpr (POL != 0) {
+          int64_t lb = bus_free;
+          for (int b = 0; b < nb; b++) {
+            const int miss = s_miss[g][b][mstar];
+            if (miss == 0) continue;
+            int64_t go = leave(b);
+            if (bus) go = max64(go, lb);
+            const int64_t a = go + s_xfer[miss * xs];
+            if (bus) lb = a;
+            if (b == 0) arr0 = a;
+            else if (b == 1) arr1 = a;
+            else arr2 = a;
+          }
+          if (bus) bus_free = lb;
+        }
+        auto arrival = [&](int b) {
+          if constexpr (POL == 0) return leave(b) + s_xfer[s_miss[g][b][mstar] * xs];
+          return b == 0 ? arr0 : (b == 1 ? arr1 : arr2);
+        };
         if (one_pass) {
-          if (my_addr >= 0 && my_m == mstar && my_x == kInf)
-            sp.vf[my_addr] = leave(my_b) + s_xfer[s_miss[g][my_b][mstar] * xs];
+          if (my_addr >= 0 && my_m == mstar && my_x == kInf) sp.vf[my_addr] = arrival(my_b);
         } else {
           for (int b = 0; b < nb; b++) {
             const int miss = s_miss[g][b][mstar];
             if (miss == 0) continue;
-            const int64_t arrive = leave(b) + s_xfer[miss * xs];
+            const int64_t arrive = arrival(b);
             const int64_t abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
             for (int a0 = 0; a0 < (1 << lg); a0 += G) {
               const int a = a0 + gl;
@@ -1006,7 +1036,11 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
       // write-around: on the host only, once that copy has arrived
       const int64_t abase = atom_base(nt, dmax, lvl, br[nb - 1], bc[nb - 1]);
       const int items = M << lg;
-      const int64_t host_at = (POL != 0 && cache != 0 && ms != 0) ? Tn + s_xfer[(1 << lg) * xs] : Tn;
+      int64_t host_at = (POL != 0 && cache != 0 && ms != 0) ? Tn + s_xfer[(1 << lg) * xs] : Tn;
+      if (bus && cache != 0 && ms != 0) {         // the host copy queues on the interconnect
+        host_at = max64(Tn, bus_free) + s_xfer[(1 << lg) * xs];
+        bus_free = host_at;
+      }
       for (int i0 = 0; i0 < items; i0 += G) {
         const int it = i0 + gl;
         if (it < items) {
@@ -1108,7 +1142,7 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
   const int per_wave = kWave / G;
   int waves = (v.nc + per_wave - 1) / per_wave;
   if (waves > slots) waves = slots;
-  const int pol = t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs || t.cache != 0 ? 1 : 0);
+  const int pol = t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs || t.cache != 0 || t.bus != 0 ? 1 : 0);
   const dim3 grid(waves), block(kWave);
 #define HESP_SIM_LAUNCH(GG, PP) hipLaunchKernelGGL((k_sim<GG, PP>), grid, block, 0, s, t, b, v, o, counter)
   if (G == 16) {

@@ -33,7 +33,7 @@ class PlatformC(ctypes.Structure):
 
 
 class Policy(ctypes.Structure):
-    _fields_ = [("order", i32), ("select", i32), ("cache", i32), ("seed", u64)]
+    _fields_ = [("order", i32), ("select", i32), ("cache", i32), ("seed", u64), ("bus", i32)]
 
 
 class Task(ctypes.Structure):

@@ -183,7 +183,7 @@ def test_unsupported_policies_rejected_before_device_work():
     pf = H.Platform.from_inputs(w.platform(), w.b, w.dmax)
     b = H.BatchC(1, 4, 1, None, None, None, None)
     out = H.OutputsC(None, None, None, None, None, None, None)
-    for pol in [(2, 0, 0), (0, 4, 0), (0, 0, 3), (0, 0, -1), (1, -1, 0)]:   # no such order / selection / caching
+    for pol in [(2, 0, 0), (0, 4, 0), (0, 0, 3), (0, 0, -1), (1, -1, 0), (0, 0, 0, 0, 2)]:   # no such setting
         rc = H.lib().hesp_simulate_batch(ctypes.c_void_p(1), ctypes.byref(pf.c), H.Policy(*pol), ctypes.byref(b),
                                          ctypes.byref(out), None)
         assert rc == H.HESP_EUNSUPPORTED, pol
