@@ -105,3 +105,48 @@ def test_chunk_pipeline_matches_single_chunk(H, torch):
         assert bool((st == 0).all().item())
         out.append(ms)
     assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+
+
+def test_graph_replay_split_trees(H, torch):
+    """Split-tree batches through a fixed-capacity plan: captured once, replayed
+    on new flags, equal to eager calls and to the oracle."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf_in = w.platform()
+    nt, dmax = 8, 2
+    pf = H.Platform.from_inputs(pf_in, w.b, dmax)
+    thr = I.split_threshold(w.p_num, w.p_den)
+    n, reps = 1024, 3
+    batches = [H.generate_tree_uniform(w.seed, 20_000 + r * n, n, nt, dmax, thr) for r in range(reps + 1)]
+    cap_t = cap_e = 0
+    for b in batches:
+        nt_, ne_ = H.count_tree_batch(b)
+        cap_t, cap_e = max(cap_t, int(nt_.max())), max(cap_e, int(ne_.max()))
+    flags = torch.empty_like(batches[0].flags)
+    flags.copy_(batches[0].flags)
+    tb = H.TreeBatch(n, nt, dmax, flags)
+    ms = torch.empty(n, dtype=torch.int64, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    plan = H.Plan(max_tasks=cap_t, max_edges=cap_e, group=16)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        H.simulate_tree_batch(plan, pf, tb, ms, st)     # sizes and allocates the workspace
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        H.simulate_tree_batch(plan, pf, tb, ms, st)
+    eager_plan = H.Plan()
+    ms2 = torch.empty_like(ms)
+    st2 = torch.empty_like(st)
+    for r in range(1, reps + 1):
+        flags.copy_(batches[r].flags)
+        g.replay()
+        torch.cuda.synchronize()
+        H.simulate_tree_batch(eager_plan, pf, batches[r], ms2, st2)
+        torch.cuda.synchronize()
+        assert bool((st == 0).all().item())
+        assert torch.equal(ms, ms2), r
+    host = I.tree_batch(w.seed, 48, nt, w.b, dmax, w.p_num, w.p_den, first=20_000 + reps * n)
+    want, _ = O.simulate_batch(pf_in, host, 8, tree=True)
+    assert np.array_equal(ms[:48].cpu().numpy(), want)
