@@ -161,7 +161,7 @@ def run_surrogate(args, torch, H):
     lh = loss.cpu().numpy()
     del X, MS, T
 
-    # held-out platforms: every partition simulated (the judge) and scored
+    # held-out platforms: every partition simulated exactly (the reference for the scores) and scored
     k_top = (n_all + 99) // 100
     Xh = torch.empty((n_all, 32), dtype=torch.int16, device=dev)
     y = torch.empty(n_all, dtype=torch.float32, device=dev)

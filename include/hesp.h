@@ -287,7 +287,7 @@ int hesp_argmin(const int64_t *d_makespan, int32_t n, int64_t *d_best, void *str
  * Not part of the paper's method: a small network that predicts a candidate's
  * normalised log-makespan from its split depths and the platform's rates, so
  * that only the best-scored proposals are simulated exactly (the exact
- * simulation above stays the judge).  Network: 32 inputs -> 256 -> 256 -> 256
+ * simulation above decides).  Network: 32 inputs -> 256 -> 256 -> 256
  * -> 1, ReLU; weights and activations bf16 (round to nearest even) wherever they
  * enter a product, fp32 accumulation on the MFMA units, fp32 biases, fp32
  * master weights updated by Adam (Kingma and Ba 2015; beta1 0.9, beta2 0.999,
@@ -349,7 +349,7 @@ int hesp_topk_score(const float *d_score, int32_t n, int32_t k, int32_t *d_idx, 
                     void *stream);
 
 /* ---- partition search --------------------------------------------------------
- * Rounds of proposals judged by the exact batched simulation (the iterative
+ * Rounds of proposals evaluated by the exact batched simulation (the iterative
  * solver of section 2.1 keeps the partition with the best simulated makespan).
  *   RANDOM:    every round draws `batch` fresh candidates (hesp_generate_uniform).
  *   GREEDY:    after `warm_rounds` random rounds of `warm_batch` candidates, each
