@@ -193,3 +193,144 @@ def solve(pf, nt, dmax, b, iters, lst=0, sampling=0, seed=0, policy=(0, 0), dept
         else:
             depth[st[0]] = st[1]
     return best_d, best_ms, trace, steps
+
+
+# ---------------------------------------------------------------- split-tree partitions
+#
+# The solver on split-tree partitions (a cluster may hold sub-clusters, section
+# 2.1): the clusters are the existing tasks of the uniform level-l tilings,
+# l < dmax ("nodes"; node x is split flag x of the partition).  Reading, as for
+# top-level clusters:
+# * span, start processor type and available parallelism of a node from the
+#   tasks under it (its leaves);
+# * an internal node proposes to merge back into its own task (p = 1): estimate
+#   = that task's time on the node's processor type; a leaf node proposes one
+#   more split (p = 1/2): estimate = ceil(work of its 2 x 2 blocked algorithm /
+#   min(available, max(1, task count >> 1))); score = span - estimate;
+# * All: every node; CP: nodes holding a task of the critical path; Shallow: the
+#   leaf nodes at the smallest level of any task;
+# * Hard / Soft over node order as before (the same draw); a split clears the
+#   flags of the new children, a merge clears the node's own flag.
+
+def _tree_nodes(nt, dmax):
+    """(level, cell, kind) of every node, in flag order."""
+    out = []
+    for l in range(dmax):
+        kinds, index = _kind_of_top(nt << l)
+        cells = sorted(index, key=index.get)
+        out += [(l, c, k) for c, k in zip(cells, kinds)]
+    return out
+
+
+def _children(cell):
+    K, I, J = cell
+    return [(a, b_, c) for a in (2 * K, 2 * K + 1) for b_ in (2 * I, 2 * I + 1) for c in (2 * J, 2 * J + 1)
+            if a <= b_ <= c]
+
+
+def partition_step_tree(pf, nt, dmax, flags, sched, cost, it, lst, sampling, seed):
+    """One partition stage on a split-tree partition: (node, action, score) with
+    action 1 = split, 0 = merge, or None."""
+    nodes = _tree_nodes(nt, dmax)
+    pos = {(l, c): x for x, (l, c, _) in enumerate(nodes)}
+    exists = np.zeros(len(nodes), bool)
+    for x, (l, c, _) in enumerate(nodes):
+        exists[x] = l == 0 or (exists[pos[(l - 1, (c[0] >> 1, c[1] >> 1, c[2] >> 1))]] and
+                               flags[pos[(l - 1, (c[0] >> 1, c[1] >> 1, c[2] >> 1))]] == 1)
+    tasks = np.asarray(sched.tasks)
+    start, finish, proc = sched.start.astype(np.int64), sched.finish.astype(np.int64), sched.proc
+    n = len(tasks)
+    # nodes holding each task: its cell shifted up to every level below dmax
+    holders = []
+    for (_, l, K, I, J) in tasks:
+        holders.append([pos[(lv, (int(K) >> (int(l) - lv), int(I) >> (int(l) - lv), int(J) >> (int(l) - lv)))]
+                        for lv in range(min(int(l), dmax - 1) + 1) if lv <= int(l)])
+    under = [[] for _ in nodes]
+    for t, hs in enumerate(holders):
+        for x in hs:
+            under[x].append(t)
+    P = pf.n_procs
+    # candidate list
+    if lst == 1:
+        preds = [[] for _ in range(n)]
+        for u, v in sched.edges:
+            preds[int(v)].append(int(u))
+        last = lambda xs: max(xs, key=lambda y: (int(finish[y]), -int(proc[y])))
+        t = last(range(n))
+        on = set()
+        while True:
+            on.update(holders[t])
+            if not preds[t]:
+                break
+            t = last(preds[t])
+        cand = [x for x in range(len(nodes)) if exists[x] and x in on]
+    elif lst == 2:
+        lmin = int(tasks[:, 1].min())
+        cand = [x for x in range(len(nodes)) if exists[x] and flags[x] == 0 and nodes[x][0] == lmin]
+    else:
+        cand = [x for x in range(len(nodes)) if exists[x]]
+    best = []
+    for x in cand:
+        idx = under[x]
+        l, cell, kind = nodes[x]
+        first = min(idx, key=lambda t: (int(start[t]), int(proc[t])))
+        t0 = int(start[first])
+        span = int(finish[idx].max()) - t0
+        pt = int(pf.proc_type[proc[first]])
+        if flags[x] == 1:
+            est, action = int(cost[pt, kind, l]), 0
+        else:
+            cnt = _fine_counts(kind, 1)
+            work = sum(cnt[k] * int(cost[pt, k, l + 1]) for k in range(4))
+            running = int(np.sum((start <= t0) & (t0 < finish)))
+            lanes = min(P - running + 1, max(1, sum(cnt) >> 1))
+            est, action = -(-work // lanes), 1
+        if span - est > 0:
+            best.append((x, action, span - est))
+    if not best:
+        return None
+    if sampling == 0:
+        return max(best, key=lambda y: (y[2], -y[0]))
+    total = sum(y[2] for y in best)
+    u = _draw(seed, 10, it) % total
+    acc = 0
+    for y in best:
+        acc += y[2]
+        if acc > u:
+            return y
+    return best[-1]
+
+
+def apply_tree_step(nt, dmax, flags, step):
+    x, action, _ = step
+    nodes = _tree_nodes(nt, dmax)
+    flags[x] = action
+    l, cell, _ = nodes[x]
+    if action == 1 and l + 1 < dmax:
+        pos = {(lv, c): y for y, (lv, c, _) in enumerate(nodes)}
+        for ch in _children(cell):
+            flags[pos[(l + 1, ch)]] = 0
+
+
+def solve_tree(pf, nt, dmax, b, iters, lst=0, sampling=0, seed=0, policy=(0, 0), flags0=None, cost=None):
+    """The solver on split-tree partitions; returns (best flags, best makespan,
+    makespans per iteration, steps (node, action, score) or None)."""
+    nf = sum(tet(nt << l) for l in range(dmax))
+    flags = np.zeros(nf, np.uint8) if flags0 is None else np.array(flags0, np.uint8)
+    if cost is None:
+        cost = np.zeros((pf.n_ptypes, 4, dmax + 1), np.int64)
+        for p in range(pf.n_ptypes):
+            for k in range(4):
+                for lv in range(dmax + 1):
+                    cost[p, k, lv] = O.task_time(k, b >> lv, int(pf.rmax[p][k]), int(pf.h[p]))
+    best_f, best_ms, trace, steps = flags.copy(), None, [], []
+    for it in range(iters):
+        s = O.simulate(pf, nt, dmax, b, flags, detail=True, policy=policy, tree=True)
+        trace.append(s.makespan)
+        if best_ms is None or s.makespan < best_ms:
+            best_ms, best_f = s.makespan, flags.copy()
+        st = partition_step_tree(pf, nt, dmax, flags, s, cost, it, lst, sampling, seed)
+        steps.append(st)
+        if st is not None:
+            apply_tree_step(nt, dmax, flags, st)
+    return best_f, best_ms, trace, steps

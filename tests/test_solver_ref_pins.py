@@ -2,6 +2,7 @@
 (oracle/solver_ref.py; section 2.1, "Iterative solver", with the readings
 stated in that module)."""
 import numpy as np
+import pytest
 
 from oracle import oracle as O
 from oracle import solver_ref as S
@@ -100,3 +101,55 @@ def test_critical_path_follows_the_last_arriving_dependence():
     assert S.candidates(10, dep, s, cl, 0) == list(range(10))
     dep2 = dep.copy(); dep2[[0, 4]] = 1
     assert S.candidates(10, dep2, s, cl, 2) == [1, 2, 3, 5, 6, 7, 8, 9]
+
+
+# ---------------------------------------------------------------- split-tree partitions
+
+@pytest.mark.parametrize("lst", [0, 1])
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_tree_solver_is_the_cluster_solver_at_depth_one(lst, sampling):
+    """With dmax = 1 the nodes are the top-level clusters, a split is depth 1 and
+    a merge depth 0: both solvers take the same steps (Shallow differs only once
+    every cluster is split, so it is left out)."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf = w.platform()
+    bt = I.uniform_batch(8, 3, 5, w.b, 1, 1, 2)
+    for r in range(3):
+        d0 = bt.candidate(r)
+        a = S.solve(pf, 5, 1, w.b, 10, lst, sampling, 4 + r, depth0=d0)
+        b = S.solve_tree(pf, 5, 1, w.b, 10, lst, sampling, 4 + r, flags0=I.tree_flags_from_depth(5, 1, d0))
+        assert a[2] == b[2]
+        assert [x if x is None else (x[0], x[1], x[2]) for x in a[3]] == b[3]
+
+
+def test_tree_solver_hand_derived_merge():
+    """One CPU, one 512 tile, the chol split and its first level-1 chol split
+    again (seven tasks in a chain, 1,518,252 ns).  Node 0 (the whole chol) merged
+    back would take 1,419,947: score 98,305; node 1 (the level-1 chol, tasks
+    0..218,454) merged: 218,454 - 185,686 = 32,768; the level-1 leaves would only
+    lose by splitting (one lane: trsm 4 x 81,920 + 2 x 163,840 = 655,360 >
+    557,056).  Hard merges node 0; the unsplit chol is then a fixed point."""
+    pf1 = I.make_platform([I.ProcType("cpu", 1, 32000, 32000, 64, False)], seed=0)
+    flags = np.array([1, 1, 0, 0, 0], np.uint8)
+    bf, bm, tr, steps = S.solve_tree(pf1, 1, 2, 512, 3, 0, 0, flags0=flags)
+    assert tr == [1518252, 1419947, 1419947]
+    assert steps == [(0, 0, 98305), None, None]
+    assert list(bf) == [0, 1, 0, 0, 0] and bm == 1419947
+    # Shallow: only the level-1 leaves, none of which gains
+    assert S.solve_tree(pf1, 1, 2, 512, 1, 2, 0, flags0=flags)[3] == [None]
+
+
+def test_tree_solver_trace_and_moves():
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf = w.platform()
+    nodes = S._tree_nodes(4, 2)
+    for lst in (0, 1, 2):
+        bf, bm, tr, steps = S.solve_tree(pf, 4, 2, w.b, 8, lst, 1, 2)
+        fl = np.zeros(I.tree_flag_count(4, 2), np.uint8)
+        for it in range(8):
+            assert tr[it] == O.simulate(pf, 4, 2, w.b, fl, detail=False, tree=True)
+            if steps[it] is not None:
+                x, action, score = steps[it]
+                assert score > 0 and fl[x] != action
+                S.apply_tree_step(4, 2, fl, steps[it])
+        assert bm == min(tr)
