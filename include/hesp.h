@@ -447,6 +447,28 @@ int hesp_solve(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy, con
                uint8_t *d_depth, uint8_t *d_best_depth, int64_t *d_best_makespan, int64_t *d_trace,
                int64_t *d_steps, void *stream);
 
+/* The same solver on split-tree partitions (section 2.1: every task cluster,
+ * nested ones included, may be merged back or repartitioned; Shallow takes the
+ * tasks of minimal depth).  The clusters ("nodes") are the existing tasks of the
+ * levels below dmax, node x being split flag x (hesp_tree_batch encoding):
+ *   an internal node (flag 1) proposes to merge back into its own task:
+ *     estimate = that task's time on the node's processor type;
+ *   a leaf node (flag 0) proposes one more split: estimate = ceil(work of its
+ *     2 x 2 blocked algorithm / min(avail, max(1, its task count >> 1)));
+ *   span, processor type and avail from the node's tasks as above; the score is
+ *   span - estimate; ALL: existing nodes; CP: those holding a task of the
+ *   critical path; SHALLOW: leaf nodes at the smallest level of any task;
+ *   HARD / SOFT over node order with the same draw as hesp_solve.
+ * A split sets the node's flag and clears its children's (they start as
+ * leaves); a merge clears the node's flag.  With dmax = 1 this is hesp_solve
+ * (except SHALLOW once every cluster is split).  d_flags [n_chains][flag_count]
+ * (device) holds the initial partitions and gets the last ones; d_steps gets
+ * (node, 1 split / 0 merge, score), node -1 when none.  Limits: 1 <= dmax,
+ * flag_count <= 4096 (nt <= 13 at dmax 2, nt <= 6 at dmax 3). */
+int hesp_solve_tree(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy, const hesp_solve_params *params,
+                    uint8_t *d_flags, uint8_t *d_best_flags, int64_t *d_best_makespan, int64_t *d_trace,
+                    int64_t *d_steps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

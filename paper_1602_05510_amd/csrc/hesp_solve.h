@@ -50,5 +50,38 @@ hipError_t launch_first(const SolveView& v, hipStream_t s);
 hipError_t launch_tasks(const SolveView& v, int64_t max_tasks, hipStream_t s);
 hipError_t launch_part(const SolveView& v, const SolveTables& t, hipStream_t s);
 
+// split-tree partitions: the clusters ("nodes") are the existing tasks of the
+// levels below dmax, one per split flag
+struct TreeSolveView {
+  int32_t n_chains, nt, dmax, n_nodes;         // n_nodes = split flags per chain (<= kMaxTop)
+  int32_t iter, iters, list, sampling;
+  uint64_t seed;
+  int64_t level_off[kLv + 1];                  // first node of each level
+  uint8_t* flags;                              // [n_chains][n_nodes] current partitions
+  uint8_t* best_flags;
+  int64_t* best_ms;
+  int64_t* trace;                              // [n_chains][iters] or null
+  int64_t* steps;                              // [n_chains][iters][3]: node, 1 split / 0 merge, score
+  int64_t stride;                              // tasks per chain in the schedule arrays
+  const int32_t* n_tasks;
+  const int32_t* proc;
+  const int64_t* start;
+  const int64_t* finish;
+  const int64_t* makespan;
+  const int32_t* status;
+  // workspace
+  uint32_t* lw;                                // [n_chains][finest blocks]: last writer
+  uint32_t* desc;                              // per task: packed descriptor
+  int32_t* par;                                // per task: latest-finishing predecessor
+  uint64_t* t0key;                             // [n_chains][n_nodes]
+  uint64_t* fin;                               // [n_chains][n_nodes]
+  uint64_t* lastkey;                           // [n_chains]
+  int32_t* lmin;                               // [n_chains]: smallest task level
+};
+
+hipError_t launch_tree_init(const TreeSolveView& v, hipStream_t s);
+hipError_t launch_tree_tasks(const TreeSolveView& v, hipStream_t s);
+hipError_t launch_tree_part(const TreeSolveView& v, const SolveTables& t, hipStream_t s);
+
 }  // namespace solve
 }  // namespace hesp

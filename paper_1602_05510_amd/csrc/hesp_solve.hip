@@ -19,7 +19,9 @@
 #include <stdint.h>
 
 #include "hesp_core.h"
+#include "hesp_device.h"
 #include "hesp_solve.h"
+#include "hesp_tree.h"
 
 namespace hesp {
 namespace solve {
@@ -208,6 +210,99 @@ __device__ __forceinline__ uint64_t block_max_u64(uint64_t x, uint64_t* s_red) {
   return m;
 }
 
+// Tasks running at each cluster's start t0 (start <= t0 < finish), for the
+// clusters tid * kPerThread + j (t0 = INT64_MAX for absent ones): the starts are
+// sorted in LDS; a task adds one over the sorted range [first t0 >= its start,
+// first t0 >= its finish), recorded as two differences, then one prefix sum.
+// The task whose finish key is lastkey goes to *s_last.  Every thread calls it.
+__device__ __forceinline__ void running_at_starts(int n_cl, const int64_t* t0, const int64_t* start,
+                                                  const int64_t* finish, const int32_t* proc, int64_t n,
+                                                  uint64_t lastkey, int64_t* s_q, int16_t* s_qc, int32_t* s_diff,
+                                                  int64_t* s_red, int32_t* s_last, int* run) {
+  const int tid = threadIdx.x, c0 = tid * kPerThread;
+  int q2 = 1;
+  while (q2 < n_cl) q2 <<= 1;
+  for (int j = 0; j < kPerThread; j++) {
+    const int c = c0 + j;
+    if (c < q2) {
+      s_q[c] = t0[j];
+      s_qc[c] = (int16_t)c;
+    }
+  }
+  for (int i = tid; i <= q2; i += kPartThreads) s_diff[i] = 0;
+  __syncthreads();
+  for (int k = 2; k <= q2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < q2; i += kPartThreads) {
+        const int x = i ^ j;
+        if (x > i) {
+          const int64_t a = s_q[i], b = s_q[x];
+          const int ca = s_qc[i], cb = s_qc[x];
+          const bool gt = a > b || (a == b && ca > cb);
+          if (((i & k) == 0) == gt) {
+            s_q[i] = b; s_q[x] = a;
+            s_qc[i] = (int16_t)cb; s_qc[x] = (int16_t)ca;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  auto lower = [&](int64_t t) {          // first sorted position with s_q >= t
+    int lo = 0, hi = q2;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_q[mid] < t) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  for (int64_t f = tid; f < n; f += kPartThreads) {
+    const int64_t st = start[f], fi = finish[f];
+    if (finish_key(fi, proc[f]) == lastkey) *s_last = (int32_t)f;
+    const int a = lower(st), b = lower(fi);
+    if (a < b) {
+      atomicAdd(&s_diff[a], 1);
+      atomicAdd(&s_diff[b], -1);
+    }
+  }
+  __syncthreads();
+  {
+    // inclusive scan of the differences: thread tid owns sorted positions tid*4 .. tid*4+3
+    int loc[kPerThread], sum = 0;
+    for (int j = 0; j < kPerThread; j++) {
+      const int i = tid * kPerThread + j;
+      sum += i < q2 ? s_diff[i] : 0;
+      loc[j] = sum;
+    }
+    const int l = tid & 63, w = tid >> 6;
+    int incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off, 64);
+      if (l >= off) incl += y;
+    }
+    __syncthreads();
+    if (l == 63) ((int*)s_red)[w] = incl;
+    __syncthreads();
+    int pre = incl - sum;
+    for (int q = 0; q < w; q++) pre += ((int*)s_red)[q];
+    __syncthreads();
+    // counts back to the clusters (s_diff is reused: count of cluster c at c)
+    for (int j = 0; j < kPerThread; j++) {
+      const int i = tid * kPerThread + j;
+      if (i < q2) loc[j] += pre;
+    }
+    __syncthreads();
+    for (int j = 0; j < kPerThread; j++) {
+      const int i = tid * kPerThread + j;
+      if (i < q2) s_diff[s_qc[i]] = loc[j];
+    }
+    __syncthreads();
+    for (int j = 0; j < kPerThread; j++)
+      if (c0 + j < n_cl) run[j] = s_diff[c0 + j];
+  }
+  __syncthreads();
+
+}
+
 __global__ void __launch_bounds__(kPartThreads) k_sv_part(SolveView v, SolveTables tb) {
   __shared__ int64_t s_q[kMaxTop];        // cluster start times, sorted
   __shared__ int16_t s_qc[kMaxTop];       // their clusters
@@ -267,89 +362,8 @@ __global__ void __launch_bounds__(kPartThreads) k_sv_part(SolveView v, SolveTabl
   if (tid == 0) s_last = -1;
   const uint64_t lastkey = v.lastkey[r];
 
-  // tasks running at every cluster's start (start <= t0 < finish): the starts
-  // are sorted; a task adds one over the sorted range [first t0 >= its start,
-  // first t0 >= its finish), recorded as two differences
-  int q2 = 1;
-  while (q2 < n_top) q2 <<= 1;
-  for (int j = 0; j < kPerThread; j++) {
-    const int c = c0 + j;
-    if (c < q2) {
-      s_q[c] = t0[j];
-      s_qc[c] = (int16_t)c;
-    }
-  }
-  for (int i = tid; i <= q2; i += kPartThreads) s_diff[i] = 0;
-  __syncthreads();
-  for (int k = 2; k <= q2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < q2; i += kPartThreads) {
-        const int x = i ^ j;
-        if (x > i) {
-          const int64_t a = s_q[i], b = s_q[x];
-          const int ca = s_qc[i], cb = s_qc[x];
-          const bool gt = a > b || (a == b && ca > cb);
-          if (((i & k) == 0) == gt) {
-            s_q[i] = b; s_q[x] = a;
-            s_qc[i] = (int16_t)cb; s_qc[x] = (int16_t)ca;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  auto lower = [&](int64_t t) {          // first sorted position with s_q >= t
-    int lo = 0, hi = q2;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (s_q[mid] < t) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-  };
-  for (int64_t f = tid; f < n; f += kPartThreads) {
-    const int64_t st = v.start[o + f], fi = v.finish[o + f];
-    if (finish_key(fi, v.proc[o + f]) == lastkey) s_last = (int32_t)f;
-    const int a = lower(st), b = lower(fi);
-    if (a < b) {
-      atomicAdd(&s_diff[a], 1);
-      atomicAdd(&s_diff[b], -1);
-    }
-  }
-  __syncthreads();
-  {
-    // inclusive scan of the differences: thread tid owns sorted positions tid*4 .. tid*4+3
-    int loc[kPerThread], sum = 0;
-    for (int j = 0; j < kPerThread; j++) {
-      const int i = tid * kPerThread + j;
-      sum += i < q2 ? s_diff[i] : 0;
-      loc[j] = sum;
-    }
-    const int l = tid & 63, w = tid >> 6;
-    int incl = sum;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int y = __shfl_up(incl, off, 64);
-      if (l >= off) incl += y;
-    }
-    __syncthreads();
-    if (l == 63) ((int*)s_red)[w] = incl;
-    __syncthreads();
-    int pre = incl - sum;
-    for (int q = 0; q < w; q++) pre += ((int*)s_red)[q];
-    __syncthreads();
-    // counts back to the clusters (s_diff is reused: count of cluster c at c)
-    for (int j = 0; j < kPerThread; j++) {
-      const int i = tid * kPerThread + j;
-      if (i < q2) loc[j] += pre;
-    }
-    __syncthreads();
-    for (int j = 0; j < kPerThread; j++) {
-      const int i = tid * kPerThread + j;
-      if (i < q2) s_diff[s_qc[i]] = loc[j];
-    }
-    __syncthreads();
-    for (int j = 0; j < kPerThread; j++)
-      if (c0 + j < n_top) run[j] = s_diff[c0 + j];
-  }
-  __syncthreads();
+  running_at_starts(n_top, t0, v.start + o, v.finish + o, v.proc + o, n, lastkey, s_q, s_qc, s_diff, s_red, &s_last,
+                    run);
 
   // candidate list
   int dmin = 255;
@@ -473,6 +487,273 @@ __global__ void k_sv_strided(int64_t stride, int32_t count, int64_t* off) {
   if (c <= count) off[c] = (int64_t)c * stride;
 }
 
+
+// ---------------------------------------------------------------- split-tree partitions
+
+// node x: its level, cell and kind (levels from the flag offsets)
+struct Node {
+  int lv, K, I, J, kind;
+};
+__device__ __forceinline__ Node node_of(const TreeSolveView& v, int x) {
+  Node d;
+  d.lv = 0;
+  while (d.lv + 1 < v.dmax && x >= v.level_off[d.lv + 1]) d.lv++;
+  const uint32_t c = top_cell(v.nt << d.lv, x - v.level_off[d.lv]);
+  d.K = cell_k(c);
+  d.I = cell_i(c);
+  d.J = cell_j(c);
+  d.kind = kind_of(d.K, d.I, d.J);
+  return d;
+}
+// flag index of the level-h ancestor (or self) of level-lv cell (K, I, J)
+__device__ __forceinline__ int64_t node_at(const TreeSolveView& v, int h, int lv, int K, int I, int J) {
+  const int sh = lv - h;
+  return v.level_off[h] + top_index(v.nt << h, K >> sh, I >> sh, J >> sh);
+}
+
+__global__ void __launch_bounds__(256) k_svt_init(TreeSolveView v) {
+  const int r = blockIdx.x;
+  for (int x = threadIdx.x; x < v.n_nodes; x += 256) {
+    v.t0key[(int64_t)r * v.n_nodes + x] = ~0ull;
+    v.fin[(int64_t)r * v.n_nodes + x] = 0;
+  }
+  if (threadIdx.x == 0) v.lastkey[r] = 0;
+}
+
+// one wavefront per chain walks its tasks in program order: descriptor, the
+// latest-finishing of the last writers of its blocks (a predecessor with the
+// latest finish, as over the whole dependence graph), bounds of the nodes
+// holding it, the last-finishing task and the smallest task level
+__global__ void __launch_bounds__(kWave) k_svt_tasks(TreeSolveView v) {
+  const int r = blockIdx.x;
+  if (v.status[r] != 0) return;
+  const int l = dev::lane();
+  const int nt = v.nt, dmax = v.dmax;
+  const int64_t o = (int64_t)r * v.stride;
+  const int64_t n_atoms = (int64_t)tri2(nt) << (2 * dmax);
+  uint32_t* lw = v.lw + (int64_t)r * n_atoms;
+  for (int64_t a = l; a < n_atoms; a += kWave) lw[a] = dev::kNil;
+  dev::wave_order();
+  uint32_t f = 0;
+  uint64_t last = 0;
+  int lmin = 255;
+  dev::walk_tree(nt, dmax, v.flags + (int64_t)r * v.n_nodes, [&](int kind, int lv, int K, int I, int J) {
+    const uint32_t t = f++;
+    if ((int64_t)t >= v.n_tasks[r]) return;            // the simulation counted the same tasks
+    uint64_t best = 0;
+    int32_t bid = -1;
+    dev::scan_task(lw, nt, dmax, kind, lv, K, I, J, t, [&](uint32_t p) {
+      const uint64_t k = finish_key(v.finish[o + p], v.proc[o + p]);
+      if (bid < 0 || k > best) {
+        best = k;
+        bid = (int32_t)p;
+      }
+    });
+    const int p = v.proc[o + t];
+    const int64_t st = v.start[o + t], fi = v.finish[o + t];
+    const uint64_t fk = finish_key(fi, p);
+    last = fk > last ? fk : last;
+    lmin = lv < lmin ? lv : lmin;
+    if (l == 0) {
+      v.par[o + t] = bid;
+      v.desc[o + t] = pack_desc(kind, lv, K, I, J);
+    }
+    const int nh = (lv < dmax - 1 ? lv : dmax - 1) + 1;   // nodes holding it: levels 0 .. min(lv, dmax-1)
+    if (l < nh) {
+      const int64_t x = node_at(v, l, lv, K, I, J);
+      atomicMin((unsigned long long*)&v.t0key[(int64_t)r * v.n_nodes + x], (unsigned long long)start_key(st, p));
+      atomicMax((unsigned long long*)&v.fin[(int64_t)r * v.n_nodes + x], (unsigned long long)fi);
+    }
+  });
+  if (l == 0) {
+    v.lastkey[r] = last;
+    v.lmin[r] = lmin;
+  }
+}
+
+__global__ void __launch_bounds__(kPartThreads) k_svt_part(TreeSolveView v, SolveTables tb) {
+  __shared__ int64_t s_q[kMaxTop];
+  __shared__ int16_t s_qc[kMaxTop];
+  __shared__ int32_t s_diff[kMaxTop + 1];
+  __shared__ int64_t s_red[kPartThreads / 64];
+  __shared__ uint32_t s_cp[kMaxTop / 32];
+  __shared__ int32_t s_last;
+  __shared__ int64_t s_pick[3];
+
+  const int r = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int it = v.iter;
+  const int nn = v.n_nodes;
+  uint8_t* flags = v.flags + (int64_t)r * nn;
+  int64_t* trace = v.trace ? v.trace + (int64_t)r * v.iters : nullptr;
+  int64_t* steps = v.steps ? v.steps + ((int64_t)r * v.iters + it) * 3 : nullptr;
+  if (v.status[r] != 0) {
+    if (tid == 0) {
+      if (trace) trace[it] = -1;
+      if (steps) { steps[0] = -1; steps[1] = -1; steps[2] = 0; }
+    }
+    return;
+  }
+  const int64_t ms = v.makespan[r];
+  const bool better = it == 0 || ms < v.best_ms[r];
+  __syncthreads();
+  if (better)
+    for (int x = tid; x < nn; x += kPartThreads) v.best_flags[(int64_t)r * nn + x] = flags[x];
+  if (tid == 0) {
+    if (trace) trace[it] = ms;
+    if (better) v.best_ms[r] = ms;
+  }
+
+  // nodes tid * kPerThread + j
+  int64_t t0[kPerThread], span[kPerThread];
+  int run[kPerThread], pt[kPerThread], state[kPerThread];   // state: 0 absent, 1 leaf, 2 internal
+  const int c0 = tid * kPerThread;
+  for (int j = 0; j < kPerThread; j++) {
+    const int x = c0 + j;
+    t0[j] = INT64_MAX;
+    span[j] = 0;
+    run[j] = 0;
+    pt[j] = 0;
+    state[j] = 0;
+    if (x < nn) {
+      const Node d = node_of(v, x);
+      bool ex = true;
+      for (int h = 0; h < d.lv; h++) ex = ex && flags[node_at(v, h, d.lv, d.K, d.I, d.J)] == 1;
+      if (ex) {
+        state[j] = flags[x] == 1 ? 2 : 1;
+        const uint64_t k = v.t0key[(int64_t)r * nn + x];
+        t0[j] = (int64_t)(k >> 6);
+        span[j] = (int64_t)v.fin[(int64_t)r * nn + x] - t0[j];
+        pt[j] = tb.proc_type[(int)(k & 63)];
+      }
+    }
+  }
+  for (int q = tid; q < kMaxTop / 32; q += kPartThreads) s_cp[q] = 0;
+  if (tid == 0) s_last = -1;
+  const int64_t o = (int64_t)r * v.stride;
+  const int64_t n = v.n_tasks[r];
+  running_at_starts(nn, t0, v.start + o, v.finish + o, v.proc + o, n, v.lastkey[r], s_q, s_qc, s_diff, s_red,
+                    &s_last, run);
+  if (v.list == 1 && tid == 0) {
+    // critical path: every node holding one of its tasks
+    int32_t x = s_last;
+    for (int64_t guard = 0; x >= 0 && guard < n; guard++) {
+      const uint32_t d = v.desc[o + x];
+      const int lv = desc_level(d), nh = (lv < v.dmax - 1 ? lv : v.dmax - 1) + 1;
+      for (int h = 0; h < nh; h++) {
+        const int64_t y = node_at(v, h, lv, desc_K(d), desc_I(d), desc_J(d));
+        s_cp[y >> 5] |= 1u << (y & 31);
+      }
+      x = v.par[o + x];
+    }
+  }
+  __syncthreads();
+
+  // proposals: an internal node merges (its own task), a leaf one splits once
+  const int lmin = v.lmin[r];
+  int64_t score[kPerThread];
+  int act[kPerThread];
+  for (int j = 0; j < kPerThread; j++) {
+    const int x = c0 + j;
+    score[j] = 0;
+    act[j] = -1;
+    if (state[j] == 0) continue;
+    const Node d = node_of(v, x);
+    bool in = true;
+    if (v.list == 1) in = (s_cp[x >> 5] >> (x & 31)) & 1u;
+    if (v.list == 2) in = state[j] == 1 && d.lv == lmin;
+    if (!in) continue;
+    int64_t est;
+    int a;
+    if (state[j] == 2) {
+      est = tb.cost[pt[j]][d.kind][d.lv];
+      a = 0;
+    } else {
+      int64_t cnt[4];
+      kind_counts(d.kind, 1, cnt);
+      int64_t work = 0;
+      for (int k = 0; k < 4; k++) work += cnt[k] * tb.cost[pt[j]][k][d.lv + 1];
+      int64_t width = (cnt[0] + cnt[1] + cnt[2] + cnt[3]) >> 1;
+      width = width < 1 ? 1 : width;
+      const int64_t avail = (int64_t)tb.n_procs - run[j] + 1;
+      const int64_t lanes = avail < width ? avail : width;
+      est = (work + lanes - 1) / lanes;
+      a = 1;
+    }
+    if (span[j] - est > 0) {
+      score[j] = span[j] - est;
+      act[j] = a;
+    }
+  }
+
+  // selection (as for top-level clusters)
+  if (tid == 0) { s_pick[0] = -1; s_pick[1] = -1; s_pick[2] = 0; }
+  if (v.sampling == 0) {
+    uint64_t key = 0;
+    for (int j = 0; j < kPerThread; j++)
+      if (act[j] >= 0) {
+        const uint64_t k = ((uint64_t)score[j] << 12) | (uint64_t)(kMaxTop - 1 - (c0 + j));
+        key = k > key ? k : key;
+      }
+    const uint64_t bestk = block_max_u64(key, (uint64_t*)s_red);
+    if (bestk != 0) {
+      const int x = kMaxTop - 1 - (int)(bestk & (kMaxTop - 1));
+      if (x >= c0 && x < c0 + kPerThread) {
+        s_pick[0] = x;
+        s_pick[1] = act[x - c0];
+        s_pick[2] = score[x - c0];
+      }
+    }
+  } else {
+    int64_t mine = 0;
+    for (int j = 0; j < kPerThread; j++) mine += score[j];
+    const int l = tid & 63, w = tid >> 6;
+    int64_t incl = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(incl, off, 64);
+      if (l >= off) incl += y;
+    }
+    __syncthreads();
+    if (l == 63) s_red[w] = incl;
+    __syncthreads();
+    int64_t pre = 0, total = 0;
+    for (int q = 0; q < kPartThreads / 64; q++) {
+      if (q < w) pre += s_red[q];
+      total += s_red[q];
+    }
+    pre += incl - mine;
+    if (total > 0) {
+      const int64_t u = (int64_t)(sm_draw(v.seed + (uint64_t)r, 10, (uint64_t)it) % (uint64_t)total);
+      int64_t acc = pre;
+      for (int j = 0; j < kPerThread; j++) {
+        if (act[j] < 0) continue;
+        if (acc <= u && u < acc + score[j]) {
+          s_pick[0] = c0 + j;
+          s_pick[1] = act[j];
+          s_pick[2] = score[j];
+        }
+        acc += score[j];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (steps) { steps[0] = s_pick[0]; steps[1] = s_pick[1]; steps[2] = s_pick[2]; }
+    if (s_pick[0] >= 0) {
+      const int x = (int)s_pick[0];
+      flags[x] = (uint8_t)s_pick[1];
+      const Node d = node_of(v, x);
+      if (s_pick[1] == 1 && d.lv + 1 < v.dmax)
+        // the new children start as leaves
+        for (int c = 0; c < fine_count(d.kind, 1); c++) {
+          int q, rr, cc;
+          local_coords(d.kind, 2, c, q, rr, cc);
+          flags[node_at(v, d.lv + 1, d.lv + 1, 2 * d.K + q, 2 * d.I + rr, 2 * d.J + cc)] = 0;
+        }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_strided(int64_t stride, int32_t count, int64_t* off, hipStream_t s) {
@@ -491,6 +772,21 @@ hipError_t launch_tasks(const SolveView& v, int64_t max_tasks, hipStream_t s) {
   nb = nb < 8 ? nb : 8;
   if (nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_sv_tasks, dim3((unsigned)nb, v.n_chains), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_init(const TreeSolveView& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_svt_init, dim3(v.n_chains), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_tasks(const TreeSolveView& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_svt_tasks, dim3(v.n_chains), dim3(kWave), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_part(const TreeSolveView& v, const SolveTables& t, hipStream_t s) {
+  hipLaunchKernelGGL(k_svt_part, dim3(v.n_chains), dim3(kPartThreads), 0, s, v, t);
   return hipGetLastError();
 }
 

@@ -142,6 +142,7 @@ def lib():
             "hesp_simulate_tree_batch": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(TreeBatchC),
                                          ctypes.POINTER(OutputsC), P],
             "hesp_solve": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(SolveParams), P, P, P, P, P, P],
+            "hesp_solve_tree": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(SolveParams), P, P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -539,4 +540,26 @@ def solve(plan: Plan, pf: Platform, nt: int, dmax: int, depth, iters: int, lst: 
     sp = SolveParams(B, nt, dmax, iters, lst, sampling, seed)
     _check("hesp_solve", lib().hesp_solve(plan.h, ctypes.byref(pf.c), Policy(*policy), ctypes.byref(sp), _dev(depth),
                                           _dev(best), _dev(best_ms), _dev(trace), _dev(steps), _stream(stream)))
+    return best, best_ms, trace, steps
+
+
+def solve_tree(plan: Plan, pf: Platform, nt: int, dmax: int, flags, iters: int, lst: int = LIST_ALL,
+               sampling: int = SAMPLE_HARD, seed: int = 0, policy=(0, 0, 0), stream=None):
+    """Runs hesp_solve_tree on the chains whose initial split-tree partitions are
+    the rows of `flags` (uint8 device tensor [n_chains, tree_flag_count], updated in
+    place); returns (best flags, best makespans, makespan per iteration, steps
+    [n_chains, iters, 3] = (node, 1 split / 0 merge, score))."""
+    import torch
+    nf = tree_flag_count(nt, dmax)
+    if flags.dtype != torch.uint8 or flags.dim() != 2 or flags.shape[1] != nf or not flags.is_contiguous():
+        raise ValueError("flags must be a contiguous uint8 tensor [n_chains, tree_flag_count(nt, dmax)]")
+    B = int(flags.shape[0])
+    best = torch.empty_like(flags)
+    best_ms = torch.empty(B, dtype=torch.int64, device=flags.device)
+    trace = torch.empty((B, iters), dtype=torch.int64, device=flags.device)
+    steps = torch.empty((B, iters, 3), dtype=torch.int64, device=flags.device)
+    sp = SolveParams(B, nt, dmax, iters, lst, sampling, seed)
+    _check("hesp_solve_tree", lib().hesp_solve_tree(plan.h, ctypes.byref(pf.c), Policy(*policy), ctypes.byref(sp),
+                                                    _dev(flags), _dev(best), _dev(best_ms), _dev(trace), _dev(steps),
+                                                    _stream(stream)))
     return best, best_ms, trace, steps

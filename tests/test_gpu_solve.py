@@ -37,7 +37,8 @@ def _run(H, torch, pf_in, nt, dmax, b, depth0, iters, lst, sampling, seed, polic
 
 def _check_chain(pf_in, nt, dmax, b, depth0, iters, lst, sampling, seed, got, r, policy=(0, 0, 0)):
     best, best_ms, trace, steps, last = got
-    pol = (policy[0], policy[1], policy[3] if len(policy) > 3 else 0)
+    # library policy (order, select, cache, seed) -> oracle policy (order, select, seed, cache)
+    pol = (policy[0], policy[1], policy[3] if len(policy) > 3 else 0, policy[2])
     bd, bm, tr, st = S.solve(pf_in, nt, dmax, b, iters, lst, sampling, seed + r, policy=pol, depth0=depth0[r])
     assert list(trace[r]) == tr, (r, lst, sampling)
     want_steps = [(-1, -1, 0) if x is None else x for x in st]
@@ -123,3 +124,73 @@ def test_sixteen_tiles_sampled_chains(H, torch):
     for r in (0, 37):
         _check_chain(pf_in, nt, dmax, w.b, depth0, iters, 0, 1, seed, got, r)
     assert (got[1] <= got[2][:, 0]).all()
+
+
+# ---------------------------------------------------------------- split-tree partitions
+
+def _run_tree(H, torch, pf_in, nt, dmax, b, flags0, iters, lst, sampling, seed, policy=(0, 0, 0)):
+    pf = H.Platform.from_inputs(pf_in, b, dmax)
+    f = torch.from_numpy(np.ascontiguousarray(flags0, np.uint8)).cuda()
+    best, best_ms, trace, steps = H.solve_tree(H.Plan(), pf, nt, dmax, f, iters, lst, sampling, seed, policy=policy)
+    torch.cuda.synchronize()
+    return (best.cpu().numpy(), best_ms.cpu().numpy(), trace.cpu().numpy(), steps.cpu().numpy(), f.cpu().numpy())
+
+
+def _check_tree_chain(pf_in, nt, dmax, b, flags0, iters, lst, sampling, seed, got, r, policy=(0, 0, 0)):
+    best, best_ms, trace, steps, last = got
+    # library policy (order, select, cache, seed) -> oracle policy (order, select, seed, cache)
+    pol = (policy[0], policy[1], policy[3] if len(policy) > 3 else 0, policy[2])
+    bf, bm, tr, st = S.solve_tree(pf_in, nt, dmax, b, iters, lst, sampling, seed + r, policy=pol, flags0=flags0[r])
+    assert list(trace[r]) == tr, (r, lst, sampling)
+    want = [(-1, -1, 0) if x is None else x for x in st]
+    assert [tuple(int(v) for v in s) for s in steps[r]] == want, (r, lst, sampling)
+    assert int(best_ms[r]) == bm and np.array_equal(best[r], bf)
+    fl = np.array(flags0[r], np.uint8)
+    for x in st:
+        if x is not None:
+            S.apply_tree_step(nt, dmax, fl, x)
+    assert np.array_equal(last[r], fl)
+
+
+def test_tree_solver_hand_derived_merge(H, torch):
+    pf_in = I.make_platform([I.ProcType("cpu", 1, 32000, 32000, 64, False)], seed=0)
+    got = _run_tree(H, torch, pf_in, 1, 2, 512, np.array([[1, 1, 0, 0, 0]]), 3, 0, 0, 0)
+    assert list(got[2][0]) == [1518252, 1419947, 1419947]
+    assert [tuple(s) for s in got[3][0]] == [(0, 0, 98305), (-1, -1, 0), (-1, -1, 0)]
+
+
+@pytest.mark.parametrize("lst", [0, 1, 2])
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_tree_chains_match_reference(H, torch, lst, sampling):
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf_in = w.platform()
+    nt, dmax, B, iters, seed = 5, 2, 5, 10, 300 + 10 * lst + sampling
+    tb = I.tree_batch(seed, B, nt, w.b, dmax, 1, 3)
+    flags0 = tb.depth.reshape(B, -1)
+    got = _run_tree(H, torch, pf_in, nt, dmax, w.b, flags0, iters, lst, sampling, seed)
+    for r in range(B):
+        _check_tree_chain(pf_in, nt, dmax, w.b, flags0, iters, lst, sampling, seed, got, r)
+
+
+def test_tree_chains_depth_three_and_other_heuristics(H, torch):
+    w = I.WORKLOADS["chol4x4_b512_d1"]
+    pf_in = w.platform()
+    nt, dmax, B, iters, seed = 3, 3, 4, 8, 17
+    tb = I.tree_batch(seed, B, nt, w.b, dmax, 1, 2)
+    flags0 = tb.depth.reshape(B, -1)
+    for policy in ((0, 0, 0), (1, 1, 2, 0), (0, 3, 0, 0)):
+        got = _run_tree(H, torch, pf_in, nt, dmax, w.b, flags0, iters, 0, 1, seed, policy=policy)
+        for r in range(B):
+            _check_tree_chain(pf_in, nt, dmax, w.b, flags0, iters, 0, 1, seed, got, r, policy=policy)
+
+
+def test_tree_chains_twelve_tiles_sampled(H, torch):
+    """nt = 12 (364 + 2,600 nodes), depths 0..2, 48 chains; two recomputed."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf_in = w.platform()
+    nt, dmax, B, iters, seed = 12, 2, 48, 8, 5
+    tb = I.tree_batch(seed, B, nt, w.b, dmax, 1, 4)
+    flags0 = tb.depth.reshape(B, -1)
+    got = _run_tree(H, torch, pf_in, nt, dmax, w.b, flags0, iters, 1, 1, seed)
+    for r in (0, 29):
+        _check_tree_chain(pf_in, nt, dmax, w.b, flags0, iters, 1, 1, seed, got, r)

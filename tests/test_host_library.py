@@ -204,3 +204,17 @@ def test_solve_argument_errors_need_no_gpu():
     assert call(H.SolveParams(1, 4, 2, 4, 0, 0, 0)) == H.HESP_EINVAL            # dmax above the tables
     assert call(H.SolveParams(1, 29, 0, 4, 0, 0, 0)) == H.HESP_EUNSUPPORTED     # tet(29) > 4096 clusters
     assert "hesp_solve" in H.lib().hesp_last_error().decode()
+
+
+
+def test_solve_tree_argument_errors_need_no_gpu():
+    w = I.WORKLOADS["chol4x4_b512_d1"]
+    pf = H.Platform.from_inputs(w.platform(), w.b, 2)
+    fake = ctypes.c_void_p(1)
+    def call(sp, plan=fake):
+        return H.lib().hesp_solve_tree(plan, ctypes.byref(pf.c), H.Policy(0, 0, 0), ctypes.byref(sp), fake, fake,
+                                       fake, None, None, None)
+    assert call(H.SolveParams(1, 4, 1, 4, 0, 0, 0), plan=None) == H.HESP_EINVAL
+    assert call(H.SolveParams(1, 4, 0, 4, 0, 0, 0)) == H.HESP_EINVAL            # no level below dmax
+    assert call(H.SolveParams(1, 14, 2, 4, 0, 0, 0)) == H.HESP_EUNSUPPORTED     # 560 + 4,060 > 4,096 flags
+    assert call(H.SolveParams(1, 4, 2, 4, 5, 0, 0)) == H.HESP_EINVAL            # no such list
