@@ -345,6 +345,79 @@ LIST_NAMES = {0: "All", 1: "CP", 2: "Shallow"}
 SAMPLING_NAMES = {0: "Hard", 1: "Soft"}
 
 
+def run_solver_tree(args, torch, H):
+    """The iterative solver on split-tree partitions (nodes of every level below
+    dmax are clusters) on a 12x12-tile instance of the 16x16 platform, beside the
+    per-cluster solver on the same instance; value = chain-iterations per second
+    of All/Soft; the CPU reference is timed on one chain and its trajectory compared."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    nt, dmax, b = 12, w.dmax, w.b
+    B, iters, seed = args.solve_chains, args.solve_iters, args.solve_seed
+    pf_in = w.platform()
+    pf = H.Platform.from_inputs(pf_in, b, dmax)
+    nf = I.tree_flag_count(nt, dmax)
+    init = I.tree_batch(seed, B, nt, b, dmax, 1, 4).depth.reshape(B, nf).copy()
+    init[0] = 0
+    f0 = torch.from_numpy(init).cuda()
+    plan = H.Plan()
+
+    def once(lst, samp):
+        f = f0.clone()
+        out = H.solve_tree(plan, pf, nt, dmax, f, iters, lst, samp, seed)
+        torch.cuda.synchronize()
+        return out
+
+    for _ in range(args.warmup):
+        once(0, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        best, best_ms, trace, steps = once(0, 1)
+    dt = time.perf_counter() - t0
+    print(f"tree solver All/Soft: {B} chains x {iters} iterations, {1e3 * dt / args.steps:.1f} ms per call",
+          file=sys.stderr, flush=True)
+    quality = []
+    for lst in (0, 1, 2):
+        for samp in (0, 1):
+            bf, bm, tr, st = (x.cpu().numpy() for x in once(lst, samp))
+            quality.append({"list": LIST_NAMES[lst], "sampling": SAMPLING_NAMES[samp],
+                            "best_makespan": int(bm.min()), "mean_best_over_initial": float(np.mean(bm / tr[:, 0])),
+                            "merges": int((st[:, :, 1] == 0).sum()), "splits": int((st[:, :, 1] == 1).sum())})
+    # the per-cluster solver on the same instance, chains from random depths
+    d_init = I.uniform_batch(seed, B, nt, b, dmax, 1, 4).depth.reshape(B, I.tet(nt)).copy()
+    d_init[0] = 0
+    cluster = {}
+    for lst in (0, 1):
+        d = torch.from_numpy(d_init).cuda()
+        _, bm, _, _ = H.solve(plan, pf, nt, dmax, d, iters, lst, 1, seed)
+        cluster[LIST_NAMES[lst] + "/Soft"] = int(bm.min().item())
+    tr0 = trace.cpu().numpy()
+    cpu = exact = None
+    if not args.no_cpu_baseline:
+        from oracle import solver_ref as S
+        r = min(B - 1, 3)
+        t1 = time.perf_counter()
+        S.solve_tree(pf_in, nt, dmax, b, 1, 0, 1, seed + r, flags0=init[r])
+        one = time.perf_counter() - t1
+        k = int(max(1, min(iters, args.cpu_budget / max(one, 1e-6))))
+        t1 = time.perf_counter()
+        _, _, want, _ = S.solve_tree(pf_in, nt, dmax, b, k, 0, 1, seed + r, flags0=init[r])
+        t_cpu = time.perf_counter() - t1
+        exact = list(tr0[r, :k]) == want
+        cpu = {"value": k / t_cpu, "unit": "chain-iterations/s", "cores": 1, "kind": "oracle",
+               "sample": f"chain {r}, {k} iterations of All/Soft on split trees"}
+    rec = {"metric": "iterative solver throughput on split-tree partitions (All/Soft)",
+           "value": B * iters * args.steps / dt, "unit": "chain-iterations/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"{w.name} platform, {nt}x{nt} tiles, split-tree solver", "nt": nt, "b": b,
+                      "dmax": dmax, "chains": B, "iterations": iters, "nodes_per_chain": nf, "seed": seed,
+                      "parallelism": "none (1 GPU)"},
+           "cpu_baseline": cpu, "bit_exact_vs_oracle": exact, "quality": quality,
+           "per_cluster_solver_best": cluster, "unsplit_makespan": int(tr0[0, 0])}
+    print(json.dumps(rec), flush=True)
+
+
 def run_solver(args, torch, H):
     """The iterative scheduler-partitioner (section 2.1) on the 16x16 instance:
     many independent chains (one unsplit, the others from random initial
@@ -488,6 +561,8 @@ def main():
         return run_policy_sweep(args, torch, H)
     if args.workload == "iterative_solver":
         return run_solver(args, torch, H)
+    if args.workload == "iterative_solver_tree":
+        return run_solver_tree(args, torch, H)
     w = I.WORKLOADS[args.workload]
     n = args.n_cand or w.n_cand
     pf_in = w.platform()
