@@ -153,3 +153,58 @@ def test_tree_solver_trace_and_moves():
                 assert score > 0 and fl[x] != action
                 S.apply_tree_step(4, 2, fl, steps[it])
         assert bm == min(tr)
+
+
+def test_hard_and_soft_choice_on_a_chain():
+    """nt = 2, nothing split, two identical CPUs: the four tasks form a chain.
+    Scores (split to depth 1, two lanes each): chol 1,419,947 - 742,742 =
+    677,205; trsm 4,259,840 - ceil(4 x 557,056 + 2 x 1,114,112) / 2) =
+    2,031,616; syrk the same; chol(1) 677,205; sum 5,417,642.  Hard takes the
+    trsm (tie with the syrk, lower cluster); Soft takes the first cluster whose
+    running sum (677,205 / 2,708,821 / 4,740,437 / 5,417,642) exceeds
+    u = draw(seed, 10, 0) mod 5,417,642."""
+    pf = I.make_platform([I.ProcType("cpu", 2, 32000, 32000, 64, False)], seed=0)
+    hard = S.solve(pf, 2, 1, 512, 1, 0, 0)
+    assert hard[2] == [11359574] and hard[3] == [(1, 1, 2031616)]
+    ends = [677205, 2708821, 4740437, 5417642]
+    scores = [677205, 2031616, 2031616, 677205]
+    seen = set()
+    for seed in range(24):
+        u = S._draw(seed, 10, 0) % 5417642
+        want = next(c for c in range(4) if u < ends[c])
+        got = S.solve(pf, 2, 1, 512, 1, 0, 1, seed)[3][0]
+        assert got == (want, 1, scores[want]), seed
+        seen.add(want)
+    assert seen == {0, 1, 2, 3}
+
+
+def test_tree_moves_change_the_task_count_as_stated():
+    """A split replaces a leaf by its 2 x 2 blocked algorithm (4, 6 or 8 tasks,
+    all leaves); a merge replaces everything under a node by one task."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf = w.platform()
+    fl = I.tree_batch(12, 1, 4, w.b, 2, 1, 2).depth.copy()    # stale flags under leaves included
+    nodes = S._tree_nodes(4, 2)
+    bf, bm, tr, steps = S.solve_tree(pf, 4, 2, w.b, 12, 0, 1, 5, flags0=fl)
+    cur = fl.copy()
+    n_prev = O.simulate(pf, 4, 2, w.b, cur, tree=True).n_tasks
+    kinds_fine = {0: 4, 1: 6, 2: 6, 3: 8}
+    moved = 0
+    for st in steps:
+        if st is None:
+            continue
+        x, action, _ = st
+        lv, cell, kind = nodes[x]
+        s_before = O.simulate(pf, 4, 2, w.b, cur, tree=True)
+        under = sum(1 for (_, l, K, i, j) in s_before.tasks
+                    if int(l) >= lv and
+                    (int(K) >> (int(l) - lv), int(i) >> (int(l) - lv), int(j) >> (int(l) - lv)) == cell)
+        S.apply_tree_step(4, 2, cur, st)
+        n_now = O.simulate(pf, 4, 2, w.b, cur, tree=True).n_tasks
+        if action == 1:
+            assert under == 1 and n_now == n_prev + kinds_fine[kind] - 1
+        else:
+            assert n_now == n_prev - under + 1
+        n_prev = n_now
+        moved += 1
+    assert moved >= 6
