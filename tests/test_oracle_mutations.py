@@ -54,6 +54,10 @@ MUTANTS = {
                                    "                        if (0) go = bus_at;"),
     "bus_host_copy_free": ("                int64_t go = Tn > bus_free ? Tn : bus_free;",
                            "                int64_t go = Tn;"),
+    "tree_ignores_deeper_flags": ("    if (l < tr->dmax && tr->flags[tr->off[l] + tr->index[l][((size_t)K * N + I) * N + J]]) {",
+                                  "    if (l < 1 && l < tr->dmax && tr->flags[tr->off[l] + tr->index[l][((size_t)K * N + I) * N + J]]) {"),
+    "tree_children_take_parent_kind": ("            if (emit_tree(out, tr, top, kids.v[c].type, l + 1, kids.v[c].K, kids.v[c].I, kids.v[c].J)) {",
+                                       "            if (emit_tree(out, tr, top, type, l + 1, kids.v[c].K, kids.v[c].I, kids.v[c].J)) {"),
     "cost_floor": ("static int64_t ceil_div_pos(int64_t a, int64_t b) { return a / b + (a % b != 0); }",
                    "static int64_t ceil_div_pos(int64_t a, int64_t b) { return a / b; }"),
     "rank_without_own_cost": ("rank[t] = W[t] + best;", "rank[t] = best;"),
@@ -108,6 +112,7 @@ def _pins_pass():
             for (kind, lvl, K, I_, J, p, st, fi) in e["schedule"]:
                 if got.get((KIND[kind], lvl, K, I_, J)) != (p, st, fi):
                     return False
+        pf1b = I.make_platform([I.ProcType("cpu", 1, 32000, 32000, 64, False)], seed=0)
         # closed-form counts, single-processor sum, lower bounds on a split case
         pf1 = I.make_platform([I.ProcType("cpu", 1, 27000, 27000, 64, False)], seed=0)
         dep = np.array([1, 0, 1, 0, 1, 1, 0, 1, 0, 1], np.uint8)
@@ -145,6 +150,13 @@ def _pins_pass():
             py = PY.Sim(3, 1, 256, dep4, pf4.proc_type, pf4.proc_mem, pf4.n_mem, pf4.rmax, pf4.h, pf4.shared_memory)
             if py.run(cache="WA", bus=True)[2] != list(r.start):
                 return False
+        # split trees: the hand-derived partial split (seven tasks on three levels)
+        fl = np.array([1, 1, 0, 0, 0], np.uint8)
+        st = O.simulate(pf1b, 1, 2, 512, fl, tree=True)
+        if [tuple(int(x) for x in t) for t in st.tasks] != [(0, 2, 0, 0, 0), (1, 2, 0, 0, 1), (2, 2, 0, 1, 1),
+                                                             (0, 2, 1, 1, 1), (1, 1, 0, 0, 1), (2, 1, 0, 1, 1),
+                                                             (0, 1, 1, 1, 1)] or st.makespan != 1518252:
+            return False
         # every top-level task of a 3x3 split DAG depends on something except chol0
         if len(s.edges) < s.n_tasks - 1:
             return False
