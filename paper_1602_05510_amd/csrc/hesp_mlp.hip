@@ -19,6 +19,9 @@ namespace {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(2))) short i16x2;
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __builtin_bit_cast(uint32_t, f);
@@ -27,6 +30,16 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+
+// bf16(relu(a)) | bf16(relu(b)) << 16: the hardware conversion rounds to nearest
+// even; ReLU then acts on the bf16 bit patterns as signed 16-bit integers (a
+// negative value or -0 has its sign bit set and becomes +0), which equals
+// rounding relu(a) and relu(b) for every finite input.
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
+  const bf16x2 h = __builtin_convertvector((f32x2{a, b}), bf16x2);
+  const i16x2 r = __builtin_elementwise_max(__builtin_bit_cast(i16x2, h), (i16x2{0, 0}));
+  return __builtin_bit_cast(uint32_t, r);
+}
 
 // ---------------------------------------------------------------- GEMM
 // C[M][N] = opA[M][K] * opB[K][N], bf16 inputs, fp32 accumulation.
@@ -116,26 +129,40 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int kc, const uint16
 // load.  Eight 16x16 blocks x two column blocks of accumulators per wave (64
 // registers), so four waves fit on each SIMD; two workgroups share a CU's LDS.
 // The last layer's dot with w4 is reduced across lanes and waves through LDS.
-constexpr int FM = 128, FLD = kHidden + 8, FWAVES = 8;
+constexpr int FM = 128, FWAVES = 8;
+
+// Activation tile layout: row-major, 256 bf16 per row with no padding, the
+// sixteen-byte chunks of a row permuted by an XOR with a row-dependent mask.
+// The mask's bits 4..2 take eight distinct values over eight consecutive rows,
+// so the sixteen-byte operand reads of a wave (16 rows x 4 chunks) spread evenly
+// over the banks; its bits 2..0 are distinct over eight rows too, so the eight-
+// byte epilogue stores of 16 rows meet at most two to a bank.
+__device__ __forceinline__ int sh_off(int row, int col) {
+  const int f = ((row & 7) << 2) | ((row >> 1) & 3);
+  return row * kHidden + (((col >> 3) ^ f) << 3) + (col & 7);
+}
 
 // Products are formed transposed (A operand = weight rows, B operand =
 // activation rows), so lane l of a 16x16 block holds output row (l % 16) and four
 // consecutive output columns 4 (l / 16) .. + 3: one 8-byte LDS store each.
 // Wave w owns all 128 rows and columns [32 w, 32 w + 32): each weight fragment
 // read from L2 feeds 8 products, each activation fragment read from LDS feeds 2.
-__device__ __forceinline__ void fwd_epilogue(const f32x4 (&acc)[8][2], const float* __restrict__ bias, int w, int l,
-                                             uint16_t (*sH)[FLD]) {
+// The accumulators start from the layer's bias, so the epilogue only applies the
+// ReLU, rounds to bf16 and stores.
+__device__ __forceinline__ void fwd_epilogue(const f32x4 (&acc)[8][2], int w, int l, uint16_t* sH) {
   for (int cb = 0; cb < 2; cb++) {
     const int col = w * 32 + cb * 16 + (l >> 4) * 4;
-    const f32x4 bv = *(const f32x4*)(bias + col);
-    for (int rb = 0; rb < 8; rb++) {
-      uint32_t q[2];
-      for (int h = 0; h < 2; h++) {
-        const float v0 = acc[rb][cb][2 * h] + bv[2 * h], v1 = acc[rb][cb][2 * h + 1] + bv[2 * h + 1];
-        q[h] = (uint32_t)f2bf(v0 > 0.f ? v0 : 0.f) | ((uint32_t)f2bf(v1 > 0.f ? v1 : 0.f) << 16);
-      }
-      *(uint2*)&sH[rb * 16 + (l & 15)][col] = make_uint2(q[0], q[1]);
-    }
+    for (int rb = 0; rb < 8; rb++)
+      *(uint2*)&sH[sh_off(rb * 16 + (l & 15), col)] =
+          make_uint2(relu_bf16x2(acc[rb][cb][0], acc[rb][cb][1]), relu_bf16x2(acc[rb][cb][2], acc[rb][cb][3]));
+  }
+}
+
+// every accumulator block of the wave starts from the bias of its four columns
+__device__ __forceinline__ void fwd_init(f32x4 (&acc)[8][2], const float* __restrict__ bias, int w, int l) {
+  for (int cb = 0; cb < 2; cb++) {
+    const f32x4 bv = *(const f32x4*)(bias + w * 32 + cb * 16 + (l >> 4) * 4);
+    for (int rb = 0; rb < 8; rb++) acc[rb][cb] = bv;
   }
 }
 
@@ -143,14 +170,13 @@ __global__ void __launch_bounds__(FWAVES * 64, 4) k_mlp_fwd(const uint16_t* __re
                                                             const uint16_t* __restrict__ wt,
                                                             const float* __restrict__ p,
                                                             const uint16_t* __restrict__ w4, float* __restrict__ y) {
-  __shared__ __attribute__((aligned(16))) uint16_t sH[FM][FLD];
+  __shared__ __attribute__((aligned(16))) uint16_t sH[FM * kHidden];
   __shared__ float sY[FWAVES][FM];
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * FM;
   f32x4 acc[8][2];
   // layer 1 (K = 32): activation operand straight from the input rows
-  for (int rb = 0; rb < 8; rb++)
-    for (int cb = 0; cb < 2; cb++) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  fwd_init(acc, p + kOffB1, w, l);
   {
     bf16x8 wf[2];
     for (int cb = 0; cb < 2; cb++)
@@ -163,40 +189,38 @@ __global__ void __launch_bounds__(FWAVES * 64, 4) k_mlp_fwd(const uint16_t* __re
       for (int cb = 0; cb < 2; cb++) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[cb], a, acc[rb][cb], 0, 0, 0);
     }
   }
-  fwd_epilogue(acc, p + kOffB1, w, l, sH);
+  fwd_epilogue(acc, w, l, sH);
   __syncthreads();
   // layers 2 and 3 (K = 256): activations from LDS, weights from L2
   for (int layer = 0; layer < 2; layer++) {
     const uint16_t* wl = wt + (layer == 0 ? kOffT2 : kOffT3) + (int64_t)(w * 32 + (l & 15)) * kHidden + (l >> 4) * 8;
-    for (int rb = 0; rb < 8; rb++)
-      for (int cb = 0; cb < 2; cb++) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    fwd_init(acc, p + (layer == 0 ? kOffB2 : kOffB3), w, l);
     for (int k0 = 0; k0 < kHidden; k0 += 32) {
       bf16x8 wf[2];
       for (int cb = 0; cb < 2; cb++) wf[cb] = *(const bf16x8*)(wl + (int64_t)cb * 16 * kHidden + k0);
       for (int rb = 0; rb < 8; rb++) {
-        const bf16x8 a = *(const bf16x8*)&sH[rb * 16 + (l & 15)][k0 + (l >> 4) * 8];
+        const bf16x8 a = *(const bf16x8*)&sH[sh_off(rb * 16 + (l & 15), k0 + (l >> 4) * 8)];
         for (int cb = 0; cb < 2; cb++)
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[cb], a, acc[rb][cb], 0, 0, 0);
       }
     }
     __syncthreads();   // every wave has read this layer's input
     if (layer == 0) {
-      fwd_epilogue(acc, p + kOffB2, w, l, sH);
+      fwd_epilogue(acc, w, l, sH);
       __syncthreads();
     }
   }
-  // output: y = bf16(relu(z3 + b3)) . w4 + b4
+  // output: y = bf16(relu(z3 + b3)) . w4 + b4, two products per dot instruction
   float part[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int cb = 0; cb < 2; cb++) {
     const int col = w * 32 + cb * 16 + (l >> 4) * 4;
-    const f32x4 bv = *(const f32x4*)(p + kOffB3 + col);
-    float wv[4];
-    for (int i = 0; i < 4; i++) wv[i] = bf2f(w4[col + i]);
-    for (int rb = 0; rb < 8; rb++)
-      for (int i = 0; i < 4; i++) {
-        const float v = acc[rb][cb][i] + bv[i];
-        part[rb] += bf2f(f2bf(v > 0.f ? v : 0.f)) * wv[i];
-      }
+    const uint2 wv = *(const uint2*)(w4 + col);
+    for (int rb = 0; rb < 8; rb++) {
+      part[rb] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, relu_bf16x2(acc[rb][cb][0], acc[rb][cb][1])),
+                                                 __builtin_bit_cast(bf16x2, wv.x), part[rb], false);
+      part[rb] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, relu_bf16x2(acc[rb][cb][2], acc[rb][cb][3])),
+                                                 __builtin_bit_cast(bf16x2, wv.y), part[rb], false);
+    }
   }
   for (int rb = 0; rb < 8; rb++) {
     float v = part[rb];
