@@ -129,7 +129,10 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int kc, const uint16
 // load.  Eight 16x16 blocks x two column blocks of accumulators per wave (64
 // registers), so four waves fit on each SIMD; two workgroups share a CU's LDS.
 // The last layer's dot with w4 is reduced across lanes and waves through LDS.
-constexpr int FM = 128, FWAVES = 8;
+constexpr int FM = 128, FRB = FM / 16, FWAVES = 8;
+// k-steps of 32 per hidden layer; weight fragments requested this many k-steps
+// ahead of their products
+constexpr int FKS = kHidden / 32, FPRE = 2;
 
 // Activation tile layout: row-major, 256 bf16 per row with no padding, the
 // sixteen-byte chunks of a row permuted by an XOR with a row-dependent mask.
@@ -149,20 +152,20 @@ __device__ __forceinline__ int sh_off(int row, int col) {
 // read from L2 feeds 8 products, each activation fragment read from LDS feeds 2.
 // The accumulators start from the layer's bias, so the epilogue only applies the
 // ReLU, rounds to bf16 and stores.
-__device__ __forceinline__ void fwd_epilogue(const f32x4 (&acc)[8][2], int w, int l, uint16_t* sH) {
+__device__ __forceinline__ void fwd_epilogue(const f32x4 (&acc)[FRB][2], int w, int l, uint16_t* sH) {
   for (int cb = 0; cb < 2; cb++) {
     const int col = w * 32 + cb * 16 + (l >> 4) * 4;
-    for (int rb = 0; rb < 8; rb++)
+    for (int rb = 0; rb < FRB; rb++)
       *(uint2*)&sH[sh_off(rb * 16 + (l & 15), col)] =
           make_uint2(relu_bf16x2(acc[rb][cb][0], acc[rb][cb][1]), relu_bf16x2(acc[rb][cb][2], acc[rb][cb][3]));
   }
 }
 
 // every accumulator block of the wave starts from the bias of its four columns
-__device__ __forceinline__ void fwd_init(f32x4 (&acc)[8][2], const float* __restrict__ bias, int w, int l) {
+__device__ __forceinline__ void fwd_init(f32x4 (&acc)[FRB][2], const float* __restrict__ bias, int w, int l) {
   for (int cb = 0; cb < 2; cb++) {
     const f32x4 bv = *(const f32x4*)(bias + w * 32 + cb * 16 + (l >> 4) * 4);
-    for (int rb = 0; rb < 8; rb++) acc[rb][cb] = bv;
+    for (int rb = 0; rb < FRB; rb++) acc[rb][cb] = bv;
   }
 }
 
@@ -174,55 +177,80 @@ __global__ void __launch_bounds__(FWAVES * 64, 4) k_mlp_fwd(const uint16_t* __re
   __shared__ float sY[FWAVES][FM];
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * FM;
-  f32x4 acc[8][2];
+  f32x4 acc[FRB][2];
   // layer 1 (K = 32): activation operand straight from the input rows
   fwd_init(acc, p + kOffB1, w, l);
   {
     bf16x8 wf[2];
     for (int cb = 0; cb < 2; cb++)
       wf[cb] = *(const bf16x8*)(wt + kOffT1 + (int64_t)(w * 32 + cb * 16 + (l & 15)) * kInDim + (l >> 4) * 8);
-    for (int rb = 0; rb < 8; rb++) {
+    // every row block's input is requested before the first product: rows past
+    // the end read the last row (n >= 1) and are then replaced by zeros, so the
+    // loads carry no branch and their memory latencies overlap
+    u32x4 av[FRB];
+#pragma unroll
+    for (int rb = 0; rb < FRB; rb++) {
       const int64_t row = r0 + rb * 16 + (l & 15);
-      u32x4 av = {0u, 0u, 0u, 0u};
-      if (row < n) av = *(const u32x4*)(x + row * kInDim + (l >> 4) * 8);
-      const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+      av[rb] = *(const u32x4*)(x + (row < n ? row : n - 1) * kInDim + (l >> 4) * 8);
+    }
+#pragma unroll
+    for (int rb = 0; rb < FRB; rb++) {
+      const bool live = r0 + rb * 16 + (l & 15) < n;
+      const u32x4 v = live ? av[rb] : (u32x4{0u, 0u, 0u, 0u});
+      const bf16x8 a = __builtin_bit_cast(bf16x8, v);
+#pragma unroll
       for (int cb = 0; cb < 2; cb++) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[cb], a, acc[rb][cb], 0, 0, 0);
     }
   }
+  // layers 2 and 3 (K = 256): activations from LDS, weights from L2.  The 16
+  // k-steps of both layers form one sequence g = 8 * layer + ks; the weight
+  // fragments of step g + FPRE are requested before step g's products, into a
+  // ring of FPRE + 1 register slots (the slot of step g - 1, already consumed).
+  bf16x8 wq[FPRE + 1][2];
+  auto wload = [&](int g) {
+    const uint16_t* wl = wt + (g < FKS ? kOffT2 : kOffT3) + (int64_t)(w * 32 + (l & 15)) * kHidden + (l >> 4) * 8 +
+                         (g % FKS) * 32;
+#pragma unroll
+    for (int cb = 0; cb < 2; cb++) wq[(g) % (FPRE + 1)][cb] = *(const bf16x8*)(wl + (int64_t)cb * 16 * kHidden);
+  };
+#pragma unroll
+  for (int g = 0; g < FPRE; g++) wload(g);
   fwd_epilogue(acc, w, l, sH);
   __syncthreads();
-  // layers 2 and 3 (K = 256): activations from LDS, weights from L2
-  for (int layer = 0; layer < 2; layer++) {
-    const uint16_t* wl = wt + (layer == 0 ? kOffT2 : kOffT3) + (int64_t)(w * 32 + (l & 15)) * kHidden + (l >> 4) * 8;
-    fwd_init(acc, p + (layer == 0 ? kOffB2 : kOffB3), w, l);
-    for (int k0 = 0; k0 < kHidden; k0 += 32) {
-      bf16x8 wf[2];
-      for (int cb = 0; cb < 2; cb++) wf[cb] = *(const bf16x8*)(wl + (int64_t)cb * 16 * kHidden + k0);
-      for (int rb = 0; rb < 8; rb++) {
-        const bf16x8 a = *(const bf16x8*)&sH[sh_off(rb * 16 + (l & 15), k0 + (l >> 4) * 8)];
-        for (int cb = 0; cb < 2; cb++)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[cb], a, acc[rb][cb], 0, 0, 0);
-      }
+#pragma unroll
+  for (int g = 0; g < 2 * FKS; g++) {
+    const int ks = g % FKS;
+    if (ks == 0) fwd_init(acc, p + (g < FKS ? kOffB2 : kOffB3), w, l);
+    if (g + FPRE < 2 * FKS) wload(g + FPRE);
+    const int k0 = ks * 32;
+#pragma unroll
+    for (int rb = 0; rb < FRB; rb++) {
+      const bf16x8 a = *(const bf16x8*)&sH[sh_off(rb * 16 + (l & 15), k0 + (l >> 4) * 8)];
+#pragma unroll
+      for (int cb = 0; cb < 2; cb++)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wq[g % (FPRE + 1)][cb], a, acc[rb][cb], 0, 0, 0);
     }
-    __syncthreads();   // every wave has read this layer's input
-    if (layer == 0) {
-      fwd_epilogue(acc, w, l, sH);
-      __syncthreads();
+    if (ks == FKS - 1) {
+      __syncthreads();   // every wave has read this layer's input
+      if (g < FKS) {
+        fwd_epilogue(acc, w, l, sH);
+        __syncthreads();
+      }
     }
   }
   // output: y = bf16(relu(z3 + b3)) . w4 + b4, two products per dot instruction
-  float part[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float part[FRB] = {};
   for (int cb = 0; cb < 2; cb++) {
     const int col = w * 32 + cb * 16 + (l >> 4) * 4;
     const uint2 wv = *(const uint2*)(w4 + col);
-    for (int rb = 0; rb < 8; rb++) {
+    for (int rb = 0; rb < FRB; rb++) {
       part[rb] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, relu_bf16x2(acc[rb][cb][0], acc[rb][cb][1])),
                                                  __builtin_bit_cast(bf16x2, wv.x), part[rb], false);
       part[rb] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, relu_bf16x2(acc[rb][cb][2], acc[rb][cb][3])),
                                                  __builtin_bit_cast(bf16x2, wv.y), part[rb], false);
     }
   }
-  for (int rb = 0; rb < 8; rb++) {
+  for (int rb = 0; rb < FRB; rb++) {
     float v = part[rb];
     v += __shfl_xor(v, 16, 64);
     v += __shfl_xor(v, 32, 64);
