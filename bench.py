@@ -27,12 +27,18 @@ from paper_1602_05510_amd import inputs as I  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_1602_05510_amd", "csrc", "hesp_sim.hip")
+# every source the simulator kernel is compiled from: stored counters count only
+# while this hash matches the one recorded with them
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1602_05510_amd", "csrc", f)
+               for f in ("hesp_sim.hip", "hesp_device.h", "hesp_core.h", "hesp_internal.h", "hesp_tree.h")]
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 # ----------------------------------------------------------------------- accounting

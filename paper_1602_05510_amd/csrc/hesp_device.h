@@ -40,12 +40,21 @@ __device__ __forceinline__ int64_t rdl64(int64_t v, int l) {
 }
 __device__ __forceinline__ int rdl32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
-// DPP lane moves of a 64-bit value (lanes left out by the row mask keep v)
+// DPP lane moves of a 64-bit value (lanes left out by the row mask keep v).
+// With every row enabled, the controls used here (quad permutations, row
+// rotations) give each lane a source inside its row, so the destination's old
+// value is never read and need not be a copy of v.
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ int64_t dpp64(int64_t v) {
   const int lo = (int)(uint32_t)(uint64_t)v, hi = (int)(uint32_t)((uint64_t)v >> 32);
-  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
-  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+  int rlo, rhi;
+  if constexpr (ROWS == 0xF) {
+    rlo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, true);
+    rhi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, true);
+  } else {
+    rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+    rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+  }
   return (int64_t)(((uint64_t)(uint32_t)rhi << 32) | (uint32_t)rlo);
 }
 constexpr int kQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
@@ -219,6 +228,17 @@ struct Grp {
     if (G >= 64) v = min64(v, dpp64<kRowBcast31, 0xC>(v));
     if (G >= 32) v = bcast64(v, G - 1);
     return v;
+  }
+  // the same for a value that is kInf outside the group's first 16 lanes whenever
+  // lo16 (uniform) holds: the cross-row steps are then skipped and lane 0 of the
+  // group, which holds the minimum of lanes 0..15, is broadcast
+  __device__ __forceinline__ int64_t min64lo(int64_t v, bool lo16) const {
+    if (G <= 16 || !lo16) return min64all(v);
+    v = min64(v, dpp64<kQuadSwap1>(v));
+    v = min64(v, dpp64<kQuadSwap2>(v));
+    v = min64(v, dpp64<kRowRor4>(v));
+    v = min64(v, dpp64<kRowRor8>(v));
+    return bcast64(v, 0);
   }
 };
 

@@ -513,6 +513,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
   __syncthreads();
 
   const int P = tb.n_procs, M = tb.n_mem;
+  const bool p16 = P <= 16;                    // processor lanes all in the group's first row
   const int pmem = gl < P ? tb.proc_mem[gl] : 0;
   const int ptype = gl < P ? tb.proc_type[gl] : 0;
   const bool want_sched = out.sched_off != nullptr;
@@ -699,9 +700,11 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
         const int wmask = (1 << sh) - 1;
         int br[3], bc[3];
         const int nb = desc_blocks(dsc, br, bc);
-        const int64_t ab0 = atom_base(nt, dmax, lvl, br[0], bc[0]);
-        const int64_t ab1 = nb > 1 ? atom_base(nt, dmax, lvl, br[1], bc[1]) : 0;
-        const int64_t ab2 = nb > 2 ? atom_base(nt, dmax, lvl, br[2], bc[2]) : 0;
+        // validity-table indices fit in 32 bits: at most 512 x 513 / 2 finest
+        // blocks (nt * 2^dmax <= 512) times at most 16 memory spaces
+        const int ab0 = (int)atom_base(nt, dmax, lvl, br[0], bc[0]);
+        const int ab1 = nb > 1 ? (int)atom_base(nt, dmax, lvl, br[1], bc[1]) : 0;
+        const int ab2 = nb > 2 ? (int)atom_base(nt, dmax, lvl, br[2], bc[2]) : 0;
         for (int x = gl; x < 4 * M; x += G) {
           (&s_fin[g][0][0])[(x >> 2) + (x & 3) * kMaxMem] = INT64_MIN;
           (&s_miss[g][0][0])[(x >> 2) + (x & 3) * kMaxMem] = 0;
@@ -711,7 +714,8 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
         // one lane per (space m, block b, finest block a): it = ((m*4 + b) << lg) | a
         const int items = (M << 2) << lg;
         const bool one_pass = items <= G;
-        int64_t my_x = 0, my_addr = -1;
+        int64_t my_x = 0;
+        int my_addr = -1;
         int my_m = 0, my_b = 0;
         for (int i0 = 0; i0 < items; i0 += G) {
           const int it = i0 + gl;
@@ -719,8 +723,8 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
           const int b = (it >> lg) & 3;
           const int m = it >> (lg + 2);
           const bool act = it < items && b < nb;
-          const int64_t abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
-          const int64_t addr = (abase + ((int64_t)(a >> sh) << dmax) + (a & wmask)) * M + m;
+          const int abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
+          const int addr = (abase + ((a >> sh) << dmax) + (a & wmask)) * M + m;
           const int64_t x = act ? vld(&sp.vf[addr]) : kInf;
           const uint64_t infm = gp.ballot(act && x == kInf);
           const int64_t fin = seg_max64((act && x != kInf) ? x : INT64_MIN, lgs);
@@ -778,7 +782,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
           if (sel == 1) score = T > avail ? T : avail;
           if (PULL && sel == 3) score = ((idle >> gl) & 1ull) ? s_cost[ptype][kind][lvl] : (kInf >> 6);
           const int64_t key = gl < P ? ((score << 6) | gl) : kInf;
-          const int64_t best = gp.min64all(key);
+          const int64_t best = gp.min64lo(key, p16);
           pstar = (int)(best & 63);
           eft_star = sel == 0 ? best >> 6 : gp.bcast64(eft, pstar);
         }
@@ -816,11 +820,11 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
             const int miss = s_miss[g][b][mstar];
             if (miss == 0) continue;
             const int64_t arrive = arrival(b);
-            const int64_t abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
+            const int abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
             for (int a0 = 0; a0 < (1 << lg); a0 += G) {
               const int a = a0 + gl;
               if (a < (1 << lg)) {
-                const int64_t addr = (abase + ((int64_t)(a >> sh) << dmax) + (a & wmask)) * M + mstar;
+                const int addr = (abase + ((a >> sh) << dmax) + (a & wmask)) * M + mstar;
                 if (vld(&sp.vf[addr]) == kInf) sp.vf[addr] = arrive;
               }
             }
@@ -898,7 +902,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
     }
 
     // (ii) next event: the earliest queue head
-    const int64_t Tn = gp.min64all(gl < P ? hfin : kInf);
+    const int64_t Tn = gp.min64lo(gl < P ? hfin : kInf, p16);
     if (Tn == kInf) {
       if (gl == 0) out.makespan[c] = T;
       active = false;
@@ -930,7 +934,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
       // write-back: the written block is valid only where it was computed;
       // write-through: also on the host, once the copy sent now has arrived;
       // write-around: on the host only, once that copy has arrived
-      const int64_t abase = atom_base(nt, dmax, lvl, br[nb - 1], bc[nb - 1]);
+      const int abase = (int)atom_base(nt, dmax, lvl, br[nb - 1], bc[nb - 1]);
       const int items = M << lg;
       int64_t host_at = (POL != 0 && cache != 0 && ms != 0) ? Tn + s_xfer[(1 << lg) * xs] : Tn;
       if (bus && cache != 0 && ms != 0) {         // the host copy queues on the interconnect
@@ -941,7 +945,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
         const int it = i0 + gl;
         if (it < items) {
           const int m = it >> lg, a = it & ((1 << lg) - 1);
-          const int64_t atom = abase + ((int64_t)(a >> sh) << dmax) + (a & wmask);
+          const int atom = abase + ((a >> sh) << dmax) + (a & wmask);
           int64_t x = (m == ms) ? Tn : kInf;
           if (POL != 0 && cache == 1) x = (m == ms) ? Tn : (m == 0 ? host_at : kInf);
           if (POL != 0 && cache == 2) x = (m == 0) ? host_at : kInf;
