@@ -159,71 +159,108 @@ __device__ __forceinline__ int64_t prep_scan_succ(const CandPtrs& sp, int64_t n_
   return ecarry;
 }
 
+// LDS of the critical-time pass: per task of the current chunk of 64, its critical
+// time (rk), the largest critical time among its successors outside the chunk
+// (ext), the sweep's running maximum (mx) and its first edge (e, e[64] = the
+// chunk's end); the chunk's internal edges as (source << 6 | target), up to
+// kPrepIn of them (more are re-read from the successor lists in each sweep)
+constexpr int kPrepIn = 1024;
+struct PrepLds {
+  int64_t rk[kWave], ext[kWave], mx[kWave];
+  uint32_t e[kWave + 1];
+  uint16_t in[kPrepIn];
+};
+
+// the task of the chunk that owns edge e (E0 <= e < E1): the last t with
+// e[t] <= e, the first edges being non-decreasing
+__device__ __forceinline__ int prep_owner(const PrepLds& s, uint32_t e) {
+  int lo = 0;
+  for (int step = kWave / 2; step > 0; step >>= 1)
+    if (s.e[lo + step] <= e) lo += step;
+  return lo;
+}
+
 // critical times, the closing record, initial validity and the first ready
 // list; cur[f] = one past the last edge of f, successor lists filled
 __device__ __forceinline__ void prep_finish(const ChunkView& cv, const OutView& out, int c, int nt, int dmax, int M,
                                             const CandPtrs& sp, int64_t n_fine, int64_t n_edges,
-                                            const int64_t (*s_W)[kLevels], int64_t* s_rk) {
+                                            const int64_t (*s_W)[kLevels], PrepLds& s) {
   const int l = lane();
-  // R: critical times, last chunk of 64 tasks first.  Successors beyond the
-  // chunk are final and read once; those inside it are resolved by iterating
-  // the chunk's values in LDS to their fixed point (monotone from below).
+  // R: critical times, last chunk of 64 tasks first.  The chunk's successor
+  // lists form one contiguous edge range, read by all lanes together, four
+  // edges per lane per round trip: a successor beyond the chunk is final, and its
+  // critical time is gathered and folded into its source's ext with an LDS
+  // maximum; one inside the chunk is kept as an internal edge.  The chunk's own
+  // values are then iterated over the internal edges to their fixed point
+  // (monotone from below).
   const int64_t n_chunks = (n_fine + kWave - 1) / kWave;
   for (int64_t ch = n_chunks - 1; ch >= 0; ch--) {
     const int64_t base = ch * kWave, lim = base + kWave;
     const int64_t f = base + l;
     const bool valid = f < n_fine;
-    int64_t w = 0, ext = 0;
-    uint64_t inl = 0;                       // up to 8 successor lanes inside the chunk
-    int nin = 0;
-    bool ovf = false;
+    const int n_valid = (int)(n_fine - base < kWave ? n_fine - base : kWave);
+    int64_t w = 0;
     uint32_t e0 = 0, e1 = 0, dsc = 0;
     if (valid) {
       dsc = vld(&sp.desc[f]);
       w = s_W[desc_kind(dsc)][desc_level(dsc)];
       e0 = f == 0 ? 0u : vld_l2(&sp.cur[f - 1]);
       e1 = vld_l2(&sp.cur[f]);
-      // four successors at a time: their ids, then the critical times of those
-      // outside the chunk, are loaded together (two dependent round trips per four)
-      for (uint32_t e = e0; e < e1; e += 4) {
-        uint32_t v[4];
-        int64_t rv[4];
-        for (int q = 0; q < 4; q++) v[q] = e + q < e1 ? vld(&sp.succ[e + q]) : kNil;
-        for (int q = 0; q < 4; q++) rv[q] = (v[q] != kNil && v[q] >= lim) ? vld(&sp.rec[2 * v[q]]) : INT64_MIN;
-        for (int q = 0; q < 4; q++) {
-          if (v[q] == kNil) continue;
-          if (v[q] >= lim) {
-            ext = max64(ext, rv[q]);
-          } else if (nin < 8) {
-            inl |= (uint64_t)(v[q] - base) << (6 * nin);
-            nin++;
-          } else {
-            ovf = true;
-          }
-        }
+    }
+    const uint32_t E0 = (uint32_t)rdl32((int)e0, 0), E1 = (uint32_t)rdl32((int)e1, n_valid - 1);
+    s.e[l] = valid ? e0 : E1;
+    if (l == 0) s.e[kWave] = E1;
+    s.ext[l] = 0;
+    __syncthreads();
+    int n_in = 0;
+    for (uint32_t eb = E0; eb < E1; eb += 4 * kWave) {
+      uint32_t v[4];
+      int64_t rv[4];
+      int src[4];
+      for (int q = 0; q < 4; q++) {
+        const uint32_t e = eb + q * kWave + l;
+        v[q] = e < E1 ? vld(&sp.succ[e]) : kNil;
+      }
+      for (int q = 0; q < 4; q++) rv[q] = (v[q] != kNil && v[q] >= lim) ? vld(&sp.rec[2 * v[q]]) : 0;
+      for (int q = 0; q < 4; q++) src[q] = v[q] != kNil ? prep_owner(s, eb + q * kWave + l) : 0;
+      for (int q = 0; q < 4; q++) {
+        if (v[q] != kNil && v[q] >= lim) atomicMax((long long*)&s.ext[src[q]], (long long)rv[q]);
+        const bool inner = v[q] != kNil && v[q] < lim;
+        const uint64_t m = __ballot(inner);
+        const int pos = n_in + __popcll(m & lanes_below());
+        if (inner && pos < kPrepIn) s.in[pos] = (uint16_t)((src[q] << 6) | (int)(v[q] - base));
+        n_in += __popcll(m);
       }
     }
+    __syncthreads();
+    const int64_t ext = s.ext[l];
     int64_t r = w + ext;
-    for (int sweep = 0; sweep < kWave + 2; sweep++) {
-      s_rk[l] = r;
+    for (int sweep = 0; n_in > 0 && sweep < kWave + 2; sweep++) {
+      s.rk[l] = r;
+      s.mx[l] = ext;
       __syncthreads();
-      int64_t mx = ext;
-      for (int j = 0; j < nin; j++) mx = max64(mx, s_rk[(inl >> (6 * j)) & 63]);
-      if (ovf)
-        for (uint32_t e = e0; e < e1; e++) {
-          const uint32_t v = vld(&sp.succ[e]);
-          if (v < lim) mx = max64(mx, s_rk[v - base]);
+      if (n_in <= kPrepIn) {
+        for (int i = l; i < n_in; i += kWave) {
+          const int u = s.in[i];
+          atomicMax((long long*)&s.mx[u >> 6], (long long)s.rk[u & 63]);
         }
-      const int64_t nr = w + mx;
+      } else {
+        for (uint32_t e = E0 + l; e < E1; e += kWave) {
+          const uint32_t vv = vld(&sp.succ[e]);
+          if (vv < lim) atomicMax((long long*)&s.mx[prep_owner(s, e)], (long long)s.rk[vv - base]);
+        }
+      }
+      __syncthreads();
+      const int64_t nr = w + s.mx[l];
       const bool changed = valid && nr != r;
       r = nr;
-      __syncthreads();
       if (!__ballot(changed)) break;
     }
     if (valid) {
       sp.rec[2 * f] = r;
       sp.rec[2 * f + 1] = (int64_t)(dsc | ((uint64_t)e0 << 32));
     }
+    __syncthreads();
   }
   if (l == 0) {
     sp.rec[2 * n_fine] = 0;
@@ -262,7 +299,7 @@ __device__ __forceinline__ void prep_finish(const ChunkView& cv, const OutView& 
 // eight waves per SIMD (64 VGPRs): the passes wait on memory most of the time
 __global__ void __launch_bounds__(kWave, 8) k_prepare(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
   __shared__ int64_t s_W[4][kLevels];
-  __shared__ int64_t s_rk[kWave];
+  __shared__ PrepLds s_p;
   const int l = lane();
   for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
   __syncthreads();
@@ -348,7 +385,7 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare(SimTables tb, BatchView bv
   });
   wave_order();
 
-  prep_finish(cv, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_rk);
+  prep_finish(cv, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_p);
 }
 
 // ---------------------------------------------------------------- split trees
@@ -391,7 +428,7 @@ __global__ void __launch_bounds__(kWave, 8) k_count_tree(BatchView bv, uint32_t*
 // candidate's validity words until they are initialized)
 __global__ void __launch_bounds__(kWave, 8) k_prepare_tree(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
   __shared__ int64_t s_W[4][kLevels];
-  __shared__ int64_t s_rk[kWave];
+  __shared__ PrepLds s_p;
   const int l = lane();
   for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
   __syncthreads();
@@ -457,7 +494,7 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare_tree(SimTables tb, BatchVi
     });
   });
   wave_order();
-  prep_finish(cv, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_rk);
+  prep_finish(cv, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_p);
 }
 
 // ---------------------------------------------------------------- event simulation
