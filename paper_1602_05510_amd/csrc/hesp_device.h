@@ -65,15 +65,16 @@ constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return b < a ? b : a; }
 __device__ __forceinline__ int64_t max64(int64_t a, int64_t b) { return b > a ? b : a; }
 
-// minimum over the 64 lanes, returned to every lane
-__device__ __forceinline__ int64_t wave_min64(int64_t v) {
-  v = min64(v, dpp64<kQuadSwap1>(v));
-  v = min64(v, dpp64<kQuadSwap2>(v));
-  v = min64(v, dpp64<kRowRor4>(v));
-  v = min64(v, dpp64<kRowRor8>(v));
-  v = min64(v, dpp64<kRowBcast15, 0xA>(v));
-  v = min64(v, dpp64<kRowBcast31, 0xC>(v));
-  return rdl64(v, kWave - 1);
+// minimum of a 32-bit unsigned value over the 64 lanes, returned to every lane
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  auto mn = [](uint32_t a, int b) { return a < (uint32_t)b ? a : (uint32_t)b; };
+  v = mn(v, __builtin_amdgcn_update_dpp(0, (int)v, kQuadSwap1, 0xF, 0xF, true));
+  v = mn(v, __builtin_amdgcn_update_dpp(0, (int)v, kQuadSwap2, 0xF, 0xF, true));
+  v = mn(v, __builtin_amdgcn_update_dpp(0, (int)v, kRowRor4, 0xF, 0xF, true));
+  v = mn(v, __builtin_amdgcn_update_dpp(0, (int)v, kRowRor8, 0xF, 0xF, true));
+  v = mn(v, __builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast15, 0xA, 0xF, false));
+  v = mn(v, __builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast31, 0xC, 0xF, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
 }
 
 // maximum over aligned segments of 2^lg lanes (lg in {0, 2, 4, 5, 6}); the

@@ -97,7 +97,7 @@ __device__ __forceinline__ int scan_task(uint32_t* lw, int nt, int dmax, int kin
   int n = 0;
   for (;;) {
     const uint32_t mine = v0 < v1 ? (v0 < v2 ? v0 : v2) : (v1 < v2 ? v1 : v2);
-    const uint32_t m = (uint32_t)wave_min64((int64_t)mine);
+    const uint32_t m = wave_min_u32(mine);
     if (m == kNil) break;
     emit(m);
     n++;
