@@ -467,11 +467,20 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare_tree(SimTables tb, BatchVi
 
   // descriptors, predecessor counts, successor counts
   uint32_t nf_seen = 0;
+  // A task's distinct last writers (at most 3 x 64: one per finest block it
+  // reads) are dealt to the lanes as they are found, lane j holding writers j,
+  // j + 64 and j + 128; their successor counters are then updated by all lanes
+  // together instead of one writer at a time.
   walk_tree(nt, dmax, flags, [&](int kind, int lv, int K, int I, int J) {
     const uint32_t f = nf_seen++;
+    uint32_t wr[3] = {kNil, kNil, kNil};
+    int k = 0;
     const int np = scan_task(lw, nt, dmax, kind, lv, K, I, J, f, [&](uint32_t p) {
-      if (l == 0) atomicAdd(&sp.cur[p], 1u);
+      for (int h = 0; h < 3; h++) wr[h] = k == l + h * kWave ? p : wr[h];
+      k++;
     });
+    for (int h = 0; h < 3; h++)
+      if (wr[h] != kNil) atomicAdd(&sp.cur[wr[h]], 1u);
     if (l == 0 && f < n_fine) {            // the counts came from the same walk: always true
       sp.desc[f] = pack_desc(kind, lv, K, I, J);
       sp.indeg[f] = (uint32_t)np;
@@ -486,12 +495,16 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare_tree(SimTables tb, BatchVi
   nf_seen = 0;
   walk_tree(nt, dmax, flags, [&](int kind, int lv, int K, int I, int J) {
     const uint32_t f = nf_seen++;
+    uint32_t wr[3] = {kNil, kNil, kNil};
+    int k = 0;
     scan_task(lw, nt, dmax, kind, lv, K, I, J, f, [&](uint32_t p) {
-      if (l == 0) {
-        const uint32_t pos = atomicAdd(&sp.cur[p], 1u);
-        if (pos < n_edges) sp.succ[pos] = f;
-      }
+      for (int h = 0; h < 3; h++) wr[h] = k == l + h * kWave ? p : wr[h];
+      k++;
     });
+    uint32_t pos[3];
+    for (int h = 0; h < 3; h++) pos[h] = wr[h] != kNil ? atomicAdd(&sp.cur[wr[h]], 1u) : 0u;
+    for (int h = 0; h < 3; h++)
+      if (wr[h] != kNil && pos[h] < n_edges) sp.succ[pos[h]] = f;
   });
   wave_order();
   prep_finish(cv, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_p);
