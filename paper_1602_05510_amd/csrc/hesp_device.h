@@ -230,16 +230,26 @@ struct Grp {
     if (G >= 32) v = bcast64(v, G - 1);
     return v;
   }
-  // the same for a value that is kInf outside the group's first 16 lanes whenever
-  // lo16 (uniform) holds: the cross-row steps are then skipped and lane 0 of the
-  // group, which holds the minimum of lanes 0..15, is broadcast
+  // the same for a non-negative value that is kInf outside the group's first 16
+  // lanes whenever lo16 (uniform) holds: the minimum of lanes 0..15 is then
+  // taken on 32-bit halves inside the first row (the high words, then the low
+  // words of the lanes holding the least high word; each step one DPP-fused
+  // unsigned minimum) and broadcast from the group's lane 0
   __device__ __forceinline__ int64_t min64lo(int64_t v, bool lo16) const {
     if (G <= 16 || !lo16) return min64all(v);
-    v = min64(v, dpp64<kQuadSwap1>(v));
-    v = min64(v, dpp64<kQuadSwap2>(v));
-    v = min64(v, dpp64<kRowRor4>(v));
-    v = min64(v, dpp64<kRowRor8>(v));
-    return bcast64(v, 0);
+    auto row_min = [](uint32_t x) {
+      auto mn = [](uint32_t a, int b) { return a < (uint32_t)b ? a : (uint32_t)b; };
+      x = mn(x, __builtin_amdgcn_update_dpp(0, (int)x, kQuadSwap1, 0xF, 0xF, true));
+      x = mn(x, __builtin_amdgcn_update_dpp(0, (int)x, kQuadSwap2, 0xF, 0xF, true));
+      x = mn(x, __builtin_amdgcn_update_dpp(0, (int)x, kRowRor4, 0xF, 0xF, true));
+      x = mn(x, __builtin_amdgcn_update_dpp(0, (int)x, kRowRor8, 0xF, 0xF, true));
+      return x;
+    };
+    const uint32_t hi = (uint32_t)((uint64_t)v >> 32), lo = (uint32_t)(uint64_t)v;
+    const uint32_t mh = row_min(hi);
+    const uint32_t ml = row_min(hi == mh ? lo : 0xFFFFFFFFu);
+    const uint32_t bh = (uint32_t)bcast((int)mh, 0), bl = (uint32_t)bcast((int)ml, 0);
+    return (int64_t)(((uint64_t)bh << 32) | bl);
   }
 };
 
