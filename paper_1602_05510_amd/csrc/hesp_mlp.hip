@@ -127,7 +127,8 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int kc, const uint16
 // LDS (128 x 256 bf16); weights come from L2 in a transposed bf16 copy
 // (wt[n][k], k contiguous) so that each lane's weight operand is one 16-byte
 // load.  Eight 16x16 blocks x two column blocks of accumulators per wave (64
-// registers), so four waves fit on each SIMD; two workgroups share a CU's LDS.
+// registers; 128 in all with the operand fragments and the ring of weight
+// fragments), so four waves fit on each SIMD; two workgroups share a CU's LDS.
 // The last layer's dot with w4 is reduced across lanes and waves through LDS.
 constexpr int FM = 128, FRB = FM / 16, FWAVES = 8;
 // k-steps of 32 per hidden layer; weight fragments requested this many k-steps
