@@ -390,22 +390,29 @@ __global__ void k_rowdot(const uint16_t* __restrict__ h, int64_t M, const uint16
 }
 
 // output layer backward: dy = 2 (y - t) / n; dz3 = bf16(dy * w4 * [h3 > 0]);
-// loss sums (y - t)^2 / n into loss[0]
+// loss sums (y - t)^2 / n into loss[0].  kOutRows rows per workgroup, whose loss
+// terms are summed first so that one atomic per workgroup reaches loss[0]
+// (atomics on one address serialize).
+constexpr int kOutRows = 16;
 __global__ void k_out_backward(const float* __restrict__ y, const float* __restrict__ t, int64_t n,
                                const uint16_t* __restrict__ w4, const uint16_t* __restrict__ h3,
                                float* __restrict__ dy, uint16_t* __restrict__ dz3, float* __restrict__ loss) {
-  const int64_t m = blockIdx.x;
-  if (m >= n) return;
-  const float d = y[m] - t[m];
-  const float g = 2.f * d / (float)n;
-  if (threadIdx.x == 0) {
-    dy[m] = g;
-    atomicAdd(loss, d * d / (float)n);
+  const int64_t m0 = (int64_t)blockIdx.x * kOutRows;
+  float part = 0.f;
+  for (int r = 0; r < kOutRows && m0 + r < n; r++) {
+    const int64_t m = m0 + r;
+    const float d = y[m] - t[m];
+    const float g = 2.f * d / (float)n;
+    if (threadIdx.x == 0) {
+      dy[m] = g;
+      part += d * d / (float)n;
+    }
+    for (int j = threadIdx.x; j < kHidden; j += blockDim.x) {
+      const uint16_t hv = h3[m * kHidden + j];
+      dz3[m * kHidden + j] = hv != 0 ? f2bf(g * bf2f(w4[j])) : (uint16_t)0;
+    }
   }
-  for (int j = threadIdx.x; j < kHidden; j += blockDim.x) {
-    const uint16_t hv = h3[m * kHidden + j];
-    dz3[m * kHidden + j] = hv != 0 ? f2bf(g * bf2f(w4[j])) : (uint16_t)0;
-  }
+  if (threadIdx.x == 0) atomicAdd(loss, part);
 }
 
 // column sums: out[j] = sum_m a[m][j] (bf16) * (wcol ? wcol[m] : 1), fp32; one
@@ -550,7 +557,8 @@ hipError_t rowdot(const uint16_t* h, int64_t M, const uint16_t* w, const float* 
 
 hipError_t out_backward(const float* y, const float* t, int64_t n, const uint16_t* w4, const uint16_t* h3, float* dy,
                         uint16_t* dz3, float* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_out_backward, dim3((unsigned)n), dim3(256), 0, s, y, t, n, w4, h3, dy, dz3, loss);
+  hipLaunchKernelGGL(k_out_backward, dim3((unsigned)((n + kOutRows - 1) / kOutRows)), dim3(256), 0, s, y, t, n, w4, h3, dy,
+                     dz3, loss);
   return hipGetLastError();
 }
 
