@@ -252,12 +252,14 @@ int hesp_mlp_grad(hesp_mlp* m, const uint16_t* d_x, const float* d_t, int32_t ba
   const int splits = (int)(n / 512);
   HIP_TRY(m->ensure(n, (int64_t)splits * kHidden * kHidden > 64 * kHidden ? (int64_t)splits * kHidden * kHidden
                                                                           : 64 * kHidden));
-  HIP_TRY(zero_f32(m->loss, 1, s));
+  // the loss accumulates straight into the caller's slot when one is given
+  float* loss = d_loss ? d_loss : m->loss;
+  HIP_TRY(zero_f32(loss, 1, s));
   HIP_TRY(forward_rows(m, d_x, n, m->y, s));
   float* g = m->g;
   const uint16_t* w = m->wbf;
   // output layer
-  HIP_TRY(out_backward(m->y, d_t, n, w + kOffW4, m->h3, m->dy, m->dza, m->loss, s));
+  HIP_TRY(out_backward(m->y, d_t, n, w + kOffW4, m->h3, m->dy, m->dza, loss, s));
   HIP_TRY(bias_grad(m, m->h3, n, m->dy, g + kOffW4, s));
   HIP_TRY(sum_f32(m->dy, n, g + kOffB4, s));
   // layer 3: dz3 in dza
@@ -273,7 +275,6 @@ int hesp_mlp_grad(hesp_mlp* m, const uint16_t* d_x, const float* d_t, int32_t ba
   // layer 1: dz1 in dza
   HIP_TRY(weight_grad(m, d_x, kInDim, m->dza, n, g + kOffW1, s));
   HIP_TRY(bias_grad(m, m->dza, n, nullptr, g + kOffB1, s));
-  if (d_loss) HIP_TRY(hipMemcpyAsync(d_loss, m->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
   return HESP_OK;
 }
 
