@@ -97,27 +97,49 @@ def algorithmic_bytes(batch, n_mem: int, n_edges_total: int) -> tuple:
 
 # ----------------------------------------------------------------------- CPU baseline
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float, policy=(0, 0, 0, 0), tree: bool = False):
-    """The oracle, as it stands, on the host cores, over a bounded sample of the batch."""
+    """The oracle, as it stands, built -O2 -march=native on this host, on its
+    cores: the whole timed batch when it fits the time budget (else its first
+    candidates), plus a single-thread rate on a smaller prefix."""
     sys.path.insert(0, ROOT)
     from oracle import oracle as O
-    O.build(force=False)
-    cores = min(os.cpu_count() or 1, 64)
+    O.build(force=True, native=True)
+    cores = min(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1), 64)
     # calibrate the sample size with a small probe
     probe = batch_host.subset(range(min(64, batch_host.n)))
     t0 = time.perf_counter()
-    ms, ntk = O.simulate_batch(pf, probe, cores, policy=policy, tree=tree)
+    O.simulate_batch(pf, probe, cores, policy=policy, tree=tree, native=True)
     dt = max(time.perf_counter() - t0, 1e-3)
     per_cand = dt / probe.n
     n = int(min(batch_host.n, max(probe.n, budget_s / per_cand)))
     sample = batch_host.subset(range(n))
     t0 = time.perf_counter()
-    ms, ntk = O.simulate_batch(pf, sample, cores, policy=policy, tree=tree)
+    ms, ntk = O.simulate_batch(pf, sample, cores, policy=policy, tree=tree, native=True)
     dt = time.perf_counter() - t0
     exact = bool(np.array_equal(ms, gpu_makespan[:n]))
+    # one thread, about a tenth of the budget
+    n1 = int(min(n, max(16, 0.1 * budget_s / (per_cand * cores))))
+    t0 = time.perf_counter()
+    _, ntk1 = O.simulate_batch(pf, batch_host.subset(range(n1)), 1, policy=policy, tree=tree, native=True)
+    dt1 = time.perf_counter() - t0
+    what = "the whole timed batch of step 0" if n == batch_host.n else f"the first {n} candidates of the timed batch of step 0"
     return {"value": float(ntk.sum()) / dt, "unit": "tasks/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} candidates of the timed batch of step 0, one candidate per thread",
-            "candidates_per_s": n / dt, "seconds": dt, "bit_exact_vs_gpu": exact}
+            "sample": f"{what}, one candidate per thread; oracle built gcc -O2 -march=native on this host",
+            "cpu_model": host_cpu_model(), "candidates": n, "candidates_per_s": n / dt, "seconds": dt,
+            "bit_exact_vs_gpu": exact,
+            "single_thread": {"value": float(ntk1.sum()) / dt1, "unit": "tasks/s", "candidates": n1,
+                              "seconds": dt1}}
 
 
 # ----------------------------------------------------------------------- surrogate
@@ -252,7 +274,11 @@ def run_surrogate(args, torch, H):
 
 def run_search(args, torch, H):
     """Plain (random warm-up + greedy mutation) search against surrogate-guided
-    search on the 64x64 instance; best makespan against wall time."""
+    search on the 64x64 instance; best makespan against wall time.  Three arms
+    share one plan, warmed (workspace sized, lanes per candidate tuned) by an
+    untimed round of every batch shape first: plain greedy at the full batch,
+    plain greedy at the surrogate's batch (what the network adds at an equal
+    simulation budget), and the surrogate-guided search."""
     w = I.WORKLOADS["chol64x64_b1024_d3"]
     nt = args.search_nt or w.nt
     dev = torch.device("cuda")
@@ -261,23 +287,37 @@ def run_search(args, torch, H):
     thr = I.split_threshold(w.p_num, w.p_den)
     mut = int(round(args.mutate * (1 << 21)))
     plan = H.Plan()
+    sbatch = max(1, args.batch // args.sur_ratio)
+    swarm = args.sur_warm or args.batch
     common = dict(rounds=args.rounds, seed=w.seed, warm_rounds=1, pool=args.pool, split_thr=thr, mutate_thr=mut)
-    _, plain_best, plain_tr = H.search(plan, pf, nt, w.dmax, H.SEARCH_GREEDY, batch=args.batch,
-                                       warm_batch=args.batch, **common)
+    for b in sorted({args.batch, sbatch, swarm}):
+        H.search(plan, pf, nt, w.dmax, H.SEARCH_RANDOM, batch=b, warm_batch=b, rounds=1, seed=w.seed + 1000,
+                 warm_rounds=1, pool=args.pool, split_thr=thr, mutate_thr=mut)
+    torch.cuda.synchronize()
+    plain_d, plain_best, plain_tr = H.search(plan, pf, nt, w.dmax, H.SEARCH_GREEDY, batch=args.batch,
+                                             warm_batch=args.batch, **common)
+    small_d, small_best, small_tr = H.search(plan, pf, nt, w.dmax, H.SEARCH_GREEDY, batch=sbatch, warm_batch=swarm,
+                                       **common)
     m = H.MLP(args.mlp_seed)
     rate = torch.from_numpy(H.mlp_rate_features(pf_in.rmax)).to(dev)
-    sbatch = max(1, args.batch // args.sur_ratio)
-    best_d, sur_best, sur_tr = H.search(plan, pf, nt, w.dmax, H.SEARCH_SURROGATE, batch=sbatch,
-                                        warm_batch=args.sur_warm or args.batch,
+    best_d, sur_best, sur_tr = H.search(plan, pf, nt, w.dmax, H.SEARCH_SURROGATE, batch=sbatch, warm_batch=swarm,
                                         proposals=sbatch * args.sur_proposals, mlp=m, rate=rate,
                                         train_steps=args.sur_train_steps, train_batch=512, lr=1e-3,
                                         replay=1 << 16, **common)
     target = plain_best * 1.01
-    reach = next((t["wall_ms"] for t in sur_tr if t["best_makespan"] <= target), None)
+
+    def reach(tr):
+        return next((t["wall_ms"] for t in tr if t["best_makespan"] <= target), None)
+
+    r_plain, r_small, r_sur = reach(plain_tr), reach(small_tr), reach(sur_tr)
     plain_ms = plain_tr[-1]["wall_ms"]
+
+    def ratio(a, b):
+        return None if a is None or b is None else a / b
+
     rec = {
         "metric": "time-to-best-makespan: surrogate-guided vs plain search",
-        "value": (reach / plain_ms) if reach is not None else None, "unit": "fraction of plain search wall time",
+        "value": ratio(r_sur, plain_ms), "unit": "fraction of plain search wall time",
         "n_gpus": 1, "steps": args.rounds, "warmup": 0, "ms_per_step": plain_ms / args.rounds,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": w.name if nt == w.nt else f"{w.name} platform and depth, nt={nt}",
@@ -285,10 +325,32 @@ def run_search(args, torch, H):
                    "plain_batch": args.batch, "surrogate_batch": sbatch,
                    "surrogate_proposals": sbatch * args.sur_proposals, "pool": args.pool,
                    "mutate_prob": args.mutate, "parallelism": "none (1 GPU)"},
-        "plain": {"best_makespan": plain_best, "wall_ms": plain_ms, "trace": plain_tr},
+        "target_makespan": target,
+        "ratios": {"surrogate_vs_plain_wall": ratio(r_sur, plain_ms),
+                   "surrogate_vs_plain_time_to_target": ratio(r_sur, r_plain),
+                   "surrogate_vs_same_batch_greedy_time_to_target": ratio(r_sur, r_small)},
+        "plain": {"best_makespan": plain_best, "wall_ms": plain_ms, "reached_target_at_ms": r_plain,
+                  "trace": plain_tr},
+        "plain_same_batch": {"best_makespan": small_best, "wall_ms": small_tr[-1]["wall_ms"],
+                             "reached_target_at_ms": r_small, "trace": small_tr},
         "surrogate": {"best_makespan": sur_best, "wall_ms": sur_tr[-1]["wall_ms"], "trace": sur_tr,
-                      "reached_1pct_of_plain_at_ms": reach},
+                      "reached_target_at_ms": r_sur},
     }
+    if args.search_check:
+        # the oracle re-simulates every arm's best partition and a seeded sample of
+        # the instance's random candidates (simulated on the GPU alongside)
+        from oracle import oracle as O
+        bests = {"plain": (plain_d, plain_best), "plain_same_batch": (small_d, small_best),
+                 "surrogate": (best_d, sur_best)}
+        chk = {k: int(O.simulate(pf_in, nt, w.dmax, w.b, d, detail=False)) == v for k, (d, v) in bests.items()}
+        n_s = args.search_check
+        host = I.uniform_batch(w.seed + 77, n_s, nt, w.b, w.dmax, w.p_num, w.p_den)
+        ms = torch.empty(n_s, dtype=torch.int64, device=dev)
+        st = torch.empty(n_s, dtype=torch.int32, device=dev)
+        H.simulate_batch(plan, pf, H.DeviceBatch.from_host(host), ms, st)
+        want, _ = O.simulate_batch(pf_in, host, min(16, os.cpu_count() or 1))
+        chk["random_sample"] = {"candidates": n_s, "bit_exact": bool(np.array_equal(ms.cpu().numpy(), want))}
+        rec["oracle_check"] = chk
     print(json.dumps(rec), flush=True)
 
 
@@ -515,8 +577,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="chol16x16_b1024_d2")
     ap.add_argument("--n-cand", type=int, default=0)
+    ap.add_argument("--group", type=int, default=0, help="lanes per candidate (0 = autotuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--train-platforms", type=int, default=64)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--train-batch", type=int, default=4096)
@@ -526,6 +589,8 @@ def main():
     ap.add_argument("--search-nt", type=int, default=16,
                     help="tiles per dimension of the searched instance (the 64x64 one: 64)")
     ap.add_argument("--rounds", type=int, default=64)
+    ap.add_argument("--search-check", type=int, default=0, metavar="N",
+                    help="search: the oracle re-simulates each arm's best and N seeded random candidates")
     ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--mutate", type=float, default=0.004)
@@ -582,7 +647,7 @@ def main():
     ntk = torch.empty(n, dtype=torch.int32, device=dev)
     best = torch.empty(2, dtype=torch.int64, device=dev)
 
-    plan = H.Plan()
+    plan = H.Plan(group=args.group)
     plan.timing(True)
     sim_ms = []
 

@@ -195,6 +195,9 @@ typedef struct {
                                   (two workspace sets); 0 or 1 = as few chunks as memory allows */
   int32_t group;               /* lanes per candidate in the event simulation: 16, 32 or 64 (>= processors);
                                   0 = chosen per batch shape by timing each size once (autotuning) */
+  int32_t prep_edges;          /* critical-time pass: dependences inside one run of 64 consecutive tasks kept
+                                  in LDS, 1..1024 (0 = 1024); a run with more re-reads its successor lists
+                                  on every sweep (same results, slower) */
 } hesp_plan_opts;
 /* A plan with max_tasks, max_edges and group all set is a fixed-capacity plan:
  * its workspace follows from the capacities and the batch shape, so after one
@@ -368,7 +371,9 @@ int hesp_topk_score(const float *d_score, int32_t n, int32_t k, int32_t *d_idx, 
  * (host, tet(nt) bytes) and best_makespan (host) get the best partition;
  * trace[rounds] (host, nullable) gets, after each round, the wall time since the
  * start, the best makespan, and the simulated and proposed candidate counts
- * (each round synchronises `stream`).  Device workspace is allocated per call. */
+ * (each round synchronises `stream`).  Device workspace is allocated per call.
+ * The plan must not limit tasks or edges per candidate (HESP_EINVAL), so that
+ * every proposal gets a makespan. */
 enum { HESP_SEARCH_RANDOM = 0, HESP_SEARCH_GREEDY = 1, HESP_SEARCH_SURROGATE = 2 };
 typedef struct {
   int32_t mode;

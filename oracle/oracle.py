@@ -15,26 +15,33 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hesp_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# the same source built for the host it runs on (-march=native): the CPU baseline
+# compiles it on the measuring machine itself, so it never travels between hosts
+LIB_NATIVE = os.path.join(HERE, "liboracle_native.so")
 
-_lib = None
-
-
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C, -O2)."""
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
-                               "-Wall", "-Wextra", "-o", tmp, SRC])
-        os.replace(tmp, LIB)
-    return LIB
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        L = ctypes.CDLL(LIB)
+def build(force: bool = True, native: bool = False, extra_flags=()) -> str:
+    """Compile the oracle with gcc (plain C, -O2; -march=native for the baseline build)."""
+    out = LIB_NATIVE if native else LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        flags = ["-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra"]
+        if native:
+            flags.append("-march=native")
+        subprocess.check_call(["gcc", *flags, *extra_flags, "-o", tmp, SRC])
+        os.replace(tmp, out)
+    return out
+
+
+def lib(native: bool = False):
+    key = bool(native)
+    if key not in _libs:
+        path = LIB_NATIVE if native else LIB
+        if not os.path.exists(path):
+            build(native=native)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         L.oracle_simulate.argtypes = [i32, i32, P, i32, P, P, i32, i32, P, P, i64, i64, i64, i64, i32,
@@ -47,8 +54,8 @@ def lib():
         L.oracle_task_time.restype = i32
         L.oracle_transfer_time.argtypes = [i64, i64, i64, i64, i64, i32, P]
         L.oracle_transfer_time.restype = i32
-        _lib = L
-    return _lib
+        _libs[key] = L
+    return _libs[key]
 
 
 def _p(a: Optional[np.ndarray]):
@@ -135,12 +142,12 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     return Schedule(int(ms[0]), tasks, proc, start, finish, rank, edges[:m])
 
 
-def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = False):
+def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = False, native: bool = False):
     """Makespans (int64) and expanded task counts of a whole batch (policy and
     tree as in simulate; with tree=True batch.depth holds split flags and
-    batch.mask_off their offsets)."""
+    batch.mask_off their offsets; native selects the -march=native build)."""
     order, select, seed, cache, bus = (tuple(policy) + (0, 0, 0))[:5]
-    L = lib()
+    L = lib(native)
     n = batch.n
     ms = np.zeros(n, np.int64)
     ntk = np.zeros(n, np.int32)

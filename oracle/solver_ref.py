@@ -45,7 +45,6 @@ from __future__ import annotations
 import numpy as np
 
 from oracle import oracle as O
-from paper_1602_05510_amd.inputs import tet
 
 LISTS = {"all": 0, "cp": 1, "shallow": 2}
 _M64 = (1 << 64) - 1
@@ -64,6 +63,11 @@ def _draw(seed: int, purpose: int, index: int) -> int:
     state = _mix((seed + _GAMMA * (purpose + 1)) & _M64)
     return _mix((state + _GAMMA * (index + 1)) & _M64)
 SAMPLING = {"hard": 0, "soft": 1}
+
+
+def tet(n: int) -> int:
+    """Top-level tasks of the nt x nt tiled Cholesky loop nest (Fig. 1): n(n+1)(n+2)/6."""
+    return n * (n + 1) * (n + 2) // 6
 
 
 def _fine_counts(kind: int, d: int):

@@ -125,6 +125,10 @@ int hesp_internal_fail(int code, const char* msg) {
   return code;
 }
 
+// 1 when the plan limits the tasks or edges of a candidate (such candidates fail
+// with HESP_ECAPACITY)
+int hesp_internal_plan_capped(const hesp_plan* p) { return p && (p->opts.max_tasks > 0 || p->opts.max_edges > 0); }
+
 const char* hesp_last_error(void) { return g_err.c_str(); }
 const char* hesp_version(void) { return "hesp-mi355x 0.1 (gfx950)"; }
 
@@ -305,7 +309,8 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
   if (!p) return fail(HESP_ENOMEM, "hesp_plan_create: out of host memory");
   if (opts) p->opts = *opts;
   if (p->opts.slots < 0 || p->opts.max_tasks < 0 || p->opts.max_edges < 0 || p->opts.chunks < 0 ||
-      (p->opts.group != 0 && p->opts.group != 16 && p->opts.group != 32 && p->opts.group != 64)) {
+      (p->opts.group != 0 && p->opts.group != 16 && p->opts.group != 32 && p->opts.group != 64) ||
+      p->opts.prep_edges < 0 || p->opts.prep_edges > 1024) {
     delete p;
     return fail(HESP_EINVAL, "hesp_plan_create: negative option");
   }
@@ -415,30 +420,38 @@ static OutView ov_of(const hesp_outputs* o) {
   return OutView{o->d_makespan, o->d_status, o->d_n_tasks, o->d_sched_off, o->d_proc, o->d_start, o->d_finish};
 }
 
-// depth batches (batch) or split-tree batches (tree)
-static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,
-                        const hesp_tree_batch* tree, const hesp_outputs* out, void* stream) {
-  if (!plan) return fail(HESP_EINVAL, "hesp_simulate_batch: null plan");
+// argument checks and launch tables shared by the batch entry points (depth
+// batches, or split-tree batches when tree is given)
+int hesp_internal_batch_setup(const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,
+                              const hesp_tree_batch* tree, const hesp_outputs* out, SimTables& tb, BatchView& bv) {
   if ((policy.order != HESP_ORDER_PL && policy.order != HESP_ORDER_FCFS) || policy.select < HESP_SELECT_EFT ||
       policy.select > HESP_SELECT_FP || policy.cache < HESP_CACHE_WB || policy.cache > HESP_CACHE_WA ||
       policy.bus < 0 || policy.bus > 1)
     return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: PL or FCFS order, EFT-P, EIT-P, R-P or F-P selection, "
                                    "WB, WT or WA caching, bus 0 or 1");
-  SimTables tb;
   if (int r = build_tables(pf, tb)) return r;
   tb.fcfs = policy.order == HESP_ORDER_FCFS;
   tb.sel = policy.select;
   tb.seed = policy.seed;
   tb.cache = policy.cache;
   tb.bus = policy.bus;
-  BatchView bv;
   if (int r = tree ? tree_view(tree, bv, "hesp_simulate_tree_batch") : batch_view(batch, bv, "hesp_simulate_batch"))
     return r;
-  const bool is_tree = tree != nullptr;
   if (bv.dmax > pf->max_level) return fail(HESP_EINVAL, "hesp_simulate_batch: dmax above the platform's max_level");
   if (!out || !out->d_makespan || !out->d_status) return fail(HESP_EINVAL, "hesp_simulate_batch: null outputs");
   if (out->d_sched_off && (!out->d_proc || !out->d_start || !out->d_finish))
     return fail(HESP_EINVAL, "hesp_simulate_batch: schedule outputs need proc, start and finish");
+  return HESP_OK;
+}
+
+// depth batches (batch) or split-tree batches (tree)
+static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,
+                        const hesp_tree_batch* tree, const hesp_outputs* out, void* stream) {
+  if (!plan) return fail(HESP_EINVAL, "hesp_simulate_batch: null plan");
+  SimTables tb;
+  BatchView bv;
+  if (int r = hesp_internal_batch_setup(pf, policy, batch, tree, out, tb, bv)) return r;
+  const bool is_tree = tree != nullptr;
   const int n = bv.n_cand;
   if (n == 0) return ok();
   hipStream_t s = (hipStream_t)stream;
@@ -459,7 +472,8 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   };
   HIP_TRY(launch_layout(bv, pf->n_mem, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(),
                         plan->opts.max_tasks, plan->opts.max_edges, plan->off_t.as<int64_t>(),
-                        plan->off_e.as<int64_t>(), plan->off_v.as<int64_t>(), plan->off_top.as<int64_t>(), s));
+                        plan->off_e.as<int64_t>(), plan->off_v.as<int64_t>(), plan->off_top.as<int64_t>(), nullptr,
+                        s));
 
   // chunk boundaries: the largest chunk must fit the memory budget
   const bool fixed = plan->opts.max_tasks > 0 && plan->opts.max_edges > 0 && plan->opts.group > 0;
@@ -547,6 +561,7 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
     cv.nc = nc;
     cv.cap_tasks = plan->opts.max_tasks;
     cv.cap_edges = plan->opts.max_edges;
+    cv.prep_in = plan->opts.prep_edges;
     cv.top_first = w.top_first.as<uint32_t>();
     cv.desc = w.desc.as<uint32_t>();
     cv.indeg = w.indeg.as<uint32_t>();

@@ -48,6 +48,7 @@ struct ChunkView {
   const int64_t* top_off;
   int32_t c0, nc;
   int64_t cap_tasks, cap_edges;            // 0 = unlimited; larger candidates get HESP_ECAPACITY
+  int32_t prep_in;                          // critical-time pass: internal edges kept in LDS (1..1024)
   uint32_t* top_first;                      // tet(nt)+1 per candidate
   uint32_t* desc;                           // per task
   uint32_t* indeg;                          // per task
@@ -62,7 +63,21 @@ struct ChunkView {
   const uint32_t* order;                    // nullable: simulation order of the chunk's candidates
   const int32_t* cnt_tasks;                 // per candidate of the batch: expanded tasks
   const int64_t* cnt_edges;                 // per candidate of the batch: edges
+  // region mode (region != nullptr): each candidate's arrays lie together in one
+  // block of region_bytes(...) bytes at region + byte_off[c] - byte_off[c0]
+  // instead of in the per-array buffers above; candidates whose block ends past
+  // region_cap get HESP_ECAPACITY
+  const int64_t* byte_off;
+  uint8_t* region;
+  int64_t region_cap;
 };
+
+// bytes of one candidate's block in region mode: T tasks, E edges, V validity
+// words, TP top-level tasks + 1 (16-byte multiple)
+__host__ __device__ inline int64_t region_bytes(int64_t T, int64_t E, int64_t V, int64_t TP) {
+  const int64_t b = 16 * (T + 1) + 24 * T + 32 * T + 8 * V + 16 * T + 4 * E + 4 * TP;
+  return (b + 15) & ~(int64_t)15;
+}
 
 struct OutView {
   int64_t* makespan;
@@ -75,9 +90,10 @@ struct OutView {
 };
 
 hipError_t launch_count(const BatchView& b, int32_t* n_tasks, int64_t* n_edges, hipStream_t s);
+// off_b (nullable): prefix sums of region_bytes per candidate
 hipError_t launch_layout(const BatchView& b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
                          int64_t cap_t, int64_t cap_e, int64_t* off_t, int64_t* off_e, int64_t* off_v,
-                         int64_t* off_top, hipStream_t s);
+                         int64_t* off_top, int64_t* off_b, hipStream_t s);
 hipError_t launch_bounds(const int64_t* off_t, const int64_t* off_e, const int64_t* off_v, const int64_t* off_top,
                          int32_t n, int32_t chunk, int32_t n_chunks, int64_t* out, hipStream_t s);
 hipError_t launch_prepare(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o,

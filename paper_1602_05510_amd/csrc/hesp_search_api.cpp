@@ -17,6 +17,7 @@
 using namespace hesp;
 
 extern "C" int hesp_internal_fail(int code, const char* msg);
+extern "C" int hesp_internal_plan_capped(const hesp_plan* p);
 
 namespace {
 
@@ -184,6 +185,10 @@ int hesp_search(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, co
   }
   if ((int64_t)sp->pool + std::max(sp->batch, sp->warm_batch) > (1 << 24))
     return fail(HESP_EINVAL, "hesp_search: pool + batch above 2^24");
+  // every proposal has depths within 0..dmax, so only a capacity limit could
+  // fail one, and a failed candidate has no makespan to learn or keep
+  if (hesp_internal_plan_capped(plan))
+    return fail(HESP_EINVAL, "hesp_search: the plan must not limit tasks or edges per candidate");
 
   hipStream_t s = (hipStream_t)stream;
   const int32_t maxb = std::max(sp->batch, sp->warm_batch);
@@ -318,6 +323,7 @@ int hesp_search(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, co
   HIP_TRY(hipMemcpyAsync(best_makespan, pool_ms[cur], 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(best_depth, pool_d[cur], (size_t)n_top, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (*best_makespan < 0) return fail(HESP_EINVAL, "hesp_search: no candidate was simulated successfully");
   return HESP_OK;
 }
 

@@ -38,21 +38,25 @@ using namespace dev;
 
 // ---------------------------------------------------------------- layout
 
-// off_X[c] = sum over candidates before c; four columns at once (one workgroup)
+// off_X[c] = sum over candidates before c; five columns at once (one workgroup):
+// tasks, edges, validity words, top-level tasks and (when off_b is given) the
+// bytes of the candidate's region (all its arrays in one block, 16-byte aligned)
 // Candidates above a plan's task or edge capacity get no task or edge storage
 // (k_prepare marks them HESP_ECAPACITY), so a chunk never needs more than
 // (candidates x capacity).
 __global__ void __launch_bounds__(1024) k_layout(BatchView b, int32_t n_mem, const int32_t* n_tasks,
                                                  const int64_t* n_edges, int64_t cap_t, int64_t cap_e,
-                                                 int64_t* off_t, int64_t* off_e, int64_t* off_v, int64_t* off_top) {
-  __shared__ int64_t s_part[4][16];
-  __shared__ int64_t s_carry[4];
+                                                 int64_t* off_t, int64_t* off_e, int64_t* off_v, int64_t* off_top,
+                                                 int64_t* off_b) {
+  constexpr int Q = 5;
+  __shared__ int64_t s_part[Q][16];
+  __shared__ int64_t s_carry[Q];
   const int l = lane(), wv = threadIdx.x / kWave;
-  if (threadIdx.x < 4) s_carry[threadIdx.x] = 0;
+  if (threadIdx.x < Q) s_carry[threadIdx.x] = 0;
   __syncthreads();
   for (int base = 0; base < b.n_cand; base += 1024) {
     const int c = base + (int)threadIdx.x;
-    int64_t x[4] = {0, 0, 0, 0};
+    int64_t x[Q] = {0, 0, 0, 0, 0};
     if (c < b.n_cand) {
       const int nt = b.nt_arr ? b.nt_arr[c] : b.nt;
       const int dmax = b.dmax_arr ? b.dmax_arr[c] : b.dmax;
@@ -62,9 +66,10 @@ __global__ void __launch_bounds__(1024) k_layout(BatchView b, int32_t n_mem, con
       x[1] = fits ? n_edges[c] : 0;
       x[2] = ok ? ((int64_t)tri2(nt) << (2 * dmax)) * n_mem : 0;
       x[3] = ok ? tet3(nt) + 1 : 0;
+      x[4] = region_bytes(x[0], x[1], x[2], x[3]);
     }
-    int64_t incl[4];
-    for (int q = 0; q < 4; q++) {
+    int64_t incl[Q];
+    for (int q = 0; q < Q; q++) {
       int64_t v = x[q];
       for (int o = 1; o < kWave; o <<= 1) {
         const int64_t y = __shfl_up(v, o, kWave);
@@ -74,22 +79,25 @@ __global__ void __launch_bounds__(1024) k_layout(BatchView b, int32_t n_mem, con
       if (l == kWave - 1) s_part[q][wv] = v;
     }
     __syncthreads();
-    for (int q = 0; q < 4; q++) {
+    for (int q = 0; q < Q; q++) {
       int64_t pre = s_carry[q];
       for (int w = 0; w < wv; w++) pre += s_part[q][w];
-      int64_t* off = q == 0 ? off_t : (q == 1 ? off_e : (q == 2 ? off_v : off_top));
-      if (c < b.n_cand) off[c + 1] = pre + incl[q];
-      if (c == 0) off[0] = 0;
+      int64_t* off = q == 0 ? off_t : (q == 1 ? off_e : (q == 2 ? off_v : (q == 3 ? off_top : off_b)));
+      if (off && c < b.n_cand) off[c + 1] = pre + incl[q];
+      if (off && c == 0) off[0] = 0;
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < Q) {
       int64_t s = 0;
       for (int w = 0; w < 16; w++) s += s_part[threadIdx.x][w];
       s_carry[threadIdx.x] += s;
     }
     __syncthreads();
   }
-  if (b.n_cand == 0 && threadIdx.x == 0) { off_t[0] = 0; off_e[0] = 0; off_v[0] = 0; off_top[0] = 0; }
+  if (b.n_cand == 0 && threadIdx.x == 0) {
+    off_t[0] = 0; off_e[0] = 0; off_v[0] = 0; off_top[0] = 0;
+    if (off_b) off_b[0] = 0;
+  }
 }
 
 // off_X at the chunk boundaries min(i * chunk, n): out[q * (n_chunks + 1) + i]
@@ -127,6 +135,25 @@ __device__ __forceinline__ CandPtrs cand_ptrs(const ChunkView& v, int c) {
   const int64_t f = v.vf_off[c] - v.vf_off[v.c0];
   const int64_t tp = v.top_off[c] - v.top_off[v.c0];
   p.toff = t;
+  if (v.region) {
+    // region mode: the candidate's arrays one after the other in its own block,
+    // 8-byte elements first
+    const int64_t T = v.task_off[c + 1] - v.task_off[c], E = v.edge_off[c + 1] - v.edge_off[c];
+    const int64_t V = v.vf_off[c + 1] - v.vf_off[c], TP = v.top_off[c + 1] - v.top_off[c];
+    uint8_t* r = v.region + (v.byte_off[c] - v.byte_off[v.c0]);
+    p.rec = (int64_t*)r;        r += 16 * (T + 1);
+    p.fifo = (int64_t*)r;       r += 24 * T;
+    p.sortbuf = (int64_t*)r;    r += 32 * T;
+    p.vf = (int64_t*)r;         r += 8 * V;
+    p.desc = (uint32_t*)r;      r += 4 * T;
+    p.indeg = (uint32_t*)r;     r += 4 * T;
+    p.cur = (uint32_t*)r;       r += 4 * T;
+    p.ready = (uint32_t*)r;     r += 4 * T;
+    p.succ = (uint32_t*)r;      r += 4 * E;
+    p.top_first = (uint32_t*)r;
+    (void)TP;
+    return p;
+  }
   p.top_first = v.top_first + tp;
   p.desc = v.desc + t;
   p.indeg = v.indeg + t;
@@ -138,6 +165,11 @@ __device__ __forceinline__ CandPtrs cand_ptrs(const ChunkView& v, int c) {
   p.sortbuf = v.sortbuf + 4 * t;
   p.vf = v.vf + f;
   return p;
+}
+
+// a region-mode candidate whose block ends beyond the region gets no storage
+__device__ __forceinline__ bool region_overflow(const ChunkView& v, int c) {
+  return v.region && v.byte_off[c + 1] - v.byte_off[v.c0] > v.region_cap;
 }
 
 // ---------------------------------------------------------------- preparation, shared steps
@@ -163,7 +195,8 @@ __device__ __forceinline__ int64_t prep_scan_succ(const CandPtrs& sp, int64_t n_
 // time (rk), the largest critical time among its successors outside the chunk
 // (ext), the sweep's running maximum (mx) and its first edge (e, e[64] = the
 // chunk's end); the chunk's internal edges as (source << 6 | target), up to
-// kPrepIn of them (more are re-read from the successor lists in each sweep)
+// kPrepIn of them, or fewer when the plan says so (more are re-read from the
+// successor lists in each sweep)
 constexpr int kPrepIn = 1024;
 struct PrepLds {
   int64_t rk[kWave], ext[kWave], mx[kWave];
@@ -186,6 +219,7 @@ __device__ __forceinline__ void prep_finish(const ChunkView& cv, const OutView& 
                                             const CandPtrs& sp, int64_t n_fine, int64_t n_edges,
                                             const int64_t (*s_W)[kLevels], PrepLds& s) {
   const int l = lane();
+  const int in_cap = cv.prep_in >= 1 && cv.prep_in <= kPrepIn ? cv.prep_in : kPrepIn;
   // R: critical times, last chunk of 64 tasks first.  The chunk's successor
   // lists form one contiguous edge range, read by all lanes together, four
   // edges per lane per round trip: a successor beyond the chunk is final, and its
@@ -228,7 +262,7 @@ __device__ __forceinline__ void prep_finish(const ChunkView& cv, const OutView& 
         const bool inner = v[q] != kNil && v[q] < lim;
         const uint64_t m = __ballot(inner);
         const int pos = n_in + __popcll(m & lanes_below());
-        if (inner && pos < kPrepIn) s.in[pos] = (uint16_t)((src[q] << 6) | (int)(v[q] - base));
+        if (inner && pos < in_cap) s.in[pos] = (uint16_t)((src[q] << 6) | (int)(v[q] - base));
         n_in += __popcll(m);
       }
     }
@@ -239,7 +273,7 @@ __device__ __forceinline__ void prep_finish(const ChunkView& cv, const OutView& 
       s.rk[l] = r;
       s.mx[l] = ext;
       __syncthreads();
-      if (n_in <= kPrepIn) {
+      if (n_in <= in_cap) {
         for (int i = l; i < n_in; i += kWave) {
           const int u = s.in[i];
           atomicMax((long long*)&s.mx[u >> 6], (long long)s.rk[u & 63]);
@@ -311,7 +345,7 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare(SimTables tb, BatchView bv
   int status = kOK;
   if (nt < 1 || dmax < 0 || dmax > kMaxLevel || dmax > tb.max_level || (nt << dmax) > kMaxFine) status = kEINVAL;
   if (status == kOK && ((cv.cap_tasks > 0 && cv.cnt_tasks[c] > cv.cap_tasks) ||
-                        (cv.cap_edges > 0 && cv.cnt_edges[c] > cv.cap_edges)))
+                        (cv.cap_edges > 0 && cv.cnt_edges[c] > cv.cap_edges) || region_overflow(cv, c)))
     status = kECAP;
   const int64_t n_tasks = cv.task_off[c + 1] - cv.task_off[c];
   const int64_t n_edges = cv.edge_off[c + 1] - cv.edge_off[c];
@@ -439,7 +473,7 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare_tree(SimTables tb, BatchVi
   int status = kOK;
   if (!tree_shape_ok(nt, dmax) || dmax > tb.max_level) status = kEINVAL;
   if (status == kOK && ((cv.cap_tasks > 0 && cv.cnt_tasks[c] > cv.cap_tasks) ||
-                        (cv.cap_edges > 0 && cv.cnt_edges[c] > cv.cap_edges)))
+                        (cv.cap_edges > 0 && cv.cnt_edges[c] > cv.cap_edges) || region_overflow(cv, c)))
     status = kECAP;
   const uint8_t* flags = bv.depth + (int64_t)c * bv.tree_stride;
   if (status == kOK) {
@@ -1048,9 +1082,9 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
 
 hipError_t launch_layout(const BatchView& b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
                          int64_t cap_t, int64_t cap_e, int64_t* off_t, int64_t* off_e, int64_t* off_v,
-                         int64_t* off_top, hipStream_t s) {
+                         int64_t* off_top, int64_t* off_b, hipStream_t s) {
   hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, b, n_mem, n_tasks, n_edges, cap_t, cap_e, off_t, off_e,
-                     off_v, off_top);
+                     off_v, off_top, off_b);
   return hipGetLastError();
 }
 

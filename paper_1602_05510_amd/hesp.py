@@ -50,7 +50,8 @@ class TreeBatchC(ctypes.Structure):
 
 
 class PlanOpts(ctypes.Structure):
-    _fields_ = [("slots", i32), ("max_tasks", i64), ("max_edges", i64), ("chunks", i32), ("group", i32)]
+    _fields_ = [("slots", i32), ("max_tasks", i64), ("max_edges", i64), ("chunks", i32), ("group", i32),
+                ("prep_edges", i32)]
 
 
 class OutputsC(ctypes.Structure):
@@ -298,9 +299,10 @@ def count_batch(batch: DeviceBatch, stream=None):
 
 
 class Plan:
-    def __init__(self, slots: int = 0, max_tasks: int = 0, max_edges: int = 0, chunks: int = 0, group: int = 0):
+    def __init__(self, slots: int = 0, max_tasks: int = 0, max_edges: int = 0, chunks: int = 0, group: int = 0,
+                 prep_edges: int = 0):
         self.h = P()
-        self.opts = PlanOpts(slots, max_tasks, max_edges, chunks, group)
+        self.opts = PlanOpts(slots, max_tasks, max_edges, chunks, group, prep_edges)
         _check("hesp_plan_create", lib().hesp_plan_create(ctypes.byref(self.h), ctypes.byref(self.opts)))
 
     def bytes(self) -> int:
@@ -417,12 +419,30 @@ class MLP:
         _check("hesp_mlp_get_grads", lib().hesp_mlp_get_grads(self.h, _np(a), a.size))
         return a
 
+    @staticmethod
+    def _need(fn: str, what: str, t, itemsize: int, is_float: bool, numel: int):
+        """Raise before any launch unless tensor t is contiguous, has elements of
+        the stated kind and holds at least numel of them."""
+        if t is None:
+            raise HespError(fn, HESP_EINVAL, f"{what} is missing")
+        if not t.is_contiguous() or t.element_size() != itemsize or t.is_floating_point() != is_float:
+            raise HespError(fn, HESP_EINVAL, f"{what} must be a contiguous {'float' if is_float else 'integer'} "
+                                             f"tensor of {itemsize}-byte elements")
+        if int(t.numel()) < numel:
+            raise HespError(fn, HESP_EINVAL, f"{what} holds {int(t.numel())} elements, {numel} needed")
+
     def forward(self, x, y, stream=None):
         """x: uint16/int16 [n][32] bf16 bit patterns (device); y: float32 [n] (device)."""
-        _check("hesp_mlp_forward", lib().hesp_mlp_forward(self.h, _dev(x), int(y.numel()), _dev(y),
-                                                          _stream(stream)))
+        n = int(y.numel())
+        self._need("hesp_mlp_forward", "y", y, 4, True, n)
+        self._need("hesp_mlp_forward", "x", x, 2, False, n * 32)
+        _check("hesp_mlp_forward", lib().hesp_mlp_forward(self.h, _dev(x), n, _dev(y), _stream(stream)))
 
     def grad(self, x, t, batch: int, loss=None, stream=None):
+        self._need("hesp_mlp_grad", "x", x, 2, False, batch * 32)
+        self._need("hesp_mlp_grad", "t", t, 4, True, batch)
+        if loss is not None:
+            self._need("hesp_mlp_grad", "loss", loss, 4, True, 1)
         _check("hesp_mlp_grad", lib().hesp_mlp_grad(self.h, _dev(x), _dev(t), batch, _dev(loss), _stream(stream)))
 
     def adam(self, lr: float, stream=None):
@@ -430,6 +450,11 @@ class MLP:
 
     def train(self, x, t, batch: int, steps: int, lr: float, seed: int = 0, loss=None, stream=None):
         """steps Adam steps on batches drawn with replacement from the rows of (x, t)."""
+        rows = int(t.numel())
+        self._need("hesp_mlp_train", "t", t, 4, True, rows)
+        self._need("hesp_mlp_train", "x", x, 2, False, rows * 32)
+        if loss is not None:
+            self._need("hesp_mlp_train", "loss", loss, 4, True, steps)
         _check("hesp_mlp_train", lib().hesp_mlp_train(self.h, _dev(x), _dev(t), int(t.numel()), batch, steps, lr,
                                                       seed, _dev(loss), _stream(stream)))
 

@@ -230,6 +230,17 @@ class Batch:
         return Batch(self.b, self.nt[idx].copy(), self.dmax[idx].copy(), off, dep.astype(np.uint8))
 
 
+def concat_batches(batches: Sequence[Batch]) -> Batch:
+    """One batch holding the candidates of every batch in turn (same block side)."""
+    assert batches and all(bt.b == batches[0].b for bt in batches)
+    sizes = [bt.mask_off[-1] for bt in batches]
+    off = np.concatenate([[0]] + [bt.mask_off[1:] + base for bt, base in
+                                  zip(batches, np.cumsum([0] + sizes[:-1]))]).astype(np.int64)
+    return Batch(batches[0].b, np.concatenate([bt.nt for bt in batches]).astype(np.int32),
+                 np.concatenate([bt.dmax for bt in batches]).astype(np.int32), off,
+                 np.concatenate([bt.depth[:bt.mask_off[-1]] for bt in batches]).astype(np.uint8))
+
+
 def uniform_batch(seed: int, n_cand: int, nt: int, b: int, dmax: int, p_num: int, p_den: int,
                   first: int = 0) -> Batch:
     """n_cand candidates of one shape; depth draws use counters (candidate, task)."""

@@ -144,15 +144,56 @@ def test_parity_chol16x16_subset(H, torch_cuda):
 
 
 def test_parity_ragged_big_little(H, torch_cuda):
+    """The uneven big.LITTLE batch without any size filter (8..32 tiles, depths
+    0..3), plus candidates drawn further on with 28..32 tiles at depth 3."""
     w = I.WORKLOADS["ragged_bl_b512_d3"]
     pf = w.platform()
-    full = w.batch(600)
-    # keep the oracle's share bounded: candidates up to 20 tiles per dimension
-    keep = [c for c in range(full.n) if full.nt[c] <= 20]
-    bt = full.subset(keep)
+    bt = w.batch(600)
+    more = w.batch(3000, first=600)
+    big = [c for c in range(more.n) if more.nt[c] >= 28 and more.dmax[c] == 3][:24]
+    assert len(big) == 24
+    bt = I.concat_batches([bt, more.subset(big)])
+    assert bt.nt.max() == 32 and int(((bt.nt >= 28) & (bt.dmax == 3)).sum()) >= 24
     ms, st = gpu_run(H, torch_cuda, pf, bt, 3)
     assert np.all(st == 0)
     assert np.array_equal(ms, oracle_batch(pf, bt))
+
+
+def _task_keys(tasks):
+    t = np.asarray(tasks, np.int64)
+    return (t[:, 0] << 40) | (t[:, 1] << 36) | (t[:, 2] << 24) | (t[:, 3] << 12) | t[:, 4]
+
+
+def _check_schedule(H, w, pf, bt, c, off, proc, start, fin):
+    """Per-task (processor, start, finish) of candidate c against the oracle's,
+    tasks matched by (kind, level, K, I, J)."""
+    s = O.simulate(pf, int(bt.nt[c]), int(bt.dmax[c]), bt.b, bt.candidate(c))
+    tasks, _, _ = H.expand(int(bt.nt[c]), int(bt.dmax[c]), bt.candidate(c))
+    kl, ko = _task_keys(tasks), _task_keys(s.tasks)
+    assert len(kl) == len(ko) == s.n_tasks
+    order_l, order_o = np.argsort(kl), np.argsort(ko)
+    assert np.array_equal(kl[order_l], ko[order_o])
+    g = off[c] + order_l                     # library positions, in the oracle's sorted order
+    assert np.array_equal(proc[g], s.proc[order_o])
+    assert np.array_equal(start[g], s.start[order_o])
+    assert np.array_equal(fin[g], s.finish[order_o])
+    return s.makespan
+
+
+def test_parity_chol64x64_d3(H, torch_cuda):
+    """The largest instance shape: 64 x 64 tiles split up to depth 3 (512 finest
+    tiles per dimension, the limit of the 9-bit fine coordinates), 16 CPUs + 4
+    accelerators in five memory spaces; 16 seeded candidates bit-exact and two
+    of them task by task."""
+    w = I.WORKLOADS["chol64x64_b1024_d3"]
+    pf = w.platform()
+    assert w.nt << w.dmax == 512 and pf.n_mem == 5 and pf.n_procs == 20
+    bt = w.batch(16)
+    ms, st, (off, proc, start, fin) = gpu_run(H, torch_cuda, pf, bt, w.dmax, sched=True)
+    assert np.all(st == 0)
+    assert np.array_equal(ms, oracle_batch(pf, bt))
+    for c in (0, 9):
+        assert ms[c] == _check_schedule(H, w, pf, bt, c, off, proc, start, fin)
 
 
 def test_schedule_parity_per_task(H, torch_cuda):
@@ -255,3 +296,22 @@ def test_argmin(H, torch_cuda):
     v = torch.full((3,), -1, dtype=torch.int64, device="cuda")
     H.argmin(v, best)
     assert best.cpu().tolist() == [-1, -1]
+
+
+def test_critical_time_reread_path(H, torch_cuda):
+    """The critical-time pass keeps the dependences inside each run of 64
+    consecutive tasks in LDS; a plan with a small budget sends most runs through
+    the path that re-reads the successor lists on every sweep: same makespans."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf = w.platform()
+    bt = w.batch(64, first=11)
+    ref = oracle_batch(pf, bt)
+    for budget in (1, 7, 64):
+        ms, st = gpu_run(H, torch_cuda, pf, bt, w.dmax, plan=H.Plan(prep_edges=budget))
+        assert np.all(st == 0) and np.array_equal(ms, ref), budget
+    wr = I.WORKLOADS["ragged_bl_b512_d3"]
+    br = wr.batch(96, first=5)
+    ms, st = gpu_run(H, torch_cuda, wr.platform(), br, 3, plan=H.Plan(prep_edges=1))
+    assert np.all(st == 0) and np.array_equal(ms, oracle_batch(wr.platform(), br))
+    with pytest.raises(H.HespError):
+        H.Plan(prep_edges=1025)

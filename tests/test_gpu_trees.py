@@ -141,3 +141,14 @@ def test_edge_cases(H, torch):
     assert got[0] == O.simulate(pf, 3, 2, w.b, fl[0], detail=False, tree=True)
     assert got[2] == O.simulate(pf, 3, 2, w.b, np.full(I.tet(3), 2, np.uint8), detail=False)
     assert ntk[2] == I.tet(12)
+
+
+def test_trees_critical_time_reread_path(H, torch):
+    """Split-tree preparation shares the critical-time pass: with an LDS budget of
+    one internal dependence per run the re-read path gives the same makespans."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf = w.platform()
+    bt = I.tree_batch(w.seed + 3, 48, 6, w.b, 2, 1, 3)
+    want, _ = O.simulate_batch(pf, bt, NTHREADS, tree=True)
+    got, st, _, _ = _run(H, torch, pf, bt, plan=H.Plan(prep_edges=1))
+    assert (st == 0).all() and np.array_equal(got, want)

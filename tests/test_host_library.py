@@ -218,3 +218,30 @@ def test_solve_tree_argument_errors_need_no_gpu():
     assert call(H.SolveParams(1, 4, 0, 4, 0, 0, 0)) == H.HESP_EINVAL            # no level below dmax
     assert call(H.SolveParams(1, 14, 2, 4, 0, 0, 0)) == H.HESP_EUNSUPPORTED     # 560 + 4,060 > 4,096 flags
     assert call(H.SolveParams(1, 4, 2, 4, 5, 0, 0)) == H.HESP_EINVAL            # no such list
+
+
+def test_surrogate_binding_rejects_undersized_tensors():
+    """The surrogate calls check every tensor's kind and length before anything
+    reaches the library (a CPU-side object stands in for the device network)."""
+    import torch
+    m = object.__new__(H.MLP)          # no device network: nothing may be launched
+    m.h = None
+    x = torch.zeros((1024, 32), dtype=torch.int16)
+    t = torch.zeros(1024, dtype=torch.float32)
+    loss = torch.zeros(10, dtype=torch.float32)
+    cases = [
+        lambda: m.forward(x[:100], torch.zeros(101, dtype=torch.float32)),       # x short of rows
+        lambda: m.forward(x, torch.zeros(1024, dtype=torch.float64)),            # y not float32
+        lambda: m.grad(x[:511], t, 512),                                         # x short
+        lambda: m.grad(x, t[:500], 512),                                         # t short
+        lambda: m.grad(x, t, 512, torch.zeros(0, dtype=torch.float32)),          # no loss slot
+        lambda: m.grad(x.float(), t, 512),                                       # x not bf16 bits
+        lambda: m.train(x[:1000], t, 512, 10, 1e-3),                             # x short of t's rows
+        lambda: m.train(x, t, 512, 11, 1e-3, loss=loss),                         # loss short of steps
+        lambda: m.train(x, t.double(), 512, 10, 1e-3),                           # t not float32
+        lambda: m.train(x.t(), t, 512, 10, 1e-3),                                # not contiguous
+    ]
+    for i, f in enumerate(cases):
+        with pytest.raises(H.HespError) as e:
+            f()
+        assert e.value.code == H.HESP_EINVAL, i

@@ -179,10 +179,12 @@ def test_reference_oracle_passes():
 def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     so = _build_mutant(str(tmp_path), name, old, new)
-    saved_lib, saved_path = O._lib, O.LIB
+    saved_libs, saved_path = dict(O._libs), O.LIB
     try:
-        O._lib = None
+        O._libs.clear()
         O.LIB = so
         assert not _pins_pass(), f"planted mistake '{name}' went unnoticed"
     finally:
-        O._lib, O.LIB = saved_lib, saved_path
+        O._libs.clear()
+        O._libs.update(saved_libs)
+        O.LIB = saved_path
