@@ -244,6 +244,28 @@ typedef struct {
 int hesp_simulate_batch(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy,
                         const hesp_batch *batch, const hesp_outputs *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): hesp_simulate_batch of
+ * a depth batch with no plan.  Every buffer beyond the caller's inputs and
+ * outputs lies in one fixed device array of HESP_NOALLOC_BYTES bytes that the
+ * library holds on each device it runs on until the process ends; the call
+ * allocates nothing, reads nothing back and only enqueues kernels on `stream`.
+ * Outputs and statuses are those of hesp_simulate_batch (same makespans and
+ * schedules).  Limits: n_cand <= HESP_NOALLOC_MAX_CAND (else HESP_EINVAL before
+ * anything is enqueued); the candidates' workspaces are laid out in candidate
+ * order, region_bytes = 88 T + 4 E + 8 V + 4 (tet(nt) + 1) + 16 bytes each (T
+ * tasks, E edges, V = finest blocks x memory spaces, rounded up to 16), and a
+ * candidate whose workspace would end past HESP_NOALLOC_REGION bytes gets
+ * HESP_ECAPACITY (makespan -1), as do all candidates after it.  group: lanes
+ * per candidate (16, 32, 64, at least n_procs), 0 = the smallest that fits.
+ * All calls on one device share the array: calls that overlap in time on one
+ * device (different streams or host threads) race and give wrong results. */
+#define HESP_NOALLOC_BYTES (64 << 20)
+#define HESP_NOALLOC_MAX_CAND 16384
+#define HESP_NOALLOC_REGION 66189824   /* the part holding candidate workspaces */
+int hesp_simulate_batch_noalloc(const hesp_platform *pf, hesp_policy policy, const hesp_batch *batch,
+                                const hesp_outputs *out, int32_t group, void *stream);
+
 /* ---- split-tree candidates ---------------------------------------------------
  * Section 2.1 ("Recursive task partitioners") applies a partition to any task,
  * so sub-tasks of one top-level task may end at different depths.  A split-tree

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhesp.so")
 
-SOURCES = ["hesp_kernels.hip", "hesp_sim.hip", "hesp_mlp.hip", "hesp_search.hip", "hesp_solve.hip", "hesp_api.cpp",
+SOURCES = ["hesp_kernels.hip", "hesp_sim.hip", "hesp_mlp.hip", "hesp_search.hip", "hesp_solve.hip", "hesp_noalloc.hip", "hesp_api.cpp",
            "hesp_mlp_api.cpp", "hesp_search_api.cpp", "hesp_solve_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

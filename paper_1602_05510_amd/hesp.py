@@ -119,6 +119,8 @@ def lib():
             "hesp_plan_last_ms": [P, P],
             "hesp_simulate_batch": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(BatchC),
                                     ctypes.POINTER(OutputsC), P],
+            "hesp_simulate_batch_noalloc": [ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(BatchC),
+                                            ctypes.POINTER(OutputsC), i32, P],
             "hesp_argmin": [P, i32, P, P],
             "hesp_mlp_create": [ctypes.POINTER(P), u64],
             "hesp_mlp_destroy": [P],
@@ -338,6 +340,20 @@ def simulate_batch(plan: Plan, pf: Platform, batch: DeviceBatch, makespan, statu
     _check("hesp_simulate_batch", lib().hesp_simulate_batch(plan.h, ctypes.byref(pf.c), Policy(*policy),
                                                             ctypes.byref(batch.c), ctypes.byref(out),
                                                             _stream(stream)))
+
+
+NOALLOC_BYTES, NOALLOC_MAX_CAND, NOALLOC_REGION = 64 << 20, 16384, 66189824
+
+
+def simulate_batch_noalloc(pf: Platform, batch: DeviceBatch, makespan, status, group: int = 0, sched_off=None,
+                           proc=None, start=None, finish=None, stream=None, policy=(0, 0, 0), n_tasks=None):
+    """simulate_batch without a plan: the library's fixed device array is the only workspace."""
+    out = OutputsC(_dev(makespan), _dev(status), _dev(n_tasks), _dev(sched_off), _dev(proc), _dev(start),
+                   _dev(finish))
+    _check("hesp_simulate_batch_noalloc", lib().hesp_simulate_batch_noalloc(ctypes.byref(pf.c), Policy(*policy),
+                                                                            ctypes.byref(batch.c),
+                                                                            ctypes.byref(out), int(group),
+                                                                            _stream(stream)))
 
 
 class TreeBatch:
