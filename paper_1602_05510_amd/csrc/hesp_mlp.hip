@@ -41,92 +41,11 @@ __device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
   return __builtin_bit_cast(uint32_t, r);
 }
 
-// ---------------------------------------------------------------- GEMM
-// C[M][N] = opA[M][K] * opB[K][N], bf16 inputs, fp32 accumulation.
-//   opA[m][k] = TA ? A[k*lda + m] : A[m*lda + k]
-//   opB[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n]
-// Epilogue: + bias[n]; ReLU; zero where mask[m*ldm + n] == 0; store fp32
-// and/or bf16 at m*ldc + n.  Split-K: blockIdx.z takes K range
-// [z*kc, (z+1)*kc) and writes fp32 to out_f32 + z*M*ldc.
-// Tile 64x64 per 256-thread workgroup (2x2 waves of 32x32, each 2x2 MFMA
-// 16x16x32 blocks); requires N % 64 == 0 and kc % 32 == 0; any M.
-constexpr int TM = 64, TN = 64, TK = 32, LDS_K = TK + 8;
-
-template <bool TA, bool TB>
-__global__ void __launch_bounds__(256) k_gemm(int M, int N, int kc, const uint16_t* __restrict__ A, int lda,
-                                              const uint16_t* __restrict__ B, int ldb, const float* __restrict__ bias,
-                                              int relu, const uint16_t* __restrict__ mask, int ldm,
-                                              float* __restrict__ out_f32, uint16_t* __restrict__ out_bf16,
-                                              int ldc) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[TM][LDS_K];   // [m][k]
-  __shared__ __attribute__((aligned(16))) uint16_t sB[TN][LDS_K];   // [n][k]
-  const int t = threadIdx.x, l = t & 63, w = t >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
-  const int kbeg = blockIdx.z * kc, kend = kbeg + kc;
-  f32x4 acc[2][2];
-  for (int i = 0; i < 2; i++)
-    for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  for (int k0 = kbeg; k0 < kend; k0 += TK) {
-    // stage A
-    if (!TA) {
-      const int r = t >> 2, kk = (t & 3) * 8;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (m0 + r < M) v = *(const u32x4*)(A + (int64_t)(m0 + r) * lda + k0 + kk);
-      *(u32x4*)&sA[r][kk] = v;
-    } else {
-      const int k = t >> 3, mm = (t & 7) * 8;
-      uint16_t v[8];
-      if (m0 + mm + 7 < M) {
-        const u32x4 q = *(const u32x4*)(A + (int64_t)(k0 + k) * lda + m0 + mm);
-        *(u32x4*)v = q;
-      } else {
-        for (int j = 0; j < 8; j++) v[j] = (m0 + mm + j < M) ? A[(int64_t)(k0 + k) * lda + m0 + mm + j] : 0;
-      }
-      for (int j = 0; j < 8; j++) sA[mm + j][k] = v[j];
-    }
-    // stage B as [n][k]
-    if (TB) {
-      const int n = t >> 2, kk = (t & 3) * 8;
-      *(u32x4*)&sB[n][kk] = *(const u32x4*)(B + (int64_t)(n0 + n) * ldb + k0 + kk);
-    } else {
-      const int k = t >> 3, nn = (t & 7) * 8;
-      uint16_t v[8];
-      *(u32x4*)v = *(const u32x4*)(B + (int64_t)(k0 + k) * ldb + n0 + nn);
-      for (int j = 0; j < 8; j++) sB[nn + j][k] = v[j];
-    }
-    __syncthreads();
-    // lane l: row/col l % 16 of a 16x16 block, k = (l / 16) * 8 .. + 8
-    bf16x8 a[2], b[2];
-    for (int i = 0; i < 2; i++) a[i] = *(const bf16x8*)&sA[wm * 32 + i * 16 + (l & 15)][(l >> 4) * 8];
-    for (int j = 0; j < 2; j++) b[j] = *(const bf16x8*)&sB[wn * 32 + j * 16 + (l & 15)][(l >> 4) * 8];
-    for (int i = 0; i < 2; i++)
-      for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
-  }
-  // lane l holds rows (l / 16) * 4 + q, column l % 16 of each block
-  float* outz = out_f32 ? out_f32 + (int64_t)blockIdx.z * M * ldc : nullptr;
-  for (int i = 0; i < 2; i++)
-    for (int j = 0; j < 2; j++)
-      for (int q = 0; q < 4; q++) {
-        const int m = m0 + wm * 32 + i * 16 + (l >> 4) * 4 + q;
-        const int n = n0 + wn * 32 + j * 16 + (l & 15);
-        if (m >= M) continue;
-        float v = acc[i][j][q];
-        if (bias) v += bias[n];
-        if (relu) v = v > 0.f ? v : 0.f;
-        if (mask && mask[(int64_t)m * ldm + n] == 0) v = 0.f;
-        if (outz) outz[(int64_t)m * ldc + n] = v;
-        if (out_bf16) out_bf16[(int64_t)m * ldc + n] = f2bf(v);
-      }
-}
-
 // ---------------------------------------------------------------- fused forward
 // The whole network for 128 rows per 512-thread workgroup.  Activations stay in
-// LDS (128 x 256 bf16); weights come from L2 in a transposed bf16 copy
-// (wt[n][k], k contiguous) so that each lane's weight operand is one 16-byte
-// load.  Eight 16x16 blocks x two column blocks of accumulators per wave (64
+// LDS (128 x 256 bf16); weights come from L2 in the fragment-ordered bf16 copy
+// of W^T (output feature rows, input features contiguous), so that each lane's
+// weight operand is one 16-byte load and a wave's is one contiguous 1 KB.  Eight 16x16 blocks x two column blocks of accumulators per wave (64
 // registers; 128 in all with the operand fragments and the ring of weight
 // fragments), so four waves fit on each SIMD; two workgroups share a CU's LDS.
 // The last layer's dot with w4 is reduced across lanes and waves through LDS.
@@ -184,7 +103,7 @@ __global__ void __launch_bounds__(FWAVES * 64, 4) k_mlp_fwd(const uint16_t* __re
   {
     bf16x8 wf[2];
     for (int cb = 0; cb < 2; cb++)
-      wf[cb] = *(const bf16x8*)(wt + kOffT1 + (int64_t)(w * 32 + cb * 16 + (l & 15)) * kInDim + (l >> 4) * 8);
+      wf[cb] = *(const bf16x8*)(wt + kFrW1T + ((int64_t)(w * 2 + cb) * 64 + l) * 8);
     // every row block's input is requested before the first product: rows past
     // the end read the last row (n >= 1) and are then replaced by zeros, so the
     // loads carry no branch and their memory latencies overlap
@@ -209,10 +128,9 @@ __global__ void __launch_bounds__(FWAVES * 64, 4) k_mlp_fwd(const uint16_t* __re
   // ring of FPRE + 1 register slots (the slot of step g - 1, already consumed).
   bf16x8 wq[FPRE + 1][2];
   auto wload = [&](int g) {
-    const uint16_t* wl = wt + (g < FKS ? kOffT2 : kOffT3) + (int64_t)(w * 32 + (l & 15)) * kHidden + (l >> 4) * 8 +
-                         (g % FKS) * 32;
+    const uint16_t* wl = wt + (g < FKS ? kFrW2T : kFrW3T) + ((int64_t)(w * 2) * FKS + g % FKS) * 64 * 8 + l * 8;
 #pragma unroll
-    for (int cb = 0; cb < 2; cb++) wq[(g) % (FPRE + 1)][cb] = *(const bf16x8*)(wl + (int64_t)cb * 16 * kHidden);
+    for (int cb = 0; cb < 2; cb++) wq[(g) % (FPRE + 1)][cb] = *(const bf16x8*)(wl + (int64_t)cb * FKS * 64 * 8);
   };
 #pragma unroll
   for (int g = 0; g < FPRE; g++) wload(g);
@@ -266,29 +184,508 @@ __global__ void __launch_bounds__(FWAVES * 64, 4) k_mlp_fwd(const uint16_t* __re
   }
 }
 
-// transposed bf16 copies of W1, W2, W3 (wt[n][k] = W[k][n])
-__global__ void k_transpose_w(const float* __restrict__ p, uint16_t* __restrict__ wt) {
-  const int64_t total = kTParams;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+// fragment-ordered bf16 copies (kFr*): W1^T, W2^T, W3^T, W2, W3
+__global__ void k_frag_w(const float* __restrict__ p, uint16_t* __restrict__ wfr) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < kFrParams; e += (int64_t)gridDim.x * blockDim.x) {
+    const int mat = e < kFrW2T ? 0 : (e < kFrW3T ? 1 : (e < kFrW2 ? 2 : (e < kFrW3 ? 3 : 4)));
+    const int64_t base = mat == 0 ? kFrW1T : (mat == 1 ? kFrW2T : (mat == 2 ? kFrW3T : (mat == 3 ? kFrW2 : kFrW3)));
+    const int K = mat == 0 ? kInDim : kHidden;
+    const int64_t x = e - base, chunk = x >> 3;
+    const int lane = (int)(chunk & 63), blk = (int)(chunk >> 6);
+    const int row = (blk / (K >> 5)) * 16 + (lane & 15);
+    const int k = (blk % (K >> 5)) * 32 + (lane >> 4) * 8 + (int)(x & 7);
     int64_t src;
-    if (e < kOffT2) {
-      const int64_t nn = e / kInDim, kk = e % kInDim;
-      src = kOffW1 + kk * kHidden + nn;
-    } else {
-      const int64_t f = e < kOffT3 ? e - kOffT2 : e - kOffT3;
-      const int64_t nn = f / kHidden, kk = f % kHidden;
-      src = (e < kOffT3 ? kOffW2 : kOffW3) + kk * kHidden + nn;
-    }
-    wt[e] = f2bf(p[src]);
+    if (mat == 0) src = kOffW1 + (int64_t)k * kHidden + row;            // W1^T[n][i] = W1[i][n]
+    else if (mat <= 2) src = (mat == 1 ? kOffW2 : kOffW3) + (int64_t)k * kHidden + row;
+    else src = (mat == 3 ? kOffW2 : kOffW3) + (int64_t)row * kHidden + k;
+    wfr[e] = f2bf(p[src]);
   }
 }
 
-// sum of `splits` fp32 slices of size count -> out (fp32)
-__global__ void k_sum_splits(const float* __restrict__ parts, int splits, int64_t count, float* __restrict__ out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+// Adam (Kingma and Ba, 2015) on one fp32 master weight, as k_adam; returns the
+// bf16 bits of the new weight, also stored in the bf16 copy
+__device__ __forceinline__ uint16_t adam_one(const AdamArgs& a, int64_t i, float gi) {
+  const float m = a.b1 * a.m1[i] + (1.f - a.b1) * gi;
+  const float v = a.b2 * a.m2[i] + (1.f - a.b2) * gi * gi;
+  a.m1[i] = m;
+  a.m2[i] = v;
+  const float wi = a.p[i] - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + a.eps);
+  a.p[i] = wi;
+  const uint16_t b = f2bf(wi);
+  a.wbf[i] = b;
+  return b;
+}
+
+// ---------------------------------------------------------------- training step
+// One gradient step is three launches.
+//   k_tr_rows  (TRB rows per workgroup): forward pass with the activations kept
+//              in LDS, output-layer backward, and the data gradients dz3, dz2,
+//              dz1 of the hidden layers (rows are independent up to here).  The
+//              inputs, activations and data gradients are also written in the
+//              packed layout below, the operand layout of the next pass.
+//   k_tr_wgrad (a 64 x 64 tile of a weight matrix and 512 rows per workgroup):
+//              partial weight and bias gradients as MFMA products over the rows;
+//   k_tr_adam  sums the partial sums of every tile in a fixed order, writes the
+//              gradient and, in a training step, applies Adam and refreshes the
+//              bf16 copies (so one gradient step is three launches).
+// Rounding points are those of the forward pass above and of the reference:
+// activations and data gradients are bf16 (round to nearest even), products
+// accumulate in fp32, dy and every gradient are fp32.
+// Row pass shape: RT 16-row blocks per workgroup (TRB = 16 RT rows) and NW waves,
+// wave w owning CT = 16 / NW column blocks of 16, columns [16 CT w, 16 CT (w + 1)).
+constexpr int TRT = 1, TNW = 16;
+constexpr int TRB = 16 * TRT;
+
+// Packed layout of a [rows][F] bf16 tensor: element (b, f) at ((b / 8) F + f) 8 + b % 8,
+// so that one feature of eight consecutive rows is one 16-byte chunk.
+__device__ __forceinline__ int64_t pk(int64_t b, int64_t f, int F) { return ((b >> 3) * F + f) * 8 + (b & 7); }
+
+__device__ __forceinline__ bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{a, b}), bf16x2));
+}
+__device__ __forceinline__ float lo_f(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
+__device__ __forceinline__ float hi_f(uint32_t w) { return __builtin_bit_cast(float, w & 0xFFFF0000u); }
+
+// 4 values of rows row0 .. row0+3 of one column: into the LDS tile (row-major,
+// swizzled) and into the packed global tensor (one 8-byte store; row0 % 4 == 0)
+__device__ __forceinline__ void tr_put(uint32_t v01, uint32_t v23, uint16_t* sT, uint16_t* __restrict__ gp,
+                                       int64_t grow0, int row0, int col) {
+  sT[sh_off(row0 + 0, col)] = (uint16_t)v01;
+  sT[sh_off(row0 + 1, col)] = (uint16_t)(v01 >> 16);
+  sT[sh_off(row0 + 2, col)] = (uint16_t)v23;
+  sT[sh_off(row0 + 3, col)] = (uint16_t)(v23 >> 16);
+  *(uint2*)(gp + pk(grow0 + row0, col, kHidden)) = make_uint2(v01, v23);
+}
+
+// The weight fragments of a K = 256 product for the wave's CT column blocks
+// (row blocks rb0 .. rb0 + CT - 1 of a fragment-ordered matrix), all eight
+// k-steps: one contiguous 1 KB per fragment.  They do not depend on the
+// activations, so each product's fragments are requested one stage ahead (a
+// scheduling barrier keeps the loads where they are issued).
+template <int CT>
+struct WFrags {
+  u32x4 f[FKS][CT];
+};
+template <int CT>
+__device__ __forceinline__ void tr_wload(WFrags<CT>& wf, const uint16_t* __restrict__ m, int rb0, int l) {
+#pragma unroll
+  for (int ks = 0; ks < FKS; ks++)
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) wf.f[ks][ct] = *(const u32x4*)(m + (((int64_t)(rb0 + ct) * FKS + ks) * 64 + l) * 8);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// acc[rt][ct] += rows 16 rt .. of the LDS tile sIn (K = 256) times the fragments
+template <int RT, int CT>
+__device__ __forceinline__ void tr_gemm(f32x4 (&acc)[RT][CT], const uint16_t* sIn, const WFrags<CT>& wf, int l) {
+#pragma unroll
+  for (int ks = 0; ks < FKS; ks++) {
+    const int k = ks * 32 + (l >> 4) * 8;
+    bf16x8 a[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) a[rt] = *(const bf16x8*)&sIn[sh_off(rt * 16 + (l & 15), k)];
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], as_bf(wf.f[ks][ct]), acc[rt][ct], 0, 0, 0);
+  }
+}
+
+// bias of the lane's column in all four rows of every accumulator block
+template <int RT, int CT>
+__device__ __forceinline__ void tr_bias(f32x4 (&acc)[RT][CT], const float* __restrict__ b, int c0) {
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++) {
+    const float v = b ? b[c0 + 16 * ct] : 0.f;
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) acc[rt][ct] = f32x4{v, v, v, v};
+  }
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): training row r of step `step` is row
+// draw(seed, 7, step << 32 | r) mod n
+__device__ __forceinline__ int64_t tr_row(uint64_t seed, uint64_t step, int64_t r, int64_t n) {
+  auto mix = [](uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  const uint64_t g = 0x9E3779B97F4A7C15ull;
+  return (int64_t)(mix(mix(seed + g * 8ull) + g * (((step << 32) | (uint64_t)r) + 1)) % (uint64_t)n);
+}
+
+// sample: rows drawn as above from (x, t) of n rows; else rows blockIdx.x * TRB .. of x, t
+template <int RT, int NW>
+__global__ void __launch_bounds__(NW * 64) k_tr_rows(const uint16_t* __restrict__ x, const float* __restrict__ t,
+                                                     int64_t n, int sample, uint64_t seed, uint64_t step, int batch,
+                                                     const uint16_t* __restrict__ wt, const uint16_t* __restrict__ wb,
+                                                     const float* __restrict__ p, TrainBufs tb) {
+  constexpr int RB = 16 * RT, CT = 16 / NW;
+  __shared__ __attribute__((aligned(16))) uint16_t sX[RB * kInDim];
+  __shared__ __attribute__((aligned(16))) uint16_t sH1[RB * kHidden];
+  __shared__ __attribute__((aligned(16))) uint16_t sH2[RB * kHidden];
+  __shared__ __attribute__((aligned(16))) uint16_t sT3[RB * kHidden];   // dz3
+  __shared__ __attribute__((aligned(16))) uint16_t sD2[RB * kHidden];   // dz2
+  __shared__ float sYp[NW][RB];
+  __shared__ float sDy[RB], sT[RB];
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * RB;
+  const int c0 = w * 16 * CT + (l & 15);   // the lane's columns: c0 + 16 ct
+  const int rb0 = w * CT;                  // their 16-row blocks of the fragment-ordered weights
+  const int rq = (l >> 4) * 4;             // first of the lane's four rows in a 16-row block
+
+  // inputs: 16 bytes per thread, and the packed copy of the rows
+  for (int q = tid; q < RB * 4; q += NW * 64) {
+    const int j = q >> 2, c = q & 3;
+    const int64_t src = sample ? tr_row(seed, step, r0 + j, n) : r0 + j;
+    *(u32x4*)&sX[j * kInDim + c * 8] = *(const u32x4*)(x + src * kInDim + c * 8);
+    if (c == 0) sT[j] = t[src];
+  }
+  WFrags<CT> wA, wB;
+  tr_wload(wA, wt + kFrW2T, rb0, l);
+  __syncthreads();
+  for (int q = tid; q < (RB / 8) * kInDim; q += NW * 64) {
+    const int b8 = q / kInDim, f = q % kInDim;
+    uint32_t v[4];
+    for (int e = 0; e < 4; e++)
+      v[e] = (uint32_t)sX[(b8 * 8 + 2 * e) * kInDim + f] | ((uint32_t)sX[(b8 * 8 + 2 * e + 1) * kInDim + f] << 16);
+    *(u32x4*)(tb.xp + ((r0 / 8 + b8) * kInDim + f) * 8) = u32x4{v[0], v[1], v[2], v[3]};
+  }
+
+  f32x4 acc[RT][CT];
+  // layer 1 (K = 32)
+  tr_bias(acc, p + kOffB1, c0);
+  {
+    u32x4 b1[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+      b1[ct] = *(const u32x4*)(wt + kFrW1T + ((int64_t)(rb0 + ct) * 64 + l) * 8);
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+      const bf16x8 a = *(const bf16x8*)&sX[(rt * 16 + (l & 15)) * kInDim + (l >> 4) * 8];
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf(b1[ct]), acc[rt][ct], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+      tr_put(relu_bf16x2(acc[rt][ct][0], acc[rt][ct][1]), relu_bf16x2(acc[rt][ct][2], acc[rt][ct][3]), sH1, tb.h1p,
+             r0, rt * 16 + rq, c0 + 16 * ct);
+  __syncthreads();
+  // layer 2
+  tr_wload(wB, wt + kFrW3T, rb0, l);
+  tr_bias(acc, p + kOffB2, c0);
+  tr_gemm(acc, sH1, wA, l);
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+      tr_put(relu_bf16x2(acc[rt][ct][0], acc[rt][ct][1]), relu_bf16x2(acc[rt][ct][2], acc[rt][ct][3]), sH2, tb.h2p,
+             r0, rt * 16 + rq, c0 + 16 * ct);
+  __syncthreads();
+  // layer 3: h3 stays in registers (the lane computes dz3 at the same places);
+  // partial output dots over the wave's columns
+  tr_wload(wA, wt + kFrW3, rb0, l);
+  tr_bias(acc, p + kOffB3, c0);
+  tr_gemm(acc, sH2, wB, l);
+  uint32_t h3[RT][CT][2];
+  float w4f[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++) w4f[ct] = bf2f(wb[kOffW4 + c0 + 16 * ct]);
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++) {
+    float py[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      h3[rt][ct][0] = relu_bf16x2(acc[rt][ct][0], acc[rt][ct][1]);
+      h3[rt][ct][1] = relu_bf16x2(acc[rt][ct][2], acc[rt][ct][3]);
+      *(uint2*)(tb.h3p + pk(r0 + rt * 16 + rq, c0 + 16 * ct, kHidden)) = make_uint2(h3[rt][ct][0], h3[rt][ct][1]);
+      py[0] += lo_f(h3[rt][ct][0]) * w4f[ct];
+      py[1] += hi_f(h3[rt][ct][0]) * w4f[ct];
+      py[2] += lo_f(h3[rt][ct][1]) * w4f[ct];
+      py[3] += hi_f(h3[rt][ct][1]) * w4f[ct];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      float v = py[q];
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      if ((l & 15) == 0) sYp[w][rt * 16 + rq + q] = v;
+    }
+  }
+  __syncthreads();
+  // output, dy = 2 (y - t) / batch, loss terms (y - t)^2 / batch
+  if (tid < RB) {
+    float y = p[kOffB4];
+    for (int q = 0; q < NW; q++) y += sYp[q][tid];
+    const float d = y - sT[tid];
+    const float g = 2.f * d / (float)batch;
+    sDy[tid] = g;
+    tb.dy[r0 + tid] = g;
+    float lp = d * d / (float)batch;
+    for (int o = 1; o < RB; o <<= 1) lp += __shfl_xor(lp, o, 64);
+    if (tid == 0) tb.lossp[blockIdx.x] = lp;   // summed in block order by k_tr_adam
+  }
+  __syncthreads();
+  // dz3 = bf16(dy w4) where h3 > 0
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      uint16_t v[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const uint32_t hb = q & 1 ? h3[rt][ct][q >> 1] >> 16 : h3[rt][ct][q >> 1] & 0xFFFFu;
+        v[q] = hb != 0 ? f2bf(sDy[rt * 16 + rq + q] * w4f[ct]) : (uint16_t)0;
+      }
+      tr_put(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), sT3, tb.d3p, r0, rt * 16 + rq,
+             c0 + 16 * ct);
+    }
+  __syncthreads();
+  // dz2 = bf16(dz3 W3^T) where h2 > 0, then dz1 = bf16(dz2 W2^T) where h1 > 0
+  // (W[i][n] rows are the weight fragments: output column i, k = n contiguous)
+#pragma unroll
+  for (int layer = 3; layer >= 2; layer--) {
+    const uint16_t* sIn = layer == 3 ? sT3 : sD2;
+    const uint16_t* sMask = layer == 3 ? sH2 : sH1;
+    if (layer == 3) tr_wload(wB, wt + kFrW2, rb0, l);
+    tr_bias(acc, nullptr, c0);
+    tr_gemm(acc, sIn, layer == 3 ? wA : wB, l);
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int col = c0 + 16 * ct, row = rt * 16 + rq;
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) v[q] = sMask[sh_off(row + q, col)] != 0 ? acc[rt][ct][q] : 0.f;
+        const uint32_t v01 = bf16x2_rne(v[0], v[1]), v23 = bf16x2_rne(v[2], v[3]);
+        if (layer == 3) {
+          tr_put(v01, v23, sD2, tb.d2p, r0, row, col);
+        } else {
+          *(uint2*)(tb.d1p + pk(r0 + row, col, kHidden)) = make_uint2(v01, v23);
+        }
+      }
+    if (layer == 3) __syncthreads();
+  }
+}
+
+// Weight-gradient tiles: 0..3 the 32 x 64 tiles of W1 (columns 64 t ..), 4..19 the
+// 64 x 64 tiles of W2 and 20..35 those of W3 (rows 64 (u / 4) .., columns 64 (u % 4) ..).
+constexpr int kTrTiles = 36;
+constexpr int kTrRows = 128;                    // rows of one wave's slice (four k-steps)
+constexpr int kPartW = 64 * 64;                 // partial sums of one workgroup: weights,
+constexpr int kPartStride = kPartW + 3 * 64;    // then bias, w4 and b4 sums (64 each)
+static_assert(kTrTiles == kTrainTiles && kPartStride == kTrainPartStride, "training workspace sizes of hesp_mlp.h");
+
+struct TileInfo {
+  int layer, i0, n0, rows, F;
+  bool bias, out4;
+};
+__device__ __forceinline__ TileInfo tile_info(int tile) {
+  TileInfo t;
+  t.layer = tile < 4 ? 1 : (tile < 20 ? 2 : 3);
+  const int u = t.layer == 1 ? 0 : (t.layer == 2 ? tile - 4 : tile - 20);
+  t.i0 = t.layer == 1 ? 0 : 64 * (u / 4);
+  t.n0 = t.layer == 1 ? 64 * tile : 64 * (u % 4);
+  t.rows = t.layer == 1 ? 32 : 64;
+  t.F = t.layer == 1 ? kInDim : kHidden;
+  t.bias = t.i0 == 0;
+  t.out4 = t.layer == 3 && t.i0 == 0;
+  return t;
+}
+
+// Partial sums: workgroup (tile, group g), g < G = batch / 512; its four waves sum
+// the rows [(4 g + w) 128, + 128) (four k-steps, every operand requested before
+// the first product) and add their sums in wave order.
+__global__ void __launch_bounds__(256) k_tr_wgrad(TrainBufs tb, int G) {
+  __shared__ float sAcc[4][kPartW];
+  __shared__ float sVec[4][3][64];
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int tile = blockIdx.x / G, grp = blockIdx.x % G;
+  const TileInfo ti = tile_info(tile);
+  const int mi = ti.rows / 16;
+  const uint16_t* A = ti.layer == 1 ? tb.xp : (ti.layer == 2 ? tb.h1p : tb.h2p);
+  const uint16_t* B = ti.layer == 1 ? tb.d1p : (ti.layer == 2 ? tb.d2p : tb.d3p);
+  const int64_t b8_0 = (int64_t)(grp * 4 + w) * (kTrRows / 8) + (l >> 4);
+
+  constexpr int KS = kTrRows / 32;
+  u32x4 fa[KS][4], fb[KS][4], fh[KS][4];
+  f32x4 fd[KS][2];
+#pragma unroll
+  for (int ks = 0; ks < KS; ks++) {
+    const int64_t b8 = b8_0 + ks * 4;
+#pragma unroll
+    for (int ib = 0; ib < 4; ib++)
+      if (ib < mi) fa[ks][ib] = *(const u32x4*)(A + (b8 * ti.F + ti.i0 + ib * 16 + (l & 15)) * 8);
+#pragma unroll
+    for (int jb = 0; jb < 4; jb++) fb[ks][jb] = *(const u32x4*)(B + (b8 * kHidden + ti.n0 + jb * 16 + (l & 15)) * 8);
+    if (ti.out4) {
+#pragma unroll
+      for (int jb = 0; jb < 4; jb++)
+        fh[ks][jb] = *(const u32x4*)(tb.h3p + (b8 * kHidden + ti.n0 + jb * 16 + (l & 15)) * 8);
+      fd[ks][0] = *(const f32x4*)(tb.dy + b8 * 8);
+      fd[ks][1] = *(const f32x4*)(tb.dy + b8 * 8 + 4);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int ib = 0; ib < 4; ib++)
+#pragma unroll
+    for (int jb = 0; jb < 4; jb++) acc[ib][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bs[4] = {0.f, 0.f, 0.f, 0.f}, ws[4] = {0.f, 0.f, 0.f, 0.f}, b4s = 0.f;
+#pragma unroll
+  for (int ks = 0; ks < KS; ks++) {
+#pragma unroll
+    for (int ib = 0; ib < 4; ib++)
+      if (ib < mi)
+#pragma unroll
+        for (int jb = 0; jb < 4; jb++)
+          acc[ib][jb] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(fa[ks][ib]), as_bf(fb[ks][jb]), acc[ib][jb], 0, 0, 0);
+    if (ti.bias) {
+#pragma unroll
+      for (int jb = 0; jb < 4; jb++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) bs[jb] += lo_f(fb[ks][jb][e]) + hi_f(fb[ks][jb][e]);
+    }
+    if (ti.out4) {
+      const float d[8] = {fd[ks][0][0], fd[ks][0][1], fd[ks][0][2], fd[ks][0][3],
+                          fd[ks][1][0], fd[ks][1][1], fd[ks][1][2], fd[ks][1][3]};
+#pragma unroll
+      for (int jb = 0; jb < 4; jb++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) ws[jb] += lo_f(fh[ks][jb][e]) * d[2 * e] + hi_f(fh[ks][jb][e]) * d[2 * e + 1];
+      if ((l & 15) == 0)
+        for (int e = 0; e < 8; e++) b4s += d[e];
+    }
+  }
+
+#pragma unroll
+  for (int ib = 0; ib < 4; ib++)
+    if (ib < mi)
+#pragma unroll
+      for (int jb = 0; jb < 4; jb++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) sAcc[w][(ib * 16 + (l >> 4) * 4 + q) * 64 + jb * 16 + (l & 15)] = acc[ib][jb][q];
+#pragma unroll
+  for (int jb = 0; jb < 4; jb++) {
+    float b = bs[jb], c = ws[jb];
+    b += __shfl_xor(b, 16, 64);
+    b += __shfl_xor(b, 32, 64);
+    c += __shfl_xor(c, 16, 64);
+    c += __shfl_xor(c, 32, 64);
+    if (l < 16) {
+      sVec[w][0][jb * 16 + l] = b;
+      sVec[w][1][jb * 16 + l] = c;
+    }
+  }
+  b4s += __shfl_xor(b4s, 16, 64);
+  b4s += __shfl_xor(b4s, 32, 64);
+  sVec[w][2][l] = l == 0 ? b4s : 0.f;
+  __syncthreads();
+  float* part = tb.part + ((int64_t)tile * G + grp) * kPartStride;
+  const int nn = tid & 63, ib0 = (tid >> 6) * 16;   // thread: column nn, rows ib0 .. ib0 + 15
+  for (int e = 0; e < 16; e++) {
+    const int i = ib0 + e;
+    if (i < ti.rows) {
+      const int x = i * 64 + nn;
+      part[x] = ((sAcc[0][x] + sAcc[1][x]) + sAcc[2][x]) + sAcc[3][x];
+    }
+  }
+  if (tid < 3 * 64) {
+    const int v = tid >> 6;
+    part[kPartW + tid] = ((sVec[0][v][nn] + sVec[1][v][nn]) + sVec[2][v][nn]) + sVec[3][v][nn];
+  }
+}
+
+// Sums of the G partial sums (in group order), one parameter per thread: a
+// workgroup of 1024 threads takes 16 rows x 64 columns of a tile (thread: row
+// t / 64, column t % 64), writes the gradient and, with ad.on, applies Adam and
+// refreshes the bf16 copies (the fragment-ordered ones through LDS, one 16-byte
+// store per thread).  Jobs 0..7: W1 tiles x 2 row groups; 8..135: W2, W3 tiles
+// x 4.  Row group 0 of a tile also takes its bias, w4 and b4 entries; job 0 also
+// sums the row pass's loss terms (in row-block order) into *loss.
+constexpr int kTrJobs = 8 + 32 * 4;
+__global__ void __launch_bounds__(1024) k_tr_adam(TrainBufs tb, int G, int n_rowblocks, float* __restrict__ grad,
+                                                  AdamArgs ad, float* __restrict__ loss) {
+  __shared__ uint16_t sW[16][64];
+  const int job = blockIdx.x, tid = threadIdx.x, nn = tid & 63, e = tid >> 6;
+  const int tile = job < 8 ? job / 2 : 4 + (job - 8) / 4;
+  const int rg = job < 8 ? job % 2 : (job - 8) % 4;
+  const TileInfo ti = tile_info(tile);
+  const float* pt = tb.part + (int64_t)tile * G * kPartStride;
+  auto total = [&](int x) {
+    // eight partial sums requested at a time, added in group order
     float s = 0.f;
-    for (int z = 0; z < splits; z++) s += parts[(int64_t)z * count + i];
-    out[i] = s;
+    for (int g0 = 0; g0 < G; g0 += 8) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) v[j] = g0 + j < G ? pt[(int64_t)(g0 + j) * kPartStride + x] : 0.f;
+#pragma unroll
+      for (int j = 0; j < 8; j++) s += v[j];
+    }
+    return s;
+  };
+  const int64_t offW = ti.layer == 1 ? kOffW1 : (ti.layer == 2 ? kOffW2 : kOffW3);
+  const int64_t offB = ti.layer == 1 ? kOffB1 : (ti.layer == 2 ? kOffB2 : kOffB3);
+  const int i = rg * 16 + e;
+  const int64_t gi = offW + (int64_t)(ti.i0 + i) * kHidden + ti.n0 + nn;
+  const float gv = total(i * 64 + nn);
+  grad[gi] = gv;
+  if (ad.on) {
+    sW[e][nn] = adam_one(ad, gi, gv);
+    __syncthreads();
+    const int ig = ti.i0 + rg * 16;   // first input feature (row of W) of the block
+    if (tid < 128) {
+      // W^T fragments: rows n, k = input feature; thread: column n0 + (tid % 64), 8 k
+      const int nl = tid & 63, c = tid >> 6, n = ti.n0 + nl;
+      uint32_t v[4];
+      for (int q = 0; q < 4; q++) v[q] = sW[8 * c + 2 * q][nl] | (uint32_t)sW[8 * c + 2 * q + 1][nl] << 16;
+      const int64_t base = ti.layer == 1 ? kFrW1T : (ti.layer == 2 ? kFrW2T : kFrW3T);
+      *(u32x4*)(ad.wfr + base + fr_index(n, ig + 8 * c, ti.F)) = u32x4{v[0], v[1], v[2], v[3]};
+    } else if (tid < 256 && ti.layer > 1) {
+      // W fragments: rows = input features ig .. ig + 15, k = n; thread: one row, 8 n
+      const int q8 = tid - 128, r = q8 & 15, c = q8 >> 4;   // c: which 8 of the 64 columns
+      uint32_t v[4];
+      for (int q = 0; q < 4; q++) v[q] = sW[r][8 * c + 2 * q] | (uint32_t)sW[r][8 * c + 2 * q + 1] << 16;
+      const int64_t base = ti.layer == 2 ? kFrW2 : kFrW3;
+      *(u32x4*)(ad.wfr + base + fr_index(ig + r, ti.n0 + 8 * c, kHidden)) = u32x4{v[0], v[1], v[2], v[3]};
+    }
+  }
+  if (rg == 0 && tid < 64) {
+    if (ti.bias) {
+      const int64_t gb = offB + ti.n0 + nn;
+      const float v = total(kPartW + nn);
+      grad[gb] = v;
+      if (ad.on) adam_one(ad, gb, v);
+    }
+    if (ti.out4) {
+      const int64_t g4 = kOffW4 + ti.n0 + nn;
+      const float v = total(kPartW + 64 + nn);
+      grad[g4] = v;
+      if (ad.on) adam_one(ad, g4, v);
+      if (ti.n0 == 0 && nn == 0) {
+        const float gb = total(kPartW + 128);
+        grad[kOffB4] = gb;
+        if (ad.on) adam_one(ad, kOffB4, gb);
+      }
+    }
+  }
+  if (job == 0 && tid < 64 && loss) {
+    float s = 0.f;
+    for (int r = tid; r < n_rowblocks; r += 64) s += tb.lossp[r];
+    for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+    if (tid == 0) *loss = s;
   }
 }
 
@@ -369,79 +766,6 @@ __global__ void k_targets(const int64_t* __restrict__ ms, int64_t n, float mu, f
     t[i] = ms[i] > 0 ? (logf((float)ms[i]) - mu) / sigma : 0.f;
 }
 
-// y[m] = sum_n h[m][n] * w[n] + b (bf16 inputs, fp32 sum); one thread per row
-__global__ void k_rowdot(const uint16_t* __restrict__ h, int64_t M, const uint16_t* __restrict__ w,
-                         const float* __restrict__ b, float* __restrict__ y) {
-  __shared__ float sw[kHidden];
-  for (int i = threadIdx.x; i < kHidden; i += blockDim.x) sw[i] = bf2f(w[i]);
-  __syncthreads();
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  const u32x4* row = (const u32x4*)(h + m * kHidden);
-  float s = 0.f;
-  for (int q = 0; q < kHidden / 8; q++) {
-    const u32x4 v = row[q];
-    for (int e = 0; e < 4; e++) {
-      s += __builtin_bit_cast(float, v[e] << 16) * sw[q * 8 + 2 * e];
-      s += __builtin_bit_cast(float, v[e] & 0xFFFF0000u) * sw[q * 8 + 2 * e + 1];
-    }
-  }
-  y[m] = s + b[0];
-}
-
-// output layer backward: dy = 2 (y - t) / n; dz3 = bf16(dy * w4 * [h3 > 0]);
-// loss sums (y - t)^2 / n into loss[0].  kOutRows rows per workgroup, whose loss
-// terms are summed first so that one atomic per workgroup reaches loss[0]
-// (atomics on one address serialize).
-constexpr int kOutRows = 16;
-__global__ void k_out_backward(const float* __restrict__ y, const float* __restrict__ t, int64_t n,
-                               const uint16_t* __restrict__ w4, const uint16_t* __restrict__ h3,
-                               float* __restrict__ dy, uint16_t* __restrict__ dz3, float* __restrict__ loss) {
-  const int64_t m0 = (int64_t)blockIdx.x * kOutRows;
-  float part = 0.f;
-  for (int r = 0; r < kOutRows && m0 + r < n; r++) {
-    const int64_t m = m0 + r;
-    const float d = y[m] - t[m];
-    const float g = 2.f * d / (float)n;
-    if (threadIdx.x == 0) {
-      dy[m] = g;
-      part += d * d / (float)n;
-    }
-    for (int j = threadIdx.x; j < kHidden; j += blockDim.x) {
-      const uint16_t hv = h3[m * kHidden + j];
-      dz3[m * kHidden + j] = hv != 0 ? f2bf(g * bf2f(w4[j])) : (uint16_t)0;
-    }
-  }
-  if (threadIdx.x == 0) atomicAdd(loss, part);
-}
-
-// column sums: out[j] = sum_m a[m][j] (bf16) * (wcol ? wcol[m] : 1), fp32; one
-// thread per (column, row slice), partial sums to parts[slice][j]
-__global__ void k_colsum(const uint16_t* __restrict__ a, int64_t M, int ncol, const float* __restrict__ wcol,
-                         int slices, float* __restrict__ parts) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = blockIdx.y;
-  if (j >= ncol) return;
-  const int64_t rows = (M + slices - 1) / slices;
-  const int64_t r0 = (int64_t)s * rows, r1 = r0 + rows < M ? r0 + rows : M;
-  float acc = 0.f;
-  for (int64_t m = r0; m < r1; m++) acc += bf2f(a[m * ncol + j]) * (wcol ? wcol[m] : 1.f);
-  parts[(int64_t)s * ncol + j] = acc;
-}
-
-__global__ void k_sum_f32(const float* __restrict__ v, int64_t n, float* __restrict__ out) {
-  __shared__ float sp[256];
-  float s = 0.f;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += v[i];
-  sp[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sp[threadIdx.x] += sp[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = sp[0];
-}
-
 // Adam (Kingma and Ba, 2015) on fp32 master weights; bf16 copies refreshed
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m1,
                        float* __restrict__ m2, int64_t n, float lr, float b1, float b2, float eps, float c1, float c2,
@@ -456,25 +780,6 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
     w[i] = wi;
     if (wbf) wbf[i] = f2bf(wi);
   }
-}
-
-// training batch: row r is row draw(seed, 7, step << 32 | r) mod n of (x, t)
-__global__ void k_sample_rows(const uint16_t* __restrict__ x, const float* __restrict__ t, int64_t n, uint64_t seed,
-                              uint64_t step, int batch, uint16_t* __restrict__ xb, float* __restrict__ tb) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= batch) return;
-  uint64_t z = seed + 0x9E3779B97F4A7C15ull * 8ull;   // purpose 7
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z = (z ^ (z >> 31)) + 0x9E3779B97F4A7C15ull * (((step << 32) | (uint64_t)r) + 1);
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z = z ^ (z >> 31);
-  const int64_t row = (int64_t)(z % (uint64_t)n);
-  const u32x4* src = (const u32x4*)(x + row * kInDim);
-  u32x4* dst = (u32x4*)(xb + (int64_t)r * kInDim);
-  for (int q = 0; q < kInDim / 8; q++) dst[q] = src[q];
-  tb[r] = t[row];
 }
 
 __global__ void k_zero_f32(float* p, int64_t n) {
@@ -493,28 +798,6 @@ int grid1(int64_t n, int bs = 256) {
 
 }  // namespace
 
-hipError_t gemm(bool ta, bool tb, int M, int N, int K, int splits, const uint16_t* A, int lda, const uint16_t* B,
-                int ldb, const float* bias, bool relu, const uint16_t* mask, int ldm, float* out_f32,
-                uint16_t* out_bf16, int ldc, hipStream_t s) {
-  if (N % TN || K % (TK * splits) || M <= 0) return hipErrorInvalidValue;
-  if (ta && M % 8) return hipErrorInvalidValue;
-  const dim3 grid((M + TM - 1) / TM, N / TN, splits), block(256);
-  const int kc = K / splits;
-  if (!ta && !tb)
-    hipLaunchKernelGGL((k_gemm<false, false>), grid, block, 0, s, M, N, kc, A, lda, B, ldb, bias, relu ? 1 : 0, mask, ldm,
-                       out_f32, out_bf16, ldc);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((k_gemm<false, true>), grid, block, 0, s, M, N, kc, A, lda, B, ldb, bias, relu ? 1 : 0, mask, ldm,
-                       out_f32, out_bf16, ldc);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((k_gemm<true, false>), grid, block, 0, s, M, N, kc, A, lda, B, ldb, bias, relu ? 1 : 0, mask, ldm,
-                       out_f32, out_bf16, ldc);
-  else
-    hipLaunchKernelGGL((k_gemm<true, true>), grid, block, 0, s, M, N, kc, A, lda, B, ldb, bias, relu ? 1 : 0, mask, ldm,
-                       out_f32, out_bf16, ldc);
-  return hipGetLastError();
-}
-
 hipError_t mlp_forward(const uint16_t* x, int64_t n, const uint16_t* wt, const float* p, const uint16_t* w4, float* y,
                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -522,13 +805,8 @@ hipError_t mlp_forward(const uint16_t* x, int64_t n, const uint16_t* wt, const f
   return hipGetLastError();
 }
 
-hipError_t transpose_w(const float* p, uint16_t* wt, hipStream_t s) {
-  hipLaunchKernelGGL(k_transpose_w, dim3(grid1(kTParams)), dim3(256), 0, s, p, wt);
-  return hipGetLastError();
-}
-
-hipError_t sum_splits(const float* parts, int splits, int64_t count, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_splits, dim3(grid1(count)), dim3(256), 0, s, parts, splits, count, out);
+hipError_t frag_w(const float* p, uint16_t* wfr, hipStream_t s) {
+  hipLaunchKernelGGL(k_frag_w, dim3(grid1(kFrParams)), dim3(256), 0, s, p, wfr);
   return hipGetLastError();
 }
 
@@ -550,28 +828,6 @@ hipError_t targets(const int64_t* ms, int64_t n, float mu, float sigma, float* t
   return hipGetLastError();
 }
 
-hipError_t rowdot(const uint16_t* h, int64_t M, const uint16_t* w, const float* b, float* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_rowdot, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, h, M, w, b, y);
-  return hipGetLastError();
-}
-
-hipError_t out_backward(const float* y, const float* t, int64_t n, const uint16_t* w4, const uint16_t* h3, float* dy,
-                        uint16_t* dz3, float* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_out_backward, dim3((unsigned)((n + kOutRows - 1) / kOutRows)), dim3(256), 0, s, y, t, n, w4, h3, dy,
-                     dz3, loss);
-  return hipGetLastError();
-}
-
-hipError_t colsum(const uint16_t* a, int64_t M, int ncol, const float* wcol, int slices, float* parts, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3((ncol + 255) / 256, slices), dim3(256), 0, s, a, M, ncol, wcol, slices, parts);
-  return hipGetLastError();
-}
-
-hipError_t sum_f32(const float* v, int64_t n, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_f32, dim3(1), dim3(256), 0, s, v, n, out);
-  return hipGetLastError();
-}
-
 hipError_t adam(float* w, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2, float eps,
                 int step, uint16_t* wbf, hipStream_t s) {
   const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
@@ -579,9 +835,22 @@ hipError_t adam(float* w, const float* g, float* m1, float* m2, int64_t n, float
   return hipGetLastError();
 }
 
-hipError_t sample_rows(const uint16_t* x, const float* t, int64_t n, uint64_t seed, uint64_t step, int batch,
-                       uint16_t* xb, float* tb, hipStream_t s) {
-  hipLaunchKernelGGL(k_sample_rows, dim3((batch + 255) / 256), dim3(256), 0, s, x, t, n, seed, step, batch, xb, tb);
+hipError_t train_rows(const uint16_t* x, const float* t, int64_t n, bool sample, uint64_t seed, uint64_t step,
+                      int batch, const uint16_t* wt, const uint16_t* wb, const float* p, const TrainBufs& tb,
+                      hipStream_t s) {
+  if (batch <= 0 || batch % 512 || n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_tr_rows<TRT, TNW>), dim3((unsigned)(batch / TRB)), dim3(TNW * 64), 0, s, x, t, n, sample ? 1 : 0, seed,
+                     step, batch, wt, wb, p, tb);
+  return hipGetLastError();
+}
+
+hipError_t train_wgrad(const TrainBufs& tb, int batch, float* g, const AdamArgs& ad, float* loss, hipStream_t s) {
+  if (batch <= 0 || batch % 512) return hipErrorInvalidValue;
+  const int G = batch / 512;
+  hipLaunchKernelGGL(k_tr_wgrad, dim3(kTrTiles * G), dim3(256), 0, s, tb, G);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tr_adam, dim3(kTrJobs), dim3(1024), 0, s, tb, G, batch / TRB, g, ad, loss);
   return hipGetLastError();
 }
 

@@ -53,92 +53,54 @@ struct hesp_mlp {
   float* m1 = nullptr;      // Adam first moment
   float* m2 = nullptr;      // Adam second moment
   uint16_t* wbf = nullptr;  // bf16 copy of the parameters
-  uint16_t* wbt = nullptr;  // transposed bf16 copies of W1, W2, W3 (fused forward)
+  uint16_t* wfr = nullptr;  // fragment-ordered bf16 copies of W1^T, W2^T, W3^T, W2, W3 (products)
   int step = 0;
-  int64_t rows = 0;         // activation capacity
-  uint16_t *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *dza = nullptr, *dzb = nullptr;
-  float *y = nullptr, *dy = nullptr, *parts = nullptr, *loss = nullptr;
-  int64_t parts_cap = 0;
-  uint16_t* xb = nullptr;   // sampled training batch
-  float* tb = nullptr;
-  int64_t sample_rows = 0;
+  // training step workspace for `rows` rows
+  int64_t rows = 0;
+  TrainBufs tb{};
   void release() {
-    for (void* q : {(void*)p, (void*)g, (void*)m1, (void*)m2, (void*)wbf, (void*)wbt, (void*)xb, (void*)tb}) hfree(q);
+    for (void* q : {(void*)p, (void*)g, (void*)m1, (void*)m2, (void*)wbf, (void*)wfr}) hfree(q);
     release_ws();
   }
   void release_ws() {
-    for (void* q : {(void*)h1, (void*)h2, (void*)h3, (void*)dza, (void*)dzb, (void*)y, (void*)dy, (void*)parts,
-                    (void*)loss})
+    for (void* q : {(void*)tb.xp, (void*)tb.h1p, (void*)tb.h2p, (void*)tb.h3p, (void*)tb.d1p, (void*)tb.d2p,
+                    (void*)tb.d3p, (void*)tb.dy, (void*)tb.part, (void*)tb.lossp})
       hfree(q);
-    h1 = h2 = h3 = dza = dzb = nullptr;
-    y = dy = parts = loss = nullptr;
-    rows = parts_cap = 0;
+    tb = TrainBufs{};
+    rows = 0;
   }
-  hipError_t ensure(int64_t n, int64_t parts_need) {
-    if (n > rows) {
-      for (void* q : {(void*)h1, (void*)h2, (void*)h3, (void*)dza, (void*)dzb, (void*)y, (void*)dy}) hfree(q);
-      h1 = h2 = h3 = dza = dzb = nullptr;
-      y = dy = nullptr;
-      rows = 0;
-      hipError_t e;
-      const size_t hb = (size_t)n * kHidden * sizeof(uint16_t);
-      if ((e = hipMalloc(&h1, hb)) || (e = hipMalloc(&h2, hb)) || (e = hipMalloc(&h3, hb)) ||
-          (e = hipMalloc(&dza, hb)) || (e = hipMalloc(&dzb, hb)) || (e = hipMalloc(&y, n * sizeof(float))) ||
-          (e = hipMalloc(&dy, n * sizeof(float))))
-        return e;
-      rows = n;
-    }
-    if (parts_need > parts_cap) {
-      hfree(parts);
-      parts = nullptr;
-      hipError_t e = hipMalloc(&parts, parts_need * sizeof(float));
-      if (e) return e;
-      parts_cap = parts_need;
-    }
-    if (!loss) {
-      hipError_t e = hipMalloc(&loss, sizeof(float));
-      if (e) return e;
-    }
+  hipError_t ensure(int64_t n) {
+    if (n <= rows) return hipSuccess;
+    release_ws();
+    hipError_t e;
+    const size_t hb = (size_t)n * kHidden * sizeof(uint16_t);
+    if ((e = hipMalloc(&tb.xp, (size_t)n * kInDim * sizeof(uint16_t))) || (e = hipMalloc(&tb.h1p, hb)) ||
+        (e = hipMalloc(&tb.h2p, hb)) || (e = hipMalloc(&tb.h3p, hb)) || (e = hipMalloc(&tb.d1p, hb)) ||
+        (e = hipMalloc(&tb.d2p, hb)) || (e = hipMalloc(&tb.d3p, hb)) ||
+        (e = hipMalloc(&tb.dy, (size_t)n * sizeof(float))) ||
+        (e = hipMalloc(&tb.part, (size_t)kTrainTiles * (n / 512) * kTrainPartStride * sizeof(float))) ||
+        (e = hipMalloc(&tb.lossp, (size_t)(n / 16) * sizeof(float))))
+      return e;
+    rows = n;
     return hipSuccess;
   }
+  AdamArgs adam_args(bool on, float lr) const {
+    AdamArgs a{};
+    a.on = on ? 1 : 0;
+    a.lr = lr;
+    a.b1 = 0.9f;
+    a.b2 = 0.999f;
+    a.eps = 1e-8f;
+    a.c1 = 1.f - powf(a.b1, (float)step);
+    a.c2 = 1.f - powf(a.b2, (float)step);
+    a.p = p;
+    a.m1 = m1;
+    a.m2 = m2;
+    a.wbf = wbf;
+    a.wfr = wfr;
+    return a;
+  }
 };
-
-namespace {
-
-// forward pass of n rows (n <= m->rows): h1, h2, h3 and y
-hipError_t forward_rows(hesp_mlp* m, const uint16_t* x, int64_t n, float* y, hipStream_t s) {
-  hipError_t e;
-  const uint16_t* w = m->wbf;
-  if ((e = gemm(false, false, (int)n, kHidden, kInDim, 1, x, kInDim, w + kOffW1, kHidden, m->p + kOffB1, true,
-                nullptr, 0, nullptr, m->h1, kHidden, s)))
-    return e;
-  if ((e = gemm(false, false, (int)n, kHidden, kHidden, 1, m->h1, kHidden, w + kOffW2, kHidden, m->p + kOffB2, true,
-                nullptr, 0, nullptr, m->h2, kHidden, s)))
-    return e;
-  if ((e = gemm(false, false, (int)n, kHidden, kHidden, 1, m->h2, kHidden, w + kOffW3, kHidden, m->p + kOffB3, true,
-                nullptr, 0, nullptr, m->h3, kHidden, s)))
-    return e;
-  return rowdot(m->h3, n, w + kOffW4, m->p + kOffB4, y, s);
-}
-
-// weight gradient dW[in][out] = act^T dz over n rows (split-K), written to g
-hipError_t weight_grad(hesp_mlp* m, const uint16_t* act, int in, const uint16_t* dz, int64_t n, float* g,
-                       hipStream_t s) {
-  const int splits = (int)(n / 512);
-  hipError_t e = gemm(true, false, in, kHidden, (int)n, splits, act, in, dz, kHidden, nullptr, false, nullptr, 0,
-                      m->parts, nullptr, kHidden, s);
-  if (e) return e;
-  return sum_splits(m->parts, splits, (int64_t)in * kHidden, g, s);
-}
-
-hipError_t bias_grad(hesp_mlp* m, const uint16_t* a, int64_t n, const float* wcol, float* g, hipStream_t s) {
-  const int slices = 64;
-  hipError_t e = colsum(a, n, kHidden, wcol, slices, m->parts, s);
-  if (e) return e;
-  return sum_splits(m->parts, slices, kHidden, g, s);
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -150,7 +112,7 @@ int hesp_mlp_create(hesp_mlp** out, uint64_t seed) {
   hipError_t e;
   if ((e = hipMalloc(&m->p, pb)) || (e = hipMalloc(&m->g, pb)) || (e = hipMalloc(&m->m1, pb)) ||
       (e = hipMalloc(&m->m2, pb)) || (e = hipMalloc(&m->wbf, kParams * sizeof(uint16_t))) ||
-      (e = hipMalloc(&m->wbt, kTParams * sizeof(uint16_t)))) {
+      (e = hipMalloc(&m->wfr, kFrParams * sizeof(uint16_t)))) {
     m->release();
     delete m;
     return fail(HESP_ENOMEM, "hesp_mlp_create: %s", hipGetErrorString(e));
@@ -196,7 +158,7 @@ int hesp_mlp_set_params(hesp_mlp* m, const float* host, int64_t n) {
   HIP_TRY(hipMemset(m->m2, 0, kParams * sizeof(float)));
   HIP_TRY(hipMemset(m->g, 0, kParams * sizeof(float)));
   HIP_TRY(to_bf16(m->p, kParams, m->wbf, nullptr));
-  HIP_TRY(transpose_w(m->p, m->wbt, nullptr));
+  HIP_TRY(frag_w(m->p, m->wfr, nullptr));
   HIP_TRY(hipDeviceSynchronize());
   m->step = 0;
   return HESP_OK;
@@ -239,7 +201,7 @@ int hesp_mlp_forward(hesp_mlp* m, const uint16_t* d_x, int64_t n, float* d_y, vo
   // one fused launch (activations never leave LDS); at most 2^31 rows per launch
   const int64_t chunk = (int64_t)1 << 31;
   for (int64_t r = 0; r < n; r += chunk)
-    HIP_TRY(mlp_forward(d_x + r * kInDim, std::min(chunk, n - r), m->wbt, m->p, m->wbf + kOffW4, d_y + r,
+    HIP_TRY(mlp_forward(d_x + r * kInDim, std::min(chunk, n - r), m->wfr, m->p, m->wbf + kOffW4, d_y + r,
                         (hipStream_t)stream));
   return HESP_OK;
 }
@@ -248,33 +210,9 @@ int hesp_mlp_grad(hesp_mlp* m, const uint16_t* d_x, const float* d_t, int32_t ba
   if (!m || !d_x || !d_t || batch <= 0 || batch % 512)
     return fail(HESP_EINVAL, "hesp_mlp_grad: batch must be a positive multiple of 512");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n = batch;
-  const int splits = (int)(n / 512);
-  HIP_TRY(m->ensure(n, (int64_t)splits * kHidden * kHidden > 64 * kHidden ? (int64_t)splits * kHidden * kHidden
-                                                                          : 64 * kHidden));
-  // the loss accumulates straight into the caller's slot when one is given
-  float* loss = d_loss ? d_loss : m->loss;
-  HIP_TRY(zero_f32(loss, 1, s));
-  HIP_TRY(forward_rows(m, d_x, n, m->y, s));
-  float* g = m->g;
-  const uint16_t* w = m->wbf;
-  // output layer
-  HIP_TRY(out_backward(m->y, d_t, n, w + kOffW4, m->h3, m->dy, m->dza, loss, s));
-  HIP_TRY(bias_grad(m, m->h3, n, m->dy, g + kOffW4, s));
-  HIP_TRY(sum_f32(m->dy, n, g + kOffB4, s));
-  // layer 3: dz3 in dza
-  HIP_TRY(weight_grad(m, m->h2, kHidden, m->dza, n, g + kOffW3, s));
-  HIP_TRY(bias_grad(m, m->dza, n, nullptr, g + kOffB3, s));
-  HIP_TRY(gemm(false, true, (int)n, kHidden, kHidden, 1, m->dza, kHidden, w + kOffW3, kHidden, nullptr, false, m->h2,
-               kHidden, nullptr, m->dzb, kHidden, s));
-  // layer 2: dz2 in dzb
-  HIP_TRY(weight_grad(m, m->h1, kHidden, m->dzb, n, g + kOffW2, s));
-  HIP_TRY(bias_grad(m, m->dzb, n, nullptr, g + kOffB2, s));
-  HIP_TRY(gemm(false, true, (int)n, kHidden, kHidden, 1, m->dzb, kHidden, w + kOffW2, kHidden, nullptr, false, m->h1,
-               kHidden, nullptr, m->dza, kHidden, s));
-  // layer 1: dz1 in dza
-  HIP_TRY(weight_grad(m, d_x, kInDim, m->dza, n, g + kOffW1, s));
-  HIP_TRY(bias_grad(m, m->dza, n, nullptr, g + kOffB1, s));
+  HIP_TRY(m->ensure(batch));
+  HIP_TRY(train_rows(d_x, d_t, batch, false, 0, 0, batch, m->wfr, m->wbf, m->p, m->tb, s));
+  HIP_TRY(train_wgrad(m->tb, batch, m->g, m->adam_args(false, 0.f), d_loss, s));
   return HESP_OK;
 }
 
@@ -282,7 +220,7 @@ int hesp_mlp_adam(hesp_mlp* m, float lr, void* stream) {
   if (!m || !(lr > 0.f)) return fail(HESP_EINVAL, "hesp_mlp_adam: bad argument");
   m->step++;
   HIP_TRY(adam(m->p, m->g, m->m1, m->m2, kParams, lr, 0.9f, 0.999f, 1e-8f, m->step, m->wbf, (hipStream_t)stream));
-  HIP_TRY(transpose_w(m->p, m->wbt, (hipStream_t)stream));
+  HIP_TRY(frag_w(m->p, m->wfr, (hipStream_t)stream));
   return HESP_OK;
 }
 
@@ -291,23 +229,13 @@ int hesp_mlp_train(hesp_mlp* m, const uint16_t* d_x, const float* d_t, int64_t n
   if (!m || !d_x || !d_t || batch <= 0 || batch % 512 || n < 1 || steps < 0 || !(lr > 0.f))
     return fail(HESP_EINVAL, "hesp_mlp_train: bad argument (batch a positive multiple of 512, n >= 1)");
   hipStream_t s = (hipStream_t)stream;
-  if (m->sample_rows < batch) {
-    hfree(m->xb);
-    hfree(m->tb);
-    m->xb = nullptr;
-    m->tb = nullptr;
-    m->sample_rows = 0;
-    HIP_TRY(hipMalloc(&m->xb, (size_t)batch * kInDim * sizeof(uint16_t)));
-    HIP_TRY(hipMalloc(&m->tb, (size_t)batch * sizeof(float)));
-    m->sample_rows = batch;
-  }
+  HIP_TRY(m->ensure(batch));
   for (int32_t i = 0; i < steps; i++) {
-    // rows drawn with replacement; the counter is the network's Adam step number
-    HIP_TRY(sample_rows(d_x, d_t, n, seed, (uint64_t)m->step, batch, m->xb, m->tb, s));
-    int rc = hesp_mlp_grad(m, m->xb, m->tb, batch, d_loss ? d_loss + i : nullptr, stream);
-    if (rc) return rc;
-    rc = hesp_mlp_adam(m, lr, stream);
-    if (rc) return rc;
+    // rows drawn with replacement (the counter is the network's Adam step
+    // number); then weight gradients, and their sums with Adam fused in
+    HIP_TRY(train_rows(d_x, d_t, n, true, seed, (uint64_t)m->step, batch, m->wfr, m->wbf, m->p, m->tb, s));
+    m->step++;
+    HIP_TRY(train_wgrad(m->tb, batch, m->g, m->adam_args(true, lr), d_loss ? d_loss + i : nullptr, s));
   }
   return HESP_OK;
 }
