@@ -578,6 +578,8 @@ def main():
     ap.add_argument("--workload", default="chol16x16_b1024_d2")
     ap.add_argument("--n-cand", type=int, default=0)
     ap.add_argument("--group", type=int, default=0, help="lanes per candidate (0 = autotuned)")
+    ap.add_argument("--fuse", action="store_true",
+                    help="fused pipeline: the 64-lane event loop prepares each candidate itself (one launch per batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--train-platforms", type=int, default=64)
@@ -647,7 +649,7 @@ def main():
     ntk = torch.empty(n, dtype=torch.int32, device=dev)
     best = torch.empty(2, dtype=torch.int64, device=dev)
 
-    plan = H.Plan(group=args.group)
+    plan = H.Plan(group=args.group, fuse=args.fuse)
     plan.timing(True)
     sim_ms = []
 

@@ -198,6 +198,11 @@ typedef struct {
   int32_t prep_edges;          /* critical-time pass: dependences inside one run of 64 consecutive tasks kept
                                   in LDS, 1..1024 (0 = 1024); a run with more re-reads its successor lists
                                   on every sweep (same results, slower) */
+  int32_t fuse;                /* 1: fused pipeline for depth batches (64 lanes per candidate; group must be
+                                  0 or 64): every wave of the persistent event loop prepares the candidates it
+                                  takes into its own workspace slot, so a batch of any size and unevenness is
+                                  one launch holding (resident waves x largest candidate) bytes; slower than
+                                  the default separate preparation launch per memory chunk */
 } hesp_plan_opts;
 /* A plan with max_tasks, max_edges and group all set is a fixed-capacity plan:
  * its workspace follows from the capacities and the batch shape, so after one
@@ -205,8 +210,9 @@ typedef struct {
  * no host synchronisation, no allocation and no autotuning -- only kernel
  * launches on `stream`, which can be captured in a HIP graph and replayed (the
  * graph keeps the batch and output pointers of the captured call).  A captured
- * call runs on `stream` alone and must fit one chunk (else HESP_EUNSUPPORTED).
- * Candidates above the capacities get HESP_ECAPACITY. */
+ * call runs on `stream` alone and must fit one chunk (else HESP_EUNSUPPORTED),
+ * unless the plan is fused: a fused fixed-capacity plan captures any batch as
+ * one simulation launch.  Candidates above the capacities get HESP_ECAPACITY. */
 int hesp_plan_create(hesp_plan **plan, const hesp_plan_opts *opts);
 int hesp_plan_destroy(hesp_plan *plan);
 /* device bytes currently held by the plan */

@@ -103,16 +103,21 @@ struct hesp_plan {
   // fixed-capacity plans: chunk size chosen for (candidates, validity words, top-level tasks)
   std::tuple<int64_t, int64_t, int64_t> fixed_key{-1, -1, -1};
   int32_t fixed_chunk = 0;
+  // fused pipeline: one slot per resident wave of the 64-lane event loop
+  DevBuf arena;
+  int32_t resident64 = 0;     // waves of the fused event loop resident at once (seven per SIMD)
+  std::tuple<int64_t, int64_t, int64_t> fused_key{-1, -1, -1};
+  int32_t fused_waves = 0;
   // optional kernel timing of the last call: events around each launch
   bool timing = false;
   std::vector<hipEvent_t> ev;   // per chunk: prepare start and end, simulation start and end
   size_t ev_used = 0;
   int64_t held() const {
     return cnt_tasks.bytes + cnt_edges.bytes + off_t.bytes + off_e.bytes + off_v.bytes + off_top.bytes +
-           bounds.bytes + tree_lw.bytes + ws[0].bytes() + ws[1].bytes();
+           bounds.bytes + tree_lw.bytes + arena.bytes + ws[0].bytes() + ws[1].bytes();
   }
   void release() {
-    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds, &tree_lw}) b->release();
+    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds, &tree_lw, &arena}) b->release();
     for (WorkSet& w : ws)
       for (DevBuf* d : w.all()) d->release();
   }
@@ -310,7 +315,7 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
   if (opts) p->opts = *opts;
   if (p->opts.slots < 0 || p->opts.max_tasks < 0 || p->opts.max_edges < 0 || p->opts.chunks < 0 ||
       (p->opts.group != 0 && p->opts.group != 16 && p->opts.group != 32 && p->opts.group != 64) ||
-      p->opts.prep_edges < 0 || p->opts.prep_edges > 1024) {
+      p->opts.prep_edges < 0 || p->opts.prep_edges > 1024 || p->opts.fuse < 0 || p->opts.fuse > 1 || (p->opts.fuse && p->opts.group != 0 && p->opts.group != 64)) {
     delete p;
     return fail(HESP_EINVAL, "hesp_plan_create: negative option");
   }
@@ -322,6 +327,7 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
     return fail(HESP_EHIP, "hesp_plan_create: %s", hipGetErrorString(e));
   }
   p->slots = p->opts.slots ? p->opts.slots : 32 * cus;
+  p->resident64 = std::min(p->slots, 28 * cus);
   p->chunk = 1 << 22;   // bounded by device memory below
   e = hipMalloc(&p->counter, sizeof(uint32_t));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->s_prep, hipStreamNonBlocking);
@@ -444,31 +450,17 @@ int hesp_internal_batch_setup(const hesp_platform* pf, hesp_policy policy, const
   return HESP_OK;
 }
 
-// depth batches (batch) or split-tree batches (tree)
-static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,
-                        const hesp_tree_batch* tree, const hesp_outputs* out, void* stream) {
-  if (!plan) return fail(HESP_EINVAL, "hesp_simulate_batch: null plan");
-  SimTables tb;
-  BatchView bv;
-  if (int r = hesp_internal_batch_setup(pf, policy, batch, tree, out, tb, bv)) return r;
-  const bool is_tree = tree != nullptr;
-  const int n = bv.n_cand;
-  if (n == 0) return ok();
-  hipStream_t s = (hipStream_t)stream;
-
-  // exact sizes of every candidate and their prefix sums
-  HIP_TRY(plan->cnt_tasks.ensure(4 * (int64_t)n));
-  HIP_TRY(plan->cnt_edges.ensure(8 * (int64_t)n));
+// The pipeline with a separate preparation launch, on the first n candidates
+// (their counts are in the plan): exact per-candidate layout, memory chunks,
+// per chunk the preparation and the event loop with `group` lanes per candidate.
+static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool is_tree, const hesp_platform* pf,
+                       const OutView& ov, hipStream_t s, int32_t n) {
+  bv.n_cand = n;
   for (DevBuf* b : {&plan->off_t, &plan->off_e, &plan->off_v, &plan->off_top}) HIP_TRY(b->ensure(8 * ((int64_t)n + 1)));
-  if (is_tree) {
-    HIP_TRY(plan->tree_lw.ensure(4 * (int64_t)n * ((int64_t)tri2(bv.nt) << (2 * bv.dmax))));
-    HIP_TRY(launch_count_tree(bv, plan->tree_lw.as<uint32_t>(), plan->cnt_tasks.as<int32_t>(),
-                              plan->cnt_edges.as<int64_t>(), s));
-  } else {
-    HIP_TRY(launch_count(bv, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(), s));
-  }
+  // the fused pipeline's arena is not given back to this path
+  const int64_t held = plan->held() - plan->arena.bytes;
   auto prepare = [&](const ChunkView& cv, hipStream_t st) {
-    return is_tree ? launch_prepare_tree(tb, bv, cv, ov_of(out), st) : launch_prepare(tb, bv, cv, ov_of(out), st);
+    return is_tree ? launch_prepare_tree(tb, bv, cv, ov, st) : launch_prepare(tb, bv, cv, ov, st);
   };
   HIP_TRY(launch_layout(bv, pf->n_mem, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(),
                         plan->opts.max_tasks, plan->opts.max_edges, plan->off_t.as<int64_t>(),
@@ -492,7 +484,7 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
     if (plan->fixed_key != key) {
       size_t free_b = 0, total_b = 0;
       HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-      const int64_t budget = (int64_t)(free_b + (size_t)plan->held()) / 2;
+      const int64_t budget = (int64_t)(free_b + (size_t)held) / 2;
       const int64_t want = plan->opts.chunks > 1 ? (n + plan->opts.chunks - 1) / plan->opts.chunks : n;
       plan->fixed_chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(want, budget / (2 * per)));
       plan->fixed_key = key;
@@ -506,7 +498,7 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   }
   size_t free_b = 0, total_b = 0;
   if (!fixed) HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-  const int64_t budget = (int64_t)(free_b + (size_t)plan->held()) / 2;
+  const int64_t budget = (int64_t)(free_b + (size_t)held) / 2;
   for (; !fixed;) {
     n_chunks = (n + chunk - 1) / chunk;
     HIP_TRY(plan->bounds.ensure(4 * 8 * ((int64_t)n_chunks + 1)));
@@ -548,8 +540,6 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
     HIP_TRY(w.order.ensure(4 * (int64_t)chunk));
   }
 
-  OutView ov{out->d_makespan, out->d_status, out->d_n_tasks, out->d_sched_off, out->d_proc, out->d_start,
-             out->d_finish};
   auto chunk_view = [&](int32_t c0, int32_t nc, int set) {
     WorkSet& w = plan->ws[set];
     ChunkView cv{};
@@ -577,6 +567,7 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
     cv.cnt_edges = plan->cnt_edges.as<int64_t>();
     return cv;
   };
+
 
   // lanes per candidate: forced by the plan, or timed once per batch shape on a
   // sub-batch of the first chunk (outputs of that sub-batch are rewritten below)
@@ -669,6 +660,122 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   }
   if (fork) HIP_TRY(hipStreamWaitEvent(s, se[2 * n_chunks], 0));
   return ok();
+}
+
+// The fused pipeline on the first n candidates (depth batches, 64 lanes per
+// candidate): one launch of the persistent event loop, each wave preparing the
+// candidates it takes into its own slot of the plan's arena.  The slot holds the
+// largest candidate of the batch (read back: one synchronisation of `s`), or, in
+// a fixed-capacity plan, the largest allowed by the capacities (no read-back, no
+// allocation after the first call of a shape: capturable).  Waves: the ones that
+// are resident at once, fewer if the arena would not fit half the free memory.
+static int run_fused(hesp_plan* plan, const SimTables& tb, BatchView bv, const OutView& ov, hipStream_t s,
+                     int32_t n) {
+  bv.n_cand = n;
+  const bool fixed = plan->opts.max_tasks > 0 && plan->opts.max_edges > 0 && plan->opts.group > 0;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cap));
+  if (cap != hipStreamCaptureStatusNone && !fixed)
+    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: a captured call needs a fixed-capacity plan");
+  const int64_t V = ((int64_t)tri2(bv.nt) << (2 * bv.dmax)) * tb.n_mem, TP = tet3(bv.nt) + 1;
+  int64_t slot = 0;
+  int32_t waves = 0;
+  if (fixed) {
+    slot = region_bytes(plan->opts.max_tasks, plan->opts.max_edges, V, TP);
+    const auto key = std::make_tuple((int64_t)n, slot, (int64_t)-2);
+    if (plan->fused_key == key) waves = plan->fused_waves;
+  } else {
+    HIP_TRY(plan->bounds.ensure(64));
+    HIP_TRY(launch_max_region(bv, tb.n_mem, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(),
+                              plan->bounds.as<int64_t>(), s));
+    int64_t mx = 0;
+    HIP_TRY(hipMemcpyAsync(&mx, plan->bounds.p, sizeof mx, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    slot = mx;
+  }
+  slot = std::max<int64_t>(256, (slot + 255) & ~(int64_t)255);
+  if (waves == 0) {
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const int64_t budget = (int64_t)(free_b + (size_t)plan->arena.bytes) / 2;
+    waves = std::min<int32_t>(n, plan->resident64);
+    while (waves > 1 && (int64_t)waves * slot > budget) waves = (waves + 1) / 2;
+    if ((int64_t)waves * slot > budget)
+      return fail(HESP_ENOMEM, "hesp_simulate_batch: one candidate needs %lld bytes", (long long)slot);
+    if (fixed) {
+      plan->fused_key = std::make_tuple((int64_t)n, slot, (int64_t)-2);
+      plan->fused_waves = waves;
+    }
+  }
+  HIP_TRY(plan->arena.ensure((int64_t)waves * slot));
+  WorkSet& w = plan->ws[0];
+  HIP_TRY(w.order_keys.ensure(8 * srch::sort_len(n)));
+  HIP_TRY(w.order.ensure(4 * (int64_t)n));
+  // largest candidates first, so that the persistent launch does not end on a long one
+  HIP_TRY(srch::size_order(plan->cnt_tasks.as<int32_t>(), 0, n, w.order_keys.as<uint64_t>(), w.order.as<uint32_t>(), s));
+  ChunkView cv{};
+  cv.c0 = 0;
+  cv.nc = n;
+  cv.cap_tasks = plan->opts.max_tasks;
+  cv.cap_edges = plan->opts.max_edges;
+  cv.prep_in = plan->opts.prep_edges;
+  cv.cnt_tasks = plan->cnt_tasks.as<int32_t>();
+  cv.cnt_edges = plan->cnt_edges.as<int64_t>();
+  cv.order = w.order.as<uint32_t>();
+  cv.region = plan->arena.as<uint8_t>();
+  cv.slot_bytes = slot;
+  plan->ev_used = 0;
+  if (plan->timing)
+    while (plan->ev.size() < 4) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      plan->ev.push_back(e);
+    }
+  if (plan->timing) {
+    HIP_TRY(hipEventRecord(plan->ev[0], s));   // no separate preparation: an empty interval
+    HIP_TRY(hipEventRecord(plan->ev[1], s));
+    HIP_TRY(hipEventRecord(plan->ev[2], s));
+  }
+  HIP_TRY(launch_sim(tb, bv, cv, ov, waves, 64, plan->counter, s));
+  if (plan->timing) {
+    HIP_TRY(hipEventRecord(plan->ev[3], s));
+    plan->ev_used = 4;
+  }
+  return ok();
+}
+
+// depth batches (batch) or split-tree batches (tree)
+static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,
+                        const hesp_tree_batch* tree, const hesp_outputs* out, void* stream) {
+  if (!plan) return fail(HESP_EINVAL, "hesp_simulate_batch: null plan");
+  SimTables tb;
+  BatchView bv;
+  if (int r = hesp_internal_batch_setup(pf, policy, batch, tree, out, tb, bv)) return r;
+  const bool is_tree = tree != nullptr;
+  const int n = bv.n_cand;
+  if (n == 0) return ok();
+  hipStream_t s = (hipStream_t)stream;
+  const OutView ov = ov_of(out);
+
+  // exact sizes of every candidate
+  HIP_TRY(plan->cnt_tasks.ensure(4 * (int64_t)n));
+  HIP_TRY(plan->cnt_edges.ensure(8 * (int64_t)n));
+  if (is_tree) {
+    HIP_TRY(plan->tree_lw.ensure(4 * (int64_t)n * ((int64_t)tri2(bv.nt) << (2 * bv.dmax))));
+    HIP_TRY(launch_count_tree(bv, plan->tree_lw.as<uint32_t>(), plan->cnt_tasks.as<int32_t>(),
+                              plan->cnt_edges.as<int64_t>(), s));
+  } else {
+    HIP_TRY(launch_count(bv, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(), s));
+  }
+
+  // the fused pipeline on request (depth batches, 64 lanes per candidate), else
+  // separate preparation and simulation launches per memory chunk
+  if (plan->opts.fuse) {
+    if (is_tree) return fail(HESP_EUNSUPPORTED, "hesp_simulate_tree_batch: the fused pipeline takes depth batches");
+    if (pf->n_procs > 64) return fail(HESP_EINVAL, "hesp_simulate_batch: more than 64 processors");
+    return run_fused(plan, tb, bv, ov, s, n);
+  }
+  return run_unfused(plan, tb, bv, is_tree, pf, ov, s, n);
 }
 
 int hesp_simulate_batch(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,

@@ -70,6 +70,11 @@ struct ChunkView {
   const int64_t* byte_off;
   uint8_t* region;
   int64_t region_cap;
+  // fused simulation (slot_bytes > 0): the persistent kernel prepares each
+  // candidate itself into slot blockIdx.x of slot_bytes bytes at region (sizes
+  // from cnt_tasks / cnt_edges); candidates whose block is larger get
+  // HESP_ECAPACITY
+  int64_t slot_bytes;
 };
 
 // bytes of one candidate's block in region mode: T tasks, E edges, V validity
@@ -108,6 +113,9 @@ hipError_t launch_prepare_tree(const SimTables& t, const BatchView& b, const Chu
 hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o, int32_t slots,
                       int32_t group, uint32_t* counter, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, hipStream_t s);
+// out[0] (int64, device) = the largest region_bytes of a candidate of the batch
+hipError_t launch_max_region(const BatchView& b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
+                             int64_t* out, hipStream_t s);
 hipError_t launch_gen_uniform(uint64_t seed, int64_t first, int32_t n_cand, int32_t nt, int32_t dmax,
                               uint32_t thr, uint8_t* depth, hipStream_t s);
 hipError_t launch_gen_tree(uint64_t seed, int64_t first, int32_t n_cand, int64_t n_flags, uint32_t thr,

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "hesp_core.h"
 #include "hesp_device.h"
 #include "hesp_internal.h"
@@ -128,32 +130,39 @@ struct CandPtrs {
   int64_t* vf;         // [finest block][memory space] valid-from times
 };
 
+// a candidate's arrays one after the other in one block of region_bytes(T, E, V, TP)
+// bytes, 8-byte elements first
+__device__ __forceinline__ CandPtrs carve(uint8_t* r, int64_t T, int64_t E, int64_t V) {
+  CandPtrs p;
+  p.toff = 0;
+  p.rec = (int64_t*)r;        r += 16 * (T + 1);
+  p.fifo = (int64_t*)r;       r += 24 * T;
+  p.sortbuf = (int64_t*)r;    r += 32 * T;
+  p.vf = (int64_t*)r;         r += 8 * V;
+  p.desc = (uint32_t*)r;      r += 4 * T;
+  p.indeg = (uint32_t*)r;     r += 4 * T;
+  p.cur = (uint32_t*)r;       r += 4 * T;
+  p.ready = (uint32_t*)r;     r += 4 * T;
+  p.succ = (uint32_t*)r;      r += 4 * E;
+  p.top_first = (uint32_t*)r;
+  return p;
+}
+
 __device__ __forceinline__ CandPtrs cand_ptrs(const ChunkView& v, int c) {
   CandPtrs p;
   const int64_t t = v.task_off[c] - v.task_off[v.c0];
   const int64_t e = v.edge_off[c] - v.edge_off[v.c0];
   const int64_t f = v.vf_off[c] - v.vf_off[v.c0];
   const int64_t tp = v.top_off[c] - v.top_off[v.c0];
-  p.toff = t;
   if (v.region) {
-    // region mode: the candidate's arrays one after the other in its own block,
-    // 8-byte elements first
+    // region mode: the candidate's own block at its byte offset
     const int64_t T = v.task_off[c + 1] - v.task_off[c], E = v.edge_off[c + 1] - v.edge_off[c];
-    const int64_t V = v.vf_off[c + 1] - v.vf_off[c], TP = v.top_off[c + 1] - v.top_off[c];
-    uint8_t* r = v.region + (v.byte_off[c] - v.byte_off[v.c0]);
-    p.rec = (int64_t*)r;        r += 16 * (T + 1);
-    p.fifo = (int64_t*)r;       r += 24 * T;
-    p.sortbuf = (int64_t*)r;    r += 32 * T;
-    p.vf = (int64_t*)r;         r += 8 * V;
-    p.desc = (uint32_t*)r;      r += 4 * T;
-    p.indeg = (uint32_t*)r;     r += 4 * T;
-    p.cur = (uint32_t*)r;       r += 4 * T;
-    p.ready = (uint32_t*)r;     r += 4 * T;
-    p.succ = (uint32_t*)r;      r += 4 * E;
-    p.top_first = (uint32_t*)r;
-    (void)TP;
+    const int64_t V = v.vf_off[c + 1] - v.vf_off[c];
+    p = carve(v.region + (v.byte_off[c] - v.byte_off[v.c0]), T, E, V);
+    p.toff = t;
     return p;
   }
+  p.toff = t;
   p.top_first = v.top_first + tp;
   p.desc = v.desc + t;
   p.indeg = v.indeg + t;
@@ -215,11 +224,12 @@ __device__ __forceinline__ int prep_owner(const PrepLds& s, uint32_t e) {
 
 // critical times, the closing record, initial validity and the first ready
 // list; cur[f] = one past the last edge of f, successor lists filled
-__device__ __forceinline__ void prep_finish(const ChunkView& cv, const OutView& out, int c, int nt, int dmax, int M,
-                                            const CandPtrs& sp, int64_t n_fine, int64_t n_edges,
-                                            const int64_t (*s_W)[kLevels], PrepLds& s) {
+// returns the number of tasks without predecessors (the first ready list)
+__device__ __forceinline__ int prep_finish(int prep_in, const OutView& out, int c, int nt, int dmax, int M,
+                                           const CandPtrs& sp, int64_t n_fine, int64_t n_edges,
+                                           const int64_t (*s_W)[kLevels], PrepLds& s) {
   const int l = lane();
-  const int in_cap = cv.prep_in >= 1 && cv.prep_in <= kPrepIn ? cv.prep_in : kPrepIn;
+  const int in_cap = prep_in >= 1 && prep_in <= kPrepIn ? prep_in : kPrepIn;
   // R: critical times, last chunk of 64 tasks first.  The chunk's successor
   // lists form one contiguous edge range, read by all lanes together, four
   // edges per lane per round trip: a successor beyond the chunk is final, and its
@@ -322,34 +332,30 @@ __device__ __forceinline__ void prep_finish(const ChunkView& cv, const OutView& 
     n_src += __popcll(m);
   }
   if (l == 0) {
-    cv.nsrc[c - cv.c0] = (int32_t)n_src;
     out.status[c] = kOK;
     if (out.n_tasks) out.n_tasks[c] = (int32_t)n_fine;
   }
+  return (int)n_src;
 }
 
 // ---------------------------------------------------------------- preparation
 
-// eight waves per SIMD (64 VGPRs): the passes wait on memory most of the time
-__global__ void __launch_bounds__(kWave, 8) k_prepare(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
-  __shared__ int64_t s_W[4][kLevels];
-  __shared__ PrepLds s_p;
+// Preparation of depth candidate c by one whole wavefront into the arrays sp
+// (T tasks and E edges, the exact counts): status checks, A -- first fine task
+// of every top-level task, B -- descriptors, predecessor counts, successor
+// counts, C -- successor offsets, D -- successor lists, then critical times,
+// initial validity and the first ready list.  cap: the candidate does not fit
+// its storage (HESP_ECAPACITY).  Returns the status (written to the outputs,
+// with makespan -1 when not OK); n_src gets the number of first ready tasks.
+__device__ __forceinline__ int prepare_cand(const SimTables& tb, const BatchView& bv, const OutView& out, int c, const CandPtrs& sp,
+                            int64_t n_tasks, int64_t n_edges, bool cap, int prep_in,
+                            const int64_t (*s_W)[kLevels], PrepLds& s_p, int& n_src) {
   const int l = lane();
-  for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
-  __syncthreads();
-
-  const int c = cv.c0 + (int)blockIdx.x;
-  if (c >= bv.n_cand) return;
   const Cand cd = load_cand(bv, c);
   const int nt = cd.nt, dmax = cd.dmax, M = tb.n_mem;
   int status = kOK;
   if (nt < 1 || dmax < 0 || dmax > kMaxLevel || dmax > tb.max_level || (nt << dmax) > kMaxFine) status = kEINVAL;
-  if (status == kOK && ((cv.cap_tasks > 0 && cv.cnt_tasks[c] > cv.cap_tasks) ||
-                        (cv.cap_edges > 0 && cv.cnt_edges[c] > cv.cap_edges) || region_overflow(cv, c)))
-    status = kECAP;
-  const int64_t n_tasks = cv.task_off[c + 1] - cv.task_off[c];
-  const int64_t n_edges = cv.edge_off[c + 1] - cv.edge_off[c];
-  const CandPtrs sp = cand_ptrs(cv, c);
+  if (status == kOK && cap) status = kECAP;
 
   // pass A: first fine task of every top-level task; depths above dmax
   int64_t carry = 0;
@@ -375,7 +381,7 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare(SimTables tb, BatchView bv
       out.status[c] = status;
       if (out.n_tasks) out.n_tasks[c] = 0;
     }
-    return;
+    return status;
   }
   const int64_t n_fine = n_tasks;
   for (int64_t f = l; f < n_fine; f += kWave) sp.cur[f] = 0u;
@@ -419,7 +425,28 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare(SimTables tb, BatchView bv
   });
   wave_order();
 
-  prep_finish(cv, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_p);
+  n_src = prep_finish(prep_in, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_p);
+  return kOK;
+}
+
+// eight waves per SIMD (64 VGPRs): the passes wait on memory most of the time
+__global__ void __launch_bounds__(kWave, 8) k_prepare(SimTables tb, BatchView bv, ChunkView cv, OutView out) {
+  __shared__ int64_t s_W[4][kLevels];
+  __shared__ PrepLds s_p;
+  const int l = lane();
+  for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
+  __syncthreads();
+
+  const int c = cv.c0 + (int)blockIdx.x;
+  if (c >= bv.n_cand) return;
+  const bool cap = (cv.cap_tasks > 0 && cv.cnt_tasks[c] > cv.cap_tasks) ||
+                   (cv.cap_edges > 0 && cv.cnt_edges[c] > cv.cap_edges) || region_overflow(cv, c);
+  const int64_t n_tasks = cv.task_off[c + 1] - cv.task_off[c];
+  const int64_t n_edges = cv.edge_off[c + 1] - cv.edge_off[c];
+  int n_src = 0;
+  if (prepare_cand(tb, bv, out, c, cand_ptrs(cv, c), n_tasks, n_edges, cap, cv.prep_in, s_W, s_p, n_src) == kOK &&
+      l == 0)
+    cv.nsrc[c - cv.c0] = n_src;
 }
 
 // ---------------------------------------------------------------- split trees
@@ -541,7 +568,8 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare_tree(SimTables tb, BatchVi
       if (wr[h] != kNil && pos[h] < n_edges) sp.succ[pos[h]] = f;
   });
   wave_order();
-  prep_finish(cv, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_p);
+  const int n_src = prep_finish(cv.prep_in, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_p);
+  if (l == 0) cv.nsrc[c - cv.c0] = n_src;
 }
 
 // ---------------------------------------------------------------- event simulation
@@ -564,9 +592,43 @@ __device__ __forceinline__ uint64_t choice_draw(uint64_t seed, uint64_t idx) {
 // loop waits on memory between short bursts of issue, and a seventh wave hides
 // more of it than the few spilled registers cost (-15% per launch measured); the
 // 16- and 32-lane variants lose when squeezed and keep their registers.
+// Per-group LDS state of the event loop.
 template <int G, int POL>
+struct SimLds {
+  static constexpr int NG = kWave / G;
+  int64_t fin[NG][4][kMaxMem];    // per (block, space): latest finite valid-from
+  int32_t miss[NG][4][kMaxMem];   // per (block, space): finest blocks missing
+  // write-around: per (block, space), the latest host valid-from of the missing
+  // finest blocks (their transfer cannot leave before)
+  int64_t src[POL == 0 ? 1 : NG][4][kMaxMem];
+  uint32_t rid[NG][G];            // ready list, first G entries, with records
+  int64_t rrank[NG][G];
+  uint32_t rdesc[NG][G];
+  uint32_t re0[NG][G];
+  uint32_t re1[NG][G];
+  uint8_t order[NG][G];
+};
+// With the preparation fused in, a wave prepares its next candidate while the
+// event loop's state is dead: the preparation's LDS overlays it.
+template <int G, int POL>
+union SimPrepLds {
+  SimLds<G, POL> sim;
+  PrepLds prep;
+};
+
+// Instantiated per policy class so that the default policy carries no policy
+// code: R-P / F-P map tasks only onto idle processors and may make them wait.
+// The whole-wave variant is limited to 72 VGPRs, seven waves per SIMD: the event
+// loop waits on memory between short bursts of issue, and a seventh wave hides
+// more of it than the few spilled registers cost (-15% per launch measured); the
+// 16- and 32-lane variants lose when squeezed and keep their registers.
+// FUSED (whole-wave groups only): each wave prepares the candidates it claims
+// itself (prepare_cand) into its own slot of cv.slot_bytes bytes of cv.region,
+// so a batch needs neither the separate preparation launch nor memory chunks.
+template <int G, int POL, bool FUSED>
 __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
                                                uint32_t* counter) {
+  static_assert(!FUSED || G == kWave, "the fused preparation needs whole-wave groups");
   // POL 0: Priority-List + EFT-P + write-back (no policy flags read); 1: the
   // other push policies (FCFS, EIT-P) and caching policies; 2: R-P / F-P
   constexpr bool PULL = POL == 2;
@@ -574,26 +636,29 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
   const int sel = POL == 0 ? 0 : tb.sel;
   const int cache = POL == 0 ? 0 : tb.cache;
   const bool bus = POL != 0 && tb.bus != 0;
-  constexpr int NG = kWave / G;
   constexpr int LGG = G == 16 ? 4 : (G == 32 ? 5 : 6);
   __shared__ int64_t s_cost[kMaxPtypes][4][kLevels];
   __shared__ int64_t s_xfer[kXferLen];
-  __shared__ int64_t s_fin[NG][4][kMaxMem];    // per (block, space): latest finite valid-from
-  __shared__ int32_t s_miss[NG][4][kMaxMem];   // per (block, space): finest blocks missing
-  // write-around: per (block, space), the latest host valid-from of the missing
-  // finest blocks (their transfer cannot leave before)
-  __shared__ int64_t s_src[POL == 0 ? 1 : NG][4][kMaxMem];
-  __shared__ uint32_t s_rid[NG][G];            // ready list, first G entries, with records
-  __shared__ int64_t s_rrank[NG][G];
-  __shared__ uint32_t s_rdesc[NG][G];
-  __shared__ uint32_t s_re0[NG][G];
-  __shared__ uint32_t s_re1[NG][G];
-  __shared__ uint8_t s_order[NG][G];
+  __shared__ int64_t s_W[FUSED ? 4 : 1][kLevels];
+  using Lds = std::conditional_t<FUSED, SimPrepLds<G, POL>, SimLds<G, POL>>;
+  __shared__ Lds s_l;
+  SimLds<G, POL>& L = reinterpret_cast<SimLds<G, POL>&>(s_l);
+  auto& s_fin = L.fin;
+  auto& s_miss = L.miss;
+  auto& s_src = L.src;
+  auto& s_rid = L.rid;
+  auto& s_rrank = L.rrank;
+  auto& s_rdesc = L.rdesc;
+  auto& s_re0 = L.re0;
+  auto& s_re1 = L.re1;
+  auto& s_order = L.order;
 
   const Grp<G> gp;
   const int l = gp.l, g = gp.g, gl = gp.gl;
   for (int x = l; x < kMaxPtypes * 4 * kLevels; x += kWave) (&s_cost[0][0][0])[x] = (&tb.cost[0][0][0])[x];
   for (int x = l; x < kXferLen; x += kWave) s_xfer[x] = tb.xfer[x];
+  if (FUSED)
+    for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
   __syncthreads();
 
   const int P = tb.n_procs, M = tb.n_mem;
@@ -602,7 +667,6 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
   const int ptype = gl < P ? tb.proc_type[gl] : 0;
   const bool want_sched = out.sched_off != nullptr;
 
-  bool active = false, exhausted = false;
   int c = 0, nt = 0, dmax = 0;
   int64_t xs = 0, T = 0, n_ready = 0, sbase = 0;
   CandPtrs sp{};
@@ -622,457 +686,100 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
     }
   };
 
-  for (;;) {
-    // groups without a candidate take the next one
-    if (!active && !exhausted) {
+  if constexpr (!FUSED) {
+    // groups without a candidate take the next one; the wave runs until every
+    // group has found the candidates exhausted
+    bool active = false, exhausted = false;
+    for (;;) {
+      if (!active && !exhausted) {
+        int cc = 0;
+        if (gl == 0) cc = (int)atomicAdd(counter, 1u);
+        cc = gp.bcast(cc, 0);
+        if (cc >= cv.nc) {
+          exhausted = true;
+        } else {
+          c = cv.c0 + (cv.order ? (int)cv.order[cc] : cc);
+          if (out.status[c] == kOK) {
+            const Cand cd = load_cand(bv, c);
+            nt = cd.nt;
+            dmax = cd.dmax;
+            xs = (int64_t)1 << (2 * (tb.max_level - dmax));
+            sp = cand_ptrs(cv, c);
+            sbase = want_sched ? out.sched_off[c] : 0;
+            T = 0;
+            avail = 0;
+            bus_free = 0;
+            hfin = kInf;
+            hid = kNil;
+            tail = kNil;
+            n_ready = cv.nsrc[c - cv.c0];
+            // FCFS keeps minus the release time in the rank slot (sources: 0)
+            for (int64_t x = gl; x < (fcfs || n_ready < G ? n_ready : G); x += G) {
+              const uint32_t v = vld(&sp.ready[x]);
+              if (fcfs) sp.rec[2 * v] = 0;
+              if (x < G) push(x, v, fcfs ? 0 : vld(&sp.rec[2 * v]), vld(&sp.rec[2 * v + 1]), vld(&sp.rec[2 * v + 3]));
+            }
+            active = true;
+          }
+        }
+      }
+      if (__ballot(!exhausted) == 0) break;
+      if (!active) continue;
+      wave_order();
+#define HESP_CANDIDATE_DONE \
+  {                         \
+    active = false;         \
+    continue;               \
+  }
+#include "hesp_sim_round.inc"
+#undef HESP_CANDIDATE_DONE
+    }
+  } else {
+    // the wave prepares each candidate it takes into its own slot, then runs it
+    // to completion (no event-loop state lives across the preparation)
+    for (;;) {
       int cc = 0;
-      if (gl == 0) cc = (int)atomicAdd(counter, 1u);
-      cc = gp.bcast(cc, 0);
-      if (cc >= cv.nc) {
-        exhausted = true;
-      } else {
-        c = cv.c0 + (cv.order ? (int)cv.order[cc] : cc);
-        if (out.status[c] == kOK) {
-          const Cand cd = load_cand(bv, c);
-          nt = cd.nt;
-          dmax = cd.dmax;
-          xs = (int64_t)1 << (2 * (tb.max_level - dmax));
-          sp = cand_ptrs(cv, c);
-          sbase = want_sched ? out.sched_off[c] : 0;
-          T = 0;
-          avail = 0;
-          bus_free = 0;
-          hfin = kInf;
-          hid = kNil;
-          tail = kNil;
-          n_ready = cv.nsrc[c - cv.c0];
-          // FCFS keeps minus the release time in the rank slot (sources: 0)
-          for (int64_t x = gl; x < (fcfs || n_ready < G ? n_ready : G); x += G) {
-            const uint32_t v = vld(&sp.ready[x]);
-            if (fcfs) sp.rec[2 * v] = 0;
-            if (x < G) push(x, v, fcfs ? 0 : vld(&sp.rec[2 * v]), vld(&sp.rec[2 * v + 1]), vld(&sp.rec[2 * v + 3]));
-          }
-          active = true;
-        }
+      if (l == 0) cc = (int)atomicAdd(counter, 1u);
+      cc = __builtin_amdgcn_readfirstlane(cc);
+      if (cc >= cv.nc) break;
+      c = cv.c0 + (cv.order ? (int)cv.order[cc] : cc);
+      {
+        const Cand cq = load_cand(bv, c);
+        const int64_t Tq = cv.cnt_tasks[c], Eq = cv.cnt_edges[c];
+        const bool shape_ok = cq.nt >= 1 && cq.dmax >= 0 && cq.dmax <= kMaxLevel && (cq.nt << cq.dmax) <= kMaxFine;
+        const int64_t Vq = shape_ok ? ((int64_t)tri2(cq.nt) << (2 * cq.dmax)) * M : 0;
+        const bool cap = (cv.cap_tasks > 0 && Tq > cv.cap_tasks) || (cv.cap_edges > 0 && Eq > cv.cap_edges) ||
+                         region_bytes(Tq, Eq, Vq, cq.n_top + 1) > cv.slot_bytes;
+        sp = carve(cv.region + (int64_t)blockIdx.x * cv.slot_bytes, Tq, Eq, Vq);
+        int n_src = 0;
+        const bool ok = prepare_cand(tb, bv, out, c, sp, Tq, Eq, cap, cv.prep_in, s_W, s_l.prep, n_src) == kOK;
+        __syncthreads();   // the preparation's LDS is the event loop's from here
+        if (!ok) continue;
+        nt = cq.nt;
+        dmax = cq.dmax;
+        n_ready = n_src;
       }
-    }
-    if (__ballot(!exhausted) == 0) break;
-    if (!active) continue;
-    wave_order();
-
-    // (i) map every released task, in priority order
-    if (n_ready > 0) {
-      const bool small = n_ready <= G;
-      if (n_ready == 1) {
-        if (gl == 0) s_order[g][0] = 0;
-      } else if (small) {
-        // position of each entry: decreasing critical time, then increasing key
-        const bool v = gl < n_ready;
-        const int64_t rk = v ? s_rrank[g][gl] : INT64_MIN;
-        const uint32_t ky = v ? task_key(s_rdesc[g][gl], dmax) : 0u;
-        int pos = 0;
-        for (int j = 0; j < (int)n_ready; j++) {
-          const int64_t rj = gp.bcast64(rk, j);
-          const uint32_t kj = (uint32_t)gp.bcast((int)ky, j);
-          pos += (rj > rk || (rj == rk && kj < ky)) ? 1 : 0;
-        }
-        if (v) s_order[g][pos] = (uint8_t)gl;
-      } else {
-        // bitonic sort of (critical time, key|id) pairs in the candidate's buffer
-        int64_t n2 = 1;
-        while (n2 < n_ready) n2 <<= 1;
-        for (int64_t x = gl; x < n2; x += G) {
-          if (x < n_ready) {
-            uint32_t id, dsc;
-            int64_t rk;
-            if (x < G) {
-              id = s_rid[g][x];
-              rk = s_rrank[g][x];
-              dsc = s_rdesc[g][x];
-            } else {
-              id = vld(&sp.ready[x]);
-              rk = vld(&sp.rec[2 * id]);
-              dsc = (uint32_t)vld(&sp.rec[2 * id + 1]);
-            }
-            sp.sortbuf[2 * x] = rk;
-            sp.sortbuf[2 * x + 1] = ((int64_t)task_key(dsc, dmax) << 32) | id;
-          } else {
-            sp.sortbuf[2 * x] = INT64_MIN;
-            sp.sortbuf[2 * x + 1] = INT64_MAX;
-          }
-        }
+      xs = (int64_t)1 << (2 * (tb.max_level - dmax));
+      sbase = want_sched ? out.sched_off[c] : 0;
+      T = 0;
+      avail = 0;
+      bus_free = 0;
+      hfin = kInf;
+      hid = kNil;
+      tail = kNil;
+      for (int64_t x = gl; x < (fcfs || n_ready < G ? n_ready : G); x += G) {
+        const uint32_t v = vld(&sp.ready[x]);
+        if (fcfs) sp.rec[2 * v] = 0;
+        if (x < G) push(x, v, fcfs ? 0 : vld(&sp.rec[2 * v]), vld(&sp.rec[2 * v + 1]), vld(&sp.rec[2 * v + 3]));
+      }
+      for (;;) {
         wave_order();
-        // R-P / F-P map at most one task per idle processor now: the entries are
-        // selected one at a time below instead of sorted
-        for (int64_t k2 = 2; k2 <= (PULL ? 1 : n2); k2 <<= 1) {
-          for (int64_t j2 = k2 >> 1; j2 > 0; j2 >>= 1) {
-            for (int64_t x = gl; x < n2; x += G) {
-              const int64_t y = x ^ j2;
-              if (y > x) {
-                const int64_t ra = vld(&sp.sortbuf[2 * x]), ka = vld(&sp.sortbuf[2 * x + 1]);
-                const int64_t rb = vld(&sp.sortbuf[2 * y]), kb = vld(&sp.sortbuf[2 * y + 1]);
-                // "a before b": larger rank, then smaller key
-                const bool a_first = ra > rb || (ra == rb && ka < kb);
-                const bool up = (x & k2) == 0;
-                if (up != a_first) {
-                  sp.sortbuf[2 * x] = rb;
-                  sp.sortbuf[2 * x + 1] = kb;
-                  sp.sortbuf[2 * y] = ra;
-                  sp.sortbuf[2 * y + 1] = ka;
-                }
-              }
-            }
-            wave_order();
-          }
-        }
+#define HESP_CANDIDATE_DONE break
+#include "hesp_sim_round.inc"
+#undef HESP_CANDIDATE_DONE
       }
-      wave_order();
-      int64_t r_stop = n_ready;
-      for (int64_t r = 0; r < n_ready; r++) {
-        // R-P / F-P map onto processors idle now; without one the rest wait
-        uint64_t idle = 0;
-        if (PULL) {
-          idle = gp.ballot(gl < P && avail <= T);
-          if (idle == 0) {
-            r_stop = r;
-            break;
-          }
-        }
-        uint32_t t, dsc, e0, e1;
-        if (small) {
-          const int q = gp.uni(s_order[g][r]);
-          t = s_rid[g][q];
-          dsc = s_rdesc[g][q];
-          e0 = s_re0[g][q];
-          e1 = s_re1[g][q];
-        } else {
-          if (PULL) {
-            // best remaining entry: largest rank, then smallest key; taken entries
-            // have their key set to INT64_MAX
-            int64_t br = INT64_MIN, bk = INT64_MAX;
-            int bp = -1;
-            for (int x = gl; x < n_ready; x += G) {
-              const int64_t ra = vld(&sp.sortbuf[2 * x]), ka = vld(&sp.sortbuf[2 * x + 1]);
-              if (ka != INT64_MAX && (bp < 0 || ra > br || (ra == br && ka < bk))) {
-                br = ra;
-                bk = ka;
-                bp = x;
-              }
-            }
-            const int64_t rbest = ~gp.min64all(bp >= 0 ? ~br : kInf);   // ~ reverses the order exactly
-            const int64_t kbest = gp.min64all(bp >= 0 && br == rbest ? bk : kInf);
-            const int owner = __ffsll((unsigned long long)gp.ballot(bp >= 0 && br == rbest && bk == kbest)) - 1;
-            const int pos = gp.bcast(bp, owner);
-            if (gl == owner) sp.sortbuf[2 * pos + 1] = INT64_MAX;
-            t = (uint32_t)(kbest & 0xFFFFFFFFll);
-          } else {
-            t = (uint32_t)(vld(&sp.sortbuf[2 * r + 1]) & 0xFFFFFFFFll);
-          }
-          const int64_t r1 = vld(&sp.rec[2 * t + 1]);
-          dsc = (uint32_t)r1;
-          e0 = (uint32_t)((uint64_t)r1 >> 32);
-          e1 = (uint32_t)((uint64_t)vld(&sp.rec[2 * t + 3]) >> 32);
-        }
-        t = (uint32_t)gp.uni((int)t);
-        dsc = (uint32_t)gp.uni((int)dsc);
-        e0 = (uint32_t)gp.uni((int)e0);
-        e1 = (uint32_t)gp.uni((int)e1);
-        const int kind = desc_kind(dsc), lvl = desc_level(dsc);
-        const int sh = dmax - lvl;                 // a block is 2^sh x 2^sh finest blocks
-        const int lg = 2 * sh;
-        const int lgs = lg < LGG ? lg : LGG;      // lanes per segment chunk: 2^lgs
-        const int wmask = (1 << sh) - 1;
-        int br[3], bc[3];
-        const int nb = desc_blocks(dsc, br, bc);
-        // validity-table indices fit in 32 bits: at most 512 x 513 / 2 finest
-        // blocks (nt * 2^dmax <= 512) times at most 16 memory spaces
-        const int ab0 = (int)atom_base(nt, dmax, lvl, br[0], bc[0]);
-        const int ab1 = nb > 1 ? (int)atom_base(nt, dmax, lvl, br[1], bc[1]) : 0;
-        const int ab2 = nb > 2 ? (int)atom_base(nt, dmax, lvl, br[2], bc[2]) : 0;
-        for (int x = gl; x < 4 * M; x += G) {
-          (&s_fin[g][0][0])[(x >> 2) + (x & 3) * kMaxMem] = INT64_MIN;
-          (&s_miss[g][0][0])[(x >> 2) + (x & 3) * kMaxMem] = 0;
-          if (POL != 0) (&s_src[POL == 0 ? 0 : g][0][0])[(x >> 2) + (x & 3) * kMaxMem] = INT64_MIN;
-        }
-        wave_order();
-        // one lane per (space m, block b, finest block a): it = ((m*4 + b) << lg) | a
-        const int items = (M << 2) << lg;
-        const bool one_pass = items <= G;
-        int64_t my_x = 0;
-        int my_addr = -1;
-        int my_m = 0, my_b = 0;
-        for (int i0 = 0; i0 < items; i0 += G) {
-          const int it = i0 + gl;
-          const int a = it & ((1 << lg) - 1);
-          const int b = (it >> lg) & 3;
-          const int m = it >> (lg + 2);
-          const bool act = it < items && b < nb;
-          const int abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
-          const int addr = (abase + ((a >> sh) << dmax) + (a & wmask)) * M + m;
-          const int64_t x = act ? vld(&sp.vf[addr]) : kInf;
-          const uint64_t infm = gp.ballot(act && x == kInf);
-          const int64_t fin = seg_max64((act && x != kInf) ? x : INT64_MIN, lgs);
-          int64_t src = INT64_MIN;
-          if (POL != 0 && cache == 2) {
-            // write-around keeps a valid (possibly future) copy of every block on
-            // the host, and no other copy is valid earlier
-            const int64_t h = (act && x == kInf) ? vld(&sp.vf[addr - m]) : INT64_MIN;
-            src = seg_max64(h, lgs);
-          }
-          if (act && (a & ((1 << lgs) - 1)) == (1 << lgs) - 1) {   // last lane of its segment chunk
-            const uint64_t segm = lgs == 6 ? ~0ull : (((1ull << (1 << lgs)) - 1ull) << (gl + 1 - (1 << lgs)));
-            s_fin[g][b][m] = max64(s_fin[g][b][m], fin);
-            s_miss[g][b][m] += __popcll(infm & segm);
-            if (POL != 0 && cache == 2) s_src[POL == 0 ? 0 : g][b][m] = max64(s_src[POL == 0 ? 0 : g][b][m], src);
-          }
-          if (one_pass) {
-            my_x = x;
-            my_addr = act ? addr : -1;
-            my_m = m;
-            my_b = b;
-          }
-        }
-        wave_order();
-        int64_t est = T > avail ? T : avail;
-        if (gl < P) {
-          int64_t lb = bus_free;                    // with a shared interconnect: the blocks in order
-          for (int b = 0; b < nb; b++) {
-            const int ms = s_miss[g][b][pmem];
-            int64_t rdy = s_fin[g][b][pmem];
-            int64_t go = T;
-            if (POL != 0 && cache == 2) go = max64(T, s_src[POL == 0 ? 0 : g][b][pmem]);
-            if (ms > 0) {
-              if (bus) go = max64(go, lb);
-              const int64_t arr = go + s_xfer[ms * xs];
-              if (bus) lb = arr;
-              rdy = max64(rdy, arr);
-            }
-            est = max64(est, rdy);
-          }
-        }
-        const int64_t eft = est + s_cost[ptype][kind][lvl];
-        int pstar;
-        int64_t eft_star;
-        if (PULL && sel == 2) {
-          // R-P: the u-th idle processor in index order
-          const int u = (int)(choice_draw(tb.seed, task_key(dsc, dmax)) % (uint64_t)__popcll(idle));
-          const bool mine = ((idle >> gl) & 1ull) && __popcll(idle & gp.below()) == u;
-          pstar = __ffsll((unsigned long long)gp.ballot(mine)) - 1;
-          eft_star = gp.bcast64(eft, pstar);
-        } else {
-          // EFT-P: earliest finish; EIT-P: earliest idle time (an idle processor
-          // from now); F-P: smallest task time among the idle processors
-          int64_t score = eft;
-          if (sel == 1) score = T > avail ? T : avail;
-          if (PULL && sel == 3) score = ((idle >> gl) & 1ull) ? s_cost[ptype][kind][lvl] : (kInf >> 6);
-          const int64_t key = gl < P ? ((score << 6) | gl) : kInf;
-          const int64_t best = gp.min64lo(key, p16);
-          pstar = (int)(best & 63);
-          eft_star = sel == 0 ? best >> 6 : gp.bcast64(eft, pstar);
-        }
-        const int64_t est_star = gp.bcast64(est, pstar);
-        const int mstar = gp.bcast(pmem, pstar);
-        // transfers of the missing finest blocks start now
-        auto leave = [&](int b) {   // when the transfer of block b's missing finest blocks can start
-          return (POL != 0 && cache == 2) ? max64(T, s_src[POL == 0 ? 0 : g][b][mstar]) : T;
-        };
-        // arrival of each block's transfer (in block order on a shared interconnect)
-        int64_t arr0 = 0, arr1 = 0, arr2 = 0;
-        if constexpr (POL != 0) {
-          int64_t lb = bus_free;
-          for (int b = 0; b < nb; b++) {
-            const int miss = s_miss[g][b][mstar];
-            if (miss == 0) continue;
-            int64_t go = leave(b);
-            if (bus) go = max64(go, lb);
-            const int64_t a = go + s_xfer[miss * xs];
-            if (bus) lb = a;
-            if (b == 0) arr0 = a;
-            else if (b == 1) arr1 = a;
-            else arr2 = a;
-          }
-          if (bus) bus_free = lb;
-        }
-        auto arrival = [&](int b) {
-          if constexpr (POL == 0) return leave(b) + s_xfer[s_miss[g][b][mstar] * xs];
-          return b == 0 ? arr0 : (b == 1 ? arr1 : arr2);
-        };
-        if (one_pass) {
-          if (my_addr >= 0 && my_m == mstar && my_x == kInf) sp.vf[my_addr] = arrival(my_b);
-        } else {
-          for (int b = 0; b < nb; b++) {
-            const int miss = s_miss[g][b][mstar];
-            if (miss == 0) continue;
-            const int64_t arrive = arrival(b);
-            const int abase = b == 0 ? ab0 : (b == 1 ? ab1 : ab2);
-            for (int a0 = 0; a0 < (1 << lg); a0 += G) {
-              const int a = a0 + gl;
-              if (a < (1 << lg)) {
-                const int addr = (abase + ((a >> sh) << dmax) + (a & wmask)) * M + mstar;
-                if (vld(&sp.vf[addr]) == kInf) sp.vf[addr] = arrive;
-              }
-            }
-          }
-        }
-        // append to the chosen processor's queue
-        if (gl == pstar) {
-          avail = eft_star;
-          if (hid == kNil) {
-            hid = t;
-            hfin = eft_star;
-            hdesc = dsc;
-            he0 = e0;
-            he1 = e1;
-          } else {
-            sp.fifo[3 * tail] = eft_star;
-            sp.fifo[3 * tail + 1] = (int64_t)(t | ((uint64_t)dsc << 32));
-            sp.fifo[3 * tail + 2] = (int64_t)(e0 | ((uint64_t)e1 << 32));
-          }
-          tail = t;
-        }
-        if (want_sched && gl == 0) {
-          out.proc[sbase + t] = pstar;
-          out.start[sbase + t] = est_star;
-          out.finish[sbase + t] = eft_star;
-        }
-        wave_order();
-      }
-      if (PULL && r_stop < n_ready) {
-        // the tasks that found no idle processor stay released, in front
-        const int rem = (int)(n_ready - r_stop);
-        if (small) {
-          uint32_t id = 0, d1 = 0, a0 = 0, a1 = 0;
-          int64_t rk = 0;
-          if (gl < rem) {
-            const int q = s_order[g][r_stop + gl];
-            id = s_rid[g][q];
-            rk = s_rrank[g][q];
-            d1 = s_rdesc[g][q];
-            a0 = s_re0[g][q];
-            a1 = s_re1[g][q];
-          }
-          wave_order();
-          if (gl < rem) {
-            s_rid[g][gl] = id;
-            s_rrank[g][gl] = rk;
-            s_rdesc[g][gl] = d1;
-            s_re0[g][gl] = a0;
-            s_re1[g][gl] = a1;
-          }
-        } else {
-          // entries not taken by the selection, in buffer order (the next round
-          // orders them again)
-          int kept = 0;
-          for (int x0 = 0; x0 < n_ready; x0 += G) {
-            const int x = x0 + gl;
-            int64_t ka = INT64_MAX;
-            if (x < n_ready) ka = vld(&sp.sortbuf[2 * x + 1]);
-            const bool keep = ka != INT64_MAX;
-            const uint64_t km = gp.ballot(keep);
-            const int at = kept + __popcll(km & gp.below());
-            if (keep) {
-              const uint32_t id = (uint32_t)(ka & 0xFFFFFFFFll);
-              if (at < G) push(at, id, vld(&sp.rec[2 * id]), vld(&sp.rec[2 * id + 1]), vld(&sp.rec[2 * id + 3]));
-              else sp.ready[at] = id;
-            }
-            kept += __popcll(km);
-          }
-        }
-        n_ready = rem;
-      } else {
-        n_ready = 0;
-      }
-      wave_order();
+      __syncthreads();   // and the next preparation's after the event loop
     }
-
-    // (ii) next event: the earliest queue head
-    const int64_t Tn = gp.min64lo(gl < P ? hfin : kInf, p16);
-    if (Tn == kInf) {
-      if (gl == 0) out.makespan[c] = T;
-      active = false;
-      continue;
-    }
-
-    // (iii) completions at Tn; the next queue entries are fetched first
-    const uint64_t cm = gp.ballot(gl < P && hfin == Tn);
-    const bool adv = (cm >> gl) & 1ull;
-    const bool has_next = adv && hid != tail;
-    int64_t nf = kInf, nid = 0, ne = 0;
-    if (has_next) {
-      nf = vld(&sp.fifo[3 * hid]);
-      nid = vld(&sp.fifo[3 * hid + 1]);
-      ne = vld(&sp.fifo[3 * hid + 2]);
-    }
-    uint64_t rem = cm;
-    while (rem) {
-      const int p = __ffsll((unsigned long long)rem) - 1;
-      rem &= rem - 1;
-      const int ms = gp.bcast(pmem, p);
-      const uint32_t dsc = (uint32_t)gp.bcast((int)hdesc, p);
-      const uint32_t e0 = (uint32_t)gp.bcast((int)he0, p);
-      const uint32_t e1 = (uint32_t)gp.bcast((int)he1, p);
-      const int lvl = desc_level(dsc);
-      const int sh = dmax - lvl, lg = 2 * sh, wmask = (1 << sh) - 1;
-      int br[3], bc[3];
-      const int nb = desc_blocks(dsc, br, bc);
-      // write-back: the written block is valid only where it was computed;
-      // write-through: also on the host, once the copy sent now has arrived;
-      // write-around: on the host only, once that copy has arrived
-      const int abase = (int)atom_base(nt, dmax, lvl, br[nb - 1], bc[nb - 1]);
-      const int items = M << lg;
-      int64_t host_at = (POL != 0 && cache != 0 && ms != 0) ? Tn + s_xfer[(1 << lg) * xs] : Tn;
-      if (bus && cache != 0 && ms != 0) {         // the host copy queues on the interconnect
-        host_at = max64(Tn, bus_free) + s_xfer[(1 << lg) * xs];
-        bus_free = host_at;
-      }
-      for (int i0 = 0; i0 < items; i0 += G) {
-        const int it = i0 + gl;
-        if (it < items) {
-          const int m = it >> lg, a = it & ((1 << lg) - 1);
-          const int atom = abase + ((a >> sh) << dmax) + (a & wmask);
-          int64_t x = (m == ms) ? Tn : kInf;
-          if (POL != 0 && cache == 1) x = (m == ms) ? Tn : (m == 0 ? host_at : kInf);
-          if (POL != 0 && cache == 2) x = (m == 0) ? host_at : kInf;
-          sp.vf[atom * M + m] = x;
-        }
-      }
-      // release successors (their records are fetched alongside the decrement)
-      for (uint32_t e = e0; e < e1; e += G) {
-        const uint32_t ee = e + gl;
-        bool rel = false;
-        uint32_t v = 0;
-        int64_t r0 = 0, r1 = 0, r3 = 0;
-        if (ee < e1) {
-          v = vld(&sp.succ[ee]);
-          r0 = vld(&sp.rec[2 * v]);
-          r1 = vld(&sp.rec[2 * v + 1]);
-          r3 = vld(&sp.rec[2 * v + 3]);
-          rel = atomicSub(&sp.indeg[v], 1u) == 1u;
-          if (fcfs) {
-            r0 = -Tn;
-            if (rel) sp.rec[2 * v] = -Tn;
-          }
-        }
-        const uint64_t rm = gp.ballot(rel);
-        if (rel) push(n_ready + __popcll(rm & gp.below()), v, r0, r1, r3);
-        n_ready += __popcll(rm);
-      }
-    }
-    if (adv) {
-      if (has_next) {
-        hid = (uint32_t)nid;
-        hdesc = (uint32_t)((uint64_t)nid >> 32);
-        hfin = nf;
-        he0 = (uint32_t)ne;
-        he1 = (uint32_t)((uint64_t)ne >> 32);
-      } else {
-        hid = kNil;
-        hfin = kInf;
-        tail = kNil;
-      }
-    }
-    wave_order();
-    T = Tn;
   }
 }
 
@@ -1120,6 +827,8 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
                       int32_t group, uint32_t* counter, hipStream_t s) {
   if (v.nc <= 0) return hipSuccess;
   if ((group != 16 && group != 32 && group != 64) || group < t.n_procs) return hipErrorInvalidValue;
+  const bool fused = v.slot_bytes > 0;
+  if (fused && (group != 64 || !v.region || b.tree_stride > 0)) return hipErrorInvalidValue;
   hipError_t e = launch_zero_u32(counter, s);
   if (e != hipSuccess) return e;
   const int G = group;
@@ -1128,21 +837,57 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
   if (waves > slots) waves = slots;
   const int pol = t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs || t.cache != 0 || t.bus != 0 ? 1 : 0);
   const dim3 grid(waves), block(kWave);
-#define HESP_SIM_LAUNCH(GG, PP) hipLaunchKernelGGL((k_sim<GG, PP>), grid, block, 0, s, t, b, v, o, counter)
-  if (G == 16) {
-    if (pol == 0) HESP_SIM_LAUNCH(16, 0);
-    else if (pol == 1) HESP_SIM_LAUNCH(16, 1);
-    else HESP_SIM_LAUNCH(16, 2);
+#define HESP_SIM_LAUNCH(GG, PP, FF) hipLaunchKernelGGL((k_sim<GG, PP, FF>), grid, block, 0, s, t, b, v, o, counter)
+  if (fused) {
+    if (pol == 0) HESP_SIM_LAUNCH(64, 0, true);
+    else if (pol == 1) HESP_SIM_LAUNCH(64, 1, true);
+    else HESP_SIM_LAUNCH(64, 2, true);
+  } else if (G == 16) {
+    if (pol == 0) HESP_SIM_LAUNCH(16, 0, false);
+    else if (pol == 1) HESP_SIM_LAUNCH(16, 1, false);
+    else HESP_SIM_LAUNCH(16, 2, false);
   } else if (G == 32) {
-    if (pol == 0) HESP_SIM_LAUNCH(32, 0);
-    else if (pol == 1) HESP_SIM_LAUNCH(32, 1);
-    else HESP_SIM_LAUNCH(32, 2);
+    if (pol == 0) HESP_SIM_LAUNCH(32, 0, false);
+    else if (pol == 1) HESP_SIM_LAUNCH(32, 1, false);
+    else HESP_SIM_LAUNCH(32, 2, false);
   } else {
-    if (pol == 0) HESP_SIM_LAUNCH(64, 0);
-    else if (pol == 1) HESP_SIM_LAUNCH(64, 1);
-    else HESP_SIM_LAUNCH(64, 2);
+    if (pol == 0) HESP_SIM_LAUNCH(64, 0, false);
+    else if (pol == 1) HESP_SIM_LAUNCH(64, 1, false);
+    else HESP_SIM_LAUNCH(64, 2, false);
   }
 #undef HESP_SIM_LAUNCH
+  return hipGetLastError();
+}
+
+// largest region_bytes of a candidate of the batch (for the fused simulation's
+// slots): out[0] = max over candidates (atomic maximum; out[0] zeroed first)
+__global__ void k_max_region(BatchView b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
+                             unsigned long long* out) {
+  unsigned long long m = 0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < b.n_cand; c += gridDim.x * blockDim.x) {
+    const int nt = b.nt_arr ? b.nt_arr[c] : b.nt;
+    const int dmax = b.dmax_arr ? b.dmax_arr[c] : b.dmax;
+    const bool ok = nt >= 1 && dmax >= 0 && dmax <= kMaxLevel && (nt << dmax) <= kMaxFine;
+    if (!ok) continue;
+    const int64_t V = ((int64_t)tri2(nt) << (2 * dmax)) * n_mem;
+    const unsigned long long r = (unsigned long long)region_bytes(n_tasks[c], n_edges[c], V, tet3(nt) + 1);
+    m = r > m ? r : m;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(m, o, kWave);
+    m = y > m ? y : m;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0 && m) atomicMax(out, m);
+}
+
+hipError_t launch_max_region(const BatchView& b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
+                             int64_t* out, hipStream_t s) {
+  hipError_t e = launch_zero_u32(reinterpret_cast<uint32_t*>(out), s);
+  if (e == hipSuccess) e = launch_zero_u32(reinterpret_cast<uint32_t*>(out) + 1, s);
+  if (e != hipSuccess) return e;
+  const int blocks = b.n_cand > 0 ? (b.n_cand + 255) / 256 < 1024 ? (b.n_cand + 255) / 256 : 1024 : 1;
+  hipLaunchKernelGGL(k_max_region, dim3(blocks), dim3(256), 0, s, b, n_mem, n_tasks, n_edges,
+                     reinterpret_cast<unsigned long long*>(out));
   return hipGetLastError();
 }
 

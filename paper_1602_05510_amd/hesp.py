@@ -51,7 +51,7 @@ class TreeBatchC(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("slots", i32), ("max_tasks", i64), ("max_edges", i64), ("chunks", i32), ("group", i32),
-                ("prep_edges", i32)]
+                ("prep_edges", i32), ("fuse", i32)]
 
 
 class OutputsC(ctypes.Structure):
@@ -302,9 +302,9 @@ def count_batch(batch: DeviceBatch, stream=None):
 
 class Plan:
     def __init__(self, slots: int = 0, max_tasks: int = 0, max_edges: int = 0, chunks: int = 0, group: int = 0,
-                 prep_edges: int = 0):
+                 prep_edges: int = 0, fuse: bool = False):
         self.h = P()
-        self.opts = PlanOpts(slots, max_tasks, max_edges, chunks, group, prep_edges)
+        self.opts = PlanOpts(slots, max_tasks, max_edges, chunks, group, prep_edges, int(bool(fuse)))
         _check("hesp_plan_create", lib().hesp_plan_create(ctypes.byref(self.h), ctypes.byref(self.opts)))
 
     def bytes(self) -> int:
