@@ -210,9 +210,9 @@ typedef struct {
  * no host synchronisation, no allocation and no autotuning -- only kernel
  * launches on `stream`, which can be captured in a HIP graph and replayed (the
  * graph keeps the batch and output pointers of the captured call).  A captured
- * call runs on `stream` alone and must fit one chunk (else HESP_EUNSUPPORTED),
- * unless the plan is fused: a fused fixed-capacity plan captures any batch as
- * one simulation launch.  Candidates above the capacities get HESP_ECAPACITY. */
+ * call runs its memory chunks one after the other on `stream` alone; a fused
+ * fixed-capacity plan captures any batch as one simulation launch.  Candidates
+ * above the capacities get HESP_ECAPACITY. */
 int hesp_plan_create(hesp_plan **plan, const hesp_plan_opts *opts);
 int hesp_plan_destroy(hesp_plan *plan);
 /* device bytes currently held by the plan */

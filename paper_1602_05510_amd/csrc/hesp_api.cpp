@@ -613,21 +613,21 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
       HIP_TRY(hipEventCreate(&e));
       plan->ev.push_back(e);
     }
-  while (plan->sync_ev.size() < 1 + 2 * (size_t)n_chunks) {
+  while (plan->sync_ev.size() < 2 + 2 * (size_t)n_chunks) {
     hipEvent_t e;
     HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     plan->sync_ev.push_back(e);
   }
   // fork: preparation and simulation run on the plan's two streams, chunk i+1
   // being prepared (into the other workspace set) while chunk i is simulated;
-  // the caller's stream waits for the last simulation.  A call being captured
-  // into a graph stays on the caller's stream and must fit one chunk: a capture
-  // of the two-stream pipeline ended in a crash of the runtime's capture_end.
+  // the caller's stream then waits for the last operation of both streams.  A
+  // call being captured into a graph keeps every chunk on the caller's stream
+  // (stream order alone keeps a workspace set from being reused early): the
+  // capture holds only kernel nodes, and no event recorded outside it.
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(s, &cap));
   const bool capturing = cap != hipStreamCaptureStatusNone;
-  if (capturing && n_chunks > 1)
-    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: a captured call must fit one chunk (%d needed)", n_chunks);
+  const bool timing = plan->timing && !capturing;
   // a single chunk has nothing to overlap: it stays on the caller's stream
   const bool fork = !capturing && n_chunks > 1;
   hipStream_t sp = fork ? plan->s_prep : s, ss = fork ? plan->s_sim : s;
@@ -640,25 +640,29 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
   for (int i = 0; i < n_chunks; i++) {
     const int set = i & 1;
     ChunkView cv = chunk_view(i * chunk, std::min(chunk, n - i * chunk), set);
-    if (i >= 2) HIP_TRY(hipStreamWaitEvent(sp, se[2 + 2 * (i - 2)], 0));   // set free again
-    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i], sp));
+    if (fork && i >= 2) HIP_TRY(hipStreamWaitEvent(sp, se[2 + 2 * (i - 2)], 0));   // set free again
+    if (timing) HIP_TRY(hipEventRecord(plan->ev[4 * i], sp));
     // largest candidates first, so that the persistent launch does not end on a long one
     HIP_TRY(srch::size_order(plan->cnt_tasks.as<int32_t>(), cv.c0, cv.nc, plan->ws[set].order_keys.as<uint64_t>(),
                              plan->ws[set].order.as<uint32_t>(), sp));
     cv.order = plan->ws[set].order.as<uint32_t>();
     HIP_TRY(prepare(cv, sp));
-    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 1], sp));
+    if (timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 1], sp));
     if (fork) {
       HIP_TRY(hipEventRecord(se[1 + 2 * i], sp));
       HIP_TRY(hipStreamWaitEvent(ss, se[1 + 2 * i], 0));
     }
-    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 2], ss));
+    if (timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 2], ss));
     HIP_TRY(launch_sim(tb, bv, cv, ov, plan->slots, group, plan->counter, ss));
-    if (plan->timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 3], ss));
+    if (timing) HIP_TRY(hipEventRecord(plan->ev[4 * i + 3], ss));
     if (fork) HIP_TRY(hipEventRecord(se[2 + 2 * i], ss));
-    if (plan->timing) plan->ev_used = 4 * (size_t)(i + 1);
+    if (timing) plan->ev_used = 4 * (size_t)(i + 1);
   }
-  if (fork) HIP_TRY(hipStreamWaitEvent(s, se[2 * n_chunks], 0));
+  if (fork) {
+    HIP_TRY(hipEventRecord(se[1 + 2 * n_chunks], sp));
+    HIP_TRY(hipStreamWaitEvent(s, se[2 * n_chunks], 0));
+    HIP_TRY(hipStreamWaitEvent(s, se[1 + 2 * n_chunks], 0));
+  }
   return ok();
 }
 

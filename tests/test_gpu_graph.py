@@ -23,12 +23,9 @@ def H(torch):
     return hesp
 
 
-@pytest.mark.parametrize("chunks", [
-    1,
-    pytest.param(3, marks=pytest.mark.skip(
-        reason="the capture of a three-chunk call (then forked over two streams) crashed in the runtime's "
-               "capture_end; captured calls are now refused unless they fit one chunk")),
-])
+# three chunks: captured calls keep every chunk on the capturing stream (the
+# eager two-stream pipeline is not captured)
+@pytest.mark.parametrize("chunks", [1, 3])
 def test_graph_replay_matches_eager(H, torch, chunks):
     w = I.WORKLOADS["chol16x16_b1024_d2"]
     pf_in = w.platform()
