@@ -18,29 +18,42 @@ LIB = os.path.join(HERE, "liboracle.so")
 # the same source built for the host it runs on (-march=native): the CPU baseline
 # compiles it on the measuring machine itself, so it never travels between hosts
 LIB_NATIVE = os.path.join(HERE, "liboracle_native.so")
+# AddressSanitizer + UndefinedBehaviorSanitizer build (clang, so that it shares one
+# sanitizer runtime with the host code of the sanitized libhesp build); loaded
+# instead of LIB when HESP_SANITIZE=1 (tests/sanitized_cpu_suite.py)
+LIB_SAN = os.path.join(HERE, "liboracle_san.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
+CLANG = "/opt/rocm/llvm/bin/clang"
 
 _libs = {}
 
 
-def build(force: bool = True, native: bool = False, extra_flags=()) -> str:
-    """Compile the oracle with gcc (plain C, -O2; -march=native for the baseline build)."""
-    out = LIB_NATIVE if native else LIB
+def build(force: bool = True, native: bool = False, extra_flags=(), sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, -O2; -march=native for the baseline
+    build), or with clang and the address and undefined-behaviour sanitizers."""
+    out = LIB_SAN if sanitize else (LIB_NATIVE if native else LIB)
     if force or not os.path.exists(out):
         tmp = out + ".tmp"
-        flags = ["-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra"]
-        if native:
-            flags.append("-march=native")
-        subprocess.check_call(["gcc", *flags, *extra_flags, "-o", tmp, SRC])
+        flags = ["-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra"]
+        if sanitize:
+            cmd = [CLANG, *flags, *SAN_FLAGS]
+        else:
+            cmd = ["gcc", "-O2", *flags] + (["-march=native"] if native else [])
+        subprocess.check_call([*cmd, *extra_flags, "-o", tmp, SRC])
         os.replace(tmp, out)
     return out
 
 
+def sanitized() -> bool:
+    return os.environ.get("HESP_SANITIZE") == "1"
+
+
 def lib(native: bool = False):
-    key = bool(native)
+    key = "san" if sanitized() else bool(native)
     if key not in _libs:
-        path = LIB_NATIVE if native else LIB
+        path = LIB_SAN if sanitized() else (LIB_NATIVE if native else LIB)
         if not os.path.exists(path):
-            build(native=native)
+            build(native=native, sanitize=sanitized())
         L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64

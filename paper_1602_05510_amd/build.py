@@ -10,6 +10,12 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhesp.so")
+# host code built with the address and undefined-behaviour sanitizers (device code
+# unchanged), for the CPU test-suite under a preloaded sanitizer runtime
+LIB_SAN = os.path.join(PKG, "libhesp_san.so")
+SAN_HOST_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-g"]
 
 SOURCES = ["hesp_kernels.hip", "hesp_sim.hip", "hesp_mlp.hip", "hesp_search.hip", "hesp_solve.hip", "hesp_noalloc.hip", "hesp_api.cpp",
            "hesp_mlp_api.cpp", "hesp_search_api.cpp", "hesp_solve_api.cpp"]
@@ -24,17 +30,18 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, sanitize: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp, *srcs]
+    out = LIB_SAN if sanitize else LIB
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, *(SAN_HOST_FLAGS if sanitize else []), "-I", INCLUDE, "-I", CSRC, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, sanitize="--sanitize" in sys.argv[1:]))
     sys.exit(0)

@@ -13,7 +13,9 @@ from typing import Optional
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libhesp.so")
+# HESP_SANITIZE=1: the build whose host code carries the address and
+# undefined-behaviour sanitizers (python -m paper_1602_05510_amd.build --sanitize)
+LIB_PATH = os.path.join(PKG, "libhesp_san.so" if os.environ.get("HESP_SANITIZE") == "1" else "libhesp.so")
 
 HESP_OK, HESP_EINVAL, HESP_ENOMEM, HESP_EHIP, HESP_ECAPACITY, HESP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MAX_PROCS, MAX_PTYPES, MAX_MEM, MAX_LEVEL, MAX_FINE = 64, 8, 16, 3, 512

@@ -179,12 +179,14 @@ def test_reference_oracle_passes():
 def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     so = _build_mutant(str(tmp_path), name, old, new)
-    saved_libs, saved_path = dict(O._libs), O.LIB
+    saved_libs, saved_path, saved_san = dict(O._libs), O.LIB, O.LIB_SAN
     try:
         O._libs.clear()
         O.LIB = so
+        O.LIB_SAN = so          # the sanitized suite loads this path instead
         assert not _pins_pass(), f"planted mistake '{name}' went unnoticed"
     finally:
         O._libs.clear()
         O._libs.update(saved_libs)
         O.LIB = saved_path
+        O.LIB_SAN = saved_san
