@@ -281,6 +281,7 @@ def run_search(args, torch, H):
     simulation budget), and the surrogate-guided search."""
     w = I.WORKLOADS["chol64x64_b1024_d3"]
     nt = args.search_nt or w.nt
+    print(f"search nt={nt}: library loaded", file=sys.stderr, flush=True)
     dev = torch.device("cuda")
     pf_in = w.platform()
     pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
@@ -290,20 +291,27 @@ def run_search(args, torch, H):
     sbatch = max(1, args.batch // args.sur_ratio)
     swarm = args.sur_warm or args.batch
     common = dict(rounds=args.rounds, seed=w.seed, warm_rounds=1, pool=args.pool, split_thr=thr, mutate_thr=mut)
+    def note(msg):
+        print(f"search nt={nt}: {msg}", file=sys.stderr, flush=True)
+
     for b in sorted({args.batch, sbatch, swarm}):
         H.search(plan, pf, nt, w.dmax, H.SEARCH_RANDOM, batch=b, warm_batch=b, rounds=1, seed=w.seed + 1000,
                  warm_rounds=1, pool=args.pool, split_thr=thr, mutate_thr=mut)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        note(f"warm-up round of {b} candidates done")
     plain_d, plain_best, plain_tr = H.search(plan, pf, nt, w.dmax, H.SEARCH_GREEDY, batch=args.batch,
                                              warm_batch=args.batch, **common)
+    note(f"plain greedy ({args.batch} per round): best {plain_best} after {plain_tr[-1]['wall_ms']:.0f} ms")
     small_d, small_best, small_tr = H.search(plan, pf, nt, w.dmax, H.SEARCH_GREEDY, batch=sbatch, warm_batch=swarm,
                                        **common)
+    note(f"plain greedy ({sbatch} per round): best {small_best} after {small_tr[-1]['wall_ms']:.0f} ms")
     m = H.MLP(args.mlp_seed)
     rate = torch.from_numpy(H.mlp_rate_features(pf_in.rmax)).to(dev)
     best_d, sur_best, sur_tr = H.search(plan, pf, nt, w.dmax, H.SEARCH_SURROGATE, batch=sbatch, warm_batch=swarm,
                                         proposals=sbatch * args.sur_proposals, mlp=m, rate=rate,
                                         train_steps=args.sur_train_steps, train_batch=512, lr=1e-3,
                                         replay=1 << 16, **common)
+    note(f"surrogate-guided: best {sur_best} after {sur_tr[-1]['wall_ms']:.0f} ms")
     target = plain_best * 1.01
 
     def reach(tr):
@@ -342,7 +350,10 @@ def run_search(args, torch, H):
         from oracle import oracle as O
         bests = {"plain": (plain_d, plain_best), "plain_same_batch": (small_d, small_best),
                  "surrogate": (best_d, sur_best)}
-        chk = {k: int(O.simulate(pf_in, nt, w.dmax, w.b, d, detail=False)) == v for k, (d, v) in bests.items()}
+        chk = {}
+        for k, (d, v) in bests.items():
+            chk[k] = int(O.simulate(pf_in, nt, w.dmax, w.b, d, detail=False)) == v
+            note(f"oracle re-simulated the best of {k}: {'equal' if chk[k] else 'DIFFERENT'}")
         n_s = args.search_check
         host = I.uniform_batch(w.seed + 77, n_s, nt, w.b, w.dmax, w.p_num, w.p_den)
         ms = torch.empty(n_s, dtype=torch.int64, device=dev)
