@@ -30,7 +30,8 @@ PROFILES = os.path.join(ROOT, "profiles")
 # every source the simulator kernel is compiled from: stored counters count only
 # while this hash matches the one recorded with them
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1602_05510_amd", "csrc", f)
-               for f in ("hesp_sim.hip", "hesp_device.h", "hesp_core.h", "hesp_internal.h", "hesp_tree.h")]
+               for f in ("hesp_sim.hip", "hesp_sim_round.inc", "hesp_device.h", "hesp_core.h", "hesp_internal.h",
+                         "hesp_tree.h")]
 
 
 def kernel_hash() -> str:
@@ -718,7 +719,7 @@ def main():
 
     # roofline accounting for the simulation kernel (steps are statistically alike;
     # the accounting uses the batch of the last step); uniform batches only
-    achieved = traffic = alg_bytes = None
+    achieved = traffic = alg_bytes = issue = None
     traffic_note = "split-tree batch: no algorithmic byte count" if args.tree else "ragged batch: no algorithmic byte count"
     if not w.ragged and not args.tree:
         host_last = w.batch(n, first=(args.steps - 1) * n)
@@ -734,6 +735,16 @@ def main():
                     and not bus):
                 traffic = pmc.get("hbm_bytes_per_launch")
         traffic_note = None if traffic is not None else "no counter run on this kernel source"
+        # issue rate of the same kernel source: instructions per simulated task and
+        # pipe occupancy from the SQ counter run
+        sq_path = os.path.join(PROFILES, f"k_sim_{w.name}_sq.json")
+        if os.path.exists(sq_path):
+            with open(sq_path) as f:
+                sq = json.load(f)
+            if (sq.get("kernel_sha") == kernel_hash() and sq.get("n_cand") == n and tuple(args.policy) == (0, 0, 0)
+                    and not bus):
+                issue = {k: sq[k] for k in ("valu_insts_per_task", "salu_insts_per_task", "insts_per_task",
+                                            "valu_busy", "salu_busy", "wave_wait_frac", "source")}
 
     value = tasks_total / elapsed
     pname = (["PL", "FCFS"][order] + "/" + ["EFT-P", "EIT-P", "R-P", "F-P"][select] + "/" +
@@ -764,6 +775,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_sim", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "traffic_note": traffic_note,
+                     "issue": issue,
                      "algorithmic_bytes_per_launch": None if alg_bytes is None else alg_bytes / launches_per_step,
                      "launch_ms": sim_avg_ms,
                      "launches_per_step": launches_per_step, "prepare_launch_ms": prep_avg_ms,

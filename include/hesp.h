@@ -259,7 +259,7 @@ int hesp_simulate_batch(hesp_plan *plan, const hesp_platform *pf, hesp_policy po
  * Outputs and statuses are those of hesp_simulate_batch (same makespans and
  * schedules).  Limits: n_cand <= HESP_NOALLOC_MAX_CAND (else HESP_EINVAL before
  * anything is enqueued); the candidates' workspaces are laid out in candidate
- * order, region_bytes = 88 T + 4 E + 8 V + 4 (tet(nt) + 1) + 16 bytes each (T
+ * order, region_bytes = 104 T + 4 E + 8 V + 4 (tet(nt) + 1) bytes each (T
  * tasks, E edges, V = finest blocks x memory spaces, rounded up to 16), and a
  * candidate whose workspace would end past HESP_NOALLOC_REGION bytes gets
  * HESP_ECAPACITY (makespan -1), as do all candidates after it.  group: lanes

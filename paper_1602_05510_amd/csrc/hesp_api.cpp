@@ -105,7 +105,7 @@ struct hesp_plan {
   int32_t fixed_chunk = 0;
   // fused pipeline: one slot per resident wave of the 64-lane event loop
   DevBuf arena;
-  int32_t resident64 = 0;     // waves of the fused event loop resident at once (seven per SIMD)
+  int32_t resident64 = 0;     // waves of the fused event loop resident at once (six per SIMD)
   std::tuple<int64_t, int64_t, int64_t> fused_key{-1, -1, -1};
   int32_t fused_waves = 0;
   // optional kernel timing of the last call: events around each launch
@@ -327,7 +327,7 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
     return fail(HESP_EHIP, "hesp_plan_create: %s", hipGetErrorString(e));
   }
   p->slots = p->opts.slots ? p->opts.slots : 32 * cus;
-  p->resident64 = std::min(p->slots, 28 * cus);
+  p->resident64 = std::min(p->slots, 24 * cus);
   p->chunk = 1 << 22;   // bounded by device memory below
   e = hipMalloc(&p->counter, sizeof(uint32_t));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->s_prep, hipStreamNonBlocking);
@@ -479,7 +479,7 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
     // batch of this shape and size (the call can be captured in a HIP graph)
     const int64_t cT = plan->opts.max_tasks, cE = plan->opts.max_edges;
     const int64_t cV = ((int64_t)tri2(bv.nt) << (2 * bv.dmax)) * pf->n_mem, cP = tet3(bv.nt) + 1;
-    const int64_t per = 88 * cT + 4 * cE + 8 * cV + 4 * cP + 24 + 4 + 16;
+    const int64_t per = 104 * cT + 4 * cE + 8 * cV + 4 * cP + 24 + 4;
     const auto key = std::make_tuple(n, cV, cP);
     if (plan->fixed_key != key) {
       size_t free_b = 0, total_b = 0;
@@ -516,7 +516,7 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
       mP = std::max(mP, hb[3 * (n_chunks + 1) + i + 1] - hb[3 * (n_chunks + 1) + i]);
     }
     // two workspace sets when chunks overlap
-    const int64_t bytes = (n_chunks > 1 ? 2 : 1) * (88 * mT + 4 * mE + 8 * mV + 4 * mP + 24 * (int64_t)chunk);
+    const int64_t bytes = (n_chunks > 1 ? 2 : 1) * (104 * mT + 4 * mE + 8 * mV + 4 * mP + 24 * (int64_t)chunk);
     if (bytes <= budget || chunk == 1) {
       if (bytes > budget) return fail(HESP_ENOMEM, "hesp_simulate_batch: one candidate needs %lld bytes", (long long)bytes);
       break;
@@ -530,7 +530,7 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
     HIP_TRY(w.indeg.ensure(4 * mT));
     HIP_TRY(w.cur.ensure(4 * mT));
     HIP_TRY(w.succ.ensure(4 * mE));
-    HIP_TRY(w.rec.ensure(16 * (mT + chunk)));
+    HIP_TRY(w.rec.ensure(32 * mT));
     HIP_TRY(w.fifo.ensure(24 * mT));
     HIP_TRY(w.ready.ensure(4 * mT));
     HIP_TRY(w.sortbuf.ensure(32 * mT));

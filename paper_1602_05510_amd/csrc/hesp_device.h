@@ -176,10 +176,44 @@ __device__ __forceinline__ int64_t atom_base(int nt, int dmax, int lvl, int R, i
 }
 
 // ordering key of a ready task: fine indices scaled to the finest level
+__device__ __forceinline__ uint32_t task_key_of(int dmax, int lvl, int K, int I, int J) {
+  const int sh = dmax - lvl;
+  return ((uint32_t)(K << sh) << 18) | ((uint32_t)(I << sh) << 9) | (uint32_t)(J << sh);
+}
 __device__ __forceinline__ uint32_t task_key(uint32_t dsc, int dmax) {
-  const int sh = dmax - desc_level(dsc);
-  return ((uint32_t)(desc_K(dsc) << sh) << 18) | ((uint32_t)(desc_I(dsc) << sh) << 9) |
-         (uint32_t)(desc_J(dsc) << sh);
+  return task_key_of(dmax, desc_level(dsc), desc_K(dsc), desc_I(dsc), desc_J(dsc));
+}
+
+// Dispatch word of a fine task, computed once by the preparation so that the
+// event loop decodes nothing: the first finest block (atom) of each data block
+// the task touches (reads first, the written block last), its level, kind and
+// number of blocks:
+//   atom0:18 | atom1:18 | atom2:18 | level:3 | kind:2 | blocks:2
+// Eighteen bits hold every atom number: a candidate has at most F (F + 2^dmax) / 2
+// finest blocks, F = nt 2^dmax <= kMaxFine.
+static_assert((int64_t)kMaxFine * (kMaxFine + (1 << kMaxLevel)) / 2 <= (1 << 18), "atom numbers need 18 bits");
+static_assert(kMaxLevel < 8, "levels need 3 bits");
+__device__ __forceinline__ uint64_t dispatch_word(int nt, int dmax, int kind, int lvl, int K, int I, int J) {
+  int br[3] = {0, 0, 0}, bc[3] = {0, 0, 0};
+  const int nb = desc_blocks(pack_desc(kind, lvl, K, I, J), br, bc);
+  // atom_base in 32-bit arithmetic (every atom number is below 2^18)
+  const int w_l = 1 << (dmax - lvl), lmask = (1 << lvl) - 1;
+  uint64_t w = 0;
+  for (int b = 0; b < 3; b++) {
+    const int tr = br[b] >> lvl, tc = bc[b] >> lvl;
+    const int tile = tr * nt - ((tr * (tr - 1)) >> 1) + (tc - tr);
+    const int atom = (tile << (2 * dmax)) + (((br[b] & lmask) * w_l) << dmax) + (bc[b] & lmask) * w_l;
+    if (b < nb) w |= (uint64_t)(uint32_t)atom << (18 * b);
+  }
+  return w | ((uint64_t)lvl << 54) | ((uint64_t)kind << 57) | ((uint64_t)nb << 59);
+}
+__device__ __forceinline__ int dw_atom(uint64_t w, int b) { return (int)((w >> (18 * b)) & 0x3FFFFu); }
+__device__ __forceinline__ int dw_level(uint64_t w) { return (int)((w >> 54) & 7u); }
+__device__ __forceinline__ int dw_kind(uint64_t w) { return (int)((w >> 57) & 3u); }
+__device__ __forceinline__ int dw_blocks(uint64_t w) { return (int)((w >> 59) & 3u); }
+// what a completion needs of the task: the written block's atom and the level
+__device__ __forceinline__ uint32_t completion_word(uint64_t w) {
+  return (uint32_t)dw_atom(w, dw_blocks(w) - 1) | ((uint32_t)dw_level(w) << 18);
 }
 
 

@@ -54,7 +54,7 @@ struct ChunkView {
   uint32_t* indeg;                          // per task
   uint32_t* cur;                            // per task
   uint32_t* succ;                           // per edge
-  int64_t* rec;                             // 2 per task + 2 per candidate
+  int64_t* rec;                             // 4 per task
   int64_t* fifo;                            // 3 per task
   uint32_t* ready;                          // per task
   int64_t* sortbuf;                         // 4 per task
@@ -80,7 +80,7 @@ struct ChunkView {
 // bytes of one candidate's block in region mode: T tasks, E edges, V validity
 // words, TP top-level tasks + 1 (16-byte multiple)
 __host__ __device__ inline int64_t region_bytes(int64_t T, int64_t E, int64_t V, int64_t TP) {
-  const int64_t b = 16 * (T + 1) + 24 * T + 32 * T + 8 * V + 16 * T + 4 * E + 4 * TP;
+  const int64_t b = 32 * T + 24 * T + 32 * T + 8 * V + 16 * T + 4 * E + 4 * TP;
   return (b + 15) & ~(int64_t)15;
 }
 

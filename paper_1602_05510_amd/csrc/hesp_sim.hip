@@ -116,15 +116,23 @@ __global__ void k_bounds(const int64_t* off_t, const int64_t* off_e, const int64
 
 // ---------------------------------------------------------------- candidate views
 
+// Task record, four 8-byte words per task (32-byte aligned): the ordering key
+// (low half) and first successor edge (high half), the dispatch word, the
+// critical time (FCFS: minus the release time) and one past the last edge.  The
+// event loop writes only the third word.
+constexpr int kRecKE = 0, kRecW = 1, kRecRank = 2, kRecE1 = 3;
+static_assert(kRecW == kRecKE + 1 && kRecE1 == kRecRank + 1 && kRecKE % 2 == 0 && kRecRank % 2 == 0,
+              "records are read and written as aligned 16-byte pairs");
+
 struct CandPtrs {
   int64_t toff;        // first task of the candidate in the chunk's task arrays
   uint32_t* top_first;
-  uint32_t* desc;
+  uint32_t* desc;      // per task: packed descriptor (preparation only)
   uint32_t* indeg;
   uint32_t* cur;
   uint32_t* succ;
-  int64_t* rec;        // per task: [critical time, descriptor | first edge << 32], plus one closing entry
-  int64_t* fifo;       // per queued task: [finish, id | desc << 32, e0 | e1 << 32] of the task behind it
+  int64_t* rec;        // per task: the record above
+  int64_t* fifo;       // per queued task: [finish, id | completion word << 32, e0 | e1 << 32] of the task behind it
   uint32_t* ready;
   int64_t* sortbuf;
   int64_t* vf;         // [finest block][memory space] valid-from times
@@ -135,7 +143,7 @@ struct CandPtrs {
 __device__ __forceinline__ CandPtrs carve(uint8_t* r, int64_t T, int64_t E, int64_t V) {
   CandPtrs p;
   p.toff = 0;
-  p.rec = (int64_t*)r;        r += 16 * (T + 1);
+  p.rec = (int64_t*)r;        r += 32 * T;
   p.fifo = (int64_t*)r;       r += 24 * T;
   p.sortbuf = (int64_t*)r;    r += 32 * T;
   p.vf = (int64_t*)r;         r += 8 * V;
@@ -168,7 +176,7 @@ __device__ __forceinline__ CandPtrs cand_ptrs(const ChunkView& v, int c) {
   p.indeg = v.indeg + t;
   p.cur = v.cur + t;
   p.succ = v.succ + e;
-  p.rec = v.rec + 2 * (t + (c - v.c0));
+  p.rec = v.rec + 4 * t;
   p.fifo = v.fifo + 3 * t;
   p.ready = v.ready + t;
   p.sortbuf = v.sortbuf + 4 * t;
@@ -222,11 +230,11 @@ __device__ __forceinline__ int prep_owner(const PrepLds& s, uint32_t e) {
   return lo;
 }
 
-// critical times, the closing record, initial validity and the first ready
+// critical times and the task records, initial validity and the first ready
 // list; cur[f] = one past the last edge of f, successor lists filled
 // returns the number of tasks without predecessors (the first ready list)
 __device__ __forceinline__ int prep_finish(int prep_in, const OutView& out, int c, int nt, int dmax, int M,
-                                           const CandPtrs& sp, int64_t n_fine, int64_t n_edges,
+                                           const CandPtrs& sp, int64_t n_fine,
                                            const int64_t (*s_W)[kLevels], PrepLds& s) {
   const int l = lane();
   const int in_cap = prep_in >= 1 && prep_in <= kPrepIn ? prep_in : kPrepIn;
@@ -265,7 +273,7 @@ __device__ __forceinline__ int prep_finish(int prep_in, const OutView& out, int 
         const uint32_t e = eb + q * kWave + l;
         v[q] = e < E1 ? vld(&sp.succ[e]) : kNil;
       }
-      for (int q = 0; q < 4; q++) rv[q] = (v[q] != kNil && v[q] >= lim) ? vld(&sp.rec[2 * v[q]]) : 0;
+      for (int q = 0; q < 4; q++) rv[q] = (v[q] != kNil && v[q] >= lim) ? vld(&sp.rec[4 * v[q] + kRecRank]) : 0;
       for (int q = 0; q < 4; q++) src[q] = v[q] != kNil ? prep_owner(s, eb + q * kWave + l) : 0;
       for (int q = 0; q < 4; q++) {
         if (v[q] != kNil && v[q] >= lim) atomicMax((long long*)&s.ext[src[q]], (long long)rv[q]);
@@ -301,14 +309,18 @@ __device__ __forceinline__ int prep_finish(int prep_in, const OutView& out, int 
       if (!__ballot(changed)) break;
     }
     if (valid) {
-      sp.rec[2 * f] = r;
-      sp.rec[2 * f + 1] = (int64_t)(dsc | ((uint64_t)e0 << 32));
+      // the whole record in two 16-byte stores
+      const int kind = desc_kind(dsc), lvl = desc_level(dsc);
+      const int K = desc_K(dsc), I = desc_I(dsc), J = desc_J(dsc);
+      longlong2 kw, re;
+      kw.x = (long long)(task_key_of(dmax, lvl, K, I, J) | ((uint64_t)e0 << 32));
+      kw.y = (long long)dispatch_word(nt, dmax, kind, lvl, K, I, J);
+      re.x = r;
+      re.y = (long long)e1;
+      *reinterpret_cast<longlong2*>(&sp.rec[4 * f + kRecKE]) = kw;
+      *reinterpret_cast<longlong2*>(&sp.rec[4 * f + kRecRank]) = re;
     }
     __syncthreads();
-  }
-  if (l == 0) {
-    sp.rec[2 * n_fine] = 0;
-    sp.rec[2 * n_fine + 1] = (int64_t)((uint64_t)n_edges << 32);   // end of the last range
   }
 
   // initial validity: data valid on the host (space 0) only
@@ -425,7 +437,7 @@ __device__ __forceinline__ int prepare_cand(const SimTables& tb, const BatchView
   });
   wave_order();
 
-  n_src = prep_finish(prep_in, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_p);
+  n_src = prep_finish(prep_in, out, c, nt, dmax, M, sp, n_fine, s_W, s_p);
   return kOK;
 }
 
@@ -568,7 +580,7 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare_tree(SimTables tb, BatchVi
       if (wr[h] != kNil && pos[h] < n_edges) sp.succ[pos[h]] = f;
   });
   wave_order();
-  const int n_src = prep_finish(cv.prep_in, out, c, nt, dmax, M, sp, n_fine, n_edges, s_W, s_p);
+  const int n_src = prep_finish(cv.prep_in, out, c, nt, dmax, M, sp, n_fine, s_W, s_p);
   if (l == 0) cv.nsrc[c - cv.c0] = n_src;
 }
 
@@ -586,24 +598,20 @@ __device__ __forceinline__ uint64_t choice_draw(uint64_t seed, uint64_t idx) {
   return mix(mix(seed + g * 9ull) + g * (idx + 1));
 }
 
-// Instantiated per policy class so that the default policy carries no policy
-// code: R-P / F-P map tasks only onto idle processors and may make them wait.
-// The whole-wave variant is limited to 72 VGPRs, seven waves per SIMD: the event
-// loop waits on memory between short bursts of issue, and a seventh wave hides
-// more of it than the few spilled registers cost (-15% per launch measured); the
-// 16- and 32-lane variants lose when squeezed and keep their registers.
 // Per-group LDS state of the event loop.
 template <int G, int POL>
 struct SimLds {
   static constexpr int NG = kWave / G;
   int64_t fin[NG][4][kMaxMem];    // per (block, space): latest finite valid-from
   int32_t miss[NG][4][kMaxMem];   // per (block, space): finest blocks missing
+  int64_t rdy[NG][kMaxMem];       // default policy: per space, when the task's data is ready there
   // write-around: per (block, space), the latest host valid-from of the missing
   // finest blocks (their transfer cannot leave before)
   int64_t src[POL == 0 ? 1 : NG][4][kMaxMem];
   uint32_t rid[NG][G];            // ready list, first G entries, with records
   int64_t rrank[NG][G];
-  uint32_t rdesc[NG][G];
+  uint64_t rw[NG][G];             // dispatch words
+  uint32_t rkey[NG][G];
   uint32_t re0[NG][G];
   uint32_t re1[NG][G];
   uint8_t order[NG][G];
@@ -618,15 +626,16 @@ union SimPrepLds {
 
 // Instantiated per policy class so that the default policy carries no policy
 // code: R-P / F-P map tasks only onto idle processors and may make them wait.
-// The whole-wave variant is limited to 72 VGPRs, seven waves per SIMD: the event
-// loop waits on memory between short bursts of issue, and a seventh wave hides
-// more of it than the few spilled registers cost (-15% per launch measured); the
+// The whole-wave variant is limited to 80 VGPRs, six waves per SIMD: the event
+// loop waits on memory and on its own dependent steps, and at six waves it needs
+// no spill code (16x16-tile headline batch, per launch: 275 ms at six waves,
+// 280 at seven with a few spills, 324 at eight, 285 at five and at four); the
 // 16- and 32-lane variants lose when squeezed and keep their registers.
 // FUSED (whole-wave groups only): each wave prepares the candidates it claims
 // itself (prepare_cand) into its own slot of cv.slot_bytes bytes of cv.region,
 // so a batch needs neither the separate preparation launch nor memory chunks.
 template <int G, int POL, bool FUSED>
-__global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
+__global__ void __launch_bounds__(kWave, G == 64 ? 6 : 1) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
                                                uint32_t* counter) {
   static_assert(!FUSED || G == kWave, "the fused preparation needs whole-wave groups");
   // POL 0: Priority-List + EFT-P + write-back (no policy flags read); 1: the
@@ -645,10 +654,12 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
   SimLds<G, POL>& L = reinterpret_cast<SimLds<G, POL>&>(s_l);
   auto& s_fin = L.fin;
   auto& s_miss = L.miss;
+  auto& s_rdy = L.rdy;
   auto& s_src = L.src;
   auto& s_rid = L.rid;
   auto& s_rrank = L.rrank;
-  auto& s_rdesc = L.rdesc;
+  auto& s_rw = L.rw;
+  auto& s_rkey = L.rkey;
   auto& s_re0 = L.re0;
   auto& s_re1 = L.re1;
   auto& s_order = L.order;
@@ -667,23 +678,35 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
   const int ptype = gl < P ? tb.proc_type[gl] : 0;
   const bool want_sched = out.sched_off != nullptr;
 
-  int c = 0, nt = 0, dmax = 0;
+  int c = 0, dmax = 0;
   int64_t xs = 0, T = 0, n_ready = 0, sbase = 0;
   CandPtrs sp{};
   int64_t avail = 0, hfin = kInf;
   int64_t bus_free = 0;                       // shared interconnect: free from this time
-  uint32_t hid = kNil, hdesc = 0, he0 = 0, he1 = 0, tail = kNil;
+  // queue head of processor lane: task, finish, completion word, successor edges
+  uint32_t hid = kNil, hcw = 0, he0 = 0, he1 = 0, tail = kNil;
 
-  auto push = [&](int64_t pos, uint32_t v, int64_t r0, int64_t r1, int64_t r3) {
+  // entry pos of the ready list: task v with its rank, key | e0 << 32, dispatch
+  // word and e1 (the first G entries in LDS, the rest by number only)
+  auto push = [&](int64_t pos, uint32_t v, int64_t rank, int64_t ke, int64_t dw, int64_t e1) {
     if (pos < G) {
       s_rid[g][pos] = v;
-      s_rrank[g][pos] = r0;
-      s_rdesc[g][pos] = (uint32_t)r1;
-      s_re0[g][pos] = (uint32_t)((uint64_t)r1 >> 32);
-      s_re1[g][pos] = (uint32_t)((uint64_t)r3 >> 32);
+      s_rrank[g][pos] = rank;
+      s_rw[g][pos] = (uint64_t)dw;
+      s_rkey[g][pos] = (uint32_t)ke;
+      s_re0[g][pos] = (uint32_t)((uint64_t)ke >> 32);
+      s_re1[g][pos] = (uint32_t)e1;
     } else {
       sp.ready[pos] = v;
     }
+  };
+  // the read-only words of task v's record: key | e0 << 32 and the dispatch word
+  // in one 16-byte load, e1
+  auto rec_ro = [&](uint32_t v, int64_t& ke, int64_t& dw, int64_t& e1) {
+    const longlong2 kw = *reinterpret_cast<const longlong2*>(&sp.rec[4 * v + kRecKE]);
+    ke = kw.x;
+    dw = kw.y;
+    e1 = sp.rec[4 * v + kRecE1];
   };
 
   if constexpr (!FUSED) {
@@ -701,7 +724,6 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
           c = cv.c0 + (cv.order ? (int)cv.order[cc] : cc);
           if (out.status[c] == kOK) {
             const Cand cd = load_cand(bv, c);
-            nt = cd.nt;
             dmax = cd.dmax;
             xs = (int64_t)1 << (2 * (tb.max_level - dmax));
             sp = cand_ptrs(cv, c);
@@ -716,8 +738,12 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
             // FCFS keeps minus the release time in the rank slot (sources: 0)
             for (int64_t x = gl; x < (fcfs || n_ready < G ? n_ready : G); x += G) {
               const uint32_t v = vld(&sp.ready[x]);
-              if (fcfs) sp.rec[2 * v] = 0;
-              if (x < G) push(x, v, fcfs ? 0 : vld(&sp.rec[2 * v]), vld(&sp.rec[2 * v + 1]), vld(&sp.rec[2 * v + 3]));
+              if (fcfs) sp.rec[4 * v + kRecRank] = 0;
+              if (x < G) {
+                int64_t ke, dw, e1;
+                rec_ro(v, ke, dw, e1);
+                push(x, v, fcfs ? 0 : vld(&sp.rec[4 * v + kRecRank]), ke, dw, e1);
+              }
             }
             active = true;
           }
@@ -755,7 +781,6 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
         const bool ok = prepare_cand(tb, bv, out, c, sp, Tq, Eq, cap, cv.prep_in, s_W, s_l.prep, n_src) == kOK;
         __syncthreads();   // the preparation's LDS is the event loop's from here
         if (!ok) continue;
-        nt = cq.nt;
         dmax = cq.dmax;
         n_ready = n_src;
       }
@@ -769,8 +794,12 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 7 : 1) k_sim(SimTables tb, Ba
       tail = kNil;
       for (int64_t x = gl; x < (fcfs || n_ready < G ? n_ready : G); x += G) {
         const uint32_t v = vld(&sp.ready[x]);
-        if (fcfs) sp.rec[2 * v] = 0;
-        if (x < G) push(x, v, fcfs ? 0 : vld(&sp.rec[2 * v]), vld(&sp.rec[2 * v + 1]), vld(&sp.rec[2 * v + 3]));
+        if (fcfs) sp.rec[4 * v + kRecRank] = 0;
+        if (x < G) {
+          int64_t ke, dw, e1;
+          rec_ro(v, ke, dw, e1);
+          push(x, v, fcfs ? 0 : vld(&sp.rec[4 * v + kRecRank]), ke, dw, e1);
+        }
       }
       for (;;) {
         wave_order();

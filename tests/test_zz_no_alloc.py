@@ -96,7 +96,7 @@ def test_noalloc_capacity_limit(H, torch):
     E = cnt_e.cpu().numpy().astype(np.int64)
     V = (w.nt * (w.nt + 1) // 2) * 4 ** w.dmax * pf_in.n_mem
     TP = I.tet(w.nt) + 1
-    rb = (88 * T + 16 + 4 * E + 8 * V + 4 * TP + 15) // 16 * 16
+    rb = (104 * T + 4 * E + 8 * V + 4 * TP + 15) // 16 * 16
     fits = np.cumsum(rb) <= H.NOALLOC_REGION
     assert fits[0] and not fits[-1], "the case must straddle the limit"
     want, got = _both(H, torch, pf, db)
