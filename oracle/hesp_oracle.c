@@ -32,7 +32,14 @@
  *      processor that becomes idle first), R-P (random) or F-P (fastest) --
  *      the last two among the processors idle at that time; a task finding no
  *      idle processor waits for the next completion; optionally every transfer
- *      shares one interconnect (one at a time, in issue order).
+ *      shares one interconnect (one at a time, in issue order);
+ *   6. optionally, finite accelerator memory spaces (section 2, problem input:
+ *      "finite-size memory spaces"; the spaces cache the host): a space holds
+ *      at most its capacity of finest blocks, a task may go only to a processor
+ *      whose space can hold the blocks of the tasks mapped there and not yet
+ *      finished plus its own, and blocks are evicted least recently used first,
+ *      a block with no valid host copy being copied back to the host first
+ *      (readings marked "reading (capacity)" below).
  * Where the paper is silent (tie-breaks, simultaneous events, transfer issue
  * time, coherence granularity) the readings are those listed in the design
  * notes of this repository; each is marked "reading:" below.
@@ -100,6 +107,8 @@ typedef struct {
     uint64_t seed;           /* R-P draws */
     int cache;               /* policy: 0 = write-back, 1 = write-through, 2 = write-around */
     int bus;                 /* 1: transfers share one interconnect, one at a time */
+    const int64_t *capacity; /* [n_mem] bytes each accelerator space holds, or NULL;
+                                <= 0 (and always for the host, space 0): unbounded */
 } or_platform;
 
 /* SplitMix64 (Steele, Lea, Flood 2014): value number idx+1 of the sequence
@@ -431,6 +440,30 @@ static int make_tables(const or_platform *pf, int dmax, or_tables *tb)
 
 static void free_tables(or_tables *tb) { free(tb->cost); free(tb->xfer); }
 
+/* 6. finite accelerator spaces.
+ * reading (capacity): the capacity of space m counts whole finest blocks of the
+ * candidate, floor(bytes / (elem_bytes (b / 2^dmax)^2)); the host is unbounded.
+ * A finest block takes a place in space m while it has a copy there, valid now
+ * or arriving.  Among blocks used equally recently the one with the smaller
+ * number goes first: tiles of the upper triangle row by row, then row-major
+ * inside a tile. */
+static int64_t atom_number(int nt, int dmax, int row, int col)
+{
+    int tr = row >> dmax, tc = col >> dmax, mask = (1 << dmax) - 1;
+    int64_t tile = (int64_t)tr * nt - (int64_t)tr * (tr - 1) / 2 + (tc - tr);
+    return (tile << (2 * dmax)) + ((int64_t)(row & mask) << dmax) + (col & mask);
+}
+
+/* does finest block (row, col) belong to one of the task's blocks? */
+static int task_has_atom(const or_task *t, int dmax, int row, int col)
+{
+    int br[3], bc[3], bw[3];
+    int nb = task_blocks(t, br, bc, bw), sh = dmax - t->level;
+    for (int bi = 0; bi < nb; bi++)
+        if ((row >> sh) == br[bi] && (col >> sh) == bc[bi]) return 1;
+    return 0;
+}
+
 /* ready-set order: larger `rank` first, then smaller scaled (K,I,J).  For the
  * Priority-List order `rank` is the critical time; for FCFS it is minus the
  * release time (earlier releases first). */
@@ -508,6 +541,8 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
     or_tables tb = {0, 0, 0, 0};
     int rc;
     int64_t *W = 0, *rank = 0, *start = 0, *finish = 0, *avail = 0, *vf = 0;
+    int64_t *cap = 0, *use = 0;
+    int *pin = 0;
     int *proc = 0, *left = 0, *fifo = 0, *fifo_head = 0, *fifo_tail = 0, *fifo_next = 0;
     or_heap heap = {0, 0};
     memset(&g, 0, sizeof(g));
@@ -541,8 +576,21 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
     fifo_tail = (int *)malloc((size_t)P * sizeof(int));
     vf = (int64_t *)malloc((size_t)N * N * M * sizeof(int64_t));
     heap.v = (or_hent *)malloc((size_t)n * sizeof(or_hent));
+    cap = (int64_t *)malloc((size_t)M * sizeof(int64_t));
+    use = (int64_t *)calloc((size_t)N * N * M, sizeof(int64_t));
+    pin = (int *)calloc((size_t)N * N * M, sizeof(int));
     if (!W || !rank || !start || !finish || !proc || !left || !fifo_next || !avail ||
-        !fifo_head || !fifo_tail || !vf || !heap.v) { rc = OR_ENOMEM; goto done; }
+        !fifo_head || !fifo_tail || !vf || !heap.v || !cap || !use || !pin) { rc = OR_ENOMEM; goto done; }
+
+    /* 6. capacities in finest blocks (-1: unbounded); supported with write-back
+     * caching, EFT-P and independent transfers */
+    int capped = 0;
+    int64_t atom_bytes = pf->elem_bytes * (pf->b >> dmax) * (pf->b >> dmax);
+    for (int m = 0; m < M; m++) {
+        cap[m] = (m > 0 && pf->capacity && pf->capacity[m] > 0) ? pf->capacity[m] / atom_bytes : -1;
+        if (cap[m] >= 0) capped = 1;
+    }
+    if (capped && (pf->cache != 0 || pf->select != 0 || pf->bus != 0)) { rc = OR_EINVAL; goto done; }
 
     /* 4. critical times: sum of the task's time over all processors, then the
      * longest such path to an exit, tasks visited in reverse program order
@@ -582,7 +630,8 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                 for (int p = 0; p < P; p++) n_idle += avail[p] <= T;
                 if (n_idle == 0) break;          /* every processor busy: wait */
             }
-            int t = heap_pop(&heap).task;
+            or_hent top = heap_pop(&heap);
+            int t = top.task;
             int br[3], bc[3], bw[3];
             int nb = task_blocks(&tl.v[t], br, bc, bw);
             int sh = dmax - tl.v[t].level, w = 1 << sh;
@@ -608,6 +657,16 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             for (int p = 0; p < P; p++) {
                 if (pick >= 0 && p != pick) continue;
                 int m = pf->proc_mem[p];
+                if (cap[m] >= 0) {
+                    /* reading (capacity): the space must hold the blocks used by the
+                     * tasks mapped there and not finished (pinned) plus this task's */
+                    int64_t places = 0;
+                    for (int r = 0; r < N; r++) for (int c = 0; c < N; c++) {
+                        int64_t a = (int64_t)r * N + c;
+                        if (pin[a * M + m] > 0 || task_has_atom(&tl.v[t], dmax, r, c)) places++;
+                    }
+                    if (places > cap[m]) continue;
+                }
                 int64_t est = T > avail[p] ? T : avail[p];
                 int64_t bus_at = bus_free;       /* where this mapping's transfers would queue */
                 for (int bi = 0; bi < nb; bi++) {
@@ -634,8 +693,39 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                 int64_t sel = pf->select ? (T > avail[p] ? T : avail[p]) : eft;
                 if (best_p < 0 || sel < best_sel) { best_p = p; best_sel = sel; best_eft = eft; best_est = est; }
             }
+            if (best_p < 0) {
+                /* reading (capacity): no space can take the task now; it and the
+                 * tasks after it wait for the next completion */
+                heap_push(&heap, top);
+                break;
+            }
             /* commit: transfers of the missing atoms are issued now, at time T */
             int m = pf->proc_mem[best_p];
+            if (cap[m] >= 0) {
+                /* make room: evict the unpinned blocks of m that the task does not
+                 * use, least recently used first; reading (capacity): a block
+                 * without a host copy is first copied back to the host, one transfer
+                 * per finest block, issued now */
+                int64_t occ = 0, need = 0;
+                for (int r = 0; r < N; r++) for (int c = 0; c < N; c++) {
+                    int64_t a = (int64_t)r * N + c;
+                    if (vf[a * M + m] != OR_INF) occ++;
+                    else if (task_has_atom(&tl.v[t], dmax, r, c)) need++;
+                }
+                for (int64_t k = occ + need - cap[m]; k > 0; k--) {
+                    int64_t va = -1, vu = 0, vn = 0;
+                    for (int r = 0; r < N; r++) for (int c = 0; c < N; c++) {
+                        int64_t a = (int64_t)r * N + c;
+                        if (vf[a * M + m] == OR_INF || pin[a * M + m] > 0 || task_has_atom(&tl.v[t], dmax, r, c))
+                            continue;
+                        int64_t u = use[a * M + m], num = atom_number(nt, dmax, r, c);
+                        if (va < 0 || u < vu || (u == vu && num < vn)) { va = a; vu = u; vn = num; }
+                    }
+                    if (va < 0) { rc = OR_EINVAL; goto done; }   /* excluded by the check above */
+                    if (vf[va * M + 0] == OR_INF) vf[va * M + 0] = T + tb.xfer[1];
+                    vf[va * M + m] = OR_INF;
+                }
+            }
             for (int bi = 0; bi < nb; bi++) {
                 int64_t miss = 0;
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
@@ -653,6 +743,13 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                     if (vf[a * M + m] == OR_INF) vf[a * M + m] = go + tb.xfer[miss];
                 }
             }
+            /* the task's blocks in m: used now, pinned until it finishes */
+            for (int bi = 0; bi < nb; bi++)
+                for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
+                    int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                    use[a * M + m] = T;
+                    pin[a * M + m]++;
+                }
             proc[t] = best_p; start[t] = best_est; finish[t] = best_eft;
             avail[best_p] = best_eft;
             fifo_next[t] = -1;
@@ -663,7 +760,10 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
         int64_t Tn = OR_INF;
         for (int p = 0; p < P; p++)
             if (fifo_head[p] >= 0 && finish[fifo_head[p]] < Tn) Tn = finish[fifo_head[p]];
-        if (Tn == OR_INF) break;
+        if (Tn == OR_INF) {
+            if (heap.n) { rc = OR_ECAP; goto done; }   /* nothing left to wait for */
+            break;
+        }
         /* (iii) all completions at Tn, before any mapping at Tn (reading) */
         for (int p = 0; p < P; p++) {
             int t = fifo_head[p];
@@ -682,6 +782,9 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             int br[3], bc[3], bw[3];
             int nb = task_blocks(&tl.v[t], br, bc, bw);
             int sh = dmax - tl.v[t].level, w = 1 << sh, m = pf->proc_mem[p];
+            for (int bi = 0; bi < nb; bi++)
+                for (int u = 0; u < w; u++) for (int v = 0; v < w; v++)
+                    pin[((int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v)) * M + m]--;
             int64_t host_at = (m == 0) ? Tn : Tn + tb.xfer[(int64_t)w * w];
             if (pf->bus && pf->cache != 0 && m != 0) {     /* the host copy queues on the interconnect */
                 int64_t go = Tn > bus_free ? Tn : bus_free;
@@ -744,6 +847,7 @@ done:
     free(tl.v); dag_free(&g); free_tables(&tb);
     free(W); free(rank); free(start); free(finish); free(proc); free(left); free(fifo_next);
     free(avail); free(fifo_head); free(fifo_tail); free(vf); free(heap.v); free(fifo);
+    free(cap); free(use); free(pin);
     return rc;
 }
 
@@ -758,7 +862,7 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
                     int32_t max_tasks, int32_t *task_info, int32_t *proc_out,
                     int64_t *start_out, int64_t *finish_out, int64_t *rank_out,
                     int64_t max_edges, int32_t *edges_out, int order, int select, uint64_t seed,
-                    int cache, int tree, int bus)
+                    int cache, int tree, int bus, const int64_t *capacity)
 {
     if (!depth || n_procs < 1 || !proc_type || !proc_mem || n_mem < 1 || !rmax || !h) return OR_EINVAL;
     if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2 || bus < 0 || bus > 1)
@@ -767,7 +871,7 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
         if (proc_type[p] < 0 || proc_type[p] >= n_ptypes || proc_mem[p] < 0 || proc_mem[p] >= n_mem)
             return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus};
+                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus, capacity};
     or_outputs o = {max_tasks, task_info, proc_out, start_out, finish_out, rank_out, max_edges, edges_out};
     or_result r;
     int rc = simulate_one(&pf, nt, dmax, depth, tree, &r, &o);
@@ -816,13 +920,14 @@ int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
                           int n_ptypes, const int64_t *rmax, const int64_t *h, int64_t b,
                           int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
                           int n_threads, int64_t *makespan, int32_t *n_tasks, int32_t *status,
-                          int order, int select, uint64_t seed, int cache, int tree, int bus)
+                          int order, int select, uint64_t seed, int cache, int tree, int bus,
+                          const int64_t *capacity)
 {
     if (n_cand < 0 || !nt || !dmax || !mask_off || !depth || !makespan || n_threads < 1) return OR_EINVAL;
     if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2 || bus < 0 || bus > 1)
         return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus};
+                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus, capacity};
     or_batch_job j;
     j.pf = &pf; j.n_cand = n_cand; j.nt = nt; j.dmax = dmax; j.mask_off = mask_off; j.depth = depth;
     j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.tree = tree; j.next = 0;

@@ -58,10 +58,10 @@ def lib(native: bool = False):
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         L.oracle_simulate.argtypes = [i32, i32, P, i32, P, P, i32, i32, P, P, i64, i64, i64, i64, i32,
-                                      P, P, P, i32, P, P, P, P, P, i64, P, i32, i32, ctypes.c_uint64, i32, i32, i32]
+                                      P, P, P, i32, P, P, P, P, P, i64, P, i32, i32, ctypes.c_uint64, i32, i32, i32, P]
         L.oracle_simulate.restype = i32
         L.oracle_simulate_batch.argtypes = [i32, P, P, P, P, i32, P, P, i32, i32, P, P, i64, i64, i64,
-                                            i64, i32, i32, P, P, P, i32, i32, ctypes.c_uint64, i32, i32, i32]
+                                            i64, i32, i32, P, P, P, i32, i32, ctypes.c_uint64, i32, i32, i32, P]
         L.oracle_simulate_batch.restype = i32
         L.oracle_task_time.argtypes = [i32, i64, i64, i64, P]
         L.oracle_task_time.restype = i32
@@ -110,7 +110,7 @@ class Schedule:
 
 
 def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = True, policy=(0, 0),
-             tree: bool = False):
+             tree: bool = False, capacity=None):
     """Simulate one candidate; returns a Schedule (detail) or the makespan.
 
     depth: split depth per top-level task, or with tree=True the split flags of
@@ -121,9 +121,14 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     1 = FCFS; select 0 = EFT-P, 1 = EIT-P, 2 = R-P, 3 = F-P (section 2.1, "Task
     and data scheduling heuristics"); seed feeds the R-P draws; cache 0 =
     write-back, 1 = write-through, 2 = write-around; bus 1 = every transfer
-    shares one interconnect."""
+    shares one interconnect.
+
+    capacity: None or bytes per memory space ([n_mem]; <= 0 and the host's
+    entry mean unbounded): finite accelerator spaces with least-recently-used
+    eviction (write-back, EFT-P, independent transfers only)."""
     order, select, seed, cache, bus = (tuple(policy) + (0, 0, 0))[:5]
     L = lib()
+    cap = None if capacity is None else np.ascontiguousarray(capacity, dtype=np.int64)
     depth = np.ascontiguousarray(depth, dtype=np.uint8)
     ptype = np.ascontiguousarray(pf.proc_type, dtype=np.int32)
     pmem = np.ascontiguousarray(pf.proc_mem, dtype=np.int32)
@@ -135,7 +140,8 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     args_pf = (pf.n_procs, _p(ptype), _p(pmem), pf.n_mem, pf.n_ptypes, _p(rmax), _p(h), b,
                pf.latency_ns, pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory))
     rc = L.oracle_simulate(nt, dmax, _p(depth), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
-                           0, None, None, None, None, None, 0, None, order, select, seed, cache, int(tree), bus)
+                           0, None, None, None, None, None, 0, None, order, select, seed, cache, int(tree), bus,
+                           _p(cap))
     if rc:
         raise ValueError(f"oracle_simulate rc={rc}")
     if not detail:
@@ -149,17 +155,21 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     edges = np.zeros((max(m, 1), 2), np.int32)
     rc = L.oracle_simulate(nt, dmax, _p(depth), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
                            n, _p(tasks), _p(proc), _p(start), _p(finish), _p(rank), m, _p(edges), order, select,
-                           seed, cache, int(tree), bus)
+                           seed, cache, int(tree), bus, _p(cap))
     if rc:
         raise ValueError(f"oracle_simulate rc={rc}")
     return Schedule(int(ms[0]), tasks, proc, start, finish, rank, edges[:m])
 
 
-def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = False, native: bool = False):
-    """Makespans (int64) and expanded task counts of a whole batch (policy and
-    tree as in simulate; with tree=True batch.depth holds split flags and
-    batch.mask_off their offsets; native selects the -march=native build)."""
+def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = False, native: bool = False,
+                   capacity=None, statuses: bool = False):
+    """Makespans (int64) and expanded task counts of a whole batch (policy,
+    tree and capacity as in simulate; with tree=True batch.depth holds split
+    flags and batch.mask_off their offsets; native selects the -march=native
+    build).  statuses=True returns (makespans, counts, statuses) instead of
+    raising on a candidate that fails (-4: no space can hold a task)."""
     order, select, seed, cache, bus = (tuple(policy) + (0, 0, 0))[:5]
+    cap = None if capacity is None else np.ascontiguousarray(capacity, dtype=np.int64)
     L = lib(native)
     n = batch.n
     ms = np.zeros(n, np.int64)
@@ -176,9 +186,11 @@ def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = Fa
     rc = L.oracle_simulate_batch(n, _p(nt), _p(dm), _p(off), _p(dep), pf.n_procs, _p(ptype), _p(pmem),
                                  pf.n_mem, pf.n_ptypes, _p(rmax), _p(h), batch.b, pf.latency_ns,
                                  pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory), n_threads,
-                                 _p(ms), _p(ntk), _p(st), order, select, seed, cache, int(tree), bus)
+                                 _p(ms), _p(ntk), _p(st), order, select, seed, cache, int(tree), bus, _p(cap))
     if rc:
         raise ValueError(f"oracle_simulate_batch rc={rc}")
+    if statuses:
+        return ms, ntk, st
     if np.any(st != 0):
         bad = int(np.nonzero(st)[0][0])
         raise ValueError(f"oracle failed on candidate {bad} rc={int(st[bad])}")

@@ -169,6 +169,7 @@ class Sim:
     def __init__(self, nt, dmax, b, depth, proc_type, proc_mem, n_mem, rmax, h, shared, tree=False):
         self.tasks = expand_tree(nt, dmax, depth) if tree else expand(nt, depth)
         self.E = edges(self.tasks, dmax)
+        self.nt = nt
         self.n = len(self.tasks)
         self.dmax, self.b = dmax, b
         self.P = len(proc_type)
@@ -232,14 +233,34 @@ class Sim:
             e = max(e, r)
         return e
 
-    def run(self, choose_task=None, choose_proc=None, order="PL", select="EFT", seed=0, cache="WB", bus=False):
+    def task_atoms(self, t):
+        return [a for (R, C, _) in blocks(self.tasks[t]) for a in atoms(R, C, self.tasks[t][1], self.dmax)]
+
+    def lru_order(self, a):
+        """Tie order among equally recently used finest blocks: upper-triangle
+        tiles row by row, then row-major inside the tile."""
+        w = 1 << self.dmax
+        tr, tc = a[0] // w, a[1] // w
+        tile = sum(self.nt - r for r in range(tr)) + (tc - tr)
+        return (tile, (a[0] % w) * w + a[1] % w)
+
+    def run(self, choose_task=None, choose_proc=None, order="PL", select="EFT", seed=0, cache="WB", bus=False,
+            capacity=None):
         """order: "PL" (decreasing critical time) or "FCFS" (first released first);
         select: "EFT" (earliest finish), "EIT" (processor idle first), "RP"
         (random idle processor) or "FP" (fastest idle processor); with RP / FP a
         task that finds no idle processor waits for a completion.  Ties: smaller
         scaled (K, I, J), then lower processor index.  cache: "WB" (the written
         block stays only where it was computed), "WT" (also sent to the host at
-        completion) or "WA" (sent to the host, not kept by an accelerator)."""
+        completion) or "WA" (sent to the host, not kept by an accelerator).
+        capacity: bytes per memory space (None or <= 0: unbounded; the host
+        always is): a space holds at most that many whole finest blocks; a task
+        goes only to a processor whose space can hold the blocks of its own and of
+        the tasks mapped there and not finished; when none can, it and the tasks
+        after it wait for the next completion; room is made by dropping the least
+        recently used other blocks (ties by lru_order), a block with no host copy
+        being copied back first (one transfer per finest block).  Returns None
+        when a task can never be taken."""
         from paper_1602_05510_amd.inputs import draw
         N = 0
         vf = {}
@@ -255,6 +276,11 @@ class Sim:
         proc, start, finish = [None] * self.n, [None] * self.n, [None] * self.n
         T = 0
         bus_free = 0
+        slots = [None] * self.n_mem             # finest blocks per space, None = unbounded
+        if capacity is not None:
+            per = 8 * self.atom_side * self.atom_side
+            slots = [None if (m == 0 or capacity[m] <= 0) else capacity[m] // per for m in range(self.n_mem)]
+        pins, last_use = {}, {}
         while True:
             while ready:
                 idle = [q for q in range(self.P) if avail[q] <= T]
@@ -269,6 +295,14 @@ class Sim:
                 ready.remove(t)
                 ests = [self.est(t, p, T, avail, vf, bus_free if bus else None) for p in range(self.P)]
                 efts = [ests[p] + self.cost[t][p] for p in range(self.P)]
+                mine = set(self.task_atoms(t))
+
+                def fits(q):
+                    m = self.proc_mem[q]
+                    if slots[m] is None:
+                        return True
+                    held = {a for (a, mm), c in pins.items() if mm == m and c > 0}
+                    return len(held | mine) <= slots[m]
                 if choose_proc:
                     p = choose_proc(t, efts, self)
                 elif select == "EIT":
@@ -281,8 +315,23 @@ class Sim:
                 elif select == "FP":
                     p = min(idle, key=lambda q: (self.cost[t][q], q))
                 else:
-                    p = min(range(self.P), key=lambda q: (efts[q], q))
+                    ok = [q for q in range(self.P) if fits(q)]
+                    if not ok:
+                        ready.append(t)          # waits, and so do the tasks after it
+                        break
+                    p = min(ok, key=lambda q: (efts[q], q))
                 m = self.proc_mem[p]
+                if slots[m] is not None:
+                    held = [a for a in vf if vf[a][m] != INF]
+                    missing = [a for a in mine if vf[a][m] == INF]
+                    extra = len(held) + len(missing) - slots[m]
+                    if extra > 0:
+                        free = [a for a in held if pins.get((a, m), 0) == 0 and a not in mine]
+                        free.sort(key=lambda a: (last_use.get((a, m), 0), self.lru_order(a)))
+                        for a in free[:extra]:
+                            if vf[a][0] == INF:
+                                vf[a][0] = T + self.xfer(1)
+                            vf[a][m] = INF
                 arr, after = self.transfers(t, m, T, vf, bus_free if bus else None)
                 if bus:
                     bus_free = after
@@ -290,17 +339,24 @@ class Sim:
                     for a in atoms(R, C, self.tasks[t][1], self.dmax):
                         if vf[a][m] == INF:
                             vf[a][m] = x
+                for a in mine:
+                    last_use[(a, m)] = T
+                    pins[(a, m)] = pins.get((a, m), 0) + 1
                 proc[t], start[t], finish[t] = p, ests[p], efts[p]
                 avail[p] = efts[p]
                 fifo[p].append(t)
             heads = [finish[f[0]] for f in fifo if f]
             if not heads:
+                if ready:
+                    return None
                 break
             Tn = min(heads)
             for p in range(self.P):
                 if fifo[p] and finish[fifo[p][0]] == Tn:
                     t = fifo[p].pop(0)
                     m = self.proc_mem[p]
+                    for a in self.task_atoms(t):
+                        pins[(a, m)] -= 1
                     for (R, C, w) in blocks(self.tasks[t]):
                         if w:
                             at = atoms(R, C, self.tasks[t][1], self.dmax)

@@ -67,6 +67,14 @@ MUTANTS = {
     "trsm_split_without_gemm": ("            for (int J = I + 1; J < js + s; J++)\n                if (in_range(J, js, s))\n                    if (tl_push(l, (or_task){OR_GEMM",
                                 "            for (int J = I + 1; J < js + s && is != ks; J++)\n                if (in_range(J, js, s))\n                    if (tl_push(l, (or_task){OR_GEMM"),
     "gemm_flops_wrong": ("static const int64_t c[4] = {1, 3, 3, 6};", "static const int64_t c[4] = {1, 3, 3, 3};"),
+    "evict_most_recent": ("if (va < 0 || u < vu || (u == vu && num < vn))", "if (va < 0 || u > vu || (u == vu && num < vn))"),
+    "evict_ties_to_last_block": ("if (va < 0 || u < vu || (u == vu && num < vn))",
+                                 "if (va < 0 || u < vu || (u == vu && num > vn))"),
+    "evict_without_copy_back": ("if (vf[va * M + 0] == OR_INF) vf[va * M + 0] = T + tb.xfer[1];",
+                                "if (0) vf[va * M + 0] = T + tb.xfer[1];"),
+    "capacity_ignores_pins": ("if (pin[a * M + m] > 0 || task_has_atom(&tl.v[t], dmax, r, c)) places++;",
+                              "if (task_has_atom(&tl.v[t], dmax, r, c)) places++;"),
+    "use_not_refreshed": ("                    use[a * M + m] = T;\n", "                    use[a * M + m] += 0;\n"),
 }
 # Not listed: ordering FCFS releases latest first is an equivalent mutant -- the
 # ready set is emptied at every instant, so it never holds two release times.
@@ -99,12 +107,15 @@ def _pins_pass():
         ex = ex + json.load(f)["examples"]
     with open(os.path.join(GOLD, "bus_examples.json")) as f:
         ex = ex + json.load(f)["examples"]
+    with open(os.path.join(GOLD, "capacity_examples.json")) as f:
+        ex = ex + json.load(f)["examples"]
     try:
         for e in ex:
             pts = [I.ProcType(n, c, r, r, h, own) for (n, c, r, h, own) in e["platform"]["types"]]
             pf = I.make_platform(pts, seed=0)
+            cap = np.array(e["capacity_bytes"], np.int64) if "capacity_bytes" in e else None
             s = O.simulate(pf, e["nt"], e["dmax"], e["b"], np.array(e["depth"], np.uint8),
-                           policy=tuple(e.get("policy", (0, 0))))
+                           policy=tuple(e.get("policy", (0, 0))), capacity=cap)
             if s.makespan != e["makespan"]:
                 return False
             got = {tuple(int(x) for x in s.tasks[t]): (int(s.proc[t]), int(s.start[t]), int(s.finish[t]))
@@ -150,6 +161,15 @@ def _pins_pass():
             py = PY.Sim(3, 1, 256, dep4, pf4.proc_type, pf4.proc_mem, pf4.n_mem, pf4.rmax, pf4.h, pf4.shared_memory)
             if py.run(cache="WA", bus=True)[2] != list(r.start):
                 return False
+        # finite accelerator space against the independent Python reading (a case
+        # where the recency of use decides which block goes)
+        pf5 = I.make_platform([I.ProcType("acc", 1, 1024000, 1024000, 512, True)], seed=0)
+        dep5 = np.array([0, 0, 0, 0, 0, 0, 1, 0, 0, 0], np.uint8)
+        cap5 = np.array([0, 12 * 8 * 256 * 256], np.int64)
+        r = O.simulate(pf5, 3, 1, 512, dep5, capacity=cap5)
+        py = PY.Sim(3, 1, 512, dep5, pf5.proc_type, pf5.proc_mem, pf5.n_mem, pf5.rmax, pf5.h, pf5.shared_memory)
+        if py.run(capacity=list(cap5))[2] != list(r.start):
+            return False
         # split trees: the hand-derived partial split (seven tasks on three levels)
         fl = np.array([1, 1, 0, 0, 0], np.uint8)
         st = O.simulate(pf1b, 1, 2, 512, fl, tree=True)
