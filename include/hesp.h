@@ -86,7 +86,23 @@ int hesp_cost_tables(const hesp_cost_model *cm, int64_t *cost_ns, int64_t *xfer_
  * Processor p has type proc_type[p] and works in memory space proc_mem[p];
  * space 0 is the host, where all data starts; every other space caches host
  * data (write-back).  The processor order is the EFT tie-break order (lowest
- * index wins).  All pointers are host pointers. */
+ * index wins).  All pointers are host pointers.
+ * Finite spaces (section 2: memory spaces of finite size): capacity[m] > 0
+ * bounds accelerator space m to that many blocks of side b / 2^max_level; a
+ * candidate of depth dmax counts whole finest blocks of side b / 2^dmax, so it
+ * holds capacity[m] / 4^(max_level - dmax) of them.  A task goes only to a
+ * processor whose space can hold the finest blocks of the tasks mapped there and
+ * not finished plus its own (EFT-P among those); when none can, it and the
+ * tasks after it in the order wait for the next completion, and a task that no
+ * space can ever hold gives HESP_ECAPACITY.  Room is made when the task is
+ * mapped by dropping the least recently used other blocks of the space (use =
+ * the latest mapping there of a task touching the block; ties: upper-triangle
+ * tiles row by row, then row-major inside the tile); a dropped block with no
+ * copy on the host is copied back first, one transfer of one finest block
+ * issued at that time.  Supported with write-back caching, EFT-P, independent
+ * transfers, depth batches and the unfused pipeline (else HESP_EUNSUPPORTED);
+ * 64 lanes per candidate.  capacity NULL, capacity[m] <= 0 and space 0:
+ * unbounded. */
 typedef struct {
   int32_t n_procs;             /* 1..HESP_MAX_PROCS */
   int32_t n_ptypes;            /* 1..HESP_MAX_PTYPES */
@@ -96,6 +112,7 @@ typedef struct {
   const int32_t *proc_mem;     /* [n_procs] */
   const int64_t *cost_ns;      /* [n_ptypes][4][max_level+1], >= 1 */
   const int64_t *xfer_ns;      /* [4^max_level + 1], xfer_ns[0] = 0, non-decreasing */
+  const int64_t *capacity;     /* [n_mem] or NULL: blocks of side b/2^max_level per space (above) */
 } hesp_platform;
 
 /* Heuristics of section 2.1 ("Task and data scheduling heuristics").  Tasks are

@@ -75,13 +75,15 @@ struct DevBuf {
 
 // Workspace of one chunk of candidates.
 struct WorkSet {
-  DevBuf top_first, desc, indeg, cur, succ, rec, fifo, ready, sortbuf, vf, nsrc, order_keys, order;
+  DevBuf top_first, desc, indeg, cur, succ, rec, fifo, ready, sortbuf, vf, use, pin, nsrc, order_keys, order;
   std::vector<DevBuf*> all() {
-    return {&top_first, &desc, &indeg, &cur, &succ, &rec, &fifo, &ready, &sortbuf, &vf, &nsrc, &order_keys, &order};
+    return {&top_first, &desc, &indeg, &cur, &succ, &rec, &fifo, &ready, &sortbuf, &vf, &use, &pin, &nsrc,
+            &order_keys, &order};
   }
   int64_t bytes() const {
     return top_first.bytes + desc.bytes + indeg.bytes + cur.bytes + succ.bytes + rec.bytes + fifo.bytes +
-           ready.bytes + sortbuf.bytes + vf.bytes + nsrc.bytes + order_keys.bytes + order.bytes;
+           ready.bytes + sortbuf.bytes + vf.bytes + use.bytes + pin.bytes + nsrc.bytes + order_keys.bytes +
+           order.bytes;
   }
 };
 
@@ -419,6 +421,10 @@ static int build_tables(const hesp_platform* pf, SimTables& t) {
       return fail(HESP_EINVAL, "hesp_simulate_batch: xfer_ns must be non-decreasing and in range");
     t.xfer[k] = pf->xfer_ns[k];
   }
+  for (int m = 0; m < kMaxMem; m++) {
+    t.capacity[m] = (m > 0 && m < pf->n_mem && pf->capacity && pf->capacity[m] > 0) ? pf->capacity[m] : -1;
+    if (t.capacity[m] >= 0) t.capped = 1;
+  }
   return HESP_OK;
 }
 
@@ -441,6 +447,9 @@ int hesp_internal_batch_setup(const hesp_platform* pf, hesp_policy policy, const
   tb.seed = policy.seed;
   tb.cache = policy.cache;
   tb.bus = policy.bus;
+  if (tb.capped && (tree || policy.cache != HESP_CACHE_WB || policy.select != HESP_SELECT_EFT || policy.bus))
+    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: finite memory spaces take depth batches, write-back "
+                                   "caching, EFT-P and independent transfers");
   if (int r = tree ? tree_view(tree, bv, "hesp_simulate_tree_batch") : batch_view(batch, bv, "hesp_simulate_batch"))
     return r;
   if (bv.dmax > pf->max_level) return fail(HESP_EINVAL, "hesp_simulate_batch: dmax above the platform's max_level");
@@ -479,7 +488,7 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
     // batch of this shape and size (the call can be captured in a HIP graph)
     const int64_t cT = plan->opts.max_tasks, cE = plan->opts.max_edges;
     const int64_t cV = ((int64_t)tri2(bv.nt) << (2 * bv.dmax)) * pf->n_mem, cP = tet3(bv.nt) + 1;
-    const int64_t per = 104 * cT + 4 * cE + 8 * cV + 4 * cP + 24 + 4;
+    const int64_t per = 104 * cT + 4 * cE + (tb.capped ? 20 : 8) * cV + 4 * cP + 24 + 4;
     const auto key = std::make_tuple(n, cV, cP);
     if (plan->fixed_key != key) {
       size_t free_b = 0, total_b = 0;
@@ -516,7 +525,8 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
       mP = std::max(mP, hb[3 * (n_chunks + 1) + i + 1] - hb[3 * (n_chunks + 1) + i]);
     }
     // two workspace sets when chunks overlap
-    const int64_t bytes = (n_chunks > 1 ? 2 : 1) * (104 * mT + 4 * mE + 8 * mV + 4 * mP + 24 * (int64_t)chunk);
+    const int64_t bytes =
+        (n_chunks > 1 ? 2 : 1) * (104 * mT + 4 * mE + (tb.capped ? 20 : 8) * mV + 4 * mP + 24 * (int64_t)chunk);
     if (bytes <= budget || chunk == 1) {
       if (bytes > budget) return fail(HESP_ENOMEM, "hesp_simulate_batch: one candidate needs %lld bytes", (long long)bytes);
       break;
@@ -535,6 +545,10 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
     HIP_TRY(w.ready.ensure(4 * mT));
     HIP_TRY(w.sortbuf.ensure(32 * mT));
     HIP_TRY(w.vf.ensure(8 * mV));
+    if (tb.capped) {
+      HIP_TRY(w.use.ensure(8 * mV));
+      HIP_TRY(w.pin.ensure(4 * mV));
+    }
     HIP_TRY(w.nsrc.ensure(4 * (int64_t)chunk));
     HIP_TRY(w.order_keys.ensure(8 * srch::sort_len(chunk)));
     HIP_TRY(w.order.ensure(4 * (int64_t)chunk));
@@ -562,6 +576,8 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
     cv.ready = w.ready.as<uint32_t>();
     cv.sortbuf = w.sortbuf.as<int64_t>();
     cv.vf = w.vf.as<int64_t>();
+    cv.use = tb.capped ? w.use.as<int64_t>() : nullptr;
+    cv.pin = tb.capped ? w.pin.as<uint32_t>() : nullptr;
     cv.nsrc = w.nsrc.as<int32_t>();
     cv.cnt_tasks = plan->cnt_tasks.as<int32_t>();
     cv.cnt_edges = plan->cnt_edges.as<int64_t>();
@@ -572,6 +588,12 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
   // lanes per candidate: forced by the plan, or timed once per batch shape on a
   // sub-batch of the first chunk (outputs of that sub-batch are rewritten below)
   int group = plan->opts.group;
+  if (tb.capped) {
+    // finite spaces: the event loop keeps its per-space state in whole-wave groups
+    if (group != 0 && group != 64)
+      return fail(HESP_EINVAL, "hesp_simulate_batch: finite memory spaces take 64 lanes per candidate");
+    group = 64;
+  }
   if (group == 0) {
     const auto key = std::make_tuple(pf->n_procs, pf->n_mem, bv.nt, bv.dmax, (bv.nt_arr ? 1 : 0) | (is_tree ? 2 : 0));
     auto it = plan->tuned.find(key);
@@ -776,6 +798,7 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   // separate preparation and simulation launches per memory chunk
   if (plan->opts.fuse) {
     if (is_tree) return fail(HESP_EUNSUPPORTED, "hesp_simulate_tree_batch: the fused pipeline takes depth batches");
+    if (tb.capped) return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: the fused pipeline has no finite spaces");
     if (pf->n_procs > 64) return fail(HESP_EINVAL, "hesp_simulate_batch: more than 64 processors");
     return run_fused(plan, tb, bv, ov, s, n);
   }

@@ -27,6 +27,8 @@ struct SimTables {
   uint64_t seed;                          // random choices (SplitMix64)
   int32_t cache;                          // written blocks: 0 write-back, 1 write-through, 2 write-around
   int32_t bus;                            // 1: transfers share one interconnect, one at a time
+  int32_t capped;                         // 1: some space has a finite capacity
+  int64_t capacity[kMaxMem];              // blocks of side b/2^max_level; -1: unbounded
 };
 
 struct BatchView {
@@ -59,6 +61,8 @@ struct ChunkView {
   uint32_t* ready;                          // per task
   int64_t* sortbuf;                         // 4 per task
   int64_t* vf;                              // finest blocks x memory spaces
+  int64_t* use;                             // finite spaces: latest use per validity word (else null)
+  uint32_t* pin;                            // finite spaces: unfinished tasks using it (else null)
   int32_t* nsrc;                            // per candidate of the chunk
   const uint32_t* order;                    // nullable: simulation order of the chunk's candidates
   const int32_t* cnt_tasks;                 // per candidate of the batch: expanded tasks

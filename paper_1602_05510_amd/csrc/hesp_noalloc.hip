@@ -91,6 +91,7 @@ extern "C" int hesp_simulate_batch_noalloc(const hesp_platform* pf, hesp_policy 
   SimTables tb;
   BatchView bv;
   if (int r = hesp_internal_batch_setup(pf, policy, batch, nullptr, out, tb, bv)) return r;
+  if (tb.capped) return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch_noalloc: no finite memory spaces");
   if (group == 0) group = tb.n_procs <= 16 ? 16 : (tb.n_procs <= 32 ? 32 : 64);
   if (group < tb.n_procs) return fail(HESP_EINVAL, "hesp_simulate_batch_noalloc: group below the processor count");
   const int n = bv.n_cand;

@@ -136,6 +136,8 @@ struct CandPtrs {
   uint32_t* ready;
   int64_t* sortbuf;
   int64_t* vf;         // [finest block][memory space] valid-from times
+  int64_t* use;        // finite spaces: [finest block][space] latest mapping there of a task using it
+  uint32_t* pin;       // finite spaces: [finest block][space] mapped tasks there not yet finished
 };
 
 // a candidate's arrays one after the other in one block of region_bytes(T, E, V, TP)
@@ -143,6 +145,8 @@ struct CandPtrs {
 __device__ __forceinline__ CandPtrs carve(uint8_t* r, int64_t T, int64_t E, int64_t V) {
   CandPtrs p;
   p.toff = 0;
+  p.use = nullptr;            // region mode has no finite spaces
+  p.pin = nullptr;
   p.rec = (int64_t*)r;        r += 32 * T;
   p.fifo = (int64_t*)r;       r += 24 * T;
   p.sortbuf = (int64_t*)r;    r += 32 * T;
@@ -181,6 +185,8 @@ __device__ __forceinline__ CandPtrs cand_ptrs(const ChunkView& v, int c) {
   p.ready = v.ready + t;
   p.sortbuf = v.sortbuf + 4 * t;
   p.vf = v.vf + f;
+  p.use = v.use ? v.use + f : nullptr;
+  p.pin = v.pin ? v.pin + f : nullptr;
   return p;
 }
 
@@ -330,6 +336,10 @@ __device__ __forceinline__ int prep_finish(int prep_in, const OutView& out, int 
     int m = l % M;
     for (int64_t e = l; e < n_vf; e += kWave) {
       sp.vf[e] = m == 0 ? 0 : kInf;
+      if (sp.pin) {
+        sp.pin[e] = 0u;
+        sp.use[e] = 0;
+      }
       m += step;
       m = m >= M ? m - M : m;
     }
@@ -608,6 +618,13 @@ struct SimLds {
   // write-around: per (block, space), the latest host valid-from of the missing
   // finest blocks (their transfer cannot leave before)
   int64_t src[POL == 0 ? 1 : NG][4][kMaxMem];
+  // finite spaces (POL 3): per (block, space) the task's finest blocks pinned by no
+  // other task; per space the candidate's capacity in finest blocks (-1:
+  // unbounded), the finest blocks held and those pinned
+  int32_t npin[POL == 3 ? NG : 1][4][kMaxMem];
+  int64_t capm[POL == 3 ? NG : 1][kMaxMem];
+  int32_t occ[POL == 3 ? NG : 1][kMaxMem];
+  int32_t pinned[POL == 3 ? NG : 1][kMaxMem];
   uint32_t rid[NG][G];            // ready list, first G entries, with records
   int64_t rrank[NG][G];
   uint64_t rw[NG][G];             // dispatch words
@@ -639,12 +656,15 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 6 : 1) k_sim(SimTables tb, Ba
                                                uint32_t* counter) {
   static_assert(!FUSED || G == kWave, "the fused preparation needs whole-wave groups");
   // POL 0: Priority-List + EFT-P + write-back (no policy flags read); 1: the
-  // other push policies (FCFS, EIT-P) and caching policies; 2: R-P / F-P
+  // other push policies (FCFS, EIT-P) and caching policies; 2: R-P / F-P; 3:
+  // finite memory spaces (PL or FCFS, EFT-P, write-back, independent transfers)
   constexpr bool PULL = POL == 2;
+  constexpr bool CAP = POL == 3;
+  static_assert(!CAP || (G == kWave && !FUSED), "finite spaces run in whole-wave groups, unfused");
   const bool fcfs = POL != 0 && tb.fcfs;
-  const int sel = POL == 0 ? 0 : tb.sel;
-  const int cache = POL == 0 ? 0 : tb.cache;
-  const bool bus = POL != 0 && tb.bus != 0;
+  const int sel = (POL == 0 || CAP) ? 0 : tb.sel;
+  const int cache = (POL == 0 || CAP) ? 0 : tb.cache;
+  const bool bus = POL != 0 && !CAP && tb.bus != 0;
   constexpr int LGG = G == 16 ? 4 : (G == 32 ? 5 : 6);
   __shared__ int64_t s_cost[kMaxPtypes][4][kLevels];
   __shared__ int64_t s_xfer[kXferLen];
@@ -656,6 +676,10 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 6 : 1) k_sim(SimTables tb, Ba
   auto& s_miss = L.miss;
   auto& s_rdy = L.rdy;
   auto& s_src = L.src;
+  auto& s_npin = L.npin;
+  auto& s_capm = L.capm;
+  auto& s_occ = L.occ;
+  auto& s_pinned = L.pinned;
   auto& s_rid = L.rid;
   auto& s_rrank = L.rrank;
   auto& s_rw = L.rw;
@@ -680,6 +704,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 6 : 1) k_sim(SimTables tb, Ba
 
   int c = 0, dmax = 0;
   int64_t xs = 0, T = 0, n_ready = 0, sbase = 0;
+  int64_t n_atoms = 0;                        // finite spaces: the candidate's finest blocks
   CandPtrs sp{};
   int64_t avail = 0, hfin = kInf;
   int64_t bus_free = 0;                       // shared interconnect: free from this time
@@ -734,6 +759,15 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 6 : 1) k_sim(SimTables tb, Ba
             hfin = kInf;
             hid = kNil;
             tail = kNil;
+            if constexpr (CAP) {
+              n_atoms = (int64_t)tri2(cd.nt) << (2 * dmax);
+              if (gl < M) {
+                const int64_t cb = tb.capacity[gl];
+                s_capm[g][gl] = cb >= 0 ? cb >> (2 * (tb.max_level - dmax)) : -1;
+                s_occ[g][gl] = 0;
+                s_pinned[g][gl] = 0;
+              }
+            }
             n_ready = cv.nsrc[c - cv.c0];
             // FCFS keeps minus the release time in the rank slot (sources: 0)
             for (int64_t x = gl; x < (fcfs || n_ready < G ? n_ready : G); x += G) {
@@ -864,7 +898,8 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
   const int per_wave = kWave / G;
   int waves = (v.nc + per_wave - 1) / per_wave;
   if (waves > slots) waves = slots;
-  const int pol = t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs || t.cache != 0 || t.bus != 0 ? 1 : 0);
+  const int pol = t.capped ? 3 : (t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs || t.cache != 0 || t.bus != 0 ? 1 : 0));
+  if (pol == 3 && (fused || G != 64 || !v.use || !v.pin)) return hipErrorInvalidValue;
   const dim3 grid(waves), block(kWave);
 #define HESP_SIM_LAUNCH(GG, PP, FF) hipLaunchKernelGGL((k_sim<GG, PP, FF>), grid, block, 0, s, t, b, v, o, counter)
   if (fused) {
@@ -882,7 +917,8 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
   } else {
     if (pol == 0) HESP_SIM_LAUNCH(64, 0, false);
     else if (pol == 1) HESP_SIM_LAUNCH(64, 1, false);
-    else HESP_SIM_LAUNCH(64, 2, false);
+    else if (pol == 2) HESP_SIM_LAUNCH(64, 2, false);
+    else HESP_SIM_LAUNCH(64, 3, false);
   }
 #undef HESP_SIM_LAUNCH
   return hipGetLastError();
