@@ -109,7 +109,8 @@ def host_cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float, policy=(0, 0, 0, 0), tree: bool = False):
+def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float, policy=(0, 0, 0, 0), tree: bool = False,
+                 capacity=None):
     """The oracle, as it stands, built -O2 -march=native on this host, on its
     cores: the whole timed batch when it fits the time budget (else its first
     candidates), plus a single-thread rate on a smaller prefix."""
@@ -120,19 +121,20 @@ def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float, policy=(0, 0,
     # calibrate the sample size with a small probe
     probe = batch_host.subset(range(min(64, batch_host.n)))
     t0 = time.perf_counter()
-    O.simulate_batch(pf, probe, cores, policy=policy, tree=tree, native=True)
+    O.simulate_batch(pf, probe, cores, policy=policy, tree=tree, native=True, capacity=capacity)
     dt = max(time.perf_counter() - t0, 1e-3)
     per_cand = dt / probe.n
     n = int(min(batch_host.n, max(probe.n, budget_s / per_cand)))
     sample = batch_host.subset(range(n))
     t0 = time.perf_counter()
-    ms, ntk = O.simulate_batch(pf, sample, cores, policy=policy, tree=tree, native=True)
+    ms, ntk = O.simulate_batch(pf, sample, cores, policy=policy, tree=tree, native=True, capacity=capacity)
     dt = time.perf_counter() - t0
     exact = bool(np.array_equal(ms, gpu_makespan[:n]))
     # one thread, about a tenth of the budget
     n1 = int(min(n, max(16, 0.1 * budget_s / (per_cand * cores))))
     t0 = time.perf_counter()
-    _, ntk1 = O.simulate_batch(pf, batch_host.subset(range(n1)), 1, policy=policy, tree=tree, native=True)
+    _, ntk1 = O.simulate_batch(pf, batch_host.subset(range(n1)), 1, policy=policy, tree=tree, native=True,
+                               capacity=capacity)
     dt1 = time.perf_counter() - t0
     what = "the whole timed batch of step 0" if n == batch_host.n else f"the first {n} candidates of the timed batch of step 0"
     return {"value": float(ntk.sum()) / dt, "unit": "tasks/s", "cores": cores, "kind": "oracle",
@@ -619,6 +621,8 @@ def main():
                     help="order 0 PL / 1 FCFS, select 0 EFT-P / 1 EIT-P / 2 R-P / 3 F-P, cache 0 WB / 1 WT / 2 WA")
     ap.add_argument("--policy-seed", type=int, default=0)
     ap.add_argument("--bus", action="store_true", help="every transfer shares one interconnect")
+    ap.add_argument("--capacity-blocks", type=int, default=0,
+                    help="finite accelerator spaces: finest blocks each one holds (0: unbounded)")
     ap.add_argument("--tree", action="store_true",
                     help="split-tree candidates (every task split on its own) of the same shape")
     ap.add_argument("--solve-chains", type=int, default=16384)
@@ -651,7 +655,12 @@ def main():
     w = I.WORKLOADS[args.workload]
     n = args.n_cand or w.n_cand
     pf_in = w.platform()
-    pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
+    cap_bytes = None
+    if args.capacity_blocks > 0:
+        # every accelerator space holds that many finest blocks (side b / 2^dmax)
+        cap_bytes = np.zeros(pf_in.n_mem, np.int64)
+        cap_bytes[1:] = args.capacity_blocks * pf_in.elem_bytes * (w.b >> w.dmax) ** 2
+    pf = H.Platform.from_inputs(pf_in, w.b, w.dmax, capacity_bytes=cap_bytes)
     thr = I.split_threshold(w.p_num, w.p_den)
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream()
@@ -732,7 +741,7 @@ def main():
             with open(pmc_path) as f:
                 pmc = json.load(f)
             if (pmc.get("kernel_sha") == kernel_hash() and pmc.get("n_cand") == n and tuple(args.policy) == (0, 0, 0)
-                    and not bus):
+                    and not bus and not args.capacity_blocks):
                 traffic = pmc.get("hbm_bytes_per_launch")
         traffic_note = None if traffic is not None else "no counter run on this kernel source"
         # issue rate of the same kernel source: instructions per simulated task and
@@ -742,7 +751,7 @@ def main():
             with open(sq_path) as f:
                 sq = json.load(f)
             if (sq.get("kernel_sha") == kernel_hash() and sq.get("n_cand") == n and tuple(args.policy) == (0, 0, 0)
-                    and not bus):
+                    and not bus and not args.capacity_blocks):
                 issue = {k: sq[k] for k in ("valu_insts_per_task", "salu_insts_per_task", "insts_per_task",
                                             "valu_busy", "salu_busy", "wave_wait_frac", "source")}
 
@@ -751,7 +760,8 @@ def main():
              ["WB", "WT", "WA"][cache] + ("/shared interconnect" if bus else ""))
     rec = {
         "metric": ("simulated tasks/sec (bit-exact PL/EFT-P makespans)" if pname == "PL/EFT-P/WB" else
-                   f"simulated tasks/sec (bit-exact {pname} makespans)") + (", split-tree candidates" if args.tree else ""),
+                   f"simulated tasks/sec (bit-exact {pname} makespans)") + (", split-tree candidates" if args.tree else "")
+                  + (f", accelerator spaces of {args.capacity_blocks} finest blocks" if args.capacity_blocks else ""),
         "value": value,
         "unit": "tasks/s",
         "n_gpus": 1,
@@ -769,7 +779,8 @@ def main():
                    "dmax": f"0..{w.ragged['dmax_hi']}" if w.ragged else w.dmax,
                    "split_prob": f"{w.p_num}/{w.p_den}",
                    "platform": " + ".join(f"{t.count} {t.name}" for t in w.ptypes),
-                   "policy": pname, "parallelism": "none (1 GPU)"},
+                   "policy": pname, "capacity_blocks": args.capacity_blocks or None,
+                   "parallelism": "none (1 GPU)"},
         "candidates_per_s": n * args.steps / elapsed,
         "tasks_per_step": tasks_total / args.steps,
         "roofline": {"bound": "hbm", "kernel": "k_sim", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -791,7 +802,8 @@ def main():
         sim(db)
         torch.cuda.synchronize()
         rec["cpu_baseline"] = cpu_baseline(w, pf_in, host0, ms.cpu().numpy(), args.cpu_budget,
-                                           policy=(order, select, args.policy_seed, cache, bus), tree=args.tree)
+                                           policy=(order, select, args.policy_seed, cache, bus), tree=args.tree,
+                                           capacity=cap_bytes)
         rec["gpu_vs_cpu"] = value / rec["cpu_baseline"]["value"]
     if args.copy_calib:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
