@@ -23,6 +23,11 @@ hipError_t sort(uint64_t* keys, int64_t n2, hipStream_t s);
 hipError_t size_order(const int32_t* n_tasks, int32_t c0, int32_t nc, uint64_t* keys, uint32_t* order, hipStream_t s);
 hipError_t key_index(const uint64_t* keys, int32_t k, uint64_t mask, int32_t* idx, hipStream_t s);
 hipError_t gather_rows(const int32_t* idx, int32_t k, const uint8_t* src, int32_t n_top, uint8_t* out, hipStream_t s);
+// rows r < n with status[r] == 0 (features x, kdim values each, and makespan ms)
+// appended to the ring buffer (rep_x, rep_ms) of `ring` rows at position pos, in
+// row order; count[0] = rows appended (one workgroup)
+hipError_t append_ok(const int32_t* status, const uint16_t* x, const int64_t* ms, int64_t n, int32_t kdim,
+                     uint16_t* rep_x, int64_t* rep_ms, int64_t ring, int64_t pos, int64_t* count, hipStream_t s);
 hipError_t gather_pool(const uint64_t* keys, int32_t k, const uint8_t* pool_d, const int64_t* pool_ms, int32_t pool_n,
                        const uint8_t* bat_d, const int64_t* bat_ms, int32_t n_top, uint8_t* out_d, int64_t* out_ms,
                        hipStream_t s);

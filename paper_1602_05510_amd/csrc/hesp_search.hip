@@ -193,7 +193,43 @@ __global__ void k_gather_pool(const uint64_t* __restrict__ keys, int32_t k, cons
   }
 }
 
+// the successfully simulated rows of a round, in row order, into the replay ring
+__global__ void __launch_bounds__(1024) k_append_ok(const int32_t* __restrict__ status,
+                                                    const uint16_t* __restrict__ x, const int64_t* __restrict__ ms,
+                                                    int64_t n, int32_t kdim, uint16_t* __restrict__ rep_x,
+                                                    int64_t* __restrict__ rep_ms, int64_t ring, int64_t pos,
+                                                    int64_t* __restrict__ count) {
+  __shared__ int s_scan[1024];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += 1024) {
+    const int64_t r = base + threadIdx.x;
+    const int ok = (r < n && status[r] == 0) ? 1 : 0;
+    s_scan[threadIdx.x] = ok;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {           // inclusive scan (Hillis-Steele)
+      const int v = threadIdx.x >= o ? s_scan[threadIdx.x - o] : 0;
+      __syncthreads();
+      s_scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (ok) {
+      const int64_t dst = (pos + carry + s_scan[threadIdx.x] - 1) % ring;
+      for (int f = 0; f < kdim; f++) rep_x[dst * kdim + f] = x[r * kdim + f];
+      rep_ms[dst] = ms[r];
+    }
+    carry += s_scan[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[0] = carry;
+}
+
 }  // namespace
+
+hipError_t append_ok(const int32_t* status, const uint16_t* x, const int64_t* ms, int64_t n, int32_t kdim,
+                     uint16_t* rep_x, int64_t* rep_ms, int64_t ring, int64_t pos, int64_t* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_append_ok, dim3(1), dim3(1024), 0, s, status, x, ms, n, kdim, rep_x, rep_ms, ring, pos, count);
+  return hipGetLastError();
+}
 
 int64_t sort_len(int64_t n) {
   int64_t n2 = kLocal;

@@ -174,10 +174,10 @@ int hesp_search(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, co
   const bool raw = n_top + n_rate <= mlp::kInDim;
   if (sur) {
     if (!sp->mlp || sp->proposals < sp->batch || sp->train_batch < 512 || sp->train_batch % 512 ||
-        sp->replay < sp->train_batch || sp->train_steps < 0 || !(sp->lr > 0.f) || n_rate < 0 ||
-        (n_rate > 0 && !sp->d_rate))
+        sp->replay < sp->train_batch || sp->replay < std::max(sp->batch, sp->warm_batch) || sp->train_steps < 0 ||
+        !(sp->lr > 0.f) || n_rate < 0 || (n_rate > 0 && !sp->d_rate))
       return fail(HESP_EINVAL, "hesp_search: surrogate mode needs mlp, proposals >= batch, train_batch a multiple "
-                               "of 512 and replay >= train_batch");
+                               "of 512 and replay >= train_batch, batch and warm_batch");
     if (!raw && n_rate > mlp::kInDim - mlp::kAggFeatures)
       return fail(HESP_EINVAL, "hesp_search: at most %d rate features", mlp::kInDim - mlp::kAggFeatures);
     if (sp->proposals > (1 << 24) || (int64_t)sp->pool + sp->batch > (1 << 24))
@@ -198,7 +198,8 @@ int hesp_search(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, co
   int64_t *ms = nullptr, *pool_ms[2] = {nullptr, nullptr}, *rep_ms = nullptr;
   int32_t *st = nullptr, *idx = nullptr;
   uint64_t* keys = nullptr;
-  uint16_t *xp = nullptr, *rep_x = nullptr;
+  uint16_t *xp = nullptr, *rep_x = nullptr, *round_x = nullptr;
+  int64_t* d_count = nullptr;
   float *yp = nullptr, *rep_t = nullptr;
   const int64_t n2 = srch::sort_len(std::max<int64_t>((int64_t)sp->pool + maxb, sur ? sp->proposals : 0));
   HIP_TRY(sc.get(&cand, (int64_t)gen_n * n_top));
@@ -217,6 +218,8 @@ int hesp_search(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, co
     HIP_TRY(sc.get(&rep_x, sp->replay * mlp::kInDim));
     HIP_TRY(sc.get(&rep_ms, sp->replay));
     HIP_TRY(sc.get(&rep_t, sp->replay));
+    HIP_TRY(sc.get(&round_x, (int64_t)maxb * mlp::kInDim));
+    HIP_TRY(sc.get(&d_count, 1));
     if (!raw) {
       const std::vector<uint8_t> info = top_info(nt);
       HIP_TRY(sc.get(&d_info, n_top));
@@ -274,16 +277,17 @@ int hesp_search(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, co
                               pool_d[cur ^ 1], pool_ms[cur ^ 1], s));
     cur ^= 1;
     pool_n = new_n;
-    // online training of the surrogate on every exact result so far (ring buffer)
+    // online training of the surrogate on every exact result so far (ring
+    // buffer); a candidate whose simulation failed (a status other than
+    // HESP_OK, e.g. a task no finite space can hold) has no makespan and is left out
     if (sur) {
-      for (int64_t done = 0; done < B;) {
-        const int64_t k = std::min<int64_t>(B - done, sp->replay - rep_pos);
-        HIP_TRY(featurize(sim + done * n_top, k, rep_x + rep_pos * mlp::kInDim));
-        HIP_TRY(hipMemcpyAsync(rep_ms + rep_pos, ms + done, 8 * k, hipMemcpyDeviceToDevice, s));
-        rep_pos = (rep_pos + k) % sp->replay;
-        filled = std::min<int64_t>(sp->replay, filled + k);
-        done += k;
-      }
+      HIP_TRY(featurize(sim, B, round_x));
+      HIP_TRY(srch::append_ok(st, round_x, ms, B, mlp::kInDim, rep_x, rep_ms, sp->replay, rep_pos, d_count, s));
+      int64_t k = 0;
+      HIP_TRY(hipMemcpyAsync(&k, d_count, 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      rep_pos = (rep_pos + k) % sp->replay;
+      filled = std::min<int64_t>(sp->replay, filled + k);
       if (r == sp->warm_rounds - 1) {
         // target normalisation from the warm-up rounds' makespans
         std::vector<int64_t> h((size_t)filled);

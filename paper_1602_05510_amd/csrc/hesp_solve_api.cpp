@@ -96,10 +96,20 @@ static int solve_setup(hesp_plan* plan, const hesp_platform* pf, const hesp_solv
 }
 
 
+// the solver's partition stage reads every task's schedule, which a candidate
+// failing on a finite memory space does not have
+static bool finite_spaces(const hesp_platform* pf) {
+  if (!pf || !pf->capacity) return false;
+  for (int m = 1; m < pf->n_mem; m++)
+    if (pf->capacity[m] > 0) return true;
+  return false;
+}
+
 int hesp_solve(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_solve_params* sp,
                uint8_t* d_depth, uint8_t* d_best_depth, int64_t* d_best_makespan, int64_t* d_trace,
                int64_t* d_steps, void* stream) {
   if (!sp) return fail(HESP_EINVAL, "hesp_solve: null parameters");
+  if (finite_spaces(pf)) return fail(HESP_EUNSUPPORTED, "hesp_solve: finite memory spaces are not supported");
   const int B = sp->n_chains, nt = sp->nt, dmax = sp->dmax;
   const int64_t n_top = nt >= 1 ? tet3(nt) : 0;
   solve::SolveTables tb;

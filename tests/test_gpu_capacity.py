@@ -148,3 +148,26 @@ def test_capacity_unsupported_combinations(H, torch):
         H.simulate_batch(H.Plan(group=16), pf, db, ms, st)
     with pytest.raises(RuntimeError, match="finite memory spaces"):
         H.simulate_batch_noalloc(pf, db, ms, st)
+
+
+def test_search_with_candidates_that_fail(H, torch):
+    """Surrogate-guided search on an accelerator-only platform where most random
+    partitions cannot run (a task larger than every space): the failed candidates
+    neither become incumbents nor training rows; the best is a valid partition
+    whose makespan the oracle reproduces."""
+    pf_in = I.make_platform([I.ProcType("acc", 2, 500_000, 2_000_000, 512, True)], seed=3)
+    b, dmax, nt = 512, 1, 3
+    cap = _cap_bytes(pf_in, b, dmax, 8)
+    pf = H.Platform.from_inputs(pf_in, b, dmax, capacity_bytes=cap)
+    m = H.MLP(1)
+    print("capacity: surrogate search with failing candidates", flush=True)
+    best_d, best, trace = H.search(H.Plan(), pf, nt, dmax, H.SEARCH_SURROGATE, rounds=4, batch=512, seed=11,
+                                   warm_batch=1024, proposals=2048, pool=16, split_thr=I.split_threshold(3, 10),
+                                   mutate_thr=int(0.2 * (1 << 21)), mlp=m, train_steps=20, train_batch=512,
+                                   replay=4096)
+    assert best > 0 and all(t["best_makespan"] > 0 for t in trace)
+    assert O.simulate(pf_in, nt, dmax, b, best_d, detail=False, capacity=cap) == best
+    # plain random search gives the same kind of answer
+    best_d2, best2, _ = H.search(H.Plan(), pf, nt, dmax, H.SEARCH_RANDOM, rounds=2, batch=512, seed=12,
+                                 split_thr=I.split_threshold(3, 10))
+    assert best2 > 0 and O.simulate(pf_in, nt, dmax, b, best_d2, detail=False, capacity=cap) == best2
