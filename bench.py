@@ -592,8 +592,9 @@ def main():
     ap.add_argument("--workload", default="chol16x16_b1024_d2")
     ap.add_argument("--n-cand", type=int, default=0)
     ap.add_argument("--group", type=int, default=0, help="lanes per candidate (0 = autotuned)")
-    ap.add_argument("--fuse", action="store_true",
-                    help="fused pipeline: the 64-lane event loop prepares each candidate itself (one launch per batch)")
+    ap.add_argument("--fuse", type=int, nargs="?", const=1, default=0, choices=[0, 1, 2],
+                    help="fused pipeline: the 64-lane event loop prepares each candidate itself (one launch per "
+                         "batch); 2: with each candidate's workspace in LDS")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--train-platforms", type=int, default=64)

@@ -219,7 +219,10 @@ typedef struct {
                                   0 or 64): every wave of the persistent event loop prepares the candidates it
                                   takes into its own workspace slot, so a batch of any size and unevenness is
                                   one launch holding (resident waves x largest candidate) bytes; slower than
-                                  the default separate preparation launch per memory chunk */
+                                  the default separate preparation launch per memory chunk.  2: the same with
+                                  each slot in the workgroup's LDS (no device workspace at all): candidates
+                                  whose workspace (104 T + 4 E + 8 V + 4 (tet(nt) + 1) bytes, T tasks, E
+                                  edges, V finest blocks x memory spaces) exceeds 48 KiB get HESP_ECAPACITY */
 } hesp_plan_opts;
 /* A plan with max_tasks, max_edges and group all set is a fixed-capacity plan:
  * its workspace follows from the capacities and the batch shape, so after one

@@ -93,7 +93,7 @@ struct hesp_plan {
   int32_t chunk = 0;          // candidates per chunk
   uint32_t* counter = nullptr;
   // per batch
-  DevBuf cnt_tasks, cnt_edges, off_t, off_e, off_v, off_top, bounds;
+  DevBuf cnt_tasks, cnt_edges, off_t, off_e, off_v, off_top, bounds, layout_part;
   DevBuf tree_lw;             // split-tree counts: last writer per finest block and candidate
   // per chunk, two sets: chunk i+1 is prepared while chunk i is simulated
   WorkSet ws[2];
@@ -116,10 +116,11 @@ struct hesp_plan {
   size_t ev_used = 0;
   int64_t held() const {
     return cnt_tasks.bytes + cnt_edges.bytes + off_t.bytes + off_e.bytes + off_v.bytes + off_top.bytes +
-           bounds.bytes + tree_lw.bytes + arena.bytes + ws[0].bytes() + ws[1].bytes();
+           bounds.bytes + layout_part.bytes + tree_lw.bytes + arena.bytes + ws[0].bytes() + ws[1].bytes();
   }
   void release() {
-    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds, &tree_lw, &arena}) b->release();
+    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds, &layout_part, &tree_lw, &arena})
+      b->release();
     for (WorkSet& w : ws)
       for (DevBuf* d : w.all()) d->release();
   }
@@ -317,7 +318,7 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
   if (opts) p->opts = *opts;
   if (p->opts.slots < 0 || p->opts.max_tasks < 0 || p->opts.max_edges < 0 || p->opts.chunks < 0 ||
       (p->opts.group != 0 && p->opts.group != 16 && p->opts.group != 32 && p->opts.group != 64) ||
-      p->opts.prep_edges < 0 || p->opts.prep_edges > 1024 || p->opts.fuse < 0 || p->opts.fuse > 1 || (p->opts.fuse && p->opts.group != 0 && p->opts.group != 64)) {
+      p->opts.prep_edges < 0 || p->opts.prep_edges > 1024 || p->opts.fuse < 0 || p->opts.fuse > 2 || (p->opts.fuse && p->opts.group != 0 && p->opts.group != 64)) {
     delete p;
     return fail(HESP_EINVAL, "hesp_plan_create: negative option");
   }
@@ -471,10 +472,11 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
   auto prepare = [&](const ChunkView& cv, hipStream_t st) {
     return is_tree ? launch_prepare_tree(tb, bv, cv, ov, st) : launch_prepare(tb, bv, cv, ov, st);
   };
+  HIP_TRY(plan->layout_part.ensure(8 * 5 * (((int64_t)n + 1023) / 1024)));
   HIP_TRY(launch_layout(bv, pf->n_mem, plan->cnt_tasks.as<int32_t>(), plan->cnt_edges.as<int64_t>(),
                         plan->opts.max_tasks, plan->opts.max_edges, plan->off_t.as<int64_t>(),
                         plan->off_e.as<int64_t>(), plan->off_v.as<int64_t>(), plan->off_top.as<int64_t>(), nullptr,
-                        s));
+                        s, plan->layout_part.as<int64_t>()));
 
   // chunk boundaries: the largest chunk must fit the memory budget
   const bool fixed = plan->opts.max_tasks > 0 && plan->opts.max_edges > 0 && plan->opts.group > 0;
@@ -720,6 +722,10 @@ static int run_fused(hesp_plan* plan, const SimTables& tb, BatchView bv, const O
     slot = mx;
   }
   slot = std::max<int64_t>(256, (slot + 255) & ~(int64_t)255);
+  const bool in_lds = plan->opts.fuse == 2;
+  // LDS slots: candidates whose workspace exceeds the largest slot get HESP_ECAPACITY
+  if (in_lds) slot = std::min<int64_t>(slot, kLdsSlotMax);
+  if (in_lds) waves = std::min<int32_t>(n, plan->resident64);
   if (waves == 0) {
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
@@ -733,7 +739,7 @@ static int run_fused(hesp_plan* plan, const SimTables& tb, BatchView bv, const O
       plan->fused_waves = waves;
     }
   }
-  HIP_TRY(plan->arena.ensure((int64_t)waves * slot));
+  if (!in_lds) HIP_TRY(plan->arena.ensure((int64_t)waves * slot));
   WorkSet& w = plan->ws[0];
   HIP_TRY(w.order_keys.ensure(8 * srch::sort_len(n)));
   HIP_TRY(w.order.ensure(4 * (int64_t)n));
@@ -748,8 +754,9 @@ static int run_fused(hesp_plan* plan, const SimTables& tb, BatchView bv, const O
   cv.cnt_tasks = plan->cnt_tasks.as<int32_t>();
   cv.cnt_edges = plan->cnt_edges.as<int64_t>();
   cv.order = w.order.as<uint32_t>();
-  cv.region = plan->arena.as<uint8_t>();
+  cv.region = in_lds ? nullptr : plan->arena.as<uint8_t>();
   cv.slot_bytes = slot;
+  cv.slot_lds = in_lds ? 1 : 0;
   plan->ev_used = 0;
   if (plan->timing)
     while (plan->ev.size() < 4) {

@@ -79,7 +79,12 @@ struct ChunkView {
   // from cnt_tasks / cnt_edges); candidates whose block is larger get
   // HESP_ECAPACITY
   int64_t slot_bytes;
+  int32_t slot_lds;                         // 1: the slot is the workgroup's dynamic LDS (no region)
 };
+
+// largest workspace slot kept in LDS by the fused pipeline (with the event
+// loop's own LDS it stays within 64 KiB per workgroup)
+constexpr int64_t kLdsSlotMax = 48 << 10;
 
 // bytes of one candidate's block in region mode: T tasks, E edges, V validity
 // words, TP top-level tasks + 1 (16-byte multiple)
@@ -99,10 +104,11 @@ struct OutView {
 };
 
 hipError_t launch_count(const BatchView& b, int32_t* n_tasks, int64_t* n_edges, hipStream_t s);
-// off_b (nullable): prefix sums of region_bytes per candidate
+// off_b (nullable): prefix sums of region_bytes per candidate; part (nullable):
+// 5 x ceil(n_cand / 1024) int64 of scratch for the many-workgroup scan
 hipError_t launch_layout(const BatchView& b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
                          int64_t cap_t, int64_t cap_e, int64_t* off_t, int64_t* off_e, int64_t* off_v,
-                         int64_t* off_top, int64_t* off_b, hipStream_t s);
+                         int64_t* off_top, int64_t* off_b, hipStream_t s, int64_t* part = nullptr);
 hipError_t launch_bounds(const int64_t* off_t, const int64_t* off_e, const int64_t* off_v, const int64_t* off_top,
                          int32_t n, int32_t chunk, int32_t n_chunks, int64_t* out, hipStream_t s);
 hipError_t launch_prepare(const SimTables& t, const BatchView& b, const ChunkView& v, const OutView& o,

@@ -40,65 +40,121 @@ using namespace dev;
 
 // ---------------------------------------------------------------- layout
 
-// off_X[c] = sum over candidates before c; five columns at once (one workgroup):
-// tasks, edges, validity words, top-level tasks and (when off_b is given) the
-// bytes of the candidate's region (all its arrays in one block, 16-byte aligned)
-// Candidates above a plan's task or edge capacity get no task or edge storage
-// (k_prepare marks them HESP_ECAPACITY), so a chunk never needs more than
+// The five columns of candidate c: tasks, edges, validity words, top-level
+// tasks and the bytes of its region (all its arrays in one block, 16-byte
+// aligned).  Candidates above a plan's task or edge capacity get no task or edge
+// storage (k_prepare marks them HESP_ECAPACITY), so a chunk never needs more than
 // (candidates x capacity).
+constexpr int kLayoutCols = 5;
+__device__ __forceinline__ void layout_cols(const BatchView& b, int32_t n_mem, const int32_t* n_tasks,
+                                            const int64_t* n_edges, int64_t cap_t, int64_t cap_e, int c,
+                                            int64_t (&x)[kLayoutCols]) {
+  for (int q = 0; q < kLayoutCols; q++) x[q] = 0;
+  if (c >= b.n_cand) return;
+  const int nt = b.nt_arr ? b.nt_arr[c] : b.nt;
+  const int dmax = b.dmax_arr ? b.dmax_arr[c] : b.dmax;
+  const bool ok = nt >= 1 && dmax >= 0 && dmax <= kMaxLevel && (nt << dmax) <= kMaxFine;
+  const bool fits = (cap_t <= 0 || n_tasks[c] <= cap_t) && (cap_e <= 0 || n_edges[c] <= cap_e);
+  x[0] = fits ? n_tasks[c] : 0;
+  x[1] = fits ? n_edges[c] : 0;
+  x[2] = ok ? ((int64_t)tri2(nt) << (2 * dmax)) * n_mem : 0;
+  x[3] = ok ? tet3(nt) + 1 : 0;
+  x[4] = region_bytes(x[0], x[1], x[2], x[3]);
+}
+
+// inclusive sums of the five columns over the 1,024 candidates of a workgroup
+// (16 wavefronts: shuffles inside each, then the wavefront totals in s_part);
+// returns, per column, the workgroup's total
+__device__ __forceinline__ void layout_block_scan(int64_t (&x)[kLayoutCols], int64_t (*s_part)[16],
+                                                  int64_t (&total)[kLayoutCols]) {
+  const int l = lane(), wv = threadIdx.x / kWave;
+  int64_t incl[kLayoutCols];
+  for (int q = 0; q < kLayoutCols; q++) {
+    int64_t v = x[q];
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t y = __shfl_up(v, o, kWave);
+      if (l >= o) v += y;
+    }
+    incl[q] = v;
+    if (l == kWave - 1) s_part[q][wv] = v;
+  }
+  __syncthreads();
+  for (int q = 0; q < kLayoutCols; q++) {
+    int64_t pre = 0, tot = 0;
+    for (int w = 0; w < 16; w++) {
+      pre += w < wv ? s_part[q][w] : 0;
+      tot += s_part[q][w];
+    }
+    x[q] = pre + incl[q];
+    total[q] = tot;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int64_t* layout_out(int q, int64_t* off_t, int64_t* off_e, int64_t* off_v,
+                                               int64_t* off_top, int64_t* off_b) {
+  return q == 0 ? off_t : (q == 1 ? off_e : (q == 2 ? off_v : (q == 3 ? off_top : off_b)));
+}
+
+// off_X[c] = sum over candidates before c, the five columns at once; one
+// workgroup walks the whole batch (small batches, and callers without scratch)
 __global__ void __launch_bounds__(1024) k_layout(BatchView b, int32_t n_mem, const int32_t* n_tasks,
                                                  const int64_t* n_edges, int64_t cap_t, int64_t cap_e,
                                                  int64_t* off_t, int64_t* off_e, int64_t* off_v, int64_t* off_top,
                                                  int64_t* off_b) {
-  constexpr int Q = 5;
-  __shared__ int64_t s_part[Q][16];
-  __shared__ int64_t s_carry[Q];
-  const int l = lane(), wv = threadIdx.x / kWave;
-  if (threadIdx.x < Q) s_carry[threadIdx.x] = 0;
-  __syncthreads();
+  __shared__ int64_t s_part[kLayoutCols][16];
+  int64_t carry[kLayoutCols] = {0, 0, 0, 0, 0};
   for (int base = 0; base < b.n_cand; base += 1024) {
     const int c = base + (int)threadIdx.x;
-    int64_t x[Q] = {0, 0, 0, 0, 0};
-    if (c < b.n_cand) {
-      const int nt = b.nt_arr ? b.nt_arr[c] : b.nt;
-      const int dmax = b.dmax_arr ? b.dmax_arr[c] : b.dmax;
-      const bool ok = nt >= 1 && dmax >= 0 && dmax <= kMaxLevel && (nt << dmax) <= kMaxFine;
-      const bool fits = (cap_t <= 0 || n_tasks[c] <= cap_t) && (cap_e <= 0 || n_edges[c] <= cap_e);
-      x[0] = fits ? n_tasks[c] : 0;
-      x[1] = fits ? n_edges[c] : 0;
-      x[2] = ok ? ((int64_t)tri2(nt) << (2 * dmax)) * n_mem : 0;
-      x[3] = ok ? tet3(nt) + 1 : 0;
-      x[4] = region_bytes(x[0], x[1], x[2], x[3]);
+    int64_t x[kLayoutCols], tot[kLayoutCols];
+    layout_cols(b, n_mem, n_tasks, n_edges, cap_t, cap_e, c, x);
+    layout_block_scan(x, s_part, tot);
+    for (int q = 0; q < kLayoutCols; q++) {
+      int64_t* off = layout_out(q, off_t, off_e, off_v, off_top, off_b);
+      if (off && c < b.n_cand) off[c + 1] = carry[q] + x[q];
+      carry[q] += tot[q];
     }
-    int64_t incl[Q];
-    for (int q = 0; q < Q; q++) {
-      int64_t v = x[q];
-      for (int o = 1; o < kWave; o <<= 1) {
-        const int64_t y = __shfl_up(v, o, kWave);
-        if (l >= o) v += y;
-      }
-      incl[q] = v;
-      if (l == kWave - 1) s_part[q][wv] = v;
-    }
-    __syncthreads();
-    for (int q = 0; q < Q; q++) {
-      int64_t pre = s_carry[q];
-      for (int w = 0; w < wv; w++) pre += s_part[q][w];
-      int64_t* off = q == 0 ? off_t : (q == 1 ? off_e : (q == 2 ? off_v : (q == 3 ? off_top : off_b)));
-      if (off && c < b.n_cand) off[c + 1] = pre + incl[q];
-      if (off && c == 0) off[0] = 0;
-    }
-    __syncthreads();
-    if (threadIdx.x < Q) {
-      int64_t s = 0;
-      for (int w = 0; w < 16; w++) s += s_part[threadIdx.x][w];
-      s_carry[threadIdx.x] += s;
-    }
-    __syncthreads();
   }
-  if (b.n_cand == 0 && threadIdx.x == 0) {
-    off_t[0] = 0; off_e[0] = 0; off_v[0] = 0; off_top[0] = 0;
-    if (off_b) off_b[0] = 0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < kLayoutCols; q++) {
+      int64_t* off = layout_out(q, off_t, off_e, off_v, off_top, off_b);
+      if (off) off[0] = 0;
+    }
+}
+
+// the same over many workgroups: each scans its 1,024 candidates and leaves its
+// totals in part[q][block]; k_layout_fix then adds the totals of the blocks before
+__global__ void __launch_bounds__(1024) k_layout_part(BatchView b, int32_t n_mem, const int32_t* n_tasks,
+                                                      const int64_t* n_edges, int64_t cap_t, int64_t cap_e,
+                                                      int64_t* off_t, int64_t* off_e, int64_t* off_v,
+                                                      int64_t* off_top, int64_t* off_b, int64_t* part) {
+  __shared__ int64_t s_part[kLayoutCols][16];
+  const int c = blockIdx.x * 1024 + (int)threadIdx.x;
+  int64_t x[kLayoutCols], tot[kLayoutCols];
+  layout_cols(b, n_mem, n_tasks, n_edges, cap_t, cap_e, c, x);
+  layout_block_scan(x, s_part, tot);
+  for (int q = 0; q < kLayoutCols; q++) {
+    int64_t* off = layout_out(q, off_t, off_e, off_v, off_top, off_b);
+    if (off && c < b.n_cand) off[c + 1] = x[q];
+    if (threadIdx.x == 0) part[q * gridDim.x + blockIdx.x] = tot[q];
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_layout_fix(int32_t n, int64_t* off_t, int64_t* off_e, int64_t* off_v,
+                                                     int64_t* off_top, int64_t* off_b, const int64_t* part) {
+  __shared__ int64_t s_carry[kLayoutCols];
+  if (threadIdx.x < kLayoutCols) {
+    int64_t sum = 0;
+    for (unsigned k = 0; k < blockIdx.x; k++) sum += part[threadIdx.x * gridDim.x + k];
+    s_carry[threadIdx.x] = sum;
+  }
+  __syncthreads();
+  const int c = blockIdx.x * 1024 + (int)threadIdx.x;
+  for (int q = 0; q < kLayoutCols; q++) {
+    int64_t* off = layout_out(q, off_t, off_e, off_v, off_top, off_b);
+    if (!off) continue;
+    if (c < n) off[c + 1] += s_carry[q];
+    if (c == 0) off[0] = 0;
   }
 }
 
@@ -649,10 +705,14 @@ union SimPrepLds {
 // 280 at seven with a few spills, 324 at eight, 285 at five and at four); the
 // 16- and 32-lane variants lose when squeezed and keep their registers.
 // FUSED (whole-wave groups only): each wave prepares the candidates it claims
-// itself (prepare_cand) into its own slot of cv.slot_bytes bytes of cv.region,
-// so a batch needs neither the separate preparation launch nor memory chunks.
-template <int G, int POL, bool FUSED>
-__global__ void __launch_bounds__(kWave, G == 64 ? 6 : 1) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
+// itself (prepare_cand) into its own slot of cv.slot_bytes bytes, so a batch
+// needs neither the separate preparation launch nor memory chunks; the slot is
+// slot blockIdx.x of cv.region (FUSED 1) or the workgroup's dynamic LDS (FUSED
+// 2: the whole state of a small candidate, validity table, records, successor
+// lists and queues, never leaves the compute unit; its LDS slot, not registers,
+// bounds the waves per compute unit, so this variant keeps its registers).
+template <int G, int POL, int FUSED>
+__global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
                                                uint32_t* counter) {
   static_assert(!FUSED || G == kWave, "the fused preparation needs whole-wave groups");
   // POL 0: Priority-List + EFT-P + write-back (no policy flags read); 1: the
@@ -669,7 +729,8 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 6 : 1) k_sim(SimTables tb, Ba
   __shared__ int64_t s_cost[kMaxPtypes][4][kLevels];
   __shared__ int64_t s_xfer[kXferLen];
   __shared__ int64_t s_W[FUSED ? 4 : 1][kLevels];
-  using Lds = std::conditional_t<FUSED, SimPrepLds<G, POL>, SimLds<G, POL>>;
+  using Lds = std::conditional_t<(FUSED != 0), SimPrepLds<G, POL>, SimLds<G, POL>>;
+  extern __shared__ __align__(16) uint8_t s_ws[];   // FUSED 2: the candidate's workspace
   __shared__ Lds s_l;
   SimLds<G, POL>& L = reinterpret_cast<SimLds<G, POL>&>(s_l);
   auto& s_fin = L.fin;
@@ -810,7 +871,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 6 : 1) k_sim(SimTables tb, Ba
         const int64_t Vq = shape_ok ? ((int64_t)tri2(cq.nt) << (2 * cq.dmax)) * M : 0;
         const bool cap = (cv.cap_tasks > 0 && Tq > cv.cap_tasks) || (cv.cap_edges > 0 && Eq > cv.cap_edges) ||
                          region_bytes(Tq, Eq, Vq, cq.n_top + 1) > cv.slot_bytes;
-        sp = carve(cv.region + (int64_t)blockIdx.x * cv.slot_bytes, Tq, Eq, Vq);
+        sp = carve(FUSED == 2 ? s_ws : cv.region + (int64_t)blockIdx.x * cv.slot_bytes, Tq, Eq, Vq);
         int n_src = 0;
         const bool ok = prepare_cand(tb, bv, out, c, sp, Tq, Eq, cap, cv.prep_in, s_W, s_l.prep, n_src) == kOK;
         __syncthreads();   // the preparation's LDS is the event loop's from here
@@ -852,9 +913,19 @@ __global__ void __launch_bounds__(kWave, G == 64 ? 6 : 1) k_sim(SimTables tb, Ba
 
 hipError_t launch_layout(const BatchView& b, int32_t n_mem, const int32_t* n_tasks, const int64_t* n_edges,
                          int64_t cap_t, int64_t cap_e, int64_t* off_t, int64_t* off_e, int64_t* off_v,
-                         int64_t* off_top, int64_t* off_b, hipStream_t s) {
-  hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, b, n_mem, n_tasks, n_edges, cap_t, cap_e, off_t, off_e,
-                     off_v, off_top, off_b);
+                         int64_t* off_top, int64_t* off_b, hipStream_t s, int64_t* part) {
+  const int blocks = (b.n_cand + 1023) / 1024;
+  if (!part || blocks <= 4) {
+    hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, b, n_mem, n_tasks, n_edges, cap_t, cap_e, off_t, off_e,
+                       off_v, off_top, off_b);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_layout_part, dim3(blocks), dim3(1024), 0, s, b, n_mem, n_tasks, n_edges, cap_t, cap_e, off_t,
+                     off_e, off_v, off_top, off_b, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_layout_fix, dim3(blocks), dim3(1024), 0, s, b.n_cand, off_t, off_e, off_v, off_top, off_b,
+                     part);
   return hipGetLastError();
 }
 
@@ -891,7 +962,8 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
   if (v.nc <= 0) return hipSuccess;
   if ((group != 16 && group != 32 && group != 64) || group < t.n_procs) return hipErrorInvalidValue;
   const bool fused = v.slot_bytes > 0;
-  if (fused && (group != 64 || !v.region || b.tree_stride > 0)) return hipErrorInvalidValue;
+  if (fused && (group != 64 || (!v.region && !v.slot_lds) || b.tree_stride > 0)) return hipErrorInvalidValue;
+  if (v.slot_lds && (!fused || v.slot_bytes > kLdsSlotMax)) return hipErrorInvalidValue;
   hipError_t e = launch_zero_u32(counter, s);
   if (e != hipSuccess) return e;
   const int G = group;
@@ -901,24 +973,30 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
   const int pol = t.capped ? 3 : (t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs || t.cache != 0 || t.bus != 0 ? 1 : 0));
   if (pol == 3 && (fused || G != 64 || !v.use || !v.pin)) return hipErrorInvalidValue;
   const dim3 grid(waves), block(kWave);
-#define HESP_SIM_LAUNCH(GG, PP, FF) hipLaunchKernelGGL((k_sim<GG, PP, FF>), grid, block, 0, s, t, b, v, o, counter)
-  if (fused) {
-    if (pol == 0) HESP_SIM_LAUNCH(64, 0, true);
-    else if (pol == 1) HESP_SIM_LAUNCH(64, 1, true);
-    else HESP_SIM_LAUNCH(64, 2, true);
+#define HESP_SIM_LAUNCH(GG, PP, FF, LDSB) \
+  hipLaunchKernelGGL((k_sim<GG, PP, FF>), grid, block, LDSB, s, t, b, v, o, counter)
+  if (fused && v.slot_lds) {
+    const size_t ws = (size_t)v.slot_bytes;
+    if (pol == 0) HESP_SIM_LAUNCH(64, 0, 2, ws);
+    else if (pol == 1) HESP_SIM_LAUNCH(64, 1, 2, ws);
+    else HESP_SIM_LAUNCH(64, 2, 2, ws);
+  } else if (fused) {
+    if (pol == 0) HESP_SIM_LAUNCH(64, 0, 1, 0);
+    else if (pol == 1) HESP_SIM_LAUNCH(64, 1, 1, 0);
+    else HESP_SIM_LAUNCH(64, 2, 1, 0);
   } else if (G == 16) {
-    if (pol == 0) HESP_SIM_LAUNCH(16, 0, false);
-    else if (pol == 1) HESP_SIM_LAUNCH(16, 1, false);
-    else HESP_SIM_LAUNCH(16, 2, false);
+    if (pol == 0) HESP_SIM_LAUNCH(16, 0, 0, 0);
+    else if (pol == 1) HESP_SIM_LAUNCH(16, 1, 0, 0);
+    else HESP_SIM_LAUNCH(16, 2, 0, 0);
   } else if (G == 32) {
-    if (pol == 0) HESP_SIM_LAUNCH(32, 0, false);
-    else if (pol == 1) HESP_SIM_LAUNCH(32, 1, false);
-    else HESP_SIM_LAUNCH(32, 2, false);
+    if (pol == 0) HESP_SIM_LAUNCH(32, 0, 0, 0);
+    else if (pol == 1) HESP_SIM_LAUNCH(32, 1, 0, 0);
+    else HESP_SIM_LAUNCH(32, 2, 0, 0);
   } else {
-    if (pol == 0) HESP_SIM_LAUNCH(64, 0, false);
-    else if (pol == 1) HESP_SIM_LAUNCH(64, 1, false);
-    else if (pol == 2) HESP_SIM_LAUNCH(64, 2, false);
-    else HESP_SIM_LAUNCH(64, 3, false);
+    if (pol == 0) HESP_SIM_LAUNCH(64, 0, 0, 0);
+    else if (pol == 1) HESP_SIM_LAUNCH(64, 1, 0, 0);
+    else if (pol == 2) HESP_SIM_LAUNCH(64, 2, 0, 0);
+    else HESP_SIM_LAUNCH(64, 3, 0, 0);
   }
 #undef HESP_SIM_LAUNCH
   return hipGetLastError();

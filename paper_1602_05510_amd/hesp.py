@@ -313,9 +313,11 @@ def count_batch(batch: DeviceBatch, stream=None):
 
 class Plan:
     def __init__(self, slots: int = 0, max_tasks: int = 0, max_edges: int = 0, chunks: int = 0, group: int = 0,
-                 prep_edges: int = 0, fuse: bool = False):
+                 prep_edges: int = 0, fuse: int = 0):
+        """fuse: 0 separate preparation launches, 1 fused pipeline (workspace
+        slots in device memory), 2 fused pipeline with each slot in LDS."""
         self.h = P()
-        self.opts = PlanOpts(slots, max_tasks, max_edges, chunks, group, prep_edges, int(bool(fuse)))
+        self.opts = PlanOpts(slots, max_tasks, max_edges, chunks, group, prep_edges, int(fuse))
         _check("hesp_plan_create", lib().hesp_plan_create(ctypes.byref(self.h), ctypes.byref(self.opts)))
 
     def bytes(self) -> int:

@@ -203,3 +203,69 @@ def test_graph_replay_ragged_batch_one_launch(H, torch):
         assert torch.equal(ms, ms2), k
     want, _ = O.simulate_batch(pf_in, hosts[reps], NTHREADS)
     assert np.array_equal(ms.cpu().numpy(), want)
+
+
+# ------------------------------------------------------------ workspace slots in LDS
+
+@pytest.mark.parametrize("name,n", [("chol4x4_b512_d1", 1024), ("chol16x16_b1024_d2", 0)])
+def test_lds_slots_equal_unfused_and_oracle(H, torch, name, n):
+    """fuse=2: each candidate's whole state in the workgroup's LDS.  The 4x4
+    workload (every candidate fits) with schedules; candidates of the
+    16x16 workload's platform and depth, 5 tiles (most fit)."""
+    w = I.WORKLOADS[name]
+    pf_in = w.platform()
+    pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
+    host = w.batch(n, first=3_000) if n else I.uniform_batch(w.seed, 256, 5, w.b, w.dmax, w.p_num, w.p_den, first=3)
+    db = H.DeviceBatch.from_host(host)
+    print(f"LDS slots: {name}, {host.n} candidates", flush=True)
+    got = _sim(H, torch, H.Plan(group=64, fuse=2), pf, db, sched=True)
+    ref = _sim(H, torch, H.Plan(), pf, db, sched=True)
+    ok = got[1] == 0
+    assert ok.sum() >= host.n // 2
+    assert (got[1][~ok] == H.HESP_ECAPACITY).all() and (got[0][~ok] == -1).all()
+    assert np.array_equal(got[0][ok], ref[0][ok])
+    want, _ = O.simulate_batch(pf_in, host, NTHREADS)
+    assert np.array_equal(got[0][ok], want[ok])
+    if ok.all():
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
+
+
+def test_lds_slots_capacity_limit(H, torch):
+    """Uneven batch: the candidates whose workspace exceeds the 48 KiB slot get
+    HESP_ECAPACITY, exactly those (104 T + 4 E + 8 V + 4 (tet(nt) + 1) bytes,
+    rounded up to 16), the others equal the oracle."""
+    w = I.WORKLOADS["ragged_bl_b512_d3"]
+    pf_in = w.platform()
+    pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
+    host = I.ragged_batch(w.seed, 128, 4, 12, 3, w.b, w.p_num, w.p_den, first=4_321)
+    db = H.DeviceBatch.from_host(host)
+    cnt_t, cnt_e = H.count_batch(db)
+    T = cnt_t.cpu().numpy().astype(np.int64)
+    E = cnt_e.cpu().numpy().astype(np.int64)
+    nt, dm = host.nt.astype(np.int64), host.dmax.astype(np.int64)
+    V = (nt * (nt + 1) // 2) * 4 ** dm * pf_in.n_mem
+    TP = nt * (nt + 1) * (nt + 2) // 6 + 1
+    rb = (104 * T + 4 * E + 8 * V + 4 * TP + 15) // 16 * 16
+    fits = rb <= 48 * 1024
+    assert fits.any() and not fits.all(), "the case must straddle the slot"
+    print("LDS slots: ragged, 128 candidates", flush=True)
+    got = _sim(H, torch, H.Plan(group=64, fuse=2), pf, db)
+    assert np.array_equal(got[1], np.where(fits, 0, H.HESP_ECAPACITY))
+    want, _ = O.simulate_batch(pf_in, host, NTHREADS)
+    assert np.array_equal(got[0][fits], want[fits]) and (got[0][~fits] == -1).all()
+
+
+@pytest.mark.parametrize("policy", [(1, 1, 0, 0, 0), (0, 3, 0, 0, 0), (0, 0, 2, 0, 1)])
+def test_lds_slots_policies(H, torch, policy):
+    w = I.WORKLOADS["chol4x4_b512_d1"]
+    pf_in = w.platform()
+    pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
+    host = w.batch(256, first=77)
+    db = H.DeviceBatch.from_host(host)
+    order, select, cache, seed, bus = policy
+    print(f"LDS slots: policy {policy}", flush=True)
+    got = _sim(H, torch, H.Plan(group=64, fuse=2), pf, db, policy=(order, select, cache, seed, bus))
+    assert (got[1] == 0).all()
+    want, _ = O.simulate_batch(pf_in, host, NTHREADS, policy=(order, select, seed, cache, bus))
+    assert np.array_equal(got[0], want)
