@@ -665,6 +665,7 @@ __device__ __forceinline__ uint64_t choice_draw(uint64_t seed, uint64_t idx) {
 }
 
 // Per-group LDS state of the event loop.
+constexpr int kEvict = 256;   // finite spaces: evictable blocks gathered at once
 template <int G, int POL>
 struct SimLds {
   static constexpr int NG = kWave / G;
@@ -681,6 +682,7 @@ struct SimLds {
   int64_t capm[POL == 3 ? NG : 1][kMaxMem];
   int32_t occ[POL == 3 ? NG : 1][kMaxMem];
   int32_t pinned[POL == 3 ? NG : 1][kMaxMem];
+  int64_t ev[POL == 3 ? NG : 1][POL == 3 ? kEvict : 1];   // evictable blocks' keys, gathered per mapping
   uint32_t rid[NG][G];            // ready list, first G entries, with records
   int64_t rrank[NG][G];
   uint64_t rw[NG][G];             // dispatch words
@@ -741,6 +743,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_s
   auto& s_capm = L.capm;
   auto& s_occ = L.occ;
   auto& s_pinned = L.pinned;
+  auto& s_ev = L.ev;
   auto& s_rid = L.rid;
   auto& s_rrank = L.rrank;
   auto& s_rw = L.rw;
