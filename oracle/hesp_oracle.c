@@ -106,7 +106,9 @@ typedef struct {
     int select;              /* policy: 0 = EFT-P, 1 = EIT-P, 2 = R-P, 3 = F-P */
     uint64_t seed;           /* R-P draws */
     int cache;               /* policy: 0 = write-back, 1 = write-through, 2 = write-around */
-    int bus;                 /* 1: transfers share one interconnect, one at a time */
+    int bus;                 /* 1: transfers contend, one at a time on each link */
+    const int32_t *link;     /* [n_mem] link carrying the transfers into each space, or
+                                NULL: one link for every space (a shared interconnect) */
     const int64_t *capacity; /* [n_mem] bytes each accelerator space holds, or NULL;
                                 <= 0 (and always for the host, space 0): unbounded */
 } or_platform;
@@ -532,6 +534,12 @@ static int64_t tree_flag_count(int nt, int dmax)
     return n;
 }
 
+/* the link that carries the transfers into memory space m */
+static int link_of(const or_platform *pf, int m)
+{
+    return pf->link ? pf->link[m] : 0;
+}
+
 /* depth: split depth per top-level task, or (tree != 0) the split flags above */
 static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *depth, int tree,
                         or_result *res, const or_outputs *o)
@@ -541,7 +549,7 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
     or_tables tb = {0, 0, 0, 0};
     int rc;
     int64_t *W = 0, *rank = 0, *start = 0, *finish = 0, *avail = 0, *vf = 0;
-    int64_t *cap = 0, *use = 0;
+    int64_t *cap = 0, *use = 0, *lfree = 0;
     int *pin = 0;
     int *proc = 0, *left = 0, *fifo = 0, *fifo_head = 0, *fifo_tail = 0, *fifo_next = 0;
     or_heap heap = {0, 0};
@@ -579,8 +587,9 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
     cap = (int64_t *)malloc((size_t)M * sizeof(int64_t));
     use = (int64_t *)calloc((size_t)N * N * M, sizeof(int64_t));
     pin = (int *)calloc((size_t)N * N * M, sizeof(int));
+    lfree = (int64_t *)calloc((size_t)M, sizeof(int64_t));
     if (!W || !rank || !start || !finish || !proc || !left || !fifo_next || !avail ||
-        !fifo_head || !fifo_tail || !vf || !heap.v || !cap || !use || !pin) { rc = OR_ENOMEM; goto done; }
+        !fifo_head || !fifo_tail || !vf || !heap.v || !cap || !use || !pin || !lfree) { rc = OR_ENOMEM; goto done; }
 
     /* 6. capacities in finest blocks (-1: unbounded); supported with write-back
      * caching, EFT-P and independent transfers */
@@ -619,7 +628,10 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             heap_push(&heap, (or_hent){pf->order ? 0 : rank[t], (int64_t)tl.v[t].K << sh,
                                        (int64_t)tl.v[t].I << sh, (int64_t)tl.v[t].J << sh, t});
         }
-    int64_t T = 0, makespan = 0, bus_free = 0;
+    /* link contention (reading of the platform's network topology): a transfer
+     * occupies the link of the space it goes into, one transfer at a time per
+     * link; lfree[l] is when link l is next free */
+    int64_t T = 0, makespan = 0;
     int done_count = 0;
     for (;;) {
         /* (i) ready tasks are mapped now, in order; with R-P / F-P only onto
@@ -668,7 +680,7 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                     if (places > cap[m]) continue;
                 }
                 int64_t est = T > avail[p] ? T : avail[p];
-                int64_t bus_at = bus_free;       /* where this mapping's transfers would queue */
+                int64_t bus_at = lfree[link_of(pf, m)];   /* where this mapping's transfers would queue */
                 for (int bi = 0; bi < nb; bi++) {
                     int64_t miss = 0, fin = INT64_MIN;
                     for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
@@ -736,8 +748,8 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                 int64_t go = xfer_start(vf, M, N, br[bi], bc[bi], sh, m, T);
                 /* shared interconnect: one transfer at a time, in issue order (the
                  * blocks of one task in their order) */
-                if (pf->bus && bus_free > go) go = bus_free;
-                if (pf->bus) bus_free = go + tb.xfer[miss];
+                if (pf->bus && lfree[link_of(pf, m)] > go) go = lfree[link_of(pf, m)];
+                if (pf->bus) lfree[link_of(pf, m)] = go + tb.xfer[miss];
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
                     int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
                     if (vf[a * M + m] == OR_INF) vf[a * M + m] = go + tb.xfer[miss];
@@ -786,10 +798,10 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++)
                     pin[((int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v)) * M + m]--;
             int64_t host_at = (m == 0) ? Tn : Tn + tb.xfer[(int64_t)w * w];
-            if (pf->bus && pf->cache != 0 && m != 0) {     /* the host copy queues on the interconnect */
-                int64_t go = Tn > bus_free ? Tn : bus_free;
+            if (pf->bus && pf->cache != 0 && m != 0) {     /* the host copy queues on the host's link */
+                int64_t go = Tn > lfree[link_of(pf, 0)] ? Tn : lfree[link_of(pf, 0)];
                 host_at = go + tb.xfer[(int64_t)w * w];
-                bus_free = host_at;
+                lfree[link_of(pf, 0)] = host_at;
             }
             for (int bi = 0; bi < nb; bi++) {
                 if (!bw[bi]) continue;
@@ -847,7 +859,7 @@ done:
     free(tl.v); dag_free(&g); free_tables(&tb);
     free(W); free(rank); free(start); free(finish); free(proc); free(left); free(fifo_next);
     free(avail); free(fifo_head); free(fifo_tail); free(vf); free(heap.v); free(fifo);
-    free(cap); free(use); free(pin);
+    free(cap); free(use); free(pin); free(lfree);
     return rc;
 }
 
@@ -862,7 +874,7 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
                     int32_t max_tasks, int32_t *task_info, int32_t *proc_out,
                     int64_t *start_out, int64_t *finish_out, int64_t *rank_out,
                     int64_t max_edges, int32_t *edges_out, int order, int select, uint64_t seed,
-                    int cache, int tree, int bus, const int64_t *capacity)
+                    int cache, int tree, int bus, const int64_t *capacity, const int32_t *link)
 {
     if (!depth || n_procs < 1 || !proc_type || !proc_mem || n_mem < 1 || !rmax || !h) return OR_EINVAL;
     if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2 || bus < 0 || bus > 1)
@@ -870,8 +882,10 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
     for (int p = 0; p < n_procs; p++)
         if (proc_type[p] < 0 || proc_type[p] >= n_ptypes || proc_mem[p] < 0 || proc_mem[p] >= n_mem)
             return OR_EINVAL;
+    for (int m = 0; link && m < n_mem; m++)
+        if (link[m] < 0 || link[m] >= n_mem) return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus, capacity};
+                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus, link, capacity};
     or_outputs o = {max_tasks, task_info, proc_out, start_out, finish_out, rank_out, max_edges, edges_out};
     or_result r;
     int rc = simulate_one(&pf, nt, dmax, depth, tree, &r, &o);
@@ -921,13 +935,15 @@ int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
                           int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
                           int n_threads, int64_t *makespan, int32_t *n_tasks, int32_t *status,
                           int order, int select, uint64_t seed, int cache, int tree, int bus,
-                          const int64_t *capacity)
+                          const int64_t *capacity, const int32_t *link)
 {
     if (n_cand < 0 || !nt || !dmax || !mask_off || !depth || !makespan || n_threads < 1) return OR_EINVAL;
     if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2 || bus < 0 || bus > 1)
         return OR_EINVAL;
+    for (int m = 0; link && m < n_mem; m++)
+        if (link[m] < 0 || link[m] >= n_mem) return OR_EINVAL;
     or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
-                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus, capacity};
+                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus, link, capacity};
     or_batch_job j;
     j.pf = &pf; j.n_cand = n_cand; j.nt = nt; j.dmax = dmax; j.mask_off = mask_off; j.depth = depth;
     j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.tree = tree; j.next = 0;

@@ -58,10 +58,10 @@ def lib(native: bool = False):
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         L.oracle_simulate.argtypes = [i32, i32, P, i32, P, P, i32, i32, P, P, i64, i64, i64, i64, i32,
-                                      P, P, P, i32, P, P, P, P, P, i64, P, i32, i32, ctypes.c_uint64, i32, i32, i32, P]
+                                      P, P, P, i32, P, P, P, P, P, i64, P, i32, i32, ctypes.c_uint64, i32, i32, i32, P, P]
         L.oracle_simulate.restype = i32
         L.oracle_simulate_batch.argtypes = [i32, P, P, P, P, i32, P, P, i32, i32, P, P, i64, i64, i64,
-                                            i64, i32, i32, P, P, P, i32, i32, ctypes.c_uint64, i32, i32, i32, P]
+                                            i64, i32, i32, P, P, P, i32, i32, ctypes.c_uint64, i32, i32, i32, P, P]
         L.oracle_simulate_batch.restype = i32
         L.oracle_task_time.argtypes = [i32, i64, i64, i64, P]
         L.oracle_task_time.restype = i32
@@ -110,7 +110,7 @@ class Schedule:
 
 
 def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = True, policy=(0, 0),
-             tree: bool = False, capacity=None):
+             tree: bool = False, capacity=None, link=None):
     """Simulate one candidate; returns a Schedule (detail) or the makespan.
 
     depth: split depth per top-level task, or with tree=True the split flags of
@@ -120,8 +120,12 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     policy = (order, select[, seed[, cache[, bus]]]): order 0 = Priority-List,
     1 = FCFS; select 0 = EFT-P, 1 = EIT-P, 2 = R-P, 3 = F-P (section 2.1, "Task
     and data scheduling heuristics"); seed feeds the R-P draws; cache 0 =
-    write-back, 1 = write-through, 2 = write-around; bus 1 = every transfer
-    shares one interconnect.
+    write-back, 1 = write-through, 2 = write-around; bus 1 = transfers
+    contend: one at a time on each link.
+
+    link: None (one link shared by every transfer) or the link of each memory
+    space ([n_mem], ids 0..n_mem-1): with bus 1 a transfer occupies the link of
+    the space it goes into (copies sent to the host occupy the host's).
 
     capacity: None or bytes per memory space ([n_mem]; <= 0 and the host's
     entry mean unbounded): finite accelerator spaces with least-recently-used
@@ -129,6 +133,7 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     order, select, seed, cache, bus = (tuple(policy) + (0, 0, 0))[:5]
     L = lib()
     cap = None if capacity is None else np.ascontiguousarray(capacity, dtype=np.int64)
+    lk = None if link is None else np.ascontiguousarray(link, dtype=np.int32)
     depth = np.ascontiguousarray(depth, dtype=np.uint8)
     ptype = np.ascontiguousarray(pf.proc_type, dtype=np.int32)
     pmem = np.ascontiguousarray(pf.proc_mem, dtype=np.int32)
@@ -141,7 +146,7 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
                pf.latency_ns, pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory))
     rc = L.oracle_simulate(nt, dmax, _p(depth), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
                            0, None, None, None, None, None, 0, None, order, select, seed, cache, int(tree), bus,
-                           _p(cap))
+                           _p(cap), _p(lk))
     if rc:
         raise ValueError(f"oracle_simulate rc={rc}")
     if not detail:
@@ -155,21 +160,22 @@ def simulate(pf, nt: int, dmax: int, b: int, depth: np.ndarray, detail: bool = T
     edges = np.zeros((max(m, 1), 2), np.int32)
     rc = L.oracle_simulate(nt, dmax, _p(depth), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
                            n, _p(tasks), _p(proc), _p(start), _p(finish), _p(rank), m, _p(edges), order, select,
-                           seed, cache, int(tree), bus, _p(cap))
+                           seed, cache, int(tree), bus, _p(cap), _p(lk))
     if rc:
         raise ValueError(f"oracle_simulate rc={rc}")
     return Schedule(int(ms[0]), tasks, proc, start, finish, rank, edges[:m])
 
 
 def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = False, native: bool = False,
-                   capacity=None, statuses: bool = False):
+                   capacity=None, statuses: bool = False, link=None):
     """Makespans (int64) and expanded task counts of a whole batch (policy,
-    tree and capacity as in simulate; with tree=True batch.depth holds split
+    tree, capacity and link as in simulate; with tree=True batch.depth holds split
     flags and batch.mask_off their offsets; native selects the -march=native
     build).  statuses=True returns (makespans, counts, statuses) instead of
     raising on a candidate that fails (-4: no space can hold a task)."""
     order, select, seed, cache, bus = (tuple(policy) + (0, 0, 0))[:5]
     cap = None if capacity is None else np.ascontiguousarray(capacity, dtype=np.int64)
+    lk = None if link is None else np.ascontiguousarray(link, dtype=np.int32)
     L = lib(native)
     n = batch.n
     ms = np.zeros(n, np.int64)
@@ -186,7 +192,8 @@ def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = Fa
     rc = L.oracle_simulate_batch(n, _p(nt), _p(dm), _p(off), _p(dep), pf.n_procs, _p(ptype), _p(pmem),
                                  pf.n_mem, pf.n_ptypes, _p(rmax), _p(h), batch.b, pf.latency_ns,
                                  pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory), n_threads,
-                                 _p(ms), _p(ntk), _p(st), order, select, seed, cache, int(tree), bus, _p(cap))
+                                 _p(ms), _p(ntk), _p(st), order, select, seed, cache, int(tree), bus, _p(cap),
+                                 _p(lk))
     if rc:
         raise ValueError(f"oracle_simulate_batch rc={rc}")
     if statuses:

@@ -245,7 +245,7 @@ class Sim:
         return (tile, (a[0] % w) * w + a[1] % w)
 
     def run(self, choose_task=None, choose_proc=None, order="PL", select="EFT", seed=0, cache="WB", bus=False,
-            capacity=None):
+            capacity=None, links=None):
         """order: "PL" (decreasing critical time) or "FCFS" (first released first);
         select: "EFT" (earliest finish), "EIT" (processor idle first), "RP"
         (random idle processor) or "FP" (fastest idle processor); with RP / FP a
@@ -260,7 +260,9 @@ class Sim:
         after it wait for the next completion; room is made by dropping the least
         recently used other blocks (ties by lru_order), a block with no host copy
         being copied back first (one transfer per finest block).  Returns None
-        when a task can never be taken."""
+        when a task can never be taken.  bus: transfers contend, one at a time
+        per link; links[m] names the link of the transfers into space m (copies
+        sent to the host take the host's); None: one link for all."""
         from paper_1602_05510_amd.inputs import draw
         N = 0
         vf = {}
@@ -275,7 +277,13 @@ class Sim:
         fifo = [[] for _ in range(self.P)]
         proc, start, finish = [None] * self.n, [None] * self.n, [None] * self.n
         T = 0
-        bus_free = 0
+        link_free = {}                          # link -> when it is next free
+
+        def link(m):
+            return links[m] if links is not None else 0
+
+        def free_at(m):
+            return link_free.get(link(m), 0) if bus else None
         slots = [None] * self.n_mem             # finest blocks per space, None = unbounded
         if capacity is not None:
             per = 8 * self.atom_side * self.atom_side
@@ -293,7 +301,7 @@ class Sim:
                 else:
                     t = min(ready, key=self.key)
                 ready.remove(t)
-                ests = [self.est(t, p, T, avail, vf, bus_free if bus else None) for p in range(self.P)]
+                ests = [self.est(t, p, T, avail, vf, free_at(self.proc_mem[p])) for p in range(self.P)]
                 efts = [ests[p] + self.cost[t][p] for p in range(self.P)]
                 mine = set(self.task_atoms(t))
 
@@ -332,9 +340,9 @@ class Sim:
                             if vf[a][0] == INF:
                                 vf[a][0] = T + self.xfer(1)
                             vf[a][m] = INF
-                arr, after = self.transfers(t, m, T, vf, bus_free if bus else None)
+                arr, after = self.transfers(t, m, T, vf, free_at(m))
                 if bus:
-                    bus_free = after
+                    link_free[link(m)] = after
                 for (R, C, _), x in zip(blocks(self.tasks[t]), arr):
                     for a in atoms(R, C, self.tasks[t][1], self.dmax):
                         if vf[a][m] == INF:
@@ -362,8 +370,8 @@ class Sim:
                             at = atoms(R, C, self.tasks[t][1], self.dmax)
                             home = Tn if m == 0 else Tn + self.xfer(len(at))
                             if bus and cache != "WB" and m != 0:
-                                home = max(Tn, bus_free) + self.xfer(len(at))
-                                bus_free = home
+                                home = max(Tn, free_at(0)) + self.xfer(len(at))
+                                link_free[link(0)] = home
                             for a in at:
                                 copies = [INF] * self.n_mem
                                 if cache == "WB" or (cache == "WT" and m != 0):

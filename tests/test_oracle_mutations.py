@@ -48,12 +48,24 @@ MUTANTS = {
     "transfer_ignores_source": ("if (src != OR_INF && src > go) go = src;", "if (src != OR_INF && src > go) go = T;"),
     "bus_estimate_blocks_in_parallel": ("                        if (pf->bus) bus_at = go + tb.xfer[miss];",
                                         "                        if (0) bus_at = go + tb.xfer[miss];"),
-    "bus_frees_at_transfer_start": ("                if (pf->bus) bus_free = go + tb.xfer[miss];",
-                                    "                if (pf->bus) bus_free = go;"),
+    "bus_frees_at_transfer_start": ("                if (pf->bus) lfree[link_of(pf, m)] = go + tb.xfer[miss];",
+                                    "                if (pf->bus) lfree[link_of(pf, m)] = go;"),
     "bus_estimate_ignores_queue": ("                        if (pf->bus && bus_at > go) go = bus_at;",
                                    "                        if (0) go = bus_at;"),
-    "bus_host_copy_free": ("                int64_t go = Tn > bus_free ? Tn : bus_free;",
+    "bus_host_copy_free": ("                int64_t go = Tn > lfree[link_of(pf, 0)] ? Tn : lfree[link_of(pf, 0)];",
                            "                int64_t go = Tn;"),
+    "links_ignored": ("    return pf->link ? pf->link[m] : 0;", "    return 0;"),
+    "estimate_on_the_host_link": ("int64_t bus_at = lfree[link_of(pf, m)];", "int64_t bus_at = lfree[link_of(pf, 0)];"),
+    "transfer_on_the_host_link": ("                if (pf->bus && lfree[link_of(pf, m)] > go) go = lfree[link_of(pf, m)];\n"
+                                  "                if (pf->bus) lfree[link_of(pf, m)] = go + tb.xfer[miss];",
+                                  "                if (pf->bus && lfree[link_of(pf, 0)] > go) go = lfree[link_of(pf, 0)];\n"
+                                  "                if (pf->bus) lfree[link_of(pf, 0)] = go + tb.xfer[miss];"),
+    "host_copy_on_the_source_link": ("                int64_t go = Tn > lfree[link_of(pf, 0)] ? Tn : lfree[link_of(pf, 0)];\n"
+                                     "                host_at = go + tb.xfer[(int64_t)w * w];\n"
+                                     "                lfree[link_of(pf, 0)] = host_at;",
+                                     "                int64_t go = Tn > lfree[link_of(pf, m)] ? Tn : lfree[link_of(pf, m)];\n"
+                                     "                host_at = go + tb.xfer[(int64_t)w * w];\n"
+                                     "                lfree[link_of(pf, m)] = host_at;"),
     "tree_ignores_deeper_flags": ("    if (l < tr->dmax && tr->flags[tr->off[l] + tr->index[l][((size_t)K * N + I) * N + J]]) {",
                                   "    if (l < 1 && l < tr->dmax && tr->flags[tr->off[l] + tr->index[l][((size_t)K * N + I) * N + J]]) {"),
     "tree_children_take_parent_kind": ("            if (emit_tree(out, tr, top, kids.v[c].type, l + 1, kids.v[c].K, kids.v[c].I, kids.v[c].J)) {",
@@ -109,13 +121,15 @@ def _pins_pass():
         ex = ex + json.load(f)["examples"]
     with open(os.path.join(GOLD, "capacity_examples.json")) as f:
         ex = ex + json.load(f)["examples"]
+    with open(os.path.join(GOLD, "link_examples.json")) as f:
+        ex = ex + json.load(f)["examples"]
     try:
         for e in ex:
             pts = [I.ProcType(n, c, r, r, h, own) for (n, c, r, h, own) in e["platform"]["types"]]
             pf = I.make_platform(pts, seed=0)
             cap = np.array(e["capacity_bytes"], np.int64) if "capacity_bytes" in e else None
             s = O.simulate(pf, e["nt"], e["dmax"], e["b"], np.array(e["depth"], np.uint8),
-                           policy=tuple(e.get("policy", (0, 0))), capacity=cap)
+                           policy=tuple(e.get("policy", (0, 0))), capacity=cap, link=e.get("link"))
             if s.makespan != e["makespan"]:
                 return False
             got = {tuple(int(x) for x in s.tasks[t]): (int(s.proc[t]), int(s.start[t]), int(s.finish[t]))
@@ -160,6 +174,15 @@ def _pins_pass():
             r = O.simulate(pf4, 3, 1, 256, dep4, policy=(0, 0, 0, 2, 1))
             py = PY.Sim(3, 1, 256, dep4, pf4.proc_type, pf4.proc_mem, pf4.n_mem, pf4.rmax, pf4.h, pf4.shared_memory)
             if py.run(cache="WA", bus=True)[2] != list(r.start):
+                return False
+        # links of their own for the host and each accelerator, write-through,
+        # against the independent Python reading
+        pf6 = I.make_platform(I.cpu_accel_types(1, 2), seed=4)
+        for _ in range(6):
+            dep6 = rng.integers(0, 2, 10).astype(np.uint8)
+            r = O.simulate(pf6, 3, 1, 256, dep6, policy=(0, 0, 0, 1, 1), link=[0, 1, 2])
+            py = PY.Sim(3, 1, 256, dep6, pf6.proc_type, pf6.proc_mem, pf6.n_mem, pf6.rmax, pf6.h, pf6.shared_memory)
+            if py.run(cache="WT", bus=True, links=[0, 1, 2])[2] != list(r.start):
                 return False
         # finite accelerator space against the independent Python reading (a case
         # where the recency of use decides which block goes)
