@@ -110,7 +110,7 @@ def host_cpu_model() -> str:
 
 
 def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float, policy=(0, 0, 0, 0), tree: bool = False,
-                 capacity=None):
+                 capacity=None, link=None):
     """The oracle, as it stands, built -O2 -march=native on this host, on its
     cores: the whole timed batch when it fits the time budget (else its first
     candidates), plus a single-thread rate on a smaller prefix."""
@@ -121,20 +121,21 @@ def cpu_baseline(w, pf, batch_host, gpu_makespan, budget_s: float, policy=(0, 0,
     # calibrate the sample size with a small probe
     probe = batch_host.subset(range(min(64, batch_host.n)))
     t0 = time.perf_counter()
-    O.simulate_batch(pf, probe, cores, policy=policy, tree=tree, native=True, capacity=capacity)
+    O.simulate_batch(pf, probe, cores, policy=policy, tree=tree, native=True, capacity=capacity, link=link)
     dt = max(time.perf_counter() - t0, 1e-3)
     per_cand = dt / probe.n
     n = int(min(batch_host.n, max(probe.n, budget_s / per_cand)))
     sample = batch_host.subset(range(n))
     t0 = time.perf_counter()
-    ms, ntk = O.simulate_batch(pf, sample, cores, policy=policy, tree=tree, native=True, capacity=capacity)
+    ms, ntk = O.simulate_batch(pf, sample, cores, policy=policy, tree=tree, native=True, capacity=capacity,
+                               link=link)
     dt = time.perf_counter() - t0
     exact = bool(np.array_equal(ms, gpu_makespan[:n]))
     # one thread, about a tenth of the budget
     n1 = int(min(n, max(16, 0.1 * budget_s / (per_cand * cores))))
     t0 = time.perf_counter()
     _, ntk1 = O.simulate_batch(pf, batch_host.subset(range(n1)), 1, policy=policy, tree=tree, native=True,
-                               capacity=capacity)
+                               capacity=capacity, link=link)
     dt1 = time.perf_counter() - t0
     what = "the whole timed batch of step 0" if n == batch_host.n else f"the first {n} candidates of the timed batch of step 0"
     return {"value": float(ntk.sum()) / dt, "unit": "tasks/s", "cores": cores, "kind": "oracle",
@@ -622,6 +623,9 @@ def main():
                     help="order 0 PL / 1 FCFS, select 0 EFT-P / 1 EIT-P / 2 R-P / 3 F-P, cache 0 WB / 1 WT / 2 WA")
     ap.add_argument("--policy-seed", type=int, default=0)
     ap.add_argument("--bus", action="store_true", help="every transfer shares one interconnect")
+    ap.add_argument("--links", choices=["own", "switch"], default=None,
+                    help="transfers contend per link: every memory space on a link of its own, or the host "
+                         "on one and the accelerators behind one switch")
     ap.add_argument("--capacity-blocks", type=int, default=0,
                     help="finite accelerator spaces: finest blocks each one holds (0: unbounded)")
     ap.add_argument("--tree", action="store_true",
@@ -661,7 +665,12 @@ def main():
         # every accelerator space holds that many finest blocks (side b / 2^dmax)
         cap_bytes = np.zeros(pf_in.n_mem, np.int64)
         cap_bytes[1:] = args.capacity_blocks * pf_in.elem_bytes * (w.b >> w.dmax) ** 2
-    pf = H.Platform.from_inputs(pf_in, w.b, w.dmax, capacity_bytes=cap_bytes)
+    link = None
+    if args.links == "own":
+        link = np.arange(pf_in.n_mem, dtype=np.int32)
+    elif args.links == "switch":
+        link = np.array([0] + [1] * (pf_in.n_mem - 1), np.int32)
+    pf = H.Platform.from_inputs(pf_in, w.b, w.dmax, capacity_bytes=cap_bytes, link=link)
     thr = I.split_threshold(w.p_num, w.p_den)
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream()
@@ -684,7 +693,7 @@ def main():
         return H.generate_uniform(w.seed, i * n, n, w.nt, w.dmax, thr)
 
     order, select, cache = args.policy
-    bus = int(args.bus)
+    bus = int(args.bus or link is not None)
     gpol = (order, select, cache, args.policy_seed, bus)
 
     def sim(db):
@@ -758,7 +767,8 @@ def main():
 
     value = tasks_total / elapsed
     pname = (["PL", "FCFS"][order] + "/" + ["EFT-P", "EIT-P", "R-P", "F-P"][select] + "/" +
-             ["WB", "WT", "WA"][cache] + ("/shared interconnect" if bus else ""))
+             ["WB", "WT", "WA"][cache] + ("" if not bus else ("/shared interconnect" if link is None else
+                                                               f"/links {args.links} {link.tolist()}")))
     rec = {
         "metric": ("simulated tasks/sec (bit-exact PL/EFT-P makespans)" if pname == "PL/EFT-P/WB" else
                    f"simulated tasks/sec (bit-exact {pname} makespans)") + (", split-tree candidates" if args.tree else "")
@@ -804,7 +814,7 @@ def main():
         torch.cuda.synchronize()
         rec["cpu_baseline"] = cpu_baseline(w, pf_in, host0, ms.cpu().numpy(), args.cpu_budget,
                                            policy=(order, select, args.policy_seed, cache, bus), tree=args.tree,
-                                           capacity=cap_bytes)
+                                           capacity=cap_bytes, link=link)
         rec["gpu_vs_cpu"] = value / rec["cpu_baseline"]["value"]
     if args.copy_calib:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)

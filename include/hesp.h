@@ -113,6 +113,7 @@ typedef struct {
   const int64_t *cost_ns;      /* [n_ptypes][4][max_level+1], >= 1 */
   const int64_t *xfer_ns;      /* [4^max_level + 1], xfer_ns[0] = 0, non-decreasing */
   const int64_t *capacity;     /* [n_mem] or NULL: blocks of side b/2^max_level per space (above) */
+  const int32_t *link;         /* [n_mem] or NULL: link of the transfers into each space (hesp_policy.bus) */
 } hesp_platform;
 
 /* Heuristics of section 2.1 ("Task and data scheduling heuristics").  Tasks are
@@ -135,10 +136,14 @@ typedef struct {
  * only that host copy.  A missing block's transfer starts at the mapping time,
  * or once every missing finest block has a valid copy somewhere (write-around:
  * its host copy may still be in flight).  Other values give HESP_EUNSUPPORTED.
- * bus = 1: every transfer uses one shared interconnect, one at a time in issue
- * order (the missing blocks of a task in their order; write-through and
- * write-around host copies queue at the completion); the EFT-P estimate sees the
- * queue.  bus = 0: transfers do not contend. */
+ * bus = 1: transfers contend (section 2: the spaces are connected by a network
+ * topology): a transfer occupies the link of the space it goes into,
+ * hesp_platform.link[m] (0..n_mem-1; spaces naming the same link share it;
+ * NULL: one interconnect shared by every transfer), one transfer at a time per
+ * link in issue order (the missing blocks of a task in their order;
+ * write-through and write-around host copies queue on the host's link at the
+ * completion); the EFT-P estimate sees each link's queue.  An out-of-range link
+ * gives HESP_EINVAL.  bus = 0: transfers do not contend (link is ignored). */
 #define HESP_ORDER_PL 0
 #define HESP_ORDER_FCFS 1
 #define HESP_SELECT_EFT 0
@@ -151,7 +156,7 @@ typedef struct {
 typedef struct {
   int32_t order, select, cache;
   uint64_t seed;               /* R-P draws */
-  int32_t bus;                 /* 0 or 1: one shared interconnect */
+  int32_t bus;                 /* 0 or 1: transfers contend on their links */
 } hesp_policy;
 
 /* ---- expansion of one candidate (host) ----------------------------------------

@@ -426,6 +426,11 @@ static int build_tables(const hesp_platform* pf, SimTables& t) {
     t.capacity[m] = (m > 0 && m < pf->n_mem && pf->capacity && pf->capacity[m] > 0) ? pf->capacity[m] : -1;
     if (t.capacity[m] >= 0) t.capped = 1;
   }
+  for (int m = 0; m < pf->n_mem; m++) {
+    if (pf->link && (pf->link[m] < 0 || pf->link[m] >= pf->n_mem))
+      return fail(HESP_EINVAL, "hesp_simulate_batch: link[%d] must be in 0..n_mem-1", m);
+    t.link[m] = pf->link ? (int8_t)pf->link[m] : 0;
+  }
   return HESP_OK;
 }
 

@@ -250,6 +250,8 @@ struct Grp {
     if (G == 64) return rdl64(v, __builtin_amdgcn_readfirstlane(j));
     return __shfl(v, gbase + j, kWave);
   }
+  // the value of group lane j, j chosen per lane (all lanes of the group active)
+  __device__ __forceinline__ int64_t read64(int64_t v, int j) const { return __shfl(v, gbase + j, kWave); }
   // a value known to be uniform inside the group (scalar for a whole-wave group)
   __device__ __forceinline__ int uni(int v) const { return G == 64 ? __builtin_amdgcn_readfirstlane(v) : v; }
   __device__ __forceinline__ int64_t uni64(int64_t v) const { return G == 64 ? rdl64(v, 0) : v; }

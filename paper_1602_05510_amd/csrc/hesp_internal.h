@@ -26,7 +26,8 @@ struct SimTables {
                                           // 3 fastest idle (2, 3: tasks wait while no processor is idle)
   uint64_t seed;                          // random choices (SplitMix64)
   int32_t cache;                          // written blocks: 0 write-back, 1 write-through, 2 write-around
-  int32_t bus;                            // 1: transfers share one interconnect, one at a time
+  int32_t bus;                            // 1: transfers contend, one at a time on each link
+  int8_t link[kMaxMem];                   // link carrying the transfers into each memory space
   int32_t capped;                         // 1: some space has a finite capacity
   int64_t capacity[kMaxMem];              // blocks of side b/2^max_level; -1: unbounded
 };

@@ -763,6 +763,8 @@ __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_s
   const int P = tb.n_procs, M = tb.n_mem;
   const bool p16 = P <= 16;                    // processor lanes all in the group's first row
   const int pmem = gl < P ? tb.proc_mem[gl] : 0;
+  const int plink = gl < P ? tb.link[pmem] : 0;   // the link of the transfers into the lane's space
+  const int hlink = tb.link[0];                   // and into the host's
   const int ptype = gl < P ? tb.proc_type[gl] : 0;
   const bool want_sched = out.sched_off != nullptr;
 
@@ -771,7 +773,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_s
   int64_t n_atoms = 0;                        // finite spaces: the candidate's finest blocks
   CandPtrs sp{};
   int64_t avail = 0, hfin = kInf;
-  int64_t bus_free = 0;                       // shared interconnect: free from this time
+  int64_t lfree = 0;                          // link contention: lane l < n_mem holds when link l is free
   // queue head of processor lane: task, finish, completion word, successor edges
   uint32_t hid = kNil, hcw = 0, he0 = 0, he1 = 0, tail = kNil;
 
@@ -819,7 +821,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_s
             sbase = want_sched ? out.sched_off[c] : 0;
             T = 0;
             avail = 0;
-            bus_free = 0;
+            lfree = 0;
             hfin = kInf;
             hid = kNil;
             tail = kNil;
@@ -886,7 +888,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_s
       sbase = want_sched ? out.sched_off[c] : 0;
       T = 0;
       avail = 0;
-      bus_free = 0;
+      lfree = 0;
       hfin = kInf;
       hid = kNil;
       tail = kNil;

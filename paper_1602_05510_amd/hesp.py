@@ -31,7 +31,7 @@ class CostModel(ctypes.Structure):
 
 class PlatformC(ctypes.Structure):
     _fields_ = [("n_procs", i32), ("n_ptypes", i32), ("n_mem", i32), ("max_level", i32),
-                ("proc_type", P), ("proc_mem", P), ("cost_ns", P), ("xfer_ns", P), ("capacity", P)]
+                ("proc_type", P), ("proc_mem", P), ("cost_ns", P), ("xfer_ns", P), ("capacity", P), ("link", P)]
 
 
 class Policy(ctypes.Structure):
@@ -206,9 +206,12 @@ def cost_tables(rmax_mflops: np.ndarray, h: np.ndarray, b: int, max_level: int, 
 class Platform:
     """A platform with its cost tables (host arrays kept alive for the C structs)."""
 
-    def __init__(self, proc_type, proc_mem, n_mem: int, cost: np.ndarray, xfer: np.ndarray, capacity=None):
+    def __init__(self, proc_type, proc_mem, n_mem: int, cost: np.ndarray, xfer: np.ndarray, capacity=None,
+                 link=None):
         """capacity: None or [n_mem] blocks of side b / 2^max_level each space
-        holds (<= 0 and the host's entry: unbounded)."""
+        holds (<= 0 and the host's entry: unbounded).  link: None (one
+        interconnect) or [n_mem] link ids 0..n_mem-1 of the transfers into each
+        space, used when the policy's bus flag is set."""
         self.proc_type = np.ascontiguousarray(proc_type, dtype=np.int32)
         self.proc_mem = np.ascontiguousarray(proc_mem, dtype=np.int32)
         self.n_mem = int(n_mem)
@@ -216,21 +219,27 @@ class Platform:
         self.xfer = np.ascontiguousarray(xfer, dtype=np.int64)
         self.max_level = self.cost.shape[2] - 1
         self.capacity = None if capacity is None else np.ascontiguousarray(capacity, dtype=np.int64)
+        self.link = None if link is None else np.ascontiguousarray(link, dtype=np.int32)
+        if self.link is not None and self.link.shape != (self.n_mem,):
+            raise HespError("Platform", HESP_EINVAL, f"link needs {self.n_mem} entries")
+        if self.capacity is not None and self.capacity.shape != (self.n_mem,):
+            raise HespError("Platform", HESP_EINVAL, f"capacity needs {self.n_mem} entries")
         self.c = PlatformC(len(self.proc_type), self.cost.shape[0], self.n_mem, self.max_level,
                            _np(self.proc_type), _np(self.proc_mem), _np(self.cost), _np(self.xfer),
-                           _np(self.capacity))
+                           _np(self.capacity), _np(self.link))
 
     @classmethod
-    def from_inputs(cls, pf, b: int, max_level: int, capacity_bytes=None) -> "Platform":
+    def from_inputs(cls, pf, b: int, max_level: int, capacity_bytes=None, link=None) -> "Platform":
         """From a drawn platform of ``inputs.make_platform``; capacity_bytes
-        ([n_mem] or None) becomes whole blocks of side b / 2^max_level."""
+        ([n_mem] or None) becomes whole blocks of side b / 2^max_level; link as
+        in the constructor."""
         cost, xfer = cost_tables(pf.rmax, pf.h, b, max_level, pf.latency_ns, pf.bw_bytes_per_ns,
                                  pf.elem_bytes, pf.shared_memory)
         cap = None
         if capacity_bytes is not None:
             blk = pf.elem_bytes * (b >> max_level) ** 2
             cap = np.array([c // blk if c > 0 else 0 for c in capacity_bytes], np.int64)
-        return cls(pf.proc_type, pf.proc_mem, pf.n_mem, cost, xfer, cap)
+        return cls(pf.proc_type, pf.proc_mem, pf.n_mem, cost, xfer, cap, link)
 
 
 # ----------------------------------------------------------------- expansion
