@@ -51,7 +51,8 @@ extern "C" {
 #define HESP_MAX_PROCS 64   /* processors of a platform (one wavefront lane each) */
 #define HESP_MAX_PTYPES 8   /* processor types */
 #define HESP_MAX_MEM 16     /* memory spaces (space 0 is the host) */
-#define HESP_MAX_LEVEL 3    /* split depth per task: block sides b, b/2, b/4, b/8 */
+#define HESP_MAX_LEVEL 5    /* split depth per task: block sides b, b/2, ..., b/32 */
+#define HESP_MAX_SEARCH_LEVEL 3  /* split trees, hesp_solve*, hesp_search, enumeration: b .. b/8 */
 #define HESP_MAX_FINE 512   /* nt * 2^dmax, the finest tile count per dimension */
 
 const char *hesp_last_error(void);
@@ -190,7 +191,9 @@ typedef struct {
 /* Candidate generation from counters (SplitMix64, Steele/Lea/Flood 2014): the
  * depth of top-level task t of candidate `first + c` is the number of leading
  * 21-bit chunks of the 64-bit value drawn for index ((first+c) << 24 | t) that
- * fall below split_thr (P(split) = split_thr / 2^21), capped at dmax. */
+ * fall below split_thr (P(split) = split_thr / 2^21), capped at dmax; past the
+ * third, the chunks of the value drawn with purpose 6 for the same index
+ * continue the count (depths 4 and 5). */
 int hesp_generate_uniform(uint64_t seed, int64_t first, int32_t n_cand, int32_t nt, int32_t dmax,
                           uint32_t split_thr, uint8_t *d_depth, void *stream);
 /* Ragged shapes: nt_c = nt_lo + u mod (nt_hi-nt_lo+1), dmax_c = (u >> 32) mod (dmax_hi+1)
@@ -262,7 +265,16 @@ int hesp_plan_last_ms(hesp_plan *plan, double *ms);
  * prefix sums of hesp_count_batch's n_tasks), the processor, start and finish
  * of every task are written at d_sched_off[c] + (task number of hesp_expand).
  * A plan with max_tasks = 0 sizes its workspace from the batch, which reads two
- * counts back to the host (one synchronisation of `stream`). */
+ * counts back to the host (one synchronisation of `stream`).
+ * Depths: up to HESP_MAX_LEVEL (block sides down to b/32, the deepest DAGs of
+ * section 3).  A batch whose dmax (its maximum) is above 3 runs with 16 or 32
+ * lanes per candidate, so it takes at most 32 processors, no finite memory
+ * spaces and the unfused pipeline (else HESP_EUNSUPPORTED; a plan forcing 64
+ * lanes gives HESP_EINVAL).  A ragged candidate above the batch's nt or dmax
+ * gets HESP_EINVAL.  A platform with max_level above 3 has more transfer times
+ * than the kernels take by value: the plan keeps a device copy of xfer_ns (made
+ * on `stream`, after it drains, whenever the table differs from the last one);
+ * a captured call needs that copy to exist already (else HESP_EUNSUPPORTED). */
 typedef struct {
   int64_t *d_makespan;         /* [n_cand] */
   int32_t *d_status;           /* [n_cand] */
@@ -289,6 +301,8 @@ int hesp_simulate_batch(hesp_plan *plan, const hesp_platform *pf, hesp_policy po
  * candidate whose workspace would end past HESP_NOALLOC_REGION bytes gets
  * HESP_ECAPACITY (makespan -1), as do all candidates after it.  group: lanes
  * per candidate (16, 32, 64, at least n_procs), 0 = the smallest that fits.
+ * Platforms with max_level above 3, finite spaces, and depths above 3 in
+ * 64-lane groups give HESP_EUNSUPPORTED.
  * All calls on one device share the array: calls that overlap in time on one
  * device (different streams or host threads) race and give wrong results. */
 #define HESP_NOALLOC_BYTES (64 << 20)
@@ -312,6 +326,7 @@ int hesp_simulate_batch_noalloc(const hesp_platform *pf, hesp_policy policy, con
  * Schedule outputs number the tasks in program order: top-level tasks in Fig. 1
  * order, each split task replaced in place by its children in the order of the
  * Fig. 1 loop nest restricted to its 2 x 2 sub-tiling, recursively.
+ * Split trees take dmax <= HESP_MAX_SEARCH_LEVEL.
  * hesp_simulate_tree_batch behaves as hesp_simulate_batch (outputs, statuses,
  * fixed-capacity plans; HESP_EINVAL for a flag above 1); it also keeps a
  * last-writer table of 4 bytes per finest block and candidate in the plan.
@@ -425,6 +440,7 @@ int hesp_topk_score(const float *d_score, int32_t n, int32_t k, int32_t *d_idx, 
  * trace[rounds] (host, nullable) gets, after each round, the wall time since the
  * start, the best makespan, and the simulated and proposed candidate counts
  * (each round synchronises `stream`).  Device workspace is allocated per call.
+ * The search takes dmax <= HESP_MAX_SEARCH_LEVEL on platforms with max_level <= 3.
  * The plan must not limit tasks or edges per candidate (HESP_EINVAL), so that
  * every proposal gets a makespan. */
 enum { HESP_SEARCH_RANDOM = 0, HESP_SEARCH_GREEDY = 1, HESP_SEARCH_SURROGATE = 2 };
@@ -486,7 +502,7 @@ int hesp_search(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy, co
  * (cluster, new depth, score; cluster -1 when none).  A chain whose simulation
  * fails (a depth above dmax, or above a fixed-capacity plan) gets -1 in its
  * trace and keeps makespan -1 if it never succeeded.  Limits: tet(nt) <= 4096,
- * n_procs <= 64.  Device workspace is allocated per call (n_chains x
+ * n_procs <= 64, dmax <= HESP_MAX_SEARCH_LEVEL, platform max_level <= 3.  Device workspace is allocated per call (n_chains x
  * tet(nt 2^dmax) tasks); the call synchronises `stream` before it returns. */
 #define HESP_LIST_ALL 0
 #define HESP_LIST_CP 1

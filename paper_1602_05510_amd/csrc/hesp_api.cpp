@@ -95,6 +95,10 @@ struct hesp_plan {
   // per batch
   DevBuf cnt_tasks, cnt_edges, off_t, off_e, off_v, off_top, bounds, layout_part;
   DevBuf tree_lw;             // split-tree counts: last writer per finest block and candidate
+  // transfer times of platforms deeper than kXferLevels: the device copy and the
+  // host table it was made from
+  DevBuf xfer_deep;
+  std::vector<int64_t> xfer_host;
   // per chunk, two sets: chunk i+1 is prepared while chunk i is simulated
   WorkSet ws[2];
   hipStream_t s_prep = nullptr, s_sim = nullptr;
@@ -116,11 +120,14 @@ struct hesp_plan {
   size_t ev_used = 0;
   int64_t held() const {
     return cnt_tasks.bytes + cnt_edges.bytes + off_t.bytes + off_e.bytes + off_v.bytes + off_top.bytes +
-           bounds.bytes + layout_part.bytes + tree_lw.bytes + arena.bytes + ws[0].bytes() + ws[1].bytes();
+           bounds.bytes + layout_part.bytes + tree_lw.bytes + arena.bytes + xfer_deep.bytes + ws[0].bytes() +
+           ws[1].bytes();
   }
   void release() {
-    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds, &layout_part, &tree_lw, &arena})
+    for (DevBuf* b : {&cnt_tasks, &cnt_edges, &off_t, &off_e, &off_v, &off_top, &bounds, &layout_part, &tree_lw, &arena,
+                      &xfer_deep})
       b->release();
+    xfer_host.clear();
     for (WorkSet& w : ws)
       for (DevBuf* d : w.all()) d->release();
   }
@@ -274,9 +281,10 @@ static int batch_view(const hesp_batch* b, BatchView& v, const char* who) {
 
 static int tree_view(const hesp_tree_batch* b, BatchView& v, const char* who) {
   if (!b) return fail(HESP_EINVAL, "%s: null batch", who);
-  if (b->n_cand < 0 || b->nt < 1 || b->dmax < 0 || b->dmax > HESP_MAX_LEVEL || (b->nt << b->dmax) > HESP_MAX_FINE)
-    return fail(HESP_EINVAL, "%s: n_cand=%d nt=%d dmax=%d outside the supported range", who, b->n_cand, b->nt,
-                b->dmax);
+  if (b->n_cand < 0 || b->nt < 1 || b->dmax < 0 || b->dmax > HESP_MAX_SEARCH_LEVEL ||
+      (b->nt << b->dmax) > HESP_MAX_FINE)
+    return fail(HESP_EINVAL, "%s: n_cand=%d nt=%d dmax=%d outside the supported range (split trees: dmax <= %d)",
+                who, b->n_cand, b->nt, b->dmax, HESP_MAX_SEARCH_LEVEL);
   const int64_t nf = hesp_tree_flag_count(b->nt, b->dmax);
   if (b->n_cand > 0 && nf > 0 && !b->d_flags) return fail(HESP_EINVAL, "%s: null flags", who);
   v.n_cand = b->n_cand;
@@ -420,8 +428,9 @@ static int build_tables(const hesp_platform* pf, SimTables& t) {
   for (int64_t k = 0; k < nx; k++) {
     if (pf->xfer_ns[k] < 0 || pf->xfer_ns[k] > ((int64_t)1 << 40) || (k > 0 && pf->xfer_ns[k] < pf->xfer_ns[k - 1]))
       return fail(HESP_EINVAL, "hesp_simulate_batch: xfer_ns must be non-decreasing and in range");
-    t.xfer[k] = pf->xfer_ns[k];
+    if (k < kXferLen) t.xfer[k] = pf->xfer_ns[k];
   }
+  t.xfer_deep = nullptr;   // set by the caller for tables deeper than kXferLevels
   for (int m = 0; m < kMaxMem; m++) {
     t.capacity[m] = (m > 0 && m < pf->n_mem && pf->capacity && pf->capacity[m] > 0) ? pf->capacity[m] : -1;
     if (t.capacity[m] >= 0) t.capped = 1;
@@ -595,6 +604,14 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
   // lanes per candidate: forced by the plan, or timed once per batch shape on a
   // sub-batch of the first chunk (outputs of that sub-batch are rewritten below)
   int group = plan->opts.group;
+  // whole-wave groups take depths up to kMaxWaveLevel; deeper batches run in 16- or
+  // 32-lane groups
+  const bool deep = bv.dmax > kMaxWaveLevel;
+  if (deep && (tb.capped || pf->n_procs > 32))
+    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: depths above %d take at most 32 processors and no finite "
+                                   "memory spaces", kMaxWaveLevel);
+  if (deep && group == 64)
+    return fail(HESP_EINVAL, "hesp_simulate_batch: 64 lanes per candidate take depths up to %d", kMaxWaveLevel);
   if (tb.capped) {
     // finite spaces: the event loop keeps its per-space state in whole-wave groups
     if (group != 0 && group != 64)
@@ -613,7 +630,7 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
       HIP_TRY(hipEventCreate(&e0));
       HIP_TRY(hipEventCreate(&e1));
       for (int G : {16, 32, 64}) {
-        if (G < pf->n_procs) continue;
+        if (G < pf->n_procs || (deep && G == kWave)) continue;
         ChunkView cv = chunk_view(0, sub, 0);
         HIP_TRY(prepare(cv, s));
         HIP_TRY(hipEventRecord(e0, s));
@@ -782,6 +799,30 @@ static int run_fused(hesp_plan* plan, const SimTables& tb, BatchView bv, const O
   return ok();
 }
 
+// Transfer times beyond the first kXferLen entries (platforms deeper than
+// kXferLevels): a device copy held by the plan, made on the call's stream and
+// remade only when the table changes (after the stream has drained, so that no
+// earlier copy still reads the host table).  A captured call finds the copy made
+// by an earlier call on the same table, or fails.
+static int deep_xfer(hesp_plan* plan, const hesp_platform* pf, SimTables& tb, hipStream_t s) {
+  const int64_t nx = pow4(pf->max_level) + 1;
+  if ((int64_t)plan->xfer_host.size() != nx ||
+      memcmp(plan->xfer_host.data(), pf->xfer_ns, (size_t)nx * sizeof(int64_t)) != 0) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone)
+      return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: a captured call on a platform with max_level above %d "
+                                     "needs an earlier call with the same transfer table", kXferLevels);
+    HIP_TRY(hipStreamSynchronize(s));
+    plan->xfer_host.assign(pf->xfer_ns, pf->xfer_ns + nx);
+    HIP_TRY(plan->xfer_deep.ensure(8 * (pow4(kMaxLevel) + 1)));
+    HIP_TRY(hipMemcpyAsync(plan->xfer_deep.p, plan->xfer_host.data(), (size_t)nx * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+  }
+  tb.xfer_deep = plan->xfer_deep.as<int64_t>();
+  return HESP_OK;
+}
+
 // depth batches (batch) or split-tree batches (tree)
 static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, const hesp_batch* batch,
                         const hesp_tree_batch* tree, const hesp_outputs* out, void* stream) {
@@ -794,6 +835,8 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   if (n == 0) return ok();
   hipStream_t s = (hipStream_t)stream;
   const OutView ov = ov_of(out);
+  if (tb.max_level > kXferLevels)
+    if (int r = deep_xfer(plan, pf, tb, s)) return r;
 
   // exact sizes of every candidate
   HIP_TRY(plan->cnt_tasks.ensure(4 * (int64_t)n));
@@ -811,6 +854,8 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   if (plan->opts.fuse) {
     if (is_tree) return fail(HESP_EUNSUPPORTED, "hesp_simulate_tree_batch: the fused pipeline takes depth batches");
     if (tb.capped) return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: the fused pipeline has no finite spaces");
+    if (bv.dmax > kMaxWaveLevel)
+      return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: the fused pipeline takes depths up to %d", kMaxWaveLevel);
     if (pf->n_procs > 64) return fail(HESP_EINVAL, "hesp_simulate_batch: more than 64 processors");
     return run_fused(plan, tb, bv, ov, s, n);
   }
@@ -830,7 +875,7 @@ int hesp_simulate_tree_batch(hesp_plan* plan, const hesp_platform* pf, hesp_poli
 }
 
 int64_t hesp_tree_flag_count(int32_t nt, int32_t dmax) {
-  if (nt < 1 || dmax < 0 || dmax > HESP_MAX_LEVEL) return -1;
+  if (nt < 1 || dmax < 0 || dmax > HESP_MAX_SEARCH_LEVEL) return -1;
   int64_t n = 0;
   for (int l = 0; l < dmax; l++) n += tet3((int64_t)nt << l);
   return n;

@@ -4,14 +4,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hesp_core.h"
+
 namespace hesp {
 
 constexpr int kWave = 64;
 constexpr int kMaxProcs = 64;
 constexpr int kMaxPtypes = 8;
 constexpr int kMaxMem = 16;
-constexpr int kLevels = 4;                 // levels 0..3
+constexpr int kLevels = kMaxLevel + 1;     // levels 0..5
+constexpr int kXferLevels = 3;             // transfer times passed by value: up to 4^3 finest blocks
 constexpr int kXferLen = 65;               // 4^3 + 1
+static_assert(kXferLen == (1 << (2 * kXferLevels)) + 1, "transfer times passed by value");
 
 // Platform tables passed by value as a kernel argument (about 1.8 KB).
 struct SimTables {
@@ -20,7 +24,8 @@ struct SimTables {
   int8_t proc_mem[kMaxProcs];
   int64_t cost[kMaxPtypes][4][kLevels];   // task time, ns
   int64_t W[4][kLevels];                  // sum of the task time over all processors
-  int64_t xfer[kXferLen];                 // transfer time by number of finest blocks
+  int64_t xfer[kXferLen];                 // transfer time by number of finest blocks (the first 65)
+  const int64_t* xfer_deep;               // device copy of all 4^max_level + 1, when max_level > 3
   int32_t fcfs;                           // task order: 0 Priority-List, 1 first released first
   int32_t sel;                            // processor: 0 earliest finish, 1 earliest idle, 2 random idle,
                                           // 3 fastest idle (2, 3: tasks wait while no processor is idle)

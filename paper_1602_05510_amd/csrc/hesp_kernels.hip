@@ -54,19 +54,24 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
-constexpr int kPurposeDepth = 2, kPurposeShape = 3, kPurposeTree = 5;
+constexpr int kPurposeDepth = 2, kPurposeShape = 3, kPurposeTree = 5, kPurposeDepth2 = 6;
 
 __device__ __forceinline__ uint64_t draw(uint64_t seed, int purpose, uint64_t idx) {
   const uint64_t s = mix64(seed + kGamma * (uint64_t)(purpose + 1));
   return mix64(s + kGamma * (idx + 1));
 }
 
-__device__ __forceinline__ uint8_t depth_of_draw(uint64_t u, uint32_t thr, int dmax) {
+// leading 21-bit chunks below thr, capped at dmax: three of the value drawn for
+// idx, then (depths 4 and 5) three of a second value drawn for the same idx
+__device__ __forceinline__ uint8_t depth_of_draw(uint64_t seed, uint64_t idx, uint32_t thr, int dmax) {
   int d = 0;
-  for (int j = 0; j < 3 && d < dmax; j++) {
-    const uint32_t ch = (uint32_t)((u >> (21 * j)) & 0x1FFFFFull);
-    if (ch < thr) d++;
-    else break;
+  for (int half = 0; half < 2 && d == 3 * half && d < dmax; half++) {
+    const uint64_t u = draw(seed, half ? kPurposeDepth2 : kPurposeDepth, idx);
+    for (int j = 0; j < 3 && d < dmax; j++) {
+      const uint32_t ch = (uint32_t)((u >> (21 * j)) & 0x1FFFFFull);
+      if (ch < thr) d++;
+      else break;
+    }
   }
   return (uint8_t)d;
 }
@@ -77,8 +82,7 @@ __global__ void k_gen_uniform(uint64_t seed, int64_t first, int32_t n_cand, int3
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
        x += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = x / n_top, t = x % n_top;
-    const uint64_t u = draw(seed, kPurposeDepth, ((uint64_t)(first + c) << 24) | (uint64_t)t);
-    depth[x] = depth_of_draw(u, thr, dmax);
+    depth[x] = depth_of_draw(seed, ((uint64_t)(first + c) << 24) | (uint64_t)t, thr, dmax);
   }
 }
 
@@ -142,8 +146,7 @@ __global__ void k_gen_ragged_depth(uint64_t seed, int64_t first, BatchView b, ui
   const int nt = b.nt_arr[c], dmax = b.dmax_arr[c];
   const int64_t n_top = tet3(nt), o = b.off[c];
   for (int64_t t = threadIdx.x; t < n_top; t += blockDim.x) {
-    const uint64_t u = draw(seed, kPurposeDepth, ((uint64_t)(first + c) << 24) | (uint64_t)t);
-    depth[o + t] = depth_of_draw(u, thr, dmax);
+    depth[o + t] = depth_of_draw(seed, ((uint64_t)(first + c) << 24) | (uint64_t)t, thr, dmax);
   }
 }
 

@@ -92,8 +92,12 @@ extern "C" int hesp_simulate_batch_noalloc(const hesp_platform* pf, hesp_policy 
   BatchView bv;
   if (int r = hesp_internal_batch_setup(pf, policy, batch, nullptr, out, tb, bv)) return r;
   if (tb.capped) return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch_noalloc: no finite memory spaces");
+  if (tb.max_level > kXferLevels)
+    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch_noalloc: platform tables of at most 3 levels");
   if (group == 0) group = tb.n_procs <= 16 ? 16 : (tb.n_procs <= 32 ? 32 : 64);
   if (group < tb.n_procs) return fail(HESP_EINVAL, "hesp_simulate_batch_noalloc: group below the processor count");
+  if (bv.dmax > kMaxWaveLevel && group == kWave)
+    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch_noalloc: depths above 3 take 16 or 32 lanes per candidate");
   const int n = bv.n_cand;
   if (n == 0) return HESP_OK;
   DevInfo d;

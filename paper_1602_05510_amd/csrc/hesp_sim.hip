@@ -432,7 +432,11 @@ __device__ __forceinline__ int prepare_cand(const SimTables& tb, const BatchView
   const Cand cd = load_cand(bv, c);
   const int nt = cd.nt, dmax = cd.dmax, M = tb.n_mem;
   int status = kOK;
-  if (nt < 1 || dmax < 0 || dmax > kMaxLevel || dmax > tb.max_level || (nt << dmax) > kMaxFine) status = kEINVAL;
+  // a ragged candidate above the batch's stated maxima is refused too (the
+  // maxima choose the lanes per candidate)
+  if (nt < 1 || dmax < 0 || dmax > kMaxLevel || dmax > tb.max_level || (nt << dmax) > kMaxFine || dmax > bv.dmax ||
+      nt > bv.nt)
+    status = kEINVAL;
   if (status == kOK && cap) status = kECAP;
 
   // pass A: first fine task of every top-level task; depths above dmax
@@ -531,7 +535,7 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare(SimTables tb, BatchView bv
 // (the walk over a candidate's tasks and the last-writer scan: hesp_tree.h)
 
 __device__ __forceinline__ bool tree_shape_ok(int nt, int dmax) {
-  return nt >= 1 && dmax >= 0 && dmax <= kMaxLevel && (nt << dmax) <= kMaxFine;
+  return nt >= 1 && dmax >= 0 && dmax <= kMaxSearchLevel && (nt << dmax) <= kMaxFine;
 }
 
 // exact task and edge counts of every split-tree candidate
@@ -728,7 +732,9 @@ __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_s
   const int cache = (POL == 0 || CAP) ? 0 : tb.cache;
   const bool bus = POL != 0 && !CAP && tb.bus != 0;
   constexpr int LGG = G == 16 ? 4 : (G == 32 ? 5 : 6);
-  __shared__ int64_t s_cost[kMaxPtypes][4][kLevels];
+  // task times of the levels the groups can meet (whole-wave groups: 0..3)
+  constexpr int kSimLevels = G == kWave ? kMaxWaveLevel + 1 : kLevels;
+  __shared__ int64_t s_cost[kMaxPtypes][4][kSimLevels];
   __shared__ int64_t s_xfer[kXferLen];
   __shared__ int64_t s_W[FUSED ? 4 : 1][kLevels];
   using Lds = std::conditional_t<(FUSED != 0), SimPrepLds<G, POL>, SimLds<G, POL>>;
@@ -754,8 +760,13 @@ __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_s
 
   const Grp<G> gp;
   const int l = gp.l, g = gp.g, gl = gp.gl;
-  for (int x = l; x < kMaxPtypes * 4 * kLevels; x += kWave) (&s_cost[0][0][0])[x] = (&tb.cost[0][0][0])[x];
+  for (int x = l; x < kMaxPtypes * 4 * kSimLevels; x += kWave)
+    (&s_cost[0][0][0])[x] = tb.cost[x / (4 * kSimLevels)][(x / kSimLevels) % 4][x % kSimLevels];
   for (int x = l; x < kXferLen; x += kWave) s_xfer[x] = tb.xfer[x];
+  // transfer time of i finest blocks of side b / 2^max_level: the first kXferLen
+  // from LDS, the rest (platforms deeper than kXferLevels) from device memory
+  const int64_t* const xdeep = tb.xfer_deep;
+  auto xfer = [&](int64_t i) -> int64_t { return i < kXferLen ? s_xfer[i] : xdeep[i]; };
   if (FUSED)
     for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
   __syncthreads();

@@ -70,7 +70,7 @@ static int solve_setup(hesp_plan* plan, const hesp_platform* pf, const hesp_solv
                        solve::SolveTables& tb) {
   if (!plan || !pf || !sp) return fail(HESP_EINVAL, "%s: null plan, platform or parameters", who);
   const int B = sp->n_chains, nt = sp->nt, dmax = sp->dmax;
-  if (B < 1 || B > 65535 || nt < 1 || dmax < 0 || dmax > kMaxLevel || (nt << dmax) > kMaxFine || sp->iters < 1)
+  if (B < 1 || B > 65535 || nt < 1 || dmax < 0 || dmax > kMaxSearchLevel || (nt << dmax) > kMaxFine || sp->iters < 1)
     return fail(HESP_EINVAL, "%s: need 1 <= n_chains <= 65535, nt >= 1, 0 <= dmax <= 3, iters >= 1", who);
   if (sp->list < HESP_LIST_ALL || sp->list > HESP_LIST_SHALLOW || sp->sampling < HESP_SAMPLE_HARD ||
       sp->sampling > HESP_SAMPLE_SOFT)
@@ -79,7 +79,7 @@ static int solve_setup(hesp_plan* plan, const hesp_platform* pf, const hesp_solv
   if (!d_part || !d_best || !d_best_makespan) return fail(HESP_EINVAL, "%s: null outputs", who);
   if (pf->n_procs < 1 || pf->n_procs > std::min<int>(HESP_MAX_PROCS, solve::kMaxP) || pf->n_ptypes < 1 ||
       pf->n_ptypes > std::min<int>(HESP_MAX_PTYPES, solve::kMaxTypes) || pf->max_level < dmax ||
-      pf->max_level > HESP_MAX_LEVEL || !pf->proc_type || !pf->cost_ns)
+      pf->max_level > kMaxSearchLevel || !pf->proc_type || !pf->cost_ns)
     return fail(HESP_EINVAL, "%s: bad platform description (or dmax above its max_level)", who);
   memset(&tb, 0, sizeof tb);
   tb.n_procs = pf->n_procs;
@@ -193,7 +193,7 @@ int hesp_solve_tree(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy
                     int64_t* d_steps, void* stream) {
   if (!sp) return fail(HESP_EINVAL, "hesp_solve_tree: null parameters");
   const int B = sp->n_chains, nt = sp->nt, dmax = sp->dmax;
-  if (dmax < 1 || nt < 1 || dmax > kMaxLevel)
+  if (dmax < 1 || nt < 1 || dmax > kMaxSearchLevel)
     return fail(HESP_EINVAL, "hesp_solve_tree: need 1 <= dmax <= 3 (the clusters are the tasks above the last level)");
   const int64_t nn = hesp_tree_flag_count(nt, dmax);
   solve::SolveTables tb;

@@ -46,6 +46,7 @@ P_DEPTH = 2
 P_SHAPE = 3
 P_PLATFORM = 4
 P_TREE = 5
+P_DEPTH2 = 6      # chunks 3..5 of a depth draw (depths 4 and 5)
 
 CHUNK_BITS = 21  # one split draw uses 21 random bits; depth <= 3 uses 63 bits
 
@@ -90,17 +91,19 @@ def split_threshold(p_num: int, p_den: int) -> int:
     return (p_num << CHUNK_BITS) // p_den
 
 
-def depth_from_draw(u: np.ndarray, thr: int, dmax: np.ndarray) -> np.ndarray:
-    """Number of leading 21-bit chunks below ``thr``, capped at ``dmax``."""
+def depth_from_draw(u: np.ndarray, thr: int, dmax: np.ndarray, u2=None) -> np.ndarray:
+    """Number of leading 21-bit chunks below ``thr``, capped at ``dmax``: the
+    three chunks of ``u``, then (depths 4 and 5) the three of ``u2``."""
     u = np.asarray(u, dtype=np.uint64)
     dmax = np.broadcast_to(np.asarray(dmax, dtype=np.int64), u.shape)
     depth = np.zeros(u.shape, dtype=np.int64)
     alive = np.ones(u.shape, dtype=bool)
-    for j in range(3):
-        chunk = (u >> np.uint64(CHUNK_BITS * j)) & np.uint64((1 << CHUNK_BITS) - 1)
-        ok = alive & (chunk < np.uint64(thr)) & (depth < dmax)
-        depth += ok
-        alive &= ok
+    for v in ([u] if u2 is None else [u, np.asarray(u2, dtype=np.uint64)]):
+        for j in range(3):
+            chunk = (v >> np.uint64(CHUNK_BITS * j)) & np.uint64((1 << CHUNK_BITS) - 1)
+            ok = alive & (chunk < np.uint64(thr)) & (depth < dmax)
+            depth += ok
+            alive &= ok
     return depth.astype(np.uint8)
 
 
@@ -248,8 +251,10 @@ def uniform_batch(seed: int, n_cand: int, nt: int, b: int, dmax: int, p_num: int
     thr = split_threshold(p_num, p_den)
     c = np.arange(first, first + n_cand, dtype=np.uint64)[:, None]
     t = np.arange(n_top, dtype=np.uint64)[None, :]
-    u = draw_np(seed, P_DEPTH, (c << np.uint64(24)) | t)
-    depth = depth_from_draw(u, thr, dmax).reshape(-1)
+    idx = (c << np.uint64(24)) | t
+    u = draw_np(seed, P_DEPTH, idx)
+    u2 = draw_np(seed, P_DEPTH2, idx) if dmax > 3 else None
+    depth = depth_from_draw(u, thr, dmax, u2).reshape(-1)
     off = np.arange(n_cand + 1, dtype=np.int64) * n_top
     return Batch(b, np.full(n_cand, nt, np.int32), np.full(n_cand, dmax, np.int32), off, depth)
 
@@ -309,8 +314,10 @@ def ragged_batch(seed: int, n_cand: int, nt_lo: int, nt_hi: int, dmax_hi: int, b
     thr = split_threshold(p_num, p_den)
     cand_of = np.repeat(c, n_top)
     t = np.arange(off[-1], dtype=np.int64) - np.repeat(off[:-1], n_top)
-    uu = draw_np(seed, P_DEPTH, (cand_of << np.uint64(24)) | t.astype(np.uint64))
-    depth = depth_from_draw(uu, thr, np.repeat(dmax.astype(np.int64), n_top))
+    idx = (cand_of << np.uint64(24)) | t.astype(np.uint64)
+    uu = draw_np(seed, P_DEPTH, idx)
+    uu2 = draw_np(seed, P_DEPTH2, idx) if int(dmax.max(initial=0)) > 3 else None
+    depth = depth_from_draw(uu, thr, np.repeat(dmax.astype(np.int64), n_top), uu2)
     return Batch(b, nt, dmax, off, depth)
 
 

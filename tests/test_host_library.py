@@ -123,7 +123,8 @@ def _compare_with_oracle(nt, dmax, depth, pf, b):
         assert rank[key_lib[tuple(int(x) for x in s.tasks[t])]] == s.rank[t]
 
 
-@pytest.mark.parametrize("nt,dmax", [(1, 0), (1, 3), (2, 1), (2, 3), (3, 2), (4, 1), (4, 3), (5, 2), (6, 3)])
+@pytest.mark.parametrize("nt,dmax", [(1, 0), (1, 3), (2, 1), (2, 3), (3, 2), (4, 1), (4, 3), (5, 2), (6, 3), (1, 4), (2, 4), (1, 5),
+                                     (2, 5)])
 def test_structural_expansion_vs_atom_scan(nt, dmax):
     pf = I.make_platform(I.cpu_accel_types(2, 1), seed=3)
     rng = np.random.default_rng(100 * nt + dmax)
