@@ -12,6 +12,7 @@ draws a fresh batch (different counters).  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -628,6 +629,8 @@ def main():
                          "on one and the accelerators behind one switch")
     ap.add_argument("--capacity-blocks", type=int, default=0,
                     help="finite accelerator spaces: finest blocks each one holds (0: unbounded)")
+    ap.add_argument("--dmax", type=int, default=None,
+                    help="maximum split depth of a uniform workload (0..5; above 3: 16 or 32 lanes per candidate)")
     ap.add_argument("--tree", action="store_true",
                     help="split-tree candidates (every task split on its own) of the same shape")
     ap.add_argument("--solve-chains", type=int, default=16384)
@@ -658,6 +661,11 @@ def main():
     if args.workload == "iterative_solver_tree":
         return run_solver_tree(args, torch, H)
     w = I.WORKLOADS[args.workload]
+    if args.dmax is not None and args.dmax != w.dmax:
+        if w.ragged:
+            print(json.dumps({"error": "--dmax applies to uniform workloads"}))
+            sys.exit(2)
+        w = dataclasses.replace(w, dmax=args.dmax, name=f"{w.name[:w.name.rindex('_d')]}_d{args.dmax}")
     n = args.n_cand or w.n_cand
     pf_in = w.platform()
     cap_bytes = None

@@ -604,14 +604,15 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
   // lanes per candidate: forced by the plan, or timed once per batch shape on a
   // sub-batch of the first chunk (outputs of that sub-batch are rewritten below)
   int group = plan->opts.group;
-  // whole-wave groups take depths up to kMaxWaveLevel; deeper batches run in 16- or
-  // 32-lane groups
-  const bool deep = bv.dmax > kMaxWaveLevel;
+  // whole-wave groups take depths up to kMaxWaveLevel on tables of at most
+  // kXferLevels levels; deeper batches and tables run in 16- or 32-lane groups
+  const bool deep = bv.dmax > kMaxWaveLevel || tb.max_level > kXferLevels;
   if (deep && (tb.capped || pf->n_procs > 32))
-    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: depths above %d take at most 32 processors and no finite "
-                                   "memory spaces", kMaxWaveLevel);
+    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: depths or platform levels above %d take at most 32 "
+                                   "processors and no finite memory spaces", kMaxWaveLevel);
   if (deep && group == 64)
-    return fail(HESP_EINVAL, "hesp_simulate_batch: 64 lanes per candidate take depths up to %d", kMaxWaveLevel);
+    return fail(HESP_EINVAL, "hesp_simulate_batch: 64 lanes per candidate take depths and platform levels up to %d",
+                kMaxWaveLevel);
   if (tb.capped) {
     // finite spaces: the event loop keeps its per-space state in whole-wave groups
     if (group != 0 && group != 64)
@@ -854,8 +855,9 @@ static int simulate_any(hesp_plan* plan, const hesp_platform* pf, hesp_policy po
   if (plan->opts.fuse) {
     if (is_tree) return fail(HESP_EUNSUPPORTED, "hesp_simulate_tree_batch: the fused pipeline takes depth batches");
     if (tb.capped) return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: the fused pipeline has no finite spaces");
-    if (bv.dmax > kMaxWaveLevel)
-      return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: the fused pipeline takes depths up to %d", kMaxWaveLevel);
+    if (bv.dmax > kMaxWaveLevel || tb.max_level > kXferLevels)
+      return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: the fused pipeline takes depths and platform levels up to "
+                                     "%d", kMaxWaveLevel);
     if (pf->n_procs > 64) return fail(HESP_EINVAL, "hesp_simulate_batch: more than 64 processors");
     return run_fused(plan, tb, bv, ov, s, n);
   }

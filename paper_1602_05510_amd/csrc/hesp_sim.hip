@@ -717,10 +717,13 @@ union SimPrepLds {
 // 2: the whole state of a small candidate, validity table, records, successor
 // lists and queues, never leaves the compute unit; its LDS slot, not registers,
 // bounds the waves per compute unit, so this variant keeps its registers).
-template <int G, int POL, int FUSED>
+// DT (16- and 32-lane groups only): the platform's transfer table is deeper than
+// the kXferLen entries in LDS; its rest is read from device memory.
+template <int G, int POL, int FUSED, int DT = 0>
 __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
                                                uint32_t* counter) {
   static_assert(!FUSED || G == kWave, "the fused preparation needs whole-wave groups");
+  static_assert(!DT || G != kWave, "whole-wave groups run on tables of at most kXferLevels levels");
   // POL 0: Priority-List + EFT-P + write-back (no policy flags read); 1: the
   // other push policies (FCFS, EIT-P) and caching policies; 2: R-P / F-P; 3:
   // finite memory spaces (PL or FCFS, EFT-P, write-back, independent transfers)
@@ -763,10 +766,16 @@ __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_s
   for (int x = l; x < kMaxPtypes * 4 * kSimLevels; x += kWave)
     (&s_cost[0][0][0])[x] = tb.cost[x / (4 * kSimLevels)][(x / kSimLevels) % 4][x % kSimLevels];
   for (int x = l; x < kXferLen; x += kWave) s_xfer[x] = tb.xfer[x];
-  // transfer time of i finest blocks of side b / 2^max_level: the first kXferLen
-  // from LDS, the rest (platforms deeper than kXferLevels) from device memory
+  // xf(m): transfer time of m of the candidate's finest blocks (side b / 2^dmax),
+  // entry m xs of the platform's table (blocks of side b / 2^max_level): in LDS,
+  // or past its first kXferLen entries (DT) in device memory
   const int64_t* const xdeep = tb.xfer_deep;
-  auto xfer = [&](int64_t i) -> int64_t { return i < kXferLen ? s_xfer[i] : xdeep[i]; };
+  int64_t xs = 0;
+  auto xf = [&](int64_t m) -> int64_t {
+    const int64_t i = m * xs;
+    if constexpr (!DT) return s_xfer[i];
+    return i < kXferLen ? s_xfer[i] : xdeep[i];
+  };
   if (FUSED)
     for (int x = l; x < 4 * kLevels; x += kWave) (&s_W[0][0])[x] = (&tb.W[0][0])[x];
   __syncthreads();
@@ -780,7 +789,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_s
   const bool want_sched = out.sched_off != nullptr;
 
   int c = 0, dmax = 0;
-  int64_t xs = 0, T = 0, n_ready = 0, sbase = 0;
+  int64_t T = 0, n_ready = 0, sbase = 0;
   int64_t n_atoms = 0;                        // finite spaces: the candidate's finest blocks
   CandPtrs sp{};
   int64_t avail = 0, hfin = kInf;
@@ -988,9 +997,16 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
   if (waves > slots) waves = slots;
   const int pol = t.capped ? 3 : (t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs || t.cache != 0 || t.bus != 0 ? 1 : 0));
   if (pol == 3 && (fused || G != 64 || !v.use || !v.pin)) return hipErrorInvalidValue;
+  const bool dt = t.max_level > kXferLevels;
+  if (dt && (G == 64 || !t.xfer_deep)) return hipErrorInvalidValue;
   const dim3 grid(waves), block(kWave);
 #define HESP_SIM_LAUNCH(GG, PP, FF, LDSB) \
   hipLaunchKernelGGL((k_sim<GG, PP, FF>), grid, block, LDSB, s, t, b, v, o, counter)
+#define HESP_SIM_LAUNCH_N(GG, PP)                                                               \
+  do {                                                                                          \
+    if (dt) hipLaunchKernelGGL((k_sim<GG, PP, 0, 1>), grid, block, 0, s, t, b, v, o, counter);  \
+    else hipLaunchKernelGGL((k_sim<GG, PP, 0, 0>), grid, block, 0, s, t, b, v, o, counter);     \
+  } while (0)
   if (fused && v.slot_lds) {
     const size_t ws = (size_t)v.slot_bytes;
     if (pol == 0) HESP_SIM_LAUNCH(64, 0, 2, ws);
@@ -1001,13 +1017,13 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
     else if (pol == 1) HESP_SIM_LAUNCH(64, 1, 1, 0);
     else HESP_SIM_LAUNCH(64, 2, 1, 0);
   } else if (G == 16) {
-    if (pol == 0) HESP_SIM_LAUNCH(16, 0, 0, 0);
-    else if (pol == 1) HESP_SIM_LAUNCH(16, 1, 0, 0);
-    else HESP_SIM_LAUNCH(16, 2, 0, 0);
+    if (pol == 0) HESP_SIM_LAUNCH_N(16, 0);
+    else if (pol == 1) HESP_SIM_LAUNCH_N(16, 1);
+    else HESP_SIM_LAUNCH_N(16, 2);
   } else if (G == 32) {
-    if (pol == 0) HESP_SIM_LAUNCH(32, 0, 0, 0);
-    else if (pol == 1) HESP_SIM_LAUNCH(32, 1, 0, 0);
-    else HESP_SIM_LAUNCH(32, 2, 0, 0);
+    if (pol == 0) HESP_SIM_LAUNCH_N(32, 0);
+    else if (pol == 1) HESP_SIM_LAUNCH_N(32, 1);
+    else HESP_SIM_LAUNCH_N(32, 2);
   } else {
     if (pol == 0) HESP_SIM_LAUNCH(64, 0, 0, 0);
     else if (pol == 1) HESP_SIM_LAUNCH(64, 1, 0, 0);
@@ -1015,6 +1031,7 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
     else HESP_SIM_LAUNCH(64, 3, 0, 0);
   }
 #undef HESP_SIM_LAUNCH
+#undef HESP_SIM_LAUNCH_N
   return hipGetLastError();
 }
 

@@ -108,17 +108,19 @@ def test_policies_deep(H, torch, policy):
 
 def test_deep_tables_with_shallow_candidates(H, torch):
     """Tables of 5 levels (4^5 + 1 transfer times) for candidates of depth <= 2:
-    a transfer of m blocks of side b/4 reads entry 64 m of the device copy; 64-lane
-    groups run them too, and a second platform's table replaces the copy."""
+    a transfer of m blocks of side b/4 reads entry 64 m of the device copy (16 and
+    32 lanes; 64 are refused), and a second platform's table replaces the copy."""
     pf_in = W.platform()
     host = I.uniform_batch(W.seed, 128, 8, W.b, 2, 3, 10, first=900)
     want, _ = O.simulate_batch(pf_in, host, NTHREADS)
     plan = H.Plan()
     pf5 = H.Platform.from_inputs(pf_in, W.b, 5)
     print("deep: 5-level tables, depth-2 candidates", flush=True)
-    for group in (64, 16):
+    for group in (16, 32):
         ms, st, _ = _run(H, torch, H.Plan(group=group), pf5, host)
         assert (st == 0).all() and np.array_equal(ms, want), group
+    with pytest.raises(RuntimeError, match="64 lanes per candidate take depths and platform levels"):
+        _run(H, torch, H.Plan(group=64), pf5, host)
     ms, _, _ = _run(H, torch, plan, pf5, host)
     assert np.array_equal(ms, want)
     other = I.make_platform(I.cpu_accel_types(8, 2), seed=W.seed + 1)
@@ -159,13 +161,13 @@ def test_deep_refusals(H, torch):
     ms = torch.empty(8, dtype=torch.int64, device="cuda")
     st = torch.empty(8, dtype=torch.int32, device="cuda")
     pf = H.Platform.from_inputs(pf_in, W.b, 4)
-    with pytest.raises(RuntimeError, match="64 lanes per candidate take depths up to 3"):
+    with pytest.raises(RuntimeError, match="64 lanes per candidate take depths and platform levels up to 3"):
         H.simulate_batch(H.Plan(group=64), pf, db, ms, st)
-    with pytest.raises(RuntimeError, match="fused pipeline takes depths up to 3"):
+    with pytest.raises(RuntimeError, match="fused pipeline takes depths and platform levels up to 3"):
         H.simulate_batch(H.Plan(group=64, fuse=True), pf, db, ms, st)
     cap = np.zeros(pf_in.n_mem, np.int64)
     cap[1:] = 1 << 30
-    with pytest.raises(RuntimeError, match="depths above 3"):
+    with pytest.raises(RuntimeError, match="depths or platform levels above 3"):
         H.simulate_batch(H.Plan(), H.Platform.from_inputs(pf_in, W.b, 4, capacity_bytes=cap), db, ms, st)
     with pytest.raises(RuntimeError, match="at most 3 levels"):
         H.simulate_batch_noalloc(pf, db, ms, st)
