@@ -226,8 +226,9 @@ typedef struct {
   int32_t fuse;                /* 1: fused pipeline for depth batches (64 lanes per candidate; group must be
                                   0 or 64): every wave of the persistent event loop prepares the candidates it
                                   takes into its own workspace slot, so a batch of any size and unevenness is
-                                  one launch holding (resident waves x largest candidate) bytes; slower than
-                                  the default separate preparation launch per memory chunk.  2: the same with
+                                  one launch holding (resident waves x largest candidate) bytes, four
+                                  waves per SIMD; about as fast as the default separate preparation launch
+                                  per memory chunk on uniform batches.  2: the same with
                                   each slot in the workgroup's LDS (no device workspace at all): candidates
                                   whose workspace (104 T + 4 E + 8 V + 4 (tet(nt) + 1) bytes, T tasks, E
                                   edges, V finest blocks x memory spaces) exceeds 48 KiB get HESP_ECAPACITY */

@@ -111,7 +111,7 @@ struct hesp_plan {
   int32_t fixed_chunk = 0;
   // fused pipeline: one slot per resident wave of the 64-lane event loop
   DevBuf arena;
-  int32_t resident64 = 0;     // waves of the fused event loop resident at once (six per SIMD)
+  int32_t resident64 = 0;     // waves of the fused event loop resident at once (four per SIMD)
   std::tuple<int64_t, int64_t, int64_t> fused_key{-1, -1, -1};
   int32_t fused_waves = 0;
   // optional kernel timing of the last call: events around each launch
@@ -338,7 +338,7 @@ int hesp_plan_create(hesp_plan** plan, const hesp_plan_opts* opts) {
     return fail(HESP_EHIP, "hesp_plan_create: %s", hipGetErrorString(e));
   }
   p->slots = p->opts.slots ? p->opts.slots : 32 * cus;
-  p->resident64 = std::min(p->slots, 24 * cus);
+  p->resident64 = std::min(p->slots, 16 * cus);
   p->chunk = 1 << 22;   // bounded by device memory below
   e = hipMalloc(&p->counter, sizeof(uint32_t));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->s_prep, hipStreamNonBlocking);

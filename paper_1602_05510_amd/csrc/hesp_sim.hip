@@ -716,11 +716,14 @@ union SimPrepLds {
 // slot blockIdx.x of cv.region (FUSED 1) or the workgroup's dynamic LDS (FUSED
 // 2: the whole state of a small candidate, validity table, records, successor
 // lists and queues, never leaves the compute unit; its LDS slot, not registers,
-// bounds the waves per compute unit, so this variant keeps its registers).
+// bounds the waves per compute unit, so this variant keeps its registers).  FUSED
+// 1 runs at four waves per SIMD (128 VGPRs): the preparation's live state spills
+// at six (16x16-tile headline batch, per step: 401 ms at four, 598 at five, 658
+// at six, 475 at three).
 // DT (16- and 32-lane groups only): the platform's transfer table is deeper than
 // the kXferLen entries in LDS; its rest is read from device memory.
 template <int G, int POL, int FUSED, int DT = 0>
-__global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : 6) : 1) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
+__global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : (FUSED == 1 ? 4 : 6)) : 1) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
                                                uint32_t* counter) {
   static_assert(!FUSED || G == kWave, "the fused preparation needs whole-wave groups");
   static_assert(!DT || G != kWave, "whole-wave groups run on tables of at most kXferLevels levels");
