@@ -269,9 +269,7 @@ int hesp_plan_last_ms(hesp_plan *plan, double *ms);
  * counts back to the host (one synchronisation of `stream`).
  * Depths: up to HESP_MAX_LEVEL (block sides down to b/32, the deepest DAGs of
  * section 3).  A batch whose dmax (its maximum) is above 3, or a platform whose
- * max_level is, runs with 16 or 32 lanes per candidate, so it takes at most 32
- * processors, no finite memory spaces and the unfused pipeline (else
- * HESP_EUNSUPPORTED; a plan forcing 64 lanes gives HESP_EINVAL).  A ragged candidate above the batch's nt or dmax
+ * max_level is, takes the unfused pipeline (else HESP_EUNSUPPORTED).  A ragged candidate above the batch's nt or dmax
  * gets HESP_EINVAL.  A platform with max_level above 3 has more transfer times
  * than the kernels take by value: the plan keeps a device copy of xfer_ns (made
  * on `stream`, after it drains, whenever the table differs from the last one);

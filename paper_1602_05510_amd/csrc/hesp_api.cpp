@@ -604,15 +604,6 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
   // lanes per candidate: forced by the plan, or timed once per batch shape on a
   // sub-batch of the first chunk (outputs of that sub-batch are rewritten below)
   int group = plan->opts.group;
-  // whole-wave groups take depths up to kMaxWaveLevel on tables of at most
-  // kXferLevels levels; deeper batches and tables run in 16- or 32-lane groups
-  const bool deep = bv.dmax > kMaxWaveLevel || tb.max_level > kXferLevels;
-  if (deep && (tb.capped || pf->n_procs > 32))
-    return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: depths or platform levels above %d take at most 32 "
-                                   "processors and no finite memory spaces", kMaxWaveLevel);
-  if (deep && group == 64)
-    return fail(HESP_EINVAL, "hesp_simulate_batch: 64 lanes per candidate take depths and platform levels up to %d",
-                kMaxWaveLevel);
   if (tb.capped) {
     // finite spaces: the event loop keeps its per-space state in whole-wave groups
     if (group != 0 && group != 64)
@@ -631,7 +622,7 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
       HIP_TRY(hipEventCreate(&e0));
       HIP_TRY(hipEventCreate(&e1));
       for (int G : {16, 32, 64}) {
-        if (G < pf->n_procs || (deep && G == kWave)) continue;
+        if (G < pf->n_procs) continue;
         ChunkView cv = chunk_view(0, sub, 0);
         HIP_TRY(prepare(cv, s));
         HIP_TRY(hipEventRecord(e0, s));

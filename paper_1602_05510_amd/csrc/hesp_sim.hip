@@ -719,14 +719,19 @@ union SimPrepLds {
 // bounds the waves per compute unit, so this variant keeps its registers).  FUSED
 // 1 runs at four waves per SIMD (128 VGPRs): the preparation's live state spills
 // at six (16x16-tile headline batch, per step: 401 ms at four, 598 at five, 658
-// at six, 475 at three).
-// DT (16- and 32-lane groups only): the platform's transfer table is deeper than
-// the kXferLen entries in LDS; its rest is read from device memory.
+// at six, 475 at three).  Finite spaces on deep tables: four (their LDS, with
+// the six-level cost table, holds no more).
+// DT: the platform's tables are deeper than kXferLevels levels (candidates of
+// depth 4 and 5 among them): the rest of the transfer table is read from device
+// memory, and whole-wave groups scan block sides up to 32 without the
+// compile-time specialisation (blocks above 8 x 8 finest blocks span passes).
+constexpr int sim_waves(int G, int POL, int FUSED, int DT) {
+  return G != 64 ? 1 : FUSED == 2 ? 2 : FUSED == 1 ? 4 : (POL == 3 && DT) ? 4 : 6;
+}
 template <int G, int POL, int FUSED, int DT = 0>
-__global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : (FUSED == 1 ? 4 : 6)) : 1) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
+__global__ void __launch_bounds__(kWave, sim_waves(G, POL, FUSED, DT)) k_sim(SimTables tb, BatchView bv, ChunkView cv, OutView out,
                                                uint32_t* counter) {
   static_assert(!FUSED || G == kWave, "the fused preparation needs whole-wave groups");
-  static_assert(!DT || G != kWave, "whole-wave groups run on tables of at most kXferLevels levels");
   // POL 0: Priority-List + EFT-P + write-back (no policy flags read); 1: the
   // other push policies (FCFS, EIT-P) and caching policies; 2: R-P / F-P; 3:
   // finite memory spaces (PL or FCFS, EFT-P, write-back, independent transfers)
@@ -739,7 +744,7 @@ __global__ void __launch_bounds__(kWave, G == 64 ? (FUSED == 2 ? 2 : (FUSED == 1
   const bool bus = POL != 0 && !CAP && tb.bus != 0;
   constexpr int LGG = G == 16 ? 4 : (G == 32 ? 5 : 6);
   // task times of the levels the groups can meet (whole-wave groups: 0..3)
-  constexpr int kSimLevels = G == kWave ? kMaxWaveLevel + 1 : kLevels;
+  constexpr int kSimLevels = G == kWave && !DT ? kMaxWaveLevel + 1 : kLevels;
   __shared__ int64_t s_cost[kMaxPtypes][4][kSimLevels];
   __shared__ int64_t s_xfer[kXferLen];
   __shared__ int64_t s_W[FUSED ? 4 : 1][kLevels];
@@ -1001,7 +1006,7 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
   const int pol = t.capped ? 3 : (t.sel >= 2 ? 2 : (t.sel == 1 || t.fcfs || t.cache != 0 || t.bus != 0 ? 1 : 0));
   if (pol == 3 && (fused || G != 64 || !v.use || !v.pin)) return hipErrorInvalidValue;
   const bool dt = t.max_level > kXferLevels;
-  if (dt && (G == 64 || !t.xfer_deep)) return hipErrorInvalidValue;
+  if (dt && (fused || !t.xfer_deep)) return hipErrorInvalidValue;
   const dim3 grid(waves), block(kWave);
 #define HESP_SIM_LAUNCH(GG, PP, FF, LDSB) \
   hipLaunchKernelGGL((k_sim<GG, PP, FF>), grid, block, LDSB, s, t, b, v, o, counter)
@@ -1028,10 +1033,10 @@ hipError_t launch_sim(const SimTables& t, const BatchView& b, const ChunkView& v
     else if (pol == 1) HESP_SIM_LAUNCH_N(32, 1);
     else HESP_SIM_LAUNCH_N(32, 2);
   } else {
-    if (pol == 0) HESP_SIM_LAUNCH(64, 0, 0, 0);
-    else if (pol == 1) HESP_SIM_LAUNCH(64, 1, 0, 0);
-    else if (pol == 2) HESP_SIM_LAUNCH(64, 2, 0, 0);
-    else HESP_SIM_LAUNCH(64, 3, 0, 0);
+    if (pol == 0) HESP_SIM_LAUNCH_N(64, 0);
+    else if (pol == 1) HESP_SIM_LAUNCH_N(64, 1);
+    else if (pol == 2) HESP_SIM_LAUNCH_N(64, 2);
+    else HESP_SIM_LAUNCH_N(64, 3);
   }
 #undef HESP_SIM_LAUNCH
 #undef HESP_SIM_LAUNCH_N

@@ -1,8 +1,9 @@
 """DAGs of depth 4 and 5 (block sides b/16 and b/32) on the GPU against the CPU
-oracle: makespans, statuses and per-task schedules bit-exact for 16 and 32 lanes
-per candidate, uniform and uneven batches, every heuristic class, caching policy
-and link contention; platforms whose transfer table is deeper than the kernels
-take by value; the seeded generators; and the combinations that are refused."""
+oracle: makespans, statuses and per-task schedules bit-exact for 16, 32 and 64
+lanes per candidate, uniform and uneven batches, every heuristic class, caching
+policy, link contention and finite memory spaces; platforms whose transfer
+table is deeper than the kernels take by value; the seeded generators; and the
+combinations that are refused."""
 import os
 
 import numpy as np
@@ -52,14 +53,14 @@ def _run(H, torch, plan, pf, host, policy=(0, 0, 0), sched=False):
 @pytest.mark.parametrize("nt,dmax", [(6, 4), (8, 4), (4, 5), (6, 5)])
 def test_parity_deep(H, torch, nt, dmax):
     """96 candidates with P(split) = 1/2 per level (about 3% reach depth 5) on
-    the platform's tables of dmax levels, 16 and 32 lanes and the tuned choice."""
+    the platform's tables of dmax levels, 16, 32 and 64 lanes and the tuned choice."""
     pf_in = W.platform()
     pf = H.Platform.from_inputs(pf_in, W.b, dmax)
     host = I.uniform_batch(W.seed, 96, nt, W.b, dmax, 1, 2, first=1_000 * dmax + nt)
     assert int(host.depth.max()) == dmax
     print(f"deep: nt {nt}, dmax {dmax}, 96 candidates", flush=True)
     want, _ = O.simulate_batch(pf_in, host, NTHREADS)
-    for group in (16, 32, 0):
+    for group in (16, 32, 64, 0):
         ms, st, _ = _run(H, torch, H.Plan(group=group), pf, host)
         assert (st == 0).all(), group
         assert np.array_equal(ms, want), group
@@ -108,19 +109,17 @@ def test_policies_deep(H, torch, policy):
 
 def test_deep_tables_with_shallow_candidates(H, torch):
     """Tables of 5 levels (4^5 + 1 transfer times) for candidates of depth <= 2:
-    a transfer of m blocks of side b/4 reads entry 64 m of the device copy (16 and
-    32 lanes; 64 are refused), and a second platform's table replaces the copy."""
+    a transfer of m blocks of side b/4 reads entry 64 m of the device copy (16, 32
+    and 64 lanes), and a second platform's table replaces the copy."""
     pf_in = W.platform()
     host = I.uniform_batch(W.seed, 128, 8, W.b, 2, 3, 10, first=900)
     want, _ = O.simulate_batch(pf_in, host, NTHREADS)
     plan = H.Plan()
     pf5 = H.Platform.from_inputs(pf_in, W.b, 5)
     print("deep: 5-level tables, depth-2 candidates", flush=True)
-    for group in (16, 32):
+    for group in (16, 32, 64):
         ms, st, _ = _run(H, torch, H.Plan(group=group), pf5, host)
         assert (st == 0).all() and np.array_equal(ms, want), group
-    with pytest.raises(RuntimeError, match="64 lanes per candidate take depths and platform levels"):
-        _run(H, torch, H.Plan(group=64), pf5, host)
     ms, _, _ = _run(H, torch, plan, pf5, host)
     assert np.array_equal(ms, want)
     other = I.make_platform(I.cpu_accel_types(8, 2), seed=W.seed + 1)
@@ -161,14 +160,8 @@ def test_deep_refusals(H, torch):
     ms = torch.empty(8, dtype=torch.int64, device="cuda")
     st = torch.empty(8, dtype=torch.int32, device="cuda")
     pf = H.Platform.from_inputs(pf_in, W.b, 4)
-    with pytest.raises(RuntimeError, match="64 lanes per candidate take depths and platform levels up to 3"):
-        H.simulate_batch(H.Plan(group=64), pf, db, ms, st)
     with pytest.raises(RuntimeError, match="fused pipeline takes depths and platform levels up to 3"):
         H.simulate_batch(H.Plan(group=64, fuse=True), pf, db, ms, st)
-    cap = np.zeros(pf_in.n_mem, np.int64)
-    cap[1:] = 1 << 30
-    with pytest.raises(RuntimeError, match="depths or platform levels above 3"):
-        H.simulate_batch(H.Plan(), H.Platform.from_inputs(pf_in, W.b, 4, capacity_bytes=cap), db, ms, st)
     with pytest.raises(RuntimeError, match="at most 3 levels"):
         H.simulate_batch_noalloc(pf, db, ms, st)
     with pytest.raises(RuntimeError, match="bad problem shape"):
@@ -231,3 +224,21 @@ def test_graph_replay_deep(H, torch):
         assert torch.equal(ms, ms2), r
     host = I.uniform_batch(W.seed, 32, 6, W.b, 5, 1, 2, first=20_000 + 2 * n)
     assert np.array_equal(ms[:32].cpu().numpy(), O.simulate_batch(pf_in, host, NTHREADS)[0])
+
+
+@pytest.mark.parametrize("nt,dmax,blocks,n", [(4, 4, 400, 32), (4, 4, 1200, 32), (3, 5, 1500, 16)])
+def test_capacity_deep(H, torch, nt, dmax, blocks, n):
+    """Finite accelerator spaces holding `blocks` finest blocks (side b / 2^dmax)
+    with candidates of depth 4 and 5: 64 lanes, statuses and makespans bit-exact,
+    and the capacity binds."""
+    pf_in = W.platform()
+    cap = np.zeros(pf_in.n_mem, np.int64)
+    cap[1:] = blocks * pf_in.elem_bytes * (W.b >> dmax) ** 2
+    pf = H.Platform.from_inputs(pf_in, W.b, dmax, capacity_bytes=cap)
+    host = I.uniform_batch(W.seed, n, nt, W.b, dmax, 1, 2, first=60 + dmax)
+    print(f"deep: capacity {blocks} blocks, nt {nt}, dmax {dmax}", flush=True)
+    want, _, wst = O.simulate_batch(pf_in, host, NTHREADS, capacity=cap, statuses=True)
+    ms, st, _ = _run(H, torch, H.Plan(), pf, host)
+    assert np.array_equal(st, wst) and (st == 0).all()
+    assert np.array_equal(ms, want)
+    assert (want != O.simulate_batch(pf_in, host, NTHREADS)[0]).sum() >= n // 2
