@@ -10,7 +10,7 @@ namespace solve {
 constexpr int kMaxTop = 4096;   // top-level tasks of one chain (nt <= 28)
 constexpr int kMaxP = 64;       // processors (6 bits of a packed time key)
 constexpr int kMaxTypes = 8;
-constexpr int kLv = 4;          // split depths 0..3
+constexpr int kLv = 6;          // split depths 0..5
 
 struct SolveTables {
   int32_t n_procs;

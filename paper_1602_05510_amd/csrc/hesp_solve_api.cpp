@@ -64,14 +64,16 @@ struct Scratch {
 
 extern "C" {
 
-// argument checks and the cost tables shared by both solvers; n_cl = clusters per chain
+// argument checks and the cost tables shared by both solvers; n_cl = clusters per
+// chain; depths and platform levels up to max_depth
 static int solve_setup(hesp_plan* plan, const hesp_platform* pf, const hesp_solve_params* sp, int64_t n_cl,
                        const void* d_part, const void* d_best, const int64_t* d_best_makespan, const char* who,
-                       solve::SolveTables& tb) {
+                       int max_depth, solve::SolveTables& tb) {
   if (!plan || !pf || !sp) return fail(HESP_EINVAL, "%s: null plan, platform or parameters", who);
   const int B = sp->n_chains, nt = sp->nt, dmax = sp->dmax;
-  if (B < 1 || B > 65535 || nt < 1 || dmax < 0 || dmax > kMaxSearchLevel || (nt << dmax) > kMaxFine || sp->iters < 1)
-    return fail(HESP_EINVAL, "%s: need 1 <= n_chains <= 65535, nt >= 1, 0 <= dmax <= 3, iters >= 1", who);
+  if (B < 1 || B > 65535 || nt < 1 || dmax < 0 || dmax > max_depth || (nt << dmax) > kMaxFine || sp->iters < 1)
+    return fail(HESP_EINVAL, "%s: need 1 <= n_chains <= 65535, nt >= 1, 0 <= dmax <= %d, iters >= 1", who,
+                max_depth);
   if (sp->list < HESP_LIST_ALL || sp->list > HESP_LIST_SHALLOW || sp->sampling < HESP_SAMPLE_HARD ||
       sp->sampling > HESP_SAMPLE_SOFT)
     return fail(HESP_EINVAL, "%s: list must be ALL, CP or SHALLOW and sampling HARD or SOFT", who);
@@ -79,7 +81,7 @@ static int solve_setup(hesp_plan* plan, const hesp_platform* pf, const hesp_solv
   if (!d_part || !d_best || !d_best_makespan) return fail(HESP_EINVAL, "%s: null outputs", who);
   if (pf->n_procs < 1 || pf->n_procs > std::min<int>(HESP_MAX_PROCS, solve::kMaxP) || pf->n_ptypes < 1 ||
       pf->n_ptypes > std::min<int>(HESP_MAX_PTYPES, solve::kMaxTypes) || pf->max_level < dmax ||
-      pf->max_level > kMaxSearchLevel || !pf->proc_type || !pf->cost_ns)
+      pf->max_level > max_depth || !pf->proc_type || !pf->cost_ns)
     return fail(HESP_EINVAL, "%s: bad platform description (or dmax above its max_level)", who);
   memset(&tb, 0, sizeof tb);
   tb.n_procs = pf->n_procs;
@@ -113,7 +115,7 @@ int hesp_solve(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, con
   const int B = sp->n_chains, nt = sp->nt, dmax = sp->dmax;
   const int64_t n_top = nt >= 1 ? tet3(nt) : 0;
   solve::SolveTables tb;
-  RC_TRY(solve_setup(plan, pf, sp, n_top, d_depth, d_best_depth, d_best_makespan, "hesp_solve", tb));
+  RC_TRY(solve_setup(plan, pf, sp, n_top, d_depth, d_best_depth, d_best_makespan, "hesp_solve", kMaxLevel, tb));
 
   hipStream_t s = (hipStream_t)stream;
   const int64_t max_tasks = tet3((int64_t)nt << dmax);   // a chain split to dmax everywhere
@@ -197,7 +199,8 @@ int hesp_solve_tree(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy
     return fail(HESP_EINVAL, "hesp_solve_tree: need 1 <= dmax <= 3 (the clusters are the tasks above the last level)");
   const int64_t nn = hesp_tree_flag_count(nt, dmax);
   solve::SolveTables tb;
-  RC_TRY(solve_setup(plan, pf, sp, nn, d_flags, d_best_flags, d_best_makespan, "hesp_solve_tree", tb));
+  RC_TRY(solve_setup(plan, pf, sp, nn, d_flags, d_best_flags, d_best_makespan, "hesp_solve_tree", kMaxSearchLevel,
+                     tb));
 
   hipStream_t s = (hipStream_t)stream;
   const int64_t max_tasks = tet3((int64_t)nt << dmax);

@@ -96,6 +96,25 @@ def test_chains_under_other_heuristics(H, torch, policy):
         _check_chain(pf_in, nt, dmax, w.b, depth0, iters, 0, 1, seed, got, r, policy=policy)
 
 
+@pytest.mark.parametrize("nt,dmax,pn,pd,lst,sampling", [(3, 4, 2, 3, 0, 1), (2, 5, 3, 4, 0, 1), (3, 4, 2, 3, 1, 0)])
+def test_chains_at_depth_four_and_five(H, torch, nt, dmax, pn, pd, lst, sampling):
+    """Chains on tables of 4 and 5 levels, from initial partitions with tasks at
+    depth 4 and 5, sixteen iterations, some steps choosing depth 4 or 5 (section
+    3.2 reports best partitions of DAG depth up to 5)."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf_in = w.platform()
+    B, iters, seed = 4, 16, 9
+    bt = I.uniform_batch(78, B, nt, w.b, dmax, pn, pd)
+    depth0 = bt.depth.reshape(B, I.tet(nt))
+    assert (depth0 >= 4).any()
+    got = _run(H, torch, pf_in, nt, dmax, w.b, depth0, iters, lst, sampling, seed)
+    deep_steps = 0
+    for r in range(B):
+        _check_chain(pf_in, nt, dmax, w.b, depth0, iters, lst, sampling, seed, got, r)
+        deep_steps += int((got[3][r][:, 1] >= 4).sum())
+    assert deep_steps >= 3
+
+
 def test_edge_cases(H, torch):
     w = I.WORKLOADS["chol16x16_b1024_d2"]
     pf_in = w.platform()
