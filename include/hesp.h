@@ -52,7 +52,7 @@ extern "C" {
 #define HESP_MAX_PTYPES 8   /* processor types */
 #define HESP_MAX_MEM 16     /* memory spaces (space 0 is the host) */
 #define HESP_MAX_LEVEL 5    /* split depth per task: block sides b, b/2, ..., b/32 */
-#define HESP_MAX_SEARCH_LEVEL 3  /* split trees, hesp_solve_tree, hesp_search, enumeration: b .. b/8 */
+#define HESP_MAX_SEARCH_LEVEL 3  /* split trees, hesp_solve_tree, exhaustive enumeration: b .. b/8 */
 #define HESP_MAX_FINE 512   /* nt * 2^dmax, the finest tile count per dimension */
 
 const char *hesp_last_error(void);
@@ -439,7 +439,8 @@ int hesp_topk_score(const float *d_score, int32_t n, int32_t k, int32_t *d_idx, 
  * trace[rounds] (host, nullable) gets, after each round, the wall time since the
  * start, the best makespan, and the simulated and proposed candidate counts
  * (each round synchronises `stream`).  Device workspace is allocated per call.
- * The search takes dmax <= HESP_MAX_SEARCH_LEVEL on platforms with max_level <= 3.
+ * The search takes dmax <= HESP_MAX_LEVEL (the aggregate features count depths
+ * 3 to 5 in one bin).
  * The plan must not limit tasks or edges per candidate (HESP_EINVAL), so that
  * every proposal gets a makespan. */
 enum { HESP_SEARCH_RANDOM = 0, HESP_SEARCH_GREEDY = 1, HESP_SEARCH_SURROGATE = 2 };

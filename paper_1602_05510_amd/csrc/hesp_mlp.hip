@@ -707,9 +707,10 @@ __global__ void k_features(const uint8_t* __restrict__ depth, int64_t n, int n_t
 }
 
 // aggregate features of large candidates, one wave per candidate: for each kind
-// the fraction of its top-level tasks at each depth 0..3 (16 values), for each
-// kind and each half of the k range the mean depth (8 values), then the rate
-// features; info[t] = kind | (k >= nt/2) << 2 for top-level task t
+// the fraction of its top-level tasks at depth 0, 1, 2 and 3 or more (16
+// values), for each kind and each half of the k range the mean depth (8
+// values), then the rate features; info[t] = kind | (k >= nt/2) << 2 for
+// top-level task t
 __global__ void __launch_bounds__(256) k_features_agg(const uint8_t* __restrict__ depth, int64_t n, int n_top,
                                                       const uint8_t* __restrict__ info, const float* __restrict__ rate,
                                                       int n_rate, uint16_t* __restrict__ x) {
@@ -721,8 +722,8 @@ __global__ void __launch_bounds__(256) k_features_agg(const uint8_t* __restrict_
   for (int q = 0; q < 8; q++) sum[q] = num[q] = 0.f;
   const uint8_t* row = depth + c * n_top;
   for (int t = l; t < n_top; t += 64) {
-    const int d = row[t] & 3, f = info[t];
-    const int slot = (f & 3) * 4 + d, part = (f & 3) * 2 + ((f >> 2) & 1);
+    const int d = row[t], f = info[t];
+    const int slot = (f & 3) * 4 + (d < 3 ? d : 3), part = (f & 3) * 2 + ((f >> 2) & 1);
     // predicated updates keep the accumulators in registers
     for (int q = 0; q < 16; q++) cnt[q] += (q == slot) ? 1.f : 0.f;
     for (int q = 0; q < 8; q++) {

@@ -161,10 +161,8 @@ int hesp_search(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy, co
                 uint8_t* best_depth, int64_t* best_makespan, hesp_trace_point* trace, void* stream) {
   if (!plan || !pf || !sp || !best_depth || !best_makespan) return fail(HESP_EINVAL, "hesp_search: null argument");
   const int nt = sp->nt, dmax = sp->dmax;
-  if (nt < 1 || dmax < 0 || dmax > kMaxSearchLevel || dmax > pf->max_level || (nt << dmax) > kMaxFine)
-    return fail(HESP_EINVAL, "hesp_search: bad problem shape (dmax <= %d)", kMaxSearchLevel);
-  if (pf->max_level > kMaxSearchLevel)
-    return fail(HESP_EINVAL, "hesp_search: platform tables of at most %d levels", kMaxSearchLevel);
+  if (nt < 1 || dmax < 0 || dmax > kMaxLevel || dmax > pf->max_level || (nt << dmax) > kMaxFine)
+    return fail(HESP_EINVAL, "hesp_search: bad problem shape (dmax <= %d)", kMaxLevel);
   if (sp->mode < HESP_SEARCH_RANDOM || sp->mode > HESP_SEARCH_SURROGATE)
     return fail(HESP_EINVAL, "hesp_search: unknown mode");
   if (sp->rounds < 1 || sp->batch < 1 || sp->warm_rounds < 1 || sp->warm_batch < 1 || sp->pool < 1 ||

@@ -165,7 +165,7 @@ def test_deep_refusals(H, torch):
     with pytest.raises(RuntimeError, match="at most 3 levels"):
         H.simulate_batch_noalloc(pf, db, ms, st)
     with pytest.raises(RuntimeError, match="bad problem shape"):
-        H.search(H.Plan(), pf, 4, 4, H.SEARCH_RANDOM, rounds=1, batch=16, seed=1)
+        H.search(H.Plan(), pf, 4, 6, H.SEARCH_RANDOM, rounds=1, batch=16, seed=1)
     with pytest.raises(Exception):
         H.generate_tree_uniform(1, 0, 4, 4, 4, 1000)
     # a ragged candidate above the batch's stated maximum depth fails alone

@@ -87,7 +87,7 @@ def test_features_agg(H, torch):
     rng = np.random.default_rng(3)
     nt, n = 8, 1001
     n_top = I.tet(nt)
-    dep = rng.integers(0, 4, (n, n_top)).astype(np.uint8)
+    dep = rng.integers(0, 6, (n, n_top)).astype(np.uint8)      # depths 3..5 share one bin
     rate = rng.normal(0, 1, 8).astype(np.float32)
     x = torch.empty((n, 32), dtype=torch.int16, device="cuda")
     H.mlp_features_agg(torch.from_numpy(dep).cuda(), n, nt, torch.from_numpy(rate).cuda(), x)
@@ -108,7 +108,7 @@ def test_features_agg(H, torch):
     for kd in range(4):
         sel = kind == kd
         for d in range(4):
-            want[:, kd * 4 + d] = (dep[:, sel] == d).sum(1) / sel.sum()
+            want[:, kd * 4 + d] = (np.minimum(dep[:, sel], 3) == d).sum(1) / sel.sum()
         for h in range(2):
             s2 = sel & (half == h)
             want[:, 16 + kd * 2 + h] = dep[:, s2].sum(1) / s2.sum() if s2.any() else 0.0
@@ -181,6 +181,35 @@ def test_search_surrogate_aggregate_features(H, torch):
                                  mutate_thr=(1 << 21) // 20, mlp=m, rate=rate, train_steps=5, train_batch=512,
                                  lr=1e-3, replay=2048)
     assert best_ms == O.simulate(pf_in, 8, 2, 512, best, detail=False)
+    assert _monotone(tr)
+
+
+def test_search_at_depth_five(H, torch):
+    """6x6 tiles of 1024 split up to 5 times on the 16x16 workload's platform:
+    the random search's best is the minimum of the same 768 seeded candidates,
+    and a surrogate-guided search (aggregate features) ends on a partition whose
+    makespan the oracle reproduces."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf_in = w.platform()
+    nt, dmax = 6, 5
+    pf = H.Platform.from_inputs(pf_in, w.b, dmax)
+    thr = I.split_threshold(1, 2)
+    print("search: depth 5, random", flush=True)
+    best, best_ms, tr = H.search(H.Plan(), pf, nt, dmax, H.SEARCH_RANDOM, rounds=3, batch=256, seed=31, pool=8,
+                                 split_thr=thr)
+    host = I.uniform_batch(31, 768, nt, w.b, dmax, 1, 2)
+    assert int(host.depth.max()) == 5
+    ms, _ = O.simulate_batch(pf_in, host, NTHREADS)
+    c = int(np.argmin(ms))
+    assert best_ms == int(ms[c]) and np.array_equal(best, host.candidate(c))
+    print("search: depth 5, surrogate", flush=True)
+    m = H.MLP(7)
+    rate = torch.from_numpy(H.mlp_rate_features(pf_in.rmax)).cuda()
+    best, best_ms, tr = H.search(H.Plan(), pf, nt, dmax, H.SEARCH_SURROGATE, rounds=3, batch=128, seed=32,
+                                 warm_rounds=1, warm_batch=512, proposals=1024, pool=8, split_thr=thr,
+                                 mutate_thr=(1 << 21) // 20, mlp=m, rate=rate, train_steps=5, train_batch=512,
+                                 lr=1e-3, replay=2048)
+    assert best_ms == O.simulate(pf_in, nt, dmax, w.b, best, detail=False)
     assert _monotone(tr)
 
 
