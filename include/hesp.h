@@ -52,7 +52,7 @@ extern "C" {
 #define HESP_MAX_PTYPES 8   /* processor types */
 #define HESP_MAX_MEM 16     /* memory spaces (space 0 is the host) */
 #define HESP_MAX_LEVEL 5    /* split depth per task: block sides b, b/2, ..., b/32 */
-#define HESP_MAX_SEARCH_LEVEL 3  /* split trees, hesp_solve_tree, exhaustive enumeration: b .. b/8 */
+#define HESP_MAX_SEARCH_LEVEL 3  /* hesp_solve_tree and exhaustive enumeration: b .. b/8 */
 #define HESP_MAX_FINE 512   /* nt * 2^dmax, the finest tile count per dimension */
 
 const char *hesp_last_error(void);
@@ -325,7 +325,6 @@ int hesp_simulate_batch_noalloc(const hesp_platform *pf, hesp_policy policy, con
  * Schedule outputs number the tasks in program order: top-level tasks in Fig. 1
  * order, each split task replaced in place by its children in the order of the
  * Fig. 1 loop nest restricted to its 2 x 2 sub-tiling, recursively.
- * Split trees take dmax <= HESP_MAX_SEARCH_LEVEL.
  * hesp_simulate_tree_batch behaves as hesp_simulate_batch (outputs, statuses,
  * fixed-capacity plans; HESP_EINVAL for a flag above 1); it also keeps a
  * last-writer table of 4 bytes per finest block and candidate in the plan.

@@ -281,10 +281,9 @@ static int batch_view(const hesp_batch* b, BatchView& v, const char* who) {
 
 static int tree_view(const hesp_tree_batch* b, BatchView& v, const char* who) {
   if (!b) return fail(HESP_EINVAL, "%s: null batch", who);
-  if (b->n_cand < 0 || b->nt < 1 || b->dmax < 0 || b->dmax > HESP_MAX_SEARCH_LEVEL ||
-      (b->nt << b->dmax) > HESP_MAX_FINE)
-    return fail(HESP_EINVAL, "%s: n_cand=%d nt=%d dmax=%d outside the supported range (split trees: dmax <= %d)",
-                who, b->n_cand, b->nt, b->dmax, HESP_MAX_SEARCH_LEVEL);
+  if (b->n_cand < 0 || b->nt < 1 || b->dmax < 0 || b->dmax > HESP_MAX_LEVEL || (b->nt << b->dmax) > HESP_MAX_FINE)
+    return fail(HESP_EINVAL, "%s: n_cand=%d nt=%d dmax=%d outside the supported range", who, b->n_cand, b->nt,
+                b->dmax);
   const int64_t nf = hesp_tree_flag_count(b->nt, b->dmax);
   if (b->n_cand > 0 && nf > 0 && !b->d_flags) return fail(HESP_EINVAL, "%s: null flags", who);
   v.n_cand = b->n_cand;
@@ -868,7 +867,7 @@ int hesp_simulate_tree_batch(hesp_plan* plan, const hesp_platform* pf, hesp_poli
 }
 
 int64_t hesp_tree_flag_count(int32_t nt, int32_t dmax) {
-  if (nt < 1 || dmax < 0 || dmax > HESP_MAX_SEARCH_LEVEL) return -1;
+  if (nt < 1 || dmax < 0 || dmax > HESP_MAX_LEVEL) return -1;
   int64_t n = 0;
   for (int l = 0; l < dmax; l++) n += tet3((int64_t)nt << l);
   return n;

@@ -535,7 +535,7 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare(SimTables tb, BatchView bv
 // (the walk over a candidate's tasks and the last-writer scan: hesp_tree.h)
 
 __device__ __forceinline__ bool tree_shape_ok(int nt, int dmax) {
-  return nt >= 1 && dmax >= 0 && dmax <= kMaxSearchLevel && (nt << dmax) <= kMaxFine;
+  return nt >= 1 && dmax >= 0 && dmax <= kMaxLevel && (nt << dmax) <= kMaxFine;
 }
 
 // exact task and edge counts of every split-tree candidate
@@ -610,16 +610,18 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare_tree(SimTables tb, BatchVi
 
   // descriptors, predecessor counts, successor counts
   uint32_t nf_seen = 0;
-  // A task's distinct last writers (at most 3 x 64: one per finest block it
-  // reads) are dealt to the lanes as they are found, lane j holding writers j,
-  // j + 64 and j + 128; their successor counters are then updated by all lanes
-  // together instead of one writer at a time.
+  // A task's distinct last writers are dealt to the lanes as they are found,
+  // lane j holding writers j, j + 64 and j + 128; their successor counters are
+  // then updated by all lanes together instead of one writer at a time.  Writers
+  // past the first 3 x 64 (blocks of side 16 or 32 only) are counted one at a
+  // time as found.
   walk_tree(nt, dmax, flags, [&](int kind, int lv, int K, int I, int J) {
     const uint32_t f = nf_seen++;
     uint32_t wr[3] = {kNil, kNil, kNil};
     int k = 0;
     const int np = scan_task(lw, nt, dmax, kind, lv, K, I, J, f, [&](uint32_t p) {
       for (int h = 0; h < 3; h++) wr[h] = k == l + h * kWave ? p : wr[h];
+      if (k >= 3 * kWave && l == 0) atomicAdd(&sp.cur[p], 1u);
       k++;
     });
     for (int h = 0; h < 3; h++)
@@ -642,6 +644,10 @@ __global__ void __launch_bounds__(kWave, 8) k_prepare_tree(SimTables tb, BatchVi
     int k = 0;
     scan_task(lw, nt, dmax, kind, lv, K, I, J, f, [&](uint32_t p) {
       for (int h = 0; h < 3; h++) wr[h] = k == l + h * kWave ? p : wr[h];
+      if (k >= 3 * kWave && l == 0) {
+        const uint32_t q = atomicAdd(&sp.cur[p], 1u);
+        if (q < n_edges) sp.succ[q] = f;
+      }
       k++;
     });
     uint32_t pos[3];

@@ -49,7 +49,8 @@ def _run(H, torch, pf_in, batch, policy=(0, 0, 0), sched=False, group=0, plan=No
 
 
 @pytest.mark.parametrize("name,nt,dmax,n", [("chol4x4_b512_d1", 4, 1, 512), ("chol4x4_b512_d1", 4, 2, 256),
-                                            ("chol4x4_b512_d1", 3, 3, 96), ("chol16x16_b1024_d2", 8, 2, 96)])
+                                            ("chol4x4_b512_d1", 3, 3, 96), ("chol16x16_b1024_d2", 8, 2, 96),
+                                            ("chol4x4_b512_d1", 3, 4, 48), ("chol16x16_b1024_d2", 2, 5, 32)])
 def test_parity_random_trees(H, torch, name, nt, dmax, n):
     w = I.WORKLOADS[name]
     pf = w.platform()
@@ -80,8 +81,24 @@ def test_uniform_trees_equal_depth_candidates(H, torch):
     assert (st == 0).all() and np.array_equal(got_tree, ms.cpu().numpy())
 
 
+def test_uniform_trees_equal_depth_candidates_at_depth_five(H, torch):
+    """Depth-5 flags that split whole clusters reproduce hesp_simulate_batch's
+    results (walk and last-writer scan on block sides down to b/32)."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf_in = w.platform()
+    nt, dmax = 3, 5
+    bt = I.uniform_batch(w.seed, 24, nt, w.b, dmax, 1, 2, first=70)
+    assert int(bt.depth.max()) == 5
+    flags = np.concatenate([I.tree_flags_from_depth(nt, dmax, bt.candidate(c)) for c in range(bt.n)])
+    nf = I.tree_flag_count(nt, dmax)
+    tb = I.Batch(w.b, bt.nt.copy(), bt.dmax.copy(), np.arange(bt.n + 1, dtype=np.int64) * nf, flags)
+    got_tree, st, _, _ = _run(H, torch, pf_in, tb)
+    want, _ = O.simulate_batch(pf_in, bt, NTHREADS)
+    assert (st == 0).all() and np.array_equal(got_tree, want)
+
+
 def test_generator_matches_host_draws(H, torch):
-    for nt, dmax in ((4, 2), (16, 2), (3, 3)):
+    for nt, dmax in ((4, 2), (16, 2), (3, 3), (3, 5)):
         thr = I.split_threshold(1, 3)
         tb = H.generate_tree_uniform(9, 1000, 20, nt, dmax, thr)
         host = I.tree_batch(9, 20, nt, 512, dmax, 1, 3, first=1000)

@@ -12,7 +12,7 @@ def _pf():
     return I.WORKLOADS["chol4x4_b512_d1"].platform()
 
 
-@pytest.mark.parametrize("nt,dmax", [(1, 1), (2, 1), (3, 2), (4, 2), (3, 3)])
+@pytest.mark.parametrize("nt,dmax", [(1, 1), (2, 1), (3, 2), (4, 2), (3, 3), (2, 4), (1, 5)])
 def test_uniform_trees_equal_per_cluster_depths(nt, dmax):
     """Flags that split every task under a top-level task down to its depth
     give exactly the per-cluster partition: same tasks, edges and schedule."""
