@@ -52,7 +52,6 @@ extern "C" {
 #define HESP_MAX_PTYPES 8   /* processor types */
 #define HESP_MAX_MEM 16     /* memory spaces (space 0 is the host) */
 #define HESP_MAX_LEVEL 5    /* split depth per task: block sides b, b/2, ..., b/32 */
-#define HESP_MAX_SEARCH_LEVEL 3  /* hesp_solve_tree and exhaustive enumeration: b .. b/8 */
 #define HESP_MAX_FINE 512   /* nt * 2^dmax, the finest tile count per dimension */
 
 const char *hesp_last_error(void);
@@ -501,8 +500,7 @@ int hesp_search(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy, co
  * (cluster, new depth, score; cluster -1 when none).  A chain whose simulation
  * fails (a depth above dmax, or above a fixed-capacity plan) gets -1 in its
  * trace and keeps makespan -1 if it never succeeded.  Limits: tet(nt) <= 4096,
- * n_procs <= 64; hesp_solve: dmax and platform max_level <= HESP_MAX_LEVEL;
- * hesp_solve_tree: dmax and max_level <= HESP_MAX_SEARCH_LEVEL.  Device
+ * n_procs <= 64, dmax and platform max_level <= HESP_MAX_LEVEL.  Device
  * workspace is allocated per call (n_chains x tet(nt 2^dmax) tasks); the call
  * synchronises `stream` before it returns. */
 #define HESP_LIST_ALL 0

@@ -48,7 +48,6 @@ enum : int { CHOL = 0, TRSM = 1, SYRK = 2, GEMM = 3 };
 constexpr int kCoordBits = 9;
 constexpr int kMaxFine = 1 << kCoordBits;     // nt * 2^dmax must not exceed this
 constexpr int kMaxLevel = 5;                  // split depth 0..5 (b, b/2, ..., b/32)
-constexpr int kMaxSearchLevel = 3;            // the split-tree solver and enumeration: depth 0..3
 constexpr int kMaxWaveLevel = 3;              // candidates simulated with 64 lanes: depth 0..3
 
 HESP_HD int64_t tet3(int64_t n) { return n * (n + 1) * (n + 2) / 6; }

@@ -88,7 +88,7 @@ double now_ms() {
 extern "C" {
 
 int hesp_generate_enumerate(int64_t first, int32_t n_cand, int32_t nt, int32_t dmax, uint8_t* d_depth, void* stream) {
-  if (first < 0 || n_cand < 0 || nt < 1 || dmax < 0 || dmax > kMaxSearchLevel || (nt << dmax) > kMaxFine ||
+  if (first < 0 || n_cand < 0 || nt < 1 || dmax < 0 || dmax > kMaxLevel || (nt << dmax) > kMaxFine ||
       (n_cand > 0 && !d_depth))
     return fail(HESP_EINVAL, "hesp_generate_enumerate: bad argument");
   if (n_cand == 0) return HESP_OK;

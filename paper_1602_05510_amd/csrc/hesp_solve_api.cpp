@@ -195,12 +195,12 @@ int hesp_solve_tree(hesp_plan* plan, const hesp_platform* pf, hesp_policy policy
                     int64_t* d_steps, void* stream) {
   if (!sp) return fail(HESP_EINVAL, "hesp_solve_tree: null parameters");
   const int B = sp->n_chains, nt = sp->nt, dmax = sp->dmax;
-  if (dmax < 1 || nt < 1 || dmax > kMaxSearchLevel)
-    return fail(HESP_EINVAL, "hesp_solve_tree: need 1 <= dmax <= 3 (the clusters are the tasks above the last level)");
+  if (dmax < 1 || nt < 1 || dmax > kMaxLevel)
+    return fail(HESP_EINVAL, "hesp_solve_tree: need 1 <= dmax <= %d (the clusters are the tasks above the last level)",
+                kMaxLevel);
   const int64_t nn = hesp_tree_flag_count(nt, dmax);
   solve::SolveTables tb;
-  RC_TRY(solve_setup(plan, pf, sp, nn, d_flags, d_best_flags, d_best_makespan, "hesp_solve_tree", kMaxSearchLevel,
-                     tb));
+  RC_TRY(solve_setup(plan, pf, sp, nn, d_flags, d_best_flags, d_best_makespan, "hesp_solve_tree", kMaxLevel, tb));
 
   hipStream_t s = (hipStream_t)stream;
   const int64_t max_tasks = tet3((int64_t)nt << dmax);

@@ -19,7 +19,6 @@ LIB_PATH = os.path.join(PKG, "libhesp_san.so" if os.environ.get("HESP_SANITIZE")
 
 HESP_OK, HESP_EINVAL, HESP_ENOMEM, HESP_EHIP, HESP_ECAPACITY, HESP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MAX_PROCS, MAX_PTYPES, MAX_MEM, MAX_LEVEL, MAX_FINE = 64, 8, 16, 5, 512
-MAX_SEARCH_LEVEL = 3
 
 P = ctypes.c_void_p
 i32, i64, u32, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64

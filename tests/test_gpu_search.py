@@ -35,7 +35,7 @@ def _host_batch(depth, nt, dmax, b):
                    np.arange(n + 1, dtype=np.int64) * n_top, dep)
 
 
-@pytest.mark.parametrize("nt,dmax,first,n", [(4, 1, 123456, 5000), (2, 2, 7, 81), (3, 3, 0, 300)])
+@pytest.mark.parametrize("nt,dmax,first,n", [(4, 1, 123456, 5000), (2, 2, 7, 81), (3, 3, 0, 300), (2, 5, 11, 1296)])
 def test_enumerate(H, torch, nt, dmax, first, n):
     db = H.generate_enumerate(first, n, nt, dmax)
     got = db.depth.cpu().numpy().reshape(n, I.tet(nt))

@@ -191,6 +191,20 @@ def test_tree_chains_match_reference(H, torch, lst, sampling):
         _check_tree_chain(pf_in, nt, dmax, w.b, flags0, iters, lst, sampling, seed, got, r)
 
 
+@pytest.mark.parametrize("dmax", [4, 5])
+def test_tree_chains_depth_four_and_five(H, torch, dmax):
+    """One 1024 tile split up to 4 or 5 times (145 or 961 split flags), three
+    chains from random split trees, ten iterations each."""
+    w = I.WORKLOADS["chol4x4_b512_d1"]
+    pf_in = w.platform()
+    nt, B, iters, seed = 1, 3, 10, 5
+    tb = I.tree_batch(23, B, nt, 1024, dmax, 1, 2)
+    flags0 = tb.depth.reshape(B, -1)
+    got = _run_tree(H, torch, pf_in, nt, dmax, 1024, flags0, iters, 0, 1, seed)
+    for r in range(B):
+        _check_tree_chain(pf_in, nt, dmax, 1024, flags0, iters, 0, 1, seed, got, r)
+
+
 def test_tree_chains_depth_three_and_other_heuristics(H, torch):
     w = I.WORKLOADS["chol4x4_b512_d1"]
     pf_in = w.platform()

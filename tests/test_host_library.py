@@ -218,7 +218,7 @@ def test_solve_tree_argument_errors_need_no_gpu():
                                        fake, None, None, None)
     assert call(H.SolveParams(1, 4, 1, 4, 0, 0, 0), plan=None) == H.HESP_EINVAL
     assert call(H.SolveParams(1, 4, 0, 4, 0, 0, 0)) == H.HESP_EINVAL            # no level below dmax
-    assert call(H.SolveParams(1, 2, 4, 4, 0, 0, 0)) == H.HESP_EINVAL            # split trees: dmax <= 3
+    assert call(H.SolveParams(1, 1, 6, 4, 0, 0, 0)) == H.HESP_EINVAL            # dmax above 5
     assert call(H.SolveParams(1, 14, 2, 4, 0, 0, 0)) == H.HESP_EUNSUPPORTED     # 560 + 4,060 > 4,096 flags
     assert call(H.SolveParams(1, 4, 2, 4, 5, 0, 0)) == H.HESP_EINVAL            # no such list
 
