@@ -167,7 +167,7 @@ def test_deep_refusals(H, torch):
     with pytest.raises(RuntimeError, match="bad problem shape"):
         H.search(H.Plan(), pf, 4, 6, H.SEARCH_RANDOM, rounds=1, batch=16, seed=1)
     with pytest.raises(Exception):
-        H.generate_tree_uniform(1, 0, 4, 4, 4, 1000)
+        H.generate_tree_uniform(1, 0, 4, 4, 6, 1000)       # split depth above 5
     # a ragged candidate above the batch's stated maximum depth fails alone
     rag = I.ragged_batch(W.seed, 32, 4, 6, 4, W.b, 1, 2, first=40)
     full = H.DeviceBatch.from_host(rag)
