@@ -232,12 +232,15 @@ typedef struct {
                                   whose workspace (104 T + 4 E + 8 V + 4 (tet(nt) + 1) bytes, T tasks, E
                                   edges, V finest blocks x memory spaces) exceeds 48 KiB get HESP_ECAPACITY */
 } hesp_plan_opts;
-/* A plan with max_tasks, max_edges and group all set is a fixed-capacity plan:
- * its workspace follows from the capacities and the batch shape, so after one
- * call with a batch of a given (n_cand, nt, dmax) further calls of that shape do
- * no host synchronisation, no allocation and no autotuning -- only kernel
- * launches on `stream`, which can be captured in a HIP graph and replayed (the
- * graph keeps the batch and output pointers of the captured call).  A captured
+/* A plan with max_tasks and max_edges set is a fixed-capacity plan: its
+ * workspace follows from the capacities and the batch shape, so after one call
+ * with a batch of a given (n_cand, nt, dmax) further calls of that shape do no
+ * host synchronisation, no allocation and no autotuning (group 0: the first call
+ * of a shape times 16, 32 and 64 lanes per candidate and the plan keeps the
+ * choice) -- only kernel launches on `stream`, which can be captured in a HIP
+ * graph and replayed (the graph keeps the batch and output pointers of the
+ * captured call).  A captured group-0 call whose shape the plan has not seen
+ * gives HESP_EUNSUPPORTED.  A captured
  * call runs its memory chunks one after the other on `stream` alone; a fused
  * fixed-capacity plan captures any batch as one simulation launch.  Candidates
  * above the capacities get HESP_ECAPACITY. */

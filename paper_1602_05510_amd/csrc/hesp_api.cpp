@@ -492,7 +492,7 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
                         s, plan->layout_part.as<int64_t>()));
 
   // chunk boundaries: the largest chunk must fit the memory budget
-  const bool fixed = plan->opts.max_tasks > 0 && plan->opts.max_edges > 0 && plan->opts.group > 0;
+  const bool fixed = plan->opts.max_tasks > 0 && plan->opts.max_edges > 0;
   int32_t chunk = std::min<int32_t>(plan->chunk, n);
   if (plan->opts.chunks > 1) chunk = std::min<int32_t>(chunk, (n + plan->opts.chunks - 1) / plan->opts.chunks);
   int32_t n_chunks = 0;
@@ -615,6 +615,13 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
     if (it != plan->tuned.end()) {
       group = it->second;
     } else {
+      // the timing calls synchronise the stream: a captured call takes the choice
+      // an earlier call of the same shape made
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      HIP_TRY(hipStreamIsCapturing(s, &cs));
+      if (cs != hipStreamCaptureStatusNone)
+        return fail(HESP_EUNSUPPORTED, "hesp_simulate_batch: a captured call with group 0 needs an earlier call "
+                                       "of the same batch shape (which chooses the lanes per candidate)");
       const int32_t sub = std::min<int32_t>(std::min(chunk, n), 8192);
       float best_ms = 0.f;
       hipEvent_t e0, e1;
@@ -713,7 +720,7 @@ static int run_unfused(hesp_plan* plan, const SimTables& tb, BatchView bv, bool 
 static int run_fused(hesp_plan* plan, const SimTables& tb, BatchView bv, const OutView& ov, hipStream_t s,
                      int32_t n) {
   bv.n_cand = n;
-  const bool fixed = plan->opts.max_tasks > 0 && plan->opts.max_edges > 0 && plan->opts.group > 0;
+  const bool fixed = plan->opts.max_tasks > 0 && plan->opts.max_edges > 0;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(s, &cap));
   if (cap != hipStreamCaptureStatusNone && !fixed)

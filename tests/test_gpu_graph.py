@@ -68,6 +68,51 @@ def test_graph_replay_matches_eager(H, torch, chunks):
     assert np.array_equal(ms[:64].cpu().numpy(), want)
 
 
+def test_graph_replay_with_tuned_lanes(H, torch):
+    """A fixed-capacity plan with group 0: the first (eager) call of the shape
+    times 16, 32 and 64 lanes per candidate and keeps the choice; the captured
+    call reuses it, and the graph's replays equal eager calls and the oracle."""
+    w = I.WORKLOADS["chol16x16_b1024_d2"]
+    pf_in = w.platform()
+    pf = H.Platform.from_inputs(pf_in, w.b, w.dmax)
+    thr = I.split_threshold(w.p_num, w.p_den)
+    n, reps = 2048, 2
+    batches = [H.generate_uniform(w.seed, 30_000 + r * n, n, w.nt, w.dmax, thr) for r in range(reps + 1)]
+    cap_t = cap_e = 0
+    for b in batches:
+        nt_, ne_ = H.count_batch(b)
+        cap_t, cap_e = max(cap_t, int(nt_.max())), max(cap_e, int(ne_.max()))
+    dep = torch.empty_like(batches[0].depth)
+    dep.copy_(batches[0].depth)
+    db = H.DeviceBatch(n, w.nt, w.dmax, dep)
+    ms = torch.empty(n, dtype=torch.int64, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    plan = H.Plan(max_tasks=cap_t, max_edges=cap_e)          # group 0: tuned by the first call
+    print("graph: fixed plan with tuned lanes", flush=True)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        H.simulate_batch(plan, pf, db, ms, st)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        H.simulate_batch(plan, pf, db, ms, st)
+    ms2 = torch.empty_like(ms)
+    st2 = torch.empty_like(st)
+    for r in range(1, reps + 1):
+        dep.copy_(batches[r].depth)
+        g.replay()
+        torch.cuda.synchronize()
+        H.simulate_batch(H.Plan(), pf, batches[r], ms2, st2)
+        torch.cuda.synchronize()
+        assert bool((st == 0).all().item())
+        assert torch.equal(ms, ms2), r
+    host = w.batch(32, first=30_000 + reps * n)
+    want, _ = O.simulate_batch(pf_in, host, 8)
+    assert np.array_equal(ms[:32].cpu().numpy(), want)
+
+
 def test_fixed_plan_capacity_status(H, torch):
     w = I.WORKLOADS["chol4x4_b512_d1"]
     pf = H.Platform.from_inputs(w.platform(), w.b, w.dmax)
