@@ -396,7 +396,8 @@ int hesp_mlp_train(hesp_mlp *mlp, const uint16_t *d_x, const float *d_t, int64_t
  * for processor type p and task kind (chol, trsm, syrk, gemm); n_out >= 4 * n_ptypes. */
 int hesp_mlp_rate_features(const hesp_cost_model *cm, float *out, int32_t n_out);
 /* Features of candidates with more top-level tasks than inputs: for each kind the
- * fraction of its top-level tasks at each depth 0..3 (16 values, kind-major), for
+ * fraction of its top-level tasks at depth 0, 1, 2 and 3 or more (16 values,
+ * kind-major), for
  * each kind and each half of the k range (k < nt/2, k >= nt/2) the mean depth (8
  * values), then the n_rate (<= 8) values of d_rate.  d_depth [n][tet(nt)].
  * Synchronises `stream` (a small table of the top-level tasks is uploaded). */
