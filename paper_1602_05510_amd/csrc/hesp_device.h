@@ -211,10 +211,17 @@ __device__ __forceinline__ int dw_atom(uint64_t w, int b) { return (int)((w >> (
 __device__ __forceinline__ int dw_level(uint64_t w) { return (int)((w >> 54) & 7u); }
 __device__ __forceinline__ int dw_kind(uint64_t w) { return (int)((w >> 57) & 3u); }
 __device__ __forceinline__ int dw_blocks(uint64_t w) { return (int)((w >> 59) & 3u); }
-// what a completion needs of the task: the written block's atom and the level
+// A task with at most two successors keeps their numbers in its record in place
+// of its edge range (kNil for an absent one); bit 61 of its dispatch word says so.
+constexpr uint64_t kDwInline = 1ull << 61;
+__device__ __forceinline__ bool dw_inline(uint64_t w) { return (w & kDwInline) != 0; }
+// what a completion needs of the task: the written block's atom, the level and
+// (bit 31) whether its successors are inline
 __device__ __forceinline__ uint32_t completion_word(uint64_t w) {
-  return (uint32_t)dw_atom(w, dw_blocks(w) - 1) | ((uint32_t)dw_level(w) << 18);
+  return (uint32_t)dw_atom(w, dw_blocks(w) - 1) | ((uint32_t)dw_level(w) << 18) | ((uint32_t)dw_inline(w) << 31);
 }
+__device__ __forceinline__ int cw_level(uint32_t cw) { return (int)((cw >> 18) & 7u); }
+__device__ __forceinline__ bool cw_inline(uint32_t cw) { return (cw >> 31) != 0; }
 
 
 // ---------------------------------------------------------------- lane groups

@@ -374,11 +374,20 @@ __device__ __forceinline__ int prep_finish(int prep_in, const OutView& out, int 
       // the whole record in two 16-byte stores
       const int kind = desc_kind(dsc), lvl = desc_level(dsc);
       const int K = desc_K(dsc), I = desc_I(dsc), J = desc_J(dsc);
+      // at most two successors: their numbers replace the edge range
+      const uint32_t deg = e1 - e0;
+      uint64_t dwv = dispatch_word(nt, dmax, kind, lvl, K, I, J);
+      uint32_t s0 = e0, s1 = e1;
+      if (deg <= 2u) {
+        s0 = deg >= 1u ? vld(&sp.succ[e0]) : kNil;
+        s1 = deg == 2u ? vld(&sp.succ[e0 + 1]) : kNil;
+        dwv |= kDwInline;
+      }
       longlong2 kw, re;
-      kw.x = (long long)(task_key_of(dmax, lvl, K, I, J) | ((uint64_t)e0 << 32));
-      kw.y = (long long)dispatch_word(nt, dmax, kind, lvl, K, I, J);
+      kw.x = (long long)(task_key_of(dmax, lvl, K, I, J) | ((uint64_t)s0 << 32));
+      kw.y = (long long)dwv;
       re.x = r;
-      re.y = (long long)e1;
+      re.y = (long long)s1;
       *reinterpret_cast<longlong2*>(&sp.rec[4 * f + kRecKE]) = kw;
       *reinterpret_cast<longlong2*>(&sp.rec[4 * f + kRecRank]) = re;
     }
