@@ -16,7 +16,10 @@
  *   2. expansion (Fig. 1 loop nest; section 2.1 "Recursive task
  *      partitioners"): every top-level task of Fig. 1 is replaced by the
  *      blocked algorithm of its own kind on a 2^d x 2^d sub-tiling, emitted in
- *      right-looking loop order;
+ *      right-looking loop order -- or, for a grain batch (partition parameter
+ *      p = 1/f with any integer f, section 2.1 "Iterative solver"), on an
+ *      f x f sub-tiling, so that blocks of different tasks may overlap
+ *      partially (Fig. 4: intersection blocks of the data DAG);
  *   3. dependences (section 2.1, RaW/WaR/WaW): a sequential scan over the
  *      finest data atoms, last writer -> later reader/writer and
  *      readers-since-last-write -> next writer;
@@ -94,6 +97,43 @@ int oracle_transfer_time(int64_t n_atoms, int64_t atom_side, int64_t elem_bytes,
     return OR_OK;
 }
 
+/*
+ * The same two models for a block side that need not be an integer (grain
+ * batches): a task on a block of side b/f, and k atoms of side b/L.
+ *   time = ceil(c 1000 b (b^2 + f^2 h^2) / (3 f^3 Rmax))  (c = 1, 3, 3, 6 as above)
+ *   xfer = latency + ceil(elem_bytes k b^2 / (L^2 bw))
+ * Both equal the integer forms above whenever b/f and b/L are integers.
+ */
+static int64_t ceil_div128(__int128 a, __int128 b) { return (int64_t)(a / b + (a % b != 0)); }
+
+static int grain_task_time(int type, int64_t b, int64_t f, int64_t rmax_mflops, int64_t h, int64_t *out)
+{
+    if (type < 0 || type > 3 || b <= 0 || f <= 0 || rmax_mflops <= 0 || h < 0) return OR_EINVAL;
+    __int128 num = (__int128)flops_times3(type, 1) * 1000 * b * ((__int128)b * b + (__int128)f * f * h * h);
+    __int128 den = (__int128)3 * f * f * f * rmax_mflops;
+    *out = ceil_div128(num, den);
+    return OR_OK;
+}
+
+static int grain_transfer_time(int64_t n_atoms, int64_t b, int64_t L, int64_t elem_bytes,
+                               int64_t latency_ns, int64_t bw, int shared, int64_t *out)
+{
+    if (n_atoms < 0 || b <= 0 || L <= 0 || bw <= 0) return OR_EINVAL;
+    if (shared || n_atoms == 0) { *out = 0; return OR_OK; }
+    *out = latency_ns + ceil_div128((__int128)elem_bytes * n_atoms * b * b, (__int128)L * L * bw);
+    return OR_OK;
+}
+
+/* Atom grid of a candidate: every tile is cut into L x L atoms, and a block of
+ * grain index g (fac[g] blocks per tile side) covers (L/fac[g])^2 of them.  A
+ * depth candidate has L = 2^dmax and fac[l] = 2^l; a grain batch has
+ * L = lcm(fac), so the blocks of two grains are unions of common atoms and
+ * their intersections (the intersection descriptors of the data DAG, Fig. 4)
+ * need no node of their own. */
+typedef struct { int L, n, pow2; int fac[8]; } or_grid;
+
+static int grid_w(const or_grid *gr, int level) { return gr->L / gr->fac[level]; }
+
 typedef struct {
     int n_procs, n_mem, n_ptypes;
     const int32_t *proc_type, *proc_mem;
@@ -156,9 +196,8 @@ static int in_range(int x, int lo, int s) { return x >= lo && x < lo + s; }
  * top-level task (its k, i, j ranges at granularity 2^d).  This emits exactly
  * the fine tasks whose (K,I,J) fall in the cell, in right-looking order.
  */
-static int emit_cell(or_tasklist *l, int top, int d, int k, int i, int j)
+static int emit_cell(or_tasklist *l, int top, int d, int s, int k, int i, int j)
 {
-    int s = 1 << d;
     int ks = k * s, is = i * s, js = j * s;
     for (int K = ks; K < ks + s; K++) {
         if (in_range(K, is, s) && in_range(K, js, s))
@@ -179,23 +218,24 @@ static int emit_cell(or_tasklist *l, int top, int d, int k, int i, int j)
     return OR_OK;
 }
 
-/* Fig. 1: top-level tasks in program order, each expanded in place */
-static int expand(int nt, const uint8_t *depth, or_tasklist *out)
+/* Fig. 1: top-level tasks in program order, each expanded in place on the
+ * fac[depth[t]] x fac[depth[t]] sub-tiling of its cell */
+static int expand(int nt, const uint8_t *depth, const or_grid *gr, or_tasklist *out)
 {
     int top = 0;
     for (int k = 0; k < nt; k++) {
-        if (emit_cell(out, top, depth[top], k, k, k)) return OR_ENOMEM;
+        if (emit_cell(out, top, depth[top], gr->fac[depth[top]], k, k, k)) return OR_ENOMEM;
         top++;
         for (int j = k + 1; j < nt; j++) {
-            if (emit_cell(out, top, depth[top], k, k, j)) return OR_ENOMEM;
+            if (emit_cell(out, top, depth[top], gr->fac[depth[top]], k, k, j)) return OR_ENOMEM;
             top++;
         }
         for (int i = k + 1; i < nt; i++) {
             for (int j = i + 1; j < nt; j++) {
-                if (emit_cell(out, top, depth[top], k, i, j)) return OR_ENOMEM;
+                if (emit_cell(out, top, depth[top], gr->fac[depth[top]], k, i, j)) return OR_ENOMEM;
                 top++;
             }
-            if (emit_cell(out, top, depth[top], k, i, i)) return OR_ENOMEM;
+            if (emit_cell(out, top, depth[top], gr->fac[depth[top]], k, i, i)) return OR_ENOMEM;
             top++;
         }
     }
@@ -251,7 +291,7 @@ static int emit_tree(or_tasklist *out, const or_tree *tr, int top, int type, int
     int N = tr->nt << l;
     if (l < tr->dmax && tr->flags[tr->off[l] + tr->index[l][((size_t)K * N + I) * N + J]]) {
         or_tasklist kids = {0, 0, 0};
-        if (emit_cell(&kids, top, 1, K, I, J)) { free(kids.v); return OR_ENOMEM; }
+        if (emit_cell(&kids, top, 1, 2, K, I, J)) { free(kids.v); return OR_ENOMEM; }
         for (int c = 0; c < kids.n; c++)
             if (emit_tree(out, tr, top, kids.v[c].type, l + 1, kids.v[c].K, kids.v[c].I, kids.v[c].J)) {
                 free(kids.v);
@@ -319,10 +359,10 @@ static int cmp_i64(const void *a, const void *b)
 }
 
 /*
- * Atoms: the finest blocks (side b/2^dmax).  A level-l block (R,C) is the set
- * of atoms (R*2^(dmax-l)+u, C*2^(dmax-l)+v), 0 <= u,v < 2^(dmax-l) -- the whole
- * square, also on the diagonal (reading).  Atoms are numbered row-major on the
- * full N x N grid, N = nt * 2^dmax.
+ * Atoms: the finest blocks (side b/L).  A block (R,C) of grain l is the set
+ * of atoms (R*w+u, C*w+v), 0 <= u,v < w = L/fac[l] -- the whole square, also on
+ * the diagonal (reading).  Atoms are numbered row-major on the full N x N grid,
+ * N = nt * L.
  */
 typedef struct {
     int n;                 /* tasks */
@@ -338,9 +378,9 @@ static void dag_free(or_dag *g)
     memset(g, 0, sizeof(*g));
 }
 
-static int build_dag(const or_tasklist *tl, int nt, int dmax, or_dag *g)
+static int build_dag(const or_tasklist *tl, int nt, const or_grid *gr, or_dag *g)
 {
-    int n = tl->n, N = nt << dmax;
+    int n = tl->n, N = nt * gr->L;
     int64_t n_atoms = (int64_t)N * N;
     int64_t *last_w = (int64_t *)malloc((size_t)n_atoms * sizeof(int64_t));
     or_i64list *readers = (or_i64list *)calloc((size_t)n_atoms, sizeof(or_i64list));
@@ -353,10 +393,10 @@ static int build_dag(const or_tasklist *tl, int nt, int dmax, or_dag *g)
     for (int t = 0; t < n; t++) {
         int br[3], bc[3], bw[3];
         int nb = task_blocks(&tl->v[t], br, bc, bw);
-        int sh = dmax - tl->v[t].level, w = 1 << sh;
+        int w = grid_w(gr, tl->v[t].level);
         for (int bi = 0; bi < nb; bi++) {
             for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
-                int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                int64_t a = (int64_t)(br[bi] * w + u) * N + (bc[bi] * w + v);
                 if (last_w[a] >= 0 && last_w[a] != t)
                     if (il_push(&edges, last_w[a] * n + t)) { rc = OR_ENOMEM; goto done; }
                 if (bw[bi]) {           /* write: WaW above, WaR from readers */
@@ -402,12 +442,11 @@ done:
  * mapping time T, or later if some missing atom has no copy valid yet (its
  * earliest valid-from over all spaces is still ahead, as for a host copy still
  * in flight after a write-around). */
-static int64_t xfer_start(const int64_t *vf, int M, int64_t N, int R, int C, int sh, int m, int64_t T)
+static int64_t xfer_start(const int64_t *vf, int M, int64_t N, int R, int C, int w, int m, int64_t T)
 {
     int64_t go = T;
-    int w = 1 << sh;
     for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
-        int64_t a = (int64_t)((R << sh) + u) * N + ((C << sh) + v);
+        int64_t a = (int64_t)(R * w + u) * N + (C * w + v);
         if (vf[a * M + m] != OR_INF) continue;
         int64_t src = OR_INF;
         for (int mm = 0; mm < M; mm++) if (vf[a * M + mm] < src) src = vf[a * M + mm];
@@ -422,21 +461,25 @@ typedef struct {
     int64_t *xfer;   /* [4^dmax + 1] */
 } or_tables;
 
-static int make_tables(const or_platform *pf, int dmax, or_tables *tb)
+static int make_tables(const or_platform *pf, const or_grid *gr, or_tables *tb)
 {
-    int L = dmax + 1;
-    int64_t na = (int64_t)1 << (2 * dmax);
+    int L = gr->n, dmax = gr->n - 1;
+    int64_t na = (int64_t)gr->L * gr->L;
     tb->cost = (int64_t *)malloc((size_t)pf->n_ptypes * 4 * L * sizeof(int64_t));
     tb->xfer = (int64_t *)malloc((size_t)(na + 1) * sizeof(int64_t));
     if (!tb->cost || !tb->xfer) return OR_ENOMEM;
     for (int pt = 0; pt < pf->n_ptypes; pt++)
         for (int ty = 0; ty < 4; ty++)
             for (int l = 0; l < L; l++)
-                if (oracle_task_time(ty, pf->b >> l, pf->rmax[pt * 4 + ty], pf->h[pt],
-                                     &tb->cost[(pt * 4 + ty) * L + l])) return OR_EINVAL;
+                if (gr->pow2 ? oracle_task_time(ty, pf->b >> l, pf->rmax[pt * 4 + ty], pf->h[pt],
+                                                &tb->cost[(pt * 4 + ty) * L + l])
+                             : grain_task_time(ty, pf->b, gr->fac[l], pf->rmax[pt * 4 + ty], pf->h[pt],
+                                               &tb->cost[(pt * 4 + ty) * L + l])) return OR_EINVAL;
     for (int64_t k = 0; k <= na; k++)
-        if (oracle_transfer_time(k, pf->b >> dmax, pf->elem_bytes, pf->latency_ns, pf->bw,
-                                 pf->shared, &tb->xfer[k])) return OR_EINVAL;
+        if (gr->pow2 ? oracle_transfer_time(k, pf->b >> dmax, pf->elem_bytes, pf->latency_ns, pf->bw,
+                                            pf->shared, &tb->xfer[k])
+                     : grain_transfer_time(k, pf->b, gr->L, pf->elem_bytes, pf->latency_ns, pf->bw,
+                                           pf->shared, &tb->xfer[k])) return OR_EINVAL;
     return OR_OK;
 }
 
@@ -449,20 +492,20 @@ static void free_tables(or_tables *tb) { free(tb->cost); free(tb->xfer); }
  * or arriving.  Among blocks used equally recently the one with the smaller
  * number goes first: tiles of the upper triangle row by row, then row-major
  * inside a tile. */
-static int64_t atom_number(int nt, int dmax, int row, int col)
+static int64_t atom_number(int nt, int L, int row, int col)
 {
-    int tr = row >> dmax, tc = col >> dmax, mask = (1 << dmax) - 1;
+    int tr = row / L, tc = col / L;
     int64_t tile = (int64_t)tr * nt - (int64_t)tr * (tr - 1) / 2 + (tc - tr);
-    return (tile << (2 * dmax)) + ((int64_t)(row & mask) << dmax) + (col & mask);
+    return tile * L * L + (int64_t)(row % L) * L + (col % L);
 }
 
 /* does finest block (row, col) belong to one of the task's blocks? */
-static int task_has_atom(const or_task *t, int dmax, int row, int col)
+static int task_has_atom(const or_task *t, int w, int row, int col)
 {
     int br[3], bc[3], bw[3];
-    int nb = task_blocks(t, br, bc, bw), sh = dmax - t->level;
+    int nb = task_blocks(t, br, bc, bw);
     for (int bi = 0; bi < nb; bi++)
-        if ((row >> sh) == br[bi] && (col >> sh) == bc[bi]) return 1;
+        if (row / w == br[bi] && col / w == bc[bi]) return 1;
     return 0;
 }
 
@@ -542,8 +585,9 @@ static int link_of(const or_platform *pf, int m)
 
 /* depth: split depth per top-level task, or (tree != 0) the split flags above */
 static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *depth, int tree,
-                        or_result *res, const or_outputs *o)
+                        const or_grid *grain, or_result *res, const or_outputs *o)
 {
+    or_grid grid;
     or_tasklist tl = {0, 0, 0};
     or_dag g;
     or_tables tb = {0, 0, 0, 0};
@@ -555,23 +599,35 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
     or_heap heap = {0, 0};
     memset(&g, 0, sizeof(g));
 
-    if (nt < 1 || dmax < 0 || dmax > 6 || (pf->b >> dmax) << dmax != pf->b) return OR_EINVAL;
-    if (tree) {
+    if (grain) {
+        /* grain batch: depth[t] is the grain index of top-level task t */
+        grid = *grain;
+        if (nt < 1 || tree) return OR_EINVAL;
+        int n_top = nt * (nt + 1) * (nt + 2) / 6;
+        for (int t = 0; t < n_top; t++) if (depth[t] >= grid.n) return OR_EINVAL;
+        rc = expand(nt, depth, &grid, &tl);
+    } else if (nt < 1 || dmax < 0 || dmax > 6 || (pf->b >> dmax) << dmax != pf->b) {
+        return OR_EINVAL;
+    } else if (tree) {
+        grid.L = 1 << dmax; grid.n = dmax + 1; grid.pow2 = 1;
+        for (int l = 0; l <= dmax; l++) grid.fac[l] = 1 << l;
         int64_t nf = tree_flag_count(nt, dmax);
         for (int64_t x = 0; x < nf; x++) if (depth[x] > 1) return OR_EINVAL;
         rc = expand_tree(nt, dmax, depth, &tl);
     } else {
         int n_top = nt * (nt + 1) * (nt + 2) / 6;
         for (int t = 0; t < n_top; t++) if (depth[t] > dmax) return OR_EINVAL;
-        rc = expand(nt, depth, &tl);
+        grid.L = 1 << dmax; grid.n = dmax + 1; grid.pow2 = 1;
+        for (int l = 0; l <= dmax; l++) grid.fac[l] = 1 << l;
+        rc = expand(nt, depth, &grid, &tl);
     }
     if (rc) goto done;
-    rc = build_dag(&tl, nt, dmax, &g);
+    rc = build_dag(&tl, nt, &grid, &g);
     if (rc) goto done;
-    rc = make_tables(pf, dmax, &tb);
+    rc = make_tables(pf, &grid, &tb);
     if (rc) goto done;
 
-    int n = tl.n, P = pf->n_procs, M = pf->n_mem, L = dmax + 1, N = nt << dmax;
+    int n = tl.n, P = pf->n_procs, M = pf->n_mem, L = grid.n, N = nt * grid.L;
     W = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     rank = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     start = (int64_t *)malloc((size_t)n * sizeof(int64_t));
@@ -594,7 +650,9 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
     /* 6. capacities in finest blocks (-1: unbounded); supported with write-back
      * caching, EFT-P and independent transfers */
     int capped = 0;
-    int64_t atom_bytes = pf->elem_bytes * (pf->b >> dmax) * (pf->b >> dmax);
+    int64_t atom_bytes = grid.pow2 ? pf->elem_bytes * (pf->b >> dmax) * (pf->b >> dmax) : 0;
+    for (int m = 0; m < M && !grid.pow2; m++)   /* grain batches: unbounded spaces only */
+        if (m > 0 && pf->capacity && pf->capacity[m] > 0) { rc = OR_EINVAL; goto done; }
     for (int m = 0; m < M; m++) {
         cap[m] = (m > 0 && pf->capacity && pf->capacity[m] > 0) ? pf->capacity[m] / atom_bytes : -1;
         if (cap[m] >= 0) capped = 1;
@@ -624,9 +682,9 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
     for (int t = 0; t < n; t++) { left[t] = g.npred[t]; proc[t] = -1; }
     for (int t = 0; t < n; t++)
         if (left[t] == 0) {
-            int sh = dmax - tl.v[t].level;
-            heap_push(&heap, (or_hent){pf->order ? 0 : rank[t], (int64_t)tl.v[t].K << sh,
-                                       (int64_t)tl.v[t].I << sh, (int64_t)tl.v[t].J << sh, t});
+            int w = grid_w(&grid, tl.v[t].level);
+            heap_push(&heap, (or_hent){pf->order ? 0 : rank[t], (int64_t)tl.v[t].K * w,
+                                       (int64_t)tl.v[t].I * w, (int64_t)tl.v[t].J * w, t});
         }
     /* link contention (reading of the platform's network topology): a transfer
      * occupies the link of the space it goes into, one transfer at a time per
@@ -646,12 +704,12 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             int t = top.task;
             int br[3], bc[3], bw[3];
             int nb = task_blocks(&tl.v[t], br, bc, bw);
-            int sh = dmax - tl.v[t].level, w = 1 << sh;
+            int w = grid_w(&grid, tl.v[t].level);
             if (pf->select == 2) {
                 /* R-P: the u-th idle processor (index order), u drawn for the
                  * task's finest-grid corner (K, I, J) */
-                uint64_t key = ((uint64_t)tl.v[t].K << sh << 18) | ((uint64_t)tl.v[t].I << sh << 9) |
-                               ((uint64_t)tl.v[t].J << sh);
+                uint64_t key = ((uint64_t)(tl.v[t].K * w) << 18) | ((uint64_t)(tl.v[t].I * w) << 9) |
+                               (uint64_t)(tl.v[t].J * w);
                 int u = (int)(sm_draw(pf->seed, 8, key) % (uint64_t)n_idle);
                 for (int p = 0; p < P; p++)
                     if (avail[p] <= T && u-- == 0) { pick = p; break; }
@@ -675,7 +733,7 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                     int64_t places = 0;
                     for (int r = 0; r < N; r++) for (int c = 0; c < N; c++) {
                         int64_t a = (int64_t)r * N + c;
-                        if (pin[a * M + m] > 0 || task_has_atom(&tl.v[t], dmax, r, c)) places++;
+                        if (pin[a * M + m] > 0 || task_has_atom(&tl.v[t], w, r, c)) places++;
                     }
                     if (places > cap[m]) continue;
                 }
@@ -684,14 +742,14 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                 for (int bi = 0; bi < nb; bi++) {
                     int64_t miss = 0, fin = INT64_MIN;
                     for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
-                        int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                        int64_t a = (int64_t)(br[bi] * w + u) * N + (bc[bi] * w + v);
                         int64_t x = vf[a * M + m];
                         if (x == OR_INF) miss++;
                         else if (x > fin) fin = x;
                     }
                     int64_t ready = fin;
                     if (miss > 0) {
-                        int64_t go = xfer_start(vf, M, N, br[bi], bc[bi], sh, m, T);
+                        int64_t go = xfer_start(vf, M, N, br[bi], bc[bi], w, m, T);
                         if (pf->bus && bus_at > go) go = bus_at;
                         if (pf->bus) bus_at = go + tb.xfer[miss];
                         if (go + tb.xfer[miss] > ready) ready = go + tb.xfer[miss];
@@ -722,15 +780,15 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
                 for (int r = 0; r < N; r++) for (int c = 0; c < N; c++) {
                     int64_t a = (int64_t)r * N + c;
                     if (vf[a * M + m] != OR_INF) occ++;
-                    else if (task_has_atom(&tl.v[t], dmax, r, c)) need++;
+                    else if (task_has_atom(&tl.v[t], w, r, c)) need++;
                 }
                 for (int64_t k = occ + need - cap[m]; k > 0; k--) {
                     int64_t va = -1, vu = 0, vn = 0;
                     for (int r = 0; r < N; r++) for (int c = 0; c < N; c++) {
                         int64_t a = (int64_t)r * N + c;
-                        if (vf[a * M + m] == OR_INF || pin[a * M + m] > 0 || task_has_atom(&tl.v[t], dmax, r, c))
+                        if (vf[a * M + m] == OR_INF || pin[a * M + m] > 0 || task_has_atom(&tl.v[t], w, r, c))
                             continue;
-                        int64_t u = use[a * M + m], num = atom_number(nt, dmax, r, c);
+                        int64_t u = use[a * M + m], num = atom_number(nt, grid.L, r, c);
                         if (va < 0 || u < vu || (u == vu && num < vn)) { va = a; vu = u; vn = num; }
                     }
                     if (va < 0) { rc = OR_EINVAL; goto done; }   /* excluded by the check above */
@@ -741,24 +799,24 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             for (int bi = 0; bi < nb; bi++) {
                 int64_t miss = 0;
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
-                    int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                    int64_t a = (int64_t)(br[bi] * w + u) * N + (bc[bi] * w + v);
                     if (vf[a * M + m] == OR_INF) miss++;
                 }
                 if (!miss) continue;
-                int64_t go = xfer_start(vf, M, N, br[bi], bc[bi], sh, m, T);
+                int64_t go = xfer_start(vf, M, N, br[bi], bc[bi], w, m, T);
                 /* shared interconnect: one transfer at a time, in issue order (the
                  * blocks of one task in their order) */
                 if (pf->bus && lfree[link_of(pf, m)] > go) go = lfree[link_of(pf, m)];
                 if (pf->bus) lfree[link_of(pf, m)] = go + tb.xfer[miss];
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
-                    int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                    int64_t a = (int64_t)(br[bi] * w + u) * N + (bc[bi] * w + v);
                     if (vf[a * M + m] == OR_INF) vf[a * M + m] = go + tb.xfer[miss];
                 }
             }
             /* the task's blocks in m: used now, pinned until it finishes */
             for (int bi = 0; bi < nb; bi++)
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
-                    int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                    int64_t a = (int64_t)(br[bi] * w + u) * N + (bc[bi] * w + v);
                     use[a * M + m] = T;
                     pin[a * M + m]++;
                 }
@@ -793,10 +851,10 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
              * reading: the copy to the host costs the transfer of the whole block */
             int br[3], bc[3], bw[3];
             int nb = task_blocks(&tl.v[t], br, bc, bw);
-            int sh = dmax - tl.v[t].level, w = 1 << sh, m = pf->proc_mem[p];
+            int w = grid_w(&grid, tl.v[t].level), m = pf->proc_mem[p];
             for (int bi = 0; bi < nb; bi++)
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++)
-                    pin[((int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v)) * M + m]--;
+                    pin[((int64_t)(br[bi] * w + u) * N + (bc[bi] * w + v)) * M + m]--;
             int64_t host_at = (m == 0) ? Tn : Tn + tb.xfer[(int64_t)w * w];
             if (pf->bus && pf->cache != 0 && m != 0) {     /* the host copy queues on the host's link */
                 int64_t go = Tn > lfree[link_of(pf, 0)] ? Tn : lfree[link_of(pf, 0)];
@@ -806,7 +864,7 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             for (int bi = 0; bi < nb; bi++) {
                 if (!bw[bi]) continue;
                 for (int u = 0; u < w; u++) for (int v = 0; v < w; v++) {
-                    int64_t a = (int64_t)((br[bi] << sh) + u) * N + ((bc[bi] << sh) + v);
+                    int64_t a = (int64_t)(br[bi] * w + u) * N + (bc[bi] * w + v);
                     for (int mm = 0; mm < M; mm++) {
                         int64_t x = OR_INF;
                         if (pf->cache == 0) x = (mm == m) ? Tn : OR_INF;
@@ -819,9 +877,9 @@ static int simulate_one(const or_platform *pf, int nt, int dmax, const uint8_t *
             for (int e = g.succ_ptr[t]; e < g.succ_ptr[t + 1]; e++) {
                 int v = g.succ[e];
                 if (--left[v] == 0) {
-                    int s2 = dmax - tl.v[v].level;
-                    heap_push(&heap, (or_hent){pf->order ? -Tn : rank[v], (int64_t)tl.v[v].K << s2,
-                                               (int64_t)tl.v[v].I << s2, (int64_t)tl.v[v].J << s2, v});
+                    int w2 = grid_w(&grid, tl.v[v].level);
+                    heap_push(&heap, (or_hent){pf->order ? -Tn : rank[v], (int64_t)tl.v[v].K * w2,
+                                               (int64_t)tl.v[v].I * w2, (int64_t)tl.v[v].J * w2, v});
                 }
             }
         }
@@ -888,7 +946,7 @@ int oracle_simulate(int nt, int dmax, const uint8_t *depth,
                       latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus, link, capacity};
     or_outputs o = {max_tasks, task_info, proc_out, start_out, finish_out, rank_out, max_edges, edges_out};
     or_result r;
-    int rc = simulate_one(&pf, nt, dmax, depth, tree, &r, &o);
+    int rc = simulate_one(&pf, nt, dmax, depth, tree, NULL, &r, &o);
     if (rc) return rc;
     if (makespan) *makespan = r.makespan;
     if (n_tasks) *n_tasks = r.n_tasks;
@@ -906,6 +964,7 @@ typedef struct {
     int32_t *n_tasks;
     int32_t *status;
     int tree;
+    const or_grid *grain;   /* grain batch, or NULL */
     int next;
     pthread_mutex_t mu;
 } or_batch_job;
@@ -919,7 +978,7 @@ static void *batch_worker(void *arg)
         pthread_mutex_unlock(&j->mu);
         if (c >= j->n_cand) break;
         or_result r = {0, 0, 0};
-        int rc = simulate_one(j->pf, j->nt[c], j->dmax[c], j->depth + j->mask_off[c], j->tree, &r, NULL);
+        int rc = simulate_one(j->pf, j->nt[c], j->dmax[c], j->depth + j->mask_off[c], j->tree, j->grain, &r, NULL);
         j->makespan[c] = rc ? -1 : r.makespan;
         if (j->n_tasks) j->n_tasks[c] = rc ? 0 : r.n_tasks;
         if (j->status) j->status[c] = rc;
@@ -946,7 +1005,7 @@ int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
                       latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus, link, capacity};
     or_batch_job j;
     j.pf = &pf; j.n_cand = n_cand; j.nt = nt; j.dmax = dmax; j.mask_off = mask_off; j.depth = depth;
-    j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.tree = tree; j.next = 0;
+    j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.tree = tree; j.grain = NULL; j.next = 0;
     pthread_mutex_init(&j.mu, NULL);
     pthread_t *th = (pthread_t *)malloc((size_t)n_threads * sizeof(pthread_t));
     if (!th) return OR_ENOMEM;
@@ -957,6 +1016,98 @@ int oracle_simulate_batch(int n_cand, const int32_t *nt, const int32_t *dmax,
     if (started == 0) batch_worker(&j);
     for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
     free(th);
+    pthread_mutex_destroy(&j.mu);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* grain batches (partition parameter p = 1/f for any integer f, section 2.1;
+ * partially overlapping blocks, Fig. 4)                                     */
+
+static int64_t gcd64(int64_t a, int64_t b) { while (b) { int64_t t = a % b; a = b; b = t; } return a; }
+
+/* the atom grid of a factor list: L = lcm(fac), at most 64 atoms per tile side */
+static int grain_grid(int n_fac, const int32_t *fac, or_grid *gr)
+{
+    if (n_fac < 1 || n_fac > 8 || !fac) return OR_EINVAL;
+    int64_t L = 1;
+    for (int g = 0; g < n_fac; g++) {
+        if (fac[g] < 1 || fac[g] > 64) return OR_EINVAL;
+        L = L / gcd64(L, fac[g]) * fac[g];
+        if (L > 64) return OR_EINVAL;
+        gr->fac[g] = fac[g];
+    }
+    gr->L = (int)L; gr->n = n_fac; gr->pow2 = 0;
+    return OR_OK;
+}
+
+int oracle_simulate_grain(int nt, int n_fac, const int32_t *fac, const uint8_t *grain,
+                          int n_procs, const int32_t *proc_type, const int32_t *proc_mem, int n_mem,
+                          int n_ptypes, const int64_t *rmax, const int64_t *h, int64_t b,
+                          int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
+                          int64_t *makespan, int32_t *n_tasks, int64_t *n_edges,
+                          int32_t max_tasks, int32_t *task_info, int32_t *proc_out,
+                          int64_t *start_out, int64_t *finish_out, int64_t *rank_out,
+                          int64_t max_edges, int32_t *edges_out, int order, int select, uint64_t seed,
+                          int cache, int bus, const int32_t *link)
+{
+    or_grid gr;
+    if (!grain || n_procs < 1 || !proc_type || !proc_mem || n_mem < 1 || !rmax || !h) return OR_EINVAL;
+    if (grain_grid(n_fac, fac, &gr)) return OR_EINVAL;
+    if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2 || bus < 0 || bus > 1)
+        return OR_EINVAL;
+    for (int p = 0; p < n_procs; p++)
+        if (proc_type[p] < 0 || proc_type[p] >= n_ptypes || proc_mem[p] < 0 || proc_mem[p] >= n_mem)
+            return OR_EINVAL;
+    for (int m = 0; link && m < n_mem; m++)
+        if (link[m] < 0 || link[m] >= n_mem) return OR_EINVAL;
+    or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
+                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus, link, NULL};
+    or_outputs o = {max_tasks, task_info, proc_out, start_out, finish_out, rank_out, max_edges, edges_out};
+    or_result r;
+    int rc = simulate_one(&pf, nt, 0, grain, 0, &gr, &r, &o);
+    if (rc) return rc;
+    if (makespan) *makespan = r.makespan;
+    if (n_tasks) *n_tasks = r.n_tasks;
+    if (n_edges) *n_edges = r.n_edges;
+    return OR_OK;
+}
+
+/* n_cand candidates of nt tiles, grain[c * tet(nt) + t]; one candidate per job */
+int oracle_simulate_grain_batch(int n_cand, int nt, int n_fac, const int32_t *fac, const uint8_t *grain,
+                                int n_procs, const int32_t *proc_type, const int32_t *proc_mem, int n_mem,
+                                int n_ptypes, const int64_t *rmax, const int64_t *h, int64_t b,
+                                int64_t latency_ns, int64_t bw, int64_t elem_bytes, int shared,
+                                int n_threads, int64_t *makespan, int32_t *n_tasks, int32_t *status,
+                                int order, int select, uint64_t seed, int cache, int bus, const int32_t *link)
+{
+    or_grid gr;
+    if (n_cand < 0 || nt < 1 || !grain || !makespan || n_threads < 1) return OR_EINVAL;
+    if (grain_grid(n_fac, fac, &gr)) return OR_EINVAL;
+    if (order < 0 || order > 1 || select < 0 || select > 3 || cache < 0 || cache > 2 || bus < 0 || bus > 1)
+        return OR_EINVAL;
+    for (int m = 0; link && m < n_mem; m++)
+        if (link[m] < 0 || link[m] >= n_mem) return OR_EINVAL;
+    int32_t *nts = (int32_t *)malloc((size_t)(n_cand ? n_cand : 1) * sizeof(int32_t));
+    int32_t *zeros = (int32_t *)calloc((size_t)(n_cand ? n_cand : 1), sizeof(int32_t));
+    int64_t *off = (int64_t *)malloc((size_t)(n_cand ? n_cand : 1) * sizeof(int64_t));
+    if (!nts || !zeros || !off) { free(nts); free(zeros); free(off); return OR_ENOMEM; }
+    int64_t n_top = (int64_t)nt * (nt + 1) * (nt + 2) / 6;
+    for (int c = 0; c < n_cand; c++) { nts[c] = nt; off[c] = c * n_top; }
+    or_platform pf = {n_procs, n_mem, n_ptypes, proc_type, proc_mem, rmax, h, b,
+                      latency_ns, bw, elem_bytes, shared, order, select, seed, cache, bus, link, NULL};
+    or_batch_job j;
+    j.pf = &pf; j.n_cand = n_cand; j.nt = nts; j.dmax = zeros; j.mask_off = off; j.depth = grain;
+    j.makespan = makespan; j.n_tasks = n_tasks; j.status = status; j.tree = 0; j.grain = &gr; j.next = 0;
+    pthread_mutex_init(&j.mu, NULL);
+    pthread_t *th = (pthread_t *)malloc((size_t)n_threads * sizeof(pthread_t));
+    int started = 0;
+    for (int i = 0; th && i < n_threads; i++)
+        if (pthread_create(&th[i], NULL, batch_worker, &j) == 0) started++;
+        else break;
+    if (started == 0) batch_worker(&j);
+    for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
+    free(th); free(nts); free(zeros); free(off);
     pthread_mutex_destroy(&j.mu);
     return OR_OK;
 }

@@ -63,6 +63,14 @@ def lib(native: bool = False):
         L.oracle_simulate_batch.argtypes = [i32, P, P, P, P, i32, P, P, i32, i32, P, P, i64, i64, i64,
                                             i64, i32, i32, P, P, P, i32, i32, ctypes.c_uint64, i32, i32, i32, P, P]
         L.oracle_simulate_batch.restype = i32
+        L.oracle_simulate_grain.argtypes = [i32, i32, P, P, i32, P, P, i32, i32, P, P, i64, i64, i64, i64, i32,
+                                            P, P, P, i32, P, P, P, P, P, i64, P, i32, i32, ctypes.c_uint64, i32,
+                                            i32, P]
+        L.oracle_simulate_grain.restype = i32
+        L.oracle_simulate_grain_batch.argtypes = [i32, i32, i32, P, P, i32, P, P, i32, i32, P, P, i64, i64,
+                                                  i64, i64, i32, i32, P, P, P, i32, i32, ctypes.c_uint64, i32,
+                                                  i32, P]
+        L.oracle_simulate_grain_batch.restype = i32
         L.oracle_task_time.argtypes = [i32, i64, i64, i64, P]
         L.oracle_task_time.restype = i32
         L.oracle_transfer_time.argtypes = [i64, i64, i64, i64, i64, i32, P]
@@ -201,4 +209,70 @@ def simulate_batch(pf, batch, n_threads: int = 1, policy=(0, 0), tree: bool = Fa
     if np.any(st != 0):
         bad = int(np.nonzero(st)[0][0])
         raise ValueError(f"oracle failed on candidate {bad} rc={int(st[bad])}")
+    return ms, ntk
+
+
+def _pf_args(pf, b):
+    ptype = np.ascontiguousarray(pf.proc_type, dtype=np.int32)
+    pmem = np.ascontiguousarray(pf.proc_mem, dtype=np.int32)
+    rmax = np.ascontiguousarray(pf.rmax, dtype=np.int64)
+    h = np.ascontiguousarray(pf.h, dtype=np.int64)
+    keep = (ptype, pmem, rmax, h)
+    return keep, (pf.n_procs, _p(ptype), _p(pmem), pf.n_mem, pf.n_ptypes, _p(rmax), _p(h), b,
+                  pf.latency_ns, pf.bw_bytes_per_ns, pf.elem_bytes, int(pf.shared_memory))
+
+
+def simulate_grain(pf, nt: int, fac, b: int, grain: np.ndarray, detail: bool = True, policy=(0, 0), link=None):
+    """One candidate of a grain batch (section 2.1: partition parameter
+    p = 1/fac[g]; Fig. 4: partially overlapping blocks): top-level task t is
+    split on the fac[grain[t]] x fac[grain[t]] sub-tiling of its cell.  The task
+    info's level column holds the grain index.  policy and link as in simulate;
+    finite capacities are not defined for grain batches."""
+    order, select, seed, cache, bus = (tuple(policy) + (0, 0, 0))[:5]
+    L = lib()
+    fa = np.ascontiguousarray(fac, dtype=np.int32)
+    gr = np.ascontiguousarray(grain, dtype=np.uint8)
+    lk = None if link is None else np.ascontiguousarray(link, dtype=np.int32)
+    keep, args_pf = _pf_args(pf, b)
+    ms = np.zeros(1, np.int64)
+    nt_out = np.zeros(1, np.int32)
+    ne_out = np.zeros(1, np.int64)
+    rc = L.oracle_simulate_grain(nt, len(fa), _p(fa), _p(gr), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
+                                 0, None, None, None, None, None, 0, None, order, select, seed, cache, bus, _p(lk))
+    if rc:
+        raise ValueError(f"oracle_simulate_grain rc={rc}")
+    if not detail:
+        return int(ms[0])
+    n, m = int(nt_out[0]), int(ne_out[0])
+    tasks = np.zeros((n, 5), np.int32)
+    proc = np.zeros(n, np.int32)
+    start = np.zeros(n, np.int64)
+    finish = np.zeros(n, np.int64)
+    rank = np.zeros(n, np.int64)
+    edges = np.zeros((max(m, 1), 2), np.int32)
+    rc = L.oracle_simulate_grain(nt, len(fa), _p(fa), _p(gr), *args_pf, _p(ms), _p(nt_out), _p(ne_out),
+                                 n, _p(tasks), _p(proc), _p(start), _p(finish), _p(rank), m, _p(edges),
+                                 order, select, seed, cache, bus, _p(lk))
+    if rc:
+        raise ValueError(f"oracle_simulate_grain rc={rc}")
+    return Schedule(int(ms[0]), tasks, proc, start, finish, rank, edges[:m])
+
+
+def simulate_grain_batch(pf, nt: int, fac, b: int, grain: np.ndarray, n_threads: int = 1, policy=(0, 0),
+                         link=None, native: bool = False):
+    """Makespans and expanded task counts of n candidates, grain [n][tet(nt)]."""
+    order, select, seed, cache, bus = (tuple(policy) + (0, 0, 0))[:5]
+    L = lib(native)
+    fa = np.ascontiguousarray(fac, dtype=np.int32)
+    gr = np.ascontiguousarray(grain, dtype=np.uint8)
+    n = int(gr.shape[0])
+    lk = None if link is None else np.ascontiguousarray(link, dtype=np.int32)
+    keep, args_pf = _pf_args(pf, b)
+    ms = np.zeros(n, np.int64)
+    ntk = np.zeros(n, np.int32)
+    st = np.zeros(n, np.int32)
+    rc = L.oracle_simulate_grain_batch(n, nt, len(fa), _p(fa), _p(gr), *args_pf, n_threads, _p(ms), _p(ntk),
+                                       _p(st), order, select, seed, cache, bus, _p(lk))
+    if rc or np.any(st != 0):
+        raise ValueError(f"oracle_simulate_grain_batch rc={rc} status={st[st != 0][:4]}")
     return ms, ntk

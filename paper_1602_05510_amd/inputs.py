@@ -47,6 +47,7 @@ P_SHAPE = 3
 P_PLATFORM = 4
 P_TREE = 5
 P_DEPTH2 = 6      # chunks 3..5 of a depth draw (depths 4 and 5)
+P_GRAIN = 7       # grain index per top-level task of a grain batch
 
 CHUNK_BITS = 21  # one split draw uses 21 random bits; depth <= 3 uses 63 bits
 
@@ -257,6 +258,16 @@ def uniform_batch(seed: int, n_cand: int, nt: int, b: int, dmax: int, p_num: int
     depth = depth_from_draw(u, thr, dmax, u2).reshape(-1)
     off = np.arange(n_cand + 1, dtype=np.int64) * n_top
     return Batch(b, np.full(n_cand, nt, np.int32), np.full(n_cand, dmax, np.int32), off, depth)
+
+
+def grain_batch(seed: int, n_cand: int, nt: int, n_fac: int, first: int = 0) -> np.ndarray:
+    """Grain indices (uint8 [n_cand][tet(nt)]) drawn uniformly from 0..n_fac-1,
+    one counter-based draw per (candidate, top-level task)."""
+    n_top = tet(nt)
+    idx = (np.arange(n_cand, dtype=np.uint64)[:, None] + np.uint64(first)) * np.uint64(n_top) \
+        + np.arange(n_top, dtype=np.uint64)[None, :]
+    u = draw_np(seed, P_GRAIN, idx.reshape(-1))
+    return (u % np.uint64(n_fac)).astype(np.uint8).reshape(n_cand, n_top)
 
 
 def tree_flag_count(nt: int, dmax: int) -> int:

@@ -84,8 +84,8 @@ MUTANTS = {
                                  "if (va < 0 || u < vu || (u == vu && num > vn))"),
     "evict_without_copy_back": ("if (vf[va * M + 0] == OR_INF) vf[va * M + 0] = T + tb.xfer[1];",
                                 "if (0) vf[va * M + 0] = T + tb.xfer[1];"),
-    "capacity_ignores_pins": ("if (pin[a * M + m] > 0 || task_has_atom(&tl.v[t], dmax, r, c)) places++;",
-                              "if (task_has_atom(&tl.v[t], dmax, r, c)) places++;"),
+    "capacity_ignores_pins": ("if (pin[a * M + m] > 0 || task_has_atom(&tl.v[t], w, r, c)) places++;",
+                              "if (task_has_atom(&tl.v[t], w, r, c)) places++;"),
     "use_not_refreshed": ("                    use[a * M + m] = T;\n", "                    use[a * M + m] += 0;\n"),
 }
 # Not listed: ordering FCFS releases latest first is an equivalent mutant -- the
