@@ -546,6 +546,62 @@ int hesp_solve_tree(hesp_plan *plan, const hesp_platform *pf, hesp_policy policy
                     uint8_t *d_flags, uint8_t *d_best_flags, int64_t *d_best_makespan, int64_t *d_trace,
                     int64_t *d_steps, void *stream);
 
+/* ---- grain batches ----------------------------------------------------------
+ * Section 2.1 ("Iterative solver"): a partitioned task's new tasks work on
+ * blocks of size p times the original one, p in (0,1].  Here p = 1/f for any
+ * integer f: top-level task t of candidate c is replaced by the blocked algorithm
+ * of its kind on the f x f sub-tiling of its cell, f = fac[grain[c * tet(nt) + t]]
+ * (right-looking order, fine tasks numbered top-level task by top-level task).
+ * Factors that do not divide each other give blocks that overlap partially
+ * (section 2.1 data DAG, Fig. 4: such an overlap gets an intersection descriptor,
+ * a common child of both blocks).  Reading: every tile is cut into L x L atoms,
+ * L = lcm(fac); a block of factor f is the union of its (L/f)^2 atoms, an
+ * intersection is the set of atoms two blocks share, and validity, dependences
+ * (the last writer of every atom a task touches) and transfers (the atoms
+ * missing in the target space, one transfer per block) are kept per atom.  The
+ * heuristics are those of hesp_policy, keyed by the task's first atom (K', I',
+ * J') = (K, I, J) * L / f.  Power-of-two factors 1, 2, .., 2^d give exactly the
+ * depth batch of dmax = d.
+ * Limits: 1..HESP_GRAIN_MAX_FAC factors, each 1..HESP_GRAIN_MAX_ATOMS with
+ * L <= HESP_GRAIN_MAX_ATOMS and nt * L <= HESP_MAX_FINE; n_mem <= HESP_GRAIN_MAX_MEM;
+ * Priority-List or FCFS, EFT-P or EIT-P, any caching, bus = 0 and unbounded
+ * spaces (else HESP_EUNSUPPORTED). */
+#define HESP_GRAIN_MAX_FAC 8
+#define HESP_GRAIN_MAX_ATOMS 64
+#define HESP_GRAIN_MAX_MEM 8
+typedef struct {
+  int32_t n_cand, nt;
+  int32_t n_fac;
+  const int32_t *fac;          /* host [n_fac]: blocks per tile side of each grain */
+  const uint8_t *grain;        /* device [n_cand][tet(nt)]: grain index (< n_fac) per top-level task */
+} hesp_grain_batch;
+
+/* Tables of the cost model of hesp_cost_tables for a grain batch: cost_ns (host
+ * [n_ptypes][4][n_fac]) for tasks of side b / fac[g], and xfer_ns (host
+ * [L*L + 1]) for k atoms of side b / L, both from the exact rational values
+ * rounded up once (sides need not be integers; cm->max_level is ignored). */
+int hesp_grain_cost_tables(const hesp_cost_model *cm, int32_t n_fac, const int32_t *fac, int64_t *cost_ns,
+                           int64_t *xfer_ns);
+
+/* Device workspace, in bytes, of hesp_simulate_grain_batch for this batch shape
+ * (gb->grain and gb->n_cand are not read), n_mem memory spaces and `slots`
+ * candidates in flight (one wavefront each). */
+int hesp_grain_workspace(const hesp_grain_batch *gb, int32_t n_mem, int32_t slots, int64_t *bytes);
+
+/* Simulates every candidate of a grain batch on `stream`: d_makespan [n_cand]
+ * (device, -1 for a failed candidate; may be NULL with d_ws when n_cand = 0),
+ * optional d_n_tasks [n_cand], d_n_edges
+ * [n_cand] (expanded tasks and dependence edges) and d_status [n_cand]
+ * (HESP_OK, or HESP_EINVAL for a grain index >= n_fac).  pf->cost_ns and
+ * pf->xfer_ns as filled by hesp_grain_cost_tables (pf->max_level = n_fac - 1;
+ * pf->capacity and pf->link unused), all task times >= 1.  d_ws holds at least
+ * hesp_grain_workspace(gb, pf->n_mem, slots) bytes owned by the caller; the call
+ * is asynchronous and the workspace must stay allocated until the stream has
+ * run it; calls sharing a workspace must not overlap. */
+int hesp_simulate_grain_batch(const hesp_platform *pf, hesp_policy policy, const hesp_grain_batch *gb,
+                              int64_t *d_makespan, int32_t *d_n_tasks, int64_t *d_n_edges, int32_t *d_status,
+                              void *d_ws, int64_t ws_bytes, int32_t slots, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

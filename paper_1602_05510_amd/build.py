@@ -17,7 +17,7 @@ SAN_HOST_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitiz
                   "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
                   "-Xarch_host", "-g"]
 
-SOURCES = ["hesp_kernels.hip", "hesp_sim.hip", "hesp_mlp.hip", "hesp_search.hip", "hesp_solve.hip", "hesp_noalloc.hip", "hesp_api.cpp",
+SOURCES = ["hesp_kernels.hip", "hesp_sim.hip", "hesp_mlp.hip", "hesp_search.hip", "hesp_solve.hip", "hesp_noalloc.hip", "hesp_grain.hip", "hesp_api.cpp",
            "hesp_mlp_api.cpp", "hesp_search_api.cpp", "hesp_solve_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

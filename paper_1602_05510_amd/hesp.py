@@ -51,6 +51,10 @@ class TreeBatchC(ctypes.Structure):
     _fields_ = [("n_cand", i32), ("nt", i32), ("dmax", i32), ("d_flags", P)]
 
 
+class GrainBatchC(ctypes.Structure):
+    _fields_ = [("n_cand", i32), ("nt", i32), ("n_fac", i32), ("fac", P), ("grain", P)]
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("slots", i32), ("max_tasks", i64), ("max_edges", i64), ("chunks", i32), ("group", i32),
                 ("prep_edges", i32), ("fuse", i32)]
@@ -148,6 +152,10 @@ def lib():
                                          ctypes.POINTER(OutputsC), P],
             "hesp_solve": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(SolveParams), P, P, P, P, P, P],
             "hesp_solve_tree": [P, ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(SolveParams), P, P, P, P, P, P],
+            "hesp_grain_cost_tables": [ctypes.POINTER(CostModel), i32, P, P, P],
+            "hesp_grain_workspace": [ctypes.POINTER(GrainBatchC), i32, i32, ctypes.POINTER(i64)],
+            "hesp_simulate_grain_batch": [ctypes.POINTER(PlatformC), Policy, ctypes.POINTER(GrainBatchC), P, P, P, P,
+                                          P, i64, i32, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -376,6 +384,66 @@ def simulate_batch_noalloc(pf: Platform, batch: DeviceBatch, makespan, status, g
                                                                             ctypes.byref(batch.c),
                                                                             ctypes.byref(out), int(group),
                                                                             _stream(stream)))
+
+
+# ----------------------------------------------------------------- grain batches
+
+def grain_cost_tables(rmax_mflops: np.ndarray, h: np.ndarray, b: int, fac, latency_ns: int = 10_000,
+                      bw_bytes_per_ns: int = 12, elem_bytes: int = 8, shared_memory: bool = False):
+    """int64 cost_ns[n_ptypes][4][n_fac] (sides b / fac[g]) and xfer_ns[L*L + 1]
+    (atoms of side b / L, L = lcm(fac))."""
+    rmax = np.ascontiguousarray(rmax_mflops, dtype=np.int64).reshape(-1, 4)
+    hh = np.ascontiguousarray(h, dtype=np.int64).reshape(-1)
+    fa = np.ascontiguousarray(fac, dtype=np.int32)
+    L = int(np.lcm.reduce(fa.astype(np.int64))) if len(fa) else 0
+    cost = np.zeros((rmax.shape[0], 4, max(len(fa), 1)), np.int64)
+    xfer = np.zeros(L * L + 1 if 0 < L <= 64 else 1, np.int64)
+    cm = CostModel(rmax.shape[0], _np(rmax), _np(hh), b, 0, latency_ns, bw_bytes_per_ns, elem_bytes,
+                   int(bool(shared_memory)))
+    _check("hesp_grain_cost_tables", lib().hesp_grain_cost_tables(ctypes.byref(cm), len(fa), _np(fa), _np(cost),
+                                                                  _np(xfer)))
+    return cost, xfer
+
+
+def grain_platform(pf, b: int, fac) -> Platform:
+    """A Platform whose tables describe the grains of ``fac`` (from a drawn
+    platform of ``inputs.make_platform``)."""
+    cost, xfer = grain_cost_tables(pf.rmax, pf.h, b, fac, pf.latency_ns, pf.bw_bytes_per_ns, pf.elem_bytes,
+                                   pf.shared_memory)
+    return Platform(pf.proc_type, pf.proc_mem, pf.n_mem, cost, xfer)
+
+
+def _grain_c(nt: int, fac: np.ndarray, grain, n_cand: int):
+    return GrainBatchC(int(n_cand), int(nt), len(fac), _np(fac), _dev(grain))
+
+
+def grain_workspace_bytes(nt: int, fac, n_mem: int, slots: int) -> int:
+    fa = np.ascontiguousarray(fac, dtype=np.int32)
+    out = i64(0)
+    c = _grain_c(nt, fa, None, 0)
+    _check("hesp_grain_workspace", lib().hesp_grain_workspace(ctypes.byref(c), int(n_mem), int(slots),
+                                                              ctypes.byref(out)))
+    return int(out.value)
+
+
+def simulate_grain_batch(pf: Platform, nt: int, fac, grain, makespan, n_tasks=None, n_edges=None, status=None,
+                         ws=None, slots: int = 2048, policy=(0, 0, 0), stream=None):
+    """Simulate a grain batch: grain is a device uint8 tensor [n_cand][tet(nt)]
+    of indices into fac; ws a device uint8 tensor of at least
+    grain_workspace_bytes(nt, fac, pf.n_mem, slots) bytes (allocated here when
+    None).  Returns the workspace."""
+    import torch
+    fa = np.ascontiguousarray(fac, dtype=np.int32)
+    n_cand = int(grain.shape[0]) if grain.dim() == 2 else 0
+    need = grain_workspace_bytes(nt, fa, pf.n_mem, slots)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=grain.device)
+    c = _grain_c(nt, fa, grain, n_cand)
+    _check("hesp_simulate_grain_batch",
+           lib().hesp_simulate_grain_batch(ctypes.byref(pf.c), Policy(*policy), ctypes.byref(c), _dev(makespan),
+                                           _dev(n_tasks), _dev(n_edges), _dev(status), _dev(ws),
+                                           int(ws.numel()), int(slots), _stream(stream)))
+    return ws
 
 
 class TreeBatch:
