@@ -502,6 +502,145 @@ def run_solver_tree(args, torch, H):
     print(json.dumps(rec), flush=True)
 
 
+GRAIN_SRC = os.path.join(ROOT, "paper_1602_05510_amd", "csrc", "hesp_grain.hip")
+
+
+def grain_kernel_hash() -> str:
+    with open(GRAIN_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+# fine tasks of each kind inside a top-level cell of kind `kind` split f x f
+def _grain_mix(kind: int, f: int):
+    if kind == 0:
+        return {0: f, 1: f * (f - 1) // 2, 2: f * (f - 1) // 2, 3: f * (f - 1) * (f - 2) // 6}
+    if kind in (1, 2):
+        return {kind: f * f, 3: f * f * (f - 1) // 2}
+    return {3: f ** 3}
+
+
+def grain_algorithmic_bytes(grain, nt: int, fac, n_mem: int, n_edges: int) -> tuple:
+    """Bytes of state the grain simulation must touch, by the accounting of the
+    depth batches (per task 4 + 8 + 16, per edge 12, per atom of every block the
+    validity in every space, the written block's twice) plus, per atom touched,
+    its 4-byte last-writer entry read (and written for the written block)."""
+    L = int(np.lcm.reduce(np.asarray(fac, np.int64)))
+    tops = [0 if (k == i == j) else (1 if k == i else (2 if i == j else 3)) for (k, i, j) in _fig1_kij(nt)]
+    per_g = {}
+    for g, f in enumerate(fac):
+        w2 = (L // f) ** 2
+        for kind in range(4):
+            t = a = aw = 0
+            for fk, cnt in _grain_mix(kind, f).items():
+                t += cnt
+                a += cnt * _NB[fk] * w2
+                aw += cnt * w2
+            per_g[(kind, g)] = (t, a, aw)
+    tasks = atoms = written = 0
+    cnt = np.zeros((4, len(fac)), np.int64)
+    for t_idx, kind in enumerate(tops):
+        np.add.at(cnt[kind], grain[:, t_idx].astype(np.int64), 1)
+    for (kind, g), (t, a, aw) in per_g.items():
+        tasks += int(cnt[kind, g]) * t
+        atoms += int(cnt[kind, g]) * a
+        written += int(cnt[kind, g]) * aw
+    b = tasks * 28 + n_edges * 12 + 8 * n_mem * (atoms + written) + 4 * (atoms + written)
+    return b, tasks
+
+
+def _fig1_kij(nt: int):
+    out = []
+    for k in range(nt):
+        out.append((k, k, k))
+        out += [(k, k, j) for j in range(k + 1, nt)]
+        for i in range(k + 1, nt):
+            out += [(k, i, j) for j in range(i + 1, nt)]
+            out.append((k, i, i))
+    return out
+
+
+def run_grain(args, torch, H):
+    """Grain batch (partition parameter p = 1/f per top-level task, partially
+    overlapping blocks): simulated tasks per second of k_grain on the 16x16-tile
+    workload, with its roofline and the oracle timed beside it."""
+    w = I.GRAIN_WORKLOAD
+    nt, b, fac = w["nt"], w["b"], list(w["fac"])
+    n = args.n_cand or w["n_cand"]
+    slots = args.slots
+    pf_in = I.make_platform(w["ptypes"], w["seed"])
+    pf = H.grain_platform(pf_in, b, fac)
+    grains = [I.grain_batch(w["seed"], n, nt, len(fac), first=s * n) for s in range(args.warmup + args.steps)]
+    dev = [torch.from_numpy(g).cuda() for g in grains]
+    ms = torch.zeros(n, dtype=torch.int64, device="cuda")
+    ntk = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ne = torch.zeros(n, dtype=torch.int64, device="cuda")
+    st = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(H.grain_workspace_bytes(nt, fac, pf_in.n_mem, slots), dtype=torch.uint8, device="cuda")
+    for s in range(args.warmup):
+        H.simulate_grain_batch(pf, nt, fac, dev[s], ms, ntk, ne, st, ws=ws, slots=slots)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tasks = 0
+    t0 = time.perf_counter()
+    ev0.record()
+    for s in range(args.steps):
+        H.simulate_grain_batch(pf, nt, fac, dev[args.warmup + s], ms, ntk, ne, st, ws=ws, slots=slots)
+        if s == args.steps - 1:
+            ev1.record()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / args.steps
+    if int((st != 0).sum().item()):
+        raise SystemExit("grain simulation reported a non-OK status; the measurement is invalid")
+    # every step's batch has the same shape; task counts of the last one times steps
+    last_tasks = int(ntk.sum().item())
+    for s in range(args.steps):
+        g = grains[args.warmup + s]
+        tasks += grain_algorithmic_bytes(g, nt, fac, pf_in.n_mem, 0)[1]
+    alg_bytes, alg_tasks = grain_algorithmic_bytes(grains[-1], nt, fac, pf_in.n_mem, int(ne.sum().item()))
+    assert alg_tasks == last_tasks, (alg_tasks, last_tasks)
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = None
+    pmc_path = os.path.join(PROFILES, f"k_grain_{w['name']}_pmc.json")
+    if os.path.exists(pmc_path):
+        with open(pmc_path) as f:
+            pmc = json.load(f)
+        if pmc.get("kernel_sha") == grain_kernel_hash() and pmc.get("n_cand") == n and pmc.get("slots") == slots:
+            traffic = pmc.get("hbm_bytes_per_launch")
+    cpu = None
+    gpu_ms = ms.cpu().numpy()
+    if not args.no_cpu_baseline:
+        sys.path.insert(0, ROOT)
+        from oracle import oracle as O
+        O.build(force=True, native=True)
+        cores = min(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1), 64)
+        g_last = grains[-1]
+        t1 = time.perf_counter()
+        O.simulate_grain_batch(pf_in, nt, fac, b, g_last[:cores], n_threads=cores, native=True)
+        per = max(time.perf_counter() - t1, 1e-3) / cores
+        k = int(min(n, max(cores, args.cpu_budget / per)))
+        t1 = time.perf_counter()
+        want, wn = O.simulate_grain_batch(pf_in, nt, fac, b, g_last[:k], n_threads=cores, native=True)
+        t_cpu = time.perf_counter() - t1
+        cpu = {"value": float(wn.sum()) / t_cpu, "unit": "tasks/s", "cores": cores, "kind": "oracle",
+               "sample": f"the first {k} candidates of the last timed batch, one candidate per thread; oracle built "
+                         "gcc -O2 -march=native on this host",
+               "cpu_model": host_cpu_model(), "candidates": k, "seconds": t_cpu,
+               "bit_exact_vs_gpu": bool(np.array_equal(want, gpu_ms[:k]))}
+    rec = {"metric": "simulated tasks per second (grain batch)", "value": tasks / dt, "unit": "tasks/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": w["name"], "nt": nt, "b": b, "factors": fac, "candidates": n, "slots": slots,
+                      "tasks_per_candidate": last_tasks / n, "platform": "8 CPU cores + 2 accelerators",
+                      "parallelism": "none (1 GPU)"},
+           "roofline": {"bound": "hbm", "kernel": "k_grain", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                        "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": kernel_ms,
+                        "kernel_sha": grain_kernel_hash()},
+           "cpu_baseline": cpu}
+    print(json.dumps(rec), flush=True)
+
+
 def run_solver(args, torch, H):
     """The iterative scheduler-partitioner (section 2.1) on the 16x16 instance:
     many independent chains (one unsplit, the others from random initial
@@ -633,6 +772,7 @@ def main():
                     help="maximum split depth of a uniform workload (0..5; above 3: 16 or 32 lanes per candidate)")
     ap.add_argument("--tree", action="store_true",
                     help="split-tree candidates (every task split on its own) of the same shape")
+    ap.add_argument("--slots", type=int, default=4096, help="grain batch: candidates in flight")
     ap.add_argument("--solve-chains", type=int, default=16384)
     ap.add_argument("--solve-iters", type=int, default=16)
     ap.add_argument("--solve-seed", type=int, default=7)
@@ -660,6 +800,8 @@ def main():
         return run_solver(args, torch, H)
     if args.workload == "iterative_solver_tree":
         return run_solver_tree(args, torch, H)
+    if args.workload == I.GRAIN_WORKLOAD["name"]:
+        return run_grain(args, torch, H)
     w = I.WORKLOADS[args.workload]
     if args.dmax is not None and args.dmax != w.dmax:
         if w.ragged:

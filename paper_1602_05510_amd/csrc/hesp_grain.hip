@@ -113,7 +113,7 @@ SlotLayout layout(int nt, int n_fac, const int32_t* fac, int L, int n_mem) {
   s.cur = take(4 * n);
   s.mark = take(4 * n);
   s.next = take(4 * n);
-  s.ready = take(4 * n);
+  s.ready = take(32 * n);
   s.pred_ptr = take(4 * (n + 1));
   s.pred = take(4 * e);
   s.pred_v = take(4 * e);
@@ -218,11 +218,17 @@ __device__ void visit(const GrainTables& tb, const SlotLayout& lay, const Slot& 
     __hip_atomic_store(&s.mark[t], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
-  // reads of every block: the last writer of each atom is a predecessor (once)
+  // one pass over the atoms of every block (blocks of one task are disjoint):
+  // the last writer of each atom is a predecessor (once); a read marks the atom,
+  // the written block takes the task as last writer, and a read of it since its
+  // last write would be a WaR hazard
+  int war = 0;
   for (int x = lane(); x < nb * per; x += 64) {
     const int bi = x / per;
     const int64_t a = block_atom(br, bc, bi, x - bi * per, w, tb.L, tb.nt);
     const int32_t lw = ld(&s.last_w[a]);
+    const bool wr = bi == nb - 1;
+    const int32_t lr = wr ? ld(&s.last_r[a]) : -1;
     if (lw >= 0 && (uint32_t)lw != t) {
       if (atomicExch(&s.mark[lw], (int32_t)t) != (int32_t)t) {
         const uint32_t pos = atomicAdd(lds_cnt, 1u);
@@ -230,25 +236,21 @@ __device__ void visit(const GrainTables& tb, const SlotLayout& lay, const Slot& 
         s.pred_v[st.ne + pos] = t;
       }
     }
-    if (bi != nb - 1) s.last_r[a] = (int32_t)t;
+    if (wr) {
+      war |= lr >= 0 && (uint32_t)lr != t;
+      s.last_r[a] = -1;
+      s.last_w[a] = (int32_t)t;
+    } else {
+      s.last_r[a] = (int32_t)t;
+    }
   }
   __syncthreads();
-  // the written block: a read since its last write would be a WaR hazard
-  int war = 0;
-  for (int x = lane(); x < per; x += 64) {
-    const int64_t a = block_atom(br, bc, nb - 1, x, w, tb.L, tb.nt);
-    const int32_t lr = ld(&s.last_r[a]);
-    war |= lr >= 0 && (uint32_t)lr != t;
-    s.last_r[a] = -1;
-    s.last_w[a] = (int32_t)t;
-  }
   const uint32_t np = *lds_cnt;
   if (wsum(war)) st.err = HESP_EINVAL;
   if (st.ne + np > lay.max_edges) st.err = HESP_ECAPACITY;
   if (lane() == 0) s.left[t] = np;
   st.ne += np;
   st.t = t + 1;
-  __syncthreads();
 }
 
 // the fine tasks of top-level cell (k, i, j) at factor f, in right-looking order
@@ -324,18 +326,38 @@ __device__ void successors(const Slot& s, uint32_t n, uint32_t ne) {
   __syncthreads();
 }
 
-// critical times, reverse program order (every edge points forward)
+// critical times, reverse program order (every edge points forward), 64 tasks
+// at a time: their successor ranges and own times are loaded together, and the
+// ranks computed in the chunk stay in the lanes' registers
 __device__ void ranks(const GrainTables& tb, const Slot& s, uint32_t n) {
-  for (int64_t t = (int64_t)n - 1; t >= 0; t--) {
-    const uint32_t e0 = ld(&s.succ_ptr[t]), e1 = ld(&s.succ_ptr[t + 1]);
-    int64_t best = 0;
-    for (uint32_t e = e0 + lane(); e < e1; e += 64) {
-      const int64_t r = ld(&s.rank[ld(&s.succ[e])]);
-      best = r > best ? r : best;
+  for (int64_t hi = n; hi > 0; hi -= 64) {
+    const int64_t lo = hi > 64 ? hi - 64 : 0;
+    const int64_t tl = lo + lane();
+    uint32_t ep0 = 0, ep1 = 0;
+    int64_t wl = 0, myrank = 0;
+    if (tl < hi) {
+      ep0 = ld(&s.succ_ptr[tl]);
+      ep1 = ld(&s.succ_ptr[tl + 1]);
+      const Task tk = unpack_rec(ld(&s.rec[tl]));
+      wl = tb.W[tk.kind][tk.g];
     }
-    best = wmax64(best);
-    const Task tk = unpack_rec(ld(&s.rec[t]));
-    if (lane() == 0) s.rank[t] = tb.W[tk.kind][tk.g] + best;
+    for (int64_t t = hi - 1; t >= lo; t--) {
+      const int j = (int)(t - lo);
+      const uint32_t e0 = __shfl(ep0, j), e1 = __shfl(ep1, j);
+      int64_t best = 0;
+      for (uint32_t eb = e0; eb < e1; eb += 64) {
+        const uint32_t e = eb + lane();
+        const int64_t sv = e < e1 ? (int64_t)ld(&s.succ[e]) : -1;
+        const int inside = sv >= lo && sv < hi;
+        const int64_t rin = __shfl(myrank, inside ? (int)(sv - lo) : 0);
+        const int64_t r = sv < 0 ? 0 : (inside ? rin : ld(&s.rank[sv]));
+        best = r > best ? r : best;
+      }
+      best = wmax64(best);
+      const int64_t r = __shfl(wl, j) + best;
+      if (lane() == j) myrank = r;
+    }
+    if (tl < hi) s.rank[tl] = myrank;
     __syncthreads();
   }
 }
@@ -346,9 +368,29 @@ __device__ __forceinline__ uint32_t corner(const GrainTables& tb, const Task& tk
   return ((uint32_t)tk.K * w << 18) | ((uint32_t)tk.I * w << 9) | ((uint32_t)tk.J * w);
 }
 
+// a released task: ordering key, (first atom << 32 | task), record
+struct Entry {
+  int64_t key;
+  uint64_t cid, rec, pad;
+};
+__device__ __forceinline__ Entry load_entry(const Entry* p) {
+  const uint64_t* q = (const uint64_t*)p;
+  return Entry{(int64_t)ld(q), ld(q + 1), ld(q + 2), 0};
+}
+__device__ __forceinline__ void store_entry(Entry* p, const Entry& e) {
+  uint64_t* q = (uint64_t*)p;
+  q[0] = (uint64_t)e.key; q[1] = e.cid; q[2] = e.rec;
+}
+__device__ __forceinline__ Entry make_entry(const GrainTables& tb, const Slot& s, uint32_t v) {
+  const uint64_t rec = ld(&s.rec[v]);
+  const int64_t key = tb.fcfs ? 0 : ld(&s.rank[v]);
+  return Entry{key, ((uint64_t)corner(tb, unpack_rec(rec)) << 32) | v, rec, 0};
+}
+
 __device__ int simulate(const GrainTables& tb, const Slot& s, uint32_t n, int64_t& makespan,
                         int* s_miss, int64_t* s_fin, int64_t* s_go) {
   const int P = tb.n_procs, M = tb.n_mem, L = tb.L, nt = tb.nt;
+  Entry* ready = (Entry*)s.ready;
   for (int64_t a = lane(); a < (int64_t)nt * (nt + 1) / 2 * L * L; a += 64)
     for (int m = 0; m < M; m++) s.vf[a * M + m] = m == 0 ? 0 : kInf;   // data starts on the host
   // ready set: the tasks without predecessors
@@ -357,15 +399,16 @@ __device__ int simulate(const GrainTables& tb, const Slot& s, uint32_t n, int64_
     const uint32_t t = t0 + lane();
     const bool r = t < n && ld(&s.left[t]) == 0u;
     const uint64_t m = __ballot(r);
-    if (r) s.ready[nb + __popcll(m & ((1ull << lane()) - 1))] = t;
+    if (r) store_entry(&ready[nb + __popcll(m & ((1ull << lane()) - 1))], make_entry(tb, s, t));
     nb += (uint32_t)__popcll(m);
   }
   __syncthreads();
-  // processor lanes
+  // processor lanes: queue head (task, finish, record) and tail, idle time
   const bool is_p = lane() < P;
   const int my_mem = is_p ? tb.proc_mem[lane()] : 0;
   const int my_type = is_p ? tb.proc_type[lane()] : 0;
   int64_t avail = 0, headfin = kInf;
+  uint64_t headrec = 0;
   int32_t head = -1, tail = -1;
   int64_t T = 0;
   uint32_t done = 0;
@@ -374,57 +417,49 @@ __device__ int simulate(const GrainTables& tb, const Slot& s, uint32_t n, int64_
     // (i) map the released tasks, in order
     while (nb > 0) {
       int64_t bk = kNegInf;
-      uint32_t bc = 0xFFFFFFFFu, bi = 0;
+      int64_t bcid = kInf;
+      uint64_t brec = 0;
+      uint32_t bi = 0;
+      Entry le{0, 0, 0, 0};
       for (uint32_t i = lane(); i < nb; i += 64) {
-        const uint32_t t = ld(&s.ready[i]);
-        const int64_t k = tb.fcfs ? 0 : ld(&s.rank[t]);
-        const uint32_t c = corner(tb, unpack_rec(ld(&s.rec[t])));
-        if (k > bk || (k == bk && c < bc)) { bk = k; bc = c; bi = i; }
+        const Entry e = load_entry(&ready[i]);
+        le = e;
+        if (e.key > bk || (e.key == bk && (int64_t)e.cid < bcid)) { bk = e.key; bcid = (int64_t)e.cid; brec = e.rec; bi = i; }
       }
       const int64_t kmax = wmax64(bk);
-      const uint32_t cmin = (uint32_t)wmin64(bk == kmax ? (int64_t)bc : kInf);
-      const uint64_t who = __ballot(bk == kmax && bc == cmin);
-      const int src = __ffsll((unsigned long long)who) - 1;
+      const int64_t cmin = wmin64(bk == kmax ? bcid : kInf);
+      const int src = __ffsll((unsigned long long)__ballot(bk == kmax && bcid == cmin)) - 1;
       const uint32_t pick = __shfl(bi, src);
-      const uint32_t t = ld(&s.ready[pick]);
-      const uint32_t last = ld(&s.ready[nb - 1]);
-      __syncthreads();
-      if (lane() == 0) s.ready[pick] = last;
+      const uint32_t t = (uint32_t)(uint64_t)cmin;
+      const uint64_t rec = __shfl(brec, src);
+      const int ll = (int)((nb - 1) & 63);
+      const Entry last{__shfl(le.key, ll), __shfl(le.cid, ll), __shfl(le.rec, ll), 0};
+      if (lane() == 0 && pick != nb - 1) store_entry(&ready[pick], last);
       nb--;
-      const Task tk = unpack_rec(ld(&s.rec[t]));
+      const Task tk = unpack_rec(rec);
       int br[3], bc3[3];
       const int nbk = task_blocks(tk, br, bc3);
       const int w = L / tb.fac[tk.g], per = w * w;
       // per block and memory space: atoms missing, latest valid-from of those
       // present, latest time a missing atom has a copy somewhere
-      for (int b = 0; b < nbk; b++) {
-        int miss[kGMaxMem];
-        int64_t fin[kGMaxMem], go[kGMaxMem];
+      if (lane() < 3 * kGMaxMem) { s_miss[lane()] = 0; s_fin[lane()] = kNegInf; s_go[lane()] = kNegInf; }
+      __syncthreads();
+      for (int x = lane(); x < nbk * per; x += 64) {
+        const int b = x / per;
+        const int64_t a = block_atom(br, bc3, b, x - b * per, w, L, nt);
+        int64_t v[kGMaxMem], src_t = kInf;
 #pragma unroll
-        for (int m = 0; m < kGMaxMem; m++) { miss[m] = 0; fin[m] = kNegInf; go[m] = kNegInf; }
-        for (int x = lane(); x < per; x += 64) {
-          const int64_t a = block_atom(br, bc3, b, x, w, L, nt);
-          int64_t v[kGMaxMem], src_t = kInf;
-#pragma unroll
-          for (int m = 0; m < kGMaxMem; m++)
-            if (m < M) { v[m] = ld(&s.vf[a * M + m]); src_t = v[m] < src_t ? v[m] : src_t; }
-#pragma unroll
-          for (int m = 0; m < kGMaxMem; m++)
-            if (m < M) {
-              if (v[m] == kInf) {
-                miss[m]++;
-                if (src_t != kInf && src_t > go[m]) go[m] = src_t;
-              } else if (v[m] > fin[m]) {
-                fin[m] = v[m];
-              }
-            }
-        }
+        for (int m = 0; m < kGMaxMem; m++)
+          if (m < M) { v[m] = ld(&s.vf[a * M + m]); src_t = v[m] < src_t ? v[m] : src_t; }
 #pragma unroll
         for (int m = 0; m < kGMaxMem; m++)
           if (m < M) {
-            const int ms = wsum(miss[m]);
-            const int64_t fm = wmax64(fin[m]), gm = wmax64(go[m]);
-            if (lane() == 0) { s_miss[b * kGMaxMem + m] = ms; s_fin[b * kGMaxMem + m] = fm; s_go[b * kGMaxMem + m] = gm; }
+            if (v[m] == kInf) {
+              atomicAdd(&s_miss[b * kGMaxMem + m], 1);
+              if (src_t != kInf) atomicMax((long long*)&s_go[b * kGMaxMem + m], (long long)src_t);
+            } else {
+              atomicMax((long long*)&s_fin[b * kGMaxMem + m], (long long)v[m]);
+            }
           }
       }
       __syncthreads();
@@ -432,14 +467,14 @@ __device__ int simulate(const GrainTables& tb, const Slot& s, uint32_t n, int64_
       int64_t est = T > avail ? T : avail;
       for (int b = 0; b < nbk; b++) {
         const int ms = s_miss[b * kGMaxMem + my_mem];
-        int64_t ready = s_fin[b * kGMaxMem + my_mem];
+        int64_t rdy = s_fin[b * kGMaxMem + my_mem];
         if (ms > 0) {
           int64_t g0 = s_go[b * kGMaxMem + my_mem];
           g0 = g0 > T ? g0 : T;
           const int64_t arr = g0 + tb.xfer[ms];
-          ready = arr > ready ? arr : ready;
+          rdy = arr > rdy ? arr : rdy;
         }
-        est = ready > est ? ready : est;
+        est = rdy > est ? rdy : est;
       }
       const int64_t eft = est + tb.cost[my_type][tk.kind][tk.g];
       const int64_t sel = is_p ? (tb.sel ? (T > avail ? T : avail) : eft) : kInf;
@@ -448,21 +483,19 @@ __device__ int simulate(const GrainTables& tb, const Slot& s, uint32_t n, int64_
       const int64_t beft = __shfl(eft, bp);
       const int bm = tb.proc_mem[bp];
       // commit: transfers of the missing atoms into the chosen space, issued now
-      for (int b = 0; b < nbk; b++) {
+      for (int x = lane(); x < nbk * per; x += 64) {
+        const int b = x / per;
         const int ms = s_miss[b * kGMaxMem + bm];
         if (ms == 0) continue;
         int64_t g0 = s_go[b * kGMaxMem + bm];
         g0 = g0 > T ? g0 : T;
-        const int64_t arr = g0 + tb.xfer[ms];
-        for (int x = lane(); x < per; x += 64) {
-          const int64_t a = block_atom(br, bc3, b, x, w, L, nt);
-          if (ld(&s.vf[a * M + bm]) == kInf) s.vf[a * M + bm] = arr;
-        }
+        const int64_t a = block_atom(br, bc3, b, x - b * per, w, L, nt);
+        if (ld(&s.vf[a * M + bm]) == kInf) s.vf[a * M + bm] = g0 + tb.xfer[ms];
       }
       if (lane() == 0) { s.finish[t] = beft; s.next[t] = -1; }
       if (lane() == bp) {
         avail = beft;
-        if (head < 0) { head = (int32_t)t; headfin = beft; }
+        if (head < 0) { head = (int32_t)t; headfin = beft; headrec = rec; }
         else s.next[tail] = (int32_t)t;
         tail = (int32_t)t;
       }
@@ -477,13 +510,13 @@ __device__ int simulate(const GrainTables& tb, const Slot& s, uint32_t n, int64_
       const int p = __ffsll((unsigned long long)fin_mask) - 1;
       fin_mask &= fin_mask - 1;
       const uint32_t t = (uint32_t)__shfl(head, p);
+      const Task tk = unpack_rec(__shfl(headrec, p));
       if (lane() == p) {
         head = ld(&s.next[t]);
         if (head < 0) { tail = -1; headfin = kInf; }
-        else headfin = ld(&s.finish[head]);
+        else { headfin = ld(&s.finish[head]); headrec = ld(&s.rec[head]); }
       }
       done++;
-      const Task tk = unpack_rec(ld(&s.rec[t]));
       int br[3], bc3[3];
       const int nbk = task_blocks(tk, br, bc3);
       const int w = L / tb.fac[tk.g], per = w * w, m = tb.proc_mem[p];
@@ -512,7 +545,7 @@ __device__ int simulate(const GrainTables& tb, const Slot& s, uint32_t n, int64_
           rel = atomicSub(&s.left[v], 1u) == 1u;
         }
         const uint64_t mk = __ballot(rel);
-        if (rel) s.ready[nb + __popcll(mk & ((1ull << lane()) - 1))] = v;
+        if (rel) store_entry(&ready[nb + __popcll(mk & ((1ull << lane()) - 1))], make_entry(tb, s, v));
         nb += (uint32_t)__popcll(mk);
       }
       __syncthreads();

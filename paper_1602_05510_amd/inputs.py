@@ -381,4 +381,4 @@ WORKLOADS = {
 # grain batch on the 16x16 shape: every top-level task split with p = 1, 1/2,
 # 1/3 or 1/4, drawn uniformly; platform of chol16x16_b1024_d2
 GRAIN_WORKLOAD = dict(name="grain16x16_b1024_f1234", seed=2, nt=16, b=1024, fac=(1, 2, 3, 4),
-                      ptypes=cpu_accel_types(8, 2), n_cand=8192)
+                      ptypes=cpu_accel_types(8, 2), n_cand=16384)
