@@ -434,10 +434,21 @@ def simulate_grain_batch(pf: Platform, nt: int, fac, grain, makespan, n_tasks=No
     None).  Returns the workspace."""
     import torch
     fa = np.ascontiguousarray(fac, dtype=np.int32)
-    n_cand = int(grain.shape[0]) if grain.dim() == 2 else 0
+    n_top = nt * (nt + 1) * (nt + 2) // 6
+    if grain.dtype != torch.uint8 or grain.dim() != 2 or grain.shape[1] != n_top or not grain.is_contiguous():
+        raise HespError("hesp_simulate_grain_batch", HESP_EINVAL, f"grain must be contiguous uint8 [n][{n_top}]")
+    n_cand = int(grain.shape[0])
+    for name, t, dt in (("makespan", makespan, torch.int64), ("n_tasks", n_tasks, torch.int32),
+                        ("n_edges", n_edges, torch.int64), ("status", status, torch.int32)):
+        if t is not None and (t.dtype != dt or not t.is_contiguous() or t.numel() < n_cand):
+            raise HespError("hesp_simulate_grain_batch", HESP_EINVAL, f"{name} must be contiguous {dt} of >= {n_cand}")
+    if makespan is None and n_cand:
+        raise HespError("hesp_simulate_grain_batch", HESP_EINVAL, "makespan is required")
     need = grain_workspace_bytes(nt, fa, pf.n_mem, slots)
     if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=grain.device)
+    if ws.dtype != torch.uint8 or not ws.is_contiguous() or ws.numel() < need:
+        raise HespError("hesp_simulate_grain_batch", HESP_EINVAL, f"ws must be contiguous uint8 of >= {need} bytes")
     c = _grain_c(nt, fa, grain, n_cand)
     _check("hesp_simulate_grain_batch",
            lib().hesp_simulate_grain_batch(ctypes.byref(pf.c), Policy(*policy), ctypes.byref(c), _dev(makespan),

@@ -63,3 +63,17 @@ def test_workspace_and_refusals():
     rc = L.hesp_simulate_grain_batch(ctypes.byref(pf.c), H.Policy(0, 0, 0), ctypes.byref(gb), fake, None, None,
                                      None, fake, 1024, 16, None)
     assert rc == H.HESP_ECAPACITY                              # workspace too small
+
+
+def test_binding_checks_tensors():
+    torch = pytest.importorskip("torch")
+    pf = H.grain_platform(PF, 1024, [1, 2])
+    g = torch.zeros((4, 10), dtype=torch.uint8)
+    ms = torch.zeros(4, dtype=torch.int64)
+    for bad in (dict(grain=g[:, :9]), dict(grain=g.to(torch.int32)), dict(makespan=ms[:3]),
+                dict(makespan=ms.to(torch.int32)), dict(ws=torch.zeros(16, dtype=torch.uint8))):
+        kw = dict(grain=g, makespan=ms)
+        kw.update(bad)
+        grain, makespan = kw.pop("grain"), kw.pop("makespan")
+        with pytest.raises(H.HespError):
+            H.simulate_grain_batch(pf, 3, [1, 2], grain, makespan, slots=1, **kw)
