@@ -627,6 +627,18 @@ def run_grain(args, torch, H):
                          "gcc -O2 -march=native on this host",
                "cpu_model": host_cpu_model(), "candidates": k, "seconds": t_cpu,
                "bit_exact_vs_gpu": bool(np.array_equal(want, gpu_ms[:k]))}
+    # quality beside the rate: best makespan of the last batch against the same
+    # number of candidates restricted to halvings (p = 1, 1/2, 1/4: the depth batch)
+    best_grain = int(ms[ms >= 0].min().item())
+    pw = [1, 2, 4]
+    pfw = H.grain_platform(pf_in, b, pw)
+    g_pw = torch.from_numpy(I.grain_batch(w["seed"], n, nt, len(pw), first=(args.warmup + args.steps) * n)).cuda()
+    ms_pw = torch.zeros(n, dtype=torch.int64, device="cuda")
+    H.simulate_grain_batch(pfw, nt, pw, g_pw, ms_pw, slots=slots,
+                           ws=ws if ws.numel() >= H.grain_workspace_bytes(nt, pw, pf_in.n_mem, slots) else None)
+    torch.cuda.synchronize()
+    quality = {"best_makespan_ns": best_grain, "best_makespan_halvings_ns": int(ms_pw[ms_pw >= 0].min().item()),
+               "candidates_each": n, "halvings": pw}
     rec = {"metric": "simulated tasks per second (grain batch)", "value": tasks / dt, "unit": "tasks/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
@@ -637,7 +649,7 @@ def run_grain(args, torch, H):
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                         "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": kernel_ms,
                         "kernel_sha": grain_kernel_hash()},
-           "cpu_baseline": cpu}
+           "cpu_baseline": cpu, "quality": quality}
     print(json.dumps(rec), flush=True)
 
 
