@@ -87,6 +87,11 @@ MUTANTS = {
     "capacity_ignores_pins": ("if (pin[a * M + m] > 0 || task_has_atom(&tl.v[t], w, r, c)) places++;",
                               "if (task_has_atom(&tl.v[t], w, r, c)) places++;"),
     "use_not_refreshed": ("                    use[a * M + m] = T;\n", "                    use[a * M + m] += 0;\n"),
+    # grain batches (partition parameter p = 1/f)
+    "grain_grid_max_not_lcm": ("L = L / gcd64(L, fac[g]) * fac[g];", "L = L > fac[g] ? L : fac[g];"),
+    "grain_time_side_squared": ("__int128 den = (__int128)3 * f * f * f * rmax_mflops;",
+                                "__int128 den = (__int128)3 * f * f * rmax_mflops;"),
+    "grain_xfer_atom_side_once": ("(__int128)L * L * bw", "(__int128)L * bw"),
 }
 # Not listed: ordering FCFS releases latest first is an equivalent mutant -- the
 # ready set is emptied at every instant, so it never holds two release times.
@@ -137,6 +142,28 @@ def _pins_pass():
             for (kind, lvl, K, I_, J, p, st, fi) in e["schedule"]:
                 if got.get((KIND[kind], lvl, K, I_, J)) != (p, st, fi):
                     return False
+        # grain batches: hand-derived intersections, the flat tiling, whole tiles
+        # on a fractional atom grid, the one-processor sum
+        with open(os.path.join(GOLD, "grain_examples.json")) as f:
+            for case in json.load(f)["cases"]:
+                pfg = I.make_platform(I.cpu_accel_types(2, 1), seed=7)
+                sg = O.simulate_grain(pfg, case["nt"], case["fac"], 1024, np.array(case["grain"], np.uint8))
+                for v, preds in case["preds"].items():
+                    if sorted(int(u) for u, w in sg.edges.tolist() if w == int(v)) != preds:
+                        return False
+        pfg = I.make_platform(I.cpu_accel_types(3, 2), seed=8)
+        g3 = O.simulate_grain(pfg, 2, [3], 1920, np.zeros(4, np.uint8))
+        fl3 = O.simulate(pfg, 6, 0, 640, np.zeros(I.tet(6), np.uint8))
+        if g3.makespan != fl3.makespan:
+            return False
+        if O.simulate_grain(pfg, 2, [1, 3], 1024, np.zeros(4, np.uint8), detail=False) != \
+                O.simulate(pfg, 2, 0, 1024, np.zeros(4, np.uint8), detail=False):
+            return False
+        pfc = I.make_platform([I.ProcType("cpu", 1, 1000, 2000, 64, False)], seed=3)
+        sgc = O.simulate_grain(pfc, 3, [1, 2, 3, 4, 6], 1536, np.array([4, 2, 1, 3, 0, 2, 1, 4, 3, 2], np.uint8))
+        if sgc.makespan != sum(O.task_time(int(t[0]), 1536 // [1, 2, 3, 4, 6][t[1]], int(pfc.rmax[0, t[0]]),
+                                           int(pfc.h[0])) for t in sgc.tasks):
+            return False
         pf1b = I.make_platform([I.ProcType("cpu", 1, 32000, 32000, 64, False)], seed=0)
         # closed-form counts, single-processor sum, lower bounds on a split case
         pf1 = I.make_platform([I.ProcType("cpu", 1, 27000, 27000, 64, False)], seed=0)
