@@ -203,20 +203,27 @@ struct ScanState {
   int err;           // 0, or a status
 };
 
+constexpr int kSet = 256;   // LDS set of a task's distinct predecessors (when its atoms fit)
+
 __device__ void visit(const GrainTables& tb, const SlotLayout& lay, const Slot& s, ScanState& st, int kind, int g,
-                      int K, int I, int J, uint32_t* lds_cnt) {
+                      int K, int I, int J, uint32_t* lds_cnt, int32_t* set) {
   const uint32_t t = st.t;
   if ((int64_t)t >= lay.max_tasks) { st.err = HESP_ECAPACITY; return; }
   const Task tk{kind, g, K, I, J};
   int br[3], bc[3];
   const int nb = task_blocks(tk, br, bc);
   const int w = tb.L / tb.fac[g], per = w * w;
+  // at most kSet atoms: distinct predecessors found in an LDS hash set, else
+  // through the per-task marks in memory
+  const bool in_lds = nb * per <= kSet;
   if (lane() == 0) {
     *lds_cnt = 0;
     s.rec[t] = pack_rec(kind, g, K, I, J);
     s.pred_ptr[t] = st.ne;
     __hip_atomic_store(&s.mark[t], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  if (in_lds)
+    for (int i = lane(); i < kSet; i += 64) set[i] = -1;
   __syncthreads();
   // one pass over the atoms of every block (blocks of one task are disjoint):
   // the last writer of each atom is a predecessor (once); a read marks the atom,
@@ -230,7 +237,20 @@ __device__ void visit(const GrainTables& tb, const SlotLayout& lay, const Slot& 
     const bool wr = bi == nb - 1;
     const int32_t lr = wr ? ld(&s.last_r[a]) : -1;
     if (lw >= 0 && (uint32_t)lw != t) {
-      if (atomicExch(&s.mark[lw], (int32_t)t) != (int32_t)t) {
+      bool fresh;
+      if (in_lds) {
+        // open addressing; the set holds at most nb * per <= kSet keys
+        uint32_t h = ((uint32_t)lw * 2654435761u) >> 24;
+        for (;;) {
+          const int32_t old = atomicCAS(&set[h], -1, lw);
+          if (old == -1) { fresh = true; break; }
+          if (old == lw) { fresh = false; break; }
+          h = (h + 1) & (kSet - 1);
+        }
+      } else {
+        fresh = atomicExch(&s.mark[lw], (int32_t)t) != (int32_t)t;
+      }
+      if (fresh) {
         const uint32_t pos = atomicAdd(lds_cnt, 1u);
         s.pred[st.ne + pos] = (uint32_t)lw;
         s.pred_v[st.ne + pos] = t;
@@ -255,23 +275,23 @@ __device__ void visit(const GrainTables& tb, const SlotLayout& lay, const Slot& 
 
 // the fine tasks of top-level cell (k, i, j) at factor f, in right-looking order
 __device__ void emit_cell(const GrainTables& tb, const SlotLayout& lay, const Slot& s, ScanState& st, int g,
-                          int k, int i, int j, uint32_t* lds_cnt) {
+                          int k, int i, int j, uint32_t* lds_cnt, int32_t* set) {
   const int f = tb.fac[g];
   const int ks = k * f, is = i * f, js = j * f;
   for (int K = ks; K < ks + f && !st.err; K++) {
     const bool kin_i = K >= is && K < is + f, kin_j = K >= js && K < js + f;
-    if (kin_i && kin_j) visit(tb, lay, s, st, CHOL, g, K, K, K, lds_cnt);
+    if (kin_i && kin_j) visit(tb, lay, s, st, CHOL, g, K, K, K, lds_cnt, set);
     if (kin_i)
-      for (int J = (K + 1 > js ? K + 1 : js); J < js + f && !st.err; J++) visit(tb, lay, s, st, TRSM, g, K, K, J, lds_cnt);
+      for (int J = (K + 1 > js ? K + 1 : js); J < js + f && !st.err; J++) visit(tb, lay, s, st, TRSM, g, K, K, J, lds_cnt, set);
     for (int I = (K + 1 > is ? K + 1 : is); I < is + f && !st.err; I++) {
-      for (int J = (I + 1 > js ? I + 1 : js); J < js + f && !st.err; J++) visit(tb, lay, s, st, GEMM, g, K, I, J, lds_cnt);
-      if (I >= js && I < js + f && !st.err) visit(tb, lay, s, st, SYRK, g, K, I, I, lds_cnt);
+      for (int J = (I + 1 > js ? I + 1 : js); J < js + f && !st.err; J++) visit(tb, lay, s, st, GEMM, g, K, I, J, lds_cnt, set);
+      if (I >= js && I < js + f && !st.err) visit(tb, lay, s, st, SYRK, g, K, I, I, lds_cnt, set);
     }
   }
 }
 
 __device__ int expand_scan(const GrainTables& tb, const SlotLayout& lay, const Slot& s, const uint8_t* grain,
-                           ScanState& st, uint32_t* lds_cnt) {
+                           ScanState& st, uint32_t* lds_cnt, int32_t* set) {
   for (int64_t a = lane(); a < lay.atoms; a += 64) { s.last_w[a] = -1; s.last_r[a] = -1; }
   __syncthreads();
   st.t = 0; st.ne = 0; st.err = 0;
@@ -279,7 +299,7 @@ __device__ int expand_scan(const GrainTables& tb, const SlotLayout& lay, const S
   auto cell = [&](int k, int i, int j) {
     const int g = grain[top++];
     if (g >= tb.n_fac) { st.err = HESP_EINVAL; return; }
-    emit_cell(tb, lay, s, st, g, k, i, j, lds_cnt);
+    emit_cell(tb, lay, s, st, g, k, i, j, lds_cnt, set);
   };
   const int nt = tb.nt;
   for (int k = 0; k < nt && !st.err; k++) {
@@ -561,6 +581,7 @@ __global__ __launch_bounds__(64) void k_grain(GrainTables tb, SlotLayout lay, co
                                               int32_t* __restrict__ out_nt, int64_t* __restrict__ out_ne,
                                               int32_t* __restrict__ out_st) {
   __shared__ uint32_t lds_cnt;
+  __shared__ int32_t set[kSet];
   __shared__ int s_miss[3 * kGMaxMem];
   __shared__ int64_t s_fin[3 * kGMaxMem], s_go[3 * kGMaxMem];
   uint8_t* base = ws + (int64_t)blockIdx.x * lay.bytes;
@@ -583,7 +604,7 @@ __global__ __launch_bounds__(64) void k_grain(GrainTables tb, SlotLayout lay, co
   s.succ = (uint32_t*)(base + lay.succ);
   for (int32_t c = blockIdx.x; c < n_cand; c += gridDim.x) {
     ScanState st;
-    int rc = expand_scan(tb, lay, s, grain + (int64_t)c * tb.n_top, st, &lds_cnt);
+    int rc = expand_scan(tb, lay, s, grain + (int64_t)c * tb.n_top, st, &lds_cnt, set);
     int64_t ms = -1;
     if (rc == HESP_OK) {
       successors(s, st.t, st.ne);
