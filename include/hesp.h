@@ -595,9 +595,11 @@ int hesp_grain_workspace(const hesp_grain_batch *gb, int32_t n_mem, int32_t slot
  * (HESP_OK, or HESP_EINVAL for a grain index >= n_fac).  pf->cost_ns and
  * pf->xfer_ns as filled by hesp_grain_cost_tables (pf->max_level = n_fac - 1;
  * pf->capacity and pf->link unused), all task times >= 1.  d_ws holds at least
- * hesp_grain_workspace(gb, pf->n_mem, slots) bytes owned by the caller; the call
- * is asynchronous and the workspace must stay allocated until the stream has
- * run it; calls sharing a workspace must not overlap. */
+ * hesp_grain_workspace(gb, pf->n_mem, slots) bytes owned by the caller; the
+ * host tables (pf, gb->fac) are read before the call returns, the device work
+ * is asynchronous on `stream`, and the workspace, grain and outputs must stay
+ * allocated until the stream has run it; calls sharing a workspace must not
+ * overlap (the transfer table is staged at its start). */
 int hesp_simulate_grain_batch(const hesp_platform *pf, hesp_policy policy, const hesp_grain_batch *gb,
                               int64_t *d_makespan, int32_t *d_n_tasks, int64_t *d_n_edges, int32_t *d_status,
                               void *d_ws, int64_t ws_bytes, int32_t slots, void *stream);
